@@ -1,0 +1,104 @@
+"""Pins of the whole discrete operator against closed-form wavefields (CPU only).
+
+The paper validates its FD scheme against the analytic solution in a medium
+whose velocity increases linearly with depth (FD-vs-FE section, Table 1).
+Here: the closed-form Green's function itself is checked against the PDE, then
+the oracle's discrete solution (PML on all faces, discrete delta source
+b = e_s/h^3, 8 points per wavelength) is compared with it outside the PML and
+more than 3h from the source.  A homogeneous medium with the Dirichlet top is
+compared with the image-source solution, which also pins the position of the
+Dirichlet plane (the ghost plane one spacing above the first node).
+"""
+import numpy as np
+import pytest
+
+import inputs
+from oracle.analytic import green_homogeneous, green_linear_gradient
+from oracle.operator import Pml, Problem, fit_weights
+from oracle.solve import setup, solve
+
+W = fit_weights()
+
+
+def test_linear_gradient_green_solves_the_pde():
+    c0, alpha, omega = 1500.0, 0.7, 2 * np.pi * 3.75
+    xs, ys, zs = 0.0, 0.0, 400.0
+    d = 0.5
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        x, y, z = rng.uniform(-800, 800), rng.uniform(-800, 800), rng.uniform(50, 1500)
+        if np.sqrt((x - xs) ** 2 + (y - ys) ** 2 + (z - zs) ** 2) < 100:
+            continue
+        g = lambda a, b, c: green_linear_gradient(a, b, c, xs, ys, zs, omega, c0, alpha)
+        # 4th-order central differences
+        lap = 0.0
+        for e in np.eye(3):
+            p = [g(x + s * d * e[0], y + s * d * e[1], z + s * d * e[2]) for s in (-2, -1, 0, 1, 2)]
+            lap += (-p[0] + 16 * p[1] - 30 * p[2] + 16 * p[3] - p[4]) / (12 * d * d)
+        k2 = (omega / (c0 + alpha * z)) ** 2
+        res = lap + k2 * g(x, y, z)
+        assert abs(res) <= 1e-6 * abs(k2 * g(x, y, z))
+    # near the source: -1/(4 pi r)
+    r = 1e-3
+    assert abs(green_linear_gradient(xs + r, ys, zs, xs, ys, zs, omega, c0, alpha) * (-4 * np.pi * r) - 1) < 1e-4
+
+
+def _numerical(c, N, h, f, npml, top):
+    prob = Problem((N, N, N), h, c, f, Pml(npml, npml, npml, top), W)
+    st = setup(prob, (4, 4, 4), 2, 2)
+    s = (N // 2, N // 2, N // 2)
+    b = np.zeros((1, N, N, N), complex)
+    b[0, s[2], s[1], s[0]] = 1.0 / h ** 3
+    res = solve(st, b, 1e-10, 30, 300)
+    z, y, x = np.meshgrid(*(np.arange(N) * h,) * 3, indexing="ij")
+    xs, ys, zs = s[0] * h, s[1] * h, s[2] * h
+    r = np.sqrt((x - xs) ** 2 + (y - ys) ** 2 + (z - zs) ** 2)
+    m = r > 3 * h
+    lo = npml if top else 0
+    m[:lo] = False
+    m[N - npml:] = False
+    m[:, :npml] = False
+    m[:, N - npml:] = False
+    m[:, :, :npml] = False
+    m[:, :, N - npml:] = False
+    return res["X"][0], (x, y, z), (xs, ys, zs), r, m
+
+
+def _err(u, G, m):
+    return np.linalg.norm(u[m] - G[m]) / np.linalg.norm(G[m])
+
+
+@pytest.mark.slow
+def test_linear_gradient_wavefield_matches_analytic():
+    N, h, f, npml = 40, 50.0, 3.75, 8
+    c = inputs.velocity_linear(N, N, N, h, 1500.0, 0.7)
+    u, (x, y, z), (xs, ys, zs), r, m = _numerical(c, N, h, f, npml, npml)
+    G = green_linear_gradient(x, y, z, xs, ys, zs, 2 * np.pi * f, 1500.0, 0.7)
+    assert _err(u, G, m) <= 0.05
+
+
+@pytest.mark.slow
+def test_dirichlet_top_matches_image_source():
+    N, h, f, npml = 32, 50.0, 3.75, 6
+    c = inputs.velocity_homogeneous(N, N, N, 1500.0)
+    u, (x, y, z), (xs, ys, zs), r, m = _numerical(c, N, h, f, npml, 0)
+    k = 2 * np.pi * f / 1500.0
+    rp = np.sqrt((x - xs) ** 2 + (y - ys) ** 2 + (z + 2 * h + zs) ** 2)
+    G = green_homogeneous(np.where(r > 0, r, 1.0), k) - green_homogeneous(rp, k)
+    err = _err(u, G, m)
+    assert err <= 0.08
+    # a mirror plane at z = 0 instead of the ghost plane z = -h fits clearly worse
+    rq = np.sqrt((x - xs) ** 2 + (y - ys) ** 2 + (z + zs) ** 2)
+    Gq = green_homogeneous(np.where(r > 0, r, 1.0), k) - green_homogeneous(rq, k)
+    assert _err(u, Gq, m) > 1.5 * err
+    # and without the image (free space) the fit is poor: the top is reflecting
+    assert _err(u, green_homogeneous(np.where(r > 0, r, 1.0), k), m) > 3 * err
+
+
+@pytest.mark.slow
+def test_pml_absorbs_in_homogeneous_medium():
+    N, h, f, npml = 32, 50.0, 3.75, 6
+    c = inputs.velocity_homogeneous(N, N, N, 1500.0)
+    u, (x, y, z), (xs, ys, zs), r, m = _numerical(c, N, h, f, npml, npml)
+    G = green_homogeneous(np.where(r > 0, r, 1.0), 2 * np.pi * f / 1500.0)
+    assert _err(u, G, m) <= 0.08

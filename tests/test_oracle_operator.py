@@ -1,0 +1,140 @@
+"""Pins of the oracle's discrete operator against closed forms (CPU only).
+
+* A = A^T exactly (complex symmetry of the stretched-coordinate form).
+* Without PML and with constant k, A is diagonalised by the DST-I basis:
+  A = c0 I + c1 sum_d S_d + c2 sum_{d<d'} S_d S_d' + c3 S_x S_y S_z with
+  S_d = tridiag(1, 0, 1) under zero-ghost truncation; the eigenvalues follow
+  from 2 cos(pi m/(n+1)) of each S_d.  This pins the weight classes, the mass
+  classes and the Dirichlet diagonal; it also gives an exact DST solver.
+* The dispersion symbol of ``phase_velocity_ratio`` is checked against the
+  assembled operator applied to a plane wave, and the fitted weights keep the
+  phase-velocity error within 1% for G >= 4 (the paper's claim that the
+  least-squares weights minimise dispersion and anisotropy).
+* The 7-point special case reduces to the textbook symbol.
+"""
+import numpy as np
+import pytest
+import scipy.fft
+import scipy.sparse.linalg as spla
+
+import inputs
+from oracle.operator import (SEVEN_POINT, Pml, Problem, Weights, assemble, fit_weights,
+                             phase_velocity_ratio, pml_xi)
+
+W = fit_weights()
+
+
+def _dst_eigs(shape, h, k, w: Weights):
+    af, ae, ac = w.alphas()
+    c1 = af / h ** 2 + w.wm2 * k ** 2
+    c2 = ae / h ** 2 + w.wm3 * k ** 2
+    c3 = ac / h ** 2 + w.wm4 * k ** 2
+    c0 = -(6 * af + 12 * ae + 8 * ac) / h ** 2 + w.wm1 * k ** 2
+    nx, ny, nz = shape
+    cx = np.cos(np.pi * np.arange(1, nx + 1) / (nx + 1))
+    cy = np.cos(np.pi * np.arange(1, ny + 1) / (ny + 1))
+    cz = np.cos(np.pi * np.arange(1, nz + 1) / (nz + 1))
+    CX, CY, CZ = cx[None, None, :], cy[None, :, None], cz[:, None, None]
+    return (c0 + 2 * c1 * (CX + CY + CZ) + 4 * c2 * (CX * CY + CX * CZ + CY * CZ)
+            + 8 * c3 * CX * CY * CZ)
+
+
+def test_symmetry_heterogeneous_pml():
+    shape = (13, 11, 9)
+    c = inputs.velocity_thrust_belt(*shape, h=25.0, q=100.0)
+    prob = Problem(shape, 25.0, c, 10.0, Pml(3, 2, 3, 0), W)
+    A = assemble(prob)
+    assert A.nnz <= 27 * prob.n
+    assert (A - A.T).count_nonzero() == 0
+    # 27 entries on an interior row
+    i = 6 + 13 * (5 + 11 * 4)
+    assert A[i].nnz == 27
+
+
+@pytest.mark.parametrize("w", [W, SEVEN_POINT], ids=["fitted", "seven"])
+def test_dst_eigenpairs(w):
+    shape = (7, 6, 5)
+    h, f = 40.0, 5.0
+    c = inputs.velocity_homogeneous(*shape, c0=1800.0, q=50.0)
+    prob = Problem(shape, h, c, f, Pml(), w)
+    A = assemble(prob)
+    k = prob.omega / c.flat[0]
+    lam = _dst_eigs(shape, h, k, w)
+    nx, ny, nz = shape
+    rng = np.random.default_rng(1)
+    for _ in range(6):
+        mx, my, mz = rng.integers(1, nx + 1), rng.integers(1, ny + 1), rng.integers(1, nz + 1)
+        vx = np.sin(np.pi * mx * np.arange(1, nx + 1) / (nx + 1))
+        vy = np.sin(np.pi * my * np.arange(1, ny + 1) / (ny + 1))
+        vz = np.sin(np.pi * mz * np.arange(1, nz + 1) / (nz + 1))
+        v = (vz[:, None, None] * vy[None, :, None] * vx[None, None, :]).ravel()
+        Av = A @ v
+        ref = lam[mz - 1, my - 1, mx - 1] * v
+        assert np.linalg.norm(Av - ref) <= 1e-12 * np.linalg.norm(Av)
+
+
+def test_dst_exact_solve_matches_sparse_direct():
+    shape = (9, 8, 7)
+    h, f = 40.0, 5.0
+    c = inputs.velocity_homogeneous(*shape, c0=1800.0, q=50.0)
+    prob = Problem(shape, h, c, f, Pml(), W)
+    A = assemble(prob)
+    b = inputs.random_field(prob.n, seed=3)
+    k = prob.omega / c.flat[0]
+    lam = _dst_eigs(shape, h, k, W)
+    nx, ny, nz = shape
+    bh = scipy.fft.dstn(b.reshape(nz, ny, nx), type=1)
+    x_dst = scipy.fft.idstn(bh / lam, type=1).ravel()
+    x_sp = spla.spsolve(A.tocsc(), b)
+    assert np.linalg.norm(x_dst - x_sp) <= 1e-10 * np.linalg.norm(x_sp)
+
+
+@pytest.mark.parametrize("G,theta,phi", [(4.0, 0.3, 0.2), (6.0, 0.9, 0.7), (10.0, 1.3, 0.1), (5.0, 0.0, 0.0)])
+def test_phase_velocity_matches_assembled_plane_wave(G, theta, phi):
+    # a plane wave of wavenumber kappa solves the discrete equation at interior
+    # nodes when k = kappa * v_ph/c from the dispersion symbol
+    shape = (9, 9, 9)
+    h = 10.0
+    kappa = 2 * np.pi / (G * h)
+    ratio = phase_velocity_ratio(W, G, theta, phi)
+    k = kappa * ratio
+    omega = 2 * np.pi * 20.0
+    c = np.full(shape[::-1], omega / k, dtype=np.complex128)
+    prob = Problem(shape, h, c, 20.0, Pml(), W)
+    A = assemble(prob)
+    n = np.array([np.sin(theta) * np.cos(phi), np.sin(theta) * np.sin(phi), np.cos(theta)])
+    z, y, x = np.meshgrid(*(np.arange(s) * h for s in shape[::-1]), indexing="ij")
+    u = np.exp(1j * kappa * (n[0] * x + n[1] * y + n[2] * z)).ravel()
+    Au = (A @ u).reshape(shape[::-1])[1:-1, 1:-1, 1:-1]
+    assert np.max(np.abs(Au)) <= 1e-10 * k ** 2
+
+
+def test_fitted_weights_dispersion_within_one_percent():
+    worst = 0.0
+    for G in np.linspace(4.0, 16.0, 13):
+        for th in np.linspace(0, np.pi / 2, 9):
+            for ph in np.linspace(0, np.pi / 2, 9):
+                worst = max(worst, abs(phase_velocity_ratio(W, G, th, ph) - 1.0))
+    assert worst <= 0.01
+    # the constraints hold and the result is better than the 7-point stencil
+    assert abs(W.w1 + W.w2 + W.w3 - 1) < 1e-14
+    assert abs(W.wm1 + 6 * W.wm2 + 12 * W.wm3 + 8 * W.wm4 - 1) < 1e-14
+    assert abs(phase_velocity_ratio(SEVEN_POINT, 4.0, 0.0, 0.0) - 1.0) > 0.05
+
+
+def test_seven_point_textbook_symbol():
+    for G in (4.0, 8.0):
+        kh = 2 * np.pi / G
+        # along an axis: k^2 h^2 = 4 sin^2(kappa h/2)
+        assert abs(phase_velocity_ratio(SEVEN_POINT, G, 0.0, 0.0) - 2 * np.sin(kh / 2) / kh) < 1e-14
+
+
+def test_pml_profile():
+    xi_i, xi_h = pml_xi(20, 5, 4, 10.0, 2 * np.pi * 5.0, 3000.0)
+    assert np.all(xi_i[5:16] == 1.0)
+    assert np.all(np.diff(xi_i[:6].imag) < 0) and np.all(np.diff(xi_i[15:].imag) > 0)
+    # gamma at the outer node = gmax * ((npml)/npml)^2 = 1.5 vmax / L ln(1/R)
+    gmax = 1.5 * 3000.0 / 50.0 * np.log(1e3)
+    assert abs(xi_i[0].imag * 2 * np.pi * 5.0 - gmax) < 1e-9 * gmax
+    assert xi_h.shape == (21,) and xi_h[0].imag > xi_i[0].imag
+    assert np.all(xi_i.real == 1.0)
