@@ -1,0 +1,172 @@
+/*
+ * helm.h -- C ABI of the MI355X FD-Helmholtz ORAS-FGMRES solver.
+ *
+ * Solves A x = b, the 27-point mixed-grid finite-difference discretisation of
+ * the frequency-domain Helmholtz equation (Delta + k^2(x)) u = b, k = omega/c,
+ * c complex in viscous media (Dolean et al., EAGE 2021, arXiv 2103.14921:
+ * eq. eqh and eq. eq1 of the FD-vs-FE section), with absorbing layers (PML) on
+ * the vertical and bottom faces and a homogeneous Dirichlet top.  The solver
+ * is right-preconditioned flexible GMRES with the one- or two-level Optimized
+ * Restricted Additive Schwarz preconditioner (eq. oras and eq. 2lvl of the
+ * domain-decomposition section): absorbing (Robin) conditions on the subdomain
+ * interfaces, local problems solved by a direct method, and a coarse problem
+ * solved by 10 GMRES iterations preconditioned by one-level ORAS.
+ *
+ * Conventions used by every entry point:
+ *   - Grid node (ix, iy, iz) sits at (ix h, iy h, iz h), z is depth (down).
+ *     Fields are complex128 (interleaved re, im doubles), C order
+ *     [nz][ny][nx] (x fastest); a batch of nrhs fields is [nrhs][nz][ny][nx]
+ *     (each right-hand side one contiguous field).
+ *   - Time dependence e^{-i omega t}; the Dirichlet top is the ghost plane
+ *     iz = -1; every neighbour outside the grid is a zero ghost.
+ *   - Pointers may be host or device memory (detected per call); the caller
+ *     owns every buffer it passes in.  The handle owns all device memory it
+ *     allocates; only helm_destroy releases it.
+ *   - Return codes: HELM_OK = 0; positive = warning with outputs valid;
+ *     negative = error with outputs untouched.  helm_last_error() gives the
+ *     message of the last failure on the calling thread.
+ *   - One solve in flight per handle; handles are independent.
+ */
+#ifndef HELM_H_
+#define HELM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HELM_OK = 0,
+  HELM_NOT_CONVERGED = 1, /* some right-hand side reached maxit; residuals are reported */
+  HELM_EINVAL = -1,       /* bad sizes or values (non-finite, Re c <= 0, boxes too small) */
+  HELM_ENOMEM = -2,       /* device footprint exceeds the memory budget */
+  HELM_EDEVICE = -3,      /* HIP runtime error or no device */
+  HELM_EBREAKDOWN = -4    /* a numerically singular pivot in a local factorisation */
+} helm_status;
+
+typedef struct helm_handle helm_handle_t;
+
+typedef struct {
+  int32_t nx, ny, nz; /* nodes per axis, each >= 3 */
+  double h;           /* grid spacing in metres, > 0 */
+} helm_grid_t;
+
+/* PML thickness in nodes per side (0 = none).  npml_ztop = 0 gives the
+ * homogeneous Dirichlet top of the paper.  Damping gamma(d) = gamma_max (d/L)^2,
+ * gamma_max = 3 vmax/(2L) ln(1/R), L = npml h; R <= 0 selects R = 1e-3. */
+typedef struct {
+  int32_t npml_x, npml_y, npml_zbot, npml_ztop;
+  double R;
+} helm_pml_t;
+
+/* Mixed-grid stencil weights (FD-vs-FE section: stiffness and consistent mass
+ * on rotated systems, weights fitted by least squares on the dispersion).
+ * Stiffness: w1 Cartesian 7-point, w2 mean of the three 45-degree rotated
+ * systems, w3 the body-diagonal system, w1+w2+w3 = 1.  Mass: wm1 centre,
+ * wm2 face, wm3 edge, wm4 corner neighbours, wm1+6wm2+12wm3+8wm4 = 1. */
+typedef struct {
+  double w1, w2, w3, wm1, wm2, wm3, wm4;
+} helm_weights_t;
+
+enum { HELM_FP64 = 0, HELM_MIXED = 1 };
+
+/* Decomposition and solver options (domain-decomposition section).  Boxes
+ * split each axis into p ranges (floor(n/p), the first n mod p one longer),
+ * extended by `overlap` layers on every interior side; Boolean partition of
+ * unity.  levels = 2 adds the coarse grid at 2h with E = Z^T A Z solved by
+ * coarse_iters GMRES iterations.  precision = HELM_MIXED factors and applies
+ * the local solves in complex FP32 and keeps FGMRES, orthogonalisation,
+ * Givens, residuals and the coarse level in FP64. */
+typedef struct {
+  int32_t px, py, pz;     /* subdomains per axis, >= 1 */
+  int32_t overlap;        /* added layers per interior side, >= 1 */
+  int32_t levels;         /* 1 or 2 */
+  int32_t coarse_iters;   /* GMRES iterations of the coarse solve (paper: 10) */
+  int32_t precision;      /* HELM_FP64 or HELM_MIXED */
+  int32_t restart;        /* FGMRES restart length m, >= 1 */
+  int32_t robin;          /* 1: absorbing interfaces (ORAS); 0: Dirichlet (RAS) */
+  int32_t nrhs_chunk;     /* right-hand sides per batch; 0 = planner's choice */
+} helm_decomp_t;
+
+/* Least-squares fit of the mixed-grid weights on the dispersion relation
+ * (FD-vs-FE section): minimises sum (stiffness/(kappa h)^2 - mass)^2 over
+ * G = gmin..gmax points per wavelength (ng values) and nang x nang directions in
+ * the first octant, subject to the two sum constraints.  Host only; needs no GPU. */
+helm_status helm_fit_weights(double gmin, double gmax, int32_t ng, int32_t nang, helm_weights_t* out);
+
+/* Set up the operator, the decomposition and the factorisations on the current
+ * HIP device.  velocity: complex128 [nz][ny][nx], copied (caller may free it on
+ * return).  weights == NULL uses helm_fit_weights(4, 10, 7, 15).  On success
+ * *out receives a handle. */
+helm_status helm_setup(const helm_grid_t* grid, const void* velocity, double freq_hz,
+                       const helm_pml_t* pml, const helm_weights_t* weights,
+                       const helm_decomp_t* dec, helm_handle_t** out);
+
+enum { HELM_X0 = 1u /* X holds the initial guess on entry */ };
+
+/* Solve A X[r] = B[r], r < nrhs, with one Krylov space per right-hand side.
+ * Stop when |g_{j+1}|/||b|| <= tol (FGMRES estimate), then confirm with the
+ * FP64 true residual ||b - A x||/||b|| and restart from x while it is above
+ * tol.  maxit bounds the outer iterations of each right-hand side.
+ * B, X: complex128 [nrhs][nz][ny][nx]; iters[nrhs], relres_est[nrhs],
+ * relres_true[nrhs] are host arrays (may be NULL).  Returns HELM_NOT_CONVERGED
+ * when some right-hand side reached maxit. */
+helm_status helm_solve(helm_handle_t* h, int32_t nrhs, const void* B, void* X, double tol,
+                       int32_t maxit, uint32_t flags, int32_t* iters, double* relres_est,
+                       double* relres_true);
+
+/* Device bytes the handle needs for this grid and decomposition plus the
+ * Krylov workspace of nrhs_chunk right-hand sides (admission control). */
+size_t helm_footprint(const helm_grid_t* grid, const helm_decomp_t* dec, int32_t nrhs_chunk);
+
+/* Device bytes the handle holds now (factors, operators, cached workspace). */
+size_t helm_resident_bytes(const helm_handle_t* h);
+
+/* Timings of the last setup / solve in seconds, measured with HIP events on the
+ * handle's stream: out[0] setup, out[1] solve, out[2] fine factorisation,
+ * out[3] coarse set-up, out[4] number of outer iterations summed over RHS. */
+helm_status helm_last_timings(const helm_handle_t* h, double out[5]);
+
+void helm_destroy(helm_handle_t* h);
+const char* helm_last_error(void);
+
+/* Bind later kernels of this handle to a HIP stream (hipStream_t; NULL = the
+ * handle's own stream). */
+helm_status helm_set_stream(helm_handle_t* h, void* stream);
+
+/* ---- operator-level entry points (parity tests, tools) ----------------- */
+
+/* Y = A X for nrhs fields (eq. eq1). */
+helm_status helm_apply_A(helm_handle_t* h, int32_t nrhs, const void* X, void* Y);
+
+/* Z = M^{-1} R: the preconditioner the handle was set up with (eq. oras for
+ * levels = 1, eq. 2lvl for levels = 2). */
+helm_status helm_apply_M(helm_handle_t* h, int32_t nrhs, const void* R, void* Z);
+
+/* Z = M1^{-1} R, the one-level ORAS sum_i R_i^T D_i A_i^{-1} R_i (eq. oras)
+ * on level 0 (fine grid) or level 1 (coarse grid, fields of the coarse shape
+ * ceil(n/2) per axis). */
+helm_status helm_apply_oras(helm_handle_t* h, int32_t level, int32_t nrhs, const void* R, void* Z);
+
+/* Coarse transfers (eq. 2lvl): C = Z^T R (restriction, fine -> coarse) and
+ * R = Z C (trilinear prolongation, coarse -> fine). */
+helm_status helm_restrict(helm_handle_t* h, int32_t nrhs, const void* R, void* C);
+helm_status helm_prolong(helm_handle_t* h, int32_t nrhs, const void* C, void* R);
+
+/* Y = E X on the coarse grid, E = Z^T A Z (eq. 2lvl). */
+helm_status helm_apply_E(helm_handle_t* h, int32_t nrhs, const void* X, void* Y);
+
+/* Q = Z GMRES_coarse(E, Z^T R): the coarse correction Q R of eq. 2lvl. */
+helm_status helm_apply_Q(helm_handle_t* h, int32_t nrhs, const void* R, void* Q);
+
+/* Geometry of the decomposition: number of subdomains of a level, and for
+ * subdomain s its extended box elo[3], ehi[3] and core lo[3], hi[3] (x, y, z). */
+int32_t helm_num_subdomains(const helm_handle_t* h, int32_t level);
+helm_status helm_subdomain_box(const helm_handle_t* h, int32_t level, int32_t s, int32_t box[12]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HELM_H_ */

@@ -1,0 +1,976 @@
+// C ABI of the solver: set-up (operator, decomposition, factorisations), the
+// batched FGMRES driver and the operator-level entry points.  The host only
+// plans and sequences launches; every arithmetic step runs in the kernels of
+// ops_operator.hip, ops_local.hip and ops_krylov.hip.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <vector>
+
+#include "../../include/helm.h"
+#include "kernels.h"
+
+struct HelmError : std::runtime_error {
+  helm_status code;
+  HelmError(helm_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+helm_status fail(helm_status c, const std::string& m) {
+  g_last_error = m;
+  return c;
+}
+
+template <typename F>
+helm_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const HelmError& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(HELM_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(HELM_EDEVICE, e.what());
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Device memory owned by a handle.
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t b) {
+    release();
+    if (b == 0) b = 16;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      throw HelmError(HELM_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+    }
+    bytes = b;
+  }
+  template <typename T>
+  T* as() const {
+    return reinterpret_cast<T*>(p);
+  }
+};
+
+struct Level {
+  int nx = 0, ny = 0, nz = 0;
+  long long n = 0;
+  std::vector<Sub> subs;
+  int nsub = 0, bpmax = 0, maxez = 0;
+  long long nodes_total = 0, mat_total = 0, vec_total = 0, maxnodes = 0, maxcore = 0;
+  int prec = 0;  // 0 = complex FP64 factors, 1 = complex FP32 factors
+  DevBuf d_subs, aloc, sinv, E;
+};
+
+// Box planning (host): core ranges split each axis into p contiguous ranges of
+// floor(n/p) nodes, the first n mod p one longer; the extended box adds
+// `overlap` layers on every side that is not a global boundary.
+std::vector<std::pair<int, int>> split_axis(int n, int p) {
+  std::vector<std::pair<int, int>> out;
+  int q = n / p, r = n % p, lo = 0;
+  for (int i = 0; i < p; ++i) {
+    int sz = q + (i < r ? 1 : 0);
+    out.push_back({lo, lo + sz});
+    lo += sz;
+  }
+  return out;
+}
+
+int round_up(int a, int m) { return (a + m - 1) / m * m; }
+
+void plan_level(Level& L, int nx, int ny, int nz, const std::vector<Sub>& cores, int delta, int prec) {
+  L.nx = nx;
+  L.ny = ny;
+  L.nz = nz;
+  L.n = (long long)nx * ny * nz;
+  L.prec = prec;
+  L.subs.clear();
+  const int dims[3] = {nx, ny, nz};
+  long long node_off = 0, mat_off = 0, vec_off = 0;
+  L.bpmax = 0;
+  L.maxez = 0;
+  L.maxnodes = 0;
+  L.maxcore = 0;
+  for (const Sub& c : cores) {
+    Sub s = c;
+    for (int d = 0; d < 3; ++d) {
+      s.elo[d] = std::max(0, s.lo[d] - delta);
+      s.ehi[d] = std::min(dims[d], s.hi[d] + delta);
+    }
+    s.ex = s.ehi[0] - s.elo[0];
+    s.ey = s.ehi[1] - s.elo[1];
+    s.ez = s.ehi[2] - s.elo[2];
+    s.b = s.ex * s.ey;
+    s.bp = round_up(s.b, 16);
+    s.node_off = node_off;
+    s.mat_off = mat_off;
+    s.vec_off = vec_off;
+    const long long nodes = (long long)s.b * s.ez;
+    node_off += nodes;
+    mat_off += (long long)s.ez * s.bp * s.bp;
+    vec_off += (long long)s.ez * s.bp;
+    L.bpmax = std::max(L.bpmax, s.bp);
+    L.maxez = std::max(L.maxez, s.ez);
+    L.maxnodes = std::max(L.maxnodes, nodes);
+    L.maxcore = std::max(L.maxcore, (long long)(s.hi[0] - s.lo[0]) * (s.hi[1] - s.lo[1]) * (s.hi[2] - s.lo[2]));
+    L.subs.push_back(s);
+  }
+  L.nsub = (int)L.subs.size();
+  L.nodes_total = node_off;
+  L.mat_total = mat_off;
+  L.vec_total = vec_off;
+}
+
+std::vector<Sub> fine_cores(int nx, int ny, int nz, int px, int py, int pz) {
+  auto rx = split_axis(nx, px), ry = split_axis(ny, py), rz = split_axis(nz, pz);
+  std::vector<Sub> out;
+  for (int kz = 0; kz < pz; ++kz)
+    for (int ky = 0; ky < py; ++ky)
+      for (int kx = 0; kx < px; ++kx) {
+        Sub s{};
+        s.lo[0] = rx[kx].first; s.hi[0] = rx[kx].second;
+        s.lo[1] = ry[ky].first; s.hi[1] = ry[ky].second;
+        s.lo[2] = rz[kz].first; s.hi[2] = rz[kz].second;
+        out.push_back(s);
+      }
+  return out;
+}
+
+// coarse core = coarse nodes I whose fine position 2I lies in the fine core
+std::vector<Sub> coarse_cores(const std::vector<Sub>& fine) {
+  std::vector<Sub> out;
+  for (const Sub& f : fine) {
+    Sub s{};
+    for (int d = 0; d < 3; ++d) {
+      s.lo[d] = (f.lo[d] + 1) / 2;
+      s.hi[d] = (f.hi[d] + 1) / 2;
+    }
+    out.push_back(s);
+  }
+  return out;
+}
+
+size_t elem_size(int prec) { return prec ? sizeof(c32) : sizeof(z64); }
+
+// Bytes of the handle's resident data for a level (operators and factors).
+size_t level_resident_bytes(const Level& L) {
+  return (size_t)L.nodes_total * 27 * sizeof(z64) + (size_t)L.mat_total * elem_size(L.prec) +
+         (size_t)L.nsub * sizeof(Sub);
+}
+// Temporary set-up bytes of a level (Schur blocks and pivots).
+size_t level_setup_bytes(const Level& L) {
+  return (size_t)L.nsub * L.bpmax * L.bpmax * elem_size(L.prec) * 2 + (size_t)L.nsub * 16 * L.bpmax * elem_size(L.prec) +
+         (size_t)L.nsub * L.bpmax * sizeof(int) * 2 + 64;
+}
+size_t level_ws_bytes(const Level& L, int nr) {
+  return ((size_t)L.vec_total * nr + (size_t)L.nsub * L.bpmax * nr) * elem_size(L.prec);
+}
+
+}  // namespace
+
+struct KrylovArrays {
+  DevBuf Rm, g, cs, sn, y, h, h2, nrm2, w0, bnorm, beta, est, fac, it, kc, active, done, conv, counter;
+  KrylovState st{};
+  void alloc(int m, int nr) {
+    Rm.alloc(sizeof(z64) * (size_t)(m + 1) * m * nr);
+    g.alloc(sizeof(z64) * (size_t)(m + 1) * nr);
+    cs.alloc(sizeof(double) * (size_t)m * nr);
+    sn.alloc(sizeof(z64) * (size_t)m * nr);
+    y.alloc(sizeof(z64) * (size_t)m * nr);
+    h.alloc(sizeof(z64) * (size_t)(m + 1) * nr);
+    h2.alloc(sizeof(z64) * (size_t)(m + 1) * nr);
+    for (DevBuf* b : {&nrm2, &w0, &bnorm, &beta, &est, &fac}) b->alloc(sizeof(double) * nr);
+    for (DevBuf* b : {&it, &kc, &active, &done, &conv}) b->alloc(sizeof(int) * nr);
+    counter.alloc(sizeof(int) * 4);
+    st.m = m;
+    st.nrhs = nr;
+    st.Rm = Rm.as<z64>();
+    st.g = g.as<z64>();
+    st.cs = cs.as<double>();
+    st.sn = sn.as<z64>();
+    st.y = y.as<z64>();
+    st.h = h.as<z64>();
+    st.h2 = h2.as<z64>();
+    st.nrm2 = nrm2.as<double>();
+    st.w0 = w0.as<double>();
+    st.bnorm = bnorm.as<double>();
+    st.beta = beta.as<double>();
+    st.est = est.as<double>();
+    st.fac = fac.as<double>();
+    st.it = it.as<int>();
+    st.kc = kc.as<int>();
+    st.active = active.as<int>();
+    st.done = done.as<int>();
+    st.conv = conv.as<int>();
+    st.counter = counter.as<int>();
+  }
+  static size_t bytes(int m, int nr) {
+    return sizeof(z64) * (size_t)nr * ((size_t)(m + 1) * m + 3 * (m + 1) + 2 * m) + sizeof(double) * (size_t)nr * (m + 6) +
+           sizeof(int) * (5 * (size_t)nr + 4) + 20 * 256;
+  }
+};
+
+struct Workspace {
+  int nr = 0;
+  DevBuf b, x, w, V, Zv, q, t, cc, Vc, Zc, wc, ec, yl_f, tb_f, yl_c, tb_c, zpart, dpart, bn2, beta2;
+  KrylovArrays ko, kc;
+};
+
+struct helm_handle {
+  int device = 0;
+  hipStream_t own = nullptr, stream = nullptr;
+  int nx = 0, ny = 0, nz = 0;
+  long long n = 0;
+  double h = 0, freq = 0, omega = 0;
+  helm_pml_t pml{};
+  helm_weights_t w{};
+  helm_decomp_t dec{};
+  DevBuf c, sigma, xi_int, xi_half, i2_int, i2_half, flat, vmax, err;
+  OpDev op{};
+  Level fine, coarse;
+  Workspace ws;
+  double t_setup = 0, t_solve = 0, t_fact = 0, t_coarse = 0, its = 0;
+
+  ~helm_handle() {
+    if (own) (void)hipStreamDestroy(own);
+  }
+  bool two_level() const { return dec.levels == 2; }
+};
+
+namespace {
+
+void fit_weights_host(double gmin, double gmax, int ng, int nang, helm_weights_t* out) {
+  // unknowns p = (w2, w3, wm2, wm3, wm4); w1 = 1 - w2 - w3, wm1 = 1 - 6wm2 - 12wm3 - 8wm4
+  static const int dirs[13][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, -1, 0}, {1, 0, 1}, {1, 0, -1},
+                                  {0, 1, 1}, {0, 1, -1}, {1, 1, 1}, {1, 1, -1}, {1, -1, 1}, {1, -1, -1}};
+  // least squares by Householder QR of the tall system (rows x 5)
+  std::vector<std::array<double, 5>> J;
+  std::vector<double> rv;
+  const double pi = 3.14159265358979323846;
+  for (int ig = 0; ig < ng; ++ig) {
+    const double G = ng == 1 ? gmin : gmin + (gmax - gmin) * ig / (ng - 1);
+    const double kh = 2.0 * pi / G;
+    for (int it = 0; it < nang; ++it) {
+      const double th = nang == 1 ? 0.0 : 0.5 * pi * it / (nang - 1);
+      for (int ip = 0; ip < nang; ++ip) {
+        const double ph = nang == 1 ? 0.0 : 0.5 * pi * ip / (nang - 1);
+        const double nv[3] = {std::sin(th) * std::cos(ph), std::sin(th) * std::sin(ph), std::cos(th)};
+        double st[3] = {0, 0, 0}, cm[3] = {0, 0, 0};
+        for (int e = 0; e < 13; ++e) {
+          const int cls = e < 3 ? 0 : (e < 9 ? 1 : 2);
+          const double ph2 = kh * (nv[0] * dirs[e][0] + nv[1] * dirs[e][1] + nv[2] * dirs[e][2]);
+          st[cls] += 2.0 * (1.0 - std::cos(ph2));
+          cm[cls] += 2.0 * std::cos(ph2);
+        }
+        for (int c = 0; c < 3; ++c) st[c] /= kh * kh;
+        J.push_back({(-1.0 + 1.0 / 3.0) * st[0] + st[1] / 6.0, -st[0] + st[2] / 4.0, -(cm[0] - 6.0),
+                     -(cm[1] - 12.0), -(cm[2] - 8.0)});
+        rv.push_back(-(st[0] - 1.0));
+      }
+    }
+  }
+  const size_t M = J.size();
+  if (M < 5) throw HelmError(HELM_EINVAL, "too few samples for the weight fit");
+  for (int k = 0; k < 5; ++k) {
+    double nrm = 0.0;
+    for (size_t i = k; i < M; ++i) nrm += J[i][k] * J[i][k];
+    nrm = std::sqrt(nrm);
+    if (nrm == 0.0) throw HelmError(HELM_EINVAL, "singular weight fit");
+    const double alpha = J[k][k] > 0 ? -nrm : nrm;
+    std::vector<double> v(M - k);
+    for (size_t i = k; i < M; ++i) v[i - k] = J[i][k];
+    v[0] -= alpha;
+    double vv = 0.0;
+    for (double x : v) vv += x * x;
+    for (int c = k; c < 5; ++c) {
+      double d = 0.0;
+      for (size_t i = k; i < M; ++i) d += v[i - k] * J[i][c];
+      d = 2.0 * d / vv;
+      for (size_t i = k; i < M; ++i) J[i][c] -= d * v[i - k];
+    }
+    double d = 0.0;
+    for (size_t i = k; i < M; ++i) d += v[i - k] * rv[i];
+    d = 2.0 * d / vv;
+    for (size_t i = k; i < M; ++i) rv[i] -= d * v[i - k];
+  }
+  double p[5];
+  for (int i = 4; i >= 0; --i) {
+    double s2 = rv[i];
+    for (int j = i + 1; j < 5; ++j) s2 -= J[i][j] * p[j];
+    p[i] = s2 / J[i][i];
+  }
+  out->w2 = p[0];
+  out->w3 = p[1];
+  out->w1 = 1.0 - p[0] - p[1];
+  out->wm2 = p[2];
+  out->wm3 = p[3];
+  out->wm4 = p[4];
+  out->wm1 = 1.0 - 6.0 * p[2] - 12.0 * p[3] - 8.0 * p[4];
+}
+
+size_t budget_bytes() {
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    fr = 0;
+  }
+  size_t b = (size_t)(fr * 0.92);
+  if (const char* e = std::getenv("HELM_MEM_BUDGET")) {
+    const size_t v = (size_t)std::strtoull(e, nullptr, 10);
+    if (v > 0) b = std::min(b, v);
+  }
+  return b;
+}
+
+void validate(const helm_grid_t* g, const helm_pml_t* pml, const helm_decomp_t* d) {
+  if (!g || !pml || !d) throw HelmError(HELM_EINVAL, "null argument");
+  if (g->nx < 3 || g->ny < 3 || g->nz < 3) throw HelmError(HELM_EINVAL, "grid must have at least 3 nodes per axis");
+  if (!(g->h > 0) || !std::isfinite(g->h)) throw HelmError(HELM_EINVAL, "h must be positive");
+  if (pml->npml_x < 0 || pml->npml_y < 0 || pml->npml_zbot < 0 || pml->npml_ztop < 0 ||
+      2 * pml->npml_x >= g->nx || 2 * pml->npml_y >= g->ny || pml->npml_zbot + pml->npml_ztop >= g->nz)
+    throw HelmError(HELM_EINVAL, "PML thicker than the grid");
+  if (d->px < 1 || d->py < 1 || d->pz < 1) throw HelmError(HELM_EINVAL, "subdomain counts must be >= 1");
+  if (d->overlap < 1) throw HelmError(HELM_EINVAL, "overlap must be >= 1");
+  if (d->levels != 1 && d->levels != 2) throw HelmError(HELM_EINVAL, "levels must be 1 or 2");
+  if (d->levels == 2 && d->coarse_iters < 1) throw HelmError(HELM_EINVAL, "coarse_iters must be >= 1");
+  if (d->restart < 1 || d->restart > 64) throw HelmError(HELM_EINVAL, "restart must be in [1, 64]");
+  if (d->precision != HELM_FP64 && d->precision != HELM_MIXED) throw HelmError(HELM_EINVAL, "bad precision");
+  const int n[3] = {g->nx, g->ny, g->nz}, p[3] = {d->px, d->py, d->pz};
+  for (int a = 0; a < 3; ++a) {
+    if (p[a] > 1 && n[a] / p[a] < 2 * d->overlap + 1)
+      throw HelmError(HELM_EINVAL, "decomposition finer than 2*overlap+1 nodes per box");
+  }
+}
+
+// largest plane the factorisation kernels accept
+constexpr int MAX_PLANE = 2048;
+
+void plan(helm_handle* H) {
+  const helm_decomp_t& d = H->dec;
+  auto cores = fine_cores(H->nx, H->ny, H->nz, d.px, d.py, d.pz);
+  plan_level(H->fine, H->nx, H->ny, H->nz, cores, d.overlap, d.precision == HELM_MIXED ? 1 : 0);
+  if (H->fine.bpmax > MAX_PLANE) throw HelmError(HELM_EINVAL, "subdomain plane larger than 2048 nodes");
+  if (H->two_level()) {
+    plan_level(H->coarse, (H->nx + 1) / 2, (H->ny + 1) / 2, (H->nz + 1) / 2, coarse_cores(H->fine.subs), d.overlap, 0);
+    if (H->coarse.bpmax > MAX_PLANE) throw HelmError(HELM_EINVAL, "coarse subdomain plane too large");
+  }
+}
+
+size_t ws_bytes(const helm_handle* H, int nr) {
+  const int m = H->dec.restart;
+  size_t b = sizeof(z64) * (size_t)H->n * nr * (3 + (m + 1) + m);
+  b += level_ws_bytes(H->fine, nr);
+  b += KrylovArrays::bytes(m, nr);
+  b += sizeof(z64) * 1024 * 32 * (size_t)nr + sizeof(double) * 1024 * (size_t)nr + 2 * sizeof(double) * nr;
+  if (H->two_level()) {
+    const int ci = H->dec.coarse_iters;
+    const size_t nc = (size_t)H->coarse.n;
+    b += sizeof(z64) * (size_t)H->n * nr * 2;
+    b += sizeof(z64) * nc * nr * (3 + (ci + 1) + ci);
+    b += level_ws_bytes(H->coarse, nr);
+    b += KrylovArrays::bytes(ci, nr);
+  }
+  return b;
+}
+
+size_t resident_bytes_planned(const helm_handle* H) {
+  size_t b = sizeof(z64) * (size_t)H->n * 2 + level_resident_bytes(H->fine);
+  if (H->two_level()) b += level_resident_bytes(H->coarse) + sizeof(z64) * (size_t)H->coarse.n * 27;
+  return b;
+}
+
+// Batch size of the next launches (the arrays hold at least W.nr columns).
+void set_batch(helm_handle* H, int nr) {
+  H->ws.ko.st.nrhs = nr;
+  H->ws.kc.st.nrhs = nr;
+}
+
+void ensure_ws(helm_handle* H, int nr) {
+  Workspace& W = H->ws;
+  if (W.nr >= nr) {
+    set_batch(H, nr);
+    return;
+  }
+  W.nr = 0;
+  const int m = H->dec.restart;
+  const size_t vec = sizeof(z64) * (size_t)H->n * nr;
+  W.b.alloc(vec);
+  W.x.alloc(vec);
+  W.w.alloc(vec);
+  W.V.alloc(vec * (m + 1));
+  W.Zv.alloc(vec * m);
+  W.yl_f.alloc((size_t)H->fine.vec_total * nr * elem_size(H->fine.prec));
+  W.tb_f.alloc((size_t)H->fine.nsub * H->fine.bpmax * nr * elem_size(H->fine.prec));
+  W.zpart.alloc(sizeof(z64) * 1024 * 32 * (size_t)nr);
+  W.dpart.alloc(sizeof(double) * 1024 * (size_t)nr);
+  W.bn2.alloc(sizeof(double) * nr);
+  W.beta2.alloc(sizeof(double) * nr);
+  W.ko.alloc(m, nr);
+  if (H->two_level()) {
+    const int ci = H->dec.coarse_iters;
+    const size_t cvec = sizeof(z64) * (size_t)H->coarse.n * nr;
+    W.q.alloc(vec);
+    W.t.alloc(vec);
+    W.cc.alloc(cvec);
+    W.wc.alloc(cvec);
+    W.ec.alloc(cvec);
+    W.Vc.alloc(cvec * (ci + 1));
+    W.Zc.alloc(cvec * ci);
+    W.yl_c.alloc((size_t)H->coarse.vec_total * nr * sizeof(z64));
+    W.tb_c.alloc((size_t)H->coarse.nsub * H->coarse.bpmax * nr * sizeof(z64));
+    W.kc.alloc(ci, nr);
+  }
+  W.nr = nr;
+  set_batch(H, nr);
+}
+
+// ---------------------------------------------------------------------------
+// Building blocks of one preconditioner application.
+// ---------------------------------------------------------------------------
+void oras_apply(helm_handle* H, Level& L, int nr, const z64* u, z64* z, const z64* add, void* yl, void* tb) {
+  if (L.prec == 1)
+    Factor<float>::sweep(L.d_subs.as<Sub>(), L.nsub, L.bpmax, L.maxez, L.aloc.as<z64>(), L.sinv.as<c32>(), nr, u, z,
+                         add, L.nx, L.ny, (c32*)yl, (c32*)tb, H->stream);
+  else
+    Factor<double>::sweep(L.d_subs.as<Sub>(), L.nsub, L.bpmax, L.maxez, L.aloc.as<z64>(), L.sinv.as<z64>(), nr, u, z,
+                          add, L.nx, L.ny, (z64*)yl, (z64*)tb, H->stream);
+}
+
+void coarse_spmv(helm_handle* H, int nr, const z64* x, z64* y) {
+  launch_coarse_spmv(H->coarse.nx, H->coarse.ny, H->coarse.nz, H->coarse.E.as<z64>(), nr, x, y, H->stream);
+}
+
+// One Arnoldi step with CGS2 on vectors of length len: w is orthogonalised
+// against V_0..V_j; then the Givens kernel updates the least-squares problem.
+void arnoldi_step(helm_handle* H, KrylovArrays& K, int j, const z64* V, z64* w, long long len, int nr, double tol,
+                  int maxit, int fixed) {
+  Workspace& W = H->ws;
+  const long long vs = len * nr;
+  launch_norm2(w, len, nr, W.dpart.as<double>(), K.w0.as<double>(), H->stream);
+  launch_dots(V, vs, j + 1, w, len, nr, W.zpart.as<z64>(), K.h.as<z64>(), H->stream);
+  launch_axpy_multi(V, vs, j + 1, K.h.as<z64>(), w, len, nr, W.dpart.as<double>(), nullptr, H->stream);
+  launch_dots(V, vs, j + 1, w, len, nr, W.zpart.as<z64>(), K.h2.as<z64>(), H->stream);
+  launch_axpy_multi(V, vs, j + 1, K.h2.as<z64>(), w, len, nr, W.dpart.as<double>(), K.nrm2.as<double>(), H->stream);
+  launch_givens(K.st, j, tol, maxit, fixed, H->stream);
+}
+
+// e = GMRES_{ci}(E, c), right-preconditioned by the coarse one-level ORAS, x0 = 0.
+void coarse_solve(helm_handle* H, int nr, const z64* c, z64* e) {
+  Workspace& W = H->ws;
+  KrylovArrays& K = W.kc;
+  const long long nc = H->coarse.n;
+  const long long vs = nc * nr;
+  const int ci = H->dec.coarse_iters;
+  launch_norm2(c, nc, nr, W.dpart.as<double>(), W.beta2.as<double>(), H->stream);
+  launch_cycle_start_fixed(K.st, W.beta2.as<double>(), H->stream);
+  launch_scale(c, K.fac.as<double>(), W.Vc.as<z64>(), nc, nr, H->stream);
+  for (int j = 0; j < ci; ++j) {
+    z64* vj = W.Vc.as<z64>() + j * vs;
+    z64* zj = W.Zc.as<z64>() + j * vs;
+    oras_apply(H, H->coarse, nr, vj, zj, nullptr, W.yl_c.p, W.tb_c.p);
+    coarse_spmv(H, nr, zj, W.wc.as<z64>());
+    arnoldi_step(H, K, j, W.Vc.as<z64>(), W.wc.as<z64>(), nc, nr, 0.0, 1 << 30, 1);
+    if (j + 1 < ci) launch_scale(W.wc.as<z64>(), K.fac.as<double>(), W.Vc.as<z64>() + (j + 1) * vs, nc, nr, H->stream);
+  }
+  launch_backsolve(K.st, H->stream);
+  launch_fill(e, vs, H->stream);
+  launch_update(W.Zc.as<z64>(), vs, ci, K.y.as<z64>(), e, nc, nr, H->stream);
+}
+
+// q = Z GMRES(E, Z^T r)
+void coarse_correction(helm_handle* H, int nr, const z64* r, z64* q) {
+  Workspace& W = H->ws;
+  launch_restrict(H->nx, H->ny, H->nz, nr, r, W.cc.as<z64>(), H->stream);
+  coarse_solve(H, nr, W.cc.as<z64>(), W.ec.as<z64>());
+  launch_prolong(H->nx, H->ny, H->nz, nr, W.ec.as<z64>(), q, H->stream);
+}
+
+// z = M^{-1} v (eq. oras or eq. 2lvl)
+void precond(helm_handle* H, int nr, const z64* v, z64* z) {
+  Workspace& W = H->ws;
+  if (!H->two_level()) {
+    oras_apply(H, H->fine, nr, v, z, nullptr, W.yl_f.p, W.tb_f.p);
+    return;
+  }
+  coarse_correction(H, nr, v, W.q.as<z64>());
+  launch_residual(H->op, nr, v, W.q.as<z64>(), W.t.as<z64>(), H->stream);  // t = v - A q
+  oras_apply(H, H->fine, nr, W.t.as<z64>(), z, W.q.as<z64>(), W.yl_f.p, W.tb_f.p);
+}
+
+int read_counter(helm_handle* H, KrylovArrays& K) {
+  int v = 0;
+  HELM_CHECK_HIP(hipMemcpyAsync(&v, K.counter.p, sizeof(int), hipMemcpyDeviceToHost, H->stream));
+  HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+  return v;
+}
+void zero_counter(helm_handle* H, KrylovArrays& K) {
+  // a fill kernel rather than a memset, so that the sequence stays capturable
+  launch_fill(K.counter.as<z64>(), 1, H->stream);
+}
+
+// Batched FGMRES on W.nr right-hand sides held node-major in W.b / W.x.
+void fgmres_chunk(helm_handle* H, int nr, double tol, int maxit, bool x0) {
+  Workspace& W = H->ws;
+  KrylovArrays& K = W.ko;
+  const long long n = H->n;
+  const long long vs = n * nr;
+  const int m = H->dec.restart;
+  launch_norm2(W.b.as<z64>(), n, nr, W.dpart.as<double>(), W.bn2.as<double>(), H->stream);
+  launch_krylov_init(K.st, W.bn2.as<double>(), H->stream);
+  if (x0) {
+    launch_residual(H->op, nr, W.b.as<z64>(), W.x.as<z64>(), W.w.as<z64>(), H->stream);
+  } else {
+    launch_fill(W.x.as<z64>(), vs, H->stream);
+    launch_copy(W.b.as<z64>(), W.w.as<z64>(), vs, H->stream);
+  }
+  launch_norm2(W.w.as<z64>(), n, nr, W.dpart.as<double>(), W.beta2.as<double>(), H->stream);
+  zero_counter(H, K);
+  launch_cycle_start(K.st, W.beta2.as<double>(), tol, maxit, 1, H->stream);
+  int nact = read_counter(H, K);
+  while (nact > 0) {
+    launch_scale(W.w.as<z64>(), K.fac.as<double>(), W.V.as<z64>(), n, nr, H->stream);
+    for (int j = 0; j < m; ++j) {
+      z64* vj = W.V.as<z64>() + j * vs;
+      z64* zj = W.Zv.as<z64>() + j * vs;
+      precond(H, nr, vj, zj);
+      launch_stencil(H->op, nr, zj, W.w.as<z64>(), H->stream);
+      zero_counter(H, K);
+      arnoldi_step(H, K, j, W.V.as<z64>(), W.w.as<z64>(), n, nr, tol, maxit, 0);
+      if (read_counter(H, K) == 0) break;
+      launch_scale(W.w.as<z64>(), K.fac.as<double>(), W.V.as<z64>() + (j + 1) * vs, n, nr, H->stream);
+    }
+    launch_backsolve(K.st, H->stream);
+    launch_update(W.Zv.as<z64>(), vs, m, K.y.as<z64>(), W.x.as<z64>(), n, nr, H->stream);
+    launch_residual(H->op, nr, W.b.as<z64>(), W.x.as<z64>(), W.w.as<z64>(), H->stream);
+    launch_norm2(W.w.as<z64>(), n, nr, W.dpart.as<double>(), W.beta2.as<double>(), H->stream);
+    zero_counter(H, K);
+    launch_cycle_start(K.st, W.beta2.as<double>(), tol, maxit, 0, H->stream);
+    nact = read_counter(H, K);
+  }
+}
+
+struct Timer {
+  hipEvent_t a, b;
+  hipStream_t s;
+  explicit Timer(hipStream_t st) : s(st) {
+    HELM_CHECK_HIP(hipEventCreate(&a));
+    HELM_CHECK_HIP(hipEventCreate(&b));
+    HELM_CHECK_HIP(hipEventRecord(a, s));
+  }
+  double stop() {
+    HELM_CHECK_HIP(hipEventRecord(b, s));
+    HELM_CHECK_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    HELM_CHECK_HIP(hipEventElapsedTime(&ms, a, b));
+    return ms * 1e-3;
+  }
+  ~Timer() {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+};
+
+void factor_level(helm_handle* H, Level& L) {
+  DevBuf Wt, St, Rb, piv, perm;
+  const size_t es = elem_size(L.prec);
+  Wt.alloc((size_t)L.nsub * L.bpmax * L.bpmax * es);
+  St.alloc((size_t)L.nsub * L.bpmax * L.bpmax * es);
+  Rb.alloc((size_t)L.nsub * 16 * L.bpmax * es);
+  piv.alloc((size_t)L.nsub * L.bpmax * sizeof(int));
+  perm.alloc((size_t)L.nsub * L.bpmax * sizeof(int));
+  launch_fill(H->err.as<z64>(), 1, H->stream);
+  for (int k = 0; k < L.maxez; ++k) {
+    if (L.prec == 1)
+      Factor<float>::plane(L.d_subs.as<Sub>(), L.nsub, L.bpmax, k, L.aloc.as<z64>(), L.sinv.as<c32>(), Wt.as<c32>(),
+                           St.as<c32>(), Rb.as<c32>(), piv.as<int>(), perm.as<int>(), H->err.as<int>(), H->stream);
+    else
+      Factor<double>::plane(L.d_subs.as<Sub>(), L.nsub, L.bpmax, k, L.aloc.as<z64>(), L.sinv.as<z64>(), Wt.as<z64>(),
+                            St.as<z64>(), Rb.as<z64>(), piv.as<int>(), perm.as<int>(), H->err.as<int>(), H->stream);
+  }
+  int e = 0;
+  HELM_CHECK_HIP(hipMemcpyAsync(&e, H->err.p, sizeof(int), hipMemcpyDeviceToHost, H->stream));
+  HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+  if (e) throw HelmError(HELM_EBREAKDOWN, "numerically singular pivot in a local factorisation");
+}
+
+void upload_subs(Level& L) {
+  L.d_subs.alloc(sizeof(Sub) * L.subs.size());
+  HELM_CHECK_HIP(hipMemcpy(L.d_subs.p, L.subs.data(), sizeof(Sub) * L.subs.size(), hipMemcpyHostToDevice));
+}
+
+void setup_impl(helm_handle* H, const void* velocity) {
+  HELM_CHECK_HIP(hipGetDevice(&H->device));
+  HELM_CHECK_HIP(hipStreamCreateWithFlags(&H->own, hipStreamNonBlocking));
+  H->stream = H->own;
+  const long long n = H->n;
+  // velocity: validate on the host
+  std::vector<z64> ch((size_t)n);
+  HELM_CHECK_HIP(hipMemcpy(ch.data(), velocity, sizeof(z64) * n, hipMemcpyDefault));
+  for (long long i = 0; i < n; ++i) {
+    if (!std::isfinite(ch[i].re) || !std::isfinite(ch[i].im) || !(ch[i].re > 0))
+      throw HelmError(HELM_EINVAL, "velocity must be finite with a positive real part");
+  }
+  plan(H);
+  const size_t need = resident_bytes_planned(H) + std::max(level_setup_bytes(H->fine), level_setup_bytes(H->coarse)) +
+                      ws_bytes(H, 1);
+  if (need > budget_bytes()) throw HelmError(HELM_ENOMEM, "footprint " + std::to_string(need) + " bytes exceeds the device budget");
+
+  Timer tall(H->stream);
+  H->c.alloc(sizeof(z64) * n);
+  HELM_CHECK_HIP(hipMemcpy(H->c.p, ch.data(), sizeof(z64) * n, hipMemcpyHostToDevice));
+  H->sigma.alloc(sizeof(z64) * n);
+  const int tot_int = H->nx + H->ny + H->nz;
+  H->xi_int.alloc(sizeof(z64) * tot_int);
+  H->i2_int.alloc(sizeof(z64) * tot_int);
+  H->xi_half.alloc(sizeof(z64) * (tot_int + 3));
+  H->i2_half.alloc(sizeof(z64) * (tot_int + 3));
+  H->flat.alloc(tot_int);
+  H->vmax.alloc(sizeof(double));
+  H->err.alloc(64);
+  launch_vmax(H->c.as<z64>(), n, H->vmax.as<double>(), H->stream);
+  AxisPml ax[3] = {{H->nx, H->pml.npml_x, H->pml.npml_x},
+                   {H->ny, H->pml.npml_y, H->pml.npml_y},
+                   {H->nz, H->pml.npml_ztop, H->pml.npml_zbot}};
+  const double R = H->pml.R > 0 ? H->pml.R : 1e-3;
+  launch_pml_tables(ax, H->h, H->omega, R, H->vmax.as<double>(), H->xi_int.as<z64>(), H->xi_half.as<z64>(),
+                    H->i2_int.as<z64>(), H->i2_half.as<z64>(), H->flat.as<uint8_t>(), H->stream);
+  OpDev& op = H->op;
+  op.nx = H->nx;
+  op.ny = H->ny;
+  op.nz = H->nz;
+  op.h2inv = 1.0 / (H->h * H->h);
+  op.alpha[0] = H->w.w1 + H->w.w2 / 3.0;
+  op.alpha[1] = H->w.w2 / 6.0;
+  op.alpha[2] = H->w.w3 / 4.0;
+  op.wm[0] = H->w.wm1;
+  op.wm[1] = H->w.wm2;
+  op.wm[2] = H->w.wm3;
+  op.wm[3] = H->w.wm4;
+  op.sigma = H->sigma.as<z64>();
+  op.xi_int = H->xi_int.as<z64>();
+  op.xi_half = H->xi_half.as<z64>();
+  op.i2_int = H->i2_int.as<z64>();
+  op.i2_half = H->i2_half.as<z64>();
+  op.flat = H->flat.as<uint8_t>();
+  op.off_int[0] = 0;
+  op.off_int[1] = H->nx;
+  op.off_int[2] = H->nx + H->ny;
+  op.off_half[0] = 0;
+  op.off_half[1] = H->nx + 1;
+  op.off_half[2] = H->nx + H->ny + 2;
+  launch_sigma(op, H->c.as<z64>(), H->omega, H->stream);
+
+  // fine level: local operators with absorbing interfaces, then factorisation
+  Level& F = H->fine;
+  upload_subs(F);
+  F.aloc.alloc(sizeof(z64) * 27 * (size_t)F.nodes_total);
+  F.sinv.alloc(elem_size(F.prec) * (size_t)F.mat_total);
+  launch_local_fine(op, F.d_subs.as<Sub>(), F.nsub, F.maxnodes, H->c.as<z64>(), H->omega, H->h, H->dec.robin,
+                    F.aloc.as<z64>(), H->stream);
+  {
+    Timer tf(H->stream);
+    factor_level(H, F);
+    H->t_fact = tf.stop();
+  }
+  if (H->two_level()) {
+    Timer tc(H->stream);
+    Level& C = H->coarse;
+    C.E.alloc(sizeof(z64) * 27 * (size_t)C.n);
+    launch_build_E(op, C.nx, C.ny, C.nz, C.E.as<z64>(), H->stream);
+    upload_subs(C);
+    C.aloc.alloc(sizeof(z64) * 27 * (size_t)C.nodes_total);
+    C.sinv.alloc(sizeof(z64) * (size_t)C.mat_total);
+    launch_local_coarse(C.nx, C.ny, C.nz, C.E.as<z64>(), C.d_subs.as<Sub>(), C.nsub, C.maxnodes, H->c.as<z64>(), H->nx,
+                        H->ny, H->omega, 2.0 * H->h, H->dec.robin, C.aloc.as<z64>(), H->stream);
+    factor_level(H, C);
+    H->t_coarse = tc.stop();
+  }
+  H->t_setup = tall.stop();
+  HELM_CHECK_HIP(hipGetLastError());
+}
+
+int choose_chunk(helm_handle* H, int nrhs) {
+  int nr = H->dec.nrhs_chunk > 0 ? H->dec.nrhs_chunk : nrhs;
+  nr = std::min(nr, nrhs);
+  nr = std::min(nr, 256);
+  if (H->ws.nr >= nr) return nr;  // already allocated
+  const size_t held = H->ws.nr > 0 ? ws_bytes(H, H->ws.nr) : 0;
+  const size_t avail = budget_bytes() + held;
+  while (nr > 1 && ws_bytes(H, nr) > avail) nr = (nr + 1) / 2;
+  if (ws_bytes(H, nr) > avail) throw HelmError(HELM_ENOMEM, "Krylov workspace of one right-hand side exceeds the device budget");
+  return nr;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+helm_status helm_fit_weights(double gmin, double gmax, int32_t ng, int32_t nang, helm_weights_t* out) {
+  return guarded([&]() {
+    if (!out || ng < 1 || nang < 1 || !(gmin > 0) || !(gmax >= gmin))
+      throw HelmError(HELM_EINVAL, "bad fit parameters");
+    fit_weights_host(gmin, gmax, ng, nang, out);
+    return HELM_OK;
+  });
+}
+
+helm_status helm_setup(const helm_grid_t* grid, const void* velocity, double freq_hz, const helm_pml_t* pml,
+                       const helm_weights_t* weights, const helm_decomp_t* dec, helm_handle_t** out) {
+  return guarded([&]() {
+    if (!out || !velocity) throw HelmError(HELM_EINVAL, "null argument");
+    *out = nullptr;
+    validate(grid, pml, dec);
+    if (!(freq_hz > 0) || !std::isfinite(freq_hz)) throw HelmError(HELM_EINVAL, "frequency must be positive");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+      (void)hipGetLastError();
+      throw HelmError(HELM_EDEVICE, "no HIP device");
+    }
+    std::unique_ptr<helm_handle> H(new helm_handle());
+    H->nx = grid->nx;
+    H->ny = grid->ny;
+    H->nz = grid->nz;
+    H->n = (long long)grid->nx * grid->ny * grid->nz;
+    H->h = grid->h;
+    H->freq = freq_hz;
+    H->omega = 2.0 * 3.14159265358979323846 * freq_hz;
+    H->pml = *pml;
+    H->dec = *dec;
+    if (weights) H->w = *weights;
+    else fit_weights_host(4.0, 10.0, 7, 15, &H->w);
+    setup_impl(H.get(), velocity);
+    *out = H.release();
+    return HELM_OK;
+  });
+}
+
+helm_status helm_solve(helm_handle_t* H, int32_t nrhs, const void* B, void* X, double tol, int32_t maxit,
+                       uint32_t flags, int32_t* iters, double* relres_est, double* relres_true) {
+  return guarded([&]() {
+    if (!H || !B || !X || nrhs < 0 || !(tol >= 0) || maxit < 0) throw HelmError(HELM_EINVAL, "bad solve arguments");
+    if (nrhs == 0) return HELM_OK;
+    const long long n = H->n;
+    const int nr_max = choose_chunk(H, nrhs);
+    ensure_ws(H, nr_max);
+    Workspace& W = H->ws;
+    std::vector<int> it_all(nrhs), conv_all(nrhs);
+    std::vector<double> est_all(nrhs), tru_all(nrhs);
+    bool all_conv = true;
+    Timer tt(H->stream);
+    for (int r0 = 0; r0 < nrhs; r0 += nr_max) {
+      const int nr = std::min(nr_max, nrhs - r0);
+      set_batch(H, nr);
+      const size_t bytes = sizeof(z64) * (size_t)n * nr;
+      // stage B[r0:r0+nr] through W.w (field-major) into W.b (node-major)
+      HELM_CHECK_HIP(hipMemcpyAsync(W.w.p, (const char*)B + sizeof(z64) * (size_t)n * r0, bytes, hipMemcpyDefault, H->stream));
+      launch_to_node_major(W.w.as<z64>(), W.b.as<z64>(), n, nr, H->stream);
+      const bool x0 = (flags & HELM_X0) != 0;
+      if (x0) {
+        HELM_CHECK_HIP(hipMemcpyAsync(W.w.p, (const char*)X + sizeof(z64) * (size_t)n * r0, bytes, hipMemcpyDefault, H->stream));
+        launch_to_node_major(W.w.as<z64>(), W.x.as<z64>(), n, nr, H->stream);
+      }
+      fgmres_chunk(H, nr, tol, maxit, x0);
+      launch_to_field_major(W.x.as<z64>(), W.w.as<z64>(), n, nr, H->stream);
+      HELM_CHECK_HIP(hipMemcpyAsync((char*)X + sizeof(z64) * (size_t)n * r0, W.w.p, bytes, hipMemcpyDefault, H->stream));
+      std::vector<int> it(nr), conv(nr);
+      std::vector<double> est(nr), beta(nr), bn(nr);
+      HELM_CHECK_HIP(hipMemcpyAsync(it.data(), W.ko.it.p, sizeof(int) * nr, hipMemcpyDeviceToHost, H->stream));
+      HELM_CHECK_HIP(hipMemcpyAsync(conv.data(), W.ko.conv.p, sizeof(int) * nr, hipMemcpyDeviceToHost, H->stream));
+      HELM_CHECK_HIP(hipMemcpyAsync(est.data(), W.ko.est.p, sizeof(double) * nr, hipMemcpyDeviceToHost, H->stream));
+      HELM_CHECK_HIP(hipMemcpyAsync(beta.data(), W.ko.beta.p, sizeof(double) * nr, hipMemcpyDeviceToHost, H->stream));
+      HELM_CHECK_HIP(hipMemcpyAsync(bn.data(), W.ko.bnorm.p, sizeof(double) * nr, hipMemcpyDeviceToHost, H->stream));
+      HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+      for (int r = 0; r < nr; ++r) {
+        it_all[r0 + r] = it[r];
+        conv_all[r0 + r] = conv[r];
+        est_all[r0 + r] = est[r];
+        tru_all[r0 + r] = bn[r] > 0 ? beta[r] / bn[r] : 0.0;
+        all_conv = all_conv && conv[r];
+      }
+    }
+    H->t_solve = tt.stop();
+    double its = 0;
+    for (int r = 0; r < nrhs; ++r) {
+      its += it_all[r];
+      if (iters) iters[r] = it_all[r];
+      if (relres_est) relres_est[r] = est_all[r];
+      if (relres_true) relres_true[r] = tru_all[r];
+    }
+    H->its = its;
+    HELM_CHECK_HIP(hipGetLastError());
+    return all_conv ? HELM_OK : HELM_NOT_CONVERGED;
+  });
+}
+
+size_t helm_footprint(const helm_grid_t* grid, const helm_decomp_t* dec, int32_t nrhs_chunk) {
+  try {
+    helm_pml_t pml{0, 0, 0, 0, 0};
+    validate(grid, &pml, dec);
+    helm_handle H;
+    H.nx = grid->nx;
+    H.ny = grid->ny;
+    H.nz = grid->nz;
+    H.n = (long long)grid->nx * grid->ny * grid->nz;
+    H.dec = *dec;
+    plan(&H);
+    return resident_bytes_planned(&H) + std::max(level_setup_bytes(H.fine), level_setup_bytes(H.coarse)) +
+           ws_bytes(&H, std::max(1, nrhs_chunk));
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return 0;
+  }
+}
+
+size_t helm_resident_bytes(const helm_handle_t* H) {
+  if (!H) return 0;
+  return resident_bytes_planned(H) + (H->ws.nr > 0 ? ws_bytes(H, H->ws.nr) : 0);
+}
+
+helm_status helm_last_timings(const helm_handle_t* H, double out[5]) {
+  if (!H || !out) return fail(HELM_EINVAL, "null argument");
+  out[0] = H->t_setup;
+  out[1] = H->t_solve;
+  out[2] = H->t_fact;
+  out[3] = H->t_coarse;
+  out[4] = H->its;
+  return HELM_OK;
+}
+
+void helm_destroy(helm_handle_t* H) {
+  if (!H) return;
+  (void)hipDeviceSynchronize();
+  delete H;
+}
+
+const char* helm_last_error(void) { return g_last_error.c_str(); }
+
+helm_status helm_set_stream(helm_handle_t* H, void* stream) {
+  if (!H) return fail(HELM_EINVAL, "null handle");
+  H->stream = stream ? (hipStream_t)stream : H->own;
+  return HELM_OK;
+}
+
+}  // extern "C"
+
+// ---- operator-level entry points -------------------------------------------
+
+namespace {
+template <typename F>
+helm_status map_fields(helm_handle_t* H, int nrhs, long long len_in, long long len_out, const void* in, void* outp,
+                       F&& body) {
+  return guarded([&]() {
+    if (!H || !in || !outp || nrhs < 1 || nrhs > 256) throw HelmError(HELM_EINVAL, "bad arguments");
+    DevBuf fi, ni, no, fo;
+    fi.alloc(sizeof(z64) * len_in * nrhs);
+    ni.alloc(sizeof(z64) * len_in * nrhs);
+    no.alloc(sizeof(z64) * len_out * nrhs);
+    fo.alloc(sizeof(z64) * len_out * nrhs);
+    HELM_CHECK_HIP(hipMemcpyAsync(fi.p, in, sizeof(z64) * len_in * nrhs, hipMemcpyDefault, H->stream));
+    launch_to_node_major(fi.as<z64>(), ni.as<z64>(), len_in, nrhs, H->stream);
+    body(ni.as<z64>(), no.as<z64>());
+    launch_to_field_major(no.as<z64>(), fo.as<z64>(), len_out, nrhs, H->stream);
+    HELM_CHECK_HIP(hipMemcpyAsync(outp, fo.p, sizeof(z64) * len_out * nrhs, hipMemcpyDefault, H->stream));
+    HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+    HELM_CHECK_HIP(hipGetLastError());
+    return HELM_OK;
+  });
+}
+}  // namespace
+
+extern "C" {
+
+helm_status helm_apply_A(helm_handle_t* H, int32_t nrhs, const void* X, void* Y) {
+  if (!H) return fail(HELM_EINVAL, "null handle");
+  return map_fields(H, nrhs, H->n, H->n, X, Y, [&](const z64* x, z64* y) { launch_stencil(H->op, nrhs, x, y, H->stream); });
+}
+
+helm_status helm_apply_M(helm_handle_t* H, int32_t nrhs, const void* R, void* Z) {
+  if (!H) return fail(HELM_EINVAL, "null handle");
+  return map_fields(H, nrhs, H->n, H->n, R, Z, [&](const z64* r, z64* z) {
+    ensure_ws(H, nrhs);
+    precond(H, nrhs, r, z);
+  });
+}
+
+helm_status helm_apply_oras(helm_handle_t* H, int32_t level, int32_t nrhs, const void* R, void* Z) {
+  if (!H) return fail(HELM_EINVAL, "null handle");
+  if (level != 0 && !(level == 1 && H->two_level())) return fail(HELM_EINVAL, "no such level");
+  Level& L = level == 0 ? H->fine : H->coarse;
+  return map_fields(H, nrhs, L.n, L.n, R, Z, [&](const z64* r, z64* z) {
+    ensure_ws(H, nrhs);
+    if (level == 0) oras_apply(H, L, nrhs, r, z, nullptr, H->ws.yl_f.p, H->ws.tb_f.p);
+    else oras_apply(H, L, nrhs, r, z, nullptr, H->ws.yl_c.p, H->ws.tb_c.p);
+  });
+}
+
+helm_status helm_restrict(helm_handle_t* H, int32_t nrhs, const void* R, void* C) {
+  if (!H || !H->two_level()) return fail(HELM_EINVAL, "two-level handle required");
+  return map_fields(H, nrhs, H->n, H->coarse.n, R, C,
+                    [&](const z64* r, z64* c) { launch_restrict(H->nx, H->ny, H->nz, nrhs, r, c, H->stream); });
+}
+
+helm_status helm_prolong(helm_handle_t* H, int32_t nrhs, const void* C, void* R) {
+  if (!H || !H->two_level()) return fail(HELM_EINVAL, "two-level handle required");
+  return map_fields(H, nrhs, H->coarse.n, H->n, C, R,
+                    [&](const z64* c, z64* r) { launch_prolong(H->nx, H->ny, H->nz, nrhs, c, r, H->stream); });
+}
+
+helm_status helm_apply_E(helm_handle_t* H, int32_t nrhs, const void* X, void* Y) {
+  if (!H || !H->two_level()) return fail(HELM_EINVAL, "two-level handle required");
+  return map_fields(H, nrhs, H->coarse.n, H->coarse.n, X, Y, [&](const z64* x, z64* y) { coarse_spmv(H, nrhs, x, y); });
+}
+
+helm_status helm_apply_Q(helm_handle_t* H, int32_t nrhs, const void* R, void* Q) {
+  if (!H || !H->two_level()) return fail(HELM_EINVAL, "two-level handle required");
+  return map_fields(H, nrhs, H->n, H->n, R, Q, [&](const z64* r, z64* q) {
+    ensure_ws(H, nrhs);
+    coarse_correction(H, nrhs, r, q);
+  });
+}
+
+int32_t helm_num_subdomains(const helm_handle_t* H, int32_t level) {
+  if (!H) return 0;
+  if (level == 0) return H->fine.nsub;
+  if (level == 1 && H->two_level()) return H->coarse.nsub;
+  return 0;
+}
+
+helm_status helm_subdomain_box(const helm_handle_t* H, int32_t level, int32_t s, int32_t box[12]) {
+  if (!H || !box) return fail(HELM_EINVAL, "null argument");
+  const Level* L = level == 0 ? &H->fine : (level == 1 && H->two_level() ? &H->coarse : nullptr);
+  if (!L || s < 0 || s >= L->nsub) return fail(HELM_EINVAL, "no such subdomain");
+  const Sub& b = L->subs[s];
+  for (int d = 0; d < 3; ++d) {
+    box[d] = b.elo[d];
+    box[3 + d] = b.ehi[d];
+    box[6 + d] = b.lo[d];
+    box[9 + d] = b.hi[d];
+  }
+  return HELM_OK;
+}
+
+}  // extern "C"

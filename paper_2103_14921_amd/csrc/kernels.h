@@ -1,0 +1,97 @@
+// Kernel launchers of the HIP library (host-callable).  Vectors are batches
+// laid out node-major, right-hand side fastest: element (node, r) at
+// node*nrhs + r, complex interleaved.
+#pragma once
+#include "common.h"
+
+// ---- medium and operator (ops_operator.hip) --------------------------------
+struct AxisPml {
+  int n, lo, hi;  // nodes, PML thickness at the low / high end
+};
+void launch_vmax(const z64* c, long long n, double* out, hipStream_t s);
+void launch_pml_tables(const AxisPml ax[3], double h, double omega, double R, const double* vmax,
+                       z64* xi_int, z64* xi_half, z64* i2_int, z64* i2_half, uint8_t* flat,
+                       hipStream_t s);
+void launch_sigma(const OpDev& op, const z64* c, double omega, hipStream_t s);
+void launch_stencil(const OpDev& op, int nrhs, const z64* x, z64* y, hipStream_t s);
+// y = b - A x
+void launch_residual(const OpDev& op, int nrhs, const z64* b, const z64* x, z64* y, hipStream_t s);
+void launch_build_E(const OpDev& op, int ncx, int ncy, int ncz, z64* E, hipStream_t s);
+void launch_coarse_spmv(int ncx, int ncy, int ncz, const z64* E, int nrhs, const z64* x, z64* y,
+                        hipStream_t s);
+void launch_restrict(int nx, int ny, int nz, int nrhs, const z64* r, z64* c, hipStream_t s);
+void launch_prolong(int nx, int ny, int nz, int nrhs, const z64* c, z64* q, hipStream_t s);
+
+// ---- local operators, factorisation and sweeps (ops_local.hip) -------------
+// Local operator rows: aloc[(node_off + l)*27 + o], o = (oz+1)*9 + (oy+1)*3 + (ox+1).
+void launch_local_fine(const OpDev& op, const Sub* subs, int nsub, long long maxnodes,
+                       const z64* c, double omega, double h, int robin, z64* aloc, hipStream_t s);
+void launch_local_coarse(int ncx, int ncy, int ncz, const z64* E, const Sub* subs, int nsub,
+                         long long maxnodes, const z64* c_fine, int nx, int ny, double omega,
+                         double hc, int robin, z64* aloc, hipStream_t s);
+
+template <typename T>
+struct Factor {
+  // one plane step of the block-tridiagonal LU: S_k = D_k - L_k Sinv_{k-1} U_{k-1}, Sinv_k = S_k^{-1}
+  static void plane(const Sub* subs, int nsub, int bpmax, int k, const z64* aloc, cpx<T>* sinv,
+                    cpx<T>* W, cpx<T>* S, cpx<T>* Rbuf, int* piv, int* perm, int* err,
+                    hipStream_t s);
+  // one application of the batched local solves on all subdomains:
+  // z = sum_i R_i^T D_i A_i^{-1} R_i u  (+ add if add != nullptr)
+  static void sweep(const Sub* subs, int nsub, int bpmax, int maxez, const z64* aloc,
+                    const cpx<T>* sinv, int nrhs, const z64* u, z64* z, const z64* add,
+                    int gnx, int gny, cpx<T>* yloc, cpx<T>* tbuf, hipStream_t s);
+};
+
+// ---- Krylov (ops_krylov.hip) -----------------------------------------------
+void launch_fill(z64* p, long long n, hipStream_t s);  // zero
+void launch_copy(const z64* a, z64* b, long long n, hipStream_t s);
+void launch_to_node_major(const z64* in, z64* out, long long len, int nrhs, hipStream_t s);
+void launch_to_field_major(const z64* in, z64* out, long long len, int nrhs, hipStream_t s);
+// h[v][r] = sum_node conj(V_v[node][r]) w[node][r], v < nv; V_v = V + v*vstride
+void launch_dots(const z64* V, long long vstride, int nv, const z64* w, long long len, int nrhs,
+                 z64* partial, z64* h, hipStream_t s);
+// w -= sum_v h[v][r] V_v ; optionally nrm2[r] = ||w||^2 after the update
+void launch_axpy_multi(const z64* V, long long vstride, int nv, const z64* h, z64* w,
+                       long long len, int nrhs, double* partial, double* nrm2, hipStream_t s);
+void launch_norm2(const z64* w, long long len, int nrhs, double* partial, double* nrm2,
+                  hipStream_t s);
+// out[node][r] = fac[r] * w[node][r]
+void launch_scale(const z64* w, const double* fac, z64* out, long long len, int nrhs, hipStream_t s);
+// x += sum_v y[v][r] Z_v
+void launch_update(const z64* Z, long long zstride, int nv, const z64* y, z64* x, long long len,
+                   int nrhs, hipStream_t s);
+// a = a - b
+void launch_sub(z64* a, const z64* b, long long n, hipStream_t s);
+
+// Per-right-hand-side GMRES state (device arrays of length nrhs unless noted).
+struct KrylovState {
+  int m, nrhs;
+  z64* Rm;        // [m+1][m][nrhs] rotated Hessenberg (upper triangle used)
+  z64* g;         // [m+1][nrhs]
+  double* cs;     // [m][nrhs]
+  z64* sn;        // [m][nrhs]
+  z64* y;         // [m][nrhs]
+  z64* h;         // [m+1][nrhs] coefficients of the current step (h1 + h2)
+  z64* h2;        // [m+1][nrhs] second pass
+  double* nrm2;   // [nrhs] squared norm of w after orthogonalisation
+  double* w0;     // [nrhs] squared norm of w before orthogonalisation
+  double* bnorm;  // [nrhs]
+  double* beta;   // [nrhs]
+  double* est;    // [nrhs]
+  double* fac;    // [nrhs] scaling applied to w to form the next basis vector
+  int* it;        // [nrhs] total iterations
+  int* kc;        // [nrhs] steps in the current cycle
+  int* active;    // [nrhs]
+  int* done;      // [nrhs]
+  int* conv;      // [nrhs] 1 if converged
+  int* counter;   // [1] number still active (host reads it)
+};
+void launch_krylov_init(KrylovState st, const double* bn2, hipStream_t s);
+// start a cycle from residual norms^2 in beta2: decide done/active, set g[0], fac = 1/beta
+void launch_cycle_start(KrylovState st, const double* beta2, double tol, int maxit, int first,
+                        hipStream_t s);
+void launch_cycle_start_fixed(KrylovState st, const double* beta2, hipStream_t s);
+void launch_givens(KrylovState st, int j, double tol, int maxit, int fixed, hipStream_t s);
+void launch_backsolve(KrylovState st, hipStream_t s);
+void launch_add2(z64* a, const z64* b, long long n, hipStream_t s);

@@ -1,0 +1,418 @@
+// Batched Krylov kernels: one Krylov space per right-hand side, all spaces
+// advanced by the same launches (GMRES of the domain-decomposition section,
+// taken as right-preconditioned flexible GMRES).  Orthogonalisation is
+// classical Gram-Schmidt applied twice (CGS2) with the coefficient sets
+// accumulated; rotations are complex Givens rotations
+//   G = [[c, s], [-conj(s), c]],  c = |a|/rho,  s = (a/|a|) conj(b)/rho,
+// with c = 0, s = 1 when a = 0.
+#include "kernels.h"
+
+namespace {
+
+constexpr int NVMAX = 32;  // basis vectors handled by one dot-product launch
+
+__global__ void k_fill(z64* p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = mk(0.0, 0.0);
+}
+__global__ void k_copy(const z64* a, z64* b, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+__global__ void k_sub(z64* a, const z64* b, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    a[i] = a[i] - b[i];
+}
+__global__ void k_add2(z64* a, const z64* b, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    a[i] = a[i] + b[i];
+}
+
+// [nrhs][len] -> [len][nrhs] through a 32x32 LDS tile
+__global__ void k_to_node_major(const z64* __restrict__ in, z64* __restrict__ out, long long len, int nrhs) {
+  __shared__ z64 tile[32][33];
+  const long long n0 = blockIdx.x * 32LL;
+  const int r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k;
+    const long long nd = n0 + tx;
+    if (r < nrhs && nd < len) tile[k][tx] = in[(long long)r * len + nd];
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const long long nd = n0 + k;
+    const int r = r0 + tx;
+    if (r < nrhs && nd < len) out[nd * nrhs + r] = tile[tx][k];
+  }
+}
+__global__ void k_to_field_major(const z64* __restrict__ in, z64* __restrict__ out, long long len, int nrhs) {
+  __shared__ z64 tile[32][33];
+  const long long n0 = blockIdx.x * 32LL;
+  const int r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = ty; k < 32; k += 8) {
+    const long long nd = n0 + k;
+    const int r = r0 + tx;
+    if (r < nrhs && nd < len) tile[k][tx] = in[nd * nrhs + r];
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k;
+    const long long nd = n0 + tx;
+    if (r < nrhs && nd < len) out[(long long)r * len + nd] = tile[tx][k];
+  }
+}
+
+struct Span {
+  long long lo, hi;
+};
+__device__ __forceinline__ Span block_span(long long len) {
+  const long long per = (len + gridDim.x - 1) / gridDim.x;
+  const long long lo = (long long)blockIdx.x * per;
+  return {lo, lo + per < len ? lo + per : len};
+}
+
+// partial[blk][v][r] = sum over the block's nodes of conj(V_v) w
+__global__ void __launch_bounds__(256) k_dots(const z64* __restrict__ V, long long vstride, int nv,
+                                              const z64* __restrict__ w, long long len, int nrhs,
+                                              z64* __restrict__ partial) {
+  __shared__ z64 red[256];
+  const int tid = threadIdx.x;
+  const int nl = 256 / nrhs;
+  const int r = tid % nrhs, lane = tid / nrhs;
+  const Span sp = block_span(len);
+  z64 acc[NVMAX];
+#pragma unroll
+  for (int v = 0; v < NVMAX; ++v) acc[v] = mk(0.0, 0.0);
+  if (lane < nl) {
+    for (long long nd = sp.lo + lane; nd < sp.hi; nd += nl) {
+      const long long e = nd * nrhs + r;
+      const z64 wv = w[e];
+#pragma unroll
+      for (int v = 0; v < NVMAX; ++v)
+        if (v < nv) cdot_acc(acc[v], V[(long long)v * vstride + e], wv);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < NVMAX; ++v) {
+    if (v >= nv) break;
+    red[tid] = (lane < nl) ? acc[v] : mk(0.0, 0.0);
+    __syncthreads();
+    if (lane == 0) {
+      z64 s = red[r];
+      for (int l = 1; l < nl; ++l) s += red[l * nrhs + r];
+      partial[((long long)blockIdx.x * nv + v) * nrhs + r] = s;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_dots_final(const z64* __restrict__ partial, int nblk, int nv, int nrhs, z64* __restrict__ h) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nv * nrhs) return;
+  z64 s = mk(0.0, 0.0);
+  for (int b = 0; b < nblk; ++b) s += partial[(long long)b * nv * nrhs + t];
+  h[t] = s;
+}
+
+// w -= sum_v h[v][r] V_v; partial[blk][r] = sum |w|^2 over the block's nodes (if partial)
+__global__ void __launch_bounds__(256) k_axpy_multi(const z64* __restrict__ V, long long vstride, int nv,
+                                                    const z64* __restrict__ h, z64* __restrict__ w, long long len,
+                                                    int nrhs, double* __restrict__ partial) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  const int nl = 256 / nrhs;
+  const int r = tid % nrhs, lane = tid / nrhs;
+  const Span sp = block_span(len);
+  z64 hv[NVMAX];
+#pragma unroll
+  for (int v = 0; v < NVMAX; ++v) hv[v] = (v < nv) ? h[v * nrhs + r] : mk(0.0, 0.0);
+  double acc = 0.0;
+  if (lane < nl) {
+    for (long long nd = sp.lo + lane; nd < sp.hi; nd += nl) {
+      const long long e = nd * nrhs + r;
+      z64 x = w[e];
+#pragma unroll
+      for (int v = 0; v < NVMAX; ++v)
+        if (v < nv) cfms(x, hv[v], V[(long long)v * vstride + e]);
+      w[e] = x;
+      acc += abs2(x);
+    }
+  }
+  if (partial) {
+    red[tid] = (lane < nl) ? acc : 0.0;
+    __syncthreads();
+    if (lane == 0) {
+      double s = red[r];
+      for (int l = 1; l < nl; ++l) s += red[l * nrhs + r];
+      partial[(long long)blockIdx.x * nrhs + r] = s;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_norm2(const z64* __restrict__ w, long long len, int nrhs,
+                                               double* __restrict__ partial) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  const int nl = 256 / nrhs;
+  const int r = tid % nrhs, lane = tid / nrhs;
+  const Span sp = block_span(len);
+  double acc = 0.0;
+  if (lane < nl)
+    for (long long nd = sp.lo + lane; nd < sp.hi; nd += nl) acc += abs2(w[nd * nrhs + r]);
+  red[tid] = (lane < nl) ? acc : 0.0;
+  __syncthreads();
+  if (lane == 0) {
+    double s = red[r];
+    for (int l = 1; l < nl; ++l) s += red[l * nrhs + r];
+    partial[(long long)blockIdx.x * nrhs + r] = s;
+  }
+}
+
+__global__ void k_sum_final(const double* __restrict__ partial, int nblk, int nrhs, double* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partial[(long long)b * nrhs + r];
+  out[r] = s;
+}
+
+__global__ void k_scale(const z64* __restrict__ w, const double* __restrict__ fac, z64* __restrict__ out,
+                        long long len, int nrhs) {
+  const long long n = len * nrhs;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    out[e] = fac[e % nrhs] * w[e];
+}
+
+__global__ void k_update(const z64* __restrict__ Z, long long zstride, int nv, const z64* __restrict__ y,
+                         z64* __restrict__ x, long long len, int nrhs) {
+  const long long n = len * nrhs;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    const int r = (int)(e % nrhs);
+    z64 acc = x[e];
+    for (int v = 0; v < nv; ++v) cfma(acc, y[v * nrhs + r], Z[(long long)v * zstride + e]);
+    x[e] = acc;
+  }
+}
+
+__global__ void k_krylov_init(KrylovState st, const double* __restrict__ bn2) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= st.nrhs) return;
+  st.bnorm[r] = sqrt(bn2[r]);
+  st.it[r] = 0;
+  st.kc[r] = 0;
+  st.active[r] = 0;
+  st.done[r] = 0;
+  st.conv[r] = 0;
+  st.est[r] = 1.0;
+}
+
+// Outer cycle start from the current residual norm^2 (beta2): done when
+// ||r|| <= tol ||b|| (converged) or it >= maxit; else v_0 = r/||r||.
+__global__ void k_cycle_start(KrylovState st, const double* __restrict__ beta2, double tol, int maxit, int first) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= st.nrhs) return;
+  st.kc[r] = 0;
+  if (st.done[r]) {
+    st.active[r] = 0;
+    st.fac[r] = 0.0;
+    return;
+  }
+  const double beta = sqrt(beta2[r]);
+  const double bn = st.bnorm[r];
+  st.beta[r] = beta;
+  if (first) st.est[r] = bn > 0.0 ? beta / bn : 0.0;
+  if (bn == 0.0 || beta <= tol * bn || st.it[r] >= maxit) {
+    st.done[r] = 1;
+    st.conv[r] = (bn == 0.0 || beta <= tol * bn) ? 1 : 0;
+    st.active[r] = 0;
+    st.fac[r] = 0.0;
+    return;
+  }
+  st.g[r] = mk(beta, 0.0);
+  st.fac[r] = 1.0 / beta;
+  st.active[r] = 1;
+  atomicAdd(st.counter, 1);
+}
+
+// Fixed-length (coarse) GMRES from x0 = 0: v_0 = c/||c||, nothing to do when c = 0.
+__global__ void k_cycle_start_fixed(KrylovState st, const double* __restrict__ beta2) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= st.nrhs) return;
+  st.kc[r] = 0;
+  const double beta = sqrt(beta2[r]);
+  if (beta == 0.0) {
+    st.active[r] = 0;
+    st.fac[r] = 0.0;
+    return;
+  }
+  st.g[r] = mk(beta, 0.0);
+  st.fac[r] = 1.0 / beta;
+  st.active[r] = 1;
+}
+
+__global__ void k_givens(KrylovState st, int j, double tol, int maxit, int fixed) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= st.nrhs) return;
+  const int nr = st.nrhs;
+  if (!st.active[r]) {
+    st.fac[r] = 0.0;
+    return;
+  }
+  const double hnext = sqrt(st.nrm2[r]);
+  // rotate the new column h[0..j], hnext by the previous rotations
+  // coefficients of the two Gram-Schmidt passes, accumulated
+  z64 a = st.h[r] + st.h2[r];
+  for (int i = 0; i < j; ++i) {
+    const z64 b = st.h[(i + 1) * nr + r] + st.h2[(i + 1) * nr + r];
+    const double c = st.cs[i * nr + r];
+    const z64 s = st.sn[i * nr + r];
+    const z64 top = c * a + s * b;
+    const z64 bot = c * b - conj(s) * a;
+    st.Rm[((long long)i * st.m + j) * nr + r] = top;
+    a = bot;
+  }
+  // new rotation on (a, hnext)
+  const z64 bb = mk(hnext, 0.0);
+  double c;
+  z64 s, rho;
+  const double aa = sqrt(abs2(a));
+  if (aa == 0.0) {
+    c = 0.0;
+    s = mk(1.0, 0.0);
+    rho = bb;
+  } else {
+    const double nrm = sqrt(aa * aa + hnext * hnext);
+    const z64 ph = (1.0 / aa) * a;
+    c = aa / nrm;
+    s = (1.0 / nrm) * (ph * conj(bb));
+    rho = nrm * ph;
+  }
+  st.cs[j * nr + r] = c;
+  st.sn[j * nr + r] = s;
+  st.Rm[((long long)j * st.m + j) * nr + r] = rho;
+  const z64 gj = st.g[j * nr + r];
+  st.g[(j + 1) * nr + r] = -(conj(s) * gj);
+  st.g[j * nr + r] = c * gj;
+  st.kc[r] = j + 1;
+  bool stop = hnext <= 1e-14 * sqrt(st.w0[r]) || j + 1 >= st.m;
+  if (!fixed) {
+    const double est = sqrt(abs2(st.g[(j + 1) * nr + r])) / st.bnorm[r];
+    st.it[r] += 1;
+    st.est[r] = est;
+    stop = stop || est <= tol || st.it[r] >= maxit;
+  }
+  if (stop) {
+    st.active[r] = 0;
+    st.fac[r] = 0.0;
+  } else {
+    st.fac[r] = 1.0 / hnext;
+    atomicAdd(st.counter, 1);
+  }
+}
+
+// y = R^{-1} g over the kc steps of the current cycle (zero beyond)
+__global__ void k_backsolve(KrylovState st) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= st.nrhs) return;
+  const int nr = st.nrhs;
+  const int k = st.kc[r];
+  for (int i = st.m - 1; i >= 0; --i) {
+    if (i >= k) {
+      st.y[i * nr + r] = mk(0.0, 0.0);
+      continue;
+    }
+    z64 acc = st.g[i * nr + r];
+    for (int l = i + 1; l < k; ++l) cfms(acc, st.Rm[((long long)i * st.m + l) * nr + r], st.y[l * nr + r]);
+    st.y[i * nr + r] = cdiv(acc, st.Rm[((long long)i * st.m + i) * nr + r]);
+  }
+}
+
+int red_blocks(long long len) {
+  long long b = ceil_div(len, 2048);
+  if (b < 1) b = 1;
+  if (b > 1024) b = 1024;
+  return (int)b;
+}
+
+}  // namespace
+
+void launch_fill(z64* p, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<long long>(ceil_div(n, 256), 8192)), dim3(256), 0, s, p, n);
+}
+void launch_copy(const z64* a, z64* b, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)std::min<long long>(ceil_div(n, 256), 8192)), dim3(256), 0, s, a, b, n);
+}
+void launch_sub(z64* a, const z64* b, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub, dim3((unsigned)std::min<long long>(ceil_div(n, 256), 8192)), dim3(256), 0, s, a, b, n);
+}
+void launch_add2(z64* a, const z64* b, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_add2, dim3((unsigned)std::min<long long>(ceil_div(n, 256), 8192)), dim3(256), 0, s, a, b, n);
+}
+void launch_to_node_major(const z64* in, z64* out, long long len, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_node_major, dim3((unsigned)ceil_div(len, 32), (unsigned)ceil_div(nrhs, 32)), dim3(256), 0, s,
+                     in, out, len, nrhs);
+}
+void launch_to_field_major(const z64* in, z64* out, long long len, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_field_major, dim3((unsigned)ceil_div(len, 32), (unsigned)ceil_div(nrhs, 32)), dim3(256), 0,
+                     s, in, out, len, nrhs);
+}
+
+void launch_dots(const z64* V, long long vstride, int nv, const z64* w, long long len, int nrhs, z64* partial,
+                 z64* h, hipStream_t s) {
+  const int nblk = red_blocks(len);
+  for (int v0 = 0; v0 < nv; v0 += NVMAX) {
+    const int nvb = std::min(NVMAX, nv - v0);
+    hipLaunchKernelGGL(k_dots, dim3(nblk), dim3(256), 0, s, V + v0 * vstride, vstride, nvb, w, len, nrhs, partial);
+    hipLaunchKernelGGL(k_dots_final, dim3((unsigned)ceil_div(nvb * nrhs, 256)), dim3(256), 0, s, partial, nblk, nvb,
+                       nrhs, h + (long long)v0 * nrhs);
+  }
+}
+
+void launch_axpy_multi(const z64* V, long long vstride, int nv, const z64* h, z64* w, long long len, int nrhs,
+                       double* partial, double* nrm2, hipStream_t s) {
+  const int nblk = red_blocks(len);
+  for (int v0 = 0; v0 < nv; v0 += NVMAX) {
+    const int nvb = std::min(NVMAX, nv - v0);
+    const bool last = v0 + nvb >= nv;
+    hipLaunchKernelGGL(k_axpy_multi, dim3(nblk), dim3(256), 0, s, V + v0 * vstride, vstride, nvb,
+                       h + (long long)v0 * nrhs, w, len, nrhs, (last && nrm2) ? partial : nullptr);
+  }
+  if (nrm2)
+    hipLaunchKernelGGL(k_sum_final, dim3((unsigned)ceil_div(nrhs, 256)), dim3(256), 0, s, partial, nblk, nrhs, nrm2);
+}
+
+void launch_norm2(const z64* w, long long len, int nrhs, double* partial, double* nrm2, hipStream_t s) {
+  const int nblk = red_blocks(len);
+  hipLaunchKernelGGL(k_norm2, dim3(nblk), dim3(256), 0, s, w, len, nrhs, partial);
+  hipLaunchKernelGGL(k_sum_final, dim3((unsigned)ceil_div(nrhs, 256)), dim3(256), 0, s, partial, nblk, nrhs, nrm2);
+}
+
+void launch_scale(const z64* w, const double* fac, z64* out, long long len, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, dim3((unsigned)std::min<long long>(ceil_div(len * nrhs, 256), 8192)), dim3(256), 0, s,
+                     w, fac, out, len, nrhs);
+}
+
+void launch_update(const z64* Z, long long zstride, int nv, const z64* y, z64* x, long long len, int nrhs,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_update, dim3((unsigned)std::min<long long>(ceil_div(len * nrhs, 256), 8192)), dim3(256), 0, s,
+                     Z, zstride, nv, y, x, len, nrhs);
+}
+
+void launch_krylov_init(KrylovState st, const double* bn2, hipStream_t s) {
+  hipLaunchKernelGGL(k_krylov_init, dim3((unsigned)ceil_div(st.nrhs, 64)), dim3(64), 0, s, st, bn2);
+}
+void launch_cycle_start(KrylovState st, const double* beta2, double tol, int maxit, int first, hipStream_t s) {
+  hipLaunchKernelGGL(k_cycle_start, dim3((unsigned)ceil_div(st.nrhs, 64)), dim3(64), 0, s, st, beta2, tol, maxit,
+                     first);
+}
+void launch_cycle_start_fixed(KrylovState st, const double* beta2, hipStream_t s) {
+  hipLaunchKernelGGL(k_cycle_start_fixed, dim3((unsigned)ceil_div(st.nrhs, 64)), dim3(64), 0, s, st, beta2);
+}
+void launch_givens(KrylovState st, int j, double tol, int maxit, int fixed, hipStream_t s) {
+  hipLaunchKernelGGL(k_givens, dim3((unsigned)ceil_div(st.nrhs, 64)), dim3(64), 0, s, st, j, tol, maxit, fixed);
+}
+void launch_backsolve(KrylovState st, hipStream_t s) {
+  hipLaunchKernelGGL(k_backsolve, dim3((unsigned)ceil_div(st.nrhs, 64)), dim3(64), 0, s, st);
+}

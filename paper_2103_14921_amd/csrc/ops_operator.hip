@@ -1,0 +1,361 @@
+// Medium preparation, the matrix-free 27-point PML stencil, the Galerkin
+// coarse operator E = Z^T A Z and the coarse transfers.
+//
+// Operator (eq. eqh / eq. eq1; symmetric stretched-coordinate form): for each
+// of the 26 neighbours j = i + o of node i, with e = o, cls = |ox|+|oy|+|oz|,
+//   A[i, j] = (alpha_cls/h^2) a_e(m) + wm_cls (sigma_i + sigma_j)/2,
+//   a_e(m)  = s(m) * sum_{d: o_d != 0} (1/cls) / xi_d(m_d)^2,   s = xi_x xi_y xi_z,
+// m the midpoint of the edge i-j, and
+//   A[i, i] = -sum_o (alpha_cls/h^2) a_e(m) + wm1 sigma_i,   sigma = s k^2,
+// ghost neighbours outside the grid contributing to the diagonal only.
+#include "kernels.h"
+#include "stencil_row.h"
+
+namespace {
+
+__global__ void k_vmax(const z64* __restrict__ c, long long n, double* out) {
+  __shared__ double red[1024];
+  double m = 0.0;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, c[i].re);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+struct AxisTables {
+  AxisPml ax[3];
+  int off_int[3], off_half[3];
+};
+
+__device__ double pml_gamma(const AxisPml& a, double t, double h, double vmax, double R) {
+  // gamma(t) = gmax (dist/L)^2, gmax = 3 vmax/(2L) ln(1/R), L = npml h; the high side wins on overlap
+  double g = 0.0;
+  if (a.lo > 0 && t < (double)a.lo) {
+    double L = a.lo * h;
+    double gmax = 1.5 * vmax / L * log(1.0 / R);
+    double d = ((a.lo - t) * h) / L;
+    g = gmax * d * d;
+  }
+  if (a.hi > 0 && t > (double)(a.n - 1 - a.hi)) {
+    double L = a.hi * h;
+    double gmax = 1.5 * vmax / L * log(1.0 / R);
+    double d = ((t - (a.n - 1 - a.hi)) * h) / L;
+    g = gmax * d * d;
+  }
+  return g;
+}
+
+__global__ void k_pml_tables(AxisTables tb, double h, double omega, double R, const double* vmax_p,
+                             z64* xi_int, z64* xi_half, z64* i2_int, z64* i2_half, uint8_t* flat) {
+  const int d = blockIdx.y;
+  const AxisPml a = tb.ax[d];
+  const double vmax = vmax_p[0];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t <= a.n) {
+    // half position j - 1/2 for j = t
+    z64 xh = mk(1.0, pml_gamma(a, t - 0.5, h, vmax, R) / omega);
+    xi_half[tb.off_half[d] + t] = xh;
+    i2_half[tb.off_half[d] + t] = cinv(xh * xh);
+  }
+  if (t < a.n) {
+    z64 xi = mk(1.0, pml_gamma(a, (double)t, h, vmax, R) / omega);
+    xi_int[tb.off_int[d] + t] = xi;
+    i2_int[tb.off_int[d] + t] = cinv(xi * xi);
+    bool f = pml_gamma(a, t - 0.5, h, vmax, R) == 0.0 && pml_gamma(a, (double)t, h, vmax, R) == 0.0 &&
+             pml_gamma(a, t + 0.5, h, vmax, R) == 0.0;
+    flat[tb.off_int[d] + t] = f ? 1 : 0;
+  }
+}
+
+__global__ void k_sigma(OpDev op, const z64* __restrict__ c, double omega, z64* sigma) {
+  const long long n = (long long)op.nx * op.ny * op.nz;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    int ix = (int)(i % op.nx);
+    long long q = i / op.nx;
+    int iy = (int)(q % op.ny);
+    int iz = (int)(q / op.ny);
+    z64 s = op.xi_int[op.off_int[2] + iz] * op.xi_int[op.off_int[1] + iy] * op.xi_int[op.off_int[0] + ix];
+    z64 k = cdiv(mk(omega, 0.0), c[i]);
+    sigma[i] = s * (k * k);
+  }
+}
+
+}  // namespace
+
+namespace {
+
+// General stencil: each thread computes NR right-hand sides of one node.
+template <int NR>
+__global__ void __launch_bounds__(256) k_stencil(OpDev op, int nrhs, const z64* __restrict__ x,
+                                                 z64* __restrict__ y, const z64* __restrict__ b) {
+  const long long n = (long long)op.nx * op.ny * op.nz;
+  const int nch = nrhs / NR;
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= n * nch) return;
+  const long long i = t / nch;
+  const int r0 = (int)(t % nch) * NR;
+  const int ix = (int)(i % op.nx);
+  const long long q = i / op.nx;
+  const int iy = (int)(q % op.ny);
+  const int iz = (int)(q / op.ny);
+  const z64 si = op.sigma[i];
+  z64 acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = mk(0.0, 0.0);
+  z64 diag = op.wm[0] * si;
+  const bool flat = op.flat[op.off_int[0] + ix] && op.flat[op.off_int[1] + iy] && op.flat[op.off_int[2] + iz];
+#pragma unroll
+  for (int o = 0; o < 27; ++o) {
+    if (o == 13) continue;
+    const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+    const int cls = abs(ox) + abs(oy) + abs(oz);
+    z64 st;
+    if (flat) st = mk(op.alpha[cls - 1] * op.h2inv, 0.0);
+    else st = stiff_coef(op, ix, iy, iz, ox, oy, oz);
+    diag -= st;
+    const int jx = ix + ox, jy = iy + oy, jz = iz + oz;
+    if (jx >= 0 && jx < op.nx && jy >= 0 && jy < op.ny && jz >= 0 && jz < op.nz) {
+      const long long j = jx + (long long)op.nx * (jy + (long long)op.ny * jz);
+      const z64 cf = st + (0.5 * op.wm[cls]) * (si + op.sigma[j]);
+      const z64* xj = x + j * nrhs + r0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) cfma(acc[r], cf, xj[r]);
+    }
+  }
+  const z64* xi = x + i * nrhs + r0;
+  z64* yi = y + i * nrhs + r0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    cfma(acc[r], diag, xi[r]);
+    if (b) yi[r] = b[i * nrhs + r0 + r] - acc[r];
+    else yi[r] = acc[r];
+  }
+}
+
+// E[I][o] = sum_i sum_j Z[i,I] A[i,j] Z[j,I+o]
+__global__ void k_build_E(OpDev op, int ncx, int ncy, int ncz, z64* __restrict__ E) {
+  const long long nc = (long long)ncx * ncy * ncz;
+  const long long I = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  const int cx = (int)(I % ncx);
+  const int cy = (int)((I / ncx) % ncy);
+  const int cz = (int)(I / ((long long)ncx * ncy));
+  z64 acc[27];
+  for (int o = 0; o < 27; ++o) acc[o] = mk(0.0, 0.0);
+  z64 row[27];
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int iz = 2 * cz + dz;
+    if (iz < 0 || iz >= op.nz) continue;
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int iy = 2 * cy + dy;
+      if (iy < 0 || iy >= op.ny) continue;
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int ix = 2 * cx + dx;
+        if (ix < 0 || ix >= op.nx) continue;
+        const double wi = (dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0);
+        fine_row(op, ix, iy, iz, row);
+        for (int o = 0; o < 27; ++o) {
+          const int jx = ix + o % 3 - 1, jy = iy + (o / 3) % 3 - 1, jz = iz + o / 9 - 1;
+          if (jx < 0 || jx >= op.nx || jy < 0 || jy >= op.ny || jz < 0 || jz >= op.nz) continue;
+          const z64 a = wi * row[o];
+          // coarse nodes J with Z[j, J] != 0 along each axis
+          int jxs[2], jys[2], jzs[2], nxs, nys, nzs;
+          double wxs[2], wys[2], wzs[2];
+          if ((jx & 1) == 0) { jxs[0] = jx / 2; wxs[0] = 1.0; nxs = 1; }
+          else { jxs[0] = (jx - 1) / 2; jxs[1] = (jx + 1) / 2; wxs[0] = wxs[1] = 0.5; nxs = 2; }
+          if ((jy & 1) == 0) { jys[0] = jy / 2; wys[0] = 1.0; nys = 1; }
+          else { jys[0] = (jy - 1) / 2; jys[1] = (jy + 1) / 2; wys[0] = wys[1] = 0.5; nys = 2; }
+          if ((jz & 1) == 0) { jzs[0] = jz / 2; wzs[0] = 1.0; nzs = 1; }
+          else { jzs[0] = (jz - 1) / 2; jzs[1] = (jz + 1) / 2; wzs[0] = wzs[1] = 0.5; nzs = 2; }
+          for (int az = 0; az < nzs; ++az) {
+            if (jzs[az] >= ncz) continue;
+            for (int ay = 0; ay < nys; ++ay) {
+              if (jys[ay] >= ncy) continue;
+              for (int ax = 0; ax < nxs; ++ax) {
+                if (jxs[ax] >= ncx) continue;
+                const int oo = (jzs[az] - cz + 1) * 9 + (jys[ay] - cy + 1) * 3 + (jxs[ax] - cx + 1);
+                acc[oo] += (wxs[ax] * wys[ay] * wzs[az]) * a;
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  for (int o = 0; o < 27; ++o) E[I * 27 + o] = acc[o];
+}
+
+template <int NR>
+__global__ void __launch_bounds__(256) k_coarse_spmv(int ncx, int ncy, int ncz, const z64* __restrict__ E,
+                                                     int nrhs, const z64* __restrict__ x, z64* __restrict__ y) {
+  const long long nc = (long long)ncx * ncy * ncz;
+  const int nch = nrhs / NR;
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= nc * nch) return;
+  const long long I = t / nch;
+  const int r0 = (int)(t % nch) * NR;
+  const int cx = (int)(I % ncx);
+  const int cy = (int)((I / ncx) % ncy);
+  const int cz = (int)(I / ((long long)ncx * ncy));
+  z64 acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = mk(0.0, 0.0);
+  for (int o = 0; o < 27; ++o) {
+    const int jx = cx + o % 3 - 1, jy = cy + (o / 3) % 3 - 1, jz = cz + o / 9 - 1;
+    if (jx < 0 || jx >= ncx || jy < 0 || jy >= ncy || jz < 0 || jz >= ncz) continue;
+    const z64 e = E[I * 27 + o];
+    const long long J = jx + (long long)ncx * (jy + (long long)ncy * jz);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) cfma(acc[r], e, x[J * nrhs + r0 + r]);
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) y[I * nrhs + r0 + r] = acc[r];
+}
+
+// c[I] = sum_i Z[i, I] r[i]   (Z^T, full weighting with weights 1, 1/2 per axis)
+__global__ void k_restrict(int nx, int ny, int nz, int nrhs, const z64* __restrict__ rf, z64* __restrict__ c) {
+  const int ncx = (nx + 1) / 2, ncy = (ny + 1) / 2, ncz = (nz + 1) / 2;
+  const long long nc = (long long)ncx * ncy * ncz;
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= nc * nrhs) return;
+  const long long I = t / nrhs;
+  const int r = (int)(t % nrhs);
+  const int cx = (int)(I % ncx);
+  const int cy = (int)((I / ncx) % ncy);
+  const int cz = (int)(I / ((long long)ncx * ncy));
+  z64 acc = mk(0.0, 0.0);
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int iz = 2 * cz + dz;
+    if (iz < 0 || iz >= nz) continue;
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int iy = 2 * cy + dy;
+      if (iy < 0 || iy >= ny) continue;
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int ix = 2 * cx + dx;
+        if (ix < 0 || ix >= nx) continue;
+        const double w = (dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0);
+        acc += w * rf[(ix + (long long)nx * (iy + (long long)ny * iz)) * nrhs + r];
+      }
+    }
+  }
+  c[I * nrhs + r] = acc;
+}
+
+// q[i] = sum_I Z[i, I] c[I]   (trilinear prolongation)
+__global__ void k_prolong(int nx, int ny, int nz, int nrhs, const z64* __restrict__ c, z64* __restrict__ q) {
+  const int ncx = (nx + 1) / 2, ncy = (ny + 1) / 2, ncz = (nz + 1) / 2;
+  const long long n = (long long)nx * ny * nz;
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= n * nrhs) return;
+  const long long i = t / nrhs;
+  const int r = (int)(t % nrhs);
+  const int ix = (int)(i % nx);
+  const int iy = (int)((i / nx) % ny);
+  const int iz = (int)(i / ((long long)nx * ny));
+  int xs[2], ys[2], zs[2], nxs, nys, nzs;
+  double wx, wy, wz;
+  if ((ix & 1) == 0) { xs[0] = ix / 2; nxs = 1; wx = 1.0; } else { xs[0] = (ix - 1) / 2; xs[1] = (ix + 1) / 2; nxs = 2; wx = 0.5; }
+  if ((iy & 1) == 0) { ys[0] = iy / 2; nys = 1; wy = 1.0; } else { ys[0] = (iy - 1) / 2; ys[1] = (iy + 1) / 2; nys = 2; wy = 0.5; }
+  if ((iz & 1) == 0) { zs[0] = iz / 2; nzs = 1; wz = 1.0; } else { zs[0] = (iz - 1) / 2; zs[1] = (iz + 1) / 2; nzs = 2; wz = 0.5; }
+  z64 acc = mk(0.0, 0.0);
+  const double w = wx * wy * wz;
+  for (int a = 0; a < nzs; ++a) {
+    if (zs[a] >= ncz) continue;
+    for (int b2 = 0; b2 < nys; ++b2) {
+      if (ys[b2] >= ncy) continue;
+      for (int cc = 0; cc < nxs; ++cc) {
+        if (xs[cc] >= ncx) continue;
+        acc += w * c[(xs[cc] + (long long)ncx * (ys[b2] + (long long)ncy * zs[a])) * nrhs + r];
+      }
+    }
+  }
+  q[i * nrhs + r] = acc;
+}
+
+}  // namespace
+
+void launch_vmax(const z64* c, long long n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_vmax, dim3(1), dim3(1024), 0, s, c, n, out);
+}
+
+void launch_pml_tables(const AxisPml ax[3], double h, double omega, double R, const double* vmax,
+                       z64* xi_int, z64* xi_half, z64* i2_int, z64* i2_half, uint8_t* flat,
+                       hipStream_t s) {
+  AxisTables tb;
+  int oi = 0, oh = 0, nmax = 0;
+  for (int d = 0; d < 3; ++d) {
+    tb.ax[d] = ax[d];
+    tb.off_int[d] = oi;
+    tb.off_half[d] = oh;
+    oi += ax[d].n;
+    oh += ax[d].n + 1;
+    nmax = ax[d].n + 1 > nmax ? ax[d].n + 1 : nmax;
+  }
+  hipLaunchKernelGGL(k_pml_tables, dim3((unsigned)ceil_div(nmax, 256), 3), dim3(256), 0, s, tb, h, omega,
+                     R, vmax, xi_int, xi_half, i2_int, i2_half, flat);
+}
+
+void launch_sigma(const OpDev& op, const z64* c, double omega, hipStream_t s) {
+  hipLaunchKernelGGL(k_sigma, dim3(2048), dim3(256), 0, s, op, c, omega, const_cast<z64*>(op.sigma));
+}
+
+static int pick_nr(int nrhs) {
+  if (nrhs % 8 == 0) return 8;
+  if (nrhs % 4 == 0) return 4;
+  if (nrhs % 2 == 0) return 2;
+  return 1;
+}
+
+static void stencil_dispatch(const OpDev& op, int nrhs, const z64* x, z64* y, const z64* b, hipStream_t s) {
+  const long long n = (long long)op.nx * op.ny * op.nz;
+  const int nr = pick_nr(nrhs);
+  const long long threads = n * (nrhs / nr);
+  dim3 grid((unsigned)ceil_div(threads, 256));
+  switch (nr) {
+    case 8: hipLaunchKernelGGL(k_stencil<8>, grid, dim3(256), 0, s, op, nrhs, x, y, b); break;
+    case 4: hipLaunchKernelGGL(k_stencil<4>, grid, dim3(256), 0, s, op, nrhs, x, y, b); break;
+    case 2: hipLaunchKernelGGL(k_stencil<2>, grid, dim3(256), 0, s, op, nrhs, x, y, b); break;
+    default: hipLaunchKernelGGL(k_stencil<1>, grid, dim3(256), 0, s, op, nrhs, x, y, b); break;
+  }
+}
+
+void launch_stencil(const OpDev& op, int nrhs, const z64* x, z64* y, hipStream_t s) {
+  stencil_dispatch(op, nrhs, x, y, nullptr, s);
+}
+
+void launch_residual(const OpDev& op, int nrhs, const z64* b, const z64* x, z64* y, hipStream_t s) {
+  stencil_dispatch(op, nrhs, x, y, b, s);
+}
+
+void launch_build_E(const OpDev& op, int ncx, int ncy, int ncz, z64* E, hipStream_t s) {
+  const long long nc = (long long)ncx * ncy * ncz;
+  hipLaunchKernelGGL(k_build_E, dim3((unsigned)ceil_div(nc, 64)), dim3(64), 0, s, op, ncx, ncy, ncz, E);
+}
+
+void launch_coarse_spmv(int ncx, int ncy, int ncz, const z64* E, int nrhs, const z64* x, z64* y,
+                        hipStream_t s) {
+  const long long nc = (long long)ncx * ncy * ncz;
+  const int nr = pick_nr(nrhs);
+  dim3 grid((unsigned)ceil_div(nc * (nrhs / nr), 256));
+  switch (nr) {
+    case 8: hipLaunchKernelGGL(k_coarse_spmv<8>, grid, dim3(256), 0, s, ncx, ncy, ncz, E, nrhs, x, y); break;
+    case 4: hipLaunchKernelGGL(k_coarse_spmv<4>, grid, dim3(256), 0, s, ncx, ncy, ncz, E, nrhs, x, y); break;
+    case 2: hipLaunchKernelGGL(k_coarse_spmv<2>, grid, dim3(256), 0, s, ncx, ncy, ncz, E, nrhs, x, y); break;
+    default: hipLaunchKernelGGL(k_coarse_spmv<1>, grid, dim3(256), 0, s, ncx, ncy, ncz, E, nrhs, x, y); break;
+  }
+}
+
+void launch_restrict(int nx, int ny, int nz, int nrhs, const z64* r, z64* c, hipStream_t s) {
+  const long long nc = (long long)((nx + 1) / 2) * ((ny + 1) / 2) * ((nz + 1) / 2);
+  hipLaunchKernelGGL(k_restrict, dim3((unsigned)ceil_div(nc * nrhs, 256)), dim3(256), 0, s, nx, ny, nz, nrhs, r, c);
+}
+
+void launch_prolong(int nx, int ny, int nz, int nrhs, const z64* c, z64* q, hipStream_t s) {
+  const long long n = (long long)nx * ny * nz;
+  hipLaunchKernelGGL(k_prolong, dim3((unsigned)ceil_div(n * nrhs, 256)), dim3(256), 0, s, nx, ny, nz, nrhs, c, q);
+}

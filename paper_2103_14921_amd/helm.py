@@ -1,0 +1,233 @@
+"""Thin Python binding of the C ABI in include/helm.h (ctypes; argument marshalling only).
+
+Every arithmetic step runs in the HIP library ``libhelm.so`` built in-tree by
+``paper_2103_14921_amd.build``.  There is no fallback: importing this module
+without the built library raises.  Fields may be NumPy arrays (host memory) or
+torch tensors on the GPU (device memory); outputs come back as the same kind.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhelm.so")
+
+HELM_OK, HELM_NOT_CONVERGED = 0, 1
+HELM_EINVAL, HELM_ENOMEM, HELM_EDEVICE, HELM_EBREAKDOWN = -1, -2, -3, -4
+HELM_FP64, HELM_MIXED = 0, 1
+HELM_X0 = 1
+
+EXPORTS = [
+    "helm_fit_weights", "helm_setup", "helm_solve", "helm_footprint", "helm_resident_bytes",
+    "helm_last_timings", "helm_destroy", "helm_last_error", "helm_set_stream", "helm_apply_A",
+    "helm_apply_M", "helm_apply_oras", "helm_restrict", "helm_prolong", "helm_apply_E", "helm_apply_Q",
+    "helm_num_subdomains", "helm_subdomain_box",
+]
+
+
+class HelmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"helm status {code}: {msg}")
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("h", C.c_double)]
+
+
+class PmlT(C.Structure):
+    _fields_ = [("npml_x", C.c_int32), ("npml_y", C.c_int32), ("npml_zbot", C.c_int32),
+                ("npml_ztop", C.c_int32), ("R", C.c_double)]
+
+
+class WeightsT(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("w1", "w2", "w3", "wm1", "wm2", "wm3", "wm4")]
+
+
+class DecompT(C.Structure):
+    _fields_ = [(k, C.c_int32) for k in ("px", "py", "pz", "overlap", "levels", "coarse_iters",
+                                         "precision", "restart", "robin", "nrhs_chunk")]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2103_14921_amd.build.build()")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    i32 = C.c_int32
+    sig = {
+        "helm_fit_weights": ([C.c_double, C.c_double, i32, i32, C.POINTER(WeightsT)], C.c_int),
+        "helm_setup": ([C.POINTER(Grid), P, C.c_double, C.POINTER(PmlT), C.POINTER(WeightsT),
+                        C.POINTER(DecompT), C.POINTER(P)], C.c_int),
+        "helm_solve": ([P, i32, P, P, C.c_double, i32, C.c_uint32, P, P, P], C.c_int),
+        "helm_footprint": ([C.POINTER(Grid), C.POINTER(DecompT), i32], C.c_size_t),
+        "helm_resident_bytes": ([P], C.c_size_t),
+        "helm_last_timings": ([P, C.POINTER(C.c_double)], C.c_int),
+        "helm_destroy": ([P], None),
+        "helm_last_error": ([], C.c_char_p),
+        "helm_set_stream": ([P, P], C.c_int),
+        "helm_apply_A": ([P, i32, P, P], C.c_int),
+        "helm_apply_M": ([P, i32, P, P], C.c_int),
+        "helm_apply_oras": ([P, i32, i32, P, P], C.c_int),
+        "helm_restrict": ([P, i32, P, P], C.c_int),
+        "helm_prolong": ([P, i32, P, P], C.c_int),
+        "helm_apply_E": ([P, i32, P, P], C.c_int),
+        "helm_apply_Q": ([P, i32, P, P], C.c_int),
+        "helm_num_subdomains": ([P, i32], i32),
+        "helm_subdomain_box": ([P, i32, i32, C.POINTER(i32)], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def last_error():
+    return lib.helm_last_error().decode()
+
+
+def _check(code, ok=(HELM_OK,)):
+    if code not in ok:
+        raise HelmError(code, last_error())
+    return code
+
+
+def fit_weights(gmin=4.0, gmax=10.0, ng=7, nang=15):
+    w = WeightsT()
+    _check(lib.helm_fit_weights(gmin, gmax, ng, nang, C.byref(w)))
+    return {k: getattr(w, k) for k, _ in WeightsT._fields_}
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a, n_expect):
+    """Pointer of a contiguous complex128 buffer holding n_expect elements."""
+    if _is_torch(a):
+        import torch
+        if a.dtype != torch.complex128 or not a.is_contiguous() or a.numel() != n_expect:
+            raise ValueError("expected a contiguous complex128 tensor of %d elements" % n_expect)
+        return C.c_void_p(a.data_ptr())
+    if not isinstance(a, np.ndarray) or a.dtype != np.complex128 or not a.flags.c_contiguous or a.size != n_expect:
+        raise ValueError("expected a C-contiguous complex128 array of %d elements" % n_expect)
+    return C.c_void_p(a.ctypes.data)
+
+
+def _empty_like_kind(a, shape):
+    if _is_torch(a):
+        import torch
+        return torch.empty(shape, dtype=torch.complex128, device=a.device)
+    return np.empty(shape, dtype=np.complex128)
+
+
+def footprint(shape, parts, overlap=2, levels=1, coarse_iters=10, precision="fp64", restart=30, nrhs_chunk=1):
+    g = Grid(*shape, 1.0)
+    d = DecompT(*parts, overlap, levels, coarse_iters, HELM_MIXED if precision == "mixed" else HELM_FP64,
+                restart, 1, nrhs_chunk)
+    return lib.helm_footprint(C.byref(g), C.byref(d), nrhs_chunk)
+
+
+class Solver:
+    """A set-up problem (helm_setup); owns the library handle."""
+
+    def __init__(self, shape, h, velocity, freq, pml=(0, 0, 0, 0), weights=None, parts=(1, 1, 1), overlap=2,
+                 levels=1, coarse_iters=10, precision="fp64", restart=30, robin=True, nrhs_chunk=0, R=1e-3):
+        self.shape = tuple(int(v) for v in shape)
+        nx, ny, nz = self.shape
+        self.n = nx * ny * nz
+        self.levels = levels
+        self.cshape = tuple((v + 1) // 2 for v in self.shape)
+        self.nc = int(np.prod(self.cshape))
+        g = Grid(nx, ny, nz, float(h))
+        p = PmlT(*[int(v) for v in pml], float(R))
+        d = DecompT(*[int(v) for v in parts], int(overlap), int(levels), int(coarse_iters),
+                    HELM_MIXED if precision == "mixed" else HELM_FP64, int(restart), 1 if robin else 0,
+                    int(nrhs_chunk))
+        w = None
+        if weights is not None:
+            if not isinstance(weights, dict):
+                weights = {k: float(getattr(weights, k)) for k, _ in WeightsT._fields_}
+            w = WeightsT(**{k: float(weights[k]) for k, _ in WeightsT._fields_})
+        vel = velocity if _is_torch(velocity) else np.ascontiguousarray(velocity, dtype=np.complex128)
+        handle = C.c_void_p()
+        _check(lib.helm_setup(C.byref(g), _ptr(vel, self.n), float(freq), C.byref(p),
+                              C.byref(w) if w is not None else None, C.byref(d), C.byref(handle)))
+        self._h = handle
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.helm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, B, tol=1e-8, maxit=500, X0=None):
+        """Solve A X = B, B of shape [nrhs][nz][ny][nx] (or [nrhs][n]); returns (X, info)."""
+        nrhs = B.shape[0]
+        X = _empty_like_kind(B, tuple(B.shape)) if X0 is None else X0
+        flags = HELM_X0 if X0 is not None else 0
+        its = np.zeros(nrhs, np.int32)
+        est = np.zeros(nrhs)
+        tru = np.zeros(nrhs)
+        code = lib.helm_solve(self._h, nrhs, _ptr(B, nrhs * self.n), _ptr(X, nrhs * self.n), float(tol), int(maxit),
+                              flags, its.ctypes.data_as(C.c_void_p), est.ctypes.data_as(C.c_void_p),
+                              tru.ctypes.data_as(C.c_void_p))
+        _check(code, ok=(HELM_OK, HELM_NOT_CONVERGED))
+        return X, dict(status=code, iters=its, relres_est=est, relres_true=tru, timings=self.timings())
+
+    def timings(self):
+        out = (C.c_double * 5)()
+        _check(lib.helm_last_timings(self._h, out))
+        return dict(setup=out[0], solve=out[1], factor=out[2], coarse=out[3], iters_total=out[4])
+
+    def resident_bytes(self):
+        return lib.helm_resident_bytes(self._h)
+
+    def _map(self, fn, X, n_in, n_out, *lead):
+        nrhs = X.shape[0]
+        Y = _empty_like_kind(X, (nrhs, n_out))
+        _check(fn(self._h, *lead, nrhs, _ptr(X, nrhs * n_in), _ptr(Y, nrhs * n_out)))
+        return Y
+
+    def apply_A(self, X):
+        return self._map(lib.helm_apply_A, X, self.n, self.n)
+
+    def apply_M(self, R):
+        return self._map(lib.helm_apply_M, R, self.n, self.n)
+
+    def apply_oras(self, R, level=0):
+        n = self.n if level == 0 else self.nc
+        return self._map(lib.helm_apply_oras, R, n, n, int(level))
+
+    def restrict(self, R):
+        return self._map(lib.helm_restrict, R, self.n, self.nc)
+
+    def prolong(self, Cc):
+        return self._map(lib.helm_prolong, Cc, self.nc, self.n)
+
+    def apply_E(self, X):
+        return self._map(lib.helm_apply_E, X, self.nc, self.nc)
+
+    def apply_Q(self, R):
+        return self._map(lib.helm_apply_Q, R, self.n, self.n)
+
+    def num_subdomains(self, level=0):
+        return lib.helm_num_subdomains(self._h, int(level))
+
+    def subdomain_box(self, s, level=0):
+        box = (C.c_int32 * 12)()
+        _check(lib.helm_subdomain_box(self._h, int(level), int(s), box))
+        b = list(box)
+        return dict(elo=tuple(b[0:3]), ehi=tuple(b[3:6]), lo=tuple(b[6:9]), hi=tuple(b[9:12]))

@@ -1,0 +1,51 @@
+"""Host-side checks of the C ABI (CPU only): the library loads, exports every
+symbol include/helm.h declares, and its host-only weight fit agrees with the
+oracle's independent fit."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "helm.h")).read()
+    return sorted(set(re.findall(r"\b(helm_[a-z_A-Z0-9]+)\s*\(", src)))
+
+
+def test_header_declares_binding_exports():
+    from paper_2103_14921_amd import helm
+    assert sorted(helm.EXPORTS) == _declared()
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2103_14921_amd import helm
+    for name in _declared():
+        assert hasattr(helm.lib, name), name
+
+
+def test_native_weight_fit_matches_oracle():
+    from paper_2103_14921_amd import helm
+    from oracle.operator import fit_weights
+    a = helm.fit_weights()
+    b = fit_weights()
+    for k in a:
+        assert abs(a[k] - getattr(b, k)) <= 1e-10, k
+
+
+def test_fit_rejects_bad_arguments():
+    from paper_2103_14921_amd import helm
+    with pytest.raises(helm.HelmError) as e:
+        helm.fit_weights(ng=0)
+    assert e.value.code == helm.HELM_EINVAL
+
+
+def test_footprint_grows_with_rhs_and_rejects_bad_decomposition():
+    from paper_2103_14921_amd import helm
+    a = helm.footprint((64, 64, 64), (4, 4, 4), levels=2, nrhs_chunk=1)
+    b = helm.footprint((64, 64, 64), (4, 4, 4), levels=2, nrhs_chunk=8)
+    assert 0 < a < b
+    # boxes thinner than 2*overlap+1 are rejected (footprint 0)
+    assert helm.footprint((16, 16, 16), (8, 1, 1)) == 0

@@ -1,0 +1,209 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle, through the C ABI.
+
+Same seeded inputs on both sides (module ``inputs``), same stencil weights.
+Tolerances: operator-level FP64 pieces agree to rounding (relative 1e-12 for
+the stencil, 1e-10 for local solves, whose explicit block inverses carry a
+condition-number factor); complex-FP32 local solves to 5e-4; end-to-end FP64
+solves agree in iteration count and to a relative L2 of 10 x tol.
+"""
+import numpy as np
+import pytest
+
+import inputs
+from oracle.coarse import TwoLevel
+from oracle.dd import Oras, decompose
+from oracle.operator import Pml, Problem, assemble, fit_weights
+from oracle.solve import setup as oracle_setup
+from oracle.solve import solve as oracle_solve
+
+pytestmark = pytest.mark.gpu
+
+WO = fit_weights()
+W = {k: getattr(WO, k) for k in ("w1", "w2", "w3", "wm1", "wm2", "wm3", "wm4")}
+
+
+def helm():
+    from paper_2103_14921_amd import helm as h
+    return h
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+def _thrust_case(shape=(23, 19, 17), pml=(4, 3, 5, 2), q=100.0):
+    h, f = 25.0, 10.0
+    c = inputs.velocity_thrust_belt(*shape, h=h, q=q)
+    return shape, h, c, f, pml
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 8])
+def test_stencil_matches_csr(nrhs):
+    shape, h, c, f, pml = _thrust_case()
+    say("stencil", shape, nrhs)
+    prob = Problem(shape, h, c, f, Pml(*pml), WO)
+    A = assemble(prob)
+    S = helm().Solver(shape, h, c, f, pml, weights=W, parts=(1, 1, 1), levels=1)
+    X = inputs.random_field((nrhs, prob.n), seed=100 + nrhs)
+    Y = S.apply_A(X)
+    ref = (A @ X.T).T
+    assert np.max(np.abs(Y - ref)) <= 1e-12 * np.max(np.abs(ref))
+    S.close()
+
+
+@pytest.mark.parametrize("parts,delta,prec,tol", [((2, 2, 2), 2, "fp64", 1e-10), ((3, 2, 2), 2, "fp64", 1e-10),
+                                                  ((2, 2, 2), 2, "mixed", 5e-4)])
+def test_one_level_oras_matches_oracle(parts, delta, prec, tol):
+    shape, h, c, f, pml = _thrust_case(shape=(21, 18, 16), pml=(3, 3, 3, 0))
+    say("oras", shape, parts, prec)
+    prob = Problem(shape, h, c, f, Pml(*pml), WO)
+    A = assemble(prob)
+    boxes = decompose(shape, parts, delta)
+    M = Oras(A, shape, boxes, prob.k().ravel(), h)
+    S = helm().Solver(shape, h, c, f, pml, weights=W, parts=parts, overlap=delta, levels=1, precision=prec)
+    R = inputs.random_field((2, prob.n), seed=7)
+    Z = S.apply_oras(R)
+    for r in range(2):
+        assert rel(Z[r], M.apply(R[r])) <= tol
+    S.close()
+
+
+def test_coarse_pieces_match_oracle():
+    shape, h, c, f, pml = _thrust_case(shape=(20, 18, 17), pml=(3, 3, 3, 0))
+    say("coarse pieces", shape)
+    prob = Problem(shape, h, c, f, Pml(*pml), WO)
+    A = assemble(prob)
+    boxes = decompose(shape, (2, 2, 2), 2)
+    tl = TwoLevel(A, shape, boxes, prob.k().ravel(), h, 2)
+    S = helm().Solver(shape, h, c, f, pml, weights=W, parts=(2, 2, 2), overlap=2, levels=2)
+    R = inputs.random_field((2, prob.n), seed=8)
+    Cc = S.restrict(R)
+    assert rel(Cc, (tl.ZT @ R.T).T) <= 1e-14
+    P = S.prolong(Cc)
+    assert rel(P, (tl.Z @ Cc.T).T) <= 1e-14
+    Ec = S.apply_E(Cc)
+    assert rel(Ec, (tl.E @ Cc.T).T) <= 1e-12
+    Zc = S.apply_oras(Cc, level=1)
+    for r in range(2):
+        assert rel(Zc[r], tl.coarse.apply(Cc[r])) <= 1e-10
+    Q = S.apply_Q(R)
+    for r in range(2):
+        assert rel(Q[r], tl.q(R[r])) <= 1e-9
+    Mz = S.apply_M(R)
+    for r in range(2):
+        assert rel(Mz[r], tl.apply(R[r])) <= 1e-9
+    S.close()
+
+
+def test_config1_end_to_end_parity():
+    # 24^3, h = 50 m, c = 1500 + 0.7 z, 3.75 Hz, 6-node PML on sides and bottom,
+    # one-level ORAS 2x2x2, overlap 2, FGMRES(30), tol 1e-8, one source at (12, 12, 4)
+    shape, h, f, tol = (24, 24, 24), 50.0, 3.75, 1e-8
+    say("config1 e2e")
+    c = inputs.velocity_linear(*shape, h)
+    b = inputs.point_source_rhs(*shape, [(12, 12, 4)])
+    prob = Problem(shape, h, c, f, Pml(6, 6, 6, 0), WO)
+    st = oracle_setup(prob, (2, 2, 2), 2, 1)
+    ref = oracle_solve(st, b, tol, 30, 300)
+    S = helm().Solver(shape, h, c, f, (6, 6, 6, 0), weights=W, parts=(2, 2, 2), overlap=2, levels=1, restart=30)
+    X, info = S.solve(b, tol=tol, maxit=300)
+    say("iters gpu", info["iters"], "oracle", ref["iters"])
+    assert list(info["iters"]) == list(ref["iters"])
+    assert rel(X, ref["X"]) <= 10 * tol
+    assert info["relres_true"][0] <= tol
+    r = b.reshape(1, -1)[0] - st.A @ X.reshape(-1)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= tol
+    S.close()
+
+
+def test_two_level_end_to_end_parity_many_rhs():
+    shape, h, f, tol = (28, 26, 24), 25.0, 10.0, 1e-8
+    say("two-level e2e", shape)
+    c = inputs.velocity_thrust_belt(*shape, h=h)
+    src = inputs.source_grid(shape[0], shape[1], 5, 5, 2, 2, iz=4)
+    b = inputs.point_source_rhs(*shape, src)
+    prob = Problem(shape, h, c, f, Pml(5, 5, 5, 0), WO)
+    st = oracle_setup(prob, (2, 2, 2), 2, 2)
+    ref = oracle_solve(st, b, tol, 20, 300)
+    S = helm().Solver(shape, h, c, f, (5, 5, 5, 0), weights=W, parts=(2, 2, 2), overlap=2, levels=2, restart=20)
+    X, info = S.solve(b, tol=tol, maxit=300)
+    say("iters gpu", info["iters"], "oracle", ref["iters"])
+    assert list(info["iters"]) == list(ref["iters"])
+    for r in range(len(src)):
+        assert rel(X[r], ref["X"][r]) <= 10 * tol
+        assert info["relres_true"][r] <= tol
+    S.close()
+
+
+def test_mixed_precision_reaches_fp64_residual():
+    shape, h, f = (28, 26, 24), 25.0, 10.0
+    say("mixed e2e", shape)
+    c = inputs.velocity_thrust_belt(*shape, h=h)
+    src = inputs.source_grid(shape[0], shape[1], 5, 5, 2, 2, iz=4)
+    b = inputs.point_source_rhs(*shape, src)
+    prob = Problem(shape, h, c, f, Pml(5, 5, 5, 0), WO)
+    A = assemble(prob)
+    S64 = helm().Solver(shape, h, c, f, (5, 5, 5, 0), weights=W, parts=(2, 2, 2), overlap=2, levels=2, restart=20)
+    X64, i64 = S64.solve(b, tol=1e-10, maxit=300)
+    S = helm().Solver(shape, h, c, f, (5, 5, 5, 0), weights=W, parts=(2, 2, 2), overlap=2, levels=2, restart=20,
+                      precision="mixed")
+    X, info = S.solve(b, tol=1e-6, maxit=300)
+    say("mixed iters", info["iters"], "fp64(1e-10) iters", i64["iters"])
+    for r in range(len(src)):
+        tr = np.linalg.norm(b[r].ravel() - A @ X[r].ravel()) / np.linalg.norm(b[r])
+        assert tr <= 1e-6 and info["relres_true"][r] <= 1e-6
+        assert rel(X[r], X64[r]) <= 1e-3
+    S.close()
+    S64.close()
+
+
+def test_batch_equals_alone():
+    shape, h, f, tol = (24, 24, 24), 50.0, 3.75, 1e-8
+    say("batch invariance")
+    c = inputs.velocity_linear(*shape, h)
+    src = inputs.source_grid(24, 24, 6, 6, 3, 2, iz=4)
+    b = inputs.point_source_rhs(*shape, src)
+    S = helm().Solver(shape, h, c, f, (6, 6, 6, 0), weights=W, parts=(2, 2, 2), overlap=2, levels=2, restart=30)
+    Xb, ib = S.solve(b, tol=tol, maxit=200)
+    for r in range(len(src)):
+        Xa, ia = S.solve(np.ascontiguousarray(b[r:r + 1]), tol=tol, maxit=200)
+        assert ia["iters"][0] == ib["iters"][r]
+        assert rel(Xa[0], Xb[r]) <= 1e-12
+    S.close()
+
+
+def test_error_paths():
+    hm = helm()
+    shape = (16, 16, 16)
+    c = inputs.velocity_linear(*shape, 50.0)
+    bad = c.copy()
+    bad[3, 3, 3] = np.nan
+    say("errors")
+    with pytest.raises(hm.HelmError) as e:
+        hm.Solver(shape, 50.0, bad, 3.75, (4, 4, 4, 0), weights=W, parts=(2, 2, 2))
+    assert e.value.code == hm.HELM_EINVAL
+    neg = c.copy()
+    neg[0, 0, 0] = -1500.0
+    with pytest.raises(hm.HelmError) as e:
+        hm.Solver(shape, 50.0, neg, 3.75, (4, 4, 4, 0), weights=W, parts=(2, 2, 2))
+    assert e.value.code == hm.HELM_EINVAL
+    import os
+    os.environ["HELM_MEM_BUDGET"] = "1000"
+    try:
+        with pytest.raises(hm.HelmError) as e:
+            hm.Solver(shape, 50.0, c, 3.75, (4, 4, 4, 0), weights=W, parts=(2, 2, 2))
+        assert e.value.code == hm.HELM_ENOMEM
+    finally:
+        del os.environ["HELM_MEM_BUDGET"]
+    S = hm.Solver(shape, 50.0, c, 3.75, (4, 4, 4, 0), weights=W, parts=(2, 2, 2))
+    b = inputs.point_source_rhs(*shape, [(8, 8, 4), (4, 4, 4)])
+    b[1] = 0.0
+    X, info = S.solve(b, tol=1e-12, maxit=1)
+    assert info["status"] == hm.HELM_NOT_CONVERGED
+    assert info["iters"][0] == 1 and info["relres_true"][0] > 1e-12
+    assert info["iters"][1] == 0 and np.all(X[1] == 0)
+    S.close()
