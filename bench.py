@@ -1,0 +1,179 @@
+"""Benchmark: right-hand sides solved per second to a 1e-6 FP64 true residual.
+
+One step = the whole hot path on one batch: set-up (medium and PML, local
+operators with absorbing interfaces, block-tridiagonal factorisations, coarse
+operator and its factorisations) and the batched two-level ORAS-FGMRES solve
+of every right-hand side to a true relative residual of 1e-6.  Inputs
+(velocity and right-hand sides) are resident in HBM before the timed region.
+
+Default workload: seeded thrust-belt model on a 192^3 grid (h = 25 m, 10 Hz =
+8 points per minimum wavelength, 10-node PML on sides and bottom, Dirichlet
+top), 12 x 12 x 12 subdomains of 16^3 with overlap 2, two-level ORAS with the
+coarse grid at 2h, 64 point sources on an 8 x 8 grid at depth index 4; local
+factors and solves in complex FP32, everything else FP64 ("mixed").  The same
+workload is also run in plain FP64 and the error of the mixed solution against
+it is reported.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+WORKLOADS = {
+    # name: (shape, parts, n_src grid, restart)
+    "thrust192_mixed": dict(shape=(192, 192, 192), parts=(12, 12, 12), src=(8, 8), restart=20, levels=2,
+                            precision="mixed", tol=1e-6, q=None),
+    "thrust128_fp64": dict(shape=(128, 128, 128), parts=(4, 4, 4), src=(4, 2), restart=30, levels=2,
+                           precision="fp64", tol=1e-6, q=None),
+    "thrust256x128_q100": dict(shape=(256, 256, 128), parts=(16, 16, 8), src=(16, 8), restart=20, levels=2,
+                               precision="mixed", tol=1e-6, q=100.0),
+    "thrust96_small": dict(shape=(96, 96, 96), parts=(6, 6, 6), src=(4, 4), restart=20, levels=2,
+                           precision="mixed", tol=1e-6, q=None),
+}
+H, FREQ, NPML = 25.0, 10.0, 10
+
+
+def describe(name, w):
+    nx, ny, nz = w["shape"]
+    px, py, pz = w["parts"]
+    return (f"thrust-belt {nx}x{ny}x{nz}, h={H:g} m, {FREQ:g} Hz, PML {NPML}, {px}x{py}x{pz} boxes, overlap 2, "
+            f"two-level ORAS-FGMRES({w['restart']}), {w['src'][0] * w['src'][1]} RHS, tol {w['tol']:g}"
+            + (f", Q={w['q']:g}" if w["q"] else ""))
+
+
+def make_inputs(w):
+    import inputs
+    nx, ny, nz = w["shape"]
+    c = inputs.velocity_thrust_belt(nx, ny, nz, H, q=w["q"])
+    src = inputs.source_grid(nx, ny, NPML, NPML, w["src"][0], w["src"][1], iz=4)
+    b = inputs.point_source_rhs(nx, ny, nz, src)
+    return c, b
+
+
+def gpu_solve(helm, w, c_dev, b_dev, precision, weights):
+    S = helm.Solver(w["shape"], H, c_dev, FREQ, (NPML, NPML, NPML, 0), weights=weights, parts=w["parts"],
+                    overlap=2, levels=w["levels"], coarse_iters=10, precision=precision, restart=w["restart"])
+    X, info = S.solve(b_dev, tol=w["tol"], maxit=400)
+    S.close()
+    return X, info
+
+
+def cpu_baseline(w, its_per_rhs, nrhs, budget_s=25.0):
+    """Oracle on a bounded sample of the workload, extrapolated to the full job.
+
+    Sample: the same physics, spacing, box size (cores of 16^3 + overlap 2) and
+    two-level method on a 3x3x3-box grid, one right-hand side.  Set-up cost
+    scales with the number of boxes; solve cost per iteration with the number
+    of boxes; the full job takes the GPU's iteration counts.
+    """
+    import inputs
+    from oracle.operator import Pml, Problem, fit_weights
+    from oracle.solve import setup, solve
+
+    core = w["shape"][0] // w["parts"][0]
+    ns = 3 * core
+    nboxes_full = int(np.prod(w["parts"]))
+    workers = min(os.cpu_count() or 1, 16)
+    c = inputs.velocity_thrust_belt(ns, ns, ns, H, q=w["q"])
+    src = inputs.source_grid(ns, ns, NPML, NPML, 1, 1, iz=4)
+    b = inputs.point_source_rhs(ns, ns, ns, src)
+    prob = Problem((ns, ns, ns), H, c, FREQ, Pml(NPML, NPML, NPML, 0), fit_weights())
+    t0 = time.perf_counter()
+    st = setup(prob, (3, 3, 3), 2, 2, workers=workers)
+    t_setup = time.perf_counter() - t0
+    res = solve(st, b, w["tol"], w["restart"], 60)
+    it_s = max(1, int(res["iters"][0]))
+    t_iter = res["t_solve"] / it_s
+    scale = nboxes_full / 27.0
+    t_full = t_setup * scale + t_iter * scale * float(np.sum(its_per_rhs))
+    return {"value": nrhs / t_full, "unit": "RHS/s", "cores": workers, "kind": "oracle",
+            "sample": (f"oracle set-up + one FGMRES solve on a {ns}^3 grid with 3x3x3 boxes of the same size "
+                       f"({t_setup:.1f} s set-up on {workers} processes, {res['t_solve']:.1f} s for {it_s} "
+                       f"iterations on 1 core), scaled by {scale:.0f}x boxes and the GPU's iteration counts"),
+            "extrapolated": True}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="thrust192_mixed", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the solver is a single-device library (no collectives); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2103_14921_amd import helm
+
+    w = WORKLOADS[args.workload]
+    c, b = make_inputs(w)
+    nrhs = b.shape[0]
+    dev = torch.device("cuda:0")
+    c_dev = torch.from_numpy(c).to(dev)
+    b_dev = torch.from_numpy(np.ascontiguousarray(b.reshape(nrhs, -1))).to(dev)
+    weights = helm.fit_weights()
+    torch.cuda.synchronize()
+    print(f"[bench] {describe(args.workload, w)}", file=sys.stderr, flush=True)
+
+    for i in range(args.warmup):
+        _, info = gpu_solve(helm, w, c_dev, b_dev, w["precision"], weights)
+        print(f"[bench] warmup {i}: setup {info['timings']['setup']:.3f} s solve {info['timings']['solve']:.3f} s "
+              f"iters {info['iters'].tolist()}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    setups, solves, infos = [], [], []
+    for i in range(args.steps):
+        X, info = gpu_solve(helm, w, c_dev, b_dev, w["precision"], weights)
+        setups.append(info["timings"]["setup"])
+        solves.append(info["timings"]["solve"])
+        infos.append(info)
+        print(f"[bench] step {i}: setup {setups[-1]:.3f} s solve {solves[-1]:.3f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    info = infos[-1]
+    value = nrhs * args.steps / T
+    out = {
+        "metric": "RHS solved/s to 1e-6 residual (mixed ORAS-FGMRES; FP64 form alongside)",
+        "value": value, "unit": "RHS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * T / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64 local factors/solves, c128 elsewhere" if w["precision"] == "mixed" else "c128",
+        "data": "synthetic (seeded thrust-belt velocity, unit point sources)",
+        "config": {"workload": describe(args.workload, w), "grid": list(w["shape"]), "boxes": list(w["parts"]),
+                   "nrhs": nrhs, "tol": w["tol"], "precision": w["precision"]},
+        "solve_only_rhs_per_s": nrhs / float(np.mean(solves)),
+        "setup_s": float(np.mean(setups)), "solve_s": float(np.mean(solves)),
+        "iters": {"min": int(info["iters"].min()), "max": int(info["iters"].max()),
+                  "mean": float(info["iters"].mean())},
+        "max_true_relres": float(info["relres_true"].max()),
+    }
+    if not args.no_fp64 and w["precision"] == "mixed":
+        X64, i64 = gpu_solve(helm, w, c_dev, b_dev, "fp64", weights)
+        t64 = i64["timings"]["setup"] + i64["timings"]["solve"]
+        err = torch.linalg.vector_norm(X - X64, dim=1) / torch.linalg.vector_norm(X64, dim=1)
+        out["fp64_form"] = {"rhs_per_s": nrhs / t64, "solve_only_rhs_per_s": nrhs / i64["timings"]["solve"],
+                            "setup_s": i64["timings"]["setup"], "solve_s": i64["timings"]["solve"],
+                            "iters_mean": float(i64["iters"].mean()),
+                            "max_true_relres": float(i64["relres_true"].max())}
+        out["mixed_vs_fp64_rel_l2_max"] = float(err.max().item())
+        out["speedup_mixed_vs_fp64"] = value / out["fp64_form"]["rhs_per_s"]
+        del X64
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, info["iters"], nrhs)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

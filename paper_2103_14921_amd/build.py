@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhelm.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["ops_operator.hip", "ops_local.hip", "ops_krylov.hip", "helm_api.hip"]
+SOURCES = ["ops_operator.hip", "ops_local.hip", "ops_sweep.hip", "ops_krylov.hip", "helm_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

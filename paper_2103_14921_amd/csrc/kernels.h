@@ -43,6 +43,14 @@ struct Factor {
                     int gnx, int gny, cpx<T>* yloc, cpx<T>* tbuf, hipStream_t s);
 };
 
+// Fused single-launch ORAS local solves on matrix cores (ops_sweep.hip).
+// Returns false when the plane does not fit the kernel's LDS budget.
+template <typename T>
+bool oras_fused(const Sub* subs, int nsub, int bpmax, const z64* aloc, const cpx<T>* sinv, int nrhs, const z64* u,
+                z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc, hipStream_t s);
+template <typename T>
+int fused_group(int bpmax, int nrhs);
+
 // ---- Krylov (ops_krylov.hip) -----------------------------------------------
 void launch_fill(z64* p, long long n, hipStream_t s);  // zero
 void launch_copy(const z64* a, z64* b, long long n, hipStream_t s);

@@ -13,6 +13,8 @@
 // Absorbing interface (Robin fold): for a box node l with a grid neighbour j
 // outside the box, A_i[l, l] += A[l, j] (1 + i k_l h) -- the ghost value is
 // replaced by the first-order outgoing condition u_j ~ (1 + i k h) u_l.
+#include <cstdlib>
+
 #include "kernels.h"
 #include "stencil_row.h"
 
@@ -541,6 +543,8 @@ template <typename T>
 void Factor<T>::sweep(const Sub* subs, int nsub, int bpmax, int maxez, const z64* aloc, const cpx<T>* sinv,
                       int nrhs, const z64* u, z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc,
                       cpx<T>* tbuf, hipStream_t s) {
+  static const bool no_fused = std::getenv("HELM_NO_FUSED") != nullptr;
+  if (!no_fused && oras_fused<T>(subs, nsub, bpmax, aloc, sinv, nrhs, u, z, add, gnx, gny, yloc, s)) return;
   dim3 gv((unsigned)ceil_div((long long)bpmax * nrhs, 256), nsub);
   const int nr = nrhs % 8 == 0 ? 8 : nrhs % 4 == 0 ? 4 : nrhs % 2 == 0 ? 2 : 1;
   dim3 gg((unsigned)ceil_div((long long)bpmax * (nrhs / nr), 256), nsub);

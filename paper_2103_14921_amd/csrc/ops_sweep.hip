@@ -1,0 +1,229 @@
+// Fused local solves of the ORAS preconditioner (eq. oras) on matrix cores.
+//
+// One workgroup owns one subdomain and one group of RG right-hand sides and
+// runs the whole block-tridiagonal solve in a single launch:
+//   forward   T_k = R_i u (plane k) - L_k y_{k-1};  y_k = Sinv_k T_k
+//   backward  T   = U_k x_{k+1};                    x_k = y_k - Sinv_k T
+// then scatters the core nodes of x (Boolean partition of unity), optionally
+// adding a second field.  The plane vector lives in LDS; the dense products
+// Sinv_k T stream Sinv_k from HBM through MFMA 16x16x4 tiles (operand lanes:
+// A[l%16][l/16], B[l/16][l%16]; output rows differ between f32 and f64).
+//
+// Complex products on real MFMA: with Sinv stored interleaved (re, im) it is a
+// real bp x 2bp matrix A; the plane vector T (bp x RG complex) is expanded on
+// the fly into the real 2bp x 2RG matrix
+//   B[2q][2r] = Re T[q][r]    B[2q][2r+1] = Im T[q][r]
+//   B[2q+1][2r] = -Im T[q][r] B[2q+1][2r+1] = Re T[q][r]
+// so that A B is the interleaved complex product (4 real products, one pass).
+#include "kernels.h"
+
+namespace {
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // output element v of lane group lg (lane / 16) sits in tile row 4 lg + v
+  static __device__ __forceinline__ int row(int lg, int v) { return 4 * lg + v; }
+};
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // the f64 variant interleaves its rows: element v of lane group lg is tile row lg + 4 v
+  static __device__ __forceinline__ int row(int lg, int v) { return lg + 4 * v; }
+};
+
+constexpr int FT = 512;  // threads per workgroup (8 waves)
+
+// Y rows of the wave's M-tiles = Sinv_k rows x Bs (T), one 16-row tile at a time;
+// out(p, r, nb, value) receives each real output entry.
+template <typename T, int RG, typename Out>
+__device__ __forceinline__ void plane_product(const cpx<T>* __restrict__ Sk, int bp, const cpx<T>* Bs, int wave,
+                                              int lane, Out&& out) {
+  using V4 = typename Mfma<T>::v4;
+  constexpr int NT = RG / 8;  // MFMA column tiles (16 real columns = 8 complex)
+  const int lrow = lane & 15, lg = lane >> 4, nb = lane & 1;
+  const int nmt = bp >> 4;
+  const cpx<T>* Bcol = Bs + 4 * lg * RG + (lrow >> 1);
+  for (int mt = wave; mt < nmt; mt += FT / 64) {
+    V4 acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = V4{0, 0, 0, 0};
+    const cpx<T>* Arow = Sk + (long long)(mt * 16 + lrow) * bp + 4 * lg;
+    cpx<T> a[4], an[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) a[t] = Arow[t];
+    for (int kc = 0; kc < bp; kc += 16) {
+      if (kc + 16 < bp) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) an[t] = Arow[kc + 16 + t];
+      }
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        cpx<T> tv[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) tv[t] = Bcol[(kc + t) * RG + nt * 8];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          acc[nt] = Mfma<T>::op(a[t].re, nb ? tv[t].im : tv[t].re, acc[nt]);
+          acc[nt] = Mfma<T>::op(a[t].im, nb ? tv[t].re : -tv[t].im, acc[nt]);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) a[t] = an[t];
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out(mt * 16 + Mfma<T>::row(lg, v), nt * 8 + ((lane & 15) >> 1), nb, acc[nt][v]);
+  }
+}
+
+// LDS: Bs (T, the product's right operand) and Ys (y or x of the current plane), each [bp][RG].
+template <typename T, int RG>
+__global__ void __launch_bounds__(FT) k_oras_fused(const Sub* __restrict__ subs, int ngroups, int nrhs, int bpmax,
+                                                   const z64* __restrict__ aloc, const cpx<T>* __restrict__ sinv,
+                                                   const z64* __restrict__ u, z64* __restrict__ z,
+                                                   const z64* __restrict__ add, int gnx, int gny,
+                                                   cpx<T>* __restrict__ yloc) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* Bs = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* Ys = Bs + (long long)bpmax * RG;
+  T* Ysr = reinterpret_cast<T*>(Ys);
+  const int s = blockIdx.x / ngroups, g = blockIdx.x % ngroups;
+  const Sub sb = subs[s];
+  const int r0 = g * RG;
+  const int nrg = min(RG, nrhs - r0);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int bp = sb.bp, b = sb.b, ex = sb.ex, ey = sb.ey, ez = sb.ez;
+  const int cx0 = sb.lo[0] - sb.elo[0], cx1 = sb.hi[0] - sb.elo[0];
+  const int cy0 = sb.lo[1] - sb.elo[1], cy1 = sb.hi[1] - sb.elo[1];
+  const int cz0 = sb.lo[2] - sb.elo[2], cz1 = sb.hi[2] - sb.elo[2];
+  T* yl = reinterpret_cast<T*>(yloc + sb.vec_off * (long long)nrhs);
+
+  auto gnode = [&](int k, int p) -> long long {
+    const int px = p % ex, py = p / ex;
+    return (sb.elo[0] + px) + (long long)gnx * ((sb.elo[1] + py) + (long long)gny * (sb.elo[2] + k));
+  };
+  // coupling of plane k to plane k+dz (dz = -1: L_k, +1: U_k) applied to Ys
+  auto couple = [&](int k, int p, int r, int dz) -> cpx<T> {
+    const int px = p % ex, py = p / ex;
+    const z64* row = aloc + (sb.node_off + (long long)k * b + p) * 27 + (dz + 1) * 9;
+    cpx<T> v = mk<T>(0, 0);
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int cy = py + dy;
+      if (cy < 0 || cy >= ey) continue;
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int cx = px + dx;
+        if (cx < 0 || cx >= ex) continue;
+        cfma(v, ccast<T>(row[(dy + 1) * 3 + (dx + 1)]), Ys[(cx + ex * cy) * RG + r]);
+      }
+    }
+    return v;
+  };
+  auto scatter = [&](int k) {
+    if (k < cz0 || k >= cz1) return;
+    for (int e = tid; e < b * RG; e += FT) {
+      const int p = e / RG, r = e % RG;
+      if (r >= nrg) continue;
+      const int px = p % ex, py = p / ex;
+      if (px < cx0 || px >= cx1 || py < cy0 || py >= cy1) continue;
+      const long long gi = gnode(k, p) * nrhs + r0 + r;
+      z64 v = ccast<double>(Ys[e]);
+      if (add) v += add[gi];
+      z[gi] = v;
+    }
+  };
+
+  // ---- forward sweep
+  for (int k = 0; k < ez; ++k) {
+    for (int e = tid; e < bp * RG; e += FT) {
+      const int p = e / RG, r = e % RG;
+      cpx<T> v = mk<T>(0, 0);
+      if (p < b && r < nrg) {
+        v = ccast<T>(u[gnode(k, p) * nrhs + r0 + r]);
+        if (k > 0) v = v - couple(k, p, r, -1);
+      }
+      Bs[e] = v;
+    }
+    __syncthreads();
+    plane_product<T, RG>(sinv + sb.mat_off + (long long)k * bp * bp, bp, Bs, wave, lane,
+                         [&](int p, int r, int nb, T val) {
+                           Ysr[(p * RG + r) * 2 + nb] = val;
+                           if (r < nrg) yl[(((long long)k * bp + p) * nrhs + r0 + r) * 2 + nb] = val;
+                         });
+    __syncthreads();
+  }
+  // ---- backward sweep: Ys holds x_{ez-1} = y_{ez-1}
+  scatter(ez - 1);
+  for (int k = ez - 2; k >= 0; --k) {
+    for (int e = tid; e < bp * RG; e += FT) {
+      const int p = e / RG, r = e % RG;
+      Bs[e] = (p < b && r < nrg) ? couple(k, p, r, +1) : mk<T>(0, 0);
+    }
+    __syncthreads();
+    plane_product<T, RG>(sinv + sb.mat_off + (long long)k * bp * bp, bp, Bs, wave, lane,
+                         [&](int p, int r, int nb, T val) {
+                           // y_k was written by this same thread in the forward sweep
+                           const T yv = r < nrg ? yl[(((long long)k * bp + p) * nrhs + r0 + r) * 2 + nb] : (T)0;
+                           Ysr[(p * RG + r) * 2 + nb] = yv - val;
+                         });
+    __syncthreads();
+    scatter(k);
+  }
+}
+
+template <typename T, int RG>
+void launch_fused_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, const z64* aloc,
+                    const cpx<T>* sinv, const z64* u, z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc,
+                    hipStream_t s) {
+  const size_t lds = 2 * (size_t)bpmax * RG * sizeof(cpx<T>);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_oras_fused<T, RG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_oras_fused<T, RG>), dim3(nsub * ngroups), dim3(FT), lds, s, subs, ngroups, nrhs, bpmax, aloc,
+                     sinv, u, z, add, gnx, gny, yloc);
+}
+
+}  // namespace
+
+// LDS budget of the fused kernel (two plane buffers)
+constexpr size_t FUSED_LDS = 150 * 1024;
+
+template <typename T>
+int fused_group(int bpmax, int nrhs) {
+  int rg = nrhs <= 8 ? 8 : (nrhs <= 16 ? 16 : 32);
+  while (rg >= 8 && 2 * (size_t)bpmax * rg * sizeof(cpx<T>) > FUSED_LDS) rg /= 2;
+  return rg >= 8 ? rg : 0;
+}
+
+template <typename T>
+bool oras_fused(const Sub* subs, int nsub, int bpmax, const z64* aloc, const cpx<T>* sinv, int nrhs, const z64* u,
+                z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc, hipStream_t s) {
+  const int rg = fused_group<T>(bpmax, nrhs);
+  if (rg == 0) return false;
+  const int ngroups = (nrhs + rg - 1) / rg;
+  switch (rg) {
+    case 8: launch_fused_t<T, 8>(subs, nsub, ngroups, nrhs, bpmax, aloc, sinv, u, z, add, gnx, gny, yloc, s); break;
+    case 16: launch_fused_t<T, 16>(subs, nsub, ngroups, nrhs, bpmax, aloc, sinv, u, z, add, gnx, gny, yloc, s); break;
+    default: launch_fused_t<T, 32>(subs, nsub, ngroups, nrhs, bpmax, aloc, sinv, u, z, add, gnx, gny, yloc, s); break;
+  }
+  return true;
+}
+
+template bool oras_fused<float>(const Sub*, int, int, const z64*, const c32*, int, const z64*, z64*, const z64*, int,
+                                int, c32*, hipStream_t);
+template bool oras_fused<double>(const Sub*, int, int, const z64*, const z64*, int, const z64*, z64*, const z64*, int,
+                                 int, z64*, hipStream_t);
+template int fused_group<float>(int, int);
+template int fused_group<double>(int, int);
