@@ -382,7 +382,7 @@ size_t ws_bytes(const helm_handle* H, int nr) {
   size_t b = sizeof(z64) * (size_t)H->n * nr * (3 + (m + 1) + m);
   b += level_ws_bytes(H->fine, nr);
   b += KrylovArrays::bytes(m, nr);
-  b += sizeof(z64) * 1024 * 32 * (size_t)nr + sizeof(double) * 1024 * (size_t)nr + 2 * sizeof(double) * nr;
+  b += sizeof(z64) * RED_BLOCKS * 32 * (size_t)nr + sizeof(double) * RED_BLOCKS * (size_t)nr + 2 * sizeof(double) * nr;
   if (H->two_level()) {
     const int ci = H->dec.coarse_iters;
     const size_t nc = (size_t)H->coarse.n;
@@ -422,8 +422,8 @@ void ensure_ws(helm_handle* H, int nr) {
   W.Zv.alloc(vec * m);
   W.yl_f.alloc((size_t)H->fine.vec_total * nr * elem_size(H->fine.prec));
   W.tb_f.alloc((size_t)H->fine.nsub * H->fine.bpmax * nr * elem_size(H->fine.prec));
-  W.zpart.alloc(sizeof(z64) * 1024 * 32 * (size_t)nr);
-  W.dpart.alloc(sizeof(double) * 1024 * (size_t)nr);
+  W.zpart.alloc(sizeof(z64) * RED_BLOCKS * 32 * (size_t)nr);
+  W.dpart.alloc(sizeof(double) * RED_BLOCKS * (size_t)nr);
   W.bn2.alloc(sizeof(double) * nr);
   W.beta2.alloc(sizeof(double) * nr);
   W.ko.alloc(m, nr);
@@ -469,8 +469,10 @@ void arnoldi_step(helm_handle* H, KrylovArrays& K, int j, const z64* V, z64* w, 
   const long long vs = len * nr;
   launch_norm2(w, len, nr, W.dpart.as<double>(), K.w0.as<double>(), H->stream);
   launch_dots(V, vs, j + 1, w, len, nr, W.zpart.as<z64>(), K.h.as<z64>(), H->stream);
-  launch_axpy_multi(V, vs, j + 1, K.h.as<z64>(), w, len, nr, W.dpart.as<double>(), nullptr, H->stream);
-  launch_dots(V, vs, j + 1, w, len, nr, W.zpart.as<z64>(), K.h2.as<z64>(), H->stream);
+  if (!launch_axpy_dots(V, vs, j + 1, K.h.as<z64>(), w, len, nr, W.zpart.as<z64>(), K.h2.as<z64>(), H->stream)) {
+    launch_axpy_multi(V, vs, j + 1, K.h.as<z64>(), w, len, nr, W.dpart.as<double>(), nullptr, H->stream);
+    launch_dots(V, vs, j + 1, w, len, nr, W.zpart.as<z64>(), K.h2.as<z64>(), H->stream);
+  }
   launch_axpy_multi(V, vs, j + 1, K.h2.as<z64>(), w, len, nr, W.dpart.as<double>(), K.nrm2.as<double>(), H->stream);
   launch_givens(K.st, j, tol, maxit, fixed, H->stream);
 }

@@ -52,6 +52,8 @@ template <typename T>
 int fused_group(int bpmax, int nrhs);
 
 // ---- Krylov (ops_krylov.hip) -----------------------------------------------
+// blocks of the two-stage reductions (sizes of the partial-sum buffers)
+constexpr int RED_BLOCKS = 4096;
 void launch_fill(z64* p, long long n, hipStream_t s);  // zero
 void launch_copy(const z64* a, z64* b, long long n, hipStream_t s);
 void launch_to_node_major(const z64* in, z64* out, long long len, int nrhs, hipStream_t s);
@@ -64,6 +66,10 @@ void launch_axpy_multi(const z64* V, long long vstride, int nv, const z64* h, z6
                        long long len, int nrhs, double* partial, double* nrm2, hipStream_t s);
 void launch_norm2(const z64* w, long long len, int nrhs, double* partial, double* nrm2,
                   hipStream_t s);
+// w -= sum_v h[v][r] V_v and h2[v][r] = sum_node conj(V_v) w (updated w), one pass;
+// false when nv or the batch is too large for the fused kernel
+bool launch_axpy_dots(const z64* V, long long vstride, int nv, const z64* h, z64* w, long long len, int nrhs,
+                      z64* partial, z64* h2, hipStream_t s);
 // out[node][r] = fac[r] * w[node][r]
 void launch_scale(const z64* w, const double* fac, z64* out, long long len, int nrhs, hipStream_t s);
 // x += sum_v y[v][r] Z_v

@@ -9,7 +9,7 @@
 
 namespace {
 
-constexpr int NVMAX = 32;  // basis vectors handled by one dot-product launch
+constexpr int NVMAX = 16;  // basis vectors handled by one dot-product / update launch
 
 __global__ void k_fill(z64* p, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -96,24 +96,35 @@ __global__ void __launch_bounds__(256) k_dots(const z64* __restrict__ V, long lo
   }
 #pragma unroll
   for (int v = 0; v < NVMAX; ++v) {
-    if (v >= nv) break;
-    red[tid] = (lane < nl) ? acc[v] : mk(0.0, 0.0);
-    __syncthreads();
-    if (lane == 0) {
-      z64 s = red[r];
-      for (int l = 1; l < nl; ++l) s += red[l * nrhs + r];
-      partial[((long long)blockIdx.x * nv + v) * nrhs + r] = s;
+    if (v < nv) {  // uniform over the block
+      red[tid] = (lane < nl) ? acc[v] : mk(0.0, 0.0);
+      __syncthreads();
+      if (lane == 0) {
+        z64 s = red[r];
+        for (int l = 1; l < nl; ++l) s += red[l * nrhs + r];
+        partial[((long long)blockIdx.x * nv + v) * nrhs + r] = s;
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
-__global__ void k_dots_final(const z64* __restrict__ partial, int nblk, int nv, int nrhs, z64* __restrict__ h) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nv * nrhs) return;
+// out[t] = sum_b partial[b][t] for t < nout: 32 outputs per block, 8 lanes each, fixed order
+__global__ void __launch_bounds__(256) k_dots_final(const z64* __restrict__ partial, int nblk, int nv, int nrhs,
+                                                    z64* __restrict__ h) {
+  __shared__ z64 red[256];
+  const int nout = nv * nrhs;
+  const int t = blockIdx.x * 32 + (threadIdx.x & 31), lane = threadIdx.x >> 5;
   z64 s = mk(0.0, 0.0);
-  for (int b = 0; b < nblk; ++b) s += partial[(long long)b * nv * nrhs + t];
-  h[t] = s;
+  if (t < nout)
+    for (int b = lane; b < nblk; b += 8) s += partial[(long long)b * nout + t];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (lane == 0 && t < nout) {
+    z64 a = red[threadIdx.x];
+    for (int l = 1; l < 8; ++l) a += red[threadIdx.x + 32 * l];
+    h[t] = a;
+  }
 }
 
 // w -= sum_v h[v][r] V_v; partial[blk][r] = sum |w|^2 over the block's nodes (if partial)
@@ -151,6 +162,55 @@ __global__ void __launch_bounds__(256) k_axpy_multi(const z64* __restrict__ V, l
   }
 }
 
+// Fused CGS pass: w -= sum_v h[v][r] V_v, then partial[blk][v][r] = sum conj(V_v) w
+// over the block's nodes -- the update of the first Gram-Schmidt pass and the
+// projections of the second in one read of the basis.
+__global__ void __launch_bounds__(256) k_axpy_dots(const z64* __restrict__ V, long long vstride, int nv,
+                                                   const z64* __restrict__ h, z64* __restrict__ w, long long len,
+                                                   int nrhs, z64* __restrict__ partial) {
+  extern __shared__ z64 hs[];  // [nv][nrhs]
+  __shared__ z64 red[256];
+  const int tid = threadIdx.x;
+  for (int t = tid; t < nv * nrhs; t += 256) hs[t] = h[t];
+  __syncthreads();
+  const int nl = 256 / nrhs;
+  const int r = tid % nrhs, lane = tid / nrhs;
+  const Span sp = block_span(len);
+  z64 acc[NVMAX];
+#pragma unroll
+  for (int v = 0; v < NVMAX; ++v) acc[v] = mk(0.0, 0.0);
+  if (lane < nl) {
+    for (long long nd = sp.lo + lane; nd < sp.hi; nd += nl) {
+      const long long e = nd * nrhs + r;
+      z64 x = w[e];
+      z64 vv[NVMAX];
+#pragma unroll
+      for (int v = 0; v < NVMAX; ++v)
+        if (v < nv) {
+          vv[v] = V[(long long)v * vstride + e];
+          cfms(x, hs[v * nrhs + r], vv[v]);
+        }
+      w[e] = x;
+#pragma unroll
+      for (int v = 0; v < NVMAX; ++v)
+        if (v < nv) cdot_acc(acc[v], vv[v], x);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < NVMAX; ++v) {
+    if (v < nv) {  // uniform over the block
+      red[tid] = (lane < nl) ? acc[v] : mk(0.0, 0.0);
+      __syncthreads();
+      if (lane == 0) {
+        z64 sacc = red[r];
+        for (int l = 1; l < nl; ++l) sacc += red[l * nrhs + r];
+        partial[((long long)blockIdx.x * nv + v) * nrhs + r] = sacc;
+      }
+      __syncthreads();
+    }
+  }
+}
+
 __global__ void __launch_bounds__(256) k_norm2(const z64* __restrict__ w, long long len, int nrhs,
                                                double* __restrict__ partial) {
   __shared__ double red[256];
@@ -160,6 +220,7 @@ __global__ void __launch_bounds__(256) k_norm2(const z64* __restrict__ w, long l
   const Span sp = block_span(len);
   double acc = 0.0;
   if (lane < nl)
+#pragma unroll 4
     for (long long nd = sp.lo + lane; nd < sp.hi; nd += nl) acc += abs2(w[nd * nrhs + r]);
   red[tid] = (lane < nl) ? acc : 0.0;
   __syncthreads();
@@ -170,12 +231,20 @@ __global__ void __launch_bounds__(256) k_norm2(const z64* __restrict__ w, long l
   }
 }
 
-__global__ void k_sum_final(const double* __restrict__ partial, int nblk, int nrhs, double* __restrict__ out) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrhs) return;
+__global__ void __launch_bounds__(256) k_sum_final(const double* __restrict__ partial, int nblk, int nrhs,
+                                                   double* __restrict__ out) {
+  __shared__ double red[256];
+  const int r = blockIdx.x * 32 + (threadIdx.x & 31), lane = threadIdx.x >> 5;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[(long long)b * nrhs + r];
-  out[r] = s;
+  if (r < nrhs)
+    for (int b = lane; b < nblk; b += 8) s += partial[(long long)b * nrhs + r];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (lane == 0 && r < nrhs) {
+    double a = red[threadIdx.x];
+    for (int l = 1; l < 8; ++l) a += red[threadIdx.x + 32 * l];
+    out[r] = a;
+  }
 }
 
 __global__ void k_scale(const z64* __restrict__ w, const double* __restrict__ fac, z64* __restrict__ out,
@@ -330,9 +399,9 @@ __global__ void k_backsolve(KrylovState st) {
 }
 
 int red_blocks(long long len) {
-  long long b = ceil_div(len, 2048);
+  long long b = ceil_div(len, 256);
   if (b < 1) b = 1;
-  if (b > 1024) b = 1024;
+  if (b > RED_BLOCKS) b = RED_BLOCKS;
   return (int)b;
 }
 
@@ -365,7 +434,7 @@ void launch_dots(const z64* V, long long vstride, int nv, const z64* w, long lon
   for (int v0 = 0; v0 < nv; v0 += NVMAX) {
     const int nvb = std::min(NVMAX, nv - v0);
     hipLaunchKernelGGL(k_dots, dim3(nblk), dim3(256), 0, s, V + v0 * vstride, vstride, nvb, w, len, nrhs, partial);
-    hipLaunchKernelGGL(k_dots_final, dim3((unsigned)ceil_div(nvb * nrhs, 256)), dim3(256), 0, s, partial, nblk, nvb,
+    hipLaunchKernelGGL(k_dots_final, dim3((unsigned)ceil_div(nvb * nrhs, 32)), dim3(256), 0, s, partial, nblk, nvb,
                        nrhs, h + (long long)v0 * nrhs);
   }
 }
@@ -380,13 +449,24 @@ void launch_axpy_multi(const z64* V, long long vstride, int nv, const z64* h, z6
                        h + (long long)v0 * nrhs, w, len, nrhs, (last && nrm2) ? partial : nullptr);
   }
   if (nrm2)
-    hipLaunchKernelGGL(k_sum_final, dim3((unsigned)ceil_div(nrhs, 256)), dim3(256), 0, s, partial, nblk, nrhs, nrm2);
+    hipLaunchKernelGGL(k_sum_final, dim3((unsigned)ceil_div(nrhs, 32)), dim3(256), 0, s, partial, nblk, nrhs, nrm2);
+}
+
+bool launch_axpy_dots(const z64* V, long long vstride, int nv, const z64* h, z64* w, long long len, int nrhs,
+                      z64* partial, z64* h2, hipStream_t s) {
+  if (nv > NVMAX || (size_t)nv * nrhs * sizeof(z64) > 64 * 1024) return false;
+  const int nblk = red_blocks(len);
+  hipLaunchKernelGGL(k_axpy_dots, dim3(nblk), dim3(256), (size_t)nv * nrhs * sizeof(z64), s, V, vstride, nv, h, w, len,
+                     nrhs, partial);
+  hipLaunchKernelGGL(k_dots_final, dim3((unsigned)ceil_div(nv * nrhs, 32)), dim3(256), 0, s, partial, nblk, nv, nrhs,
+                     h2);
+  return true;
 }
 
 void launch_norm2(const z64* w, long long len, int nrhs, double* partial, double* nrm2, hipStream_t s) {
   const int nblk = red_blocks(len);
   hipLaunchKernelGGL(k_norm2, dim3(nblk), dim3(256), 0, s, w, len, nrhs, partial);
-  hipLaunchKernelGGL(k_sum_final, dim3((unsigned)ceil_div(nrhs, 256)), dim3(256), 0, s, partial, nblk, nrhs, nrm2);
+  hipLaunchKernelGGL(k_sum_final, dim3((unsigned)ceil_div(nrhs, 32)), dim3(256), 0, s, partial, nblk, nrhs, nrm2);
 }
 
 void launch_scale(const z64* w, const double* fac, z64* out, long long len, int nrhs, hipStream_t s) {

@@ -89,51 +89,71 @@ __global__ void k_sigma(OpDev op, const z64* __restrict__ c, double omega, z64* 
 
 namespace {
 
-// General stencil: each thread computes NR right-hand sides of one node.
-template <int NR>
-__global__ void __launch_bounds__(256) k_stencil(OpDev op, int nrhs, const z64* __restrict__ x,
-                                                 z64* __restrict__ y, const z64* __restrict__ b) {
+// Stencil y = A x (or y = b - A x).  A block of 256 threads owns nb = 256/nrhs
+// (at most 64) consecutive nodes: phase 1 computes the 27 row coefficients of each node
+// once into LDS (shared by all right-hand sides), phase 2 maps one thread to
+// each (node, right-hand side) pair, right-hand side fastest, so that the
+// neighbour loads of a wave are contiguous.
+__global__ void __launch_bounds__(256) k_stencil2(OpDev op, int nrhs, const z64* __restrict__ x,
+                                                  z64* __restrict__ y, const z64* __restrict__ b) {
+  extern __shared__ z64 lds_coef[];
   const long long n = (long long)op.nx * op.ny * op.nz;
-  const int nch = nrhs / NR;
-  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= n * nch) return;
-  const long long i = t / nch;
-  const int r0 = (int)(t % nch) * NR;
-  const int ix = (int)(i % op.nx);
-  const long long q = i / op.nx;
-  const int iy = (int)(q % op.ny);
-  const int iz = (int)(q / op.ny);
-  const z64 si = op.sigma[i];
-  z64 acc[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) acc[r] = mk(0.0, 0.0);
-  z64 diag = op.wm[0] * si;
-  const bool flat = op.flat[op.off_int[0] + ix] && op.flat[op.off_int[1] + iy] && op.flat[op.off_int[2] + iz];
-#pragma unroll
-  for (int o = 0; o < 27; ++o) {
-    if (o == 13) continue;
+  const int nb = nrhs >= 256 ? 1 : (nrhs >= 4 ? 256 / nrhs : 64);
+  z64(*coef)[27] = reinterpret_cast<z64(*)[27]>(lds_coef);
+  z64(*stf)[27] = reinterpret_cast<z64(*)[27]>(lds_coef + nb * 27);
+  const long long i0 = (long long)blockIdx.x * nb;
+  const int tid = threadIdx.x;
+  // phase 1: coefficients (node a, offset o)
+  for (int t = tid; t < nb * 27; t += 256) {
+    const int a = t / 27, o = t % 27;
+    const long long i = i0 + a;
+    if (i >= n || o == 13) continue;
+    const int ix = (int)(i % op.nx);
+    const long long q = i / op.nx;
+    const int iy = (int)(q % op.ny);
+    const int iz = (int)(q / op.ny);
     const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
     const int cls = abs(ox) + abs(oy) + abs(oz);
-    z64 st;
-    if (flat) st = mk(op.alpha[cls - 1] * op.h2inv, 0.0);
-    else st = stiff_coef(op, ix, iy, iz, ox, oy, oz);
-    diag -= st;
+    const bool flat = op.flat[op.off_int[0] + ix] && op.flat[op.off_int[1] + iy] && op.flat[op.off_int[2] + iz];
+    const z64 st = flat ? mk(op.alpha[cls - 1] * op.h2inv, 0.0) : stiff_coef(op, ix, iy, iz, ox, oy, oz);
+    stf[a][o] = st;
     const int jx = ix + ox, jy = iy + oy, jz = iz + oz;
     if (jx >= 0 && jx < op.nx && jy >= 0 && jy < op.ny && jz >= 0 && jz < op.nz) {
       const long long j = jx + (long long)op.nx * (jy + (long long)op.ny * jz);
-      const z64 cf = st + (0.5 * op.wm[cls]) * (si + op.sigma[j]);
-      const z64* xj = x + j * nrhs + r0;
-#pragma unroll
-      for (int r = 0; r < NR; ++r) cfma(acc[r], cf, xj[r]);
+      coef[a][o] = st + (0.5 * op.wm[cls]) * (op.sigma[i] + op.sigma[j]);
+    } else {
+      coef[a][o] = mk(0.0, 0.0);
     }
   }
-  const z64* xi = x + i * nrhs + r0;
-  z64* yi = y + i * nrhs + r0;
+  __syncthreads();
+  for (int a = tid; a < nb; a += 256) {
+    const long long i = i0 + a;
+    if (i >= n) continue;
+    z64 d = op.wm[0] * op.sigma[i];
+    for (int o = 0; o < 27; ++o)
+      if (o != 13) d -= stf[a][o];
+    coef[a][13] = d;
+  }
+  __syncthreads();
+  // phase 2: one thread per (node, rhs)
+  for (int t = tid; t < nb * nrhs; t += 256) {
+    const int a = t / nrhs, r = t % nrhs;
+    const long long i = i0 + a;
+    if (i >= n) continue;
+    const int ix = (int)(i % op.nx);
+    const long long q = i / op.nx;
+    const int iy = (int)(q % op.ny);
+    const int iz = (int)(q / op.ny);
+    z64 acc = mk(0.0, 0.0);
 #pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    cfma(acc[r], diag, xi[r]);
-    if (b) yi[r] = b[i * nrhs + r0 + r] - acc[r];
-    else yi[r] = acc[r];
+    for (int o = 0; o < 27; ++o) {
+      const int jx = ix + o % 3 - 1, jy = iy + (o / 3) % 3 - 1, jz = iz + o / 9 - 1;
+      if (jx < 0 || jx >= op.nx || jy < 0 || jy >= op.ny || jz < 0 || jz >= op.nz) continue;
+      const long long j = jx + (long long)op.nx * (jy + (long long)op.ny * jz);
+      cfma(acc, coef[a][o], x[j * nrhs + r]);
+    }
+    if (b) y[i * nrhs + r] = b[i * nrhs + r] - acc;
+    else y[i * nrhs + r] = acc;
   }
 }
 
@@ -190,31 +210,28 @@ __global__ void k_build_E(OpDev op, int ncx, int ncy, int ncz, z64* __restrict__
   for (int o = 0; o < 27; ++o) E[I * 27 + o] = acc[o];
 }
 
-template <int NR>
-__global__ void __launch_bounds__(256) k_coarse_spmv(int ncx, int ncy, int ncz, const z64* __restrict__ E,
-                                                     int nrhs, const z64* __restrict__ x, z64* __restrict__ y) {
+// y = E x on the coarse grid: one thread per (coarse node, rhs), rhs fastest;
+// the 27 stored coefficients of a node are shared (broadcast) by its rhs lanes.
+__global__ void __launch_bounds__(256) k_coarse_spmv2(int ncx, int ncy, int ncz, const z64* __restrict__ E, int nrhs,
+                                                      const z64* __restrict__ x, z64* __restrict__ y) {
   const long long nc = (long long)ncx * ncy * ncz;
-  const int nch = nrhs / NR;
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= nc * nch) return;
-  const long long I = t / nch;
-  const int r0 = (int)(t % nch) * NR;
+  if (t >= nc * nrhs) return;
+  const long long I = t / nrhs;
+  const int r = (int)(t % nrhs);
   const int cx = (int)(I % ncx);
   const int cy = (int)((I / ncx) % ncy);
   const int cz = (int)(I / ((long long)ncx * ncy));
-  z64 acc[NR];
+  const z64* e = E + I * 27;
+  z64 acc = mk(0.0, 0.0);
 #pragma unroll
-  for (int r = 0; r < NR; ++r) acc[r] = mk(0.0, 0.0);
   for (int o = 0; o < 27; ++o) {
     const int jx = cx + o % 3 - 1, jy = cy + (o / 3) % 3 - 1, jz = cz + o / 9 - 1;
     if (jx < 0 || jx >= ncx || jy < 0 || jy >= ncy || jz < 0 || jz >= ncz) continue;
-    const z64 e = E[I * 27 + o];
     const long long J = jx + (long long)ncx * (jy + (long long)ncy * jz);
-#pragma unroll
-    for (int r = 0; r < NR; ++r) cfma(acc[r], e, x[J * nrhs + r0 + r]);
+    cfma(acc, e[o], x[J * nrhs + r]);
   }
-#pragma unroll
-  for (int r = 0; r < NR; ++r) y[I * nrhs + r0 + r] = acc[r];
+  y[t] = acc;
 }
 
 // c[I] = sum_i Z[i, I] r[i]   (Z^T, full weighting with weights 1, 1/2 per axis)
@@ -304,24 +321,11 @@ void launch_sigma(const OpDev& op, const z64* c, double omega, hipStream_t s) {
   hipLaunchKernelGGL(k_sigma, dim3(2048), dim3(256), 0, s, op, c, omega, const_cast<z64*>(op.sigma));
 }
 
-static int pick_nr(int nrhs) {
-  if (nrhs % 8 == 0) return 8;
-  if (nrhs % 4 == 0) return 4;
-  if (nrhs % 2 == 0) return 2;
-  return 1;
-}
-
 static void stencil_dispatch(const OpDev& op, int nrhs, const z64* x, z64* y, const z64* b, hipStream_t s) {
   const long long n = (long long)op.nx * op.ny * op.nz;
-  const int nr = pick_nr(nrhs);
-  const long long threads = n * (nrhs / nr);
-  dim3 grid((unsigned)ceil_div(threads, 256));
-  switch (nr) {
-    case 8: hipLaunchKernelGGL(k_stencil<8>, grid, dim3(256), 0, s, op, nrhs, x, y, b); break;
-    case 4: hipLaunchKernelGGL(k_stencil<4>, grid, dim3(256), 0, s, op, nrhs, x, y, b); break;
-    case 2: hipLaunchKernelGGL(k_stencil<2>, grid, dim3(256), 0, s, op, nrhs, x, y, b); break;
-    default: hipLaunchKernelGGL(k_stencil<1>, grid, dim3(256), 0, s, op, nrhs, x, y, b); break;
-  }
+  const int nb = nrhs >= 256 ? 1 : (nrhs >= 4 ? 256 / nrhs : 64);
+  hipLaunchKernelGGL(k_stencil2, dim3((unsigned)ceil_div(n, nb)), dim3(256), sizeof(z64) * 27 * 2 * nb, s, op, nrhs, x,
+                     y, b);
 }
 
 void launch_stencil(const OpDev& op, int nrhs, const z64* x, z64* y, hipStream_t s) {
@@ -340,14 +344,8 @@ void launch_build_E(const OpDev& op, int ncx, int ncy, int ncz, z64* E, hipStrea
 void launch_coarse_spmv(int ncx, int ncy, int ncz, const z64* E, int nrhs, const z64* x, z64* y,
                         hipStream_t s) {
   const long long nc = (long long)ncx * ncy * ncz;
-  const int nr = pick_nr(nrhs);
-  dim3 grid((unsigned)ceil_div(nc * (nrhs / nr), 256));
-  switch (nr) {
-    case 8: hipLaunchKernelGGL(k_coarse_spmv<8>, grid, dim3(256), 0, s, ncx, ncy, ncz, E, nrhs, x, y); break;
-    case 4: hipLaunchKernelGGL(k_coarse_spmv<4>, grid, dim3(256), 0, s, ncx, ncy, ncz, E, nrhs, x, y); break;
-    case 2: hipLaunchKernelGGL(k_coarse_spmv<2>, grid, dim3(256), 0, s, ncx, ncy, ncz, E, nrhs, x, y); break;
-    default: hipLaunchKernelGGL(k_coarse_spmv<1>, grid, dim3(256), 0, s, ncx, ncy, ncz, E, nrhs, x, y); break;
-  }
+  hipLaunchKernelGGL(k_coarse_spmv2, dim3((unsigned)ceil_div(nc * nrhs, 256)), dim3(256), 0, s, ncx, ncy, ncz, E, nrhs,
+                     x, y);
 }
 
 void launch_restrict(int nx, int ny, int nz, int nrhs, const z64* r, z64* c, hipStream_t s) {

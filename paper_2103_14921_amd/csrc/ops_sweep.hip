@@ -40,44 +40,58 @@ struct Mfma<double> {
   static __device__ __forceinline__ int row(int lg, int v) { return lg + 4 * v; }
 };
 
-constexpr int FT = 512;  // threads per workgroup (8 waves)
 
-// Y rows of the wave's M-tiles = Sinv_k rows x Bs (T), one 16-row tile at a time;
+// Make this workgroup's global stores visible to its other waves.
+__device__ __forceinline__ void wg_sync_global() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Rows of the wave's M-tiles of Sinv_k x Bs (Bs = T, [bp][RG] in LDS), one
+// 16-row tile at a time, with PF chunks of Sinv in flight per wave;
 // out(p, r, nb, value) receives each real output entry.
-template <typename T, int RG, typename Out>
+template <typename T, int RG, int PF, typename Out>
 __device__ __forceinline__ void plane_product(const cpx<T>* __restrict__ Sk, int bp, const cpx<T>* Bs, int wave,
-                                              int lane, Out&& out) {
+                                              int nwaves, int lane, Out&& out) {
   using V4 = typename Mfma<T>::v4;
   constexpr int NT = RG / 8;  // MFMA column tiles (16 real columns = 8 complex)
   const int lrow = lane & 15, lg = lane >> 4, nb = lane & 1;
   const int nmt = bp >> 4;
   const cpx<T>* Bcol = Bs + 4 * lg * RG + (lrow >> 1);
-  for (int mt = wave; mt < nmt; mt += FT / 64) {
+  for (int mt = wave; mt < nmt; mt += nwaves) {
     V4 acc[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[nt] = V4{0, 0, 0, 0};
     const cpx<T>* Arow = Sk + (long long)(mt * 16 + lrow) * bp + 4 * lg;
-    cpx<T> a[4], an[4];
+    cpx<T> a[PF][4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) a[t] = Arow[t];
-    for (int kc = 0; kc < bp; kc += 16) {
-      if (kc + 16 < bp) {
+    for (int j = 0; j < PF; ++j)
+      if (16 * j < bp)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) an[t] = Arow[kc + 16 + t];
-      }
+        for (int t = 0; t < 4; ++t) a[j][t] = Arow[16 * j + t];
+    for (int kc0 = 0; kc0 < bp; kc0 += 16 * PF) {
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        cpx<T> tv[4];
+      for (int j = 0; j < PF; ++j) {
+        const int kc = kc0 + 16 * j;
+        if (kc < bp) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) tv[t] = Bcol[(kc + t) * RG + nt * 8];
+          for (int nt = 0; nt < NT; ++nt) {
+            cpx<T> tv[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          acc[nt] = Mfma<T>::op(a[t].re, nb ? tv[t].im : tv[t].re, acc[nt]);
-          acc[nt] = Mfma<T>::op(a[t].im, nb ? tv[t].re : -tv[t].im, acc[nt]);
+            for (int t = 0; t < 4; ++t) tv[t] = Bcol[(kc + t) * RG + nt * 8];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              acc[nt] = Mfma<T>::op(a[j][t].re, nb ? tv[t].im : tv[t].re, acc[nt]);
+              acc[nt] = Mfma<T>::op(a[j][t].im, nb ? tv[t].re : -tv[t].im, acc[nt]);
+            }
+          }
+          const int kn = kc + 16 * PF;
+          if (kn < bp)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) a[j][t] = Arow[kn + t];
         }
       }
-#pragma unroll
-      for (int t = 0; t < 4; ++t) a[t] = an[t];
     }
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
@@ -86,63 +100,65 @@ __device__ __forceinline__ void plane_product(const cpx<T>* __restrict__ Sk, int
   }
 }
 
-// LDS: Bs (T, the product's right operand) and Ys (y or x of the current plane), each [bp][RG].
-template <typename T, int RG>
-__global__ void __launch_bounds__(FT) k_oras_fused(const Sub* __restrict__ subs, int ngroups, int nrhs, int bpmax,
+// LDS holds only the right operand T of the plane product ([bp][RG]); the
+// plane solutions y_k / x_k live in yloc and reach the other waves of the
+// workgroup through L2 (workgroup-scope release/acquire around the barrier).
+template <typename T, int RG, int PF>
+__global__ void __launch_bounds__(1024) k_oras_fused(const Sub* __restrict__ subs, int ngroups, int nrhs,
                                                    const z64* __restrict__ aloc, const cpx<T>* __restrict__ sinv,
                                                    const z64* __restrict__ u, z64* __restrict__ z,
                                                    const z64* __restrict__ add, int gnx, int gny,
                                                    cpx<T>* __restrict__ yloc) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* Bs = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* Ys = Bs + (long long)bpmax * RG;
-  T* Ysr = reinterpret_cast<T*>(Ys);
   const int s = blockIdx.x / ngroups, g = blockIdx.x % ngroups;
   const Sub sb = subs[s];
   const int r0 = g * RG;
   const int nrg = min(RG, nrhs - r0);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int FT = blockDim.x, nwaves = FT >> 6;
   const int bp = sb.bp, b = sb.b, ex = sb.ex, ey = sb.ey, ez = sb.ez;
   const int cx0 = sb.lo[0] - sb.elo[0], cx1 = sb.hi[0] - sb.elo[0];
   const int cy0 = sb.lo[1] - sb.elo[1], cy1 = sb.hi[1] - sb.elo[1];
   const int cz0 = sb.lo[2] - sb.elo[2], cz1 = sb.hi[2] - sb.elo[2];
-  T* yl = reinterpret_cast<T*>(yloc + sb.vec_off * (long long)nrhs);
+  cpx<T>* yb = yloc + sb.vec_off * (long long)nrhs + r0;  // plane k, row p, column r at (k*bp + p)*nrhs + r
+  T* yr = reinterpret_cast<T*>(yb);
+  double* zr = reinterpret_cast<double*>(z);
+  const double* ar = reinterpret_cast<const double*>(add);
 
   auto gnode = [&](int k, int p) -> long long {
     const int px = p % ex, py = p / ex;
     return (sb.elo[0] + px) + (long long)gnx * ((sb.elo[1] + py) + (long long)gny * (sb.elo[2] + k));
   };
-  // coupling of plane k to plane k+dz (dz = -1: L_k, +1: U_k) applied to Ys
+  // coupling of plane k to plane kn = k + dz (dz = -1: L_k, +1: U_k) applied to the stored plane kn
   auto couple = [&](int k, int p, int r, int dz) -> cpx<T> {
     const int px = p % ex, py = p / ex;
     const z64* row = aloc + (sb.node_off + (long long)k * b + p) * 27 + (dz + 1) * 9;
+    const cpx<T>* yn = yb + (long long)(k + dz) * bp * nrhs + r;
     cpx<T> v = mk<T>(0, 0);
+#pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
       const int cy = py + dy;
       if (cy < 0 || cy >= ey) continue;
+#pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
         const int cx = px + dx;
         if (cx < 0 || cx >= ex) continue;
-        cfma(v, ccast<T>(row[(dy + 1) * 3 + (dx + 1)]), Ys[(cx + ex * cy) * RG + r]);
+        cfma(v, ccast<T>(row[(dy + 1) * 3 + (dx + 1)]), yn[(long long)(cx + ex * cy) * nrhs]);
       }
     }
     return v;
   };
-  auto scatter = [&](int k) {
-    if (k < cz0 || k >= cz1) return;
-    for (int e = tid; e < b * RG; e += FT) {
-      const int p = e / RG, r = e % RG;
-      if (r >= nrg) continue;
-      const int px = p % ex, py = p / ex;
-      if (px < cx0 || px >= cx1 || py < cy0 || py >= cy1) continue;
-      const long long gi = gnode(k, p) * nrhs + r0 + r;
-      z64 v = ccast<double>(Ys[e]);
-      if (add) v += add[gi];
-      z[gi] = v;
-    }
+  // core node (k, p) of the box: z = x (+ add), one real component per lane
+  auto scatter = [&](int k, int p, int r, int nb, T val) {
+    if (k < cz0 || k >= cz1 || p >= b || r >= nrg) return;
+    const int px = p % ex, py = p / ex;
+    if (px < cx0 || px >= cx1 || py < cy0 || py >= cy1) return;
+    const long long gi = (gnode(k, p) * nrhs + r0 + r) * 2 + nb;
+    zr[gi] = (double)val + (ar ? ar[gi] : 0.0);
   };
 
-  // ---- forward sweep
+  // ---- forward sweep: y_k = Sinv_k (R_i u - L_k y_{k-1})
   for (int k = 0; k < ez; ++k) {
     for (int e = tid; e < bp * RG; e += FT) {
       const int p = e / RG, r = e % RG;
@@ -154,29 +170,30 @@ __global__ void __launch_bounds__(FT) k_oras_fused(const Sub* __restrict__ subs,
       Bs[e] = v;
     }
     __syncthreads();
-    plane_product<T, RG>(sinv + sb.mat_off + (long long)k * bp * bp, bp, Bs, wave, lane,
-                         [&](int p, int r, int nb, T val) {
-                           Ysr[(p * RG + r) * 2 + nb] = val;
-                           if (r < nrg) yl[(((long long)k * bp + p) * nrhs + r0 + r) * 2 + nb] = val;
-                         });
-    __syncthreads();
+    const bool last = k == ez - 1;
+    plane_product<T, RG, PF>(sinv + sb.mat_off + (long long)k * bp * bp, bp, Bs, wave, nwaves, lane,
+                             [&](int p, int r, int nb, T val) {
+                               if (r < nrg) yr[(((long long)k * bp + p) * nrhs + r) * 2 + nb] = val;
+                               if (last) scatter(k, p, r, nb, val);  // x_{ez-1} = y_{ez-1}
+                             });
+    wg_sync_global();
   }
-  // ---- backward sweep: Ys holds x_{ez-1} = y_{ez-1}
-  scatter(ez - 1);
+  // ---- backward sweep: x_k = y_k - Sinv_k U_k x_{k+1}, x_k overwrites y_k
   for (int k = ez - 2; k >= 0; --k) {
     for (int e = tid; e < bp * RG; e += FT) {
       const int p = e / RG, r = e % RG;
       Bs[e] = (p < b && r < nrg) ? couple(k, p, r, +1) : mk<T>(0, 0);
     }
     __syncthreads();
-    plane_product<T, RG>(sinv + sb.mat_off + (long long)k * bp * bp, bp, Bs, wave, lane,
-                         [&](int p, int r, int nb, T val) {
-                           // y_k was written by this same thread in the forward sweep
-                           const T yv = r < nrg ? yl[(((long long)k * bp + p) * nrhs + r0 + r) * 2 + nb] : (T)0;
-                           Ysr[(p * RG + r) * 2 + nb] = yv - val;
-                         });
-    __syncthreads();
-    scatter(k);
+    plane_product<T, RG, PF>(sinv + sb.mat_off + (long long)k * bp * bp, bp, Bs, wave, nwaves, lane,
+                             [&](int p, int r, int nb, T val) {
+                               if (r >= nrg) return;
+                               T* yp = yr + (((long long)k * bp + p) * nrhs + r) * 2 + nb;
+                               const T x = *yp - val;
+                               *yp = x;
+                               scatter(k, p, r, nb, x);
+                             });
+    wg_sync_global();
   }
 }
 
@@ -184,26 +201,31 @@ template <typename T, int RG>
 void launch_fused_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, const z64* aloc,
                     const cpx<T>* sinv, const z64* u, z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc,
                     hipStream_t s) {
-  const size_t lds = 2 * (size_t)bpmax * RG * sizeof(cpx<T>);
+  constexpr int PF = sizeof(T) == 4 ? 4 : 2;
+  const size_t lds = (size_t)bpmax * RG * sizeof(cpx<T>);
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_oras_fused<T, RG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)k_oras_fused<T, RG, PF>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               160 * 1024);
     attr = true;
   }
-  hipLaunchKernelGGL((k_oras_fused<T, RG>), dim3(nsub * ngroups), dim3(FT), lds, s, subs, ngroups, nrhs, bpmax, aloc,
+  // waves per workgroup: as few rounds of 16-row tiles as 16 waves allow, evenly spread
+  const int nmt = bpmax / 16;
+  const int rounds = (nmt + 15) / 16;
+  const int nwaves = (nmt + rounds - 1) / rounds;
+  hipLaunchKernelGGL((k_oras_fused<T, RG, PF>), dim3(nsub * ngroups), dim3(64 * nwaves), lds, s, subs, ngroups, nrhs, aloc,
                      sinv, u, z, add, gnx, gny, yloc);
 }
 
 }  // namespace
 
-// LDS budget of the fused kernel (two plane buffers)
+// LDS budget of the fused kernel (one plane operand)
 constexpr size_t FUSED_LDS = 150 * 1024;
 
 template <typename T>
 int fused_group(int bpmax, int nrhs) {
   int rg = nrhs <= 8 ? 8 : (nrhs <= 16 ? 16 : 32);
-  while (rg >= 8 && 2 * (size_t)bpmax * rg * sizeof(cpx<T>) > FUSED_LDS) rg /= 2;
+  while (rg >= 8 && (size_t)bpmax * rg * sizeof(cpx<T>) > FUSED_LDS) rg /= 2;
   return rg >= 8 ? rg : 0;
 }
 
