@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <vector>
 
@@ -42,8 +44,62 @@ helm_status guarded(F&& f) {
 }
 
 // ---------------------------------------------------------------------------
-// Device memory owned by a handle.
+// Device memory.  Freed blocks go to a process-wide cache and are handed out
+// again for requests of the same size class (handles of the same geometry,
+// repeated solves); the cache is returned to the runtime when an allocation
+// fails.
 // ---------------------------------------------------------------------------
+struct DevicePool {
+  std::mutex mu;
+  std::multimap<size_t, void*> blocks;
+  size_t cached = 0;
+
+  void* get(size_t want, size_t* got) {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      auto it = blocks.lower_bound(want);
+      if (it != blocks.end() && it->first <= want + want / 8) {
+        void* p = it->second;
+        *got = it->first;
+        cached -= it->first;
+        blocks.erase(it);
+        return p;
+      }
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+      (void)hipGetLastError();
+      trim();
+      if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+    }
+    *got = want;
+    return p;
+  }
+  void put(void* p, size_t b) {
+    std::lock_guard<std::mutex> lk(mu);
+    blocks.insert({b, p});
+    cached += b;
+  }
+  void trim() {
+    std::lock_guard<std::mutex> lk(mu);
+    if (!blocks.empty()) (void)hipDeviceSynchronize();
+    for (auto& kv : blocks) (void)hipFree(kv.second);
+    blocks.clear();
+    cached = 0;
+  }
+  size_t cached_bytes() {
+    std::lock_guard<std::mutex> lk(mu);
+    return cached;
+  }
+};
+DevicePool& pool() {
+  static DevicePool* p = new DevicePool();  // never destroyed: blocks live until process exit
+  return *p;
+}
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -52,20 +108,16 @@ struct DevBuf {
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) pool().put(p, bytes);
     p = nullptr;
     bytes = 0;
   }
   void alloc(size_t b) {
     release();
     if (b == 0) b = 16;
-    hipError_t e = hipMalloc(&p, b);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
-      throw HelmError(HELM_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
-    }
-    bytes = b;
+    b = (b + 255) / 256 * 256;
+    p = pool().get(b, &bytes);
+    if (!p) throw HelmError(HELM_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
   }
   template <typename T>
   T* as() const {
@@ -335,7 +387,7 @@ size_t budget_bytes() {
     (void)hipGetLastError();
     fr = 0;
   }
-  size_t b = (size_t)(fr * 0.92);
+  size_t b = (size_t)((fr + pool().cached_bytes()) * 0.92);
   if (const char* e = std::getenv("HELM_MEM_BUDGET")) {
     const size_t v = (size_t)std::strtoull(e, nullptr, 10);
     if (v > 0) b = std::min(b, v);

@@ -50,6 +50,8 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const z64* aloc, const cpx
                 z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc, hipStream_t s);
 template <typename T>
 int fused_group(int bpmax, int nrhs);
+// right-hand-side group the autotuner chose for this shape (0 = not tuned yet)
+int tuned_group(int es, int bpmax, int nsub, int nrhs, int gnx, int gny);
 
 // ---- Krylov (ops_krylov.hip) -----------------------------------------------
 // blocks of the two-stage reductions (sizes of the partial-sum buffers)

@@ -313,8 +313,9 @@ __global__ void k_gj_swap(const Sub* __restrict__ subs, int k, int j0, int bpmax
 }
 
 // Deferred Gauss-Jordan update of the columns outside the panel:
-// A[i][c] = (i in panel rows ? 0 : A[i][c]) + sum_jj A[i][j0+jj] R[jj][c]
-template <typename T, int NB>
+// A[i][c] = (i in panel rows ? 0 : A[i][c]) + sum_jj A[i][j0+jj] R[jj][c].
+// One thread per row and CPT consecutive columns; the panel row is read once.
+template <typename T, int NB, int CPT>
 __global__ void __launch_bounds__(256) k_gj_update(const Sub* __restrict__ subs, int k, int j0, int bpmax,
                                                    cpx<T>* __restrict__ S, const cpx<T>* __restrict__ Rbuf) {
   const int s = blockIdx.y;
@@ -323,18 +324,34 @@ __global__ void __launch_bounds__(256) k_gj_update(const Sub* __restrict__ subs,
   const int b = sb.b, bp = sb.bp;
   if (j0 >= b) return;
   const int nbw = min(NB, b - j0);
+  const int ncg = (b + CPT - 1) / CPT;
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= (long long)b * b) return;
-  const int i = (int)(t / b), c = (int)(t % b);
-  if (c >= j0 && c < j0 + nbw) return;
+  if (t >= (long long)b * ncg) return;
+  const int i = (int)(t / ncg), c0 = (int)(t % ncg) * CPT;
   cpx<T>* A = S + (long long)s * bpmax * bpmax;
-  cpx<T> acc = (i >= j0 && i < j0 + nbw) ? mk<T>(0, 0) : A[(long long)i * bp + c];
-  const cpx<T>* Ri = A + (long long)i * bp + j0;
-  const cpx<T>* Rb = Rbuf + (long long)s * NB * bpmax + c;
+  const bool prow = i >= j0 && i < j0 + nbw;
+  cpx<T> acc[CPT];
 #pragma unroll
-  for (int jj = 0; jj < NB; ++jj)
-    if (jj < nbw) cfma(acc, Ri[jj], Rb[(long long)jj * bpmax]);
-  A[(long long)i * bp + c] = acc;
+  for (int q = 0; q < CPT; ++q) {
+    const int c = c0 + q;
+    acc[q] = (c < b && !prow) ? A[(long long)i * bp + c] : mk<T>(0, 0);
+  }
+  const cpx<T>* Ri = A + (long long)i * bp + j0;
+  const cpx<T>* Rb = Rbuf + (long long)s * NB * bpmax + c0;
+#pragma unroll
+  for (int jj = 0; jj < NB; ++jj) {
+    if (jj < nbw) {
+      const cpx<T> pv = Ri[jj];
+#pragma unroll
+      for (int q = 0; q < CPT; ++q)
+        if (c0 + q < b) cfma(acc[q], pv, Rb[(long long)jj * bpmax + q]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int c = c0 + q;
+    if (c < b && (c < j0 || c >= j0 + nbw)) A[(long long)i * bp + c] = acc[q];
+  }
 }
 
 // Column permutation that undoes the row interchanges: apply swaps (j, piv[j])
@@ -516,8 +533,8 @@ void gj_panels(const Sub* subs, int nsub, int bpmax, int k, cpx<T>* S, cpx<T>* R
     hipLaunchKernelGGL((k_gj_panel<T, NB, R>), dim3(nsub), dim3(256), 0, s, subs, k, j0, bpmax, S, piv, err);
     hipLaunchKernelGGL((k_gj_swap<T, NB>), dim3((unsigned)ceil_div(bpmax, 256), nsub), dim3(256), 0, s, subs, k, j0,
                        bpmax, S, piv, Rbuf);
-    hipLaunchKernelGGL((k_gj_update<T, NB>), dim3((unsigned)ceil_div(cells, 256), nsub), dim3(256), 0, s, subs, k,
-                       j0, bpmax, S, Rbuf);
+    hipLaunchKernelGGL((k_gj_update<T, NB, 4>), dim3((unsigned)ceil_div(cells / 4 + bpmax, 256), nsub), dim3(256), 0,
+                       s, subs, k, j0, bpmax, S, Rbuf);
   }
 }
 }  // namespace

@@ -15,6 +15,11 @@
 //   B[2q][2r] = Re T[q][r]    B[2q][2r+1] = Im T[q][r]
 //   B[2q+1][2r] = -Im T[q][r] B[2q+1][2r+1] = Re T[q][r]
 // so that A B is the interleaved complex product (4 real products, one pass).
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "kernels.h"
 
 namespace {
@@ -48,12 +53,28 @@ __device__ __forceinline__ void wg_sync_global() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// First PF chunks of Sinv_k for the wave's first 16-row tile; they do not
+// depend on the plane operand, so they are issued before T is built.
+template <typename T, int PF>
+__device__ __forceinline__ void prefetch_tile(const cpx<T>* __restrict__ Sk, int bp, int wave, int lane,
+                                              cpx<T> (&a)[PF][4]) {
+  const int nmt = bp >> 4;
+  if (wave >= nmt) return;
+  const cpx<T>* Arow = Sk + (long long)(wave * 16 + (lane & 15)) * bp + 4 * (lane >> 4);
+#pragma unroll
+  for (int j = 0; j < PF; ++j)
+    if (16 * j < bp)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) a[j][t] = Arow[16 * j + t];
+}
+
 // Rows of the wave's M-tiles of Sinv_k x Bs (Bs = T, [bp][RG] in LDS), one
-// 16-row tile at a time, with PF chunks of Sinv in flight per wave;
-// out(p, r, nb, value) receives each real output entry.
+// 16-row tile at a time, with PF chunks of Sinv in flight per wave (the first
+// tile's initial chunks arrive pre-loaded in a); out(p, r, nb, value)
+// receives each real output entry.
 template <typename T, int RG, int PF, typename Out>
 __device__ __forceinline__ void plane_product(const cpx<T>* __restrict__ Sk, int bp, const cpx<T>* Bs, int wave,
-                                              int nwaves, int lane, Out&& out) {
+                                              int nwaves, int lane, cpx<T> (&a)[PF][4], Out&& out) {
   using V4 = typename Mfma<T>::v4;
   constexpr int NT = RG / 8;  // MFMA column tiles (16 real columns = 8 complex)
   const int lrow = lane & 15, lg = lane >> 4, nb = lane & 1;
@@ -64,12 +85,13 @@ __device__ __forceinline__ void plane_product(const cpx<T>* __restrict__ Sk, int
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[nt] = V4{0, 0, 0, 0};
     const cpx<T>* Arow = Sk + (long long)(mt * 16 + lrow) * bp + 4 * lg;
-    cpx<T> a[PF][4];
+    if (mt != wave) {
 #pragma unroll
-    for (int j = 0; j < PF; ++j)
-      if (16 * j < bp)
+      for (int j = 0; j < PF; ++j)
+        if (16 * j < bp)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) a[j][t] = Arow[16 * j + t];
+          for (int t = 0; t < 4; ++t) a[j][t] = Arow[16 * j + t];
+    }
     for (int kc0 = 0; kc0 < bp; kc0 += 16 * PF) {
 #pragma unroll
       for (int j = 0; j < PF; ++j) {
@@ -158,41 +180,58 @@ __global__ void __launch_bounds__(1024) k_oras_fused(const Sub* __restrict__ sub
     zr[gi] = (double)val + (ar ? ar[gi] : 0.0);
   };
 
+  cpx<T> a[PF][4];
   // ---- forward sweep: y_k = Sinv_k (R_i u - L_k y_{k-1})
   for (int k = 0; k < ez; ++k) {
-    for (int e = tid; e < bp * RG; e += FT) {
+    const cpx<T>* Sk = sinv + sb.mat_off + (long long)k * bp * bp;
+    prefetch_tile<T, PF>(Sk, bp, wave, lane, a);
+    auto tf = [&](int e) -> cpx<T> {
       const int p = e / RG, r = e % RG;
       cpx<T> v = mk<T>(0, 0);
       if (p < b && r < nrg) {
         v = ccast<T>(u[gnode(k, p) * nrhs + r0 + r]);
         if (k > 0) v = v - couple(k, p, r, -1);
       }
-      Bs[e] = v;
+      return v;
+    };
+    for (int e = tid; e < bp * RG; e += 2 * FT) {
+      const cpx<T> v0 = tf(e);
+      const bool two = e + FT < bp * RG;
+      const cpx<T> v1 = two ? tf(e + FT) : mk<T>(0, 0);
+      Bs[e] = v0;
+      if (two) Bs[e + FT] = v1;
     }
     __syncthreads();
     const bool last = k == ez - 1;
-    plane_product<T, RG, PF>(sinv + sb.mat_off + (long long)k * bp * bp, bp, Bs, wave, nwaves, lane,
-                             [&](int p, int r, int nb, T val) {
-                               if (r < nrg) yr[(((long long)k * bp + p) * nrhs + r) * 2 + nb] = val;
-                               if (last) scatter(k, p, r, nb, val);  // x_{ez-1} = y_{ez-1}
-                             });
+    plane_product<T, RG, PF>(Sk, bp, Bs, wave, nwaves, lane, a, [&](int p, int r, int nb, T val) {
+      if (r < nrg) yr[(((long long)k * bp + p) * nrhs + r) * 2 + nb] = val;
+      if (last) scatter(k, p, r, nb, val);  // x_{ez-1} = y_{ez-1}
+    });
     wg_sync_global();
   }
   // ---- backward sweep: x_k = y_k - Sinv_k U_k x_{k+1}, x_k overwrites y_k
   for (int k = ez - 2; k >= 0; --k) {
-    for (int e = tid; e < bp * RG; e += FT) {
+    const cpx<T>* Sk = sinv + sb.mat_off + (long long)k * bp * bp;
+    prefetch_tile<T, PF>(Sk, bp, wave, lane, a);
+    auto tb = [&](int e) -> cpx<T> {
       const int p = e / RG, r = e % RG;
-      Bs[e] = (p < b && r < nrg) ? couple(k, p, r, +1) : mk<T>(0, 0);
+      return (p < b && r < nrg) ? couple(k, p, r, +1) : mk<T>(0, 0);
+    };
+    for (int e = tid; e < bp * RG; e += 2 * FT) {
+      const cpx<T> v0 = tb(e);
+      const bool two = e + FT < bp * RG;
+      const cpx<T> v1 = two ? tb(e + FT) : mk<T>(0, 0);
+      Bs[e] = v0;
+      if (two) Bs[e + FT] = v1;
     }
     __syncthreads();
-    plane_product<T, RG, PF>(sinv + sb.mat_off + (long long)k * bp * bp, bp, Bs, wave, nwaves, lane,
-                             [&](int p, int r, int nb, T val) {
-                               if (r >= nrg) return;
-                               T* yp = yr + (((long long)k * bp + p) * nrhs + r) * 2 + nb;
-                               const T x = *yp - val;
-                               *yp = x;
-                               scatter(k, p, r, nb, x);
-                             });
+    plane_product<T, RG, PF>(Sk, bp, Bs, wave, nwaves, lane, a, [&](int p, int r, int nb, T val) {
+      if (r >= nrg) return;
+      T* yp = yr + (((long long)k * bp + p) * nrhs + r) * 2 + nb;
+      const T x = *yp - val;
+      *yp = x;
+      scatter(k, p, r, nb, x);
+    });
     wg_sync_global();
   }
 }
@@ -229,17 +268,82 @@ int fused_group(int bpmax, int nrhs) {
   return rg >= 8 ? rg : 0;
 }
 
+namespace {
+
 template <typename T>
-bool oras_fused(const Sub* subs, int nsub, int bpmax, const z64* aloc, const cpx<T>* sinv, int nrhs, const z64* u,
-                z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc, hipStream_t s) {
-  const int rg = fused_group<T>(bpmax, nrhs);
-  if (rg == 0) return false;
+void launch_rg(int rg, const Sub* subs, int nsub, int nrhs, int bpmax, const z64* aloc, const cpx<T>* sinv,
+               const z64* u, z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc, hipStream_t s) {
   const int ngroups = (nrhs + rg - 1) / rg;
   switch (rg) {
     case 8: launch_fused_t<T, 8>(subs, nsub, ngroups, nrhs, bpmax, aloc, sinv, u, z, add, gnx, gny, yloc, s); break;
     case 16: launch_fused_t<T, 16>(subs, nsub, ngroups, nrhs, bpmax, aloc, sinv, u, z, add, gnx, gny, yloc, s); break;
     default: launch_fused_t<T, 32>(subs, nsub, ngroups, nrhs, bpmax, aloc, sinv, u, z, add, gnx, gny, yloc, s); break;
   }
+}
+
+// Autotuned right-hand-side group of the fused sweep, per problem shape.
+struct TuneKey {
+  int es, bpmax, nsub, nrhs, gnx, gny;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(es, bpmax, nsub, nrhs, gnx, gny) < std::tie(o.es, o.bpmax, o.nsub, o.nrhs, o.gnx, o.gny);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+
+}  // namespace
+
+int tuned_group(int es, int bpmax, int nsub, int nrhs, int gnx, int gny) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find({es, bpmax, nsub, nrhs, gnx, gny});
+  return it == g_tune.end() ? 0 : it->second;
+}
+
+template <typename T>
+bool oras_fused(const Sub* subs, int nsub, int bpmax, const z64* aloc, const cpx<T>* sinv, int nrhs, const z64* u,
+                z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc, hipStream_t s) {
+  const int rgmax = fused_group<T>(bpmax, nrhs);
+  if (rgmax == 0) return false;
+  const TuneKey key{(int)sizeof(T), bpmax, nsub, nrhs, gnx, gny};
+  int rg = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) rg = it->second;
+  }
+  static const bool no_tune = std::getenv("HELM_NO_TUNE") != nullptr;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  (void)hipStreamIsCapturing(s, &cap);
+  if (rg == 0 && !no_tune && cap == hipStreamCaptureStatusNone && rgmax > 8) {
+    // time every admissible group size twice on this very input (the sweep is
+    // idempotent: z and the scratch planes are overwritten) and keep the fastest
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    float best = 1e30f;
+    for (int cand = 8; cand <= rgmax; cand *= 2) {
+      float tot = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {
+        (void)hipEventRecord(e0, s);
+        launch_rg<T>(cand, subs, nsub, nrhs, bpmax, aloc, sinv, u, z, add, gnx, gny, yloc, s);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) tot += ms;
+      }
+      if (tot < best) {
+        best = tot;
+        rg = cand;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = rg;
+  }
+  if (rg == 0) rg = rgmax;
+  launch_rg<T>(rg, subs, nsub, nrhs, bpmax, aloc, sinv, u, z, add, gnx, gny, yloc, s);
   return true;
 }
 
