@@ -57,12 +57,44 @@ def make_inputs(w):
     return c, b
 
 
-def gpu_solve(helm, w, c_dev, b_dev, precision, weights):
+def gpu_solve(helm, w, c_dev, b_dev, precision, weights, timing=False):
     S = helm.Solver(w["shape"], H, c_dev, FREQ, (NPML, NPML, NPML, 0), weights=weights, parts=w["parts"],
                     overlap=2, levels=w["levels"], coarse_iters=10, precision=precision, restart=w["restart"])
+    if timing:
+        S.set_sweep_timing(True)
     X, info = S.solve(b_dev, tol=w["tol"], maxit=400)
+    if timing:
+        info["sweeps"] = [S.sweep_stats(0), S.sweep_stats(w["levels"] - 1)]
     S.close()
     return X, info
+
+
+PEAK = {"c64": 157.3, "c128": 78.6}  # dense MFMA TFLOP/s of one MI355X (fp32, fp64)
+
+
+def measured_traffic(kernel_file, profile_md):
+    """HBM bytes per launch from the committed PMC summary, if the kernel source is unchanged since."""
+    import hashlib
+    import re as _re
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        text = open(os.path.join(root, "profiles", profile_md)).read()
+        data = json.loads(_re.search(r"```json\n(.*?)\n```", text, _re.S).group(1))
+        src = open(os.path.join(root, "paper_2103_14921_amd", "csrc", kernel_file), "rb").read()
+        if hashlib.sha256(src).hexdigest()[:16] != data["source_sha256_16"]:
+            return None
+        return data["traffic_bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def roofline_entry(st, dtype):
+    ms = st["ms"] / max(st["launches"], 1)
+    flops = st["flops"] / max(st["launches"], 1)
+    achieved = flops / (ms * 1e-3) / 1e12
+    return {"bound": "mfma", "achieved": achieved, "peak": PEAK[dtype], "unit": "TFLOP/s",
+            "frac": achieved / PEAK[dtype], "traffic": None, "launches": st["launches"], "avg_ms": ms,
+            "flops_per_launch": flops, "bytes_per_launch": st["bytes"] / max(st["launches"], 1)}
 
 
 def cpu_baseline(w, its_per_rhs, nrhs, budget_s=25.0):
@@ -80,24 +112,30 @@ def cpu_baseline(w, its_per_rhs, nrhs, budget_s=25.0):
     core = w["shape"][0] // w["parts"][0]
     ns = 3 * core
     nboxes_full = int(np.prod(w["parts"]))
-    workers = min(os.cpu_count() or 1, 16)
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
     c = inputs.velocity_thrust_belt(ns, ns, ns, H, q=w["q"])
     src = inputs.source_grid(ns, ns, NPML, NPML, 1, 1, iz=4)
     b = inputs.point_source_rhs(ns, ns, ns, src)
     prob = Problem((ns, ns, ns), H, c, FREQ, Pml(NPML, NPML, NPML, 0), fit_weights())
     t0 = time.perf_counter()
-    st = setup(prob, (3, 3, 3), 2, 2, workers=workers)
+    st = setup(prob, (3, 3, 3), 2, 2)
     t_setup = time.perf_counter() - t0
     res = solve(st, b, w["tol"], w["restart"], 60)
     it_s = max(1, int(res["iters"][0]))
     t_iter = res["t_solve"] / it_s
     scale = nboxes_full / 27.0
     t_full = t_setup * scale + t_iter * scale * float(np.sum(its_per_rhs))
-    return {"value": nrhs / t_full, "unit": "RHS/s", "cores": workers, "kind": "oracle",
-            "sample": (f"oracle set-up + one FGMRES solve on a {ns}^3 grid with 3x3x3 boxes of the same size "
-                       f"({t_setup:.1f} s set-up on {workers} processes, {res['t_solve']:.1f} s for {it_s} "
-                       f"iterations on 1 core), scaled by {scale:.0f}x boxes and the GPU's iteration counts"),
-            "extrapolated": True}
+    return {"value": nrhs / t_full, "unit": "RHS/s", "cores": threads, "kind": "oracle",
+            "sample": (f"oracle set-up + one FGMRES solve of one source on a {ns}^3 grid with 3x3x3 boxes of the "
+                       f"same size ({t_setup:.1f} s set-up, {res['t_solve']:.1f} s for {it_s} iterations; one "
+                       f"process, LAPACK on {threads} threads), scaled by {scale:.0f}x boxes and the GPU's "
+                       f"iteration counts summed over all right-hand sides"),
+            "extrapolated": True, "t_setup_full_s": t_setup * scale,
+            "t_solve_full_s": t_iter * scale * float(np.sum(its_per_rhs))}
 
 
 def main():
@@ -108,6 +146,8 @@ def main():
     ap.add_argument("--workload", default="thrust192_mixed", choices=sorted(WORKLOADS))
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the solver is a single-device library (no collectives); "
@@ -125,6 +165,12 @@ def main():
     c_dev = torch.from_numpy(c).to(dev)
     b_dev = torch.from_numpy(np.ascontiguousarray(b.reshape(nrhs, -1))).to(dev)
     weights = helm.fit_weights()
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)  # reads and writes 1 GiB
+        torch.cuda.synchronize()
+        del src, dst
     torch.cuda.synchronize()
     print(f"[bench] {describe(args.workload, w)}", file=sys.stderr, flush=True)
 
@@ -136,7 +182,7 @@ def main():
     t0 = time.perf_counter()
     setups, solves, infos = [], [], []
     for i in range(args.steps):
-        X, info = gpu_solve(helm, w, c_dev, b_dev, w["precision"], weights)
+        X, info = gpu_solve(helm, w, c_dev, b_dev, w["precision"], weights, timing=True)
         setups.append(info["timings"]["setup"])
         solves.append(info["timings"]["solve"])
         infos.append(info)
@@ -159,6 +205,18 @@ def main():
                   "mean": float(info["iters"].mean())},
         "max_true_relres": float(info["relres_true"].max()),
     }
+    # dominant kernel: the batched local solves of the coarse level (FP64 MFMA);
+    # the fine-level sweep (complex FP32 on MFMA in the mixed form) alongside
+    fine_dtype = "c64" if w["precision"] == "mixed" else "c128"
+    if w["levels"] == 2:
+        out["roofline"] = roofline_entry(info["sweeps"][1], "c128")
+        out["roofline"]["kernel"] = "k_oras_fused (coarse level, FP64 complex, MFMA 16x16x4 f64)"
+        if args.workload == "thrust192_mixed":
+            out["roofline"]["traffic"] = measured_traffic("ops_sweep.hip", "oras_sweep_coarse_thrust192_mixed_pmc.md")
+        out["roofline_fine_sweep"] = roofline_entry(info["sweeps"][0], fine_dtype)
+    else:
+        out["roofline"] = roofline_entry(info["sweeps"][0], fine_dtype)
+        out["roofline"]["kernel"] = "k_oras_fused (fine level)"
     if not args.no_fp64 and w["precision"] == "mixed":
         X64, i64 = gpu_solve(helm, w, c_dev, b_dev, "fp64", weights)
         t64 = i64["timings"]["setup"] + i64["timings"]["solve"]

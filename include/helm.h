@@ -129,6 +129,17 @@ size_t helm_resident_bytes(const helm_handle_t* h);
  * out[3] coarse set-up, out[4] number of outer iterations summed over RHS. */
 helm_status helm_last_timings(const helm_handle_t* h, double out[5]);
 
+/* Live timing of the batched local solves (the one-level ORAS sweep of eq.
+ * oras, one kernel launch per application): when enabled, HIP events on the
+ * handle's stream bracket every sweep launch; helm_sweep_stats returns, for
+ * level 0 (fine) or 1 (coarse), out[0] launches, out[1] total milliseconds,
+ * out[2] algorithmic real flops (8 b^2 per plane product and right-hand side,
+ * b the unpadded plane size, 2 ez - 1 plane products per box) and out[3]
+ * algorithmic bytes (factors once per right-hand-side group plus plane
+ * vectors), summed over the launches since enabling.  Enabling resets them. */
+helm_status helm_set_sweep_timing(helm_handle_t* h, int32_t enable);
+helm_status helm_sweep_stats(const helm_handle_t* h, int32_t level, double out[4]);
+
 void helm_destroy(helm_handle_t* h);
 const char* helm_last_error(void);
 

@@ -303,6 +303,11 @@ struct helm_handle {
   Level fine, coarse;
   Workspace ws;
   double t_setup = 0, t_solve = 0, t_fact = 0, t_coarse = 0, its = 0;
+  // live timing of the local-solve sweeps (HIP events around each launch, per level)
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> sweep_ev[2];
+  std::vector<double> sweep_flops[2], sweep_bytes[2];
+  double sweep_stat[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // launches, ms, flops, bytes
 
   ~helm_handle() {
     if (own) (void)hipStreamDestroy(own);
@@ -500,7 +505,69 @@ void ensure_ws(helm_handle* H, int nr) {
 // ---------------------------------------------------------------------------
 // Building blocks of one preconditioner application.
 // ---------------------------------------------------------------------------
+void oras_sweep(helm_handle* H, Level& L, int nr, const z64* u, z64* z, const z64* add, void* yl, void* tb);
+
+// Algorithmic work of one batched local-solve launch: every plane product
+// Sinv_k T (ez forward + ez-1 backward per box) costs 8 b^2 real flops per
+// right-hand side; the bytes count the factors once per right-hand-side group
+// plus the plane vectors (gather, scatter, stored planes).
+void sweep_work(const helm_handle* H, const Level& L, int nr, double* flops, double* bytes) {
+  const int es = (int)elem_size(L.prec);
+  int rg = tuned_group(es, L.bpmax, L.nsub, nr, L.nx, L.ny);
+  if (rg == 0) rg = L.prec ? fused_group<float>(L.bpmax, nr) : fused_group<double>(L.bpmax, nr);
+  const int ngroups = rg > 0 ? (nr + rg - 1) / rg : 1;
+  double f = 0, by = 0;
+  for (const Sub& sb : L.subs) {
+    const double planes = 2.0 * sb.ez - 1.0;
+    const double b = sb.b;
+    f += planes * 8.0 * b * b * nr;
+    by += planes * b * b * es * ngroups;                      // factors
+    by += (double)sb.b * sb.ez * nr * (16.0 + 3.0 * es);      // gather + stored planes (w, r, w)
+    by += (double)(sb.hi[0] - sb.lo[0]) * (sb.hi[1] - sb.lo[1]) * (sb.hi[2] - sb.lo[2]) * nr * 16.0;  // scatter
+  }
+  *flops = f;
+  *bytes = by;
+}
+
 void oras_apply(helm_handle* H, Level& L, int nr, const z64* u, z64* z, const z64* add, void* yl, void* tb) {
+  const int lv = &L == &H->fine ? 0 : 1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (H->timing) {
+    HELM_CHECK_HIP(hipEventCreate(&e0));
+    HELM_CHECK_HIP(hipEventCreate(&e1));
+    HELM_CHECK_HIP(hipEventRecord(e0, H->stream));
+  }
+  oras_sweep(H, L, nr, u, z, add, yl, tb);
+  if (H->timing) {
+    HELM_CHECK_HIP(hipEventRecord(e1, H->stream));
+    double f, by;
+    sweep_work(H, L, nr, &f, &by);
+    H->sweep_ev[lv].push_back({e0, e1});
+    H->sweep_flops[lv].push_back(f);
+    H->sweep_bytes[lv].push_back(by);
+  }
+}
+
+// Fold the recorded sweep events into the statistics (the stream has been synchronised).
+void collect_sweep_timing(helm_handle* H) {
+  for (int lv = 0; lv < 2; ++lv) {
+    for (size_t i = 0; i < H->sweep_ev[lv].size(); ++i) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, H->sweep_ev[lv][i].first, H->sweep_ev[lv][i].second);
+      H->sweep_stat[lv][0] += 1;
+      H->sweep_stat[lv][1] += ms;
+      H->sweep_stat[lv][2] += H->sweep_flops[lv][i];
+      H->sweep_stat[lv][3] += H->sweep_bytes[lv][i];
+      (void)hipEventDestroy(H->sweep_ev[lv][i].first);
+      (void)hipEventDestroy(H->sweep_ev[lv][i].second);
+    }
+    H->sweep_ev[lv].clear();
+    H->sweep_flops[lv].clear();
+    H->sweep_bytes[lv].clear();
+  }
+}
+
+void oras_sweep(helm_handle* H, Level& L, int nr, const z64* u, z64* z, const z64* add, void* yl, void* tb) {
   if (L.prec == 1)
     Factor<float>::sweep(L.d_subs.as<Sub>(), L.nsub, L.bpmax, L.maxez, L.aloc.as<z64>(), L.sinv.as<c32>(), nr, u, z,
                          add, L.nx, L.ny, (c32*)yl, (c32*)tb, H->stream);
@@ -867,6 +934,7 @@ helm_status helm_solve(helm_handle_t* H, int32_t nrhs, const void* B, void* X, d
       }
     }
     H->t_solve = tt.stop();
+    collect_sweep_timing(H);
     double its = 0;
     for (int r = 0; r < nrhs; ++r) {
       its += it_all[r];
@@ -917,7 +985,22 @@ helm_status helm_last_timings(const helm_handle_t* H, double out[5]) {
 void helm_destroy(helm_handle_t* H) {
   if (!H) return;
   (void)hipDeviceSynchronize();
+  collect_sweep_timing(H);
   delete H;
+}
+
+helm_status helm_set_sweep_timing(helm_handle_t* H, int32_t enable) {
+  if (!H) return fail(HELM_EINVAL, "null handle");
+  H->timing = enable != 0;
+  for (int lv = 0; lv < 2; ++lv)
+    for (int i = 0; i < 4; ++i) H->sweep_stat[lv][i] = 0;
+  return HELM_OK;
+}
+
+helm_status helm_sweep_stats(const helm_handle_t* H, int32_t level, double out[4]) {
+  if (!H || !out || level < 0 || level > 1) return fail(HELM_EINVAL, "bad arguments");
+  for (int i = 0; i < 4; ++i) out[i] = H->sweep_stat[level][i];
+  return HELM_OK;
 }
 
 const char* helm_last_error(void) { return g_last_error.c_str(); }

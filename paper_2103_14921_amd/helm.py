@@ -24,7 +24,7 @@ EXPORTS = [
     "helm_fit_weights", "helm_setup", "helm_solve", "helm_footprint", "helm_resident_bytes",
     "helm_last_timings", "helm_destroy", "helm_last_error", "helm_set_stream", "helm_apply_A",
     "helm_apply_M", "helm_apply_oras", "helm_restrict", "helm_prolong", "helm_apply_E", "helm_apply_Q",
-    "helm_num_subdomains", "helm_subdomain_box",
+    "helm_num_subdomains", "helm_subdomain_box", "helm_set_sweep_timing", "helm_sweep_stats",
 ]
 
 
@@ -78,6 +78,8 @@ def _load():
         "helm_apply_Q": ([P, i32, P, P], C.c_int),
         "helm_num_subdomains": ([P, i32], i32),
         "helm_subdomain_box": ([P, i32, i32, C.POINTER(i32)], C.c_int),
+        "helm_set_sweep_timing": ([P, i32], C.c_int),
+        "helm_sweep_stats": ([P, i32, C.POINTER(C.c_double)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -191,6 +193,14 @@ class Solver:
         out = (C.c_double * 5)()
         _check(lib.helm_last_timings(self._h, out))
         return dict(setup=out[0], solve=out[1], factor=out[2], coarse=out[3], iters_total=out[4])
+
+    def set_sweep_timing(self, enable=True):
+        _check(lib.helm_set_sweep_timing(self._h, 1 if enable else 0))
+
+    def sweep_stats(self, level=0):
+        out = (C.c_double * 4)()
+        _check(lib.helm_sweep_stats(self._h, int(level), out))
+        return dict(launches=int(out[0]), ms=out[1], flops=out[2], bytes=out[3])
 
     def resident_bytes(self):
         return lib.helm_resident_bytes(self._h)
