@@ -161,6 +161,12 @@ helm_status helm_apply_M(helm_handle_t* h, int32_t nrhs, const void* R, void* Z)
  * ceil(n/2) per axis). */
 helm_status helm_apply_oras(helm_handle_t* h, int32_t level, int32_t nrhs, const void* R, void* Z);
 
+/* X = A_i^{-1} R for one subdomain s of a level (the local problem of eq.
+ * oras, with its absorbing interface fold), through the same factors and
+ * sweep kernels as the preconditioner.  R, X: complex128 [nrhs][ez][ey][ex]
+ * in the extended box's natural order (x fastest; see helm_subdomain_box). */
+helm_status helm_local_solve(helm_handle_t* h, int32_t level, int32_t s, int32_t nrhs, const void* R, void* X);
+
 /* Coarse transfers (eq. 2lvl): C = Z^T R (restriction, fine -> coarse) and
  * R = Z C (trilinear prolongation, coarse -> fine). */
 helm_status helm_restrict(helm_handle_t* h, int32_t nrhs, const void* R, void* C);

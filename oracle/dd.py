@@ -180,3 +180,35 @@ class Oras:
     @property
     def nbytes(self):
         return sum(lu.nbytes for lu in self.lu)
+
+
+def local_matrix_from_rows(prob, box, robin=True):
+    """A_i built row by row from ``operator.row`` (no global assembly): the same
+    matrix as ``local_matrix`` (restriction + absorbing fold), usable on grids
+    too large to assemble.  Returns CSR in the box's natural order."""
+    from .operator import row
+    nx, ny, _ = prob.shape
+    idx = box_indices(prob.shape, box.elo, box.ehi)
+    pos = -np.ones(prob.n, dtype=np.int64) if prob.n <= 50_000_000 else None
+    lookup = {}
+    if pos is not None:
+        pos[idx] = np.arange(len(idx))
+    else:
+        lookup = {g: l for l, g in enumerate(idx)}
+    k = prob.k()
+    rows, cols, vals = [], [], []
+    for l, g in enumerate(idx):
+        ix, iy, iz = g % nx, (g // nx) % ny, g // (nx * ny)
+        c, v = row(prob, ix, iy, iz)
+        loc = pos[c] if pos is not None else np.array([lookup.get(int(cc), -1) for cc in c])
+        inside = loc >= 0
+        d = 0j
+        if robin:
+            d = v[~inside].sum() * (1.0 + 1j * k[iz, iy, ix] * prob.h)
+        rows.append(np.full(inside.sum(), l))
+        cols.append(loc[inside])
+        vv = v[inside].copy()
+        vv[loc[inside] == l] += d
+        vals.append(vv)
+    n = len(idx)
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))

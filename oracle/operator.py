@@ -260,3 +260,44 @@ def assemble(prob: Problem):
                       shape=(prob.n, prob.n)).tocsr()
     A.sum_duplicates()
     return A
+
+
+def row(prob: Problem, ix, iy, iz):
+    """Row (ix, iy, iz) of A computed on its own: (global column indices, values).
+
+    The same entries as ``assemble`` (FD-vs-FE section, readings in the module
+    docstring), evaluated one neighbour at a time so that single rows of very
+    large grids can be checked without assembling the matrix.
+    """
+    if "_row_cache" not in prob.__dict__:
+        prob.__dict__["_row_cache"] = (prob.profiles(), prob.sigma())
+    prof, sig = prob.__dict__["_row_cache"]
+    nx, ny, nz = prob.shape
+    h2 = prob.h ** 2
+    al = prob.weights.alphas()
+    ms = prob.weights.masses()
+    pos = (ix, iy, iz)
+    si = sig[iz, iy, ix]
+    diag = prob.weights.wm1 * si
+    cols, vals = [], []
+    for cls, ci in _classes():
+        for e in cls:
+            for sign in (+1, -1):
+                s = 1.0 + 0j
+                inv = 0j
+                e2 = float(e[0] ** 2 + e[1] ** 2 + e[2] ** 2)
+                for d in range(3):
+                    xi_int, xi_half = prof[d]
+                    ed = sign * e[d]
+                    xv = xi_int[pos[d]] if ed == 0 else (xi_half[pos[d] + 1] if ed > 0 else xi_half[pos[d]])
+                    s = s * xv
+                    inv = inv + (e[d] ** 2 / e2) / xv ** 2
+                st = (al[ci] / h2) * (s * inv)
+                diag = diag - st
+                jx, jy, jz = ix + sign * e[0], iy + sign * e[1], iz + sign * e[2]
+                if 0 <= jx < nx and 0 <= jy < ny and 0 <= jz < nz:
+                    cols.append(jx + nx * (jy + ny * jz))
+                    vals.append(st + ms[ci] * 0.5 * (si + sig[jz, jy, jx]))
+    cols.append(ix + nx * (iy + ny * iz))
+    vals.append(diag)
+    return np.array(cols, dtype=np.int64), np.array(vals, dtype=np.complex128)

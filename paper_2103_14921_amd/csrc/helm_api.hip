@@ -1064,6 +1064,46 @@ helm_status helm_apply_oras(helm_handle_t* H, int32_t level, int32_t nrhs, const
   });
 }
 
+helm_status helm_local_solve(helm_handle_t* H, int32_t level, int32_t s, int32_t nrhs, const void* R, void* X) {
+  return guarded([&]() {
+    if (!H || !R || !X || nrhs < 1 || nrhs > 256) throw HelmError(HELM_EINVAL, "bad arguments");
+    if (level != 0 && !(level == 1 && H->two_level())) throw HelmError(HELM_EINVAL, "no such level");
+    Level& L = level == 0 ? H->fine : H->coarse;
+    if (s < 0 || s >= L.nsub) throw HelmError(HELM_EINVAL, "no such subdomain");
+    const Sub& sb = L.subs[s];
+    const long long nloc = (long long)sb.b * sb.ez;
+    ensure_ws(H, nrhs);
+    DevBuf fi, ni, u, zg, xo, fo;
+    fi.alloc(sizeof(z64) * nloc * nrhs);
+    ni.alloc(sizeof(z64) * nloc * nrhs);
+    xo.alloc(sizeof(z64) * nloc * nrhs);
+    fo.alloc(sizeof(z64) * nloc * nrhs);
+    u.alloc(sizeof(z64) * L.n * nrhs);
+    zg.alloc(sizeof(z64) * L.n * nrhs);
+    HELM_CHECK_HIP(hipMemcpyAsync(fi.p, R, sizeof(z64) * nloc * nrhs, hipMemcpyDefault, H->stream));
+    launch_to_node_major(fi.as<z64>(), ni.as<z64>(), nloc, nrhs, H->stream);
+    launch_fill(u.as<z64>(), L.n * nrhs, H->stream);
+    launch_box_scatter(sb, L.nx, L.ny, nrhs, ni.as<z64>(), u.as<z64>(), H->stream);
+    void* yl = level == 0 ? H->ws.yl_f.p : H->ws.yl_c.p;
+    void* tb = level == 0 ? H->ws.tb_f.p : H->ws.tb_c.p;
+    const Sub* one = L.d_subs.as<Sub>() + s;
+    if (L.prec == 1) {
+      Factor<float>::sweep(one, 1, L.bpmax, sb.ez, L.aloc.as<z64>(), L.sinv.as<c32>(), nrhs, u.as<z64>(), zg.as<z64>(),
+                           nullptr, L.nx, L.ny, (c32*)yl, (c32*)tb, H->stream);
+      launch_box_gather<float>(sb, nrhs, (const c32*)yl, xo.as<z64>(), H->stream);
+    } else {
+      Factor<double>::sweep(one, 1, L.bpmax, sb.ez, L.aloc.as<z64>(), L.sinv.as<z64>(), nrhs, u.as<z64>(),
+                            zg.as<z64>(), nullptr, L.nx, L.ny, (z64*)yl, (z64*)tb, H->stream);
+      launch_box_gather<double>(sb, nrhs, (const z64*)yl, xo.as<z64>(), H->stream);
+    }
+    launch_to_field_major(xo.as<z64>(), fo.as<z64>(), nloc, nrhs, H->stream);
+    HELM_CHECK_HIP(hipMemcpyAsync(X, fo.p, sizeof(z64) * nloc * nrhs, hipMemcpyDefault, H->stream));
+    HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+    HELM_CHECK_HIP(hipGetLastError());
+    return HELM_OK;
+  });
+}
+
 helm_status helm_restrict(helm_handle_t* H, int32_t nrhs, const void* R, void* C) {
   if (!H || !H->two_level()) return fail(HELM_EINVAL, "two-level handle required");
   return map_fields(H, nrhs, H->n, H->coarse.n, R, C,

@@ -30,6 +30,11 @@ void launch_local_coarse(int ncx, int ncy, int ncz, const z64* E, const Sub* sub
                          long long maxnodes, const z64* c_fine, int nx, int ny, double omega,
                          double hc, int robin, z64* aloc, hipStream_t s);
 
+// one box: scatter a local field into a zeroed global field / read back the stored plane solutions
+void launch_box_scatter(const Sub& sb, int gnx, int gny, int nrhs, const z64* rl, z64* u, hipStream_t s);
+template <typename T>
+void launch_box_gather(const Sub& sb, int nrhs, const cpx<T>* yloc, z64* xl, hipStream_t s);
+
 template <typename T>
 struct Factor {
   // one plane step of the block-tridiagonal LU: S_k = D_k - L_k Sinv_{k-1} U_{k-1}, Sinv_k = S_k^{-1}

@@ -510,6 +510,43 @@ __global__ void k_scatter(const Sub* __restrict__ subs, int nrhs, const cpx<T>* 
 
 }  // namespace
 
+namespace {
+// u[g(l)][r] = rl[l][r] on the nodes of one box (natural order, x fastest)
+__global__ void k_box_scatter(Sub sb, int gnx, int gny, int nrhs, const z64* __restrict__ rl, z64* __restrict__ u) {
+  const long long nl = (long long)sb.ex * sb.ey * sb.ez;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nl * nrhs;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long l = t / nrhs;
+    const int r = (int)(t % nrhs);
+    const int lx = (int)(l % sb.ex), ly = (int)((l / sb.ex) % sb.ey), lz = (int)(l / ((long long)sb.ex * sb.ey));
+    const long long g = (sb.elo[0] + lx) + (long long)gnx * ((sb.elo[1] + ly) + (long long)gny * (sb.elo[2] + lz));
+    u[g * nrhs + r] = rl[t];
+  }
+}
+// xl[l][r] = the box's stored plane solution (plane lz, row p = l mod b)
+template <typename T>
+__global__ void k_box_gather(Sub sb, int nrhs, const cpx<T>* __restrict__ yloc, z64* __restrict__ xl) {
+  const long long nl = (long long)sb.b * sb.ez;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nl * nrhs;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long l = t / nrhs;
+    const int r = (int)(t % nrhs);
+    const long long lz = l / sb.b, p = l % sb.b;
+    xl[t] = ccast<double>(yloc[(sb.vec_off + lz * sb.bp + p) * nrhs + r]);
+  }
+}
+}  // namespace
+
+void launch_box_scatter(const Sub& sb, int gnx, int gny, int nrhs, const z64* rl, z64* u, hipStream_t s) {
+  hipLaunchKernelGGL(k_box_scatter, dim3(1024), dim3(256), 0, s, sb, gnx, gny, nrhs, rl, u);
+}
+template <typename T>
+void launch_box_gather(const Sub& sb, int nrhs, const cpx<T>* yloc, z64* xl, hipStream_t s) {
+  hipLaunchKernelGGL(k_box_gather<T>, dim3(1024), dim3(256), 0, s, sb, nrhs, yloc, xl);
+}
+template void launch_box_gather<float>(const Sub&, int, const c32*, z64*, hipStream_t);
+template void launch_box_gather<double>(const Sub&, int, const z64*, z64*, hipStream_t);
+
 void launch_local_fine(const OpDev& op, const Sub* subs, int nsub, long long maxnodes, const z64* c,
                        double omega, double h, int robin, z64* aloc, hipStream_t s) {
   dim3 grid((unsigned)std::min<long long>(ceil_div(maxnodes, 256), 4096), nsub);

@@ -25,6 +25,7 @@ EXPORTS = [
     "helm_last_timings", "helm_destroy", "helm_last_error", "helm_set_stream", "helm_apply_A",
     "helm_apply_M", "helm_apply_oras", "helm_restrict", "helm_prolong", "helm_apply_E", "helm_apply_Q",
     "helm_num_subdomains", "helm_subdomain_box", "helm_set_sweep_timing", "helm_sweep_stats",
+    "helm_local_solve",
 ]
 
 
@@ -80,6 +81,7 @@ def _load():
         "helm_subdomain_box": ([P, i32, i32, C.POINTER(i32)], C.c_int),
         "helm_set_sweep_timing": ([P, i32], C.c_int),
         "helm_sweep_stats": ([P, i32, C.POINTER(C.c_double)], C.c_int),
+        "helm_local_solve": ([P, i32, i32, i32, P, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -232,6 +234,14 @@ class Solver:
 
     def apply_Q(self, R):
         return self._map(lib.helm_apply_Q, R, self.n, self.n)
+
+    def local_solve(self, R, s, level=0):
+        """A_i^{-1} R for subdomain s (R: [nrhs][ez*ey*ex] in the box's natural order)."""
+        nrhs = R.shape[0]
+        nloc = R.shape[1] if R.ndim == 2 else int(np.prod(R.shape[1:]))
+        X = _empty_like_kind(R, (nrhs, nloc))
+        _check(lib.helm_local_solve(self._h, int(level), int(s), nrhs, _ptr(R, nrhs * nloc), _ptr(X, nrhs * nloc)))
+        return X
 
     def num_subdomains(self, level=0):
         return lib.helm_num_subdomains(self._h, int(level))

@@ -1,0 +1,118 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py uses.
+
+The oracle cannot assemble or factor these grids in a test, so the checks are
+on sampled outputs it computes one by one, and on properties that hold at any
+size:
+  * the stencil: sampled rows of A x against the oracle's single-row formula;
+  * local solves: A_i x = r for sampled boxes, with A_i built row by row by the
+    oracle (FP64 local solves to 1e-10, complex-FP32 ones to 2e-5);
+  * the solve: every right-hand side reaches its FP64 true residual (reported
+    by the library) and, for sampled right-hand sides, the residual recomputed
+    at sampled nodes with the oracle's rows stays below tol ||b||.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import inputs
+from oracle.dd import decompose, local_matrix_from_rows
+from oracle.operator import Pml, Problem, fit_weights, row
+
+pytestmark = pytest.mark.gpu
+
+WO = fit_weights()
+W = {k: getattr(WO, k) for k in ("w1", "w2", "w3", "wm1", "wm2", "wm3", "wm4")}
+H, F, NPML = 25.0, 10.0, 10
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _sample_rows(prob, rng, n):
+    nx, ny, nz = prob.shape
+    pts = [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (nx // 2, ny // 2, 4)]
+    pts += [tuple(int(v) for v in (rng.integers(0, nx), rng.integers(0, ny), rng.integers(0, nz))) for _ in range(n)]
+    return pts
+
+
+def _check_stencil(S, prob, dev, rng):
+    import torch
+    nx, ny, nz = prob.shape
+    x = inputs.random_field((1, prob.n), seed=31)
+    y = S.apply_A(torch.from_numpy(x).to(dev)).cpu().numpy()[0]
+    for (ix, iy, iz) in _sample_rows(prob, rng, 200):
+        cols, vals = row(prob, ix, iy, iz)
+        ref = np.dot(vals, x[0][cols])
+        i = ix + nx * (iy + ny * iz)
+        assert abs(y[i] - ref) <= 1e-12 * np.sum(np.abs(vals * x[0][cols])), (ix, iy, iz)
+
+
+def _check_local(S, prob, parts, tol, which):
+    boxes = decompose(prob.shape, parts, 2)
+    for s in which:
+        b = boxes[s]
+        bx = S.subdomain_box(s)
+        assert bx["elo"] == b.elo and bx["ehi"] == b.ehi
+        Ai = local_matrix_from_rows(prob, b)
+        r = inputs.random_field((1, Ai.shape[0]), seed=40 + s)
+        x = S.local_solve(r, s)
+        res = np.linalg.norm(Ai @ x[0] - r[0]) / np.linalg.norm(r[0])
+        say("local", s, b.ext_shape, f"residual {res:.2e}")
+        assert res <= tol
+
+
+def _check_solve(prob, Xd, info, B, tol, rng, which):
+    assert np.all(info["relres_true"] <= tol), info["relres_true"].max()
+    nx, ny, nz = prob.shape
+    for r in which:
+        x = Xd[r].cpu().numpy()
+        b = B[r].reshape(-1)
+        nb = np.linalg.norm(b)
+        worst = 0.0
+        for (ix, iy, iz) in _sample_rows(prob, rng, 300):
+            cols, vals = row(prob, ix, iy, iz)
+            i = ix + nx * (iy + ny * iz)
+            worst = max(worst, abs(b[i] - np.dot(vals, x[cols])))
+        say("rhs", r, f"max sampled |r_i|/||b|| {worst / nb:.2e}")
+        assert worst <= tol * nb
+
+
+def _run(shape, parts, src, precision, tol, restart, q, local_tol, local_which, rhs_which):
+    import torch
+    from paper_2103_14921_amd import helm
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(7)
+    nx, ny, nz = shape
+    c = inputs.velocity_thrust_belt(nx, ny, nz, H, q=q)
+    srcs = inputs.source_grid(nx, ny, NPML, NPML, src[0], src[1], iz=4)
+    B = inputs.point_source_rhs(nx, ny, nz, srcs)
+    prob = Problem(shape, H, c, F, Pml(NPML, NPML, NPML, 0), WO)
+    t0 = time.time()
+    S = helm.Solver(shape, H, torch.from_numpy(c).to(dev), F, (NPML, NPML, NPML, 0), weights=W, parts=parts,
+                    overlap=2, levels=2, precision=precision, restart=restart)
+    say("setup", shape, precision, f"{time.time() - t0:.1f} s")
+    _check_stencil(S, prob, dev, rng)
+    _check_local(S, prob, parts, local_tol, local_which)
+    Bd = torch.from_numpy(np.ascontiguousarray(B.reshape(len(srcs), -1))).to(dev)
+    t0 = time.time()
+    Xd, info = S.solve(Bd, tol=tol, maxit=400)
+    say("solve", f"{time.time() - t0:.1f} s", "iters", info["iters"].min(), info["iters"].max())
+    _check_solve(prob, Xd, info, B, tol, rng, rhs_which)
+    S.close()
+
+
+def test_thrust128_fp64_two_level_full_size():
+    # 128^3, 4x4x4 boxes of 32^3 (planes of 36x36 = 1296 nodes), FP64, 8 sources on a 4x2 grid
+    _run((128, 128, 128), (4, 4, 4), (4, 2), "fp64", 1e-8, 30, None, 1e-10, [0, 21, 63], [0, 5])
+
+
+def test_thrust192_mixed_full_size():
+    # the benchmark workload: 192^3, 12^3 boxes of 16^3, complex-FP32 local solves, 64 sources
+    _run((192, 192, 192), (12, 12, 12), (8, 8), "mixed", 1e-6, 20, None, 2e-5, [0, 866, 1727], [0, 37, 63])
+
+
+def test_thrust256x128_q100_mixed_full_size():
+    # largest one-GPU share: 256x256x128 with Q = 100 attenuation, 16x16x8 boxes, 128 sources
+    _run((256, 256, 128), (16, 16, 8), (16, 8), "mixed", 1e-6, 20, 100.0, 2e-5, [0, 1000, 2047], [0, 127])

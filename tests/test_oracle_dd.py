@@ -199,3 +199,13 @@ def test_absorbing_interfaces_beat_dirichlet_and_wrong_sign():
         its[name] = fgmres(lambda v: A @ v, M.apply, b, 1e-8, 30, 300)[1]
     assert its["oras"] < its["ras"] / 2
     assert its["oras"] < its["wrong"]
+
+
+def test_local_matrix_from_rows_matches_restriction():
+    from oracle.dd import local_matrix_from_rows
+    prob = _prob(shape=(13, 11, 10), pml=(3, 3, 3, 0), q=40.0)
+    A = assemble(prob)
+    for b in decompose(prob.shape, (2, 2, 2), 2)[::3]:
+        Ai, _ = local_matrix(A, prob.shape, b, prob.k().ravel(), prob.h)
+        Bi = local_matrix_from_rows(prob, b)
+        assert abs(Ai - Bi).max() <= 1e-13 * abs(Ai).max()

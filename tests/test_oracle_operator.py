@@ -138,3 +138,20 @@ def test_pml_profile():
     assert abs(xi_i[0].imag * 2 * np.pi * 5.0 - gmax) < 1e-9 * gmax
     assert xi_h.shape == (21,) and xi_h[0].imag > xi_i[0].imag
     assert np.all(xi_i.real == 1.0)
+
+
+def test_single_row_matches_assembled_rows():
+    shape = (11, 9, 8)
+    c = inputs.velocity_thrust_belt(*shape, h=25.0, q=100.0)
+    prob = Problem(shape, 25.0, c, 10.0, Pml(3, 2, 3, 2), W)
+    A = assemble(prob)
+    from oracle.operator import row
+    rng = np.random.default_rng(4)
+    for _ in range(40):
+        ix, iy, iz = rng.integers(0, 11), rng.integers(0, 9), rng.integers(0, 8)
+        cols, vals = row(prob, ix, iy, iz)
+        i = ix + 11 * (iy + 9 * iz)
+        ref = A[i].toarray().ravel()
+        got = np.zeros_like(ref)
+        np.add.at(got, cols, vals)
+        assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
