@@ -140,6 +140,11 @@ helm_status helm_last_timings(const helm_handle_t* h, double out[5]);
 helm_status helm_set_sweep_timing(helm_handle_t* h, int32_t enable);
 helm_status helm_sweep_stats(const helm_handle_t* h, int32_t level, double out[4]);
 
+/* Return the handle's cached Krylov workspace (sized for its last batch) to
+ * the library's device cache, keeping operators and factors resident: lets a
+ * server hold many set-up problems and pay workspace only while solving. */
+helm_status helm_release_workspace(helm_handle_t* h);
+
 void helm_destroy(helm_handle_t* h);
 const char* helm_last_error(void);
 

@@ -184,3 +184,46 @@ def workload_inputs(name, shape=None, n_src=None):
         src = source_grid(nx, ny, npx, npy, sx, sy, iz=4)
     b = point_source_rhs(nx, ny, nz, src)
     return c, b, src
+
+
+# ---------------------------------------------------------------------------
+# Serving workload: a seeded catalogue of (model, grid, frequency) problems and
+# a stream of requests drawn from it (grids 64^3..160^3, 2-8 Hz, 1-64 sources).
+# ---------------------------------------------------------------------------
+
+def serving_catalogue(n_entries=16, seed=4, grids=(64, 96, 128, 160), core=16, npml=10):
+    """List of dicts(name, model, n, h, freq, parts): n^3 grids, h = min(25, vmin/(8 f)),
+    boxes of core^3 nodes per axis."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_entries):
+        model = "thrust" if rng.uniform() < 0.5 else "linear"
+        n = int(grids[rng.integers(0, len(grids))])
+        f = float(rng.uniform(2.0, 8.0))
+        vmin = 2000.0 if model == "thrust" else 1500.0
+        h = min(25.0, vmin / (8.0 * f))
+        out.append(dict(name=f"{model}{n}_{i}", model=model, n=n, h=h, freq=f, parts=(n // core,) * 3, npml=npml))
+    return out
+
+
+def serving_velocity(entry):
+    n, h = entry["n"], entry["h"]
+    if entry["model"] == "thrust":
+        return velocity_thrust_belt(n, n, n, h)
+    return velocity_linear(n, n, n, h)
+
+
+def serving_requests(catalogue, n_requests, seed=4, max_rhs=64):
+    """(entry index, sources [nrhs][3]) per request: entry uniform over the catalogue,
+    1..max_rhs sources at distinct random positions of the non-PML interior, depth index 4."""
+    rng = np.random.default_rng(seed + 1)
+    reqs = []
+    for _ in range(n_requests):
+        e = int(rng.integers(0, len(catalogue)))
+        ent = catalogue[e]
+        n, p = ent["n"], ent["npml"]
+        k = int(rng.integers(1, max_rhs + 1))
+        cells = rng.choice((n - 2 * p) * (n - 2 * p), size=k, replace=False)
+        src = np.stack([p + cells % (n - 2 * p), p + cells // (n - 2 * p), np.full(k, 4)], axis=1)
+        reqs.append((e, src.astype(np.int64)))
+    return reqs

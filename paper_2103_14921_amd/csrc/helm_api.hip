@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <new>
 #include <mutex>
 #include <stdexcept>
 #include <vector>
@@ -984,9 +985,20 @@ helm_status helm_last_timings(const helm_handle_t* H, double out[5]) {
 
 void helm_destroy(helm_handle_t* H) {
   if (!H) return;
-  (void)hipDeviceSynchronize();
+  // the handle's device work is ordered on its stream
+  if (H->stream) (void)hipStreamSynchronize(H->stream);
   collect_sweep_timing(H);
   delete H;
+}
+
+helm_status helm_release_workspace(helm_handle_t* H) {
+  return guarded([&]() {
+    if (!H) throw HelmError(HELM_EINVAL, "null handle");
+    HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+    H->ws.~Workspace();  // buffers go back to the device cache
+    new (&H->ws) Workspace();
+    return HELM_OK;
+  });
 }
 
 helm_status helm_set_sweep_timing(helm_handle_t* H, int32_t enable) {

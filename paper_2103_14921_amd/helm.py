@@ -25,7 +25,7 @@ EXPORTS = [
     "helm_last_timings", "helm_destroy", "helm_last_error", "helm_set_stream", "helm_apply_A",
     "helm_apply_M", "helm_apply_oras", "helm_restrict", "helm_prolong", "helm_apply_E", "helm_apply_Q",
     "helm_num_subdomains", "helm_subdomain_box", "helm_set_sweep_timing", "helm_sweep_stats",
-    "helm_local_solve",
+    "helm_local_solve", "helm_release_workspace",
 ]
 
 
@@ -53,7 +53,19 @@ class DecompT(C.Structure):
                                          "precision", "restart", "robin", "nrhs_chunk")]
 
 
+def _init_torch_runtime_first():
+    """PyTorch ships its own HIP runtime; it must initialise before this library's
+    runtime in a process that uses both (for device buffers and streams)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except Exception:
+        pass
+
+
 def _load():
+    _init_torch_runtime_first()
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2103_14921_amd.build.build()")
     lib = C.CDLL(LIB_PATH)
@@ -82,6 +94,7 @@ def _load():
         "helm_set_sweep_timing": ([P, i32], C.c_int),
         "helm_sweep_stats": ([P, i32, C.POINTER(C.c_double)], C.c_int),
         "helm_local_solve": ([P, i32, i32, i32, P, P], C.c_int),
+        "helm_release_workspace": ([P], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -203,6 +216,9 @@ class Solver:
         out = (C.c_double * 4)()
         _check(lib.helm_sweep_stats(self._h, int(level), out))
         return dict(launches=int(out[0]), ms=out[1], flops=out[2], bytes=out[3])
+
+    def release_workspace(self):
+        _check(lib.helm_release_workspace(self._h))
 
     def resident_bytes(self):
         return lib.helm_resident_bytes(self._h)

@@ -1,0 +1,281 @@
+"""Continuous-batching server for many Helmholtz solves (serving form).
+
+Requests name a problem (velocity model, grid, spacing, frequency, PML and
+decomposition) and carry right-hand sides.  The server keeps the set-up of
+every problem it has seen resident (operators, factorisations) until device
+memory is needed for something else, admits a request when its device
+footprint (``helm_footprint``) fits next to what is resident and in flight,
+and runs admitted work on worker threads: each resident problem has its own
+library handle and HIP stream, so solves of different problems overlap on the
+device.  Requests for the same problem and tolerance that are waiting when
+the problem's handle becomes free are merged into one batched solve (one
+Krylov space per right-hand side, so each result is the same as when solved
+alone, up to rounding).  Latency = completion time - arrival time.
+
+Only orchestration lives here; every arithmetic step runs in the HIP library.
+"""
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from concurrent.futures import Future, ThreadPoolExecutor
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import helm
+
+
+@dataclass(frozen=True)
+class ProblemSpec:
+    """Everything that determines a set-up (and so the resident factorisation)."""
+    name: str
+    shape: tuple
+    h: float
+    freq: float
+    pml: tuple = (10, 10, 10, 0)
+    parts: tuple = (1, 1, 1)
+    overlap: int = 2
+    levels: int = 2
+    coarse_iters: int = 10
+    precision: str = "mixed"
+    restart: int = 20
+
+    @property
+    def n(self):
+        return int(np.prod(self.shape))
+
+
+@dataclass
+class _Request:
+    spec: ProblemSpec
+    B: object
+    tol: float
+    maxit: int
+    arrival: float
+    future: Future
+    nrhs: int
+
+
+@dataclass
+class _Entry:
+    spec: ProblemSpec
+    solver: object = None
+    resident: int = 0
+    busy: bool = False
+    last_used: float = 0.0
+
+
+@dataclass
+class ServerStats:
+    latencies: list = field(default_factory=list)
+    rhs: int = 0
+    batches: int = 0
+    setups: int = 0
+    evictions: int = 0
+    peak_accounted: int = 0
+
+
+class Server:
+    """Continuous-batching solve server on one GPU.
+
+    velocity_of(spec) must return the complex128 velocity [nz][ny][nx] of a
+    problem (host array or device tensor); it is called once per set-up.
+    """
+
+    def __init__(self, velocity_of, budget_bytes=None, workers=4, max_batch_rhs=64, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        if budget_bytes is None:
+            free, total = torch.cuda.mem_get_info(self.device)
+            budget_bytes = int(0.85 * total)
+        self.budget = int(budget_bytes)
+        self.velocity_of = velocity_of
+        self.max_batch_rhs = max_batch_rhs
+        self.weights = helm.fit_weights()
+        self._pool = ThreadPoolExecutor(max_workers=workers)
+        self._cv = threading.Condition()
+        self._queue = collections.deque()
+        self._entries = collections.OrderedDict()
+        self._inflight = 0
+        self._closed = False
+        self.stats = ServerStats()
+        self._sched = threading.Thread(target=self._loop, daemon=True)
+        self._sched.start()
+
+    # ---- public -----------------------------------------------------------
+    def submit(self, spec: ProblemSpec, B, tol=1e-6, maxit=400):
+        """Queue a solve; returns a Future of dict(X, iters, relres_true, latency_s, batch_rhs)."""
+        fut = Future()
+        req = _Request(spec, B, float(tol), int(maxit), time.perf_counter(), fut, int(B.shape[0]))
+        with self._cv:
+            if self._closed:
+                raise RuntimeError("server closed")
+            self._queue.append(req)
+            self._cv.notify_all()
+        return fut
+
+    def drain(self):
+        """Block until every submitted request has completed."""
+        with self._cv:
+            while self._queue or self._inflight_count():
+                self._cv.wait(0.05)
+
+    def close(self):
+        self.drain()
+        with self._cv:
+            self._closed = True
+            self._cv.notify_all()
+        self._sched.join()
+        self._pool.shutdown(wait=True)
+        for e in self._entries.values():
+            if e.solver is not None:
+                e.solver.close()
+        self._entries.clear()
+
+    def latency_percentiles(self):
+        lat = np.array(self.stats.latencies)
+        if lat.size == 0:
+            return {}
+        return {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                "mean_s": float(lat.mean()), "max_s": float(lat.max())}
+
+    # ---- internals ---------------------------------------------------------
+    def _inflight_count(self):
+        return sum(1 for e in self._entries.values() if e.busy)
+
+    def _footprint(self, spec, nrhs):
+        return helm.footprint(spec.shape, spec.parts, spec.overlap, spec.levels, spec.coarse_iters, spec.precision,
+                              spec.restart, nrhs)
+
+    def _accounted(self):
+        return sum(e.resident for e in self._entries.values()) + self._inflight
+
+    def _evict_for(self, need, keep_key):
+        for key in list(self._entries.keys()):  # least recently used first
+            if self._accounted() + need <= self.budget:
+                return True
+            e = self._entries[key]
+            if key == keep_key or e.busy:
+                continue
+            if e.solver is not None:
+                e.solver.close()
+            del self._entries[key]
+            self.stats.evictions += 1
+        return self._accounted() + need <= self.budget
+
+    def _loop(self):
+        with self._cv:
+            while True:
+                if self._closed and not self._queue:
+                    return
+                launched = self._try_launch()
+                if not launched:
+                    self._cv.wait(0.05)
+
+    def _try_launch(self):
+        for head in list(self._queue):
+            key = (head.spec, head.tol, head.maxit)
+            e = self._entries.get(head.spec)
+            if e is not None and e.busy:
+                continue
+            batch, nr = [], 0
+            for r in self._queue:
+                if (r.spec, r.tol, r.maxit) == key and (not batch or nr + r.nrhs <= self.max_batch_rhs):
+                    batch.append(r)
+                    nr += r.nrhs
+            full = self._footprint(head.spec, nr)
+            if e is not None and e.solver is not None:
+                # resident already: only the Krylov workspace of this batch
+                need = max(full - self._footprint(head.spec, 1), 0) + (64 << 20)
+            else:
+                need = full
+            if need > self.budget:
+                for r in batch:
+                    self._queue.remove(r)
+                    r.future.set_exception(helm.HelmError(helm.HELM_ENOMEM, "request larger than the device budget"))
+                return True
+            if not self._evict_for(need, head.spec):
+                continue
+            if e is None:
+                e = _Entry(head.spec)
+                self._entries[head.spec] = e
+            self._entries.move_to_end(head.spec)
+            e.busy = True
+            self._inflight += need
+            for r in batch:
+                self._queue.remove(r)
+            self.stats.peak_accounted = max(self.stats.peak_accounted, self._accounted())
+            self._pool.submit(self._work, e, batch, nr, need)
+            return True
+        return False
+
+    def _work(self, e, batch, nr, reserved):
+        torch = self.torch
+        try:
+            spec = e.spec
+            if e.solver is None:
+                vel = self.velocity_of(spec)
+                e.solver = helm.Solver(spec.shape, spec.h, vel, spec.freq, spec.pml, weights=self.weights,
+                                       parts=spec.parts, overlap=spec.overlap, levels=spec.levels,
+                                       coarse_iters=spec.coarse_iters, precision=spec.precision,
+                                       restart=spec.restart)
+                self.stats.setups += 1
+            parts = []
+            for r in batch:
+                b = r.B if helm._is_torch(r.B) else torch.from_numpy(np.ascontiguousarray(r.B))
+                parts.append(b.reshape(r.nrhs, -1).to(self.device))
+            Bd = torch.cat(parts, 0).contiguous() if len(parts) > 1 else parts[0].contiguous()
+            X, info = e.solver.solve(Bd, tol=batch[0].tol, maxit=batch[0].maxit)
+            e.solver.release_workspace()
+            done = time.perf_counter()
+            i0 = 0
+            with self._cv:
+                self.stats.batches += 1
+                self.stats.rhs += nr
+                for r in batch:
+                    sl = slice(i0, i0 + r.nrhs)
+                    i0 += r.nrhs
+                    lat = done - r.arrival
+                    self.stats.latencies.append(lat)
+                    r.future.set_result({"X": X[sl], "iters": info["iters"][sl], "relres_true": info["relres_true"][sl],
+                                         "status": info["status"], "latency_s": lat, "batch_rhs": nr})
+        except Exception as exc:  # report the failure on every request of the batch
+            with self._cv:
+                for r in batch:
+                    if not r.future.done():
+                        r.future.set_exception(exc)
+        finally:
+            with self._cv:
+                e.resident = e.solver.resident_bytes() if e.solver is not None else 0
+                e.busy = False
+                e.last_used = time.perf_counter()
+                self._inflight -= reserved
+                self._cv.notify_all()
+
+
+def run_poisson(server, requests, rate_hz, seed=4):
+    """Submit (spec, B, tol) requests with Poisson arrivals of the given rate; wait for all.
+
+    Returns dict(elapsed_s, rhs, rhs_per_s, latency percentiles, results).
+    """
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate_hz, size=len(requests))
+    t0 = time.perf_counter()
+    futs = []
+    t_next = t0
+    for (spec, B, tol), gap in zip(requests, gaps):
+        t_next += gap
+        dt = t_next - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        futs.append(server.submit(spec, B, tol))
+    results = [f.result() for f in futs]
+    elapsed = time.perf_counter() - t0
+    rhs = sum(int(r["X"].shape[0]) for r in results)
+    out = {"elapsed_s": elapsed, "rhs": rhs, "rhs_per_s": rhs / elapsed, "requests": len(results),
+           "results": results}
+    out.update(server.latency_percentiles())
+    return out
