@@ -138,6 +138,47 @@ def cpu_baseline(w, its_per_rhs, nrhs, budget_s=25.0):
             "t_solve_full_s": t_iter * scale * float(np.sum(its_per_rhs))}
 
 
+def serving_phase(n_requests, max_rhs=64, seed=4):
+    """Poisson stream over the seeded serving catalogue (grids 64^3..160^3, 2-8 Hz, 1-64 sources,
+    two-level ORAS with 16^3 boxes, mixed precision, tol 1e-6) at 0.8 x the capacity measured on a
+    burst of the first requests; returns p50/p99 latency and RHS/s."""
+    import inputs
+    from paper_2103_14921_amd.serving import ProblemSpec, Server, run_poisson
+    cat = inputs.serving_catalogue(seed=seed)
+    specs = [ProblemSpec(e["name"], (e["n"],) * 3, e["h"], e["freq"], (e["npml"],) * 3 + (0,), e["parts"])
+             for e in cat]
+    vel_cache = {}
+
+    def vel(spec):
+        if spec.name not in vel_cache:
+            vel_cache[spec.name] = inputs.serving_velocity(cat[[s.name for s in specs].index(spec.name)])
+        return vel_cache[spec.name]
+
+    reqs = []
+    for e, src in inputs.serving_requests(cat, n_requests, seed=seed, max_rhs=max_rhs):
+        n = cat[e]["n"]
+        B = inputs.point_source_rhs(n, n, n, src).reshape(len(src), -1)
+        reqs.append((specs[e], B, 1e-6))
+    ncal = max(4, n_requests // 4)
+    srv = Server(vel, workers=4)
+    t0 = time.perf_counter()
+    for i, f in enumerate([srv.submit(*r) for r in reqs[:ncal]]):
+        f.result()
+        print(f"[bench] serving calibration {i + 1}/{ncal} done", file=sys.stderr, flush=True)
+    capacity = ncal / (time.perf_counter() - t0)  # requests/s with set-ups included
+    srv.stats.latencies.clear()
+    out = run_poisson(srv, reqs[ncal:], rate_hz=0.8 * capacity, seed=seed,
+                      progress=lambda i, n: print(f"[bench] serving request {i}/{n} done", file=sys.stderr,
+                                                  flush=True))
+    st = srv.stats
+    srv.close()
+    worst = max(float(r["relres_true"].max()) for r in out["results"])
+    return {"requests": out["requests"], "calibration_requests": ncal, "rate_hz": 0.8 * capacity,
+            "p50_s": out["p50_s"], "p99_s": out["p99_s"], "mean_s": out["mean_s"], "rhs_per_s": out["rhs_per_s"],
+            "rhs": out["rhs"], "elapsed_s": out["elapsed_s"], "setups": st.setups, "evictions": st.evictions,
+            "batches": st.batches, "max_true_relres": worst}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +187,9 @@ def main():
     ap.add_argument("--workload", default="thrust192_mixed", choices=sorted(WORKLOADS))
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--serving-requests", type=int, default=12,
+                    help="requests in the serving stream reported beside the main line (0: skip)")
+    ap.add_argument("--serving-max-rhs", type=int, default=16, help="largest request of the serving stream")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -192,7 +236,7 @@ def main():
     info = infos[-1]
     value = nrhs * args.steps / T
     out = {
-        "metric": "RHS solved/s to 1e-6 residual (mixed ORAS-FGMRES; FP64 form alongside)",
+        "metric": "RHS solved/s to 1e-6 residual (mixed ORAS-FGMRES; FP64 form alongside; serving p50/p99)",
         "value": value, "unit": "RHS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * T / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "c64 local factors/solves, c128 elsewhere" if w["precision"] == "mixed" else "c128",
@@ -228,6 +272,11 @@ def main():
         out["mixed_vs_fp64_rel_l2_max"] = float(err.max().item())
         out["speedup_mixed_vs_fp64"] = value / out["fp64_form"]["rhs_per_s"]
         del X64
+    if args.serving_requests > 0:
+        del X
+        torch.cuda.empty_cache()
+        helm.trim_cache()
+        out["serving"] = serving_phase(args.serving_requests, args.serving_max_rhs)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, info["iters"], nrhs)
     print(json.dumps(out))

@@ -145,6 +145,11 @@ helm_status helm_sweep_stats(const helm_handle_t* h, int32_t level, double out[4
  * server hold many set-up problems and pay workspace only while solving. */
 helm_status helm_release_workspace(helm_handle_t* h);
 
+/* Device blocks freed by handles are kept in a process-wide cache and reused
+ * for requests of the same size class; this returns them all to the HIP
+ * runtime (for other allocators in the process) and reports the bytes freed. */
+size_t helm_trim_cache(void);
+
 void helm_destroy(helm_handle_t* h);
 const char* helm_last_error(void);
 

@@ -991,6 +991,12 @@ void helm_destroy(helm_handle_t* H) {
   delete H;
 }
 
+size_t helm_trim_cache(void) {
+  const size_t b = pool().cached_bytes();
+  pool().trim();
+  return b;
+}
+
 helm_status helm_release_workspace(helm_handle_t* H) {
   return guarded([&]() {
     if (!H) throw HelmError(HELM_EINVAL, "null handle");

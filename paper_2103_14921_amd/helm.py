@@ -25,7 +25,7 @@ EXPORTS = [
     "helm_last_timings", "helm_destroy", "helm_last_error", "helm_set_stream", "helm_apply_A",
     "helm_apply_M", "helm_apply_oras", "helm_restrict", "helm_prolong", "helm_apply_E", "helm_apply_Q",
     "helm_num_subdomains", "helm_subdomain_box", "helm_set_sweep_timing", "helm_sweep_stats",
-    "helm_local_solve", "helm_release_workspace",
+    "helm_local_solve", "helm_release_workspace", "helm_trim_cache",
 ]
 
 
@@ -95,6 +95,7 @@ def _load():
         "helm_sweep_stats": ([P, i32, C.POINTER(C.c_double)], C.c_int),
         "helm_local_solve": ([P, i32, i32, i32, P, P], C.c_int),
         "helm_release_workspace": ([P], C.c_int),
+        "helm_trim_cache": ([], C.c_size_t),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -138,10 +139,26 @@ def _ptr(a, n_expect):
     return C.c_void_p(a.ctypes.data)
 
 
+def trim_cache():
+    """Return the library's cached device blocks to the runtime; bytes freed."""
+    return lib.helm_trim_cache()
+
+
+def torch_alloc(fn):
+    """Run a PyTorch allocation; on out-of-memory, trim the library's device cache and retry once."""
+    import torch
+    try:
+        return fn()
+    except torch.OutOfMemoryError:
+        trim_cache()
+        torch.cuda.empty_cache()
+        return fn()
+
+
 def _empty_like_kind(a, shape):
     if _is_torch(a):
         import torch
-        return torch.empty(shape, dtype=torch.complex128, device=a.device)
+        return torch_alloc(lambda: torch.empty(shape, dtype=torch.complex128, device=a.device))
     return np.empty(shape, dtype=np.complex128)
 
 

@@ -223,11 +223,14 @@ class Server:
                                        coarse_iters=spec.coarse_iters, precision=spec.precision,
                                        restart=spec.restart)
                 self.stats.setups += 1
-            parts = []
-            for r in batch:
-                b = r.B if helm._is_torch(r.B) else torch.from_numpy(np.ascontiguousarray(r.B))
-                parts.append(b.reshape(r.nrhs, -1).to(self.device))
-            Bd = torch.cat(parts, 0).contiguous() if len(parts) > 1 else parts[0].contiguous()
+            def stage():
+                parts = []
+                for r in batch:
+                    b = r.B if helm._is_torch(r.B) else torch.from_numpy(np.ascontiguousarray(r.B))
+                    parts.append(b.reshape(r.nrhs, -1).to(self.device))
+                return torch.cat(parts, 0).contiguous() if len(parts) > 1 else parts[0].contiguous()
+
+            Bd = helm.torch_alloc(stage)
             X, info = e.solver.solve(Bd, tol=batch[0].tol, maxit=batch[0].maxit)
             e.solver.release_workspace()
             done = time.perf_counter()
@@ -256,7 +259,7 @@ class Server:
                 self._cv.notify_all()
 
 
-def run_poisson(server, requests, rate_hz, seed=4):
+def run_poisson(server, requests, rate_hz, seed=4, progress=None):
     """Submit (spec, B, tol) requests with Poisson arrivals of the given rate; wait for all.
 
     Returns dict(elapsed_s, rhs, rhs_per_s, latency percentiles, results).
@@ -272,7 +275,11 @@ def run_poisson(server, requests, rate_hz, seed=4):
         if dt > 0:
             time.sleep(dt)
         futs.append(server.submit(spec, B, tol))
-    results = [f.result() for f in futs]
+    results = []
+    for i, f in enumerate(futs):
+        results.append(f.result())
+        if progress:
+            progress(i + 1, len(futs))
     elapsed = time.perf_counter() - t0
     rhs = sum(int(r["X"].shape[0]) for r in results)
     out = {"elapsed_s": elapsed, "rhs": rhs, "rhs_per_s": rhs / elapsed, "requests": len(results),
