@@ -57,14 +57,17 @@ def make_inputs(w):
     return c, b
 
 
-def gpu_solve(helm, w, c_dev, b_dev, precision, weights, timing=False):
+def gpu_solve(helm, w, c_dev, b_dev, precision, weights, timing=False, graphs=True):
     S = helm.Solver(w["shape"], H, c_dev, FREQ, (NPML, NPML, NPML, 0), weights=weights, parts=w["parts"],
                     overlap=2, levels=w["levels"], coarse_iters=10, precision=precision, restart=w["restart"])
     if timing:
         S.set_sweep_timing(True)
+    if not graphs:
+        S.set_graphs(False)
     X, info = S.solve(b_dev, tol=w["tol"], maxit=400)
     if timing:
         info["sweeps"] = [S.sweep_stats(0), S.sweep_stats(w["levels"] - 1)]
+    info["graphs"] = S.graph_stats()
     S.close()
     return X, info
 
@@ -190,6 +193,7 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=12,
                     help="requests in the serving stream reported beside the main line (0: skip)")
     ap.add_argument("--serving-max-rhs", type=int, default=16, help="largest request of the serving stream")
+    ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly (no captured iterations)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -219,14 +223,14 @@ def main():
     print(f"[bench] {describe(args.workload, w)}", file=sys.stderr, flush=True)
 
     for i in range(args.warmup):
-        _, info = gpu_solve(helm, w, c_dev, b_dev, w["precision"], weights)
+        _, info = gpu_solve(helm, w, c_dev, b_dev, w["precision"], weights, graphs=not args.no_graphs)
         print(f"[bench] warmup {i}: setup {info['timings']['setup']:.3f} s solve {info['timings']['solve']:.3f} s "
               f"iters {info['iters'].tolist()}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     setups, solves, infos = [], [], []
     for i in range(args.steps):
-        X, info = gpu_solve(helm, w, c_dev, b_dev, w["precision"], weights, timing=True)
+        X, info = gpu_solve(helm, w, c_dev, b_dev, w["precision"], weights, timing=True, graphs=not args.no_graphs)
         setups.append(info["timings"]["setup"])
         solves.append(info["timings"]["solve"])
         infos.append(info)
@@ -248,6 +252,7 @@ def main():
         "iters": {"min": int(info["iters"].min()), "max": int(info["iters"].max()),
                   "mean": float(info["iters"].mean())},
         "max_true_relres": float(info["relres_true"].max()),
+        "graphs": info["graphs"],
     }
     # dominant kernel: the batched local solves of the coarse level (FP64 MFMA);
     # the fine-level sweep (complex FP32 on MFMA in the mixed form) alongside
@@ -262,7 +267,7 @@ def main():
         out["roofline"] = roofline_entry(info["sweeps"][0], fine_dtype)
         out["roofline"]["kernel"] = "k_oras_fused (fine level)"
     if not args.no_fp64 and w["precision"] == "mixed":
-        X64, i64 = gpu_solve(helm, w, c_dev, b_dev, "fp64", weights)
+        X64, i64 = gpu_solve(helm, w, c_dev, b_dev, "fp64", weights, graphs=not args.no_graphs)
         t64 = i64["timings"]["setup"] + i64["timings"]["solve"]
         err = torch.linalg.vector_norm(X - X64, dim=1) / torch.linalg.vector_norm(X64, dim=1)
         out["fp64_form"] = {"rhs_per_s": nrhs / t64, "solve_only_rhs_per_s": nrhs / i64["timings"]["solve"],

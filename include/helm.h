@@ -140,6 +140,19 @@ helm_status helm_last_timings(const helm_handle_t* h, double out[5]);
 helm_status helm_set_sweep_timing(helm_handle_t* h, int32_t enable);
 helm_status helm_sweep_stats(const helm_handle_t* h, int32_t level, double out[4]);
 
+/* Captured iterations (batching form).  With graphs enabled (the default),
+ * each outer FGMRES iteration -- the two-level preconditioner of eq. 2lvl with
+ * its ten inner coarse GMRES iterations, the operator product and the Arnoldi
+ * step -- is captured once as a HIP graph per iteration index, batch width,
+ * tolerance and iteration limit, after the first direct run has tuned the
+ * sweeps, and replayed from then on; results are bitwise those of direct
+ * launches.  Sweep timing stays live inside graphs (external event nodes).
+ * helm_set_graphs(h, 0) launches directly and drops the captured graphs;
+ * helm_graph_stats gives out[0] captures and out[1] replays since set-up.
+ * Graphs are dropped whenever the workspace is reallocated or released. */
+helm_status helm_set_graphs(helm_handle_t* h, int32_t enable);
+helm_status helm_graph_stats(const helm_handle_t* h, double out[2]);
+
 /* Return the handle's cached Krylov workspace (sized for its last batch) to
  * the library's device cache, keeping operators and factors resident: lets a
  * server hold many set-up problems and pay workspace only while solving. */

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -290,6 +291,31 @@ struct Workspace {
   KrylovArrays ko, kc;
 };
 
+// One outer FGMRES iteration (preconditioner, operator, Arnoldi step) captured
+// as an executable HIP graph.  Kernel arguments are baked in, so an entry is
+// valid for one iteration index, batch width, tolerance, iteration limit and
+// workspace generation.  With sweep timing on, the sweeps are bracketed by
+// external event nodes whose times are harvested at the next host sync.
+struct Captured {
+  int j = 0, nr = 0, maxit = 0;
+  double tol = 0;
+  unsigned gen = 0;
+  bool timed = false;
+  hipGraphExec_t exec = nullptr;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[2];
+  std::vector<double> fl[2], by[2];
+  bool pending = false;  // replayed with timing, events not yet read
+
+  ~Captured() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    for (int lv = 0; lv < 2; ++lv)
+      for (auto& e : ev[lv]) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+      }
+  }
+};
+
 struct helm_handle {
   int device = 0;
   hipStream_t own = nullptr, stream = nullptr;
@@ -309,8 +335,16 @@ struct helm_handle {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> sweep_ev[2];
   std::vector<double> sweep_flops[2], sweep_bytes[2];
   double sweep_stat[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // launches, ms, flops, bytes
+  // captured outer iterations
+  bool graphs = true;
+  bool graph_timing = true;  // event-record nodes accepted inside captured graphs
+  unsigned ws_gen = 0;  // bumped whenever workspace buffers move
+  std::vector<std::unique_ptr<Captured>> captured;
+  Captured* capturing = nullptr;
+  double graph_stat[2] = {0, 0};  // captures, replays
 
   ~helm_handle() {
+    captured.clear();
     if (own) (void)hipStreamDestroy(own);
   }
   bool two_level() const { return dec.levels == 2; }
@@ -458,6 +492,33 @@ size_t resident_bytes_planned(const helm_handle* H) {
   return b;
 }
 
+// Fold the sweep times of replayed graphs into the statistics (the stream has
+// been synchronised since the replay).
+void harvest_graphs(helm_handle* H) {
+  for (auto& c : H->captured) {
+    if (!c->pending) continue;
+    for (int lv = 0; lv < 2; ++lv)
+      for (size_t i = 0; i < c->ev[lv].size(); ++i) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, c->ev[lv][i].first, c->ev[lv][i].second);
+        H->sweep_stat[lv][0] += 1;
+        H->sweep_stat[lv][1] += ms;
+        H->sweep_stat[lv][2] += c->fl[lv][i];
+        H->sweep_stat[lv][3] += c->by[lv][i];
+      }
+    c->pending = false;
+  }
+}
+
+// Forget every captured iteration (their arguments point into workspace that is
+// about to move or be released).
+void drop_graphs(helm_handle* H) {
+  if (H->captured.empty()) return;
+  (void)hipStreamSynchronize(H->stream);
+  harvest_graphs(H);
+  H->captured.clear();
+}
+
 // Batch size of the next launches (the arrays hold at least W.nr columns).
 void set_batch(helm_handle* H, int nr) {
   H->ws.ko.st.nrhs = nr;
@@ -470,6 +531,8 @@ void ensure_ws(helm_handle* H, int nr) {
     set_batch(H, nr);
     return;
   }
+  drop_graphs(H);
+  ++H->ws_gen;
   W.nr = 0;
   const int m = H->dec.restart;
   const size_t vec = sizeof(z64) * (size_t)H->n * nr;
@@ -514,7 +577,7 @@ void oras_sweep(helm_handle* H, Level& L, int nr, const z64* u, z64* z, const z6
 // plus the plane vectors (gather, scatter, stored planes).
 void sweep_work(const helm_handle* H, const Level& L, int nr, double* flops, double* bytes) {
   const int es = (int)elem_size(L.prec);
-  int rg = tuned_group(es, L.bpmax, L.nsub, nr, L.nx, L.ny);
+  int rg = tuned_group(es / 2, L.bpmax, L.nsub, nr, L.nx, L.ny);  // keyed by the real type's size
   if (rg == 0) rg = L.prec ? fused_group<float>(L.bpmax, nr) : fused_group<double>(L.bpmax, nr);
   const int ngroups = rg > 0 ? (nr + rg - 1) / rg : 1;
   double f = 0, by = 0;
@@ -530,22 +593,43 @@ void sweep_work(const helm_handle* H, const Level& L, int nr, double* flops, dou
   *bytes = by;
 }
 
+// Record a timing event on the handle's stream; while the stream is being
+// captured, as an event-record node appended to the captured graph.
+void record_timing_event(helm_handle* H, hipEvent_t e) {
+  if (!H->capturing) {
+    HELM_CHECK_HIP(hipEventRecord(e, H->stream));
+    return;
+  }
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  unsigned long long id = 0;
+  hipGraph_t g = nullptr;
+  const hipGraphNode_t* deps = nullptr;
+  size_t nd = 0;
+  HELM_CHECK_HIP(hipStreamGetCaptureInfo_v2(H->stream, &st, &id, &g, &deps, &nd));
+  hipGraphNode_t node = nullptr;
+  HELM_CHECK_HIP(hipGraphAddEventRecordNode(&node, g, deps, nd, e));
+  HELM_CHECK_HIP(hipStreamUpdateCaptureDependencies(H->stream, &node, 1, hipStreamSetCaptureDependencies));
+}
+
 void oras_apply(helm_handle* H, Level& L, int nr, const z64* u, z64* z, const z64* add, void* yl, void* tb) {
   const int lv = &L == &H->fine ? 0 : 1;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (H->timing) {
     HELM_CHECK_HIP(hipEventCreate(&e0));
     HELM_CHECK_HIP(hipEventCreate(&e1));
-    HELM_CHECK_HIP(hipEventRecord(e0, H->stream));
+    record_timing_event(H, e0);
   }
   oras_sweep(H, L, nr, u, z, add, yl, tb);
   if (H->timing) {
-    HELM_CHECK_HIP(hipEventRecord(e1, H->stream));
+    record_timing_event(H, e1);
     double f, by;
     sweep_work(H, L, nr, &f, &by);
-    H->sweep_ev[lv].push_back({e0, e1});
-    H->sweep_flops[lv].push_back(f);
-    H->sweep_bytes[lv].push_back(by);
+    auto& ev = H->capturing ? H->capturing->ev[lv] : H->sweep_ev[lv];
+    auto& fl = H->capturing ? H->capturing->fl[lv] : H->sweep_flops[lv];
+    auto& bb = H->capturing ? H->capturing->by[lv] : H->sweep_bytes[lv];
+    ev.push_back({e0, e1});
+    fl.push_back(f);
+    bb.push_back(by);
   }
 }
 
@@ -644,11 +728,112 @@ int read_counter(helm_handle* H, KrylovArrays& K) {
   int v = 0;
   HELM_CHECK_HIP(hipMemcpyAsync(&v, K.counter.p, sizeof(int), hipMemcpyDeviceToHost, H->stream));
   HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+  harvest_graphs(H);
   return v;
 }
 void zero_counter(helm_handle* H, KrylovArrays& K) {
   // a fill kernel rather than a memset, so that the sequence stays capturable
   launch_fill(K.counter.as<z64>(), 1, H->stream);
+}
+
+// Outer iteration j: z_j = M^{-1} v_j, w = A z_j, Arnoldi step on w (CGS2,
+// Givens, convergence count).  No host synchronisation inside, so it can be
+// captured.
+void outer_step(helm_handle* H, int nr, int j, double tol, int maxit) {
+  Workspace& W = H->ws;
+  const long long vs = H->n * nr;
+  z64* vj = W.V.as<z64>() + j * vs;
+  z64* zj = W.Zv.as<z64>() + j * vs;
+  precond(H, nr, vj, zj);
+  launch_stencil(H->op, nr, zj, W.w.as<z64>(), H->stream);
+  zero_counter(H, W.ko);
+  arnoldi_step(H, W.ko, j, W.V.as<z64>(), W.w.as<z64>(), H->n, nr, tol, maxit, 0);
+}
+
+// Whether the next sweep of level L on nr right-hand sides would still run the
+// group-size tuner (which synchronises, so it must not be captured).
+bool sweep_untuned(const Level& L, int nr) {
+  static const bool no_tune = std::getenv("HELM_NO_TUNE") != nullptr || std::getenv("HELM_NO_FUSED") != nullptr;
+  if (no_tune) return false;
+  const int rgmax = L.prec ? fused_group<float>(L.bpmax, nr) : fused_group<double>(L.bpmax, nr);
+  if (rgmax <= 8) return false;
+  return tuned_group((int)elem_size(L.prec) / 2, L.bpmax, L.nsub, nr, L.nx, L.ny) == 0;
+}
+
+// Run outer iteration j from its captured graph, capturing it first if needed.
+// Falls back to direct launches while a sweep is untuned, and for good if the
+// runtime refuses capture.
+void run_outer_step(helm_handle* H, int nr, int j, double tol, int maxit) {
+  if (!H->graphs || (H->timing && !H->graph_timing) || sweep_untuned(H->fine, nr) ||
+      (H->two_level() && sweep_untuned(H->coarse, nr))) {
+    outer_step(H, nr, j, tol, maxit);
+    return;
+  }
+  Captured* c = nullptr;
+  for (auto& e : H->captured)
+    if (e->j == j && e->nr == nr && e->maxit == maxit && e->tol == tol && e->gen == H->ws_gen && e->timed == H->timing) {
+      c = e.get();
+      break;
+    }
+  if (!c) {
+    auto e = std::make_unique<Captured>();
+    e->j = j;
+    e->nr = nr;
+    e->maxit = maxit;
+    e->tol = tol;
+    e->gen = H->ws_gen;
+    e->timed = H->timing;
+    const hipError_t be = hipStreamBeginCapture(H->stream, hipStreamCaptureModeRelaxed);
+    if (be != hipSuccess) {
+      (void)hipGetLastError();
+      std::fprintf(stderr, "helm: stream capture unavailable (%s); launching directly\n", hipGetErrorString(be));
+      H->graphs = false;
+      outer_step(H, nr, j, tol, maxit);
+      return;
+    }
+    H->capturing = e.get();
+    hipGraph_t g = nullptr;
+    try {
+      outer_step(H, nr, j, tol, maxit);
+    } catch (const HelmError& err) {
+      H->capturing = nullptr;
+      if (hipStreamEndCapture(H->stream, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+      if (!H->timing) throw;
+      // event nodes refused by the runtime: time the sweeps with direct launches
+      (void)hipGetLastError();
+      std::fprintf(stderr, "helm: no timing events inside graphs (%s); timed iterations launch directly\n", err.what());
+      H->graph_timing = false;
+      outer_step(H, nr, j, tol, maxit);
+      return;
+    } catch (...) {
+      H->capturing = nullptr;
+      if (hipStreamEndCapture(H->stream, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    H->capturing = nullptr;
+    hipError_t ce = hipStreamEndCapture(H->stream, &g);
+    if (ce == hipSuccess && !g) ce = hipErrorInvalidValue;
+    if (ce == hipSuccess) ce = hipGraphInstantiate(&e->exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (ce != hipSuccess) {
+      // nothing captured has run: do the iteration directly, and stop capturing
+      (void)hipGetLastError();
+      std::fprintf(stderr, "helm: graph capture failed (%s); launching directly\n", hipGetErrorString(ce));
+      H->graphs = false;
+      outer_step(H, nr, j, tol, maxit);
+      return;
+    }
+    H->graph_stat[0] += 1;
+    c = e.get();
+    H->captured.push_back(std::move(e));
+  }
+  if (c->pending) {  // replayed twice without a sync in between: read the first replay's times
+    HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+    harvest_graphs(H);
+  }
+  HELM_CHECK_HIP(hipGraphLaunch(c->exec, H->stream));
+  c->pending = c->timed;
+  H->graph_stat[1] += 1;
 }
 
 // Batched FGMRES on W.nr right-hand sides held node-major in W.b / W.x.
@@ -673,12 +858,7 @@ void fgmres_chunk(helm_handle* H, int nr, double tol, int maxit, bool x0) {
   while (nact > 0) {
     launch_scale(W.w.as<z64>(), K.fac.as<double>(), W.V.as<z64>(), n, nr, H->stream);
     for (int j = 0; j < m; ++j) {
-      z64* vj = W.V.as<z64>() + j * vs;
-      z64* zj = W.Zv.as<z64>() + j * vs;
-      precond(H, nr, vj, zj);
-      launch_stencil(H->op, nr, zj, W.w.as<z64>(), H->stream);
-      zero_counter(H, K);
-      arnoldi_step(H, K, j, W.V.as<z64>(), W.w.as<z64>(), n, nr, tol, maxit, 0);
+      run_outer_step(H, nr, j, tol, maxit);
       if (read_counter(H, K) == 0) break;
       launch_scale(W.w.as<z64>(), K.fac.as<double>(), W.V.as<z64>() + (j + 1) * vs, n, nr, H->stream);
     }
@@ -988,6 +1168,7 @@ void helm_destroy(helm_handle_t* H) {
   // the handle's device work is ordered on its stream
   if (H->stream) (void)hipStreamSynchronize(H->stream);
   collect_sweep_timing(H);
+  harvest_graphs(H);
   delete H;
 }
 
@@ -1001,6 +1182,8 @@ helm_status helm_release_workspace(helm_handle_t* H) {
   return guarded([&]() {
     if (!H) throw HelmError(HELM_EINVAL, "null handle");
     HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+    drop_graphs(H);
+    ++H->ws_gen;
     H->ws.~Workspace();  // buffers go back to the device cache
     new (&H->ws) Workspace();
     return HELM_OK;
@@ -1012,6 +1195,22 @@ helm_status helm_set_sweep_timing(helm_handle_t* H, int32_t enable) {
   H->timing = enable != 0;
   for (int lv = 0; lv < 2; ++lv)
     for (int i = 0; i < 4; ++i) H->sweep_stat[lv][i] = 0;
+  return HELM_OK;
+}
+
+helm_status helm_set_graphs(helm_handle_t* H, int32_t enable) {
+  if (!H) return fail(HELM_EINVAL, "null handle");
+  return guarded([&]() {
+    drop_graphs(H);
+    H->graphs = enable != 0;
+    return HELM_OK;
+  });
+}
+
+helm_status helm_graph_stats(const helm_handle_t* H, double out[2]) {
+  if (!H || !out) return fail(HELM_EINVAL, "null argument");
+  out[0] = H->graph_stat[0];
+  out[1] = H->graph_stat[1];
   return HELM_OK;
 }
 

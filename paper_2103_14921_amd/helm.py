@@ -25,7 +25,7 @@ EXPORTS = [
     "helm_last_timings", "helm_destroy", "helm_last_error", "helm_set_stream", "helm_apply_A",
     "helm_apply_M", "helm_apply_oras", "helm_restrict", "helm_prolong", "helm_apply_E", "helm_apply_Q",
     "helm_num_subdomains", "helm_subdomain_box", "helm_set_sweep_timing", "helm_sweep_stats",
-    "helm_local_solve", "helm_release_workspace", "helm_trim_cache",
+    "helm_local_solve", "helm_release_workspace", "helm_trim_cache", "helm_set_graphs", "helm_graph_stats",
 ]
 
 
@@ -96,6 +96,8 @@ def _load():
         "helm_local_solve": ([P, i32, i32, i32, P, P], C.c_int),
         "helm_release_workspace": ([P], C.c_int),
         "helm_trim_cache": ([], C.c_size_t),
+        "helm_set_graphs": ([P, i32], C.c_int),
+        "helm_graph_stats": ([P, C.POINTER(C.c_double)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -233,6 +235,15 @@ class Solver:
         out = (C.c_double * 4)()
         _check(lib.helm_sweep_stats(self._h, int(level), out))
         return dict(launches=int(out[0]), ms=out[1], flops=out[2], bytes=out[3])
+
+    def set_graphs(self, enable=True):
+        """Capture outer iterations as HIP graphs (default on) or launch directly."""
+        _check(lib.helm_set_graphs(self._h, 1 if enable else 0))
+
+    def graph_stats(self):
+        out = (C.c_double * 2)()
+        _check(lib.helm_graph_stats(self._h, out))
+        return dict(captures=int(out[0]), replays=int(out[1]))
 
     def release_workspace(self):
         _check(lib.helm_release_workspace(self._h))
