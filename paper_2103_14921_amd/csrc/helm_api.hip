@@ -135,6 +135,7 @@ struct Level {
   long long nodes_total = 0, mat_total = 0, vec_total = 0, maxnodes = 0, maxcore = 0;
   int prec = 0;  // 0 = complex FP64 factors, 1 = complex FP32 factors
   DevBuf d_subs, aloc, sinv, E;
+  DevBuf cpl;  // plane couplings [node][18] in the factor precision (aloc is set-up only)
 };
 
 // Box planning (host): core ranges split each axis into p contiguous ranges of
@@ -229,13 +230,13 @@ size_t elem_size(int prec) { return prec ? sizeof(c32) : sizeof(z64); }
 
 // Bytes of the handle's resident data for a level (operators and factors).
 size_t level_resident_bytes(const Level& L) {
-  return (size_t)L.nodes_total * 27 * sizeof(z64) + (size_t)L.mat_total * elem_size(L.prec) +
+  return (size_t)L.nodes_total * 18 * elem_size(L.prec) + (size_t)L.mat_total * elem_size(L.prec) +
          (size_t)L.nsub * sizeof(Sub);
 }
-// Temporary set-up bytes of a level (Schur blocks and pivots).
+// Temporary set-up bytes of a level (local operator rows, Schur blocks, pivots).
 size_t level_setup_bytes(const Level& L) {
-  return (size_t)L.nsub * L.bpmax * L.bpmax * elem_size(L.prec) * 2 + (size_t)L.nsub * 16 * L.bpmax * elem_size(L.prec) +
-         (size_t)L.nsub * L.bpmax * sizeof(int) * 2 + 64;
+  return (size_t)L.nodes_total * 27 * sizeof(z64) + (size_t)L.nsub * L.bpmax * L.bpmax * elem_size(L.prec) * 2 +
+         (size_t)L.nsub * 16 * L.bpmax * elem_size(L.prec) + (size_t)L.nsub * L.bpmax * sizeof(int) * 2 + 64;
 }
 size_t level_ws_bytes(const Level& L, int nr) {
   return ((size_t)L.vec_total * nr + (size_t)L.nsub * L.bpmax * nr) * elem_size(L.prec);
@@ -654,10 +655,10 @@ void collect_sweep_timing(helm_handle* H) {
 
 void oras_sweep(helm_handle* H, Level& L, int nr, const z64* u, z64* z, const z64* add, void* yl, void* tb) {
   if (L.prec == 1)
-    Factor<float>::sweep(L.d_subs.as<Sub>(), L.nsub, L.bpmax, L.maxez, L.aloc.as<z64>(), L.sinv.as<c32>(), nr, u, z,
+    Factor<float>::sweep(L.d_subs.as<Sub>(), L.nsub, L.bpmax, L.maxez, L.cpl.as<c32>(), L.sinv.as<c32>(), nr, u, z,
                          add, L.nx, L.ny, (c32*)yl, (c32*)tb, H->stream);
   else
-    Factor<double>::sweep(L.d_subs.as<Sub>(), L.nsub, L.bpmax, L.maxez, L.aloc.as<z64>(), L.sinv.as<z64>(), nr, u, z,
+    Factor<double>::sweep(L.d_subs.as<Sub>(), L.nsub, L.bpmax, L.maxez, L.cpl.as<z64>(), L.sinv.as<z64>(), nr, u, z,
                           add, L.nx, L.ny, (z64*)yl, (z64*)tb, H->stream);
 }
 
@@ -756,7 +757,7 @@ bool sweep_untuned(const Level& L, int nr) {
   static const bool no_tune = std::getenv("HELM_NO_TUNE") != nullptr || std::getenv("HELM_NO_FUSED") != nullptr;
   if (no_tune) return false;
   const int rgmax = L.prec ? fused_group<float>(L.bpmax, nr) : fused_group<double>(L.bpmax, nr);
-  if (rgmax <= 8) return false;
+  if (rgmax == 0) return false;  // the per-plane path has nothing to tune
   return tuned_group((int)elem_size(L.prec) / 2, L.bpmax, L.nsub, nr, L.nx, L.ny) == 0;
 }
 
@@ -893,6 +894,18 @@ struct Timer {
   }
 };
 
+// The sweeps need only the plane couplings of the local operators: keep them
+// in the factor precision and release the full rows.
+void extract_couplings(helm_handle* H, Level& L) {
+  L.cpl.alloc(elem_size(L.prec) * 18 * (size_t)L.nodes_total);
+  if (L.prec)
+    launch_couplings<float>(L.nodes_total, L.aloc.as<z64>(), L.cpl.as<c32>(), H->stream);
+  else
+    launch_couplings<double>(L.nodes_total, L.aloc.as<z64>(), L.cpl.as<z64>(), H->stream);
+  HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+  L.aloc.release();
+}
+
 void factor_level(helm_handle* H, Level& L) {
   DevBuf Wt, St, Rb, piv, perm;
   const size_t es = elem_size(L.prec);
@@ -995,6 +1008,7 @@ void setup_impl(helm_handle* H, const void* velocity) {
     factor_level(H, F);
     H->t_fact = tf.stop();
   }
+  extract_couplings(H, F);
   if (H->two_level()) {
     Timer tc(H->stream);
     Level& C = H->coarse;
@@ -1006,6 +1020,7 @@ void setup_impl(helm_handle* H, const void* velocity) {
     launch_local_coarse(C.nx, C.ny, C.nz, C.E.as<z64>(), C.d_subs.as<Sub>(), C.nsub, C.maxnodes, H->c.as<z64>(), H->nx,
                         H->ny, H->omega, 2.0 * H->h, H->dec.robin, C.aloc.as<z64>(), H->stream);
     factor_level(H, C);
+    extract_couplings(H, C);
     H->t_coarse = tc.stop();
   }
   H->t_setup = tall.stop();
@@ -1249,6 +1264,7 @@ helm_status map_fields(helm_handle_t* H, int nrhs, long long len_in, long long l
     launch_to_field_major(no.as<z64>(), fo.as<z64>(), len_out, nrhs, H->stream);
     HELM_CHECK_HIP(hipMemcpyAsync(outp, fo.p, sizeof(z64) * len_out * nrhs, hipMemcpyDefault, H->stream));
     HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+    collect_sweep_timing(H);
     HELM_CHECK_HIP(hipGetLastError());
     return HELM_OK;
   });
@@ -1305,11 +1321,11 @@ helm_status helm_local_solve(helm_handle_t* H, int32_t level, int32_t s, int32_t
     void* tb = level == 0 ? H->ws.tb_f.p : H->ws.tb_c.p;
     const Sub* one = L.d_subs.as<Sub>() + s;
     if (L.prec == 1) {
-      Factor<float>::sweep(one, 1, L.bpmax, sb.ez, L.aloc.as<z64>(), L.sinv.as<c32>(), nrhs, u.as<z64>(), zg.as<z64>(),
+      Factor<float>::sweep(one, 1, L.bpmax, sb.ez, L.cpl.as<c32>(), L.sinv.as<c32>(), nrhs, u.as<z64>(), zg.as<z64>(),
                            nullptr, L.nx, L.ny, (c32*)yl, (c32*)tb, H->stream);
       launch_box_gather<float>(sb, nrhs, (const c32*)yl, xo.as<z64>(), H->stream);
     } else {
-      Factor<double>::sweep(one, 1, L.bpmax, sb.ez, L.aloc.as<z64>(), L.sinv.as<z64>(), nrhs, u.as<z64>(),
+      Factor<double>::sweep(one, 1, L.bpmax, sb.ez, L.cpl.as<z64>(), L.sinv.as<z64>(), nrhs, u.as<z64>(),
                             zg.as<z64>(), nullptr, L.nx, L.ny, (z64*)yl, (z64*)tb, H->stream);
       launch_box_gather<double>(sb, nrhs, (const z64*)yl, xo.as<z64>(), H->stream);
     }

@@ -35,6 +35,11 @@ void launch_box_scatter(const Sub& sb, int gnx, int gny, int nrhs, const z64* rl
 template <typename T>
 void launch_box_gather(const Sub& sb, int nrhs, const cpx<T>* yloc, z64* xl, hipStream_t s);
 
+// Plane couplings [node][18] (taps to plane k-1, then to plane k+1) in the
+// factor precision, extracted from the local operator rows.
+template <typename T>
+void launch_couplings(long long nodes, const z64* aloc, cpx<T>* cpl, hipStream_t s);
+
 template <typename T>
 struct Factor {
   // one plane step of the block-tridiagonal LU: S_k = D_k - L_k Sinv_{k-1} U_{k-1}, Sinv_k = S_k^{-1}
@@ -43,7 +48,7 @@ struct Factor {
                     hipStream_t s);
   // one application of the batched local solves on all subdomains:
   // z = sum_i R_i^T D_i A_i^{-1} R_i u  (+ add if add != nullptr)
-  static void sweep(const Sub* subs, int nsub, int bpmax, int maxez, const z64* aloc,
+  static void sweep(const Sub* subs, int nsub, int bpmax, int maxez, const cpx<T>* cpl,
                     const cpx<T>* sinv, int nrhs, const z64* u, z64* z, const z64* add,
                     int gnx, int gny, cpx<T>* yloc, cpx<T>* tbuf, hipStream_t s);
 };
@@ -51,7 +56,7 @@ struct Factor {
 // Fused single-launch ORAS local solves on matrix cores (ops_sweep.hip).
 // Returns false when the plane does not fit the kernel's LDS budget.
 template <typename T>
-bool oras_fused(const Sub* subs, int nsub, int bpmax, const z64* aloc, const cpx<T>* sinv, int nrhs, const z64* u,
+bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const cpx<T>* sinv, int nrhs, const z64* u,
                 z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc, hipStream_t s);
 template <typename T>
 int fused_group(int bpmax, int nrhs);

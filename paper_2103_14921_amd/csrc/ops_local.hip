@@ -391,7 +391,7 @@ __global__ void k_gj_final(const Sub* __restrict__ subs, int k, int bpmax, const
 
 // tbuf[s][p][r] = f_k[p][r] - sum_{c in N(p)} L_k[p][c] y_{k-1}[c][r], f = R_i u
 template <typename T>
-__global__ void k_fwd_rhs(const Sub* __restrict__ subs, int k, int bpmax, const z64* __restrict__ aloc,
+__global__ void k_fwd_rhs(const Sub* __restrict__ subs, int k, int bpmax, const cpx<T>* __restrict__ cpl,
                           int nrhs, const z64* __restrict__ u, int gnx, int gny, const cpx<T>* __restrict__ yloc,
                           cpx<T>* __restrict__ tbuf) {
   const int s = blockIdx.y;
@@ -409,7 +409,7 @@ __global__ void k_fwd_rhs(const Sub* __restrict__ subs, int k, int bpmax, const 
   const long long g = (sb.elo[0] + px) + (long long)gnx * ((sb.elo[1] + py) + (long long)gny * (sb.elo[2] + k));
   cpx<T> v = ccast<T>(u[g * nrhs + r]);
   if (k >= 1) {
-    const z64* rowp = aloc + (sb.node_off + (long long)k * sb.b + p) * 27;
+    const cpx<T>* rowp = cpl + (sb.node_off + (long long)k * sb.b + p) * 18;
     const cpx<T>* yprev = yloc + (sb.vec_off + (long long)(k - 1) * sb.bp) * nrhs + r;
     for (int dy = -1; dy <= 1; ++dy) {
       const int cy = py + dy;
@@ -417,7 +417,7 @@ __global__ void k_fwd_rhs(const Sub* __restrict__ subs, int k, int bpmax, const 
       for (int dx = -1; dx <= 1; ++dx) {
         const int cx = px + dx;
         if (cx < 0 || cx >= sb.ex) continue;
-        cfms(v, ccast<T>(rowp[(dy + 1) * 3 + (dx + 1)]), yprev[(long long)(cx + sb.ex * cy) * nrhs]);
+        cfms(v, rowp[(dy + 1) * 3 + (dx + 1)], yprev[(long long)(cx + sb.ex * cy) * nrhs]);
       }
     }
   }
@@ -426,7 +426,7 @@ __global__ void k_fwd_rhs(const Sub* __restrict__ subs, int k, int bpmax, const 
 
 // tbuf[s][p][r] = sum_{c in N(p)} U_k[p][c] x_{k+1}[c][r],  k = ez - 2 - step
 template <typename T>
-__global__ void k_bwd_rhs(const Sub* __restrict__ subs, int step, int bpmax, const z64* __restrict__ aloc,
+__global__ void k_bwd_rhs(const Sub* __restrict__ subs, int step, int bpmax, const cpx<T>* __restrict__ cpl,
                           int nrhs, const cpx<T>* __restrict__ yloc, cpx<T>* __restrict__ tbuf) {
   const int s = blockIdx.y;
   const Sub sb = subs[s];
@@ -441,7 +441,7 @@ __global__ void k_bwd_rhs(const Sub* __restrict__ subs, int step, int bpmax, con
     return;
   }
   const int px = p % sb.ex, py = p / sb.ex;
-  const z64* rowp = aloc + (sb.node_off + (long long)k * sb.b + p) * 27;
+  const cpx<T>* rowp = cpl + (sb.node_off + (long long)k * sb.b + p) * 18 + 9;
   const cpx<T>* xnext = yloc + (sb.vec_off + (long long)(k + 1) * sb.bp) * nrhs + r;
   cpx<T> v = mk<T>(0, 0);
   for (int dy = -1; dy <= 1; ++dy) {
@@ -450,7 +450,7 @@ __global__ void k_bwd_rhs(const Sub* __restrict__ subs, int step, int bpmax, con
     for (int dx = -1; dx <= 1; ++dx) {
       const int cx = px + dx;
       if (cx < 0 || cx >= sb.ex) continue;
-      cfma(v, ccast<T>(rowp[18 + (dy + 1) * 3 + (dx + 1)]), xnext[(long long)(cx + sb.ex * cy) * nrhs]);
+      cfma(v, rowp[(dy + 1) * 3 + (dx + 1)], xnext[(long long)(cx + sb.ex * cy) * nrhs]);
     }
   }
   *out = v;
@@ -561,6 +561,27 @@ void launch_local_coarse(int ncx, int ncy, int ncz, const z64* E, const Sub* sub
                      robin, aloc);
 }
 
+// Plane couplings of the local operators, in the factor precision, for the
+// sweeps: per local node the nine taps to the plane below (L_k) then the nine
+// to the plane above (U_k); taps that leave the box are already zero.
+template <typename T>
+__global__ void k_couplings(long long nodes, const z64* __restrict__ aloc, cpx<T>* __restrict__ cpl) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nodes * 18;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long l = i / 18;
+    const int t = (int)(i % 18);
+    cpl[i] = ccast<T>(aloc[l * 27 + (t < 9 ? t : t + 9)]);
+  }
+}
+
+template <typename T>
+void launch_couplings(long long nodes, const z64* aloc, cpx<T>* cpl, hipStream_t s) {
+  const unsigned blocks = (unsigned)std::min<long long>(ceil_div(nodes * 18, 256), 65536);
+  hipLaunchKernelGGL(k_couplings<T>, dim3(blocks), dim3(256), 0, s, nodes, aloc, cpl);
+}
+template void launch_couplings<float>(long long, const z64*, c32*, hipStream_t);
+template void launch_couplings<double>(long long, const z64*, z64*, hipStream_t);
+
 namespace {
 template <typename T, int NB, int R>
 void gj_panels(const Sub* subs, int nsub, int bpmax, int k, cpx<T>* S, cpx<T>* Rbuf, int* piv, int* err,
@@ -594,11 +615,11 @@ void Factor<T>::plane(const Sub* subs, int nsub, int bpmax, int k, const z64* al
 }
 
 template <typename T>
-void Factor<T>::sweep(const Sub* subs, int nsub, int bpmax, int maxez, const z64* aloc, const cpx<T>* sinv,
+void Factor<T>::sweep(const Sub* subs, int nsub, int bpmax, int maxez, const cpx<T>* cpl, const cpx<T>* sinv,
                       int nrhs, const z64* u, z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc,
                       cpx<T>* tbuf, hipStream_t s) {
   static const bool no_fused = std::getenv("HELM_NO_FUSED") != nullptr;
-  if (!no_fused && oras_fused<T>(subs, nsub, bpmax, aloc, sinv, nrhs, u, z, add, gnx, gny, yloc, s)) return;
+  if (!no_fused && oras_fused<T>(subs, nsub, bpmax, cpl, sinv, nrhs, u, z, add, gnx, gny, yloc, s)) return;
   dim3 gv((unsigned)ceil_div((long long)bpmax * nrhs, 256), nsub);
   const int nr = nrhs % 8 == 0 ? 8 : nrhs % 4 == 0 ? 4 : nrhs % 2 == 0 ? 2 : 1;
   dim3 gg((unsigned)ceil_div((long long)bpmax * (nrhs / nr), 256), nsub);
@@ -611,11 +632,11 @@ void Factor<T>::sweep(const Sub* subs, int nsub, int bpmax, int maxez, const z64
     }
   };
   for (int step = 0; step < maxez; ++step) {
-    hipLaunchKernelGGL(k_fwd_rhs<T>, gv, dim3(256), 0, s, subs, step, bpmax, aloc, nrhs, u, gnx, gny, yloc, tbuf);
+    hipLaunchKernelGGL(k_fwd_rhs<T>, gv, dim3(256), 0, s, subs, step, bpmax, cpl, nrhs, u, gnx, gny, yloc, tbuf);
     gemm(step, 0);
   }
   for (int step = 0; step + 1 < maxez; ++step) {
-    hipLaunchKernelGGL(k_bwd_rhs<T>, gv, dim3(256), 0, s, subs, step, bpmax, aloc, nrhs, yloc, tbuf);
+    hipLaunchKernelGGL(k_bwd_rhs<T>, gv, dim3(256), 0, s, subs, step, bpmax, cpl, nrhs, yloc, tbuf);
     gemm(step, 1);
   }
   hipLaunchKernelGGL(k_scatter<T>, dim3(1024, nsub), dim3(256), 0, s, subs, nrhs, yloc, gnx, gny, z, add);

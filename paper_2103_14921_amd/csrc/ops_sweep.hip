@@ -3,18 +3,18 @@
 // One workgroup owns one subdomain and one group of RG right-hand sides and
 // runs the whole block-tridiagonal solve in a single launch:
 //   forward   T_k = R_i u (plane k) - L_k y_{k-1};  y_k = Sinv_k T_k
-//   backward  T   = U_k x_{k+1};                    x_k = y_k - Sinv_k T
+//   backward  T   = -U_k x_{k+1};                   x_k = y_k + Sinv_k T
 // then scatters the core nodes of x (Boolean partition of unity), optionally
 // adding a second field.  The plane vector lives in LDS; the dense products
 // Sinv_k T stream Sinv_k from HBM through MFMA 16x16x4 tiles (operand lanes:
 // A[l%16][l/16], B[l/16][l%16]; output rows differ between f32 and f64).
 //
-// Complex products on real MFMA: with Sinv stored interleaved (re, im) it is a
-// real bp x 2bp matrix A; the plane vector T (bp x RG complex) is expanded on
-// the fly into the real 2bp x 2RG matrix
-//   B[2q][2r] = Re T[q][r]    B[2q][2r+1] = Im T[q][r]
-//   B[2q+1][2r] = -Im T[q][r] B[2q+1][2r+1] = Re T[q][r]
-// so that A B is the interleaved complex product (4 real products, one pass).
+// Complex products on real MFMA: Sinv is stored interleaved (re, im), so each
+// lane's A operand yields Re S and Im S together; the product is formed from
+// real 16x16x4 steps as described at plane_product (no complex arithmetic and
+// no lane-dependent operand selection inside the MFMA loop).
+#include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -53,8 +53,17 @@ __device__ __forceinline__ void wg_sync_global() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// First PF chunks of Sinv_k for the wave's first 16-row tile; they do not
-// depend on the plane operand, so they are issued before T is built.
+// Row width (in complex elements) of the plane operand in LDS.  RG >= 16 keeps
+// T itself ([bp][RG], plus 4 elements of padding in complex FP32 so that the
+// four lane groups of a read fall in different bank halves).  RG = 8 keeps the
+// lane-ready split form [bp][16] described at plane_product.
+template <typename T>
+__host__ __device__ constexpr int lds_width(int rg) {
+  return rg >= 16 ? rg + (sizeof(T) == 4 ? 4 : 0) : 16;
+}
+
+// First PF chunks of Sinv_k for the wave's first 16-row tile, issued before the
+// barrier that publishes the plane operand.
 template <typename T, int PF>
 __device__ __forceinline__ void prefetch_tile(const cpx<T>* __restrict__ Sk, int bp, int wave, int lane,
                                               cpx<T> (&a)[PF][4]) {
@@ -68,22 +77,37 @@ __device__ __forceinline__ void prefetch_tile(const cpx<T>* __restrict__ Sk, int
       for (int t = 0; t < 4; ++t) a[j][t] = Arow[16 * j + t];
 }
 
-// Rows of the wave's M-tiles of Sinv_k x Bs (Bs = T, [bp][RG] in LDS), one
+// Rows of the wave's M-tiles of Sinv_k x T (T = plane operand in LDS), one
 // 16-row tile at a time, with PF chunks of Sinv in flight per wave (the first
-// tile's initial chunks arrive pre-loaded in a); out(p, r, nb, value)
-// receives each real output entry.
+// tile's initial chunks arrive pre-loaded in a).  Lane l supplies A[l%16][l/16]
+// and B[l/16][l%16] of each 16x16x4 step; chunk j, step t covers column
+// 16 j + 4 (l/16) + t of Sinv_k.
+//
+// RG >= 16 (planar): each 16-column tile of complex right-hand sides keeps a
+// real and an imaginary accumulator,
+//   Re C += Re S Re T - Im S Im T,   Im C += Re S Im T + Im S Re T,
+// four real MFMAs per step whose B operands are read straight from T.
+// RG = 8 (split): one accumulator whose columns 0..7 hold Re C and 8..15 Im C;
+// with B1 = [Re T | Im T] and B2 = [-Im T | Re T],  C = Re S B1 + Im S B2.  The
+// operand pair (B1, B2) of each lane is stored ready in LDS, so no lane selects
+// or negates anything inside the loop.
+// out(p, r, value) receives each complex output entry (row p, column r).
 template <typename T, int RG, int PF, typename Out>
 __device__ __forceinline__ void plane_product(const cpx<T>* __restrict__ Sk, int bp, const cpx<T>* Bs, int wave,
                                               int nwaves, int lane, cpx<T> (&a)[PF][4], Out&& out) {
   using V4 = typename Mfma<T>::v4;
-  constexpr int NT = RG / 8;  // MFMA column tiles (16 real columns = 8 complex)
-  const int lrow = lane & 15, lg = lane >> 4, nb = lane & 1;
+  constexpr int W = lds_width<T>(RG);
+  constexpr int NT = RG >= 16 ? RG / 16 : 1;  // 16-column MFMA tiles
+  constexpr int NACC = RG >= 16 ? 2 : 1;
+  const int lrow = lane & 15, lg = lane >> 4;
   const int nmt = bp >> 4;
-  const cpx<T>* Bcol = Bs + 4 * lg * RG + (lrow >> 1);
+  const cpx<T>* Bcol = Bs + 4 * lg * W + lrow;
   for (int mt = wave; mt < nmt; mt += nwaves) {
-    V4 acc[NT];
+    V4 acc[NT][NACC];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = V4{0, 0, 0, 0};
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int c = 0; c < NACC; ++c) acc[nt][c] = V4{0, 0, 0, 0};
     const cpx<T>* Arow = Sk + (long long)(mt * 16 + lrow) * bp + 4 * lg;
     if (mt != wave) {
 #pragma unroll
@@ -98,14 +122,22 @@ __device__ __forceinline__ void plane_product(const cpx<T>* __restrict__ Sk, int
         const int kc = kc0 + 16 * j;
         if (kc < bp) {
 #pragma unroll
-          for (int nt = 0; nt < NT; ++nt) {
-            cpx<T> tv[4];
+          for (int t = 0; t < 4; ++t) {
+            const T are = a[j][t].re, aim = a[j][t].im;
+            if constexpr (RG >= 16) {
+              const T naim = -aim;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) tv[t] = Bcol[(kc + t) * RG + nt * 8];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-              acc[nt] = Mfma<T>::op(a[j][t].re, nb ? tv[t].im : tv[t].re, acc[nt]);
-              acc[nt] = Mfma<T>::op(a[j][t].im, nb ? tv[t].re : -tv[t].im, acc[nt]);
+              for (int nt = 0; nt < NT; ++nt) {
+                const cpx<T> tv = Bcol[(kc + t) * W + nt * 16];
+                acc[nt][0] = Mfma<T>::op(are, tv.re, acc[nt][0]);
+                acc[nt][1] = Mfma<T>::op(are, tv.im, acc[nt][1]);
+                acc[nt][0] = Mfma<T>::op(naim, tv.im, acc[nt][0]);
+                acc[nt][1] = Mfma<T>::op(aim, tv.re, acc[nt][1]);
+              }
+            } else {
+              const cpx<T> tv = Bcol[(kc + t) * W];  // (B1, B2) of this lane
+              acc[0][0] = Mfma<T>::op(are, tv.re, acc[0][0]);
+              acc[0][0] = Mfma<T>::op(aim, tv.im, acc[0][0]);
             }
           }
           const int kn = kc + 16 * PF;
@@ -115,19 +147,47 @@ __device__ __forceinline__ void plane_product(const cpx<T>* __restrict__ Sk, int
         }
       }
     }
+    if constexpr (RG >= 16) {
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
+      for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) out(mt * 16 + Mfma<T>::row(lg, v), nt * 8 + ((lane & 15) >> 1), nb, acc[nt][v]);
+        for (int v = 0; v < 4; ++v)
+          out(mt * 16 + Mfma<T>::row(lg, v), nt * 16 + lrow, mk<T>(acc[nt][0][v], acc[nt][1][v]));
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const T im = __shfl_xor(acc[0][0][v], 8);  // column lrow + 8 holds Im of column lrow
+        if (lrow < 8) out(mt * 16 + Mfma<T>::row(lg, v), lrow, mk<T>(acc[0][0][v], im));
+      }
+    }
   }
 }
 
-// LDS holds only the right operand T of the plane product ([bp][RG]); the
-// plane solutions y_k / x_k live in yloc and reach the other waves of the
-// workgroup through L2 (workgroup-scope release/acquire around the barrier).
+// Store entry (p, r) of the plane operand in the layout plane_product reads.
+template <typename T, int RG>
+__device__ __forceinline__ void put_operand(cpx<T>* Bs, int p, int r, cpx<T> v) {
+  constexpr int W = lds_width<T>(RG);
+  if constexpr (RG >= 16) {
+    Bs[p * W + r] = v;
+  } else {
+    Bs[p * W + r] = mk<T>(v.re, -v.im);     // lane r:     B1 = Re T, B2 = -Im T
+    Bs[p * W + r + 8] = mk<T>(v.im, v.re);  // lane r + 8: B1 = Im T, B2 = Re T
+  }
+}
+
+// LDS holds only the right operand T of the plane product; the plane solutions
+// y_k / x_k live in yloc and reach the other waves of the workgroup through L2
+// (workgroup-scope release/acquire around the barrier).
+// Waves per workgroup at most: 12 in FP64 (three per SIMD leave 168 registers
+// for the operand build and the product), 16 in FP32.
+template <typename T>
+constexpr int fused_max_waves() {
+  return sizeof(T) == 8 ? 12 : 16;
+}
+
 template <typename T, int RG, int PF>
-__global__ void __launch_bounds__(1024) k_oras_fused(const Sub* __restrict__ subs, int ngroups, int nrhs,
-                                                   const z64* __restrict__ aloc, const cpx<T>* __restrict__ sinv,
+__global__ void __launch_bounds__(64 * fused_max_waves<T>()) k_oras_fused(const Sub* __restrict__ subs, int ngroups, int nrhs,
+                                                   const cpx<T>* __restrict__ cpl, const cpx<T>* __restrict__ sinv,
                                                    const z64* __restrict__ u, z64* __restrict__ z,
                                                    const z64* __restrict__ add, int gnx, int gny,
                                                    cpx<T>* __restrict__ yloc) {
@@ -144,115 +204,130 @@ __global__ void __launch_bounds__(1024) k_oras_fused(const Sub* __restrict__ sub
   const int cy0 = sb.lo[1] - sb.elo[1], cy1 = sb.hi[1] - sb.elo[1];
   const int cz0 = sb.lo[2] - sb.elo[2], cz1 = sb.hi[2] - sb.elo[2];
   cpx<T>* yb = yloc + sb.vec_off * (long long)nrhs + r0;  // plane k, row p, column r at (k*bp + p)*nrhs + r
-  T* yr = reinterpret_cast<T*>(yb);
-  double* zr = reinterpret_cast<double*>(z);
-  const double* ar = reinterpret_cast<const double*>(add);
 
   auto gnode = [&](int k, int p) -> long long {
     const int px = p % ex, py = p / ex;
     return (sb.elo[0] + px) + (long long)gnx * ((sb.elo[1] + py) + (long long)gny * (sb.elo[2] + k));
   };
-  // coupling of plane k to plane kn = k + dz (dz = -1: L_k, +1: U_k) applied to the stored plane kn
-  auto couple = [&](int k, int p, int r, int dz) -> cpx<T> {
-    const int px = p % ex, py = p / ex;
-    const z64* row = aloc + (sb.node_off + (long long)k * b + p) * 27 + (dz + 1) * 9;
-    const cpx<T>* yn = yb + (long long)(k + dz) * bp * nrhs + r;
-    cpx<T> v = mk<T>(0, 0);
+  // Operand build: each thread handles NE columns r, r + LP, ... of one node p
+  // (LP = RG / NE lanes per node), so the nine coupling coefficients are loaded
+  // once for NE entries.  All loads of an entry group are issued before any is
+  // used: indices are clamped into the box (and columns into the batch) and
+  // the coefficients of clamped taps are zero.  Bases are wave-uniform and
+  // offsets 32-bit (plane vectors of a box stay far below 2^31 elements).
+  constexpr int NE = sizeof(T) == 8 ? 1 : 2, LP = RG / NE;
+  const cpx<T>* __restrict__ cbox = cpl + sb.node_off * 18;
+  // v[j] = (u_k - L_k y_{k-1}) (dz = -1, with_u) or U_k x_{k+1} (dz = +1) at (p, r + j LP)
+  auto build = [&](int k, int p, int r, int dz, bool with_u, cpx<T> (&v)[NE]) {
 #pragma unroll
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int cy = py + dy;
-      if (cy < 0 || cy >= ey) continue;
+    for (int j = 0; j < NE; ++j) v[j] = mk<T>(0, 0);
+    if (p >= b) return;
+    int col[NE];
 #pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int cx = px + dx;
-        if (cx < 0 || cx >= ex) continue;
-        cfma(v, ccast<T>(row[(dy + 1) * 3 + (dx + 1)]), yn[(long long)(cx + ex * cy) * nrhs]);
-      }
+    for (int j = 0; j < NE; ++j) col[j] = min(r + j * LP, nrg - 1);
+    if (with_u) {
+      const long long gu = gnode(k, p) * nrhs + r0;
+#pragma unroll
+      for (int j = 0; j < NE; ++j) v[j] = ccast<T>(u[gu + col[j]]);
     }
-    return v;
+    if (k + dz < 0 || k + dz >= ez) return;
+    const int px = p % ex, py = p / ex;
+    const int ro = (k * b + p) * 18 + (dz + 1) / 2 * 9;
+    const int yo = (k + dz) * bp * nrhs;
+    cpx<T> cv[9];
+    cpx<T> yv[9][NE];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int cx = px + i % 3 - 1, cy = py + i / 3 - 1;
+      const bool in = cx >= 0 && cx < ex && cy >= 0 && cy < ey;  // taps leaving the box have zero coefficients
+      const int q = yo + (in ? cx + ex * cy : p) * nrhs;
+      cv[i] = cbox[ro + i];
+#pragma unroll
+      for (int j = 0; j < NE; ++j) yv[i][j] = yb[q + col[j]];
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+#pragma unroll
+      for (int j = 0; j < NE; ++j) cfms(v[j], cv[i], yv[i][j]);
   };
-  // core node (k, p) of the box: z = x (+ add), one real component per lane
-  auto scatter = [&](int k, int p, int r, int nb, T val) {
+  auto build_plane = [&](int k, int dz, bool with_u) {
+#pragma unroll 1
+    for (int e = tid; e < bp * LP; e += FT) {
+      const int p = e / LP, r = e % LP;
+      cpx<T> v[NE];
+      build(k, p, r, dz, with_u, v);
+#pragma unroll
+      for (int j = 0; j < NE; ++j) put_operand<T, RG>(Bs, p, r + j * LP, r + j * LP < nrg ? v[j] : mk<T>(0, 0));
+    }
+  };
+  // core node (k, p) of the box: z = x (+ add)
+  auto scatter = [&](int k, int p, int r, cpx<T> val) {
     if (k < cz0 || k >= cz1 || p >= b || r >= nrg) return;
     const int px = p % ex, py = p / ex;
     if (px < cx0 || px >= cx1 || py < cy0 || py >= cy1) return;
-    const long long gi = (gnode(k, p) * nrhs + r0 + r) * 2 + nb;
-    zr[gi] = (double)val + (ar ? ar[gi] : 0.0);
+    const long long gi = gnode(k, p) * nrhs + r0 + r;
+    z64 o = ccast<double>(val);
+    if (add) o += add[gi];
+    z[gi] = o;
   };
 
-  cpx<T> a[PF][4];
   // ---- forward sweep: y_k = Sinv_k (R_i u - L_k y_{k-1})
   for (int k = 0; k < ez; ++k) {
     const cpx<T>* Sk = sinv + sb.mat_off + (long long)k * bp * bp;
-    prefetch_tile<T, PF>(Sk, bp, wave, lane, a);
-    auto tf = [&](int e) -> cpx<T> {
-      const int p = e / RG, r = e % RG;
-      cpx<T> v = mk<T>(0, 0);
-      if (p < b && r < nrg) {
-        v = ccast<T>(u[gnode(k, p) * nrhs + r0 + r]);
-        if (k > 0) v = v - couple(k, p, r, -1);
-      }
-      return v;
-    };
-    for (int e = tid; e < bp * RG; e += 2 * FT) {
-      const cpx<T> v0 = tf(e);
-      const bool two = e + FT < bp * RG;
-      const cpx<T> v1 = two ? tf(e + FT) : mk<T>(0, 0);
-      Bs[e] = v0;
-      if (two) Bs[e + FT] = v1;
-    }
+    build_plane(k, -1, true);
+    cpx<T> a[PF][4];  // per plane, so nothing stays live across the operand build
+    prefetch_tile<T, PF>(Sk, bp, wave, lane, a);  // in flight across the barrier
     __syncthreads();
     const bool last = k == ez - 1;
-    plane_product<T, RG, PF>(Sk, bp, Bs, wave, nwaves, lane, a, [&](int p, int r, int nb, T val) {
-      if (r < nrg) yr[(((long long)k * bp + p) * nrhs + r) * 2 + nb] = val;
-      if (last) scatter(k, p, r, nb, val);  // x_{ez-1} = y_{ez-1}
+    plane_product<T, RG, PF>(Sk, bp, Bs, wave, nwaves, lane, a, [&](int p, int r, cpx<T> val) {
+      if (r < nrg) yb[((long long)k * bp + p) * nrhs + r] = val;
+      if (last) scatter(k, p, r, val);  // x_{ez-1} = y_{ez-1}
     });
     wg_sync_global();
   }
   // ---- backward sweep: x_k = y_k - Sinv_k U_k x_{k+1}, x_k overwrites y_k
   for (int k = ez - 2; k >= 0; --k) {
     const cpx<T>* Sk = sinv + sb.mat_off + (long long)k * bp * bp;
-    prefetch_tile<T, PF>(Sk, bp, wave, lane, a);
-    auto tb = [&](int e) -> cpx<T> {
-      const int p = e / RG, r = e % RG;
-      return (p < b && r < nrg) ? couple(k, p, r, +1) : mk<T>(0, 0);
-    };
-    for (int e = tid; e < bp * RG; e += 2 * FT) {
-      const cpx<T> v0 = tb(e);
-      const bool two = e + FT < bp * RG;
-      const cpx<T> v1 = two ? tb(e + FT) : mk<T>(0, 0);
-      Bs[e] = v0;
-      if (two) Bs[e + FT] = v1;
-    }
+    build_plane(k, +1, false);
+    cpx<T> a[PF][4];
+    prefetch_tile<T, PF>(Sk, bp, wave, lane, a);  // in flight across the barrier
     __syncthreads();
-    plane_product<T, RG, PF>(Sk, bp, Bs, wave, nwaves, lane, a, [&](int p, int r, int nb, T val) {
+    plane_product<T, RG, PF>(Sk, bp, Bs, wave, nwaves, lane, a, [&](int p, int r, cpx<T> val) {
       if (r >= nrg) return;
-      T* yp = yr + (((long long)k * bp + p) * nrhs + r) * 2 + nb;
-      const T x = *yp - val;
+      cpx<T>* yp = yb + ((long long)k * bp + p) * nrhs + r;
+      const cpx<T> x = *yp + val;  // the operand holds -U_k x_{k+1}
       *yp = x;
-      scatter(k, p, r, nb, x);
+      scatter(k, p, r, x);
     });
     wg_sync_global();
   }
 }
+// Rounds of 16-row tiles per wave: at least enough for the wave limit; more
+// rounds mean fewer waves per workgroup, so that two workgroups (two boxes) can
+// share a compute unit and overlap one's operand build with the other's product.
+template <typename T>
+int min_rounds(int bpmax) {
+  constexpr int MW = fused_max_waves<T>();
+  return (bpmax / 16 + MW - 1) / MW;
+}
 
 template <typename T, int RG>
-void launch_fused_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, const z64* aloc,
+void launch_fused_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, int rounds, const cpx<T>* cpl,
                     const cpx<T>* sinv, const z64* u, z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc,
                     hipStream_t s) {
   constexpr int PF = sizeof(T) == 4 ? 4 : 2;
-  const size_t lds = (size_t)bpmax * RG * sizeof(cpx<T>);
+  const size_t lds = (size_t)bpmax * lds_width<T>(RG) * sizeof(cpx<T>);
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute((const void*)k_oras_fused<T, RG, PF>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               160 * 1024);
     attr = true;
   }
-  // waves per workgroup: as few rounds of 16-row tiles as 16 waves allow, evenly spread
+  // waves per workgroup: the tiles spread evenly over the given number of rounds
   const int nmt = bpmax / 16;
-  const int rounds = (nmt + 15) / 16;
+  rounds = std::max(rounds, min_rounds<T>(bpmax));
   const int nwaves = (nmt + rounds - 1) / rounds;
-  hipLaunchKernelGGL((k_oras_fused<T, RG, PF>), dim3(nsub * ngroups), dim3(64 * nwaves), lds, s, subs, ngroups, nrhs, aloc,
+  hipLaunchKernelGGL((k_oras_fused<T, RG, PF>), dim3(nsub * ngroups), dim3(64 * nwaves), lds, s, subs, ngroups, nrhs, cpl,
                      sinv, u, z, add, gnx, gny, yloc);
 }
 
@@ -264,90 +339,113 @@ constexpr size_t FUSED_LDS = 150 * 1024;
 template <typename T>
 int fused_group(int bpmax, int nrhs) {
   int rg = nrhs <= 8 ? 8 : (nrhs <= 16 ? 16 : 32);
-  while (rg >= 8 && (size_t)bpmax * rg * sizeof(cpx<T>) > FUSED_LDS) rg /= 2;
+  while (rg >= 8 && (size_t)bpmax * lds_width<T>(rg) * sizeof(cpx<T>) > FUSED_LDS) rg /= 2;
   return rg >= 8 ? rg : 0;
 }
 
 namespace {
 
 template <typename T>
-void launch_rg(int rg, const Sub* subs, int nsub, int nrhs, int bpmax, const z64* aloc, const cpx<T>* sinv,
-               const z64* u, z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc, hipStream_t s) {
+void launch_rg(int rg, int rounds, const Sub* subs, int nsub, int nrhs, int bpmax, const cpx<T>* cpl,
+               const cpx<T>* sinv, const z64* u, z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc,
+               hipStream_t s) {
   const int ngroups = (nrhs + rg - 1) / rg;
   switch (rg) {
-    case 8: launch_fused_t<T, 8>(subs, nsub, ngroups, nrhs, bpmax, aloc, sinv, u, z, add, gnx, gny, yloc, s); break;
-    case 16: launch_fused_t<T, 16>(subs, nsub, ngroups, nrhs, bpmax, aloc, sinv, u, z, add, gnx, gny, yloc, s); break;
-    default: launch_fused_t<T, 32>(subs, nsub, ngroups, nrhs, bpmax, aloc, sinv, u, z, add, gnx, gny, yloc, s); break;
+    case 8:
+      launch_fused_t<T, 8>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx, gny, yloc, s);
+      break;
+    case 16:
+      launch_fused_t<T, 16>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx, gny, yloc, s);
+      break;
+    default:
+      launch_fused_t<T, 32>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx, gny, yloc, s);
+      break;
   }
 }
 
-// Autotuned right-hand-side group of the fused sweep, per problem shape.
+// Autotuned launch shape of the fused sweep (right-hand-side group, tile
+// rounds per wave), per problem shape.
 struct TuneKey {
   int es, bpmax, nsub, nrhs, gnx, gny;
   bool operator<(const TuneKey& o) const {
     return std::tie(es, bpmax, nsub, nrhs, gnx, gny) < std::tie(o.es, o.bpmax, o.nsub, o.nrhs, o.gnx, o.gny);
   }
 };
+struct TuneVal {
+  int rg, rounds;
+};
 std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tune;
+std::map<TuneKey, TuneVal> g_tune;
 
 }  // namespace
 
 int tuned_group(int es, int bpmax, int nsub, int nrhs, int gnx, int gny) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tune.find({es, bpmax, nsub, nrhs, gnx, gny});
-  return it == g_tune.end() ? 0 : it->second;
+  return it == g_tune.end() ? 0 : it->second.rg;
 }
 
 template <typename T>
-bool oras_fused(const Sub* subs, int nsub, int bpmax, const z64* aloc, const cpx<T>* sinv, int nrhs, const z64* u,
+bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const cpx<T>* sinv, int nrhs, const z64* u,
                 z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc, hipStream_t s) {
   const int rgmax = fused_group<T>(bpmax, nrhs);
   if (rgmax == 0) return false;
   const TuneKey key{(int)sizeof(T), bpmax, nsub, nrhs, gnx, gny};
-  int rg = 0;
+  TuneVal tv{0, 0};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(key);
-    if (it != g_tune.end()) rg = it->second;
+    if (it != g_tune.end()) tv = it->second;
   }
   static const bool no_tune = std::getenv("HELM_NO_TUNE") != nullptr;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   (void)hipStreamIsCapturing(s, &cap);
-  if (rg == 0 && !no_tune && cap == hipStreamCaptureStatusNone && rgmax > 8) {
-    // time every admissible group size twice on this very input (the sweep is
-    // idempotent: z and the scratch planes are overwritten) and keep the fastest
+  const int r0 = min_rounds<T>(bpmax), nmt = bpmax / 16;
+  if (tv.rg == 0 && !no_tune && cap == hipStreamCaptureStatusNone) {
+    // time every admissible (group, rounds) pair twice on this very input (the
+    // sweep is idempotent: z and the scratch planes are overwritten) and keep
+    // the fastest
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     float best = 1e30f;
     for (int cand = 8; cand <= rgmax; cand *= 2) {
-      float tot = 0.f;
-      for (int rep = 0; rep < 2; ++rep) {
-        (void)hipEventRecord(e0, s);
-        launch_rg<T>(cand, subs, nsub, nrhs, bpmax, aloc, sinv, u, z, add, gnx, gny, yloc, s);
-        (void)hipEventRecord(e1, s);
-        (void)hipEventSynchronize(e1);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (rep > 0) tot += ms;
-      }
-      if (tot < best) {
-        best = tot;
-        rg = cand;
+      int last_waves = 0;
+      for (int rounds = r0; rounds <= r0 + 2; ++rounds) {
+        const int waves = (nmt + rounds - 1) / rounds;
+        if (waves == last_waves) continue;
+        last_waves = waves;
+        float tot = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {
+          (void)hipEventRecord(e0, s);
+          launch_rg<T>(cand, rounds, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, s);
+          (void)hipEventRecord(e1, s);
+          (void)hipEventSynchronize(e1);
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          if (rep > 0) tot += ms;
+        }
+        if (tot < best) {
+          best = tot;
+          tv = {cand, rounds};
+        }
       }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    static const bool verbose = std::getenv("HELM_TUNE_VERBOSE") != nullptr;
+    if (verbose)
+      std::fprintf(stderr, "helm: sweep tuned (fp%d, bp %d, %d boxes, %d rhs): group %d, %d waves, %.3f ms\n",
+                   (int)sizeof(T) * 8, bpmax, nsub, nrhs, tv.rg, (nmt + tv.rounds - 1) / tv.rounds, best);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[key] = rg;
+    g_tune[key] = tv;
   }
-  if (rg == 0) rg = rgmax;
-  launch_rg<T>(rg, subs, nsub, nrhs, bpmax, aloc, sinv, u, z, add, gnx, gny, yloc, s);
+  if (tv.rg == 0) tv = {rgmax, r0};
+  launch_rg<T>(tv.rg, tv.rounds, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, s);
   return true;
 }
 
-template bool oras_fused<float>(const Sub*, int, int, const z64*, const c32*, int, const z64*, z64*, const z64*, int,
+template bool oras_fused<float>(const Sub*, int, int, const c32*, const c32*, int, const z64*, z64*, const z64*, int,
                                 int, c32*, hipStream_t);
 template bool oras_fused<double>(const Sub*, int, int, const z64*, const z64*, int, const z64*, z64*, const z64*, int,
                                  int, z64*, hipStream_t);
