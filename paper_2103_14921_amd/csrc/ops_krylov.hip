@@ -73,7 +73,10 @@ __device__ __forceinline__ Span block_span(long long len) {
   return {lo, lo + per < len ? lo + per : len};
 }
 
-// partial[blk][v][r] = sum over the block's nodes of conj(V_v) w
+// Block partial sums are stored output-major, partial[(v * nrhs + r) * nblk + blk],
+// so that the final reductions read each output's partials contiguously.
+
+// partial[v][r][blk] = sum over the block's nodes of conj(V_v) w
 __global__ void __launch_bounds__(256) k_dots(const z64* __restrict__ V, long long vstride, int nv,
                                               const z64* __restrict__ w, long long len, int nrhs,
                                               z64* __restrict__ partial) {
@@ -102,32 +105,43 @@ __global__ void __launch_bounds__(256) k_dots(const z64* __restrict__ V, long lo
       if (lane == 0) {
         z64 s = red[r];
         for (int l = 1; l < nl; ++l) s += red[l * nrhs + r];
-        partial[((long long)blockIdx.x * nv + v) * nrhs + r] = s;
+        partial[((long long)v * nrhs + r) * gridDim.x + blockIdx.x] = s;
       }
       __syncthreads();
     }
   }
 }
 
-// out[t] = sum_b partial[b][t] for t < nout: 32 outputs per block, 8 lanes each, fixed order
+// Fixed-order sum over the 64 lanes of a wave (the same tree on every call).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+  return v;
+}
+__device__ __forceinline__ z64 wave_sum(z64 v) { return mk(wave_sum(v.re), wave_sum(v.im)); }
+
+// out[t] = sum_b partial[t][b] for t < nout: one wave per output, lanes over
+// the blocks (coalesced), four independent accumulators, fixed order.
 __global__ void __launch_bounds__(256) k_dots_final(const z64* __restrict__ partial, int nblk, int nv, int nrhs,
                                                     z64* __restrict__ h) {
-  __shared__ z64 red[256];
   const int nout = nv * nrhs;
-  const int t = blockIdx.x * 32 + (threadIdx.x & 31), lane = threadIdx.x >> 5;
-  z64 s = mk(0.0, 0.0);
-  if (t < nout)
-    for (int b = lane; b < nblk; b += 8) s += partial[(long long)b * nout + t];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  if (lane == 0 && t < nout) {
-    z64 a = red[threadIdx.x];
-    for (int l = 1; l < 8; ++l) a += red[threadIdx.x + 32 * l];
-    h[t] = a;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (t >= nout) return;
+  const z64* p = partial + (long long)t * nblk;
+  z64 s[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+  int b = lane;
+  for (; b + 192 < nblk; b += 256) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s[i] += p[b + 64 * i];
   }
+  if (b < nblk) s[0] += p[b];
+  if (b + 64 < nblk) s[1] += p[b + 64];
+  if (b + 128 < nblk) s[2] += p[b + 128];
+  const z64 tot = wave_sum((s[0] + s[1]) + (s[2] + s[3]));
+  if (lane == 0) h[t] = tot;
 }
 
-// w -= sum_v h[v][r] V_v; partial[blk][r] = sum |w|^2 over the block's nodes (if partial)
+// w -= sum_v h[v][r] V_v; partial[r][blk] = sum |w|^2 over the block's nodes (if partial)
 __global__ void __launch_bounds__(256) k_axpy_multi(const z64* __restrict__ V, long long vstride, int nv,
                                                     const z64* __restrict__ h, z64* __restrict__ w, long long len,
                                                     int nrhs, double* __restrict__ partial) {
@@ -157,12 +171,12 @@ __global__ void __launch_bounds__(256) k_axpy_multi(const z64* __restrict__ V, l
     if (lane == 0) {
       double s = red[r];
       for (int l = 1; l < nl; ++l) s += red[l * nrhs + r];
-      partial[(long long)blockIdx.x * nrhs + r] = s;
+      partial[(long long)r * gridDim.x + blockIdx.x] = s;
     }
   }
 }
 
-// Fused CGS pass: w -= sum_v h[v][r] V_v, then partial[blk][v][r] = sum conj(V_v) w
+// Fused CGS pass: w -= sum_v h[v][r] V_v, then partial[v][r][blk] = sum conj(V_v) w
 // over the block's nodes -- the update of the first Gram-Schmidt pass and the
 // projections of the second in one read of the basis.
 __global__ void __launch_bounds__(256) k_axpy_dots(const z64* __restrict__ V, long long vstride, int nv,
@@ -204,7 +218,7 @@ __global__ void __launch_bounds__(256) k_axpy_dots(const z64* __restrict__ V, lo
       if (lane == 0) {
         z64 sacc = red[r];
         for (int l = 1; l < nl; ++l) sacc += red[l * nrhs + r];
-        partial[((long long)blockIdx.x * nv + v) * nrhs + r] = sacc;
+        partial[((long long)v * nrhs + r) * gridDim.x + blockIdx.x] = sacc;
       }
       __syncthreads();
     }
@@ -227,24 +241,27 @@ __global__ void __launch_bounds__(256) k_norm2(const z64* __restrict__ w, long l
   if (lane == 0) {
     double s = red[r];
     for (int l = 1; l < nl; ++l) s += red[l * nrhs + r];
-    partial[(long long)blockIdx.x * nrhs + r] = s;
+    partial[(long long)r * gridDim.x + blockIdx.x] = s;
   }
 }
 
+// out[r] = sum_b partial[r][b]: one wave per output, as k_dots_final.
 __global__ void __launch_bounds__(256) k_sum_final(const double* __restrict__ partial, int nblk, int nrhs,
                                                    double* __restrict__ out) {
-  __shared__ double red[256];
-  const int r = blockIdx.x * 32 + (threadIdx.x & 31), lane = threadIdx.x >> 5;
-  double s = 0.0;
-  if (r < nrhs)
-    for (int b = lane; b < nblk; b += 8) s += partial[(long long)b * nrhs + r];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  if (lane == 0 && r < nrhs) {
-    double a = red[threadIdx.x];
-    for (int l = 1; l < 8; ++l) a += red[threadIdx.x + 32 * l];
-    out[r] = a;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (r >= nrhs) return;
+  const double* p = partial + (long long)r * nblk;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  int b = lane;
+  for (; b + 192 < nblk; b += 256) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s[i] += p[b + 64 * i];
   }
+  if (b < nblk) s[0] += p[b];
+  if (b + 64 < nblk) s[1] += p[b + 64];
+  if (b + 128 < nblk) s[2] += p[b + 128];
+  const double tot = wave_sum((s[0] + s[1]) + (s[2] + s[3]));
+  if (lane == 0) out[r] = tot;
 }
 
 __global__ void k_scale(const z64* __restrict__ w, const double* __restrict__ fac, z64* __restrict__ out,
@@ -434,7 +451,7 @@ void launch_dots(const z64* V, long long vstride, int nv, const z64* w, long lon
   for (int v0 = 0; v0 < nv; v0 += NVMAX) {
     const int nvb = std::min(NVMAX, nv - v0);
     hipLaunchKernelGGL(k_dots, dim3(nblk), dim3(256), 0, s, V + v0 * vstride, vstride, nvb, w, len, nrhs, partial);
-    hipLaunchKernelGGL(k_dots_final, dim3((unsigned)ceil_div(nvb * nrhs, 32)), dim3(256), 0, s, partial, nblk, nvb,
+    hipLaunchKernelGGL(k_dots_final, dim3((unsigned)ceil_div(nvb * nrhs, 4)), dim3(256), 0, s, partial, nblk, nvb,
                        nrhs, h + (long long)v0 * nrhs);
   }
 }
@@ -449,7 +466,7 @@ void launch_axpy_multi(const z64* V, long long vstride, int nv, const z64* h, z6
                        h + (long long)v0 * nrhs, w, len, nrhs, (last && nrm2) ? partial : nullptr);
   }
   if (nrm2)
-    hipLaunchKernelGGL(k_sum_final, dim3((unsigned)ceil_div(nrhs, 32)), dim3(256), 0, s, partial, nblk, nrhs, nrm2);
+    hipLaunchKernelGGL(k_sum_final, dim3((unsigned)ceil_div(nrhs, 4)), dim3(256), 0, s, partial, nblk, nrhs, nrm2);
 }
 
 bool launch_axpy_dots(const z64* V, long long vstride, int nv, const z64* h, z64* w, long long len, int nrhs,
@@ -458,7 +475,7 @@ bool launch_axpy_dots(const z64* V, long long vstride, int nv, const z64* h, z64
   const int nblk = red_blocks(len);
   hipLaunchKernelGGL(k_axpy_dots, dim3(nblk), dim3(256), (size_t)nv * nrhs * sizeof(z64), s, V, vstride, nv, h, w, len,
                      nrhs, partial);
-  hipLaunchKernelGGL(k_dots_final, dim3((unsigned)ceil_div(nv * nrhs, 32)), dim3(256), 0, s, partial, nblk, nv, nrhs,
+  hipLaunchKernelGGL(k_dots_final, dim3((unsigned)ceil_div(nv * nrhs, 4)), dim3(256), 0, s, partial, nblk, nv, nrhs,
                      h2);
   return true;
 }
@@ -466,7 +483,7 @@ bool launch_axpy_dots(const z64* V, long long vstride, int nv, const z64* h, z64
 void launch_norm2(const z64* w, long long len, int nrhs, double* partial, double* nrm2, hipStream_t s) {
   const int nblk = red_blocks(len);
   hipLaunchKernelGGL(k_norm2, dim3(nblk), dim3(256), 0, s, w, len, nrhs, partial);
-  hipLaunchKernelGGL(k_sum_final, dim3((unsigned)ceil_div(nrhs, 32)), dim3(256), 0, s, partial, nblk, nrhs, nrm2);
+  hipLaunchKernelGGL(k_sum_final, dim3((unsigned)ceil_div(nrhs, 4)), dim3(256), 0, s, partial, nblk, nrhs, nrm2);
 }
 
 void launch_scale(const z64* w, const double* fac, z64* out, long long len, int nrhs, hipStream_t s) {
