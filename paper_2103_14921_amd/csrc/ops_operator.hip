@@ -144,17 +144,147 @@ __global__ void __launch_bounds__(256) k_stencil2(OpDev op, int nrhs, const z64*
     const long long q = i / op.nx;
     const int iy = (int)(q % op.ny);
     const int iz = (int)(q / op.ny);
+    // ghost neighbours have zero coefficients: their loads are clamped into the
+    // grid and issued with the others (no branches, all 27 loads in flight)
     z64 acc = mk(0.0, 0.0);
 #pragma unroll
     for (int o = 0; o < 27; ++o) {
-      const int jx = ix + o % 3 - 1, jy = iy + (o / 3) % 3 - 1, jz = iz + o / 9 - 1;
-      if (jx < 0 || jx >= op.nx || jy < 0 || jy >= op.ny || jz < 0 || jz >= op.nz) continue;
+      const int jx = min(max(ix + o % 3 - 1, 0), op.nx - 1);
+      const int jy = min(max(iy + (o / 3) % 3 - 1, 0), op.ny - 1);
+      const int jz = min(max(iz + o / 9 - 1, 0), op.nz - 1);
       const long long j = jx + (long long)op.nx * (jy + (long long)op.ny * jz);
       cfma(acc, coef[a][o], x[j * nrhs + r]);
     }
     if (b) y[i * nrhs + r] = b[i * nrhs + r] - acc;
     else y[i * nrhs + r] = acc;
   }
+}
+
+// Row-tiled 27-point products (batches of 8 or more right-hand sides).  A
+// block owns a segment of at most TW consecutive nodes of one grid row (iy, iz)
+// and all right-hand sides.  Phase 1 puts the 27 coefficients of each node in
+// LDS (zero towards neighbours outside the grid); phase 2 gives each thread NXT
+// consecutive nodes of one right-hand side: for each of the nine neighbour
+// rows it loads NXT + 2 values once and uses them for all NXT outputs, where a
+// node-per-thread product issues 27 vector loads per output.
+constexpr int TW = 64, NXT = 4;
+
+struct RowTile {
+  int iy, iz, x0, w;
+};
+// Workgroups are dispatched round-robin over the XCDs (each with its own L2):
+// give XCD c the contiguous range of tiles [start_c, start_c + count_c), so that
+// neighbouring rows, which share eight of their nine input rows, meet in the
+// same L2.
+__device__ __forceinline__ long long xcd_contiguous(long long b, long long nb) {
+  constexpr int NXCD = 8;
+  const long long q = nb / NXCD, rem = nb % NXCD;
+  const long long c = b % NXCD, k = b / NXCD;
+  return c * q + (c < rem ? c : rem) + k;
+}
+
+__device__ __forceinline__ RowTile row_tile(int nx, int ny) {
+  const int nt = (nx + TW - 1) / TW;
+  const int tw = ((nx + nt - 1) / nt + NXT - 1) / NXT * NXT;  // balanced segment width, multiple of NXT
+  const long long lb = xcd_contiguous(blockIdx.x, gridDim.x);
+  const long long row = lb / nt;
+  RowTile t;
+  t.iy = (int)(row % ny);
+  t.iz = (int)(row / ny);
+  t.x0 = (int)(lb % nt) * tw;
+  t.w = min(tw, nx - t.x0);
+  return t;
+}
+
+// y = cf x (or b - cf x) on the tile; cf[a][o] holds node x0 + a's row.
+__device__ __forceinline__ void tile_product(const RowTile& t, int nx, int ny, int nz, int nrhs,
+                                             const z64 (*cf)[27], const z64* __restrict__ x, z64* __restrict__ y,
+                                             const z64* __restrict__ b) {
+  const int ngr = (t.w + NXT - 1) / NXT;
+  for (int item = threadIdx.x; item < ngr * nrhs; item += blockDim.x) {
+    const int g = item / nrhs, r = item % nrhs;
+    const int xa = t.x0 + g * NXT;
+    z64 acc[NXT];
+#pragma unroll
+    for (int m = 0; m < NXT; ++m) acc[m] = mk(0.0, 0.0);
+    // the nine neighbour rows (dz, dy) in order; latency is hidden by the
+    // other waves of the compute unit
+#pragma unroll 1
+    for (int k = 0; k < 9; ++k) {
+      const int jz = min(max(t.iz + k / 3 - 1, 0), nz - 1), jy = min(max(t.iy + k % 3 - 1, 0), ny - 1);
+      const z64* xr = x + (long long)nx * (jy + (long long)ny * jz) * nrhs + r;
+      z64 v[NXT + 2];
+#pragma unroll
+      for (int q = 0; q < NXT + 2; ++q) v[q] = xr[(long long)min(max(xa - 1 + q, 0), nx - 1) * nrhs];
+      const int ob = 3 * k;
+#pragma unroll
+      for (int m = 0; m < NXT; ++m)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) cfma(acc[m], cf[g * NXT + m][ob + dx], v[m + dx]);
+    }
+    const long long rowi = (long long)nx * (t.iy + (long long)ny * t.iz);
+#pragma unroll
+    for (int m = 0; m < NXT; ++m) {
+      if (xa + m >= t.x0 + t.w) break;
+      const long long e = (rowi + xa + m) * nrhs + r;
+      y[e] = b ? b[e] - acc[m] : acc[m];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_stencil_rows(OpDev op, int nrhs, const z64* __restrict__ x,
+                                                      z64* __restrict__ y, const z64* __restrict__ b) {
+  __shared__ z64 cf[TW][27];
+  const RowTile t = row_tile(op.nx, op.ny);
+  // phase 1: four lanes per node, offsets o = q, q + 4, ...; the stiffness sum
+  // of the diagonal is reduced over the four lanes
+  const int a = threadIdx.x >> 2, q = threadIdx.x & 3;
+  z64 ssum = mk(0.0, 0.0), si = mk(0.0, 0.0);
+  if (a < t.w) {
+    const int ix = t.x0 + a;
+    const long long i = ix + (long long)op.nx * (t.iy + (long long)op.ny * t.iz);
+    si = op.sigma[i];
+    const bool flat = op.flat[op.off_int[0] + ix] && op.flat[op.off_int[1] + t.iy] && op.flat[op.off_int[2] + t.iz];
+    for (int o = q; o < 27; o += 4) {
+      if (o == 13) continue;
+      const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+      const int cls = abs(ox) + abs(oy) + abs(oz);
+      const z64 st = flat ? mk(op.alpha[cls - 1] * op.h2inv, 0.0) : stiff_coef(op, ix, t.iy, t.iz, ox, oy, oz);
+      ssum += st;
+      const int jx = ix + ox, jy = t.iy + oy, jz = t.iz + oz;
+      z64 c = mk(0.0, 0.0);
+      if (jx >= 0 && jx < op.nx && jy >= 0 && jy < op.ny && jz >= 0 && jz < op.nz)
+        c = st + (0.5 * op.wm[cls]) * (si + op.sigma[jx + (long long)op.nx * (jy + (long long)op.ny * jz)]);
+      cf[a][o] = c;
+    }
+  } else if (a < TW) {
+    for (int o = q; o < 27; o += 4) cf[a][o] = mk(0.0, 0.0);
+  }
+  ssum.re += __shfl_xor(ssum.re, 1);
+  ssum.im += __shfl_xor(ssum.im, 1);
+  ssum.re += __shfl_xor(ssum.re, 2);
+  ssum.im += __shfl_xor(ssum.im, 2);
+  if (q == 0 && a < TW) cf[a][13] = a < t.w ? op.wm[0] * si - ssum : mk(0.0, 0.0);
+  __syncthreads();
+  tile_product(t, op.nx, op.ny, op.nz, nrhs, cf, x, y, b);
+}
+
+__global__ void __launch_bounds__(256) k_coarse_spmv_rows(int ncx, int ncy, int ncz, const z64* __restrict__ E,
+                                                          int nrhs, const z64* __restrict__ x, z64* __restrict__ y) {
+  __shared__ z64 cf[TW][27];
+  const RowTile t = row_tile(ncx, ncy);
+  const long long rowi = (long long)ncx * (t.iy + (long long)ncy * t.iz);
+  for (int e = threadIdx.x; e < TW * 27; e += blockDim.x) {
+    const int a = e / 27, o = e % 27;
+    z64 c = mk(0.0, 0.0);
+    if (a < t.w) {
+      const int jx = t.x0 + a + o % 3 - 1, jy = t.iy + (o / 3) % 3 - 1, jz = t.iz + o / 9 - 1;
+      if (jx >= 0 && jx < ncx && jy >= 0 && jy < ncy && jz >= 0 && jz < ncz) c = E[(rowi + t.x0 + a) * 27 + o];
+    }
+    cf[a][o] = c;
+  }
+  __syncthreads();
+  tile_product(t, ncx, ncy, ncz, nrhs, cf, x, y, nullptr);
 }
 
 // E[I][o] = sum_i sum_j Z[i,I] A[i,j] Z[j,I+o]
@@ -224,12 +354,15 @@ __global__ void __launch_bounds__(256) k_coarse_spmv2(int ncx, int ncy, int ncz,
   const int cz = (int)(I / ((long long)ncx * ncy));
   const z64* e = E + I * 27;
   z64 acc = mk(0.0, 0.0);
+  // branch-free: indices clamped into the grid, taps leaving it masked
 #pragma unroll
   for (int o = 0; o < 27; ++o) {
-    const int jx = cx + o % 3 - 1, jy = cy + (o / 3) % 3 - 1, jz = cz + o / 9 - 1;
-    if (jx < 0 || jx >= ncx || jy < 0 || jy >= ncy || jz < 0 || jz >= ncz) continue;
+    const int ux = cx + o % 3 - 1, uy = cy + (o / 3) % 3 - 1, uz = cz + o / 9 - 1;
+    const bool in = ux >= 0 && ux < ncx && uy >= 0 && uy < ncy && uz >= 0 && uz < ncz;
+    const int jx = min(max(ux, 0), ncx - 1), jy = min(max(uy, 0), ncy - 1), jz = min(max(uz, 0), ncz - 1);
     const long long J = jx + (long long)ncx * (jy + (long long)ncy * jz);
-    cfma(acc, e[o], x[J * nrhs + r]);
+    const z64 c = e[o];
+    cfma(acc, in ? c : mk(0.0, 0.0), x[J * nrhs + r]);
   }
   y[t] = acc;
 }
@@ -246,16 +379,18 @@ __global__ void k_restrict(int nx, int ny, int nz, int nrhs, const z64* __restri
   const int cy = (int)((I / ncx) % ncy);
   const int cz = (int)(I / ((long long)ncx * ncy));
   z64 acc = mk(0.0, 0.0);
+  // branch-free: fine indices clamped into the grid, weights of taps leaving it zero
+#pragma unroll
   for (int dz = -1; dz <= 1; ++dz) {
-    const int iz = 2 * cz + dz;
-    if (iz < 0 || iz >= nz) continue;
+    const int uz = 2 * cz + dz, iz = min(max(uz, 0), nz - 1);
+#pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
-      const int iy = 2 * cy + dy;
-      if (iy < 0 || iy >= ny) continue;
+      const int uy = 2 * cy + dy, iy = min(max(uy, 0), ny - 1);
+#pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
-        const int ix = 2 * cx + dx;
-        if (ix < 0 || ix >= nx) continue;
-        const double w = (dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0);
+        const int ux = 2 * cx + dx, ix = min(max(ux, 0), nx - 1);
+        const bool in = ux >= 0 && ux < nx && uy >= 0 && uy < ny && uz >= 0 && uz < nz;
+        const double w = in ? (dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0) : 0.0;
         acc += w * rf[(ix + (long long)nx * (iy + (long long)ny * iz)) * nrhs + r];
       }
     }
@@ -274,23 +409,30 @@ __global__ void k_prolong(int nx, int ny, int nz, int nrhs, const z64* __restric
   const int ix = (int)(i % nx);
   const int iy = (int)((i / nx) % ny);
   const int iz = (int)(i / ((long long)nx * ny));
-  int xs[2], ys[2], zs[2], nxs, nys, nzs;
-  double wx, wy, wz;
-  if ((ix & 1) == 0) { xs[0] = ix / 2; nxs = 1; wx = 1.0; } else { xs[0] = (ix - 1) / 2; xs[1] = (ix + 1) / 2; nxs = 2; wx = 0.5; }
-  if ((iy & 1) == 0) { ys[0] = iy / 2; nys = 1; wy = 1.0; } else { ys[0] = (iy - 1) / 2; ys[1] = (iy + 1) / 2; nys = 2; wy = 0.5; }
-  if ((iz & 1) == 0) { zs[0] = iz / 2; nzs = 1; wz = 1.0; } else { zs[0] = (iz - 1) / 2; zs[1] = (iz + 1) / 2; nzs = 2; wz = 0.5; }
+  // two coarse taps per axis: (i - 1)/2 and (i + 1)/2 with weight 1/2 each for
+  // odd i; i/2 with weight 1 (and a zero-weight second tap) for even i; taps
+  // beyond the coarse grid get weight zero and a clamped index
+  int xs[2], ys[2], zs[2];
+  double wx[2], wy[2], wz[2];
+  auto taps = [](int i, int nc, int* js, double* ws) {
+    const bool odd = i & 1;
+    js[0] = i >> 1;
+    ws[0] = odd ? 0.5 : 1.0;
+    const int j1 = (i + 1) >> 1;
+    js[1] = min(j1, nc - 1);
+    ws[1] = (odd && j1 < nc) ? 0.5 : 0.0;
+  };
+  taps(ix, ncx, xs, wx);
+  taps(iy, ncy, ys, wy);
+  taps(iz, ncz, zs, wz);
   z64 acc = mk(0.0, 0.0);
-  const double w = wx * wy * wz;
-  for (int a = 0; a < nzs; ++a) {
-    if (zs[a] >= ncz) continue;
-    for (int b2 = 0; b2 < nys; ++b2) {
-      if (ys[b2] >= ncy) continue;
-      for (int cc = 0; cc < nxs; ++cc) {
-        if (xs[cc] >= ncx) continue;
-        acc += w * c[(xs[cc] + (long long)ncx * (ys[b2] + (long long)ncy * zs[a])) * nrhs + r];
-      }
-    }
-  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b2 = 0; b2 < 2; ++b2)
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc)
+        acc += (wz[a] * wy[b2] * wx[cc]) * c[(xs[cc] + (long long)ncx * (ys[b2] + (long long)ncy * zs[a])) * nrhs + r];
   q[i * nrhs + r] = acc;
 }
 
@@ -321,7 +463,15 @@ void launch_sigma(const OpDev& op, const z64* c, double omega, hipStream_t s) {
   hipLaunchKernelGGL(k_sigma, dim3(2048), dim3(256), 0, s, op, c, omega, const_cast<z64*>(op.sigma));
 }
 
+static unsigned row_tiles(int nx, int ny, int nz) {
+  return (unsigned)((long long)((nx + TW - 1) / TW) * ny * nz);
+}
+
 static void stencil_dispatch(const OpDev& op, int nrhs, const z64* x, z64* y, const z64* b, hipStream_t s) {
+  if (nrhs >= NXT) {
+    hipLaunchKernelGGL(k_stencil_rows, dim3(row_tiles(op.nx, op.ny, op.nz)), dim3(256), 0, s, op, nrhs, x, y, b);
+    return;
+  }
   const long long n = (long long)op.nx * op.ny * op.nz;
   const int nb = nrhs >= 256 ? 1 : (nrhs >= 4 ? 256 / nrhs : 64);
   hipLaunchKernelGGL(k_stencil2, dim3((unsigned)ceil_div(n, nb)), dim3(256), sizeof(z64) * 27 * 2 * nb, s, op, nrhs, x,
@@ -343,6 +493,11 @@ void launch_build_E(const OpDev& op, int ncx, int ncy, int ncz, z64* E, hipStrea
 
 void launch_coarse_spmv(int ncx, int ncy, int ncz, const z64* E, int nrhs, const z64* x, z64* y,
                         hipStream_t s) {
+  if (nrhs >= NXT) {
+    hipLaunchKernelGGL(k_coarse_spmv_rows, dim3(row_tiles(ncx, ncy, ncz)), dim3(256), 0, s, ncx, ncy, ncz, E, nrhs, x,
+                       y);
+    return;
+  }
   const long long nc = (long long)ncx * ncy * ncz;
   hipLaunchKernelGGL(k_coarse_spmv2, dim3((unsigned)ceil_div(nc * nrhs, 256)), dim3(256), 0, s, ncx, ncy, ncz, E, nrhs,
                      x, y);
