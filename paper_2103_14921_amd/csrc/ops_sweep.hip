@@ -62,26 +62,54 @@ __host__ __device__ constexpr int lds_width(int rg) {
   return rg >= 16 ? rg + (sizeof(T) == 4 ? 4 : 0) : 16;
 }
 
-// First PF chunks of Sinv_k for the wave's first 16-row tile, issued before the
-// barrier that publishes the plane operand.
+// The chunks of Sinv_k a wave reads, in order: its tiles mt = wave, wave +
+// nwaves, ... (16 rows each), each cut into bp / 16 chunks of 16 columns.  The
+// stream runs across tile boundaries, so the loads of the next tile's first
+// chunks are in flight while the current tile finishes; past the end it
+// repeats the last chunk (a harmless, always valid address), so every load is
+// unconditional and the compiler can wait on exact counts.
+template <typename T>
+struct ChunkStream {
+  const cpx<T>* base;  // row (wave*16 + lane%16), column 4*(lane/16) of Sk
+  long long tile_step;  // elements between the wave's consecutive tiles
+  int nct, ntw, tile, chunk;
+  __device__ __forceinline__ ChunkStream(const cpx<T>* Sk, int bp, int wave, int nwaves, int lane) {
+    const int nmt = bp >> 4;
+    nct = nmt;
+    ntw = wave < nmt ? (nmt - wave + nwaves - 1) / nwaves : 0;
+    base = Sk + (long long)(min(wave, nmt - 1) * 16 + (lane & 15)) * bp + 4 * (lane >> 4);
+    tile_step = (long long)nwaves * 16 * bp;
+    tile = 0;
+    chunk = 0;
+  }
+  __device__ __forceinline__ void next(cpx<T> (&dst)[4]) {
+    const bool past = tile >= ntw;
+    const cpx<T>* p = base + (past ? (long long)(ntw > 0 ? ntw - 1 : 0) * tile_step + 16 * (nct - 1)
+                                   : (long long)tile * tile_step + 16 * chunk);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) dst[t] = p[t];
+    if (++chunk == nct) {
+      chunk = 0;
+      ++tile;
+    }
+  }
+};
+
+// Start a wave's chunk stream: the first PF chunks, issued before the barrier
+// that publishes the plane operand.
 template <typename T, int PF>
-__device__ __forceinline__ void prefetch_tile(const cpx<T>* __restrict__ Sk, int bp, int wave, int lane,
-                                              cpx<T> (&a)[PF][4]) {
-  const int nmt = bp >> 4;
-  if (wave >= nmt) return;
-  const cpx<T>* Arow = Sk + (long long)(wave * 16 + (lane & 15)) * bp + 4 * (lane >> 4);
+__device__ __forceinline__ ChunkStream<T> prefetch_tile(const cpx<T>* __restrict__ Sk, int bp, int wave, int nwaves,
+                                                        int lane, cpx<T> (&a)[PF][4]) {
+  ChunkStream<T> cs(Sk, bp, wave, nwaves, lane);
 #pragma unroll
-  for (int j = 0; j < PF; ++j)
-    if (16 * j < bp)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) a[j][t] = Arow[16 * j + t];
+  for (int j = 0; j < PF; ++j) cs.next(a[j]);
+  return cs;
 }
 
-// Rows of the wave's M-tiles of Sinv_k x T (T = plane operand in LDS), one
-// 16-row tile at a time, with PF chunks of Sinv in flight per wave (the first
-// tile's initial chunks arrive pre-loaded in a).  Lane l supplies A[l%16][l/16]
-// and B[l/16][l%16] of each 16x16x4 step; chunk j, step t covers column
-// 16 j + 4 (l/16) + t of Sinv_k.
+// Rows of the wave's M-tiles of Sinv_k x T (T = plane operand in LDS): the
+// wave walks its chunk stream with PF chunks in flight.  Lane l supplies
+// A[l%16][l/16] and B[l/16][l%16] of each 16x16x4 step; chunk c, step t covers
+// column 16 c + 4 (l/16) + t of Sinv_k.
 //
 // RG >= 16 (planar): each 16-column tile of complex right-hand sides keeps a
 // real and an imaginary accumulator,
@@ -91,74 +119,81 @@ __device__ __forceinline__ void prefetch_tile(const cpx<T>* __restrict__ Sk, int
 // with B1 = [Re T | Im T] and B2 = [-Im T | Re T],  C = Re S B1 + Im S B2.  The
 // operand pair (B1, B2) of each lane is stored ready in LDS, so no lane selects
 // or negates anything inside the loop.
-// out(p, r, value) receives each complex output entry (row p, column r).
-template <typename T, int RG, int PF, typename Out>
-__device__ __forceinline__ void plane_product(const cpx<T>* __restrict__ Sk, int bp, const cpx<T>* Bs, int wave,
-                                              int nwaves, int lane, cpx<T> (&a)[PF][4], Out&& out) {
+// Each tile's accumulators start from init(p, r); out(p, r, value) receives
+// each complex output entry (row p, column r).
+template <typename T, int RG, int PF, typename Init, typename Out>
+__device__ __forceinline__ void plane_product(ChunkStream<T>& cs, const cpx<T>* Bs, int wave, int nwaves, int lane,
+                                              cpx<T> (&a)[PF][4], Init&& init, Out&& out) {
   using V4 = typename Mfma<T>::v4;
   constexpr int W = lds_width<T>(RG);
   constexpr int NT = RG >= 16 ? RG / 16 : 1;  // 16-column MFMA tiles
   constexpr int NACC = RG >= 16 ? 2 : 1;
   const int lrow = lane & 15, lg = lane >> 4;
-  const int nmt = bp >> 4;
+  const int nct = cs.nct, total = cs.ntw * cs.nct;
   const cpx<T>* Bcol = Bs + 4 * lg * W + lrow;
-  for (int mt = wave; mt < nmt; mt += nwaves) {
-    V4 acc[NT][NACC];
+  V4 acc[NT][NACC];
+  int mt = wave, kc = 0;
+  for (int c0 = 0; c0 < total; c0 += PF) {
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
+    for (int j = 0; j < PF; ++j) {
+      if (c0 + j < total) {
+        if (kc == 0) {  // accumulators start from init(p, r) (zero, or y_k in the backward sweep)
+          if constexpr (RG >= 16) {
 #pragma unroll
-      for (int c = 0; c < NACC; ++c) acc[nt][c] = V4{0, 0, 0, 0};
-    const cpx<T>* Arow = Sk + (long long)(mt * 16 + lrow) * bp + 4 * lg;
-    if (mt != wave) {
+            for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-      for (int j = 0; j < PF; ++j)
-        if (16 * j < bp)
-#pragma unroll
-          for (int t = 0; t < 4; ++t) a[j][t] = Arow[16 * j + t];
-    }
-    for (int kc0 = 0; kc0 < bp; kc0 += 16 * PF) {
-#pragma unroll
-      for (int j = 0; j < PF; ++j) {
-        const int kc = kc0 + 16 * j;
-        if (kc < bp) {
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const T are = a[j][t].re, aim = a[j][t].im;
-            if constexpr (RG >= 16) {
-              const T naim = -aim;
-#pragma unroll
-              for (int nt = 0; nt < NT; ++nt) {
-                const cpx<T> tv = Bcol[(kc + t) * W + nt * 16];
-                acc[nt][0] = Mfma<T>::op(are, tv.re, acc[nt][0]);
-                acc[nt][1] = Mfma<T>::op(are, tv.im, acc[nt][1]);
-                acc[nt][0] = Mfma<T>::op(naim, tv.im, acc[nt][0]);
-                acc[nt][1] = Mfma<T>::op(aim, tv.re, acc[nt][1]);
+              for (int v = 0; v < 4; ++v) {
+                const cpx<T> y0 = init(mt * 16 + Mfma<T>::row(lg, v), nt * 16 + lrow);
+                acc[nt][0][v] = y0.re;
+                acc[nt][1][v] = y0.im;
               }
-            } else {
-              const cpx<T> tv = Bcol[(kc + t) * W];  // (B1, B2) of this lane
-              acc[0][0] = Mfma<T>::op(are, tv.re, acc[0][0]);
-              acc[0][0] = Mfma<T>::op(aim, tv.im, acc[0][0]);
+          } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const cpx<T> y0 = init(mt * 16 + Mfma<T>::row(lg, v), lrow & 7);
+              acc[0][0][v] = lrow < 8 ? y0.re : y0.im;
             }
           }
-          const int kn = kc + 16 * PF;
-          if (kn < bp)
+        }
 #pragma unroll
-            for (int t = 0; t < 4; ++t) a[j][t] = Arow[kn + t];
+        for (int t = 0; t < 4; ++t) {
+          const T are = a[j][t].re, aim = a[j][t].im;
+          if constexpr (RG >= 16) {
+            const T naim = -aim;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+              const cpx<T> tv = Bcol[(kc + t) * W + nt * 16];
+              acc[nt][0] = Mfma<T>::op(are, tv.re, acc[nt][0]);
+              acc[nt][1] = Mfma<T>::op(are, tv.im, acc[nt][1]);
+              acc[nt][0] = Mfma<T>::op(naim, tv.im, acc[nt][0]);
+              acc[nt][1] = Mfma<T>::op(aim, tv.re, acc[nt][1]);
+            }
+          } else {
+            const cpx<T> tv = Bcol[(kc + t) * W];  // (B1, B2) of this lane
+            acc[0][0] = Mfma<T>::op(are, tv.re, acc[0][0]);
+            acc[0][0] = Mfma<T>::op(aim, tv.im, acc[0][0]);
+          }
+        }
+        kc += 16;
+        if (kc == 16 * nct) {
+          if constexpr (RG >= 16) {
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                out(mt * 16 + Mfma<T>::row(lg, v), nt * 16 + lrow, mk<T>(acc[nt][0][v], acc[nt][1][v]));
+          } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const T im = __shfl_xor(acc[0][0][v], 8);  // column lrow + 8 holds Im of column lrow
+              if (lrow < 8) out(mt * 16 + Mfma<T>::row(lg, v), lrow, mk<T>(acc[0][0][v], im));
+            }
+          }
+          kc = 0;
+          mt += nwaves;
         }
       }
-    }
-    if constexpr (RG >= 16) {
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          out(mt * 16 + Mfma<T>::row(lg, v), nt * 16 + lrow, mk<T>(acc[nt][0][v], acc[nt][1][v]));
-    } else {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const T im = __shfl_xor(acc[0][0][v], 8);  // column lrow + 8 holds Im of column lrow
-        if (lrow < 8) out(mt * 16 + Mfma<T>::row(lg, v), lrow, mk<T>(acc[0][0][v], im));
-      }
+      cs.next(a[j]);  // chunk c0 + j + PF (unconditional)
     }
   }
 }
@@ -276,13 +311,15 @@ __global__ void __launch_bounds__(64 * fused_max_waves<T>()) k_oras_fused(const 
     const cpx<T>* Sk = sinv + sb.mat_off + (long long)k * bp * bp;
     build_plane(k, -1, true);
     cpx<T> a[PF][4];  // per plane, so nothing stays live across the operand build
-    prefetch_tile<T, PF>(Sk, bp, wave, lane, a);  // in flight across the barrier
+    ChunkStream<T> cs = prefetch_tile<T, PF>(Sk, bp, wave, nwaves, lane, a);  // in flight across the barrier
     __syncthreads();
     const bool last = k == ez - 1;
-    plane_product<T, RG, PF>(Sk, bp, Bs, wave, nwaves, lane, a, [&](int p, int r, cpx<T> val) {
-      if (r < nrg) yb[((long long)k * bp + p) * nrhs + r] = val;
-      if (last) scatter(k, p, r, val);  // x_{ez-1} = y_{ez-1}
-    });
+    plane_product<T, RG, PF>(
+        cs, Bs, wave, nwaves, lane, a, [](int, int) { return mk<T>(0, 0); },
+        [&](int p, int r, cpx<T> val) {
+          if (r < nrg) yb[((long long)k * bp + p) * nrhs + r] = val;
+          if (last) scatter(k, p, r, val);  // x_{ez-1} = y_{ez-1}
+        });
     wg_sync_global();
   }
   // ---- backward sweep: x_k = y_k - Sinv_k U_k x_{k+1}, x_k overwrites y_k
@@ -290,15 +327,18 @@ __global__ void __launch_bounds__(64 * fused_max_waves<T>()) k_oras_fused(const 
     const cpx<T>* Sk = sinv + sb.mat_off + (long long)k * bp * bp;
     build_plane(k, +1, false);
     cpx<T> a[PF][4];
-    prefetch_tile<T, PF>(Sk, bp, wave, lane, a);  // in flight across the barrier
+    ChunkStream<T> cs = prefetch_tile<T, PF>(Sk, bp, wave, nwaves, lane, a);  // in flight across the barrier
     __syncthreads();
-    plane_product<T, RG, PF>(Sk, bp, Bs, wave, nwaves, lane, a, [&](int p, int r, cpx<T> val) {
-      if (r >= nrg) return;
-      cpx<T>* yp = yb + ((long long)k * bp + p) * nrhs + r;
-      const cpx<T> x = *yp + val;  // the operand holds -U_k x_{k+1}
-      *yp = x;
-      scatter(k, p, r, x);
-    });
+    // x_k = y_k + Sinv_k T (the operand holds -U_k x_{k+1}): the accumulators
+    // start from y_k (column clamped into the group, always a valid address)
+    plane_product<T, RG, PF>(
+        cs, Bs, wave, nwaves, lane, a,
+        [&](int p, int r) { return yb[((long long)k * bp + p) * nrhs + min(r, nrg - 1)]; },
+        [&](int p, int r, cpx<T> x) {
+          if (r >= nrg) return;
+          yb[((long long)k * bp + p) * nrhs + r] = x;
+          scatter(k, p, r, x);
+        });
     wg_sync_global();
   }
 }
