@@ -153,6 +153,15 @@ helm_status helm_sweep_stats(const helm_handle_t* h, int32_t level, double out[4
 helm_status helm_set_graphs(helm_handle_t* h, int32_t enable);
 helm_status helm_graph_stats(const helm_handle_t* h, double out[2]);
 
+/* Process-wide choice among the implementations of the batched local solves
+ * (the one-level ORAS sweep of eq. oras): 0 (default) times the admissible
+ * variants once per problem shape and keeps the fastest; 1 restricts to the
+ * one-workgroup-per-box sweep; 2 uses the pipelined persistent sweep (two
+ * boxes per compute unit, operand build overlapped with the matrix-core
+ * product) wherever its two operand slots fit in LDS.  Results agree to
+ * rounding.  Graphs captured under one policy are not replayed under another. */
+helm_status helm_set_sweep_policy(int32_t policy);
+
 /* Return the handle's cached Krylov workspace (sized for its last batch) to
  * the library's device cache, keeping operators and factors resident: lets a
  * server hold many set-up problems and pay workspace only while solving. */

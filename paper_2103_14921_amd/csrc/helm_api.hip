@@ -298,7 +298,7 @@ struct Workspace {
 // workspace generation.  With sweep timing on, the sweeps are bracketed by
 // external event nodes whose times are harvested at the next host sync.
 struct Captured {
-  int j = 0, nr = 0, maxit = 0;
+  int j = 0, nr = 0, maxit = 0, policy = 0;
   double tol = 0;
   unsigned gen = 0;
   bool timed = false;
@@ -772,7 +772,8 @@ void run_outer_step(helm_handle* H, int nr, int j, double tol, int maxit) {
   }
   Captured* c = nullptr;
   for (auto& e : H->captured)
-    if (e->j == j && e->nr == nr && e->maxit == maxit && e->tol == tol && e->gen == H->ws_gen && e->timed == H->timing) {
+    if (e->j == j && e->nr == nr && e->maxit == maxit && e->tol == tol && e->gen == H->ws_gen &&
+        e->timed == H->timing && e->policy == sweep_policy()) {
       c = e.get();
       break;
     }
@@ -784,6 +785,7 @@ void run_outer_step(helm_handle* H, int nr, int j, double tol, int maxit) {
     e->tol = tol;
     e->gen = H->ws_gen;
     e->timed = H->timing;
+    e->policy = sweep_policy();
     const hipError_t be = hipStreamBeginCapture(H->stream, hipStreamCaptureModeRelaxed);
     if (be != hipSuccess) {
       (void)hipGetLastError();
@@ -1220,6 +1222,12 @@ helm_status helm_set_graphs(helm_handle_t* H, int32_t enable) {
     H->graphs = enable != 0;
     return HELM_OK;
   });
+}
+
+helm_status helm_set_sweep_policy(int32_t policy) {
+  if (policy < 0 || policy > 2) return fail(HELM_EINVAL, "sweep policy must be 0, 1 or 2");
+  set_sweep_policy(policy);
+  return HELM_OK;
 }
 
 helm_status helm_graph_stats(const helm_handle_t* H, double out[2]) {

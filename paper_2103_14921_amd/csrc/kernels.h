@@ -62,6 +62,10 @@ template <typename T>
 int fused_group(int bpmax, int nrhs);
 // right-hand-side group the autotuner chose for this shape (0 = not tuned yet)
 int tuned_group(int es, int bpmax, int nsub, int nrhs, int gnx, int gny);
+// process-wide sweep policy: 0 autotune over all variants, 1 one-item sweeps,
+// 2 the pipelined persistent sweep wherever it fits
+void set_sweep_policy(int policy);
+int sweep_policy();
 
 // ---- Krylov (ops_krylov.hip) -----------------------------------------------
 // blocks of the two-stage reductions (sizes of the partial-sum buffers)

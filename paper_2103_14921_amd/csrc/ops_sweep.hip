@@ -14,6 +14,7 @@
 // real 16x16x4 steps as described at plane_product (no complex arithmetic and
 // no lane-dependent operand selection inside the MFMA loop).
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -73,6 +74,7 @@ struct ChunkStream {
   const cpx<T>* base;  // row (wave*16 + lane%16), column 4*(lane/16) of Sk
   long long tile_step;  // elements between the wave's consecutive tiles
   int nct, ntw, tile, chunk;
+  ChunkStream() = default;
   __device__ __forceinline__ ChunkStream(const cpx<T>* Sk, int bp, int wave, int nwaves, int lane) {
     const int nmt = bp >> 4;
     nct = nmt;
@@ -121,11 +123,13 @@ __device__ __forceinline__ ChunkStream<T> prefetch_tile(const cpx<T>* __restrict
 // or negates anything inside the loop.
 // Each tile's accumulators start from init(p, r); out(p, r, value) receives
 // each complex output entry (row p, column r).
-template <typename T, int RG, int PF, typename Init, typename Out>
+// WS is the row stride of the operand in LDS (a wider operand's column block
+// can be multiplied on its own).
+template <typename T, int RG, int PF, int WS = lds_width<T>(RG), typename Init, typename Out>
 __device__ __forceinline__ void plane_product(ChunkStream<T>& cs, const cpx<T>* Bs, int wave, int nwaves, int lane,
                                               cpx<T> (&a)[PF][4], Init&& init, Out&& out) {
   using V4 = typename Mfma<T>::v4;
-  constexpr int W = lds_width<T>(RG);
+  constexpr int W = WS;
   constexpr int NT = RG >= 16 ? RG / 16 : 1;  // 16-column MFMA tiles
   constexpr int NACC = RG >= 16 ? 2 : 1;
   const int lrow = lane & 15, lg = lane >> 4;
@@ -220,40 +224,47 @@ constexpr int fused_max_waves() {
   return sizeof(T) == 8 ? 12 : 16;
 }
 
-template <typename T, int RG, int PF>
-__global__ void __launch_bounds__(64 * fused_max_waves<T>()) k_oras_fused(const Sub* __restrict__ subs, int ngroups, int nrhs,
-                                                   const cpx<T>* __restrict__ cpl, const cpx<T>* __restrict__ sinv,
-                                                   const z64* __restrict__ u, z64* __restrict__ z,
-                                                   const z64* __restrict__ add, int gnx, int gny,
-                                                   cpx<T>* __restrict__ yloc) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cpx<T>* Bs = reinterpret_cast<cpx<T>*>(smem_raw);
-  const int s = blockIdx.x / ngroups, g = blockIdx.x % ngroups;
-  const Sub sb = subs[s];
-  const int r0 = g * RG;
-  const int nrg = min(RG, nrhs - r0);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int FT = blockDim.x, nwaves = FT >> 6;
-  const int bp = sb.bp, b = sb.b, ex = sb.ex, ey = sb.ey, ez = sb.ez;
-  const int cx0 = sb.lo[0] - sb.elo[0], cx1 = sb.hi[0] - sb.elo[0];
-  const int cy0 = sb.lo[1] - sb.elo[1], cy1 = sb.hi[1] - sb.elo[1];
-  const int cz0 = sb.lo[2] - sb.elo[2], cz1 = sb.hi[2] - sb.elo[2];
-  cpx<T>* yb = yloc + sb.vec_off * (long long)nrhs + r0;  // plane k, row p, column r at (k*bp + p)*nrhs + r
+// One (box, right-hand-side group) item of the batched local solves: plane
+// vectors in yloc (plane k, row p, column r at (k*bp + p)*nrhs + r0 + r),
+// plane couplings in the factor precision, and the box's place in the grid.
+template <typename T, int RG>
+struct BoxCtx {
+  Sub sb;
+  int r0, nrg, nrhs, gnx, gny;
+  cpx<T>* yb;
+  const cpx<T>* cbox;
+  const z64* u;
+  z64* z;
+  const z64* add;
 
-  auto gnode = [&](int k, int p) -> long long {
-    const int px = p % ex, py = p / ex;
+  __device__ __forceinline__ BoxCtx(const Sub* subs, int item, int ngroups, int nrhs_, const cpx<T>* cpl,
+                                    const z64* u_, z64* z_, const z64* add_, int gnx_, int gny_, cpx<T>* yloc) {
+    sb = subs[item / ngroups];
+    r0 = (item % ngroups) * RG;
+    nrhs = nrhs_;
+    nrg = min(RG, nrhs - r0);
+    gnx = gnx_;
+    gny = gny_;
+    yb = yloc + sb.vec_off * (long long)nrhs + r0;
+    cbox = cpl + sb.node_off * 18;
+    u = u_;
+    z = z_;
+    add = add_;
+  }
+  __device__ __forceinline__ long long gnode(int k, int p) const {
+    const int px = p % sb.ex, py = p / sb.ex;
     return (sb.elo[0] + px) + (long long)gnx * ((sb.elo[1] + py) + (long long)gny * (sb.elo[2] + k));
-  };
+  }
   // Operand build: each thread handles NE columns r, r + LP, ... of one node p
   // (LP = RG / NE lanes per node), so the nine coupling coefficients are loaded
   // once for NE entries.  All loads of an entry group are issued before any is
   // used: indices are clamped into the box (and columns into the batch) and
-  // the coefficients of clamped taps are zero.  Bases are wave-uniform and
-  // offsets 32-bit (plane vectors of a box stay far below 2^31 elements).
-  constexpr int NE = sizeof(T) == 8 ? 1 : 2, LP = RG / NE;
-  const cpx<T>* __restrict__ cbox = cpl + sb.node_off * 18;
-  // v[j] = (u_k - L_k y_{k-1}) (dz = -1, with_u) or U_k x_{k+1} (dz = +1) at (p, r + j LP)
-  auto build = [&](int k, int p, int r, int dz, bool with_u, cpx<T> (&v)[NE]) {
+  // the coefficients of clamped taps are zero.  Offsets from the wave-uniform
+  // bases are 32-bit (plane vectors of a box stay far below 2^31 elements).
+  static constexpr int NE = sizeof(T) == 8 ? 1 : 2, LP = RG / NE;
+  // v[j] = (u_k - L_k y_{k-1}) (dz = -1, with_u) or -U_k x_{k+1} (dz = +1) at (p, r + j LP)
+  __device__ __forceinline__ void build(int k, int p, int r, int dz, bool with_u, cpx<T> (&v)[NE]) const {
+    const int b = sb.b, ex = sb.ex, ey = sb.ey, bp = sb.bp;
 #pragma unroll
     for (int j = 0; j < NE; ++j) v[j] = mk<T>(0, 0);
     if (p >= b) return;
@@ -265,7 +276,7 @@ __global__ void __launch_bounds__(64 * fused_max_waves<T>()) k_oras_fused(const 
 #pragma unroll
       for (int j = 0; j < NE; ++j) v[j] = ccast<T>(u[gu + col[j]]);
     }
-    if (k + dz < 0 || k + dz >= ez) return;
+    if (k + dz < 0 || k + dz >= sb.ez) return;
     const int px = p % ex, py = p / ex;
     const int ro = (k * b + p) * 18 + (dz + 1) / 2 * 9;
     const int yo = (k + dz) * bp * nrhs;
@@ -284,64 +295,146 @@ __global__ void __launch_bounds__(64 * fused_max_waves<T>()) k_oras_fused(const 
     for (int i = 0; i < 9; ++i)
 #pragma unroll
       for (int j = 0; j < NE; ++j) cfms(v[j], cv[i], yv[i][j]);
-  };
-  auto build_plane = [&](int k, int dz, bool with_u) {
+  }
+  // operand of plane k into Bs, threads t0, t0 + nt, ... of the workgroup
+  __device__ __forceinline__ void build_plane(int k, int dz, bool with_u, cpx<T>* Bs, int t0, int nt) const {
 #pragma unroll 1
-    for (int e = tid; e < bp * LP; e += FT) {
+    for (int e = t0; e < sb.bp * LP; e += nt) {
       const int p = e / LP, r = e % LP;
       cpx<T> v[NE];
       build(k, p, r, dz, with_u, v);
 #pragma unroll
       for (int j = 0; j < NE; ++j) put_operand<T, RG>(Bs, p, r + j * LP, r + j * LP < nrg ? v[j] : mk<T>(0, 0));
     }
-  };
+  }
   // core node (k, p) of the box: z = x (+ add)
-  auto scatter = [&](int k, int p, int r, cpx<T> val) {
-    if (k < cz0 || k >= cz1 || p >= b || r >= nrg) return;
-    const int px = p % ex, py = p / ex;
-    if (px < cx0 || px >= cx1 || py < cy0 || py >= cy1) return;
+  __device__ __forceinline__ void scatter(int k, int p, int r, cpx<T> val) const {
+    if (k < sb.lo[2] - sb.elo[2] || k >= sb.hi[2] - sb.elo[2] || p >= sb.b || r >= nrg) return;
+    const int px = p % sb.ex, py = p / sb.ex;
+    if (px < sb.lo[0] - sb.elo[0] || px >= sb.hi[0] - sb.elo[0] || py < sb.lo[1] - sb.elo[1] ||
+        py >= sb.hi[1] - sb.elo[1])
+      return;
     const long long gi = gnode(k, p) * nrhs + r0 + r;
     z64 o = ccast<double>(val);
     if (add) o += add[gi];
     z[gi] = o;
-  };
-
-  // ---- forward sweep: y_k = Sinv_k (R_i u - L_k y_{k-1})
-  for (int k = 0; k < ez; ++k) {
-    const cpx<T>* Sk = sinv + sb.mat_off + (long long)k * bp * bp;
-    build_plane(k, -1, true);
-    cpx<T> a[PF][4];  // per plane, so nothing stays live across the operand build
-    ChunkStream<T> cs = prefetch_tile<T, PF>(Sk, bp, wave, nwaves, lane, a);  // in flight across the barrier
-    __syncthreads();
-    const bool last = k == ez - 1;
-    plane_product<T, RG, PF>(
-        cs, Bs, wave, nwaves, lane, a, [](int, int) { return mk<T>(0, 0); },
-        [&](int p, int r, cpx<T> val) {
-          if (r < nrg) yb[((long long)k * bp + p) * nrhs + r] = val;
-          if (last) scatter(k, p, r, val);  // x_{ez-1} = y_{ez-1}
-        });
-    wg_sync_global();
   }
-  // ---- backward sweep: x_k = y_k - Sinv_k U_k x_{k+1}, x_k overwrites y_k
-  for (int k = ez - 2; k >= 0; --k) {
-    const cpx<T>* Sk = sinv + sb.mat_off + (long long)k * bp * bp;
-    build_plane(k, +1, false);
-    cpx<T> a[PF][4];
-    ChunkStream<T> cs = prefetch_tile<T, PF>(Sk, bp, wave, nwaves, lane, a);  // in flight across the barrier
+  // Step s of the block-tridiagonal solve: s < ez is forward plane k = s,
+  // then backward planes k = ez - 2, ..., 0.
+  __device__ __forceinline__ int nsteps() const { return 2 * sb.ez - 1; }
+  __device__ __forceinline__ int plane_of(int s) const { return s < sb.ez ? s : 2 * sb.ez - 2 - s; }
+  __device__ __forceinline__ void build_step(int s, cpx<T>* Bs, int t0, int nt) const {
+    if (s < sb.ez) build_plane(s, -1, true, Bs, t0, nt);
+    else build_plane(plane_of(s), +1, false, Bs, t0, nt);
+  }
+  __device__ __forceinline__ const cpx<T>* factor(const cpx<T>* sinv, int s) const {
+    return sinv + sb.mat_off + (long long)plane_of(s) * sb.bp * sb.bp;
+  }
+  // accumulator start: zero forward, y_k backward (x_k = y_k + Sinv_k T with
+  // the operand holding -U_k x_{k+1}; column clamped into the group)
+  __device__ __forceinline__ cpx<T> init(int s, int p, int r) const {
+    if (s < sb.ez) return mk<T>(0, 0);
+    return yb[((long long)plane_of(s) * sb.bp + p) * nrhs + min(r, nrg - 1)];
+  }
+  // product output: forward y_k (and x = y on the last plane), backward x_k
+  __device__ __forceinline__ void output(int s, int p, int r, cpx<T> val) const {
+    if (r >= nrg) return;
+    const int k = plane_of(s);
+    yb[((long long)k * sb.bp + p) * nrhs + r] = val;
+    if (s >= sb.ez - 1) scatter(k, p, r, val);
+  }
+};
+
+// LDS holds only the right operand T of the plane product; the plane solutions
+// y_k / x_k live in yloc and reach the other waves of the workgroup through L2
+// (workgroup-scope release/acquire around the barrier).  One workgroup per
+// item, all its waves building and then multiplying each plane in turn.
+template <typename T, int RG, int PF>
+__global__ void __launch_bounds__(64 * fused_max_waves<T>()) k_oras_fused(const Sub* __restrict__ subs, int ngroups, int nrhs,
+                                                   const cpx<T>* __restrict__ cpl, const cpx<T>* __restrict__ sinv,
+                                                   const z64* __restrict__ u, z64* __restrict__ z,
+                                                   const z64* __restrict__ add, int gnx, int gny,
+                                                   cpx<T>* __restrict__ yloc) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* Bs = reinterpret_cast<cpx<T>*>(smem_raw);
+  const BoxCtx<T, RG> bx(subs, blockIdx.x, ngroups, nrhs, cpl, u, z, add, gnx, gny, yloc);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int FT = blockDim.x, nwaves = FT >> 6;
+  const int bp = bx.sb.bp, ns = bx.nsteps();
+  for (int st = 0; st < ns; ++st) {
+    bx.build_step(st, Bs, tid, FT);
+    cpx<T> a[PF][4];  // per plane, so nothing stays live across the operand build
+    ChunkStream<T> cs = prefetch_tile<T, PF>(bx.factor(sinv, st), bp, wave, nwaves, lane, a);  // across the barrier
     __syncthreads();
-    // x_k = y_k + Sinv_k T (the operand holds -U_k x_{k+1}): the accumulators
-    // start from y_k (column clamped into the group, always a valid address)
     plane_product<T, RG, PF>(
-        cs, Bs, wave, nwaves, lane, a,
-        [&](int p, int r) { return yb[((long long)k * bp + p) * nrhs + min(r, nrg - 1)]; },
-        [&](int p, int r, cpx<T> x) {
-          if (r >= nrg) return;
-          yb[((long long)k * bp + p) * nrhs + r] = x;
-          scatter(k, p, r, x);
-        });
+        cs, Bs, wave, nwaves, lane, a, [&](int p, int r) { return bx.init(st, p, r); },
+        [&](int p, int r, cpx<T> val) { bx.output(st, p, r, val); });
     wg_sync_global();
   }
 }
+
+// Persistent pipelined variant: one workgroup per compute unit works through
+// the items blockIdx.x, blockIdx.x + gridDim.x, ... with two items in flight
+// (two operand slots in LDS).  In every phase the eight consumer waves (two per
+// SIMD) form the plane product of one item while the producer waves build the
+// next plane operand of the other, so the latency-bound build hides behind the
+// matrix-core work; a barrier ends each phase.  Consumer wave cw owns the
+// 16-column half nh = cw % NH (NH = RG / 16) of the tiles mt = cw / NH,
+// cw / NH + 8 / NH, ..., which spreads the 16 x 16 output blocks evenly over
+// the SIMDs.
+constexpr int PIPE_CONSUMERS = 8;
+
+template <typename T, int RG, int PF>
+__global__ void __launch_bounds__(64 * 12) k_oras_pipe(const Sub* __restrict__ subs, int nitems, int ngroups,
+                                                       int nrhs, int bpmax, const cpx<T>* __restrict__ cpl,
+                                                       const cpx<T>* __restrict__ sinv, const z64* __restrict__ u,
+                                                       z64* __restrict__ z, const z64* __restrict__ add, int gnx,
+                                                       int gny, cpx<T>* __restrict__ yloc) {
+  static_assert(RG >= 16, "the pipelined sweep uses the planar operand layout");
+  constexpr int NH = RG / 16, W = lds_width<T>(RG);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* slots[2] = {reinterpret_cast<cpx<T>*>(smem_raw), reinterpret_cast<cpx<T>*>(smem_raw) + (long long)bpmax * W};
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool consumer = wave < PIPE_CONSUMERS;
+  const int ptid = tid - 64 * PIPE_CONSUMERS, pthreads = blockDim.x - 64 * PIPE_CONSUMERS;
+  const int cw = wave, nh = cw % NH;
+  int item[2] = {-1, -1}, step[2] = {0, 0};
+  int next = blockIdx.x;
+  cpx<T> a[PF][4];
+  ChunkStream<T> cs;
+  for (int ph = 0;; ++ph) {
+    const int B = ph & 1, P = B ^ 1;
+    if (item[B] < 0 && next < nitems) {
+      item[B] = next;
+      step[B] = 0;
+      next += gridDim.x;
+    }
+    if (item[B] < 0 && item[P] < 0) break;  // uniform: every thread tracks the same state
+    if (consumer) {
+      if (item[P] >= 0) {
+        const BoxCtx<T, RG> bx(subs, item[P], ngroups, nrhs, cpl, u, z, add, gnx, gny, yloc);
+        const int st = step[P];
+        const cpx<T>* Bcol = slots[P] + nh * 16;
+        plane_product<T, 16, PF, W>(
+            cs, Bcol, cw / NH, PIPE_CONSUMERS / NH, lane, a, [&](int p, int r) { return bx.init(st, p, nh * 16 + r); },
+            [&](int p, int r, cpx<T> val) { bx.output(st, p, nh * 16 + r, val); });
+      }
+      if (item[B] >= 0) {  // the next product: slot B's plane being built now
+        const BoxCtx<T, RG> bx(subs, item[B], ngroups, nrhs, cpl, u, z, add, gnx, gny, yloc);
+        cs = prefetch_tile<T, PF>(bx.factor(sinv, step[B]), bx.sb.bp, cw / NH, PIPE_CONSUMERS / NH, lane, a);
+      }
+    } else if (item[B] >= 0) {
+      const BoxCtx<T, RG> bx(subs, item[B], ngroups, nrhs, cpl, u, z, add, gnx, gny, yloc);
+      bx.build_step(step[B], slots[B], ptid, pthreads);
+    }
+    wg_sync_global();
+    if (item[P] >= 0) {
+      const int ns = 2 * subs[item[P] / ngroups].ez - 1;
+      if (++step[P] == ns) item[P] = -1;
+    }
+  }
+}
+
 // Rounds of 16-row tiles per wave: at least enough for the wave limit; more
 // rounds mean fewer waves per workgroup, so that two workgroups (two boxes) can
 // share a compute unit and overlap one's operand build with the other's product.
@@ -371,6 +464,42 @@ void launch_fused_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax,
                      sinv, u, z, add, gnx, gny, yloc);
 }
 
+// Two operand slots of the pipelined sweep must fit one compute unit's LDS.
+template <typename T>
+bool pipe_fits(int rg, int bpmax) {
+  return rg >= 16 && 2 * (size_t)bpmax * lds_width<T>(rg) * sizeof(cpx<T>) <= 160 * 1024;
+}
+
+int compute_units() {
+  static int per_device[64] = {0};
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (dev < 0 || dev >= 64) dev = 0;
+  if (per_device[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    per_device[dev] = n;
+  }
+  return per_device[dev];
+}
+
+template <typename T, int RG>
+void launch_pipe_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, const cpx<T>* cpl, const cpx<T>* sinv,
+                   const z64* u, z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc, hipStream_t s) {
+  constexpr int PF = sizeof(T) == 4 ? 4 : 2;
+  const size_t lds = 2 * (size_t)bpmax * lds_width<T>(RG) * sizeof(cpx<T>);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_oras_pipe<T, RG, PF>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr = true;
+  }
+  const int nitems = nsub * ngroups;
+  const int grid = std::min(nitems, compute_units());
+  hipLaunchKernelGGL((k_oras_pipe<T, RG, PF>), dim3(grid), dim3(64 * 12), lds, s, subs, nitems, ngroups, nrhs, bpmax,
+                     cpl, sinv, u, z, add, gnx, gny, yloc);
+}
+
 }  // namespace
 
 // LDS budget of the fused kernel (one plane operand)
@@ -390,6 +519,13 @@ void launch_rg(int rg, int rounds, const Sub* subs, int nsub, int nrhs, int bpma
                const cpx<T>* sinv, const z64* u, z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc,
                hipStream_t s) {
   const int ngroups = (nrhs + rg - 1) / rg;
+  if (rounds == 0) {  // pipelined persistent sweep
+    if (rg == 16)
+      launch_pipe_t<T, 16>(subs, nsub, ngroups, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, s);
+    else
+      launch_pipe_t<T, 32>(subs, nsub, ngroups, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, s);
+    return;
+  }
   switch (rg) {
     case 8:
       launch_fused_t<T, 8>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx, gny, yloc, s);
@@ -406,11 +542,13 @@ void launch_rg(int rg, int rounds, const Sub* subs, int nsub, int nrhs, int bpma
 // Autotuned launch shape of the fused sweep (right-hand-side group, tile
 // rounds per wave), per problem shape.
 struct TuneKey {
-  int es, bpmax, nsub, nrhs, gnx, gny;
+  int es, bpmax, nsub, nrhs, gnx, gny, policy;
   bool operator<(const TuneKey& o) const {
-    return std::tie(es, bpmax, nsub, nrhs, gnx, gny) < std::tie(o.es, o.bpmax, o.nsub, o.nrhs, o.gnx, o.gny);
+    return std::tie(es, bpmax, nsub, nrhs, gnx, gny, policy) <
+           std::tie(o.es, o.bpmax, o.nsub, o.nrhs, o.gnx, o.gny, o.policy);
   }
 };
+std::atomic<int> g_sweep_policy{0};
 struct TuneVal {
   int rg, rounds;
 };
@@ -419,9 +557,12 @@ std::map<TuneKey, TuneVal> g_tune;
 
 }  // namespace
 
+void set_sweep_policy(int policy) { g_sweep_policy.store(policy); }
+int sweep_policy() { return g_sweep_policy.load(); }
+
 int tuned_group(int es, int bpmax, int nsub, int nrhs, int gnx, int gny) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto it = g_tune.find({es, bpmax, nsub, nrhs, gnx, gny});
+  auto it = g_tune.find({es, bpmax, nsub, nrhs, gnx, gny, g_sweep_policy.load()});
   return it == g_tune.end() ? 0 : it->second.rg;
 }
 
@@ -430,7 +571,12 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
                 z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc, hipStream_t s) {
   const int rgmax = fused_group<T>(bpmax, nrhs);
   if (rgmax == 0) return false;
-  const TuneKey key{(int)sizeof(T), bpmax, nsub, nrhs, gnx, gny};
+  const int policy = g_sweep_policy.load();
+  const TuneKey key{(int)sizeof(T), bpmax, nsub, nrhs, gnx, gny, policy};
+  // policy 1: one-item sweeps only; 2: the pipelined sweep wherever it fits
+  bool any_pipe = false;
+  for (int cand = 8; cand <= rgmax; cand *= 2) any_pipe = any_pipe || pipe_fits<T>(cand, bpmax);
+  const bool allow_pipe = policy != 1, allow_item = policy != 2 || !any_pipe;
   TuneVal tv{0, 0};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -449,10 +595,15 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     float best = 1e30f;
+    static const bool verbose = std::getenv("HELM_TUNE_VERBOSE") != nullptr;
     for (int cand = 8; cand <= rgmax; cand *= 2) {
       int last_waves = 0;
-      for (int rounds = r0; rounds <= r0 + 2; ++rounds) {
-        const int waves = (nmt + rounds - 1) / rounds;
+      // rounds 0 = the pipelined persistent sweep, then the one-item sweep with
+      // r0, r0 + 1, r0 + 2 tile rounds per wave
+      for (int rounds = 0; rounds <= r0 + 2; rounds = rounds == 0 ? r0 : rounds + 1) {
+        if (rounds == 0 && (!allow_pipe || !pipe_fits<T>(cand, bpmax))) continue;
+        if (rounds != 0 && !allow_item) continue;
+        const int waves = rounds == 0 ? -1 : (nmt + rounds - 1) / rounds;
         if (waves == last_waves) continue;
         last_waves = waves;
         float tot = 0.f;
@@ -465,6 +616,9 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
           (void)hipEventElapsedTime(&ms, e0, e1);
           if (rep > 0) tot += ms;
         }
+        if (verbose)
+          std::fprintf(stderr, "helm:   candidate group %d %s %d waves: %.3f ms\n", cand,
+                       rounds == 0 ? "pipelined," : "", rounds == 0 ? 12 : waves, tot);
         if (tot < best) {
           best = tot;
           tv = {cand, rounds};
@@ -473,14 +627,23 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    static const bool verbose = std::getenv("HELM_TUNE_VERBOSE") != nullptr;
     if (verbose)
-      std::fprintf(stderr, "helm: sweep tuned (fp%d, bp %d, %d boxes, %d rhs): group %d, %d waves, %.3f ms\n",
-                   (int)sizeof(T) * 8, bpmax, nsub, nrhs, tv.rg, (nmt + tv.rounds - 1) / tv.rounds, best);
+      std::fprintf(stderr, "helm: sweep tuned (fp%d, bp %d, %d boxes, %d rhs): group %d, %s %d waves, %.3f ms\n",
+                   (int)sizeof(T) * 8, bpmax, nsub, nrhs, tv.rg, tv.rounds == 0 ? "pipelined," : "",
+                   tv.rounds == 0 ? 12 : (nmt + tv.rounds - 1) / tv.rounds, best);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = tv;
   }
-  if (tv.rg == 0) tv = {rgmax, r0};
+  if (tv.rg == 0) {  // untuned (tuning off, or inside a capture): the widest group
+    tv = {rgmax, r0};
+    if (!allow_item) {
+      for (int cand = rgmax; cand >= 16; cand /= 2)
+        if (pipe_fits<T>(cand, bpmax)) {
+          tv = {cand, 0};
+          break;
+        }
+    }
+  }
   launch_rg<T>(tv.rg, tv.rounds, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, s);
   return true;
 }

@@ -26,6 +26,7 @@ EXPORTS = [
     "helm_apply_M", "helm_apply_oras", "helm_restrict", "helm_prolong", "helm_apply_E", "helm_apply_Q",
     "helm_num_subdomains", "helm_subdomain_box", "helm_set_sweep_timing", "helm_sweep_stats",
     "helm_local_solve", "helm_release_workspace", "helm_trim_cache", "helm_set_graphs", "helm_graph_stats",
+    "helm_set_sweep_policy",
 ]
 
 
@@ -98,6 +99,7 @@ def _load():
         "helm_trim_cache": ([], C.c_size_t),
         "helm_set_graphs": ([P, i32], C.c_int),
         "helm_graph_stats": ([P, C.POINTER(C.c_double)], C.c_int),
+        "helm_set_sweep_policy": ([i32], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -162,6 +164,14 @@ def _empty_like_kind(a, shape):
         import torch
         return torch_alloc(lambda: torch.empty(shape, dtype=torch.complex128, device=a.device))
     return np.empty(shape, dtype=np.complex128)
+
+
+SWEEP_POLICIES = {"auto": 0, "item": 1, "pipelined": 2}
+
+
+def set_sweep_policy(policy):
+    """Process-wide choice of local-solve sweep: "auto" (tuned), "item" or "pipelined"."""
+    _check(lib.helm_set_sweep_policy(SWEEP_POLICIES[policy]))
 
 
 def footprint(shape, parts, overlap=2, levels=1, coarse_iters=10, precision="fp64", restart=30, nrhs_chunk=1):

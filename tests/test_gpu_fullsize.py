@@ -80,8 +80,15 @@ def _check_solve(prob, Xd, info, B, tol, rng, which):
 
 
 def _run(shape, parts, src, precision, tol, restart, q, local_tol, local_which, rhs_which):
+    import gc
+
     import torch
     from paper_2103_14921_amd import helm
+    # the previous cases' buffers may still sit in PyTorch's and the library's
+    # device caches: hand them back before sizing this problem
+    gc.collect()
+    torch.cuda.empty_cache()
+    helm.trim_cache()
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(7)
     nx, ny, nz = shape
@@ -101,6 +108,9 @@ def _run(shape, parts, src, precision, tol, restart, q, local_tol, local_which, 
     say("solve", f"{time.time() - t0:.1f} s", "iters", info["iters"].min(), info["iters"].max())
     _check_solve(prob, Xd, info, B, tol, rng, rhs_which)
     S.close()
+    del Xd, Bd
+    torch.cuda.empty_cache()
+    helm.trim_cache()
 
 
 def test_thrust128_fp64_two_level_full_size():
