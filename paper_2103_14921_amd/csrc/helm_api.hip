@@ -236,7 +236,7 @@ size_t level_resident_bytes(const Level& L) {
 // Temporary set-up bytes of a level (local operator rows, Schur blocks, pivots).
 size_t level_setup_bytes(const Level& L) {
   return (size_t)L.nodes_total * 27 * sizeof(z64) + (size_t)L.nsub * L.bpmax * L.bpmax * elem_size(L.prec) * 2 +
-         (size_t)L.nsub * 16 * L.bpmax * elem_size(L.prec) + (size_t)L.nsub * L.bpmax * sizeof(int) * 2 + 64;
+         (size_t)L.nsub * (16 + 64) * L.bpmax * elem_size(L.prec) + (size_t)L.nsub * L.bpmax * sizeof(int) * 2 + 64;
 }
 size_t level_ws_bytes(const Level& L, int nr) {
   return ((size_t)L.vec_total * nr + (size_t)L.nsub * L.bpmax * nr) * elem_size(L.prec);
@@ -909,21 +909,24 @@ void extract_couplings(helm_handle* H, Level& L) {
 }
 
 void factor_level(helm_handle* H, Level& L) {
-  DevBuf Wt, St, Rb, piv, perm;
+  DevBuf Wt, St, Rb, R64, piv, perm;
   const size_t es = elem_size(L.prec);
   Wt.alloc((size_t)L.nsub * L.bpmax * L.bpmax * es);
   St.alloc((size_t)L.nsub * L.bpmax * L.bpmax * es);
   Rb.alloc((size_t)L.nsub * 16 * L.bpmax * es);
+  R64.alloc((size_t)L.nsub * 64 * L.bpmax * es);
   piv.alloc((size_t)L.nsub * L.bpmax * sizeof(int));
   perm.alloc((size_t)L.nsub * L.bpmax * sizeof(int));
   launch_fill(H->err.as<z64>(), 1, H->stream);
   for (int k = 0; k < L.maxez; ++k) {
     if (L.prec == 1)
       Factor<float>::plane(L.d_subs.as<Sub>(), L.nsub, L.bpmax, k, L.aloc.as<z64>(), L.sinv.as<c32>(), Wt.as<c32>(),
-                           St.as<c32>(), Rb.as<c32>(), piv.as<int>(), perm.as<int>(), H->err.as<int>(), H->stream);
+                           St.as<c32>(), Rb.as<c32>(), R64.as<c32>(), piv.as<int>(), perm.as<int>(), H->err.as<int>(),
+                           H->stream);
     else
       Factor<double>::plane(L.d_subs.as<Sub>(), L.nsub, L.bpmax, k, L.aloc.as<z64>(), L.sinv.as<z64>(), Wt.as<z64>(),
-                            St.as<z64>(), Rb.as<z64>(), piv.as<int>(), perm.as<int>(), H->err.as<int>(), H->stream);
+                            St.as<z64>(), Rb.as<z64>(), R64.as<z64>(), piv.as<int>(), perm.as<int>(),
+                            H->err.as<int>(), H->stream);
   }
   int e = 0;
   HELM_CHECK_HIP(hipMemcpyAsync(&e, H->err.p, sizeof(int), hipMemcpyDeviceToHost, H->stream));

@@ -43,8 +43,9 @@ void launch_couplings(long long nodes, const z64* aloc, cpx<T>* cpl, hipStream_t
 template <typename T>
 struct Factor {
   // one plane step of the block-tridiagonal LU: S_k = D_k - L_k Sinv_{k-1} U_{k-1}, Sinv_k = S_k^{-1}
+  // Rbuf: [nsub][16][bpmax] panel pivot rows; R64: [nsub][64][bpmax] block pivot rows
   static void plane(const Sub* subs, int nsub, int bpmax, int k, const z64* aloc, cpx<T>* sinv,
-                    cpx<T>* W, cpx<T>* S, cpx<T>* Rbuf, int* piv, int* perm, int* err,
+                    cpx<T>* W, cpx<T>* S, cpx<T>* Rbuf, cpx<T>* R64, int* piv, int* perm, int* err,
                     hipStream_t s);
   // one application of the batched local solves on all subdomains:
   // z = sum_i R_i^T D_i A_i^{-1} R_i u  (+ add if add != nullptr)

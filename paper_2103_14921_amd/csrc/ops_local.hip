@@ -16,6 +16,7 @@
 #include <cstdlib>
 
 #include "kernels.h"
+#include "mfma.h"
 #include "stencil_row.h"
 
 namespace {
@@ -312,29 +313,31 @@ __global__ void k_gj_swap(const Sub* __restrict__ subs, int k, int j0, int bpmax
     Rbuf[((long long)s * NB + jj) * bpmax + c] = A[(long long)(j0 + jj) * bp + c];
 }
 
-// Deferred Gauss-Jordan update of the columns outside the panel:
-// A[i][c] = (i in panel rows ? 0 : A[i][c]) + sum_jj A[i][j0+jj] R[jj][c].
+// Deferred Gauss-Jordan update of the columns c in [c_lo, c_hi) outside the
+// panel: A[i][c] = (i in panel rows ? 0 : A[i][c]) + sum_jj A[i][j0+jj] R[jj][c].
 // One thread per row and CPT consecutive columns; the panel row is read once.
 template <typename T, int NB, int CPT>
-__global__ void __launch_bounds__(256) k_gj_update(const Sub* __restrict__ subs, int k, int j0, int bpmax,
-                                                   cpx<T>* __restrict__ S, const cpx<T>* __restrict__ Rbuf) {
+__global__ void __launch_bounds__(256) k_gj_update(const Sub* __restrict__ subs, int k, int j0, int bpmax, int c_lo,
+                                                   int c_hi, cpx<T>* __restrict__ S, const cpx<T>* __restrict__ Rbuf) {
   const int s = blockIdx.y;
   const Sub sb = subs[s];
   if (k >= sb.ez) return;
   const int b = sb.b, bp = sb.bp;
   if (j0 >= b) return;
+  c_hi = min(c_hi, b);
+  if (c_lo >= c_hi) return;
   const int nbw = min(NB, b - j0);
-  const int ncg = (b + CPT - 1) / CPT;
+  const int ncg = (c_hi - c_lo + CPT - 1) / CPT;
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (t >= (long long)b * ncg) return;
-  const int i = (int)(t / ncg), c0 = (int)(t % ncg) * CPT;
+  const int i = (int)(t / ncg), c0 = c_lo + (int)(t % ncg) * CPT;
   cpx<T>* A = S + (long long)s * bpmax * bpmax;
   const bool prow = i >= j0 && i < j0 + nbw;
   cpx<T> acc[CPT];
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     const int c = c0 + q;
-    acc[q] = (c < b && !prow) ? A[(long long)i * bp + c] : mk<T>(0, 0);
+    acc[q] = (c < c_hi && !prow) ? A[(long long)i * bp + c] : mk<T>(0, 0);
   }
   const cpx<T>* Ri = A + (long long)i * bp + j0;
   const cpx<T>* Rb = Rbuf + (long long)s * NB * bpmax + c0;
@@ -344,14 +347,102 @@ __global__ void __launch_bounds__(256) k_gj_update(const Sub* __restrict__ subs,
       const cpx<T> pv = Ri[jj];
 #pragma unroll
       for (int q = 0; q < CPT; ++q)
-        if (c0 + q < b) cfma(acc[q], pv, Rb[(long long)jj * bpmax + q]);
+        if (c0 + q < c_hi) cfma(acc[q], pv, Rb[(long long)jj * bpmax + q]);
     }
   }
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     const int c = c0 + q;
-    if (c < b && (c < j0 || c >= j0 + nbw)) A[(long long)i * bp + c] = acc[q];
+    if (c < c_hi && (c < j0 || c >= j0 + nbw)) A[(long long)i * bp + c] = acc[q];
   }
+}
+
+// Pivot rows of a block of OB Gauss-Jordan columns [J0, J0 + OB), as they stand
+// after the block's row interchanges (the columns outside the block are only
+// interchanged while the block is processed), for the block's deferred update.
+constexpr int GJ_OB = 64;
+
+template <typename T>
+__global__ void k_gj_rows(const Sub* __restrict__ subs, int k, int J0, int bpmax, const cpx<T>* __restrict__ S,
+                          cpx<T>* __restrict__ R64) {
+  const int s = blockIdx.y;
+  const Sub sb = subs[s];
+  if (k >= sb.ez) return;
+  const int b = sb.b, bp = sb.bp;
+  if (J0 >= b) return;
+  const int nbw = min(GJ_OB, b - J0);
+  const cpx<T>* A = S + (long long)s * bpmax * bpmax;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nbw * b; e += gridDim.x * blockDim.x) {
+    const int jj = e / b, c = e % b;
+    R64[((long long)s * GJ_OB + jj) * bpmax + c] = A[(long long)(J0 + jj) * bp + c];
+  }
+}
+
+// Deferred update of the columns outside the processed block on matrix cores:
+// A[i][c] = (i in block rows ? 0 : A[i][c]) + sum_jj A[i][J0 + jj] R64[jj][c],
+// a rank-OB complex product.  A workgroup owns a 64 x 64 tile of one box's
+// matrix; its R64 rows are staged in LDS, each of the four waves forms 16 rows
+// with the planar complex scheme (real and imaginary accumulators, four real
+// MFMAs per 16x16x4 step).
+template <typename T>
+__global__ void __launch_bounds__(256) k_gj_outer(const Sub* __restrict__ subs, int k, int J0, int bpmax,
+                                                  cpx<T>* __restrict__ S, const cpx<T>* __restrict__ R64) {
+  using V4 = typename Mfma<T>::v4;
+  constexpr int RW = 64 + (sizeof(T) == 4 ? 4 : 2);  // padded LDS row
+  __shared__ cpx<T> Rs[GJ_OB][RW];
+  const int s = blockIdx.y;
+  const Sub sb = subs[s];
+  if (k >= sb.ez) return;
+  const int b = sb.b, bp = sb.bp;
+  if (J0 >= b) return;
+  const int nbw = min(GJ_OB, b - J0);
+  const int ntc = (b + 63) / 64;
+  const int i0 = (blockIdx.x / ntc) * 64, c0 = (blockIdx.x % ntc) * 64;
+  if (i0 >= b) return;
+  if (c0 >= J0 && c0 + 64 <= J0 + nbw) return;  // every column of the tile is in the block
+  cpx<T>* A = S + (long long)s * bpmax * bpmax;
+  for (int e = threadIdx.x; e < GJ_OB * 64; e += 256) {
+    const int kk = e / 64, cc = e % 64;
+    Rs[kk][cc] = (kk < nbw && c0 + cc < b) ? R64[((long long)s * GJ_OB + kk) * bpmax + c0 + cc] : mk<T>(0, 0);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lrow = lane & 15, lg = lane >> 4;
+  const int row = i0 + 16 * wave + lrow;
+  const cpx<T>* Arow = A + (long long)min(row, b - 1) * bp + J0;  // clamped: rows past b contribute nothing stored
+  V4 acc[4][2];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) acc[nt][0] = acc[nt][1] = V4{0, 0, 0, 0};
+  for (int kc = 0; kc < nbw; kc += 16) {
+    cpx<T> av[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int kk = kc + 4 * lg + t;
+      av[t] = kk < nbw ? Arow[kk] : mk<T>(0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const T are = av[t].re, aim = av[t].im, naim = -aim;
+      const int kk = kc + 4 * lg + t;
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        const cpx<T> tv = Rs[kk][nt * 16 + lrow];
+        acc[nt][0] = Mfma<T>::op(are, tv.re, acc[nt][0]);
+        acc[nt][1] = Mfma<T>::op(are, tv.im, acc[nt][1]);
+        acc[nt][0] = Mfma<T>::op(naim, tv.im, acc[nt][0]);
+        acc[nt][1] = Mfma<T>::op(aim, tv.re, acc[nt][1]);
+      }
+    }
+  }
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + 16 * wave + Mfma<T>::row(lg, v), c = c0 + nt * 16 + lrow;
+      if (i >= b || c >= b || (c >= J0 && c < J0 + nbw)) continue;
+      cpx<T>* a = A + (long long)i * bp + c;
+      const cpx<T> old = (i >= J0 && i < J0 + nbw) ? mk<T>(0, 0) : *a;
+      *a = mk<T>(old.re + acc[nt][0][v], old.im + acc[nt][1][v]);
+    }
 }
 
 // Column permutation that undoes the row interchanges: apply swaps (j, piv[j])
@@ -583,33 +674,46 @@ template void launch_couplings<float>(long long, const z64*, c32*, hipStream_t);
 template void launch_couplings<double>(long long, const z64*, z64*, hipStream_t);
 
 namespace {
+// Blocked Gauss-Jordan inversion of the plane Schur complements: blocks of
+// GJ_OB columns, each processed as NB-column panels whose deferred updates
+// touch only the block; the rest of the matrix then receives the whole block's
+// update in one rank-GJ_OB product on matrix cores.
 template <typename T, int NB, int R>
-void gj_panels(const Sub* subs, int nsub, int bpmax, int k, cpx<T>* S, cpx<T>* Rbuf, int* piv, int* err,
+void gj_panels(const Sub* subs, int nsub, int bpmax, int k, cpx<T>* S, cpx<T>* Rbuf, cpx<T>* R64, int* piv, int* err,
                hipStream_t s) {
-  const long long cells = (long long)bpmax * bpmax;
-  for (int j0 = 0; j0 < bpmax; j0 += NB) {
-    hipLaunchKernelGGL((k_gj_panel<T, NB, R>), dim3(nsub), dim3(256), 0, s, subs, k, j0, bpmax, S, piv, err);
-    hipLaunchKernelGGL((k_gj_swap<T, NB>), dim3((unsigned)ceil_div(bpmax, 256), nsub), dim3(256), 0, s, subs, k, j0,
-                       bpmax, S, piv, Rbuf);
-    hipLaunchKernelGGL((k_gj_update<T, NB, 4>), dim3((unsigned)ceil_div(cells / 4 + bpmax, 256), nsub), dim3(256), 0,
-                       s, subs, k, j0, bpmax, S, Rbuf);
+  static_assert(GJ_OB % NB == 0, "panels tile the block");
+  const int nt = (int)ceil_div(bpmax, 64);
+  for (int J0 = 0; J0 < bpmax; J0 += GJ_OB) {
+    for (int j0 = J0; j0 < J0 + GJ_OB && j0 < bpmax; j0 += NB) {
+      hipLaunchKernelGGL((k_gj_panel<T, NB, R>), dim3(nsub), dim3(256), 0, s, subs, k, j0, bpmax, S, piv, err);
+      hipLaunchKernelGGL((k_gj_swap<T, NB>), dim3((unsigned)ceil_div(bpmax, 256), nsub), dim3(256), 0, s, subs, k, j0,
+                         bpmax, S, piv, Rbuf);
+      const int c_hi = std::min(J0 + GJ_OB, bpmax);
+      const long long cells = (long long)bpmax * ((c_hi - J0 + 3) / 4);
+      hipLaunchKernelGGL((k_gj_update<T, NB, 4>), dim3((unsigned)ceil_div(cells, 256), nsub), dim3(256), 0, s, subs,
+                         k, j0, bpmax, J0, c_hi, S, Rbuf);
+    }
+    if (J0 + GJ_OB >= bpmax && J0 == 0) continue;  // one block covers the matrix: nothing outside it
+    hipLaunchKernelGGL(k_gj_rows<T>, dim3((unsigned)ceil_div((long long)GJ_OB * bpmax, 256), nsub), dim3(256), 0, s,
+                       subs, k, J0, bpmax, S, R64);
+    hipLaunchKernelGGL(k_gj_outer<T>, dim3((unsigned)(nt * nt), nsub), dim3(256), 0, s, subs, k, J0, bpmax, S, R64);
   }
 }
 }  // namespace
 
 template <typename T>
 void Factor<T>::plane(const Sub* subs, int nsub, int bpmax, int k, const z64* aloc, cpx<T>* sinv, cpx<T>* W,
-                      cpx<T>* S, cpx<T>* Rbuf, int* piv, int* perm, int* err, hipStream_t s) {
+                      cpx<T>* S, cpx<T>* Rbuf, cpx<T>* R64, int* piv, int* perm, int* err, hipStream_t s) {
   const long long cells = (long long)bpmax * bpmax;
   dim3 grid((unsigned)ceil_div(cells, 256), nsub);
   if (k >= 1) hipLaunchKernelGGL(k_schur_W<T>, grid, dim3(256), 0, s, subs, k, bpmax, aloc, sinv, W);
   hipLaunchKernelGGL(k_schur_S<T>, grid, dim3(256), 0, s, subs, k, bpmax, aloc, W, S);
   const int R = (int)ceil_div(bpmax, 256);
-  if (R <= 1) gj_panels<T, 16, 1>(subs, nsub, bpmax, k, S, Rbuf, piv, err, s);
-  else if (R <= 2) gj_panels<T, 16, 2>(subs, nsub, bpmax, k, S, Rbuf, piv, err, s);
-  else if (R <= 4) gj_panels<T, 8, 4>(subs, nsub, bpmax, k, S, Rbuf, piv, err, s);
-  else if (R <= 6) gj_panels<T, 8, 6>(subs, nsub, bpmax, k, S, Rbuf, piv, err, s);
-  else gj_panels<T, 8, 8>(subs, nsub, bpmax, k, S, Rbuf, piv, err, s);
+  if (R <= 1) gj_panels<T, 16, 1>(subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
+  else if (R <= 2) gj_panels<T, 16, 2>(subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
+  else if (R <= 4) gj_panels<T, 8, 4>(subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
+  else if (R <= 6) gj_panels<T, 8, 6>(subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
+  else gj_panels<T, 8, 8>(subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
   hipLaunchKernelGGL(k_gj_perm, dim3((unsigned)ceil_div(nsub, 64)), dim3(64), 0, s, subs, nsub, k, bpmax, piv, perm);
   hipLaunchKernelGGL(k_gj_final<T>, grid, dim3(256), 0, s, subs, k, bpmax, S, perm, sinv);
 }

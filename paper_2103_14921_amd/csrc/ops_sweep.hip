@@ -22,30 +22,9 @@
 #include <tuple>
 
 #include "kernels.h"
+#include "mfma.h"
 
 namespace {
-
-template <typename T>
-struct Mfma;
-template <>
-struct Mfma<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  // output element v of lane group lg (lane / 16) sits in tile row 4 lg + v
-  static __device__ __forceinline__ int row(int lg, int v) { return 4 * lg + v; }
-};
-template <>
-struct Mfma<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  // the f64 variant interleaves its rows: element v of lane group lg is tile row lg + 4 v
-  static __device__ __forceinline__ int row(int lg, int v) { return lg + 4 * v; }
-};
-
 
 // Make this workgroup's global stores visible to its other waves.
 __device__ __forceinline__ void wg_sync_global() {
