@@ -207,27 +207,20 @@ __device__ __forceinline__ void tile_product(const RowTile& t, int nx, int ny, i
     z64 acc[NXT];
 #pragma unroll
     for (int m = 0; m < NXT; ++m) acc[m] = mk(0.0, 0.0);
-    // the neighbour rows plane by plane (dz), the three rows (dy) of a plane
-    // loaded together: three memory round trips per item
+    // the nine neighbour rows (dz, dy) in order; latency is hidden by the
+    // other waves of the compute unit
 #pragma unroll 1
-    for (int dz = 0; dz < 3; ++dz) {
-      const int jz = min(max(t.iz + dz - 1, 0), nz - 1);
-      z64 v[3][NXT + 2];
+    for (int k = 0; k < 9; ++k) {
+      const int jz = min(max(t.iz + k / 3 - 1, 0), nz - 1), jy = min(max(t.iy + k % 3 - 1, 0), ny - 1);
+      const z64* xr = x + (long long)nx * (jy + (long long)ny * jz) * nrhs + r;
+      z64 v[NXT + 2];
 #pragma unroll
-      for (int dy = 0; dy < 3; ++dy) {
-        const int jy = min(max(t.iy + dy - 1, 0), ny - 1);
-        const z64* xr = x + (long long)nx * (jy + (long long)ny * jz) * nrhs + r;
+      for (int q = 0; q < NXT + 2; ++q) v[q] = xr[(long long)min(max(xa - 1 + q, 0), nx - 1) * nrhs];
+      const int ob = 3 * k;
 #pragma unroll
-        for (int q = 0; q < NXT + 2; ++q) v[dy][q] = xr[(long long)min(max(xa - 1 + q, 0), nx - 1) * nrhs];
-      }
+      for (int m = 0; m < NXT; ++m)
 #pragma unroll
-      for (int dy = 0; dy < 3; ++dy) {
-        const int ob = 9 * dz + 3 * dy;
-#pragma unroll
-        for (int m = 0; m < NXT; ++m)
-#pragma unroll
-          for (int dx = 0; dx < 3; ++dx) cfma(acc[m], cf[g * NXT + m][ob + dx], v[dy][m + dx]);
-      }
+        for (int dx = 0; dx < 3; ++dx) cfma(acc[m], cf[g * NXT + m][ob + dx], v[m + dx]);
     }
     const long long rowi = (long long)nx * (t.iy + (long long)ny * t.iz);
 #pragma unroll
