@@ -51,6 +51,16 @@ helm_status guarded(F&& f) {
 // repeated solves); the cache is returned to the runtime when an allocation
 // fails.
 // ---------------------------------------------------------------------------
+// Stream capture (one outer iteration recorded into a graph) may run on one
+// handle's thread while other handles allocate, free or set up on theirs.
+// Device-wide operations (hipMalloc, hipFree) and captures are serialised by
+// this lock; everything else the library enqueues goes to the handles' own
+// non-blocking streams, never to the legacy stream.
+std::recursive_mutex& capture_lock() {
+  static std::recursive_mutex* m = new std::recursive_mutex();
+  return *m;
+}
+
 struct DevicePool {
   std::mutex mu;
   std::multimap<size_t, void*> blocks;
@@ -69,6 +79,7 @@ struct DevicePool {
       }
     }
     void* p = nullptr;
+    std::lock_guard<std::recursive_mutex> cl(capture_lock());
     if (hipMalloc(&p, want) != hipSuccess) {
       (void)hipGetLastError();
       trim();
@@ -85,9 +96,10 @@ struct DevicePool {
     blocks.insert({b, p});
     cached += b;
   }
+  // Cached blocks are idle (their owners synchronised before releasing them).
   void trim() {
+    std::lock_guard<std::recursive_mutex> cl(capture_lock());
     std::lock_guard<std::mutex> lk(mu);
-    if (!blocks.empty()) (void)hipDeviceSynchronize();
     for (auto& kv : blocks) (void)hipFree(kv.second);
     blocks.clear();
     cached = 0;
@@ -786,6 +798,7 @@ void run_outer_step(helm_handle* H, int nr, int j, double tol, int maxit) {
     e->gen = H->ws_gen;
     e->timed = H->timing;
     e->policy = sweep_policy();
+    std::lock_guard<std::recursive_mutex> cl(capture_lock());
     const hipError_t be = hipStreamBeginCapture(H->stream, hipStreamCaptureModeRelaxed);
     if (be != hipSuccess) {
       (void)hipGetLastError();
@@ -934,9 +947,10 @@ void factor_level(helm_handle* H, Level& L) {
   if (e) throw HelmError(HELM_EBREAKDOWN, "numerically singular pivot in a local factorisation");
 }
 
-void upload_subs(Level& L) {
+void upload_subs(Level& L, hipStream_t stream) {
   L.d_subs.alloc(sizeof(Sub) * L.subs.size());
-  HELM_CHECK_HIP(hipMemcpy(L.d_subs.p, L.subs.data(), sizeof(Sub) * L.subs.size(), hipMemcpyHostToDevice));
+  HELM_CHECK_HIP(hipMemcpyAsync(L.d_subs.p, L.subs.data(), sizeof(Sub) * L.subs.size(), hipMemcpyHostToDevice, stream));
+  HELM_CHECK_HIP(hipStreamSynchronize(stream));
 }
 
 void setup_impl(helm_handle* H, const void* velocity) {
@@ -946,7 +960,8 @@ void setup_impl(helm_handle* H, const void* velocity) {
   const long long n = H->n;
   // velocity: validate on the host
   std::vector<z64> ch((size_t)n);
-  HELM_CHECK_HIP(hipMemcpy(ch.data(), velocity, sizeof(z64) * n, hipMemcpyDefault));
+  HELM_CHECK_HIP(hipMemcpyAsync(ch.data(), velocity, sizeof(z64) * n, hipMemcpyDefault, H->stream));
+  HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
   for (long long i = 0; i < n; ++i) {
     if (!std::isfinite(ch[i].re) || !std::isfinite(ch[i].im) || !(ch[i].re > 0))
       throw HelmError(HELM_EINVAL, "velocity must be finite with a positive real part");
@@ -958,7 +973,8 @@ void setup_impl(helm_handle* H, const void* velocity) {
 
   Timer tall(H->stream);
   H->c.alloc(sizeof(z64) * n);
-  HELM_CHECK_HIP(hipMemcpy(H->c.p, ch.data(), sizeof(z64) * n, hipMemcpyHostToDevice));
+  HELM_CHECK_HIP(hipMemcpyAsync(H->c.p, ch.data(), sizeof(z64) * n, hipMemcpyHostToDevice, H->stream));
+  HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
   H->sigma.alloc(sizeof(z64) * n);
   const int tot_int = H->nx + H->ny + H->nz;
   H->xi_int.alloc(sizeof(z64) * tot_int);
@@ -1003,7 +1019,7 @@ void setup_impl(helm_handle* H, const void* velocity) {
 
   // fine level: local operators with absorbing interfaces, then factorisation
   Level& F = H->fine;
-  upload_subs(F);
+  upload_subs(F, H->stream);
   F.aloc.alloc(sizeof(z64) * 27 * (size_t)F.nodes_total);
   F.sinv.alloc(elem_size(F.prec) * (size_t)F.mat_total);
   launch_local_fine(op, F.d_subs.as<Sub>(), F.nsub, F.maxnodes, H->c.as<z64>(), H->omega, H->h, H->dec.robin,
@@ -1019,7 +1035,7 @@ void setup_impl(helm_handle* H, const void* velocity) {
     Level& C = H->coarse;
     C.E.alloc(sizeof(z64) * 27 * (size_t)C.n);
     launch_build_E(op, C.nx, C.ny, C.nz, C.E.as<z64>(), H->stream);
-    upload_subs(C);
+    upload_subs(C, H->stream);
     C.aloc.alloc(sizeof(z64) * 27 * (size_t)C.nodes_total);
     C.sinv.alloc(sizeof(z64) * (size_t)C.mat_total);
     launch_local_coarse(C.nx, C.ny, C.nz, C.E.as<z64>(), C.d_subs.as<Sub>(), C.nsub, C.maxnodes, H->c.as<z64>(), H->nx,

@@ -108,3 +108,40 @@ def test_sweep_timing_inside_graphs():
     assert g.graph_stats()["replays"] > before
     g.close()
     d.close()
+
+
+def test_capture_concurrent_with_setup_and_trim():
+    # one thread solves (capturing its outer iterations) while another sets up
+    # and destroys handles and trims the device cache: captures never see a
+    # device-wide operation and set-ups never touch the legacy stream
+    import threading
+
+    import torch
+    from paper_2103_14921_amd import helm
+    shape = (40, 40, 40)
+    g, d, dev = _pair(shape, (2, 2, 2), 2, "mixed", 5)
+    d.close()
+    B = _rhs(shape, (3, 3), dev)
+    c2 = torch.from_numpy(inputs.velocity_thrust_belt(32, 32, 32, H)).to(dev)
+    errors = []
+
+    def churn():
+        try:
+            for i in range(6):
+                S = helm.Solver((32, 32, 32), H, c2, F, (NPML, NPML, NPML, 0), parts=(2, 2, 2), overlap=2, levels=2,
+                                precision="mixed", restart=5)
+                S.close()
+                helm.trim_cache()
+        except Exception as exc:  # reported below
+            errors.append(exc)
+
+    say("concurrent capture and set-up")
+    t = threading.Thread(target=churn)
+    t.start()
+    results = [g.solve(B, tol=1e-6, maxit=200) for _ in range(3)]
+    t.join()
+    assert not errors, errors
+    for X, info in results:
+        assert np.all(info["relres_true"] <= 1e-6)
+    assert g.graph_stats()["replays"] > 0
+    g.close()

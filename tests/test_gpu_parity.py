@@ -41,7 +41,7 @@ def _thrust_case(shape=(23, 19, 17), pml=(4, 3, 5, 2), q=100.0):
     return shape, h, c, f, pml
 
 
-@pytest.mark.parametrize("nrhs", [1, 3, 8])
+@pytest.mark.parametrize("nrhs", [1, 3, 8, 12, 20])
 def test_stencil_matches_csr(nrhs):
     shape, h, c, f, pml = _thrust_case()
     say("stencil", shape, nrhs)
@@ -96,6 +96,21 @@ def test_coarse_pieces_match_oracle():
     Mz = S.apply_M(R)
     for r in range(2):
         assert rel(Mz[r], tl.apply(R[r])) <= 1e-9
+    S.close()
+
+
+@pytest.mark.parametrize("nrhs", [2, 12])
+def test_coarse_operator_batches_match_oracle(nrhs):
+    # coarse product E x on batches below and above the row-tiled threshold,
+    # on a grid whose rows do not divide into the tile width
+    shape, h, c, f, pml = _thrust_case(shape=(30, 22, 19), pml=(3, 3, 3, 0))
+    say("coarse E", shape, nrhs)
+    prob = Problem(shape, h, c, f, Pml(*pml), WO)
+    A = assemble(prob)
+    tl = TwoLevel(A, shape, decompose(shape, (2, 2, 2), 2), prob.k().ravel(), h, 2)
+    S = helm().Solver(shape, h, c, f, pml, weights=W, parts=(2, 2, 2), overlap=2, levels=2)
+    Cc = inputs.random_field((nrhs, S.nc), seed=90 + nrhs)
+    assert rel(S.apply_E(Cc), (tl.E @ Cc.T).T) <= 1e-12
     S.close()
 
 
