@@ -75,8 +75,9 @@ def gpu_solve(helm, w, c_dev, b_dev, precision, weights, timing=False, graphs=Tr
 PEAK = {"c64": 157.3, "c128": 78.6}  # dense MFMA TFLOP/s of one MI355X (fp32, fp64)
 
 
-def measured_traffic(kernel_file, profile_md):
-    """HBM bytes per launch from the committed PMC summary, if the kernel source is unchanged since."""
+def measured_traffic(kernel_file, profile_md, algorithmic_bytes):
+    """HBM bytes per launch from the committed PMC summary, if the kernel source is unchanged since and
+    the tuner chose the same launch shape (same algorithmic bytes per launch)."""
     import hashlib
     import re as _re
     root = os.path.dirname(os.path.abspath(__file__))
@@ -85,6 +86,8 @@ def measured_traffic(kernel_file, profile_md):
         data = json.loads(_re.search(r"```json\n(.*?)\n```", text, _re.S).group(1))
         src = open(os.path.join(root, "paper_2103_14921_amd", "csrc", kernel_file), "rb").read()
         if hashlib.sha256(src).hexdigest()[:16] != data["source_sha256_16"]:
+            return None
+        if abs(algorithmic_bytes - data["algorithmic_bytes_per_launch"]) > 1e-6 * algorithmic_bytes:
             return None
         return data["traffic_bytes_per_launch"]
     except Exception:
@@ -261,7 +264,8 @@ def main():
         out["roofline"] = roofline_entry(info["sweeps"][1], "c128")
         out["roofline"]["kernel"] = "k_oras_fused (coarse level, FP64 complex, MFMA 16x16x4 f64)"
         if args.workload == "thrust192_mixed":
-            out["roofline"]["traffic"] = measured_traffic("ops_sweep.hip", "oras_sweep_coarse_thrust192_mixed_pmc.md")
+            out["roofline"]["traffic"] = measured_traffic("ops_sweep.hip", "oras_sweep_coarse_thrust192_mixed_pmc.md",
+                                                          out["roofline"]["bytes_per_launch"])
         out["roofline_fine_sweep"] = roofline_entry(info["sweeps"][0], fine_dtype)
     else:
         out["roofline"] = roofline_entry(info["sweeps"][0], fine_dtype)

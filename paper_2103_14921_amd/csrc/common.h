@@ -144,3 +144,14 @@ struct Sub {
   } while (0)
 
 __host__ __device__ __forceinline__ long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
+
+// Workgroups are dispatched round-robin over the XCDs (each with its own L2):
+// the logical index xcd_contiguous(blockIdx.x, gridDim.x) gives XCD c the
+// contiguous range [start_c, start_c + count_c) of logical workgroups, so that
+// neighbouring logical workgroups, which share data, meet in the same L2.
+__device__ __forceinline__ long long xcd_contiguous(long long b, long long nb) {
+  constexpr int NXCD = 8;
+  const long long q = nb / NXCD, rem = nb % NXCD;
+  const long long c = b % NXCD, k = b / NXCD;
+  return c * q + (c < rem ? c : rem) + k;
+}

@@ -172,17 +172,6 @@ constexpr int TW = 64, NXT = 4;
 struct RowTile {
   int iy, iz, x0, w;
 };
-// Workgroups are dispatched round-robin over the XCDs (each with its own L2):
-// give XCD c the contiguous range of tiles [start_c, start_c + count_c), so that
-// neighbouring rows, which share eight of their nine input rows, meet in the
-// same L2.
-__device__ __forceinline__ long long xcd_contiguous(long long b, long long nb) {
-  constexpr int NXCD = 8;
-  const long long q = nb / NXCD, rem = nb % NXCD;
-  const long long c = b % NXCD, k = b / NXCD;
-  return c * q + (c < rem ? c : rem) + k;
-}
-
 __device__ __forceinline__ RowTile row_tile(int nx, int ny) {
   const int nt = (nx + TW - 1) / TW;
   const int tw = ((nx + nt - 1) / nt + NXT - 1) / NXT * NXT;  // balanced segment width, multiple of NXT

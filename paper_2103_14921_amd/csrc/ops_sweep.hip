@@ -336,7 +336,10 @@ __global__ void __launch_bounds__(64 * fused_max_waves<T>()) k_oras_fused(const 
                                                    cpx<T>* __restrict__ yloc) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* Bs = reinterpret_cast<cpx<T>*>(smem_raw);
-  const BoxCtx<T, RG> bx(subs, blockIdx.x, ngroups, nrhs, cpl, u, z, add, gnx, gny, yloc);
+  // items of one box (its RHS groups) and neighbouring boxes go to the same XCD
+  // back to back, so the groups' reads of the box's factors meet in its L2
+  const int item = (int)xcd_contiguous(blockIdx.x, gridDim.x);
+  const BoxCtx<T, RG> bx(subs, item, ngroups, nrhs, cpl, u, z, add, gnx, gny, yloc);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int FT = blockDim.x, nwaves = FT >> 6;
   const int bp = bx.sb.bp, ns = bx.nsteps();
