@@ -684,8 +684,9 @@ void arnoldi_step(helm_handle* H, KrylovArrays& K, int j, const z64* V, z64* w, 
                   int maxit, int fixed) {
   Workspace& W = H->ws;
   const long long vs = len * nr;
-  launch_norm2(w, len, nr, W.dpart.as<double>(), K.w0.as<double>(), H->stream);
-  launch_dots(V, vs, j + 1, w, len, nr, W.zpart.as<z64>(), K.h.as<z64>(), H->stream);
+  // first Gram-Schmidt projections, with ||w||^2 (for the breakdown test) from the same read of w
+  launch_dots(V, vs, j + 1, w, len, nr, W.zpart.as<z64>(), K.h.as<z64>(), H->stream, W.dpart.as<double>(),
+              K.w0.as<double>());
   if (!launch_axpy_dots(V, vs, j + 1, K.h.as<z64>(), w, len, nr, W.zpart.as<z64>(), K.h2.as<z64>(), H->stream)) {
     launch_axpy_multi(V, vs, j + 1, K.h.as<z64>(), w, len, nr, W.dpart.as<double>(), nullptr, H->stream);
     launch_dots(V, vs, j + 1, w, len, nr, W.zpart.as<z64>(), K.h2.as<z64>(), H->stream);

@@ -77,7 +77,8 @@ void launch_to_node_major(const z64* in, z64* out, long long len, int nrhs, hipS
 void launch_to_field_major(const z64* in, z64* out, long long len, int nrhs, hipStream_t s);
 // h[v][r] = sum_node conj(V_v[node][r]) w[node][r], v < nv; V_v = V + v*vstride
 void launch_dots(const z64* V, long long vstride, int nv, const z64* w, long long len, int nrhs,
-                 z64* partial, z64* h, hipStream_t s);
+                 z64* partial, z64* h, hipStream_t s, double* npart = nullptr,
+                 double* nrm2 = nullptr);
 // w -= sum_v h[v][r] V_v ; optionally nrm2[r] = ||w||^2 after the update
 void launch_axpy_multi(const z64* V, long long vstride, int nv, const z64* h, z64* w,
                        long long len, int nrhs, double* partial, double* nrm2, hipStream_t s);

@@ -76,11 +76,13 @@ __device__ __forceinline__ Span block_span(long long len) {
 // Block partial sums are stored output-major, partial[(v * nrhs + r) * nblk + blk],
 // so that the final reductions read each output's partials contiguously.
 
-// partial[v][r][blk] = sum over the block's nodes of conj(V_v) w
+// partial[v][r][blk] = sum over the block's nodes of conj(V_v) w; with npart,
+// also npart[r][blk] = sum |w|^2 (the norm read along with the projections)
 __global__ void __launch_bounds__(256) k_dots(const z64* __restrict__ V, long long vstride, int nv,
                                               const z64* __restrict__ w, long long len, int nrhs,
-                                              z64* __restrict__ partial) {
+                                              z64* __restrict__ partial, double* __restrict__ npart) {
   __shared__ z64 red[256];
+  __shared__ double nred[256];
   const int tid = threadIdx.x;
   const int nl = 256 / nrhs;
   const int r = tid % nrhs, lane = tid / nrhs;
@@ -88,13 +90,24 @@ __global__ void __launch_bounds__(256) k_dots(const z64* __restrict__ V, long lo
   z64 acc[NVMAX];
 #pragma unroll
   for (int v = 0; v < NVMAX; ++v) acc[v] = mk(0.0, 0.0);
+  double nacc = 0.0;
   if (lane < nl) {
     for (long long nd = sp.lo + lane; nd < sp.hi; nd += nl) {
       const long long e = nd * nrhs + r;
       const z64 wv = w[e];
+      nacc += abs2(wv);
 #pragma unroll
       for (int v = 0; v < NVMAX; ++v)
         if (v < nv) cdot_acc(acc[v], V[(long long)v * vstride + e], wv);
+    }
+  }
+  if (npart) {  // uniform over the block
+    nred[tid] = (lane < nl) ? nacc : 0.0;
+    __syncthreads();
+    if (lane == 0) {
+      double t = nred[r];
+      for (int l = 1; l < nl; ++l) t += nred[l * nrhs + r];
+      npart[(long long)r * gridDim.x + blockIdx.x] = t;
     }
   }
 #pragma unroll
@@ -446,11 +459,15 @@ void launch_to_field_major(const z64* in, z64* out, long long len, int nrhs, hip
 }
 
 void launch_dots(const z64* V, long long vstride, int nv, const z64* w, long long len, int nrhs, z64* partial,
-                 z64* h, hipStream_t s) {
+                 z64* h, hipStream_t s, double* npart, double* nrm2) {
   const int nblk = red_blocks(len);
   for (int v0 = 0; v0 < nv; v0 += NVMAX) {
     const int nvb = std::min(NVMAX, nv - v0);
-    hipLaunchKernelGGL(k_dots, dim3(nblk), dim3(256), 0, s, V + v0 * vstride, vstride, nvb, w, len, nrhs, partial);
+    double* np = (v0 == 0 && nrm2) ? npart : nullptr;
+    hipLaunchKernelGGL(k_dots, dim3(nblk), dim3(256), 0, s, V + v0 * vstride, vstride, nvb, w, len, nrhs, partial,
+                       np);
+    if (np)
+      hipLaunchKernelGGL(k_sum_final, dim3((unsigned)ceil_div(nrhs, 4)), dim3(256), 0, s, np, nblk, nrhs, nrm2);
     hipLaunchKernelGGL(k_dots_final, dim3((unsigned)ceil_div(nvb * nrhs, 4)), dim3(256), 0, s, partial, nblk, nvb,
                        nrhs, h + (long long)v0 * nrhs);
   }
