@@ -162,6 +162,15 @@ helm_status helm_graph_stats(const helm_handle_t* h, double out[2]);
  * rounding.  Graphs captured under one policy are not replayed under another. */
 helm_status helm_set_sweep_policy(int32_t policy);
 
+/* Process-wide tiling of the 27-point products (the fine operator of eq. eq1
+ * and the coarse operator E of eq. 2lvl) for batches of 4 or
+ * more right-hand sides: each thread computes nodes_per_thread consecutive
+ * nodes of a grid row (2, 4 or 8); 0 (default) times the three once per grid
+ * and batch size and keeps the fastest.  Every tiling sums the 27 terms of an
+ * output in the same order, so results are bitwise identical.  Returns
+ * HELM_EINVAL for any other value. */
+helm_status helm_set_row_tiling(int32_t nodes_per_thread);
+
 /* Return the handle's cached Krylov workspace (sized for its last batch) to
  * the library's device cache, keeping operators and factors resident: lets a
  * server hold many set-up problems and pay workspace only while solving. */

@@ -80,6 +80,13 @@ struct DevicePool {
     }
     void* p = nullptr;
     std::lock_guard<std::recursive_mutex> cl(capture_lock());
+    // never take the last free bytes: the runtime allocates for itself at
+    // dispatch (kernel arguments, signals, graph instantiation), and a failure
+    // there aborts the queue instead of returning an error
+    if (free_bytes() < want + headroom_bytes()) {
+      trim();
+      if (free_bytes() < want + headroom_bytes()) return nullptr;
+    }
     if (hipMalloc(&p, want) != hipSuccess) {
       (void)hipGetLastError();
       trim();
@@ -90,6 +97,23 @@ struct DevicePool {
     }
     *got = want;
     return p;
+  }
+  static size_t free_bytes() {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      (void)hipGetLastError();
+      return 0;
+    }
+    return fr;
+  }
+  // Device memory left to the runtime: 1% of the device, at least 1 GiB.
+  static size_t headroom_bytes() {
+    static const size_t h = [] {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) != hipSuccess) (void)hipGetLastError();
+      return std::max<size_t>(size_t(1) << 30, tot / 100);
+    }();
+    return h;
   }
   void put(void* p, size_t b) {
     std::lock_guard<std::mutex> lk(mu);
@@ -440,7 +464,9 @@ size_t budget_bytes() {
     (void)hipGetLastError();
     fr = 0;
   }
-  size_t b = (size_t)((fr + pool().cached_bytes()) * 0.92);
+  const size_t avail = fr + pool().cached_bytes();
+  const size_t head = DevicePool::headroom_bytes();
+  size_t b = avail > head ? (size_t)((avail - head) * 0.92) : 0;
   if (const char* e = std::getenv("HELM_MEM_BUDGET")) {
     const size_t v = (size_t)std::strtoull(e, nullptr, 10);
     if (v > 0) b = std::min(b, v);
@@ -775,11 +801,12 @@ bool sweep_untuned(const Level& L, int nr) {
 }
 
 // Run outer iteration j from its captured graph, capturing it first if needed.
-// Falls back to direct launches while a sweep is untuned, and for good if the
-// runtime refuses capture.
+// Falls back to direct launches while a sweep or a row-tiled product is
+// untuned, and for good if the runtime refuses capture.
 void run_outer_step(helm_handle* H, int nr, int j, double tol, int maxit) {
   if (!H->graphs || (H->timing && !H->graph_timing) || sweep_untuned(H->fine, nr) ||
-      (H->two_level() && sweep_untuned(H->coarse, nr))) {
+      (H->two_level() && sweep_untuned(H->coarse, nr)) || stencil_untuned(H->op, nr) ||
+      (H->two_level() && coarse_spmv_untuned(H->coarse.nx, H->coarse.ny, H->coarse.nz, nr))) {
     outer_step(H, nr, j, tol, maxit);
     return;
   }
@@ -1247,6 +1274,11 @@ helm_status helm_set_graphs(helm_handle_t* H, int32_t enable) {
 helm_status helm_set_sweep_policy(int32_t policy) {
   if (policy < 0 || policy > 2) return fail(HELM_EINVAL, "sweep policy must be 0, 1 or 2");
   set_sweep_policy(policy);
+  return HELM_OK;
+}
+
+helm_status helm_set_row_tiling(int32_t nodes_per_thread) {
+  if (!set_row_tiling(nodes_per_thread)) return fail(HELM_EINVAL, "nodes per thread must be 0, 2, 4 or 8");
   return HELM_OK;
 }
 

@@ -13,9 +13,17 @@ void launch_pml_tables(const AxisPml ax[3], double h, double omega, double R, co
                        z64* xi_int, z64* xi_half, z64* i2_int, z64* i2_half, uint8_t* flat,
                        hipStream_t s);
 void launch_sigma(const OpDev& op, const z64* c, double omega, hipStream_t s);
+// y = A x; y aliases neither x nor b (the first application of a shape outside
+// a capture is run several times by the autotuner).
 void launch_stencil(const OpDev& op, int nrhs, const z64* x, z64* y, hipStream_t s);
 // y = b - A x
 void launch_residual(const OpDev& op, int nrhs, const z64* b, const z64* x, z64* y, hipStream_t s);
+// True while the row-tiled product for this grid and batch has not been timed
+// (an application outside a stream capture times it).
+bool stencil_untuned(const OpDev& op, int nrhs);
+bool coarse_spmv_untuned(int ncx, int ncy, int ncz, int nrhs);
+// Nodes per thread of the row-tiled products: 0 = autotuned, else 2, 4 or 8.
+bool set_row_tiling(int nxt);
 void launch_build_E(const OpDev& op, int ncx, int ncy, int ncz, z64* E, hipStream_t s);
 void launch_coarse_spmv(int ncx, int ncy, int ncz, const z64* E, int nrhs, const z64* x, z64* y,
                         hipStream_t s);

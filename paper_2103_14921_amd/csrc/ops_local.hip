@@ -21,7 +21,7 @@
 
 namespace {
 
-__global__ void k_local_fine(OpDev op, const Sub* __restrict__ subs, const z64* __restrict__ c,
+__global__ void __launch_bounds__(256) k_local_fine(OpDev op, const Sub* __restrict__ subs, const z64* __restrict__ c,
                              double omega, double h, int robin, z64* __restrict__ aloc) {
   const Sub sb = subs[blockIdx.y];
   const long long nl = (long long)sb.ex * sb.ey * sb.ez;
@@ -33,6 +33,7 @@ __global__ void k_local_fine(OpDev op, const Sub* __restrict__ subs, const z64* 
     fine_row(op, gx, gy, gz, row);
     z64 fold = mk(0.0, 0.0);
     z64* out = aloc + (sb.node_off + l) * 27;
+#pragma unroll
     for (int o = 0; o < 27; ++o) {
       if (o == 13) continue;
       const int jx = gx + o % 3 - 1, jy = gy + (o / 3) % 3 - 1, jz = gz + o / 9 - 1;
@@ -187,7 +188,7 @@ __global__ void __launch_bounds__(256) k_gj_panel(const Sub* __restrict__ subs, 
   }
 #pragma unroll
   for (int jj = 0; jj < NB; ++jj) {
-    if (jj >= nbw) break;
+    if (jj >= nbw) continue;  // uniform; a constant trip count keeps P in registers
     const int j = j0 + jj;
     // pivot search: largest |re|+|im| over rows i >= j, ties to the smallest index
     T best = (T)-1;

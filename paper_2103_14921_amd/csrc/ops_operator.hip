@@ -8,6 +8,12 @@
 // m the midpoint of the edge i-j, and
 //   A[i, i] = -sum_o (alpha_cls/h^2) a_e(m) + wm1 sigma_i,   sigma = s k^2,
 // ghost neighbours outside the grid contributing to the diagonal only.
+#include <atomic>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include "kernels.h"
 #include "stencil_row.h"
 
@@ -166,12 +172,15 @@ __global__ void __launch_bounds__(256) k_stencil2(OpDev op, int nrhs, const z64*
 // LDS (zero towards neighbours outside the grid); phase 2 gives each thread NXT
 // consecutive nodes of one right-hand side: for each of the nine neighbour
 // rows it loads NXT + 2 values once and uses them for all NXT outputs, where a
-// node-per-thread product issues 27 vector loads per output.
-constexpr int TW = 64, NXT = 4;
+// node-per-thread product issues 27 vector loads per output.  NXT (2, 4 or 8)
+// is chosen per grid and batch by the autotuner below; every choice sums the
+// 27 taps of an output in the same order, so results do not depend on it.
+constexpr int TW = 64;
 
 struct RowTile {
   int iy, iz, x0, w;
 };
+template <int NXT>
 __device__ __forceinline__ RowTile row_tile(int nx, int ny) {
   const int nt = (nx + TW - 1) / TW;
   const int tw = ((nx + nt - 1) / nt + NXT - 1) / NXT * NXT;  // balanced segment width, multiple of NXT
@@ -186,6 +195,7 @@ __device__ __forceinline__ RowTile row_tile(int nx, int ny) {
 }
 
 // y = cf x (or b - cf x) on the tile; cf[a][o] holds node x0 + a's row.
+template <int NXT>
 __device__ __forceinline__ void tile_product(const RowTile& t, int nx, int ny, int nz, int nrhs,
                                              const z64 (*cf)[27], const z64* __restrict__ x, z64* __restrict__ y,
                                              const z64* __restrict__ b) {
@@ -221,10 +231,11 @@ __device__ __forceinline__ void tile_product(const RowTile& t, int nx, int ny, i
   }
 }
 
+template <int NXT>
 __global__ void __launch_bounds__(256) k_stencil_rows(OpDev op, int nrhs, const z64* __restrict__ x,
                                                       z64* __restrict__ y, const z64* __restrict__ b) {
   __shared__ z64 cf[TW][27];
-  const RowTile t = row_tile(op.nx, op.ny);
+  const RowTile t = row_tile<NXT>(op.nx, op.ny);
   // phase 1: four lanes per node, offsets o = q, q + 4, ...; the stiffness sum
   // of the diagonal is reduced over the four lanes
   const int a = threadIdx.x >> 2, q = threadIdx.x & 3;
@@ -255,13 +266,14 @@ __global__ void __launch_bounds__(256) k_stencil_rows(OpDev op, int nrhs, const 
   ssum.im += __shfl_xor(ssum.im, 2);
   if (q == 0 && a < TW) cf[a][13] = a < t.w ? op.wm[0] * si - ssum : mk(0.0, 0.0);
   __syncthreads();
-  tile_product(t, op.nx, op.ny, op.nz, nrhs, cf, x, y, b);
+  tile_product<NXT>(t, op.nx, op.ny, op.nz, nrhs, cf, x, y, b);
 }
 
+template <int NXT>
 __global__ void __launch_bounds__(256) k_coarse_spmv_rows(int ncx, int ncy, int ncz, const z64* __restrict__ E,
                                                           int nrhs, const z64* __restrict__ x, z64* __restrict__ y) {
   __shared__ z64 cf[TW][27];
-  const RowTile t = row_tile(ncx, ncy);
+  const RowTile t = row_tile<NXT>(ncx, ncy);
   const long long rowi = (long long)ncx * (t.iy + (long long)ncy * t.iz);
   for (int e = threadIdx.x; e < TW * 27; e += blockDim.x) {
     const int a = e / 27, o = e % 27;
@@ -273,18 +285,21 @@ __global__ void __launch_bounds__(256) k_coarse_spmv_rows(int ncx, int ncy, int 
     cf[a][o] = c;
   }
   __syncthreads();
-  tile_product(t, ncx, ncy, ncz, nrhs, cf, x, y, nullptr);
+  tile_product<NXT>(t, ncx, ncy, ncz, nrhs, cf, x, y, nullptr);
 }
 
-// E[I][o] = sum_i sum_j Z[i,I] A[i,j] Z[j,I+o]
-__global__ void k_build_E(OpDev op, int ncx, int ncy, int ncz, z64* __restrict__ E) {
+// E[I][o] = sum_i sum_j Z[i,I] A[i,j] Z[j,I+o]; one thread per coarse node I,
+// its 27 sums in LDS (indexed at run time), the fine row in registers.
+constexpr int BUILD_E_BLOCK = 64;
+__global__ void __launch_bounds__(BUILD_E_BLOCK) k_build_E(OpDev op, int ncx, int ncy, int ncz, z64* __restrict__ E) {
+  __shared__ z64 acc_s[BUILD_E_BLOCK][27];
   const long long nc = (long long)ncx * ncy * ncz;
   const long long I = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (I >= nc) return;
   const int cx = (int)(I % ncx);
   const int cy = (int)((I / ncx) % ncy);
   const int cz = (int)(I / ((long long)ncx * ncy));
-  z64 acc[27];
+  z64* acc = acc_s[threadIdx.x];
   for (int o = 0; o < 27; ++o) acc[o] = mk(0.0, 0.0);
   z64 row[27];
   for (int dz = -1; dz <= 1; ++dz) {
@@ -298,6 +313,7 @@ __global__ void k_build_E(OpDev op, int ncx, int ncy, int ncz, z64* __restrict__
         if (ix < 0 || ix >= op.nx) continue;
         const double wi = (dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0);
         fine_row(op, ix, iy, iz, row);
+#pragma unroll
         for (int o = 0; o < 27; ++o) {
           const int jx = ix + o % 3 - 1, jy = iy + (o / 3) % 3 - 1, jz = iz + o / 9 - 1;
           if (jx < 0 || jx >= op.nx || jy < 0 || jy >= op.ny || jz < 0 || jz >= op.nz) continue;
@@ -456,9 +472,92 @@ static unsigned row_tiles(int nx, int ny, int nz) {
   return (unsigned)((long long)((nx + TW - 1) / TW) * ny * nz);
 }
 
+// Autotuned nodes per thread of the row-tiled products, per grid and batch:
+// every candidate is timed twice on the live input at the first application
+// outside a stream capture (the products are idempotent) and the fastest kept.
+namespace {
+struct RowKey {
+  int kind, nx, ny, nz, nrhs;
+  bool operator<(const RowKey& o) const {
+    return std::tie(kind, nx, ny, nz, nrhs) < std::tie(o.kind, o.nx, o.ny, o.nz, o.nrhs);
+  }
+};
+std::mutex g_row_mu;
+std::map<RowKey, int> g_row_tune;
+std::atomic<int> g_row_forced{0};
+
+bool row_no_tune() {
+  static const bool v = std::getenv("HELM_NO_TUNE") != nullptr;
+  return v;
+}
+
+bool row_untuned(const RowKey& key) {
+  if (key.nrhs < 4 || row_no_tune() || g_row_forced.load() != 0) return false;
+  std::lock_guard<std::mutex> lk(g_row_mu);
+  return g_row_tune.find(key) == g_row_tune.end();
+}
+
+template <typename Launch>
+int tuned_nxt(const RowKey& key, hipStream_t s, Launch&& launch) {
+  if (const int f = g_row_forced.load()) return f;
+  {
+    std::lock_guard<std::mutex> lk(g_row_mu);
+    auto it = g_row_tune.find(key);
+    if (it != g_row_tune.end()) return it->second;
+  }
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  (void)hipStreamIsCapturing(s, &cap);
+  if (row_no_tune() || cap != hipStreamCaptureStatusNone) return 4;
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  int bestn = 4;
+  float best = 1e30f;
+  for (int nxt : {2, 4, 8}) {
+    float tot = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {
+      (void)hipEventRecord(e0, s);
+      launch(nxt);
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) tot += ms;
+    }
+    if (tot < best) {
+      best = tot;
+      bestn = nxt;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  static const bool verbose = std::getenv("HELM_TUNE_VERBOSE") != nullptr;
+  if (verbose)
+    std::fprintf(stderr, "helm: %s tuned (%dx%dx%d, %d rhs): %d nodes per thread, %.3f ms\n",
+                 key.kind ? "coarse product" : "stencil", key.nx, key.ny, key.nz, key.nrhs, bestn, best);
+  std::lock_guard<std::mutex> lk(g_row_mu);
+  g_row_tune[key] = bestn;
+  return bestn;
+}
+}  // namespace
+
+bool stencil_untuned(const OpDev& op, int nrhs) { return row_untuned({0, op.nx, op.ny, op.nz, nrhs}); }
+bool coarse_spmv_untuned(int ncx, int ncy, int ncz, int nrhs) { return row_untuned({1, ncx, ncy, ncz, nrhs}); }
+bool set_row_tiling(int nxt) {
+  if (nxt != 0 && nxt != 2 && nxt != 4 && nxt != 8) return false;
+  g_row_forced.store(nxt);
+  return true;
+}
+
 static void stencil_dispatch(const OpDev& op, int nrhs, const z64* x, z64* y, const z64* b, hipStream_t s) {
-  if (nrhs >= NXT) {
-    hipLaunchKernelGGL(k_stencil_rows, dim3(row_tiles(op.nx, op.ny, op.nz)), dim3(256), 0, s, op, nrhs, x, y, b);
+  if (nrhs >= 4) {
+    const dim3 grid(row_tiles(op.nx, op.ny, op.nz));
+    auto launch = [&](int nxt) {
+      if (nxt == 2) hipLaunchKernelGGL(k_stencil_rows<2>, grid, dim3(256), 0, s, op, nrhs, x, y, b);
+      else if (nxt == 8) hipLaunchKernelGGL(k_stencil_rows<8>, grid, dim3(256), 0, s, op, nrhs, x, y, b);
+      else hipLaunchKernelGGL(k_stencil_rows<4>, grid, dim3(256), 0, s, op, nrhs, x, y, b);
+    };
+    launch(tuned_nxt({0, op.nx, op.ny, op.nz, nrhs}, s, launch));
     return;
   }
   const long long n = (long long)op.nx * op.ny * op.nz;
@@ -477,14 +576,20 @@ void launch_residual(const OpDev& op, int nrhs, const z64* b, const z64* x, z64*
 
 void launch_build_E(const OpDev& op, int ncx, int ncy, int ncz, z64* E, hipStream_t s) {
   const long long nc = (long long)ncx * ncy * ncz;
-  hipLaunchKernelGGL(k_build_E, dim3((unsigned)ceil_div(nc, 64)), dim3(64), 0, s, op, ncx, ncy, ncz, E);
+  hipLaunchKernelGGL(k_build_E, dim3((unsigned)ceil_div(nc, BUILD_E_BLOCK)), dim3(BUILD_E_BLOCK), 0, s, op, ncx, ncy,
+                     ncz, E);
 }
 
 void launch_coarse_spmv(int ncx, int ncy, int ncz, const z64* E, int nrhs, const z64* x, z64* y,
                         hipStream_t s) {
-  if (nrhs >= NXT) {
-    hipLaunchKernelGGL(k_coarse_spmv_rows, dim3(row_tiles(ncx, ncy, ncz)), dim3(256), 0, s, ncx, ncy, ncz, E, nrhs, x,
-                       y);
+  if (nrhs >= 4) {
+    const dim3 grid(row_tiles(ncx, ncy, ncz));
+    auto launch = [&](int nxt) {
+      if (nxt == 2) hipLaunchKernelGGL(k_coarse_spmv_rows<2>, grid, dim3(256), 0, s, ncx, ncy, ncz, E, nrhs, x, y);
+      else if (nxt == 8) hipLaunchKernelGGL(k_coarse_spmv_rows<8>, grid, dim3(256), 0, s, ncx, ncy, ncz, E, nrhs, x, y);
+      else hipLaunchKernelGGL(k_coarse_spmv_rows<4>, grid, dim3(256), 0, s, ncx, ncy, ncz, E, nrhs, x, y);
+    };
+    launch(tuned_nxt({1, ncx, ncy, ncz, nrhs}, s, launch));
     return;
   }
   const long long nc = (long long)ncx * ncy * ncz;

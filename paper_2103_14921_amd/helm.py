@@ -27,6 +27,7 @@ EXPORTS = [
     "helm_num_subdomains", "helm_subdomain_box", "helm_set_sweep_timing", "helm_sweep_stats",
     "helm_local_solve", "helm_release_workspace", "helm_trim_cache", "helm_set_graphs", "helm_graph_stats",
     "helm_set_sweep_policy",
+    "helm_set_row_tiling",
 ]
 
 
@@ -100,6 +101,7 @@ def _load():
         "helm_set_graphs": ([P, i32], C.c_int),
         "helm_graph_stats": ([P, C.POINTER(C.c_double)], C.c_int),
         "helm_set_sweep_policy": ([i32], C.c_int),
+        "helm_set_row_tiling": ([i32], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -172,6 +174,11 @@ SWEEP_POLICIES = {"auto": 0, "item": 1, "pipelined": 2}
 def set_sweep_policy(policy):
     """Process-wide choice of local-solve sweep: "auto" (tuned), "item" or "pipelined"."""
     _check(lib.helm_set_sweep_policy(SWEEP_POLICIES[policy]))
+
+
+def set_row_tiling(nodes_per_thread):
+    """Process-wide nodes per thread of the 27-point products: 0 (autotuned), 2, 4 or 8."""
+    _check(lib.helm_set_row_tiling(int(nodes_per_thread)))
 
 
 def footprint(shape, parts, overlap=2, levels=1, coarse_iters=10, precision="fp64", restart=30, nrhs_chunk=1):

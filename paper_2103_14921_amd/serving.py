@@ -10,7 +10,11 @@ library handle and HIP stream, so solves of different problems overlap on the
 device.  Requests for the same problem and tolerance that are waiting when
 the problem's handle becomes free are merged into one batched solve (one
 Krylov space per right-hand side, so each result is the same as when solved
-alone, up to rounding).  Latency = completion time - arrival time.
+alone, up to rounding).  Solutions come back where the right-hand sides were
+(host arrays for host arrays, device tensors for device tensors), so results
+held by callers take no device memory from the admission budget unless the
+caller chose device inputs.  Latency = completion time - arrival time,
+including the copy of the solutions back.
 
 Only orchestration lives here; every arithmetic step runs in the HIP library.
 """
@@ -233,17 +237,27 @@ class Server:
             Bd = helm.torch_alloc(stage)
             X, info = e.solver.solve(Bd, tol=batch[0].tol, maxit=batch[0].maxit)
             e.solver.release_workspace()
+            del Bd
+            # a request gets X where its B was: host arrays come back as host
+            # arrays, so delivered results hold no device memory outside the
+            # admission accounting
+            outs, i0 = [], 0
+            for r in batch:
+                Xr = X[i0:i0 + r.nrhs]
+                i0 += r.nrhs
+                outs.append(Xr.clone() if helm._is_torch(r.B) else Xr.cpu().numpy())
+            del X
             done = time.perf_counter()
             i0 = 0
             with self._cv:
                 self.stats.batches += 1
                 self.stats.rhs += nr
-                for r in batch:
+                for r, Xr in zip(batch, outs):
                     sl = slice(i0, i0 + r.nrhs)
                     i0 += r.nrhs
                     lat = done - r.arrival
                     self.stats.latencies.append(lat)
-                    r.future.set_result({"X": X[sl], "iters": info["iters"][sl], "relres_true": info["relres_true"][sl],
+                    r.future.set_result({"X": Xr, "iters": info["iters"][sl], "relres_true": info["relres_true"][sl],
                                          "status": info["status"], "latency_s": lat, "batch_rhs": nr})
         except Exception as exc:  # report the failure on every request of the batch
             with self._cv:
@@ -277,11 +291,13 @@ def run_poisson(server, requests, rate_hz, seed=4, progress=None):
         futs.append(server.submit(spec, B, tol))
     results = []
     for i, f in enumerate(futs):
-        results.append(f.result())
+        r = dict(f.result())
+        r["nrhs"] = int(r.pop("X").shape[0])  # the stream's figures need no solutions
+        results.append(r)
         if progress:
             progress(i + 1, len(futs))
     elapsed = time.perf_counter() - t0
-    rhs = sum(int(r["X"].shape[0]) for r in results)
+    rhs = sum(r["nrhs"] for r in results)
     out = {"elapsed_s": elapsed, "rhs": rhs, "rhs_per_s": rhs / elapsed, "requests": len(results),
            "results": results}
     out.update(server.latency_percentiles())

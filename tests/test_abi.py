@@ -49,3 +49,13 @@ def test_footprint_grows_with_rhs_and_rejects_bad_decomposition():
     assert 0 < a < b
     # boxes thinner than 2*overlap+1 are rejected (footprint 0)
     assert helm.footprint((16, 16, 16), (8, 1, 1)) == 0
+
+
+def test_process_wide_settings_reject_bad_values():
+    from paper_2103_14921_amd import helm
+    for bad in (1, 3, 16, -2):
+        with pytest.raises(helm.HelmError) as e:
+            helm.set_row_tiling(bad)
+        assert e.value.code == helm.HELM_EINVAL
+    assert helm.lib.helm_set_sweep_policy(3) == helm.HELM_EINVAL
+    helm.set_row_tiling(0)

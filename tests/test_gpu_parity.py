@@ -114,6 +114,35 @@ def test_coarse_operator_batches_match_oracle(nrhs):
     S.close()
 
 
+def test_row_tilings_agree_bitwise():
+    # the fine and coarse 27-point products under each forced tiling (2, 4, 8
+    # nodes per thread) and the autotuned one: every tiling matches the oracle
+    # and all are bitwise equal; 70 nodes per row leave a ragged second tile
+    shape, h, c, f, pml = _thrust_case(shape=(70, 13, 11), pml=(3, 3, 3, 0))
+    say("row tilings", shape)
+    prob = Problem(shape, h, c, f, Pml(*pml), WO)
+    A = assemble(prob)
+    tl = TwoLevel(A, shape, decompose(shape, (2, 1, 1), 2), prob.k().ravel(), h, 2)
+    hm = helm()
+    S = hm.Solver(shape, h, c, f, pml, weights=W, parts=(2, 1, 1), overlap=2, levels=2)
+    X = inputs.random_field((12, prob.n), seed=55)
+    Cc = inputs.random_field((9, S.nc), seed=56)
+    ref, refE = (A @ X.T).T, (tl.E @ Cc.T).T
+    outs = []
+    try:
+        for nxt in (2, 4, 8, 0):
+            hm.set_row_tiling(nxt)
+            Y, E = S.apply_A(X), S.apply_E(Cc)
+            assert np.max(np.abs(Y - ref)) <= 1e-12 * np.max(np.abs(ref)), nxt
+            assert rel(E, refE) <= 1e-12, nxt
+            outs.append((Y, E))
+    finally:
+        hm.set_row_tiling(0)
+    for Y, E in outs[1:]:
+        assert np.array_equal(Y, outs[0][0]) and np.array_equal(E, outs[0][1])
+    S.close()
+
+
 def test_config1_end_to_end_parity():
     # 24^3, h = 50 m, c = 1500 + 0.7 z, 3.75 Hz, 6-node PML on sides and bottom,
     # one-level ORAS 2x2x2, overlap 2, FGMRES(30), tol 1e-8, one source at (12, 12, 4)
