@@ -171,6 +171,15 @@ helm_status helm_set_sweep_policy(int32_t policy);
  * HELM_EINVAL for any other value. */
 helm_status helm_set_row_tiling(int32_t nodes_per_thread);
 
+/* Process-wide panel width of the blocked Gauss-Jordan inversion of the plane
+ * Schur complements (the local factorisation of eq. oras, done by set-up):
+ * 0 (default) times the admissible widths on the first plane of each new
+ * (precision, plane size, box count) and keeps the fastest; 4, 8 or 16 forces
+ * that width wherever it is admissible (16 or 8 for planes of up to 512 rows,
+ * 8 or 4 above).  Widths change only the rounding of the inverses.  Returns
+ * HELM_EINVAL for any other value. */
+helm_status helm_set_lu_panel(int32_t columns);
+
 /* Return the handle's cached Krylov workspace (sized for its last batch) to
  * the library's device cache, keeping operators and factors resident: lets a
  * server hold many set-up problems and pay workspace only while solving. */

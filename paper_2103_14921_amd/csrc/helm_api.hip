@@ -1282,6 +1282,11 @@ helm_status helm_set_row_tiling(int32_t nodes_per_thread) {
   return HELM_OK;
 }
 
+helm_status helm_set_lu_panel(int32_t columns) {
+  if (!set_lu_panel(columns)) return fail(HELM_EINVAL, "panel width must be 0, 4, 8 or 16");
+  return HELM_OK;
+}
+
 helm_status helm_graph_stats(const helm_handle_t* H, double out[2]) {
   if (!H || !out) return fail(HELM_EINVAL, "null argument");
   out[0] = H->graph_stat[0];

@@ -62,6 +62,10 @@ struct Factor {
                     int gnx, int gny, cpx<T>* yloc, cpx<T>* tbuf, hipStream_t s);
 };
 
+// Panel width (columns) of the blocked Gauss-Jordan plane inversion: 0 =
+// autotuned per shape, else 4, 8 or 16 wherever admissible for the plane size.
+bool set_lu_panel(int nb);
+
 // Fused single-launch ORAS local solves on matrix cores (ops_sweep.hip).
 // Returns false when the plane does not fit the kernel's LDS budget.
 template <typename T>

@@ -13,7 +13,12 @@
 // Absorbing interface (Robin fold): for a box node l with a grid neighbour j
 // outside the box, A_i[l, l] += A[l, j] (1 + i k_l h) -- the ghost value is
 // replaced by the first-order outgoing condition u_j ~ (1 + i k h) u_l.
+#include <atomic>
+#include <cstdio>
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "kernels.h"
 #include "mfma.h"
@@ -702,21 +707,138 @@ void gj_panels(const Sub* subs, int nsub, int bpmax, int k, cpx<T>* S, cpx<T>* R
 }
 }  // namespace
 
+namespace {
+// Panel widths admissible for rows-per-thread R (the panel lives in registers,
+// R x NB complex entries per thread): the first is the default.
+int gj_candidates(int R, int (&nb)[2]) {
+  if (R <= 2) {
+    nb[0] = 16;
+    nb[1] = 8;
+  } else {
+    nb[0] = 8;
+    nb[1] = 4;
+  }
+  return 2;
+}
+
+// planes of up to 512 rows (R <= 2) and of up to 2048 rows (R = 4, 6, 8)
+template <typename T, int NB>
+void gj_small(int R, const Sub* subs, int nsub, int bpmax, int k, cpx<T>* S, cpx<T>* Rbuf, cpx<T>* R64, int* piv,
+              int* err, hipStream_t s) {
+  if (R <= 1) gj_panels<T, NB, 1>(subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
+  else gj_panels<T, NB, 2>(subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
+}
+template <typename T, int NB>
+void gj_large(int R, const Sub* subs, int nsub, int bpmax, int k, cpx<T>* S, cpx<T>* Rbuf, cpx<T>* R64, int* piv,
+              int* err, hipStream_t s) {
+  if (R <= 4) gj_panels<T, NB, 4>(subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
+  else if (R <= 6) gj_panels<T, NB, 6>(subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
+  else gj_panels<T, NB, 8>(subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
+}
+
+template <typename T>
+void gj_dispatch(int nb, const Sub* subs, int nsub, int bpmax, int k, cpx<T>* S, cpx<T>* Rbuf, cpx<T>* R64, int* piv,
+                 int* err, hipStream_t s) {
+  const int R = (int)ceil_div(bpmax, 256);
+  if (R <= 2) {
+    if (nb == 8) gj_small<T, 8>(R, subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
+    else gj_small<T, 16>(R, subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
+  } else {
+    if (nb == 4) gj_large<T, 4>(R, subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
+    else gj_large<T, 8>(R, subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
+  }
+}
+
+// Autotuned panel width of the blocked Gauss-Jordan inversion, per (precision,
+// padded plane size, number of boxes): every admissible width is timed twice on
+// the first plane (its factorisation is recomputed from the local rows, so
+// repeating it changes nothing) and the fastest kept.
+struct GjKey {
+  int es, bpmax, nsub;
+  bool operator<(const GjKey& o) const { return std::tie(es, bpmax, nsub) < std::tie(o.es, o.bpmax, o.nsub); }
+};
+std::mutex g_gj_mu;
+std::map<GjKey, int> g_gj_tune;
+std::atomic<int> g_gj_forced{0};
+}  // namespace
+
+bool set_lu_panel(int nb) {
+  if (nb != 0 && nb != 4 && nb != 8 && nb != 16) return false;
+  g_gj_forced.store(nb);
+  return true;
+}
+
+namespace {
+// Width for this shape: forced (where admissible), tuned, or the default.
+template <typename T>
+int gj_width(int bpmax, int nsub) {
+  int nb[2];
+  const int nc = gj_candidates((int)ceil_div(bpmax, 256), nb);
+  if (const int f = g_gj_forced.load())
+    for (int i = 0; i < nc; ++i)
+      if (nb[i] == f) return f;
+  std::lock_guard<std::mutex> lk(g_gj_mu);
+  auto it = g_gj_tune.find({(int)sizeof(T), bpmax, nsub});
+  return it == g_gj_tune.end() ? nb[0] : it->second;
+}
+}  // namespace
+
 template <typename T>
 void Factor<T>::plane(const Sub* subs, int nsub, int bpmax, int k, const z64* aloc, cpx<T>* sinv, cpx<T>* W,
                       cpx<T>* S, cpx<T>* Rbuf, cpx<T>* R64, int* piv, int* perm, int* err, hipStream_t s) {
   const long long cells = (long long)bpmax * bpmax;
   dim3 grid((unsigned)ceil_div(cells, 256), nsub);
-  if (k >= 1) hipLaunchKernelGGL(k_schur_W<T>, grid, dim3(256), 0, s, subs, k, bpmax, aloc, sinv, W);
-  hipLaunchKernelGGL(k_schur_S<T>, grid, dim3(256), 0, s, subs, k, bpmax, aloc, W, S);
-  const int R = (int)ceil_div(bpmax, 256);
-  if (R <= 1) gj_panels<T, 16, 1>(subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
-  else if (R <= 2) gj_panels<T, 16, 2>(subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
-  else if (R <= 4) gj_panels<T, 8, 4>(subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
-  else if (R <= 6) gj_panels<T, 8, 6>(subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
-  else gj_panels<T, 8, 8>(subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
-  hipLaunchKernelGGL(k_gj_perm, dim3((unsigned)ceil_div(nsub, 64)), dim3(64), 0, s, subs, nsub, k, bpmax, piv, perm);
-  hipLaunchKernelGGL(k_gj_final<T>, grid, dim3(256), 0, s, subs, k, bpmax, S, perm, sinv);
+  auto factor_with = [&](int nb) {
+    if (k >= 1) hipLaunchKernelGGL(k_schur_W<T>, grid, dim3(256), 0, s, subs, k, bpmax, aloc, sinv, W);
+    hipLaunchKernelGGL(k_schur_S<T>, grid, dim3(256), 0, s, subs, k, bpmax, aloc, W, S);
+    gj_dispatch<T>(nb, subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
+    hipLaunchKernelGGL(k_gj_perm, dim3((unsigned)ceil_div(nsub, 64)), dim3(64), 0, s, subs, nsub, k, bpmax, piv,
+                       perm);
+    hipLaunchKernelGGL(k_gj_final<T>, grid, dim3(256), 0, s, subs, k, bpmax, S, perm, sinv);
+  };
+  static const bool no_tune = std::getenv("HELM_NO_TUNE") != nullptr;
+  const GjKey key{(int)sizeof(T), bpmax, nsub};
+  bool tuned;
+  {
+    std::lock_guard<std::mutex> lk(g_gj_mu);
+    tuned = g_gj_tune.count(key) != 0;
+  }
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  (void)hipStreamIsCapturing(s, &cap);
+  if (k == 0 && !tuned && !no_tune && g_gj_forced.load() == 0 && cap == hipStreamCaptureStatusNone) {
+    int nb[2];
+    const int nc = gj_candidates((int)ceil_div(bpmax, 256), nb);
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    int best_nb = nb[0];
+    float best = 1e30f;
+    for (int i = 0; i < nc; ++i) {
+      float tot = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {
+        (void)hipEventRecord(e0, s);
+        factor_with(nb[i]);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) tot += ms;
+      }
+      if (tot < best) {
+        best = tot;
+        best_nb = nb[i];
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    static const bool verbose = std::getenv("HELM_TUNE_VERBOSE") != nullptr;
+    if (verbose)
+      std::fprintf(stderr, "helm: LU panel tuned (fp%d, bp %d, %d boxes): %d columns, %.3f ms per plane\n",
+                   (int)sizeof(T) * 8, bpmax, nsub, best_nb, best);
+    std::lock_guard<std::mutex> lk(g_gj_mu);
+    g_gj_tune[key] = best_nb;
+  }
+  factor_with(gj_width<T>(bpmax, nsub));
 }
 
 template <typename T>

@@ -180,16 +180,27 @@ constexpr int TW = 64;
 struct RowTile {
   int iy, iz, x0, w;
 };
+// Tile order: bands of ROW_BAND grid rows (y), each swept through all planes
+// (z), segments of a row fastest.  The workgroups resident on one XCD then
+// cover a compact (y, z) patch, whose nine neighbour rows per tile largely
+// overlap in that XCD's L2 (plane-by-plane order re-fetches each input row
+// about four times from beyond L2; this order about one and a half).
+constexpr int ROW_BAND = 8;
 template <int NXT>
-__device__ __forceinline__ RowTile row_tile(int nx, int ny) {
+__device__ __forceinline__ RowTile row_tile(int nx, int ny, int nz) {
   const int nt = (nx + TW - 1) / TW;
   const int tw = ((nx + nt - 1) / nt + NXT - 1) / NXT * NXT;  // balanced segment width, multiple of NXT
   const long long lb = xcd_contiguous(blockIdx.x, gridDim.x);
-  const long long row = lb / nt;
+  const long long per_band = (long long)ROW_BAND * nz * nt;
+  const int band = (int)(lb / per_band);
+  long long rem = lb - band * per_band;
+  const int tx = (int)(rem % nt);
+  rem /= nt;
+  const int nyb = min(ROW_BAND, ny - band * ROW_BAND);  // the last band may be narrower
   RowTile t;
-  t.iy = (int)(row % ny);
-  t.iz = (int)(row / ny);
-  t.x0 = (int)(lb % nt) * tw;
+  t.iy = band * ROW_BAND + (int)(rem % nyb);
+  t.iz = (int)(rem / nyb);
+  t.x0 = tx * tw;
   t.w = min(tw, nx - t.x0);
   return t;
 }
@@ -235,7 +246,7 @@ template <int NXT>
 __global__ void __launch_bounds__(256) k_stencil_rows(OpDev op, int nrhs, const z64* __restrict__ x,
                                                       z64* __restrict__ y, const z64* __restrict__ b) {
   __shared__ z64 cf[TW][27];
-  const RowTile t = row_tile<NXT>(op.nx, op.ny);
+  const RowTile t = row_tile<NXT>(op.nx, op.ny, op.nz);
   // phase 1: four lanes per node, offsets o = q, q + 4, ...; the stiffness sum
   // of the diagonal is reduced over the four lanes
   const int a = threadIdx.x >> 2, q = threadIdx.x & 3;
@@ -273,7 +284,7 @@ template <int NXT>
 __global__ void __launch_bounds__(256) k_coarse_spmv_rows(int ncx, int ncy, int ncz, const z64* __restrict__ E,
                                                           int nrhs, const z64* __restrict__ x, z64* __restrict__ y) {
   __shared__ z64 cf[TW][27];
-  const RowTile t = row_tile<NXT>(ncx, ncy);
+  const RowTile t = row_tile<NXT>(ncx, ncy, ncz);
   const long long rowi = (long long)ncx * (t.iy + (long long)ncy * t.iz);
   for (int e = threadIdx.x; e < TW * 27; e += blockDim.x) {
     const int a = e / 27, o = e % 27;

@@ -28,6 +28,7 @@ EXPORTS = [
     "helm_local_solve", "helm_release_workspace", "helm_trim_cache", "helm_set_graphs", "helm_graph_stats",
     "helm_set_sweep_policy",
     "helm_set_row_tiling",
+    "helm_set_lu_panel",
 ]
 
 
@@ -102,6 +103,7 @@ def _load():
         "helm_graph_stats": ([P, C.POINTER(C.c_double)], C.c_int),
         "helm_set_sweep_policy": ([i32], C.c_int),
         "helm_set_row_tiling": ([i32], C.c_int),
+        "helm_set_lu_panel": ([i32], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -179,6 +181,11 @@ def set_sweep_policy(policy):
 def set_row_tiling(nodes_per_thread):
     """Process-wide nodes per thread of the 27-point products: 0 (autotuned), 2, 4 or 8."""
     _check(lib.helm_set_row_tiling(int(nodes_per_thread)))
+
+
+def set_lu_panel(columns):
+    """Process-wide panel width of the local Gauss-Jordan inversions: 0 (autotuned), 4, 8 or 16."""
+    _check(lib.helm_set_lu_panel(int(columns)))
 
 
 def footprint(shape, parts, overlap=2, levels=1, coarse_iters=10, precision="fp64", restart=30, nrhs_chunk=1):

@@ -72,6 +72,33 @@ def test_one_level_oras_matches_oracle(parts, delta, prec, tol):
     S.close()
 
 
+@pytest.mark.parametrize("shape,parts,widths", [((21, 18, 16), (2, 2, 2), (16, 8)),
+                                                 ((44, 44, 8), (2, 2, 1), (8, 4))])
+def test_lu_panel_widths_match_oracle(shape, parts, widths):
+    # every admissible panel width of the plane inversions, forced, and the
+    # autotuned one: one-level ORAS matches the oracle; planes of 576 rows use
+    # the wide-plane widths
+    h, f, pml = 25.0, 10.0, (3, 3, 3, 0)
+    c = inputs.velocity_thrust_belt(*shape, h=h, q=100.0)
+    say("lu panels", shape, parts, widths)
+    prob = Problem(shape, h, c, f, Pml(*pml), WO)
+    A = assemble(prob)
+    M = Oras(A, shape, decompose(shape, parts, 2), prob.k().ravel(), h)
+    R = inputs.random_field((2, prob.n), seed=17)
+    ref = [M.apply(R[r]) for r in range(2)]
+    hm = helm()
+    try:
+        for nb in widths + (0,):
+            hm.set_lu_panel(nb)
+            S = hm.Solver(shape, h, c, f, pml, weights=W, parts=parts, overlap=2, levels=1)
+            Z = S.apply_oras(R)
+            S.close()
+            for r in range(2):
+                assert rel(Z[r], ref[r]) <= 1e-10, (nb, r)
+    finally:
+        hm.set_lu_panel(0)
+
+
 def test_coarse_pieces_match_oracle():
     shape, h, c, f, pml = _thrust_case(shape=(20, 18, 17), pml=(3, 3, 3, 0))
     say("coarse pieces", shape)
