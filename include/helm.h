@@ -40,6 +40,7 @@ extern "C" {
 typedef enum {
   HELM_OK = 0,
   HELM_NOT_CONVERGED = 1, /* some right-hand side reached maxit; residuals are reported */
+  HELM_PENDING = 2,       /* an asynchronous solve is still running (helm_request_query) */
   HELM_EINVAL = -1,       /* bad sizes or values (non-finite, Re c <= 0, boxes too small) */
   HELM_ENOMEM = -2,       /* device footprint exceeds the memory budget */
   HELM_EDEVICE = -3,      /* HIP runtime error or no device */
@@ -116,6 +117,30 @@ enum { HELM_X0 = 1u /* X holds the initial guess on entry */ };
 helm_status helm_solve(helm_handle_t* h, int32_t nrhs, const void* B, void* X, double tol,
                        int32_t maxit, uint32_t flags, int32_t* iters, double* relres_est,
                        double* relres_true);
+
+/* Asynchronous form of helm_solve for callers that overlap solves of several
+ * handles (continuous batching of a serving loop): the arguments are checked
+ * at once, then the solve runs on a library thread with the handle's device
+ * current, in the same order of device work as helm_solve on the handle's
+ * stream, so its results are bitwise those of helm_solve.  B, X and the result
+ * arrays belong to the caller and must stay valid until helm_request_wait
+ * returns.  One solve at a time per handle: helm_solve, helm_solve_async and
+ * helm_release_workspace on a handle with a request in flight return
+ * HELM_EINVAL; helm_destroy waits for it (the request stays valid for
+ * helm_request_wait, which must not run concurrently with helm_destroy of the
+ * same handle).  On success *req receives a request that the caller must pass
+ * to helm_request_wait exactly once. */
+typedef struct helm_request helm_request_t;
+helm_status helm_solve_async(helm_handle_t* h, int32_t nrhs, const void* B, void* X, double tol,
+                             int32_t maxit, uint32_t flags, int32_t* iters, double* relres_est,
+                             double* relres_true, helm_request_t** req);
+/* HELM_PENDING while the solve runs, then its helm_solve status (the request
+ * stays valid). */
+helm_status helm_request_query(const helm_request_t* req);
+/* Block until the solve has finished, free the request and return its
+ * helm_solve status; on failure helm_last_error (in the calling thread) holds
+ * the solve's message. */
+helm_status helm_request_wait(helm_request_t* req);
 
 /* Device bytes the handle needs for this grid and decomposition plus the
  * Krylov workspace of nrhs_chunk right-hand sides (admission control). */

@@ -4,6 +4,7 @@
 // ops_operator.hip, ops_local.hip and ops_krylov.hip.
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -13,6 +14,7 @@
 #include <new>
 #include <mutex>
 #include <stdexcept>
+#include <thread>
 #include <vector>
 
 #include "../../include/helm.h"
@@ -379,6 +381,9 @@ struct helm_handle {
   std::vector<std::unique_ptr<Captured>> captured;
   Captured* capturing = nullptr;
   double graph_stat[2] = {0, 0};  // captures, replays
+  // the asynchronous solve in flight, if any (helm_solve_async)
+  helm_request* pending = nullptr;
+  std::mutex pending_mu;
 
   ~helm_handle() {
     captured.clear();
@@ -1134,7 +1139,36 @@ helm_status helm_setup(const helm_grid_t* grid, const void* velocity, double fre
   });
 }
 
-helm_status helm_solve(helm_handle_t* H, int32_t nrhs, const void* B, void* X, double tol, int32_t maxit,
+struct helm_request {
+  std::atomic<helm_handle*> H{nullptr};  // null once helm_destroy has joined the solve
+  std::thread worker;
+  std::atomic<bool> done{false};
+  std::atomic<int> status{HELM_PENDING};
+  std::string message;
+  bool joined = false;  // guarded by H->pending_mu
+};
+
+namespace {
+bool busy(helm_handle* H) {
+  std::lock_guard<std::mutex> lk(H->pending_mu);
+  return H->pending != nullptr;
+}
+// Join the handle's in-flight request (if any) and detach it from the handle.
+void finish_pending(helm_handle* H) {
+  std::lock_guard<std::mutex> lk(H->pending_mu);
+  helm_request* q = H->pending;
+  if (!q) return;
+  if (!q->joined) {
+    q->worker.join();
+    q->joined = true;
+  }
+  q->H.store(nullptr);
+  H->pending = nullptr;
+}
+}  // namespace
+
+namespace {
+helm_status solve_impl(helm_handle* H, int32_t nrhs, const void* B, void* X, double tol, int32_t maxit,
                        uint32_t flags, int32_t* iters, double* relres_est, double* relres_true) {
   return guarded([&]() {
     if (!H || !B || !X || nrhs < 0 || !(tol >= 0) || maxit < 0) throw HelmError(HELM_EINVAL, "bad solve arguments");
@@ -1192,6 +1226,13 @@ helm_status helm_solve(helm_handle_t* H, int32_t nrhs, const void* B, void* X, d
     return all_conv ? HELM_OK : HELM_NOT_CONVERGED;
   });
 }
+}  // namespace
+
+helm_status helm_solve(helm_handle_t* H, int32_t nrhs, const void* B, void* X, double tol, int32_t maxit,
+                       uint32_t flags, int32_t* iters, double* relres_est, double* relres_true) {
+  if (H && busy(H)) return fail(HELM_EINVAL, "a solve is already in flight on this handle");
+  return solve_impl(H, nrhs, B, X, tol, maxit, flags, iters, relres_est, relres_true);
+}
 
 size_t helm_footprint(const helm_grid_t* grid, const helm_decomp_t* dec, int32_t nrhs_chunk) {
   try {
@@ -1227,8 +1268,64 @@ helm_status helm_last_timings(const helm_handle_t* H, double out[5]) {
   return HELM_OK;
 }
 
+helm_status helm_solve_async(helm_handle_t* H, int32_t nrhs, const void* B, void* X, double tol, int32_t maxit,
+                             uint32_t flags, int32_t* iters, double* relres_est, double* relres_true,
+                             helm_request_t** req) {
+  return guarded([&]() {
+    if (!H || !B || !X || !req || nrhs < 0 || !(tol >= 0) || maxit < 0)
+      throw HelmError(HELM_EINVAL, "bad solve arguments");
+    std::lock_guard<std::mutex> lk(H->pending_mu);
+    if (H->pending) throw HelmError(HELM_EINVAL, "a solve is already in flight on this handle");
+    auto q = std::make_unique<helm_request>();
+    q->H = H;
+    helm_request* qp = q.get();
+    H->pending = qp;
+    try {
+      qp->worker = std::thread([=]() {
+        helm_status st;
+        if (hipSetDevice(H->device) != hipSuccess) {
+          (void)hipGetLastError();
+          st = fail(HELM_EDEVICE, "hipSetDevice failed on the solve thread");
+        } else {
+          st = solve_impl(H, nrhs, B, X, tol, maxit, flags, iters, relres_est, relres_true);
+        }
+        if (st != HELM_OK && st != HELM_NOT_CONVERGED) qp->message = g_last_error;
+        qp->status.store(st);
+        qp->done.store(true);
+      });
+    } catch (...) {
+      H->pending = nullptr;
+      throw HelmError(HELM_EDEVICE, "could not start the solve thread");
+    }
+    *req = q.release();
+    return HELM_OK;
+  });
+}
+
+helm_status helm_request_query(const helm_request_t* q) {
+  if (!q) return fail(HELM_EINVAL, "null request");
+  return q->done.load() ? (helm_status)q->status.load() : HELM_PENDING;
+}
+
+helm_status helm_request_wait(helm_request_t* q) {
+  if (!q) return fail(HELM_EINVAL, "null request");
+  if (helm_handle* H = q->H.load()) {  // else helm_destroy already joined the solve
+    std::lock_guard<std::mutex> lk(H->pending_mu);
+    if (!q->joined) {
+      q->worker.join();
+      q->joined = true;
+    }
+    if (H->pending == q) H->pending = nullptr;
+  }
+  const helm_status st = (helm_status)q->status.load();
+  if (st != HELM_OK && st != HELM_NOT_CONVERGED) g_last_error = q->message;
+  delete q;
+  return st;
+}
+
 void helm_destroy(helm_handle_t* H) {
   if (!H) return;
+  finish_pending(H);  // a request still owned by the caller stays valid for helm_request_wait
   // the handle's device work is ordered on its stream
   if (H->stream) (void)hipStreamSynchronize(H->stream);
   collect_sweep_timing(H);
@@ -1245,6 +1342,7 @@ size_t helm_trim_cache(void) {
 helm_status helm_release_workspace(helm_handle_t* H) {
   return guarded([&]() {
     if (!H) throw HelmError(HELM_EINVAL, "null handle");
+    if (busy(H)) throw HelmError(HELM_EINVAL, "a solve is in flight on this handle");
     HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
     drop_graphs(H);
     ++H->ws_gen;

@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhelm.so")
 
-HELM_OK, HELM_NOT_CONVERGED = 0, 1
+HELM_OK, HELM_NOT_CONVERGED, HELM_PENDING = 0, 1, 2
 HELM_EINVAL, HELM_ENOMEM, HELM_EDEVICE, HELM_EBREAKDOWN = -1, -2, -3, -4
 HELM_FP64, HELM_MIXED = 0, 1
 HELM_X0 = 1
@@ -29,6 +29,7 @@ EXPORTS = [
     "helm_set_sweep_policy",
     "helm_set_row_tiling",
     "helm_set_lu_panel",
+    "helm_solve_async", "helm_request_query", "helm_request_wait",
 ]
 
 
@@ -104,6 +105,9 @@ def _load():
         "helm_set_sweep_policy": ([i32], C.c_int),
         "helm_set_row_tiling": ([i32], C.c_int),
         "helm_set_lu_panel": ([i32], C.c_int),
+        "helm_solve_async": ([P, i32, P, P, C.c_double, i32, C.c_uint32, P, P, P, C.POINTER(C.c_void_p)], C.c_int),
+        "helm_request_query": ([P], C.c_int),
+        "helm_request_wait": ([P], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -168,6 +172,40 @@ def _empty_like_kind(a, shape):
         import torch
         return torch_alloc(lambda: torch.empty(shape, dtype=torch.complex128, device=a.device))
     return np.empty(shape, dtype=np.complex128)
+
+
+class Request:
+    """An asynchronous solve in flight (Solver.solve_async).  It keeps B, X and the
+    result arrays alive until wait() returns."""
+
+    def __init__(self, solver, B, X, nrhs):
+        self.solver, self.B, self.X = solver, B, X
+        self.its = np.zeros(nrhs, np.int32)
+        self.est = np.zeros(nrhs)
+        self.tru = np.zeros(nrhs)
+        self._h = None
+        self._result = None
+
+    def done(self):
+        if self._result is not None:
+            return True
+        return lib.helm_request_query(self._h) != HELM_PENDING
+
+    def wait(self):
+        if self._result is None:
+            h, self._h = self._h, None
+            code = lib.helm_request_wait(h)
+            self._result = (code, last_error())
+            self.B = None
+        code, msg = self._result
+        if code not in (HELM_OK, HELM_NOT_CONVERGED):
+            raise HelmError(code, msg)
+        timings = self.solver.timings() if getattr(self.solver, "_h", None) else None
+        return self.X, dict(status=code, iters=self.its, relres_est=self.est, relres_true=self.tru, timings=timings)
+
+    def __del__(self):
+        if self._result is None and self._h is not None:
+            lib.helm_request_wait(self._h)
 
 
 SWEEP_POLICIES = {"auto": 0, "item": 1, "pipelined": 2}
@@ -246,6 +284,19 @@ class Solver:
                               tru.ctypes.data_as(C.c_void_p))
         _check(code, ok=(HELM_OK, HELM_NOT_CONVERGED))
         return X, dict(status=code, iters=its, relres_est=est, relres_true=tru, timings=self.timings())
+
+    def solve_async(self, B, tol=1e-8, maxit=500, X0=None):
+        """Start the solve of A X = B on a library thread; returns a Request (wait() -> (X, info))."""
+        nrhs = B.shape[0]
+        X = _empty_like_kind(B, tuple(B.shape)) if X0 is None else X0
+        req = Request(self, B, X, nrhs)
+        h = C.c_void_p()
+        _check(lib.helm_solve_async(self._h, nrhs, _ptr(B, nrhs * self.n), _ptr(X, nrhs * self.n), float(tol),
+                                    int(maxit), HELM_X0 if X0 is not None else 0,
+                                    req.its.ctypes.data_as(C.c_void_p), req.est.ctypes.data_as(C.c_void_p),
+                                    req.tru.ctypes.data_as(C.c_void_p), C.byref(h)))
+        req._h = h
+        return req
 
     def timings(self):
         out = (C.c_double * 5)()

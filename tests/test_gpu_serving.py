@@ -85,3 +85,45 @@ def test_admission_respects_the_budget():
     assert all(np.all(r["relres_true"] <= TOL) for r in res)
     assert peak <= budget
     assert evictions >= 1
+
+
+def test_async_solves_overlap_and_match_sync():
+    # helm_solve_async on two handles at once: each result is bitwise the
+    # synchronous result of its handle; a handle with a request in flight
+    # refuses another solve; closing a handle waits for its request
+    import time
+
+    from paper_2103_14921_amd import helm
+    specs, vel = _catalogue()
+    solvers, rhs, ref = [], [], []
+    for spec, seed in zip(specs[:2], (5, 6)):
+        nx, ny, nz = spec.shape
+        S = helm.Solver(spec.shape, spec.h, vel(spec), spec.freq, spec.pml, parts=spec.parts, overlap=2, levels=2,
+                        precision="mixed", restart=20)
+        rng = np.random.default_rng(seed)
+        src = np.stack([rng.integers(6, nx - 6, 3), rng.integers(6, ny - 6, 3), np.full(3, 4)], axis=1)
+        B = inputs.point_source_rhs(nx, ny, nz, src).reshape(3, -1)
+        X, info = S.solve(B, tol=TOL, maxit=200)
+        assert np.all(info["relres_true"] <= TOL)
+        solvers.append(S)
+        rhs.append(B)
+        ref.append(X)
+    print("[case] async pair", flush=True)
+    reqs = [S.solve_async(B, tol=TOL, maxit=200) for S, B in zip(solvers, rhs)]
+    with pytest.raises(helm.HelmError) as e:
+        solvers[0].solve(rhs[0], tol=TOL, maxit=200)
+    assert e.value.code == helm.HELM_EINVAL
+    t0 = time.time()
+    while not all(r.done() for r in reqs):
+        assert time.time() - t0 < 120
+        time.sleep(0.01)
+    for r, X0 in zip(reqs, ref):
+        X, info = r.wait()
+        assert np.array_equal(X, X0)
+        assert np.all(info["relres_true"] <= TOL)
+    print("[case] async close while pending", flush=True)
+    r = solvers[1].solve_async(rhs[1], tol=TOL, maxit=200)
+    solvers[1].close()
+    X, info = r.wait()
+    assert np.array_equal(X, ref[1])
+    solvers[0].close()
