@@ -63,3 +63,36 @@ def test_process_wide_settings_reject_bad_values():
             helm.set_lu_panel(bad)
     helm.set_lu_panel(0)
     helm.set_row_tiling(0)
+
+
+def test_no_kernel_uses_scratch(tmp_path):
+    # every kernel of the built library keeps its state in registers and LDS:
+    # per-wave scratch would be allocated by the runtime at dispatch, where a
+    # failure under memory pressure aborts the queue instead of returning an error
+    import shutil
+    import subprocess
+    objdump, readelf = "/opt/rocm/llvm/bin/llvm-objdump", "/opt/rocm/llvm/bin/llvm-readelf"
+    if not (os.path.exists(objdump) and os.path.exists(readelf)):
+        pytest.skip("ROCm LLVM tools not installed")
+    lib = os.path.join(ROOT, "paper_2103_14921_amd", "libhelm.so")
+    if not os.path.exists(lib):
+        pytest.skip("library not built")
+    shutil.copy(lib, tmp_path / "libhelm.so")
+    subprocess.run([objdump, "--offloading", str(tmp_path / "libhelm.so")], check=True, capture_output=True,
+                   cwd=tmp_path)
+    objs = sorted(p for p in tmp_path.iterdir() if "amdgcn" in p.name and "gfx950" in p.name)
+    assert objs, "no gfx950 code objects in the library"
+    kernels = {}
+    for o in objs:
+        notes = subprocess.run([readelf, "--notes", str(o)], check=True, capture_output=True, text=True).stdout
+        name = None
+        for line in notes.splitlines():
+            s = line.strip()
+            if s.startswith(".name:"):
+                name = s.split(":", 1)[1].strip()
+            elif s.startswith(".private_segment_fixed_size:") and name:
+                kernels[name] = int(s.split(":", 1)[1])
+                name = None
+    assert len(kernels) > 40
+    spilled = {k: v for k, v in kernels.items() if v != 0}
+    assert not spilled, spilled
