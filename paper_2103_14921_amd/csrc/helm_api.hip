@@ -326,7 +326,7 @@ struct KrylovArrays {
 
 struct Workspace {
   int nr = 0;
-  DevBuf b, x, w, V, Zv, q, t, cc, Vc, Zc, wc, ec, yl_f, tb_f, yl_c, tb_c, zpart, dpart, bn2, beta2;
+  DevBuf b, x, w, V, Zv, q, t, cc, Vc, Zc, wc, ec, yl_f, tb_f, yl_c, tb_c, zpart, dpart, bn2, beta2, cols;
   KrylovArrays ko, kc;
 };
 
@@ -591,6 +591,7 @@ void ensure_ws(helm_handle* H, int nr) {
   W.dpart.alloc(sizeof(double) * RED_BLOCKS * (size_t)nr);
   W.bn2.alloc(sizeof(double) * nr);
   W.beta2.alloc(sizeof(double) * nr);
+  W.cols.alloc(sizeof(int) * nr);
   W.ko.alloc(m, nr);
   if (H->two_level()) {
     const int ci = H->dec.coarse_iters;
@@ -886,25 +887,146 @@ void run_outer_step(helm_handle* H, int nr, int j, double tol, int maxit) {
 }
 
 // Batched FGMRES on W.nr right-hand sides held node-major in W.b / W.x.
-void fgmres_chunk(helm_handle* H, int nr, double tol, int maxit, bool x0) {
+// Per-RHS results of a batch column, reported under its index in the chunk.
+struct ChunkOut {
+  std::vector<int> it, conv;
+  std::vector<double> est, tru;
+};
+
+// Hand finished columns `cols` of the current batch (width nr, column c holds
+// the chunk's right-hand side orig[c]) to the caller: per-RHS results into out,
+// solutions field-major into X (chunk offset r0).  The basis storage V is free
+// here and serves as staging.
+void emit_columns(helm_handle* H, int nr, const std::vector<int>& orig, const std::vector<int>& cols, void* X,
+                  int r0, ChunkOut& out) {
   Workspace& W = H->ws;
   KrylovArrays& K = W.ko;
   const long long n = H->n;
-  const long long vs = n * nr;
+  const int nc = (int)cols.size();
+  if (nc == 0) return;
+  std::vector<int> it(nr), conv(nr);
+  std::vector<double> est(nr), beta(nr), bn(nr);
+  HELM_CHECK_HIP(hipMemcpyAsync(it.data(), K.it.p, sizeof(int) * nr, hipMemcpyDeviceToHost, H->stream));
+  HELM_CHECK_HIP(hipMemcpyAsync(conv.data(), K.conv.p, sizeof(int) * nr, hipMemcpyDeviceToHost, H->stream));
+  HELM_CHECK_HIP(hipMemcpyAsync(est.data(), K.est.p, sizeof(double) * nr, hipMemcpyDeviceToHost, H->stream));
+  HELM_CHECK_HIP(hipMemcpyAsync(beta.data(), K.beta.p, sizeof(double) * nr, hipMemcpyDeviceToHost, H->stream));
+  HELM_CHECK_HIP(hipMemcpyAsync(bn.data(), K.bnorm.p, sizeof(double) * nr, hipMemcpyDeviceToHost, H->stream));
+  HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+  bool identity = nc == nr;
+  for (int k = 0; k < nc && identity; ++k) identity = cols[k] == k && orig[k] == k;
+  for (int c : cols) {
+    const int o = orig[c];
+    out.it[o] = it[c];
+    out.conv[o] = conv[c];
+    out.est[o] = est[c];
+    out.tru[o] = bn[c] > 0 ? beta[c] / bn[c] : 0.0;
+  }
+  if (identity) {  // the whole batch in its original order: one transpose and one copy
+    launch_to_field_major(W.x.as<z64>(), W.w.as<z64>(), n, nr, H->stream);
+    HELM_CHECK_HIP(hipMemcpyAsync((char*)X + sizeof(z64) * (size_t)n * r0, W.w.p, sizeof(z64) * (size_t)n * nr,
+                                  hipMemcpyDefault, H->stream));
+    return;
+  }
+  z64* sel = W.V.as<z64>();
+  z64* fm = sel + (long long)n * nc;
+  HELM_CHECK_HIP(hipMemcpyAsync(W.cols.p, cols.data(), sizeof(int) * nc, hipMemcpyHostToDevice, H->stream));
+  launch_gather_cols(W.x.as<z64>(), nr, W.cols.as<int>(), nc, n, sel, H->stream);
+  launch_to_field_major(sel, fm, n, nc, H->stream);
+  for (int k = 0; k < nc; ++k)
+    HELM_CHECK_HIP(hipMemcpyAsync((char*)X + sizeof(z64) * (size_t)n * (r0 + orig[cols[k]]), fm + (long long)n * k,
+                                  sizeof(z64) * (size_t)n, hipMemcpyDefault, H->stream));
+  HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+}
+
+// At a restart some right-hand sides are done: report them and continue with
+// a narrower batch of the rest (x, b and the residual w repacked, the per-RHS
+// Krylov state of the kept columns moved to the front).  Each column's
+// arithmetic is unchanged; only the batch width shrinks.
+void compact_batch(helm_handle* H, int& nr, std::vector<int>& orig, void* X, int r0, ChunkOut& out) {
+  Workspace& W = H->ws;
+  KrylovArrays& K = W.ko;
+  const long long n = H->n;
+  std::vector<int> act(nr);
+  HELM_CHECK_HIP(hipMemcpyAsync(act.data(), K.active.p, sizeof(int) * nr, hipMemcpyDeviceToHost, H->stream));
+  HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+  std::vector<int> keep, done;
+  for (int c = 0; c < nr; ++c) (act[c] ? keep : done).push_back(c);
+  emit_columns(H, nr, orig, done, X, r0, out);
+  const int nk = (int)keep.size();
+  // vectors: gather the kept columns into the (free) basis storage, copy back narrower
+  z64* tmp = W.V.as<z64>();
+  const long long blk = n * nk;
+  HELM_CHECK_HIP(hipMemcpyAsync(W.cols.p, keep.data(), sizeof(int) * nk, hipMemcpyHostToDevice, H->stream));
+  launch_gather_cols(W.x.as<z64>(), nr, W.cols.as<int>(), nk, n, tmp, H->stream);
+  launch_gather_cols(W.b.as<z64>(), nr, W.cols.as<int>(), nk, n, tmp + blk, H->stream);
+  launch_gather_cols(W.w.as<z64>(), nr, W.cols.as<int>(), nk, n, tmp + 2 * blk, H->stream);
+  launch_copy(tmp, W.x.as<z64>(), blk, H->stream);
+  launch_copy(tmp + blk, W.b.as<z64>(), blk, H->stream);
+  launch_copy(tmp + 2 * blk, W.w.as<z64>(), blk, H->stream);
+  // per-RHS state of a fresh cycle: bnorm, beta, est, fac, it and g[0] move, the flags are known
+  std::vector<double> bn(nr), beta(nr), est(nr), fac(nr);
+  std::vector<int> it(nr);
+  std::vector<z64> g0(nr);
+  HELM_CHECK_HIP(hipMemcpyAsync(bn.data(), K.bnorm.p, sizeof(double) * nr, hipMemcpyDeviceToHost, H->stream));
+  HELM_CHECK_HIP(hipMemcpyAsync(beta.data(), K.beta.p, sizeof(double) * nr, hipMemcpyDeviceToHost, H->stream));
+  HELM_CHECK_HIP(hipMemcpyAsync(est.data(), K.est.p, sizeof(double) * nr, hipMemcpyDeviceToHost, H->stream));
+  HELM_CHECK_HIP(hipMemcpyAsync(fac.data(), K.fac.p, sizeof(double) * nr, hipMemcpyDeviceToHost, H->stream));
+  HELM_CHECK_HIP(hipMemcpyAsync(it.data(), K.it.p, sizeof(int) * nr, hipMemcpyDeviceToHost, H->stream));
+  HELM_CHECK_HIP(hipMemcpyAsync(g0.data(), K.g.p, sizeof(z64) * nr, hipMemcpyDeviceToHost, H->stream));
+  HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+  auto pick = [&](auto& v) {
+    std::remove_reference_t<decltype(v)> o(nk);
+    for (int k = 0; k < nk; ++k) o[k] = v[keep[k]];
+    return o;
+  };
+  const auto bn2 = pick(bn), beta2 = pick(beta), est2 = pick(est), fac2 = pick(fac);
+  const auto it2 = pick(it);
+  const auto g02 = pick(g0);
+  const std::vector<int> ones(nk, 1), zeros(nk, 0);
+  HELM_CHECK_HIP(hipMemcpyAsync(K.bnorm.p, bn2.data(), sizeof(double) * nk, hipMemcpyHostToDevice, H->stream));
+  HELM_CHECK_HIP(hipMemcpyAsync(K.beta.p, beta2.data(), sizeof(double) * nk, hipMemcpyHostToDevice, H->stream));
+  HELM_CHECK_HIP(hipMemcpyAsync(K.est.p, est2.data(), sizeof(double) * nk, hipMemcpyHostToDevice, H->stream));
+  HELM_CHECK_HIP(hipMemcpyAsync(K.fac.p, fac2.data(), sizeof(double) * nk, hipMemcpyHostToDevice, H->stream));
+  HELM_CHECK_HIP(hipMemcpyAsync(K.it.p, it2.data(), sizeof(int) * nk, hipMemcpyHostToDevice, H->stream));
+  HELM_CHECK_HIP(hipMemcpyAsync(K.g.p, g02.data(), sizeof(z64) * nk, hipMemcpyHostToDevice, H->stream));
+  HELM_CHECK_HIP(hipMemcpyAsync(K.active.p, ones.data(), sizeof(int) * nk, hipMemcpyHostToDevice, H->stream));
+  HELM_CHECK_HIP(hipMemcpyAsync(K.done.p, zeros.data(), sizeof(int) * nk, hipMemcpyHostToDevice, H->stream));
+  HELM_CHECK_HIP(hipMemcpyAsync(K.conv.p, zeros.data(), sizeof(int) * nk, hipMemcpyHostToDevice, H->stream));
+  HELM_CHECK_HIP(hipMemcpyAsync(K.kc.p, zeros.data(), sizeof(int) * nk, hipMemcpyHostToDevice, H->stream));
+  HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+  std::vector<int> orig2(nk);
+  for (int k = 0; k < nk; ++k) orig2[k] = orig[keep[k]];
+  orig.swap(orig2);
+  nr = nk;
+  set_batch(H, nr);
+}
+
+// FGMRES on one batch; finished right-hand sides leave the batch at restarts.
+void fgmres_chunk(helm_handle* H, int nr, double tol, int maxit, bool x0, void* X, int r0, ChunkOut& out) {
+  Workspace& W = H->ws;
+  KrylovArrays& K = W.ko;
+  const long long n = H->n;
   const int m = H->dec.restart;
+  std::vector<int> orig(nr);
+  for (int c = 0; c < nr; ++c) orig[c] = c;
+  // compaction stages three vectors of the batch in the basis storage
+  static const bool no_compact = std::getenv("HELM_NO_COMPACT") != nullptr;
+  const bool compact = !no_compact && m + 1 >= 3;
   launch_norm2(W.b.as<z64>(), n, nr, W.dpart.as<double>(), W.bn2.as<double>(), H->stream);
   launch_krylov_init(K.st, W.bn2.as<double>(), H->stream);
   if (x0) {
     launch_residual(H->op, nr, W.b.as<z64>(), W.x.as<z64>(), W.w.as<z64>(), H->stream);
   } else {
-    launch_fill(W.x.as<z64>(), vs, H->stream);
-    launch_copy(W.b.as<z64>(), W.w.as<z64>(), vs, H->stream);
+    launch_fill(W.x.as<z64>(), n * nr, H->stream);
+    launch_copy(W.b.as<z64>(), W.w.as<z64>(), n * nr, H->stream);
   }
   launch_norm2(W.w.as<z64>(), n, nr, W.dpart.as<double>(), W.beta2.as<double>(), H->stream);
   zero_counter(H, K);
   launch_cycle_start(K.st, W.beta2.as<double>(), tol, maxit, 1, H->stream);
   int nact = read_counter(H, K);
   while (nact > 0) {
+    if (compact && nact < nr) compact_batch(H, nr, orig, X, r0, out);
+    const long long vs = n * nr;
     launch_scale(W.w.as<z64>(), K.fac.as<double>(), W.V.as<z64>(), n, nr, H->stream);
     for (int j = 0; j < m; ++j) {
       run_outer_step(H, nr, j, tol, maxit);
@@ -919,6 +1041,9 @@ void fgmres_chunk(helm_handle* H, int nr, double tol, int maxit, bool x0) {
     launch_cycle_start(K.st, W.beta2.as<double>(), tol, maxit, 0, H->stream);
     nact = read_counter(H, K);
   }
+  std::vector<int> all(nr);
+  for (int c = 0; c < nr; ++c) all[c] = c;
+  emit_columns(H, nr, orig, all, X, r0, out);
 }
 
 struct Timer {
@@ -1193,23 +1318,18 @@ helm_status solve_impl(helm_handle* H, int32_t nrhs, const void* B, void* X, dou
         HELM_CHECK_HIP(hipMemcpyAsync(W.w.p, (const char*)X + sizeof(z64) * (size_t)n * r0, bytes, hipMemcpyDefault, H->stream));
         launch_to_node_major(W.w.as<z64>(), W.x.as<z64>(), n, nr, H->stream);
       }
-      fgmres_chunk(H, nr, tol, maxit, x0);
-      launch_to_field_major(W.x.as<z64>(), W.w.as<z64>(), n, nr, H->stream);
-      HELM_CHECK_HIP(hipMemcpyAsync((char*)X + sizeof(z64) * (size_t)n * r0, W.w.p, bytes, hipMemcpyDefault, H->stream));
-      std::vector<int> it(nr), conv(nr);
-      std::vector<double> est(nr), beta(nr), bn(nr);
-      HELM_CHECK_HIP(hipMemcpyAsync(it.data(), W.ko.it.p, sizeof(int) * nr, hipMemcpyDeviceToHost, H->stream));
-      HELM_CHECK_HIP(hipMemcpyAsync(conv.data(), W.ko.conv.p, sizeof(int) * nr, hipMemcpyDeviceToHost, H->stream));
-      HELM_CHECK_HIP(hipMemcpyAsync(est.data(), W.ko.est.p, sizeof(double) * nr, hipMemcpyDeviceToHost, H->stream));
-      HELM_CHECK_HIP(hipMemcpyAsync(beta.data(), W.ko.beta.p, sizeof(double) * nr, hipMemcpyDeviceToHost, H->stream));
-      HELM_CHECK_HIP(hipMemcpyAsync(bn.data(), W.ko.bnorm.p, sizeof(double) * nr, hipMemcpyDeviceToHost, H->stream));
-      HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+      ChunkOut co;
+      co.it.assign(nr, 0);
+      co.conv.assign(nr, 0);
+      co.est.assign(nr, 0.0);
+      co.tru.assign(nr, 0.0);
+      fgmres_chunk(H, nr, tol, maxit, x0, X, r0, co);
       for (int r = 0; r < nr; ++r) {
-        it_all[r0 + r] = it[r];
-        conv_all[r0 + r] = conv[r];
-        est_all[r0 + r] = est[r];
-        tru_all[r0 + r] = bn[r] > 0 ? beta[r] / bn[r] : 0.0;
-        all_conv = all_conv && conv[r];
+        it_all[r0 + r] = co.it[r];
+        conv_all[r0 + r] = co.conv[r];
+        est_all[r0 + r] = co.est[r];
+        tru_all[r0 + r] = co.tru[r];
+        all_conv = all_conv && co.conv[r];
       }
     }
     H->t_solve = tt.stop();

@@ -87,6 +87,8 @@ void launch_fill(z64* p, long long n, hipStream_t s);  // zero
 void launch_copy(const z64* a, z64* b, long long n, hipStream_t s);
 void launch_to_node_major(const z64* in, z64* out, long long len, int nrhs, hipStream_t s);
 void launch_to_field_major(const z64* in, z64* out, long long len, int nrhs, hipStream_t s);
+// out[i][c] = in[i][cols[c]] for c < nout (cols: device array of column indices < nin)
+void launch_gather_cols(const z64* in, int nin, const int* cols, int nout, long long len, z64* out, hipStream_t s);
 // h[v][r] = sum_node conj(V_v[node][r]) w[node][r], v < nv; V_v = V + v*vstride
 void launch_dots(const z64* V, long long vstride, int nv, const z64* w, long long len, int nrhs,
                  z64* partial, z64* h, hipStream_t s, double* npart = nullptr,

@@ -453,6 +453,20 @@ void launch_to_node_major(const z64* in, z64* out, long long len, int nrhs, hipS
   hipLaunchKernelGGL(k_to_node_major, dim3((unsigned)ceil_div(len, 32), (unsigned)ceil_div(nrhs, 32)), dim3(256), 0, s,
                      in, out, len, nrhs);
 }
+// out[i][c] = in[i][cols[c]]: selected columns of a node-major block ([len][nin] -> [len][nout])
+__global__ void k_gather_cols(const z64* __restrict__ in, int nin, const int* __restrict__ cols, int nout,
+                              long long len, z64* __restrict__ out) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= len * nout) return;
+  const long long i = e / nout;
+  const int c = (int)(e - i * nout);
+  out[e] = in[i * nin + cols[c]];
+}
+void launch_gather_cols(const z64* in, int nin, const int* cols, int nout, long long len, z64* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)ceil_div(len * nout, 256)), dim3(256), 0, s, in, nin, cols, nout,
+                     len, out);
+}
+
 void launch_to_field_major(const z64* in, z64* out, long long len, int nrhs, hipStream_t s) {
   hipLaunchKernelGGL(k_to_field_major, dim3((unsigned)ceil_div(len, 32), (unsigned)ceil_div(nrhs, 32)), dim3(256), 0,
                      s, in, out, len, nrhs);

@@ -210,6 +210,33 @@ def test_two_level_end_to_end_parity_many_rhs():
     S.close()
 
 
+def test_batch_narrows_at_restarts():
+    # right-hand sides of different difficulty in one batch (a zero one done at
+    # once, point sources, a random field) with short restart cycles, so they
+    # leave the batch at different restarts: each matches its solve alone in
+    # iteration count and solution (rounding of the batch-width dependent
+    # reductions aside), and the zero one returns zero after no iteration
+    shape, h, f, tol = (28, 26, 24), 25.0, 10.0, 1e-8
+    say("narrowing batch", shape)
+    c = inputs.velocity_thrust_belt(*shape, h=h)
+    b = inputs.point_source_rhs(*shape, [(6, 6, 4), (14, 13, 4), (21, 19, 4)]).reshape(3, -1)
+    rnd = inputs.random_field((1, b.shape[1]), seed=31)
+    B = np.concatenate([b[:1], np.zeros_like(b[:1]), rnd, b[1:]], 0)
+    S = helm().Solver(shape, h, c, f, (5, 5, 5, 0), weights=W, parts=(2, 2, 2), overlap=2, levels=2, restart=5)
+    X, info = S.solve(B, tol=tol, maxit=300)
+    say("iters batch", info["iters"])
+    assert len(set(int(i) for i in info["iters"])) >= 3
+    for r in range(B.shape[0]):
+        Xr, ir = S.solve(B[r:r + 1], tol=tol, maxit=300)
+        assert int(ir["iters"][0]) == int(info["iters"][r]), r
+        if r == 1:
+            assert int(info["iters"][r]) == 0 and not np.any(X[r]) and info["relres_true"][r] == 0
+            continue
+        assert rel(X[r], Xr[0]) <= 1e-10, r
+        assert info["relres_true"][r] <= tol
+    S.close()
+
+
 def test_mixed_precision_reaches_fp64_residual():
     shape, h, f = (28, 26, 24), 25.0, 10.0
     say("mixed e2e", shape)
