@@ -68,6 +68,7 @@ def gpu_solve(helm, w, c_dev, b_dev, precision, weights, timing=False, graphs=Tr
     if timing:
         info["sweeps"] = [S.sweep_stats(0), S.sweep_stats(w["levels"] - 1)]
     info["graphs"] = S.graph_stats()
+    info["bound"] = S.solve_bound()
     S.close()
     return X, info
 
@@ -256,6 +257,10 @@ def main():
                   "mean": float(info["iters"].mean())},
         "max_true_relres": float(info["relres_true"].max()),
         "graphs": info["graphs"],
+        # the whole solve against its roofline: every launch at max(bytes / 8 TB/s, flops / peak)
+        "solve_roofline": {"bound_s": info["bound"]["seconds"], "solve_s": float(solves[-1]),
+                           "frac": info["bound"]["seconds"] / float(solves[-1]),
+                           "algorithmic_bytes": info["bound"]["bytes"], "algorithmic_flops": info["bound"]["flops"]},
     }
     # dominant kernel: the batched local solves of the coarse level (FP64 MFMA);
     # the fine-level sweep (complex FP32 on MFMA in the mixed form) alongside

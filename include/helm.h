@@ -154,6 +154,15 @@ size_t helm_resident_bytes(const helm_handle_t* h);
  * out[3] coarse set-up, out[4] number of outer iterations summed over RHS. */
 helm_status helm_last_timings(const helm_handle_t* h, double out[5]);
 
+/* Lower bound of the last solve on this handle: every kernel launch of the
+ * solve (the local-solve sweeps of eq. oras, the 27-point products of eq. eq1,
+ * the coarse correction of eq. 2lvl, the Krylov passes, staging) contributes
+ * max(algorithmic bytes / 8 TB/s, algorithmic flops / peak), with the FP64
+ * (78.6 TFLOP/s) or FP32 (157.3 TFLOP/s) peak of its arithmetic.  out[0] the
+ * bound in seconds, out[1] algorithmic bytes, out[2] algorithmic flops.  The
+ * solve's roofline fraction is out[0] over the measured solve time. */
+helm_status helm_solve_bound(const helm_handle_t* h, double out[3]);
+
 /* Live timing of the batched local solves (the one-level ORAS sweep of eq.
  * oras, one kernel launch per application): when enabled, HIP events on the
  * handle's stream bracket every sweep launch; helm_sweep_stats returns, for

@@ -25,6 +25,8 @@ struct HelmError : std::runtime_error {
   HelmError(helm_status c, const std::string& m) : std::runtime_error(m), code(c) {}
 };
 
+thread_local WorkBound* g_work = nullptr;
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -344,6 +346,7 @@ struct Captured {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[2];
   std::vector<double> fl[2], by[2];
   bool pending = false;  // replayed with timing, events not yet read
+  WorkBound work;        // algorithmic work of one replay
 
   ~Captured() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -381,6 +384,7 @@ struct helm_handle {
   std::vector<std::unique_ptr<Captured>> captured;
   Captured* capturing = nullptr;
   double graph_stat[2] = {0, 0};  // captures, replays
+  WorkBound work_solve;           // lower bound of the last solve
   // the asynchronous solve in flight, if any (helm_solve_async)
   helm_request* pending = nullptr;
   std::mutex pending_mu;
@@ -665,6 +669,11 @@ void oras_apply(helm_handle* H, Level& L, int nr, const z64* u, z64* z, const z6
     record_timing_event(H, e0);
   }
   oras_sweep(H, L, nr, u, z, add, yl, tb);
+  if (g_work) {  // after the launch: a first sweep of a shape has run the tuner, whose group sets the bytes
+    double f, by;
+    sweep_work(H, L, nr, &f, &by);
+    account(by, f, L.prec ? FP32_PEAK : FP64_PEAK);
+  }
   if (H->timing) {
     record_timing_event(H, e1);
     double f, by;
@@ -843,9 +852,13 @@ void run_outer_step(helm_handle* H, int nr, int j, double tol, int maxit) {
     }
     H->capturing = e.get();
     hipGraph_t g = nullptr;
+    WorkBound* const outer_work = g_work;
+    g_work = outer_work ? &e->work : nullptr;  // one replay's work; added per launch below
     try {
       outer_step(H, nr, j, tol, maxit);
+      g_work = outer_work;
     } catch (const HelmError& err) {
+      g_work = outer_work;
       H->capturing = nullptr;
       if (hipStreamEndCapture(H->stream, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
       if (!H->timing) throw;
@@ -856,6 +869,7 @@ void run_outer_step(helm_handle* H, int nr, int j, double tol, int maxit) {
       outer_step(H, nr, j, tol, maxit);
       return;
     } catch (...) {
+      g_work = outer_work;
       H->capturing = nullptr;
       if (hipStreamEndCapture(H->stream, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
       throw;
@@ -884,6 +898,7 @@ void run_outer_step(helm_handle* H, int nr, int j, double tol, int maxit) {
   HELM_CHECK_HIP(hipGraphLaunch(c->exec, H->stream));
   c->pending = c->timed;
   H->graph_stat[1] += 1;
+  if (g_work) g_work->add(c->work);
 }
 
 // Batched FGMRES on W.nr right-hand sides held node-major in W.b / W.x.
@@ -1302,6 +1317,12 @@ helm_status solve_impl(helm_handle* H, int32_t nrhs, const void* B, void* X, dou
     const int nr_max = choose_chunk(H, nrhs);
     ensure_ws(H, nr_max);
     Workspace& W = H->ws;
+    H->work_solve = WorkBound{};
+    struct Install {  // this thread's launches count towards the solve's bound until return
+      WorkBound* prev;
+      explicit Install(WorkBound* w) : prev(g_work) { g_work = w; }
+      ~Install() { g_work = prev; }
+    } install(&H->work_solve);
     std::vector<int> it_all(nrhs), conv_all(nrhs);
     std::vector<double> est_all(nrhs), tru_all(nrhs);
     bool all_conv = true;
@@ -1502,6 +1523,14 @@ helm_status helm_set_row_tiling(int32_t nodes_per_thread) {
 
 helm_status helm_set_lu_panel(int32_t columns) {
   if (!set_lu_panel(columns)) return fail(HELM_EINVAL, "panel width must be 0, 4, 8 or 16");
+  return HELM_OK;
+}
+
+helm_status helm_solve_bound(const helm_handle_t* H, double out[3]) {
+  if (!H || !out) return fail(HELM_EINVAL, "null argument");
+  out[0] = H->work_solve.seconds;
+  out[1] = H->work_solve.bytes;
+  out[2] = H->work_solve.flops;
   return HELM_OK;
 }
 

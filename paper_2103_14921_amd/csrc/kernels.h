@@ -8,6 +8,28 @@
 struct AxisPml {
   int n, lo, hi;  // nodes, PML thickness at the low / high end
 };
+// Lower bound of the solve: every launch of the solve phase adds its
+// algorithmic bytes and flops and the time they take at the device's peaks
+// (HBM 8 TB/s; FP64 78.6, FP32 157.3 TFLOP/s), into the accumulator the
+// calling thread has installed (none outside solves).
+struct WorkBound {
+  double bytes = 0, flops = 0, seconds = 0;
+  void add(const WorkBound& o) {
+    bytes += o.bytes;
+    flops += o.flops;
+    seconds += o.seconds;
+  }
+};
+constexpr double HBM_PEAK = 8.0e12, FP64_PEAK = 78.6e12, FP32_PEAK = 157.3e12;
+extern thread_local WorkBound* g_work;
+inline void account(double bytes, double flops, double peak = FP64_PEAK) {
+  if (WorkBound* w = g_work) {
+    w->bytes += bytes;
+    w->flops += flops;
+    w->seconds += bytes / HBM_PEAK > flops / peak ? bytes / HBM_PEAK : flops / peak;
+  }
+}
+
 void launch_vmax(const z64* c, long long n, double* out, hipStream_t s);
 void launch_pml_tables(const AxisPml ax[3], double h, double omega, double R, const double* vmax,
                        z64* xi_int, z64* xi_half, z64* i2_int, z64* i2_half, uint8_t* flat,

@@ -438,9 +438,11 @@ int red_blocks(long long len) {
 }  // namespace
 
 void launch_fill(z64* p, long long n, hipStream_t s) {
+  account(16.0 * n, 0);
   hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<long long>(ceil_div(n, 256), 8192)), dim3(256), 0, s, p, n);
 }
 void launch_copy(const z64* a, z64* b, long long n, hipStream_t s) {
+  account(32.0 * n, 0);
   hipLaunchKernelGGL(k_copy, dim3((unsigned)std::min<long long>(ceil_div(n, 256), 8192)), dim3(256), 0, s, a, b, n);
 }
 void launch_sub(z64* a, const z64* b, long long n, hipStream_t s) {
@@ -450,6 +452,7 @@ void launch_add2(z64* a, const z64* b, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_add2, dim3((unsigned)std::min<long long>(ceil_div(n, 256), 8192)), dim3(256), 0, s, a, b, n);
 }
 void launch_to_node_major(const z64* in, z64* out, long long len, int nrhs, hipStream_t s) {
+  account(32.0 * len * nrhs, 0);
   hipLaunchKernelGGL(k_to_node_major, dim3((unsigned)ceil_div(len, 32), (unsigned)ceil_div(nrhs, 32)), dim3(256), 0, s,
                      in, out, len, nrhs);
 }
@@ -463,17 +466,20 @@ __global__ void k_gather_cols(const z64* __restrict__ in, int nin, const int* __
   out[e] = in[i * nin + cols[c]];
 }
 void launch_gather_cols(const z64* in, int nin, const int* cols, int nout, long long len, z64* out, hipStream_t s) {
+  account(32.0 * len * nout, 0);
   hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)ceil_div(len * nout, 256)), dim3(256), 0, s, in, nin, cols, nout,
                      len, out);
 }
 
 void launch_to_field_major(const z64* in, z64* out, long long len, int nrhs, hipStream_t s) {
+  account(32.0 * len * nrhs, 0);
   hipLaunchKernelGGL(k_to_field_major, dim3((unsigned)ceil_div(len, 32), (unsigned)ceil_div(nrhs, 32)), dim3(256), 0,
                      s, in, out, len, nrhs);
 }
 
 void launch_dots(const z64* V, long long vstride, int nv, const z64* w, long long len, int nrhs, z64* partial,
                  z64* h, hipStream_t s, double* npart, double* nrm2) {
+  account(16.0 * (nv + 1) * len * nrhs, 8.0 * nv * len * nrhs);
   const int nblk = red_blocks(len);
   for (int v0 = 0; v0 < nv; v0 += NVMAX) {
     const int nvb = std::min(NVMAX, nv - v0);
@@ -489,6 +495,7 @@ void launch_dots(const z64* V, long long vstride, int nv, const z64* w, long lon
 
 void launch_axpy_multi(const z64* V, long long vstride, int nv, const z64* h, z64* w, long long len, int nrhs,
                        double* partial, double* nrm2, hipStream_t s) {
+  account(16.0 * (nv + 2) * len * nrhs, 8.0 * nv * len * nrhs);
   const int nblk = red_blocks(len);
   for (int v0 = 0; v0 < nv; v0 += NVMAX) {
     const int nvb = std::min(NVMAX, nv - v0);
@@ -503,6 +510,7 @@ void launch_axpy_multi(const z64* V, long long vstride, int nv, const z64* h, z6
 bool launch_axpy_dots(const z64* V, long long vstride, int nv, const z64* h, z64* w, long long len, int nrhs,
                       z64* partial, z64* h2, hipStream_t s) {
   if (nv > NVMAX || (size_t)nv * nrhs * sizeof(z64) > 64 * 1024) return false;
+  account(16.0 * (nv + 2) * len * nrhs, 16.0 * nv * len * nrhs);
   const int nblk = red_blocks(len);
   hipLaunchKernelGGL(k_axpy_dots, dim3(nblk), dim3(256), (size_t)nv * nrhs * sizeof(z64), s, V, vstride, nv, h, w, len,
                      nrhs, partial);
@@ -512,18 +520,21 @@ bool launch_axpy_dots(const z64* V, long long vstride, int nv, const z64* h, z64
 }
 
 void launch_norm2(const z64* w, long long len, int nrhs, double* partial, double* nrm2, hipStream_t s) {
+  account(16.0 * len * nrhs, 4.0 * len * nrhs);
   const int nblk = red_blocks(len);
   hipLaunchKernelGGL(k_norm2, dim3(nblk), dim3(256), 0, s, w, len, nrhs, partial);
   hipLaunchKernelGGL(k_sum_final, dim3((unsigned)ceil_div(nrhs, 4)), dim3(256), 0, s, partial, nblk, nrhs, nrm2);
 }
 
 void launch_scale(const z64* w, const double* fac, z64* out, long long len, int nrhs, hipStream_t s) {
+  account(32.0 * len * nrhs, 2.0 * len * nrhs);
   hipLaunchKernelGGL(k_scale, dim3((unsigned)std::min<long long>(ceil_div(len * nrhs, 256), 8192)), dim3(256), 0, s,
                      w, fac, out, len, nrhs);
 }
 
 void launch_update(const z64* Z, long long zstride, int nv, const z64* y, z64* x, long long len, int nrhs,
                    hipStream_t s) {
+  account(16.0 * (nv + 2) * len * nrhs, 8.0 * nv * len * nrhs);
   hipLaunchKernelGGL(k_update, dim3((unsigned)std::min<long long>(ceil_div(len * nrhs, 256), 8192)), dim3(256), 0, s,
                      Z, zstride, nv, y, x, len, nrhs);
 }

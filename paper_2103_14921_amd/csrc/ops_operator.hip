@@ -561,6 +561,10 @@ bool set_row_tiling(int nxt) {
 }
 
 static void stencil_dispatch(const OpDev& op, int nrhs, const z64* x, z64* y, const z64* b, hipStream_t s) {
+  {  // x read and y written once, b read once for a residual, the node values s k^2 once; 27 complex products
+    const double n = (double)op.nx * op.ny * op.nz;
+    account(16.0 * n * nrhs * (b ? 3 : 2) + 16.0 * n, 216.0 * n * nrhs);
+  }
   if (nrhs >= 4) {
     const dim3 grid(row_tiles(op.nx, op.ny, op.nz));
     auto launch = [&](int nxt) {
@@ -593,6 +597,10 @@ void launch_build_E(const OpDev& op, int ncx, int ncy, int ncz, z64* E, hipStrea
 
 void launch_coarse_spmv(int ncx, int ncy, int ncz, const z64* E, int nrhs, const z64* x, z64* y,
                         hipStream_t s) {
+  {  // E once (27 coefficients per node), x read and y written once
+    const double nc = (double)ncx * ncy * ncz;
+    account(nc * (27.0 * 16 + 32.0 * nrhs), 216.0 * nc * nrhs);
+  }
   if (nrhs >= 4) {
     const dim3 grid(row_tiles(ncx, ncy, ncz));
     auto launch = [&](int nxt) {
@@ -610,10 +618,12 @@ void launch_coarse_spmv(int ncx, int ncy, int ncz, const z64* E, int nrhs, const
 
 void launch_restrict(int nx, int ny, int nz, int nrhs, const z64* r, z64* c, hipStream_t s) {
   const long long nc = (long long)((nx + 1) / 2) * ((ny + 1) / 2) * ((nz + 1) / 2);
+  account(16.0 * ((double)nx * ny * nz + nc) * nrhs, 2.0 * 27 * nc * nrhs);
   hipLaunchKernelGGL(k_restrict, dim3((unsigned)ceil_div(nc * nrhs, 256)), dim3(256), 0, s, nx, ny, nz, nrhs, r, c);
 }
 
 void launch_prolong(int nx, int ny, int nz, int nrhs, const z64* c, z64* q, hipStream_t s) {
   const long long n = (long long)nx * ny * nz;
+  account(16.0 * (n + (double)((nx + 1) / 2) * ((ny + 1) / 2) * ((nz + 1) / 2)) * nrhs, 2.0 * 8 * n * nrhs);
   hipLaunchKernelGGL(k_prolong, dim3((unsigned)ceil_div(n * nrhs, 256)), dim3(256), 0, s, nx, ny, nz, nrhs, c, q);
 }

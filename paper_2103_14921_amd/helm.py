@@ -29,7 +29,7 @@ EXPORTS = [
     "helm_set_sweep_policy",
     "helm_set_row_tiling",
     "helm_set_lu_panel",
-    "helm_solve_async", "helm_request_query", "helm_request_wait",
+    "helm_solve_async", "helm_request_query", "helm_request_wait", "helm_solve_bound",
 ]
 
 
@@ -108,6 +108,7 @@ def _load():
         "helm_solve_async": ([P, i32, P, P, C.c_double, i32, C.c_uint32, P, P, P, C.POINTER(C.c_void_p)], C.c_int),
         "helm_request_query": ([P], C.c_int),
         "helm_request_wait": ([P], C.c_int),
+        "helm_solve_bound": ([P, C.POINTER(C.c_double)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -302,6 +303,12 @@ class Solver:
         out = (C.c_double * 5)()
         _check(lib.helm_last_timings(self._h, out))
         return dict(setup=out[0], solve=out[1], factor=out[2], coarse=out[3], iters_total=out[4])
+
+    def solve_bound(self):
+        """Lower bound of the last solve: seconds at the device's peaks, algorithmic bytes and flops."""
+        out = (C.c_double * 3)()
+        _check(lib.helm_solve_bound(self._h, out))
+        return dict(seconds=out[0], bytes=out[1], flops=out[2])
 
     def set_sweep_timing(self, enable=True):
         _check(lib.helm_set_sweep_timing(self._h, 1 if enable else 0))

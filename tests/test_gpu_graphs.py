@@ -63,6 +63,11 @@ def test_two_level_mixed_graphs_bitwise_equal_direct():
         b = d.solve(B, tol=1e-6, maxit=200)
         assert np.all(a[1]["relres_true"] <= 1e-6)
         _same(a, b, tag)
+        # the solve's lower bound counts a replayed iteration like a direct one
+        bg, bd = g.solve_bound(), d.solve_bound()
+        assert bg["seconds"] > 0 and bg["bytes"] > 0 and bg["flops"] > 0
+        for k in bg:
+            assert abs(bg[k] - bd[k]) <= 1e-9 * bd[k], (tag, k, bg[k], bd[k])
         st = g.graph_stats()
         say(tag, "iters", a[1]["iters"].max(), st)
         assert st["replays"] > st["captures"] > 0
