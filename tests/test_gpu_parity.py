@@ -237,6 +237,30 @@ def test_batch_narrows_at_restarts():
     S.close()
 
 
+def test_batch_narrowing_with_iteration_limit_and_initial_guess():
+    # right-hand sides that stop at maxit leave the batch like converged ones
+    # (status NOT_CONVERGED, their residuals reported); with an initial guess
+    # (one exact, one zero, one rough) each column matches its solve alone
+    shape, h, f, tol = (28, 26, 24), 25.0, 10.0, 1e-10
+    say("narrowing batch, maxit and x0", shape)
+    c = inputs.velocity_thrust_belt(*shape, h=h)
+    b = inputs.point_source_rhs(*shape, [(6, 6, 4), (14, 13, 4), (21, 19, 4)]).reshape(3, -1)
+    S = helm().Solver(shape, h, c, f, (5, 5, 5, 0), weights=W, parts=(2, 2, 2), overlap=2, levels=2, restart=4)
+    ref, _ = S.solve(b, tol=tol, maxit=400)
+    X0 = np.stack([ref[0], np.zeros_like(ref[1]), ref[2] + 1e-3 * inputs.random_field((1, b.shape[1]), seed=3)[0]])
+    X, info = S.solve(b, tol=tol, maxit=9, X0=X0.copy())
+    say("iters", info["iters"], "status", info["status"])
+    assert info["status"] == helm().HELM_NOT_CONVERGED
+    assert int(info["iters"][0]) == 0 and info["relres_true"][0] <= tol
+    assert int(info["iters"][1]) == 9 and info["relres_true"][1] > tol
+    for r in range(3):
+        Xr, ir = S.solve(b[r:r + 1], tol=tol, maxit=9, X0=X0[r:r + 1].copy())
+        assert int(ir["iters"][0]) == int(info["iters"][r]), r
+        assert rel(X[r], Xr[0]) <= 1e-10, r
+        assert abs(ir["relres_true"][0] - info["relres_true"][r]) <= 1e-6 * ir["relres_true"][0] + 1e-300, r
+    S.close()
+
+
 def test_mixed_precision_reaches_fp64_residual():
     shape, h, f = (28, 26, 24), 25.0, 10.0
     say("mixed e2e", shape)
