@@ -205,8 +205,12 @@ class Request:
         return self.X, dict(status=code, iters=self.its, relres_est=self.est, relres_true=self.tru, timings=timings)
 
     def __del__(self):
-        if self._result is None and self._h is not None:
-            lib.helm_request_wait(self._h)
+        # an abandoned request still owns a library thread: join it
+        try:
+            if self._result is None and self._h is not None:
+                lib.helm_request_wait(self._h)
+        except Exception:
+            pass
 
 
 SWEEP_POLICIES = {"auto": 0, "item": 1, "pipelined": 2}
