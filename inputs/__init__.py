@@ -191,9 +191,11 @@ def workload_inputs(name, shape=None, n_src=None):
 # a stream of requests drawn from it (grids 64^3..160^3, 2-8 Hz, 1-64 sources).
 # ---------------------------------------------------------------------------
 
-def serving_catalogue(n_entries=16, seed=4, grids=(64, 96, 128, 160), core=16, npml=10):
-    """List of dicts(name, model, n, h, freq, parts): n^3 grids, h = min(25, vmin/(8 f)),
-    boxes of core^3 nodes per axis."""
+def serving_catalogue(n_entries=16, seed=4, grids=(64, 96, 128, 160), core=16, npml=10, pml_wavelengths=0.3):
+    """List of dicts(name, model, n, h, freq, parts, npml): n^3 grids, h = min(25, vmin/(8 f)),
+    boxes of core^3 nodes per axis, PML at least pml_wavelengths of the longest wavelength
+    (and at least npml nodes) thick: a layer much thinner than the wavelength leaves the
+    low-frequency problems of the catalogue nearly undamped cavities."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(n_entries):
@@ -202,7 +204,9 @@ def serving_catalogue(n_entries=16, seed=4, grids=(64, 96, 128, 160), core=16, n
         f = float(rng.uniform(2.0, 8.0))
         vmin = 2000.0 if model == "thrust" else 1500.0
         h = min(25.0, vmin / (8.0 * f))
-        out.append(dict(name=f"{model}{n}_{i}", model=model, n=n, h=h, freq=f, parts=(n // core,) * 3, npml=npml))
+        vmax = 6000.0 if model == "thrust" else 1500.0 + 0.7 * (n - 1) * h
+        layer = max(npml, int(np.ceil(pml_wavelengths * vmax / (f * h))))
+        out.append(dict(name=f"{model}{n}_{i}", model=model, n=n, h=h, freq=f, parts=(n // core,) * 3, npml=layer))
     return out
 
 
