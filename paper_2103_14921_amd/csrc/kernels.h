@@ -115,15 +115,18 @@ void launch_gather_cols(const z64* in, int nin, const int* cols, int nout, long 
 void launch_dots(const z64* V, long long vstride, int nv, const z64* w, long long len, int nrhs,
                  z64* partial, z64* h, hipStream_t s, double* npart = nullptr,
                  double* nrm2 = nullptr);
-// w -= sum_v h[v][r] V_v ; optionally nrm2[r] = ||w||^2 after the update
+// w -= sum_v h[v][r] V_v ; optionally nrm2[r] = ||w||^2 after the update.  With
+// skip given, every kernel of the update returns at once when *skip != 0 (a
+// decision taken on the device, so the sequence stays capturable).
 void launch_axpy_multi(const z64* V, long long vstride, int nv, const z64* h, z64* w,
-                       long long len, int nrhs, double* partial, double* nrm2, hipStream_t s);
+                       long long len, int nrhs, double* partial, double* nrm2, hipStream_t s,
+                       const int* skip = nullptr);
 void launch_norm2(const z64* w, long long len, int nrhs, double* partial, double* nrm2,
                   hipStream_t s);
 // w -= sum_v h[v][r] V_v and h2[v][r] = sum_node conj(V_v) w (updated w), one pass;
 // false when nv or the batch is too large for the fused kernel
 bool launch_axpy_dots(const z64* V, long long vstride, int nv, const z64* h, z64* w, long long len, int nrhs,
-                      z64* partial, z64* h2, hipStream_t s);
+                      z64* partial, z64* h2, hipStream_t s, double* npart = nullptr, double* nrm2 = nullptr);
 // out[node][r] = fac[r] * w[node][r]
 void launch_scale(const z64* w, const double* fac, z64* out, long long len, int nrhs, hipStream_t s);
 // x += sum_v y[v][r] Z_v
@@ -154,7 +157,15 @@ struct KrylovState {
   int* done;      // [nrhs]
   int* conv;      // [nrhs] 1 if converged
   int* counter;   // [1] number still active (host reads it)
+  double* w1;     // [nrhs] squared norm of w after the first Gram-Schmidt update
+  int* skip;      // [1] 1 when the second update of this step is negligible for every RHS
+  double* extra;  // [1] algorithmic bytes of the second updates that ran (solve accounting)
 };
+// Second Gram-Schmidt pass: when sum_v |h2[v][r]|^2 <= tau2 ||w'||^2 for every
+// active right-hand side, the second update would change w' by less than
+// sqrt(tau2) relative: skip it (h2 := 0, ||w||^2 := ||w'||^2); otherwise let it
+// run and add vec_bytes (nv + 2) to *extra.
+void launch_reorth_check(KrylovState st, int nv, double tau2, double vec_bytes, hipStream_t s);
 void launch_krylov_init(KrylovState st, const double* bn2, hipStream_t s);
 // start a cycle from residual norms^2 in beta2: decide done/active, set g[0], fac = 1/beta
 void launch_cycle_start(KrylovState st, const double* beta2, double tol, int maxit, int first,

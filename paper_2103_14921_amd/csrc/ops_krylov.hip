@@ -157,7 +157,9 @@ __global__ void __launch_bounds__(256) k_dots_final(const z64* __restrict__ part
 // w -= sum_v h[v][r] V_v; partial[r][blk] = sum |w|^2 over the block's nodes (if partial)
 __global__ void __launch_bounds__(256) k_axpy_multi(const z64* __restrict__ V, long long vstride, int nv,
                                                     const z64* __restrict__ h, z64* __restrict__ w, long long len,
-                                                    int nrhs, double* __restrict__ partial) {
+                                                    int nrhs, double* __restrict__ partial,
+                                                    const int* __restrict__ skip) {
+  if (skip && *skip) return;  // uniform: one flag for the whole launch
   __shared__ double red[256];
   const int tid = threadIdx.x;
   const int nl = 256 / nrhs;
@@ -194,7 +196,7 @@ __global__ void __launch_bounds__(256) k_axpy_multi(const z64* __restrict__ V, l
 // projections of the second in one read of the basis.
 __global__ void __launch_bounds__(256) k_axpy_dots(const z64* __restrict__ V, long long vstride, int nv,
                                                    const z64* __restrict__ h, z64* __restrict__ w, long long len,
-                                                   int nrhs, z64* __restrict__ partial) {
+                                                   int nrhs, z64* __restrict__ partial, double* __restrict__ npart) {
   extern __shared__ z64 hs[];  // [nv][nrhs]
   __shared__ z64 red[256];
   const int tid = threadIdx.x;
@@ -206,6 +208,7 @@ __global__ void __launch_bounds__(256) k_axpy_dots(const z64* __restrict__ V, lo
   z64 acc[NVMAX];
 #pragma unroll
   for (int v = 0; v < NVMAX; ++v) acc[v] = mk(0.0, 0.0);
+  double accn = 0.0;
   if (lane < nl) {
     for (long long nd = sp.lo + lane; nd < sp.hi; nd += nl) {
       const long long e = nd * nrhs + r;
@@ -218,10 +221,22 @@ __global__ void __launch_bounds__(256) k_axpy_dots(const z64* __restrict__ V, lo
           cfms(x, hs[v * nrhs + r], vv[v]);
         }
       w[e] = x;
+      accn += abs2(x);
 #pragma unroll
       for (int v = 0; v < NVMAX; ++v)
         if (v < nv) cdot_acc(acc[v], vv[v], x);
     }
+  }
+  if (npart) {  // ||w'||^2 partial, [r][blk] as k_norm2 (red reused as doubles after a barrier)
+    double* rd = reinterpret_cast<double*>(red);
+    rd[tid] = (lane < nl) ? accn : 0.0;
+    __syncthreads();
+    if (lane == 0) {
+      double sn = rd[r];
+      for (int l = 1; l < nl; ++l) sn += rd[l * nrhs + r];
+      npart[(long long)r * gridDim.x + blockIdx.x] = sn;
+    }
+    __syncthreads();
   }
 #pragma unroll
   for (int v = 0; v < NVMAX; ++v) {
@@ -260,7 +275,8 @@ __global__ void __launch_bounds__(256) k_norm2(const z64* __restrict__ w, long l
 
 // out[r] = sum_b partial[r][b]: one wave per output, as k_dots_final.
 __global__ void __launch_bounds__(256) k_sum_final(const double* __restrict__ partial, int nblk, int nrhs,
-                                                   double* __restrict__ out) {
+                                                   double* __restrict__ out, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (r >= nrhs) return;
   const double* p = partial + (long long)r * nblk;
@@ -487,33 +503,64 @@ void launch_dots(const z64* V, long long vstride, int nv, const z64* w, long lon
     hipLaunchKernelGGL(k_dots, dim3(nblk), dim3(256), 0, s, V + v0 * vstride, vstride, nvb, w, len, nrhs, partial,
                        np);
     if (np)
-      hipLaunchKernelGGL(k_sum_final, dim3((unsigned)ceil_div(nrhs, 4)), dim3(256), 0, s, np, nblk, nrhs, nrm2);
+      hipLaunchKernelGGL(k_sum_final, dim3((unsigned)ceil_div(nrhs, 4)), dim3(256), 0, s, np, nblk, nrhs, nrm2,
+                         (const int*)nullptr);
     hipLaunchKernelGGL(k_dots_final, dim3((unsigned)ceil_div(nvb * nrhs, 4)), dim3(256), 0, s, partial, nblk, nvb,
                        nrhs, h + (long long)v0 * nrhs);
   }
 }
 
 void launch_axpy_multi(const z64* V, long long vstride, int nv, const z64* h, z64* w, long long len, int nrhs,
-                       double* partial, double* nrm2, hipStream_t s) {
-  account(16.0 * (nv + 2) * len * nrhs, 8.0 * nv * len * nrhs);
+                       double* partial, double* nrm2, hipStream_t s, const int* skip) {
+  // a conditional update is accounted on the device, when it runs (launch_reorth_check)
+  if (!skip) account(16.0 * (nv + 2) * len * nrhs, 8.0 * nv * len * nrhs);
   const int nblk = red_blocks(len);
   for (int v0 = 0; v0 < nv; v0 += NVMAX) {
     const int nvb = std::min(NVMAX, nv - v0);
     const bool last = v0 + nvb >= nv;
     hipLaunchKernelGGL(k_axpy_multi, dim3(nblk), dim3(256), 0, s, V + v0 * vstride, vstride, nvb,
-                       h + (long long)v0 * nrhs, w, len, nrhs, (last && nrm2) ? partial : nullptr);
+                       h + (long long)v0 * nrhs, w, len, nrhs, (last && nrm2) ? partial : nullptr, skip);
   }
   if (nrm2)
-    hipLaunchKernelGGL(k_sum_final, dim3((unsigned)ceil_div(nrhs, 4)), dim3(256), 0, s, partial, nblk, nrhs, nrm2);
+    hipLaunchKernelGGL(k_sum_final, dim3((unsigned)ceil_div(nrhs, 4)), dim3(256), 0, s, partial, nblk, nrhs, nrm2,
+                       skip);
+}
+
+// One workgroup; each thread owns right-hand sides r = tid, tid + 256, ...
+__global__ void __launch_bounds__(256) k_reorth_check(KrylovState st, int nv, double tau2, double vec_bytes) {
+  const int nr = st.nrhs;
+  int need = 0;
+  for (int r = threadIdx.x; r < nr; r += blockDim.x) {
+    if (!st.active[r]) continue;
+    double s2 = 0.0;
+    for (int v = 0; v < nv; ++v) s2 += abs2(st.h2[v * nr + r]);
+    if (s2 > tau2 * st.w1[r]) need = 1;
+  }
+  const int any = __syncthreads_or(need);
+  if (!any) {
+    for (int r = threadIdx.x; r < nr; r += blockDim.x) {
+      for (int v = 0; v < nv; ++v) st.h2[v * nr + r] = mk(0.0, 0.0);
+      st.nrm2[r] = st.w1[r];
+    }
+  } else if (threadIdx.x == 0) {
+    atomicAdd(st.extra, vec_bytes * (nv + 2));
+  }
+  if (threadIdx.x == 0) *st.skip = any ? 0 : 1;
+}
+void launch_reorth_check(KrylovState st, int nv, double tau2, double vec_bytes, hipStream_t s) {
+  hipLaunchKernelGGL(k_reorth_check, dim3(1), dim3(256), 0, s, st, nv, tau2, vec_bytes);
 }
 
 bool launch_axpy_dots(const z64* V, long long vstride, int nv, const z64* h, z64* w, long long len, int nrhs,
-                      z64* partial, z64* h2, hipStream_t s) {
+                      z64* partial, z64* h2, hipStream_t s, double* npart, double* nrm2) {
   if (nv > NVMAX || (size_t)nv * nrhs * sizeof(z64) > 64 * 1024) return false;
   account(16.0 * (nv + 2) * len * nrhs, 16.0 * nv * len * nrhs);
   const int nblk = red_blocks(len);
   hipLaunchKernelGGL(k_axpy_dots, dim3(nblk), dim3(256), (size_t)nv * nrhs * sizeof(z64), s, V, vstride, nv, h, w, len,
-                     nrhs, partial);
+                     nrhs, partial, nrm2 ? npart : nullptr);
+  if (nrm2)
+    hipLaunchKernelGGL(k_sum_final, dim3((unsigned)ceil_div(nrhs, 4)), dim3(256), 0, s, npart, nblk, nrhs, nrm2,
+                       (const int*)nullptr);
   hipLaunchKernelGGL(k_dots_final, dim3((unsigned)ceil_div(nv * nrhs, 4)), dim3(256), 0, s, partial, nblk, nv, nrhs,
                      h2);
   return true;
@@ -523,7 +570,8 @@ void launch_norm2(const z64* w, long long len, int nrhs, double* partial, double
   account(16.0 * len * nrhs, 4.0 * len * nrhs);
   const int nblk = red_blocks(len);
   hipLaunchKernelGGL(k_norm2, dim3(nblk), dim3(256), 0, s, w, len, nrhs, partial);
-  hipLaunchKernelGGL(k_sum_final, dim3((unsigned)ceil_div(nrhs, 4)), dim3(256), 0, s, partial, nblk, nrhs, nrm2);
+  hipLaunchKernelGGL(k_sum_final, dim3((unsigned)ceil_div(nrhs, 4)), dim3(256), 0, s, partial, nblk, nrhs, nrm2,
+                     (const int*)nullptr);
 }
 
 void launch_scale(const z64* w, const double* fac, z64* out, long long len, int nrhs, hipStream_t s) {
