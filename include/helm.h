@@ -71,21 +71,26 @@ typedef struct {
   double w1, w2, w3, wm1, wm2, wm3, wm4;
 } helm_weights_t;
 
-enum { HELM_FP64 = 0, HELM_MIXED = 1 };
+enum { HELM_FP64 = 0, HELM_MIXED = 1, HELM_SINGLE_LOCAL = 2 };
 
 /* Decomposition and solver options (domain-decomposition section).  Boxes
  * split each axis into p ranges (floor(n/p), the first n mod p one longer),
  * extended by `overlap` layers on every interior side; Boolean partition of
  * unity.  levels = 2 adds the coarse grid at 2h with E = Z^T A Z solved by
  * coarse_iters GMRES iterations.  precision = HELM_MIXED factors and applies
- * the local solves in complex FP32 and keeps FGMRES, orthogonalisation,
- * Givens, residuals and the coarse level in FP64. */
+ * the fine level's local solves in complex FP32 and keeps FGMRES,
+ * orthogonalisation, Givens, residuals and the coarse level in FP64.
+ * HELM_SINGLE_LOCAL also factors and applies the coarse level's local solves
+ * (the one-level preconditioner of the coarse GMRES) in complex FP32; the
+ * coarse GMRES itself, E and the transfers stay FP64 (the numerical-results
+ * section runs every part in single precision with unchanged iteration
+ * counts, Table 2). */
 typedef struct {
   int32_t px, py, pz;     /* subdomains per axis, >= 1 */
   int32_t overlap;        /* added layers per interior side, >= 1 */
   int32_t levels;         /* 1 or 2 */
   int32_t coarse_iters;   /* GMRES iterations of the coarse solve (paper: 10) */
-  int32_t precision;      /* HELM_FP64 or HELM_MIXED */
+  int32_t precision;      /* HELM_FP64, HELM_MIXED or HELM_SINGLE_LOCAL */
   int32_t restart;        /* FGMRES restart length m, >= 1 */
   int32_t robin;          /* 1: absorbing interfaces (ORAS); 0: Dirichlet (RAS) */
   int32_t nrhs_chunk;     /* right-hand sides per batch; 0 = planner's choice */
@@ -145,6 +150,12 @@ helm_status helm_request_wait(helm_request_t* req);
 /* Device bytes the handle needs for this grid and decomposition plus the
  * Krylov workspace of nrhs_chunk right-hand sides (admission control). */
 size_t helm_footprint(const helm_grid_t* grid, const helm_decomp_t* dec, int32_t nrhs_chunk);
+
+/* Device bytes of the Krylov workspace alone for nrhs_chunk right-hand sides
+ * (the part of helm_footprint that a solve on an already set-up handle
+ * allocates; released by helm_release_workspace).  0 on invalid arguments,
+ * with the reason in helm_last_error. */
+size_t helm_workspace_bytes(const helm_grid_t* grid, const helm_decomp_t* dec, int32_t nrhs_chunk);
 
 /* Device bytes the handle holds now (factors, operators, cached workspace). */
 size_t helm_resident_bytes(const helm_handle_t* h);

@@ -501,7 +501,8 @@ void validate(const helm_grid_t* g, const helm_pml_t* pml, const helm_decomp_t* 
   if (d->levels != 1 && d->levels != 2) throw HelmError(HELM_EINVAL, "levels must be 1 or 2");
   if (d->levels == 2 && d->coarse_iters < 1) throw HelmError(HELM_EINVAL, "coarse_iters must be >= 1");
   if (d->restart < 1 || d->restart > 64) throw HelmError(HELM_EINVAL, "restart must be in [1, 64]");
-  if (d->precision != HELM_FP64 && d->precision != HELM_MIXED) throw HelmError(HELM_EINVAL, "bad precision");
+  if (d->precision != HELM_FP64 && d->precision != HELM_MIXED && d->precision != HELM_SINGLE_LOCAL)
+    throw HelmError(HELM_EINVAL, "bad precision");
   const int n[3] = {g->nx, g->ny, g->nz}, p[3] = {d->px, d->py, d->pz};
   for (int a = 0; a < 3; ++a) {
     if (p[a] > 1 && n[a] / p[a] < 2 * d->overlap + 1)
@@ -515,10 +516,11 @@ constexpr int MAX_PLANE = 2048;
 void plan(helm_handle* H) {
   const helm_decomp_t& d = H->dec;
   auto cores = fine_cores(H->nx, H->ny, H->nz, d.px, d.py, d.pz);
-  plan_level(H->fine, H->nx, H->ny, H->nz, cores, d.overlap, d.precision == HELM_MIXED ? 1 : 0);
+  plan_level(H->fine, H->nx, H->ny, H->nz, cores, d.overlap, d.precision != HELM_FP64 ? 1 : 0);
   if (H->fine.bpmax > MAX_PLANE) throw HelmError(HELM_EINVAL, "subdomain plane larger than 2048 nodes");
   if (H->two_level()) {
-    plan_level(H->coarse, (H->nx + 1) / 2, (H->ny + 1) / 2, (H->nz + 1) / 2, coarse_cores(H->fine.subs), d.overlap, 0);
+    plan_level(H->coarse, (H->nx + 1) / 2, (H->ny + 1) / 2, (H->nz + 1) / 2, coarse_cores(H->fine.subs), d.overlap,
+               d.precision == HELM_SINGLE_LOCAL ? 1 : 0);
     if (H->coarse.bpmax > MAX_PLANE) throw HelmError(HELM_EINVAL, "coarse subdomain plane too large");
   }
 }
@@ -613,8 +615,8 @@ void ensure_ws(helm_handle* H, int nr) {
     W.ec.alloc(cvec);
     W.Vc.alloc(cvec * (ci + 1));
     W.Zc.alloc(cvec * ci);
-    W.yl_c.alloc((size_t)H->coarse.vec_total * nr * sizeof(z64));
-    W.tb_c.alloc((size_t)H->coarse.nsub * H->coarse.bpmax * nr * sizeof(z64));
+    W.yl_c.alloc((size_t)H->coarse.vec_total * nr * elem_size(H->coarse.prec));
+    W.tb_c.alloc((size_t)H->coarse.nsub * H->coarse.bpmax * nr * elem_size(H->coarse.prec));
     W.kc.alloc(ci, nr);
   }
   W.nr = nr;
@@ -1223,7 +1225,7 @@ void setup_impl(helm_handle* H, const void* velocity) {
     launch_build_E(op, C.nx, C.ny, C.nz, C.E.as<z64>(), H->stream);
     upload_subs(C, H->stream);
     C.aloc.alloc(sizeof(z64) * 27 * (size_t)C.nodes_total);
-    C.sinv.alloc(sizeof(z64) * (size_t)C.mat_total);
+    C.sinv.alloc(elem_size(C.prec) * (size_t)C.mat_total);
     launch_local_coarse(C.nx, C.ny, C.nz, C.E.as<z64>(), C.d_subs.as<Sub>(), C.nsub, C.maxnodes, H->c.as<z64>(), H->nx,
                         H->ny, H->omega, 2.0 * H->h, H->dec.robin, C.aloc.as<z64>(), H->stream);
     factor_level(H, C);
@@ -1412,6 +1414,25 @@ size_t helm_footprint(const helm_grid_t* grid, const helm_decomp_t* dec, int32_t
     plan(&H);
     return resident_bytes_planned(&H) + std::max(level_setup_bytes(H.fine), level_setup_bytes(H.coarse)) +
            ws_bytes(&H, std::max(1, nrhs_chunk));
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return 0;
+  }
+}
+
+size_t helm_workspace_bytes(const helm_grid_t* grid, const helm_decomp_t* dec, int32_t nrhs_chunk) {
+  try {
+    helm_pml_t pml{0, 0, 0, 0, 0};
+    validate(grid, &pml, dec);
+    if (nrhs_chunk < 1) throw HelmError(HELM_EINVAL, "nrhs_chunk must be at least 1");
+    helm_handle H;
+    H.nx = grid->nx;
+    H.ny = grid->ny;
+    H.nz = grid->nz;
+    H.n = (long long)grid->nx * grid->ny * grid->nz;
+    H.dec = *dec;
+    plan(&H);
+    return ws_bytes(&H, nrhs_chunk);
   } catch (const std::exception& e) {
     g_last_error = e.what();
     return 0;

@@ -17,11 +17,22 @@ LIB_PATH = os.path.join(_HERE, "libhelm.so")
 
 HELM_OK, HELM_NOT_CONVERGED, HELM_PENDING = 0, 1, 2
 HELM_EINVAL, HELM_ENOMEM, HELM_EDEVICE, HELM_EBREAKDOWN = -1, -2, -3, -4
-HELM_FP64, HELM_MIXED = 0, 1
+HELM_FP64, HELM_MIXED, HELM_SINGLE_LOCAL = 0, 1, 2
+PRECISIONS = {"fp64": HELM_FP64, "mixed": HELM_MIXED, "single_local": HELM_SINGLE_LOCAL}
+
+
+def _precision(name):
+    """Library code of a precision name: "fp64" (everything complex FP64), "mixed"
+    (fine local solves complex FP32) or "single_local" (local solves of both
+    levels complex FP32); Krylov, residuals and the coarse GMRES stay FP64."""
+    try:
+        return PRECISIONS[name]
+    except KeyError:
+        raise ValueError(f"precision must be one of {sorted(PRECISIONS)}, not {name!r}") from None
 HELM_X0 = 1
 
 EXPORTS = [
-    "helm_fit_weights", "helm_setup", "helm_solve", "helm_footprint", "helm_resident_bytes",
+    "helm_fit_weights", "helm_setup", "helm_solve", "helm_footprint", "helm_workspace_bytes", "helm_resident_bytes",
     "helm_last_timings", "helm_destroy", "helm_last_error", "helm_set_stream", "helm_apply_A",
     "helm_apply_M", "helm_apply_oras", "helm_restrict", "helm_prolong", "helm_apply_E", "helm_apply_Q",
     "helm_num_subdomains", "helm_subdomain_box", "helm_set_sweep_timing", "helm_sweep_stats",
@@ -81,6 +92,7 @@ def _load():
                         C.POINTER(DecompT), C.POINTER(P)], C.c_int),
         "helm_solve": ([P, i32, P, P, C.c_double, i32, C.c_uint32, P, P, P], C.c_int),
         "helm_footprint": ([C.POINTER(Grid), C.POINTER(DecompT), i32], C.c_size_t),
+        "helm_workspace_bytes": ([C.POINTER(Grid), C.POINTER(DecompT), i32], C.c_size_t),
         "helm_resident_bytes": ([P], C.c_size_t),
         "helm_last_timings": ([P, C.POINTER(C.c_double)], C.c_int),
         "helm_destroy": ([P], None),
@@ -233,9 +245,17 @@ def set_lu_panel(columns):
 
 def footprint(shape, parts, overlap=2, levels=1, coarse_iters=10, precision="fp64", restart=30, nrhs_chunk=1):
     g = Grid(*shape, 1.0)
-    d = DecompT(*parts, overlap, levels, coarse_iters, HELM_MIXED if precision == "mixed" else HELM_FP64,
+    d = DecompT(*parts, overlap, levels, coarse_iters, _precision(precision),
                 restart, 1, nrhs_chunk)
     return lib.helm_footprint(C.byref(g), C.byref(d), nrhs_chunk)
+
+
+def workspace_bytes(shape, parts, overlap=2, levels=1, coarse_iters=10, precision="fp64", restart=30, nrhs_chunk=1):
+    """Device bytes of the Krylov workspace of nrhs_chunk right-hand sides (helm_workspace_bytes)."""
+    g = Grid(*shape, 1.0)
+    d = DecompT(*parts, overlap, levels, coarse_iters, _precision(precision),
+                restart, 1, nrhs_chunk)
+    return lib.helm_workspace_bytes(C.byref(g), C.byref(d), nrhs_chunk)
 
 
 class Solver:
@@ -252,7 +272,7 @@ class Solver:
         g = Grid(nx, ny, nz, float(h))
         p = PmlT(*[int(v) for v in pml], float(R))
         d = DecompT(*[int(v) for v in parts], int(overlap), int(levels), int(coarse_iters),
-                    HELM_MIXED if precision == "mixed" else HELM_FP64, int(restart), 1 if robin else 0,
+                    _precision(precision), int(restart), 1 if robin else 0,
                     int(nrhs_chunk))
         w = None
         if weights is not None:

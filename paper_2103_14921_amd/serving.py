@@ -4,7 +4,9 @@ Requests name a problem (velocity model, grid, spacing, frequency, PML and
 decomposition) and carry right-hand sides.  The server keeps the set-up of
 every problem it has seen resident (operators, factorisations) until device
 memory is needed for something else, admits a request when its device
-footprint (``helm_footprint``) fits next to what is resident and in flight,
+footprint fits next to what is resident, in flight and idle in PyTorch's
+cache (``helm_footprint`` for a problem not yet set up, else the Krylov
+workspace ``helm_workspace_bytes``, plus the staging of B and X),
 and runs admitted work on worker threads: each resident problem has its own
 library handle and HIP stream, so solves of different problems overlap on the
 device.  Requests for the same problem and tolerance that are waiting when
@@ -51,7 +53,7 @@ class ProblemSpec:
         return int(np.prod(self.shape))
 
 
-@dataclass
+@dataclass(eq=False)  # identity: requests carry arrays, and the queue removes them one by one
 class _Request:
     spec: ProblemSpec
     B: object
@@ -154,13 +156,41 @@ class Server:
         return helm.footprint(spec.shape, spec.parts, spec.overlap, spec.levels, spec.coarse_iters, spec.precision,
                               spec.restart, nrhs)
 
+    def _workspace(self, spec, nrhs):
+        return helm.workspace_bytes(spec.shape, spec.parts, spec.overlap, spec.levels, spec.coarse_iters,
+                                    spec.precision, spec.restart, nrhs)
+
+    @staticmethod
+    def _staging(spec, nrhs):
+        # B and X of the batch on the device (complex128 each)
+        return 2 * 16 * nrhs * int(np.prod(spec.shape))
+
+    def _need(self, spec, nrhs, resident):
+        """Device bytes a batch of nrhs right-hand sides takes while in flight: the
+        whole Krylov workspace (released after every batch) when the set-up is
+        resident, else the full footprint (set-up transients included), plus the
+        staging of B and X."""
+        base = self._workspace(spec, nrhs) if resident else self._footprint(spec, nrhs)
+        return base + self._staging(spec, nrhs) + (64 << 20)
+
+    def _torch_idle(self):
+        # blocks PyTorch's caching allocator holds without using them: device
+        # memory the library cannot get while they stay cached
+        t = self.torch
+        return max(t.cuda.memory_reserved(self.device) - t.cuda.memory_allocated(self.device), 0)
+
     def _accounted(self):
-        return sum(e.resident for e in self._entries.values()) + self._inflight
+        return sum(e.resident for e in self._entries.values()) + self._inflight + self._torch_idle()
 
     def _evict_for(self, need, keep_key):
+        """Make room for need bytes (idle PyTorch cache first, then least recently
+        used set-ups); returns the accounted total with need added, or None."""
+        if self._accounted() + need > self.budget and self._torch_idle() > 0:
+            self.torch.cuda.empty_cache()
         for key in list(self._entries.keys()):  # least recently used first
-            if self._accounted() + need <= self.budget:
-                return True
+            acc = self._accounted() + need
+            if acc <= self.budget:
+                return acc
             e = self._entries[key]
             if key == keep_key or e.busy:
                 continue
@@ -168,7 +198,8 @@ class Server:
                 e.solver.close()
             del self._entries[key]
             self.stats.evictions += 1
-        return self._accounted() + need <= self.budget
+        acc = self._accounted() + need
+        return acc if acc <= self.budget else None
 
     def _loop(self):
         with self._cv:
@@ -185,23 +216,24 @@ class Server:
             e = self._entries.get(head.spec)
             if e is not None and e.busy:
                 continue
+            resident = e is not None and e.solver is not None
             batch, nr = [], 0
             for r in self._queue:
-                if (r.spec, r.tol, r.maxit) == key and (not batch or nr + r.nrhs <= self.max_batch_rhs):
+                # merge waiting requests of the same problem while the batch stays
+                # within max_batch_rhs and the device budget
+                if (r.spec, r.tol, r.maxit) == key and (not batch or (
+                        nr + r.nrhs <= self.max_batch_rhs
+                        and self._need(head.spec, nr + r.nrhs, resident) <= self.budget)):
                     batch.append(r)
                     nr += r.nrhs
-            full = self._footprint(head.spec, nr)
-            if e is not None and e.solver is not None:
-                # resident already: only the Krylov workspace of this batch
-                need = max(full - self._footprint(head.spec, 1), 0) + (64 << 20)
-            else:
-                need = full
+            need = self._need(head.spec, nr, resident)
             if need > self.budget:
                 for r in batch:
                     self._queue.remove(r)
                     r.future.set_exception(helm.HelmError(helm.HELM_ENOMEM, "request larger than the device budget"))
                 return True
-            if not self._evict_for(need, head.spec):
+            acc = self._evict_for(need, head.spec)
+            if acc is None:
                 continue
             if e is None:
                 e = _Entry(head.spec)
@@ -211,7 +243,7 @@ class Server:
             self._inflight += need
             for r in batch:
                 self._queue.remove(r)
-            self.stats.peak_accounted = max(self.stats.peak_accounted, self._accounted())
+            self.stats.peak_accounted = max(self.stats.peak_accounted, acc)
             self._pool.submit(self._work, e, batch, nr, need)
             return True
         return False

@@ -51,6 +51,20 @@ def test_footprint_grows_with_rhs_and_rejects_bad_decomposition():
     assert helm.footprint((16, 16, 16), (8, 1, 1)) == 0
 
 
+def test_workspace_bytes_is_the_rhs_dependent_part_of_the_footprint():
+    # a solve on a set-up handle allocates the Krylov workspace alone: it is the
+    # part of the footprint that grows with the batch, and less than the whole
+    from paper_2103_14921_amd import helm
+    for levels, prec in ((1, "fp64"), (2, "mixed")):
+        f = [helm.footprint((48, 40, 32), (3, 2, 2), levels=levels, precision=prec, nrhs_chunk=k) for k in (1, 8)]
+        w = [helm.workspace_bytes((48, 40, 32), (3, 2, 2), levels=levels, precision=prec, nrhs_chunk=k)
+             for k in (1, 8)]
+        assert 0 < w[0] < f[0] and w[0] < w[1]
+        assert f[1] - f[0] == w[1] - w[0]
+    assert helm.workspace_bytes((48, 40, 32), (3, 2, 2), nrhs_chunk=0) == 0
+    assert helm.workspace_bytes((16, 16, 16), (8, 1, 1)) == 0
+
+
 def test_process_wide_settings_reject_bad_values():
     from paper_2103_14921_amd import helm
     for bad in (1, 3, 16, -2):
@@ -96,3 +110,22 @@ def test_no_kernel_uses_scratch(tmp_path):
     assert len(kernels) > 40
     spilled = {k: v for k, v in kernels.items() if v != 0}
     assert not spilled, spilled
+
+
+def test_serving_admission_reserves_whole_workspace_and_staging():
+    # a batch on a resident problem allocates the full Krylov workspace (it is
+    # released after every batch) and stages B and X on the device; a problem
+    # not yet set up needs its whole footprint on top of the staging
+    from paper_2103_14921_amd import helm
+    from paper_2103_14921_amd.serving import ProblemSpec, Server
+    srv = Server.__new__(Server)  # host-side accounting only: no device, no threads
+    spec = ProblemSpec("p", (48, 40, 32), 25.0, 4.0, parts=(3, 2, 2))
+    for nr in (1, 5, 16):
+        ws = helm.workspace_bytes(spec.shape, spec.parts, spec.overlap, spec.levels, spec.coarse_iters,
+                                  spec.precision, spec.restart, nr)
+        fp = helm.footprint(spec.shape, spec.parts, spec.overlap, spec.levels, spec.coarse_iters, spec.precision,
+                            spec.restart, nr)
+        staging = 2 * 16 * nr * spec.n
+        assert srv._need(spec, nr, resident=True) >= ws + staging
+        assert srv._need(spec, nr, resident=False) >= fp + staging
+        assert srv._need(spec, nr, resident=True) < srv._need(spec, nr, resident=False)
