@@ -45,7 +45,7 @@ class ProblemSpec:
     overlap: int = 2
     levels: int = 2
     coarse_iters: int = 10
-    precision: str = "mixed"
+    precision: str = "single_local"
     restart: int = 20
 
     @property

@@ -118,9 +118,10 @@ def test_thrust128_fp64_two_level_full_size():
     _run((128, 128, 128), (4, 4, 4), (4, 2), "fp64", 1e-8, 30, None, 1e-10, [0, 21, 63], [0, 5])
 
 
-def test_thrust192_mixed_full_size():
+@pytest.mark.parametrize("prec", ["single_local", "mixed"])
+def test_thrust192_full_size(prec):
     # the benchmark workload: 192^3, 12^3 boxes of 16^3, complex-FP32 local solves, 64 sources
-    _run((192, 192, 192), (12, 12, 12), (8, 8), "mixed", 1e-6, 20, None, 2e-5, [0, 866, 1727], [0, 37, 63])
+    _run((192, 192, 192), (12, 12, 12), (8, 8), prec, 1e-6, 20, None, 2e-5, [0, 866, 1727], [0, 37, 63])
 
 
 def test_thrust256x128_q100_mixed_full_size():

@@ -126,6 +126,27 @@ def test_coarse_pieces_match_oracle():
     S.close()
 
 
+def test_single_local_coarse_oras_matches_oracle():
+    # complex-FP32 factors and sweeps on the coarse level too: the coarse
+    # one-level ORAS within single-precision rounding of the FP64 oracle, the
+    # operators around it (E, transfers) still FP64-exact
+    shape, h, c, f, pml = _thrust_case(shape=(20, 18, 17), pml=(3, 3, 3, 0))
+    say("coarse pieces single_local", shape)
+    prob = Problem(shape, h, c, f, Pml(*pml), WO)
+    A = assemble(prob)
+    tl = TwoLevel(A, shape, decompose(shape, (2, 2, 2), 2), prob.k().ravel(), h, 2)
+    S = helm().Solver(shape, h, c, f, pml, weights=W, parts=(2, 2, 2), overlap=2, levels=2, precision="single_local")
+    R = inputs.random_field((2, prob.n), seed=8)
+    Cc = S.restrict(R)
+    assert rel(S.apply_E(Cc), (tl.E @ Cc.T).T) <= 1e-12
+    Zc = S.apply_oras(Cc, level=1)
+    Zf = S.apply_oras(R, level=0)
+    for r in range(2):
+        assert rel(Zc[r], tl.coarse.apply(Cc[r])) <= 5e-4
+        assert rel(Zf[r], tl.fine.apply(R[r])) <= 5e-4
+    S.close()
+
+
 @pytest.mark.parametrize("nrhs", [2, 12])
 def test_coarse_operator_batches_match_oracle(nrhs):
     # coarse product E x on batches below and above the row-tiled threshold,
@@ -261,9 +282,10 @@ def test_batch_narrowing_with_iteration_limit_and_initial_guess():
     S.close()
 
 
-def test_mixed_precision_reaches_fp64_residual():
+@pytest.mark.parametrize("prec", ["mixed", "single_local"])
+def test_mixed_precision_reaches_fp64_residual(prec):
     shape, h, f = (28, 26, 24), 25.0, 10.0
-    say("mixed e2e", shape)
+    say("mixed e2e", shape, prec)
     c = inputs.velocity_thrust_belt(*shape, h=h)
     src = inputs.source_grid(shape[0], shape[1], 5, 5, 2, 2, iz=4)
     b = inputs.point_source_rhs(*shape, src)
@@ -272,9 +294,9 @@ def test_mixed_precision_reaches_fp64_residual():
     S64 = helm().Solver(shape, h, c, f, (5, 5, 5, 0), weights=W, parts=(2, 2, 2), overlap=2, levels=2, restart=20)
     X64, i64 = S64.solve(b, tol=1e-10, maxit=300)
     S = helm().Solver(shape, h, c, f, (5, 5, 5, 0), weights=W, parts=(2, 2, 2), overlap=2, levels=2, restart=20,
-                      precision="mixed")
+                      precision=prec)
     X, info = S.solve(b, tol=1e-6, maxit=300)
-    say("mixed iters", info["iters"], "fp64(1e-10) iters", i64["iters"])
+    say(prec, "iters", info["iters"], "fp64(1e-10) iters", i64["iters"])
     for r in range(len(src)):
         tr = np.linalg.norm(b[r].ravel() - A @ X[r].ravel()) / np.linalg.norm(b[r])
         assert tr <= 1e-6 and info["relres_true"][r] <= 1e-6
