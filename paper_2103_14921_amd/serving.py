@@ -165,13 +165,27 @@ class Server:
         # B and X of the batch on the device (complex128 each)
         return 2 * 16 * nrhs * int(np.prod(spec.shape))
 
-    def _need(self, spec, nrhs, resident):
-        """Device bytes a batch of nrhs right-hand sides takes while in flight: the
-        whole Krylov workspace (released after every batch) when the set-up is
-        resident, else the full footprint (set-up transients included), plus the
-        staging of B and X."""
-        base = self._workspace(spec, nrhs) if resident else self._footprint(spec, nrhs)
+    def _need(self, spec, nrhs, resident, chunk=None):
+        """Device bytes a batch of nrhs right-hand sides takes while in flight when
+        the library solves chunk of them at a time (all by default): the whole
+        Krylov workspace of a chunk (released after every batch) when the set-up
+        is resident, else the full footprint (set-up transients included), plus
+        the staging of B and X."""
+        k = min(chunk or nrhs, nrhs)
+        base = self._workspace(spec, k) if resident else self._footprint(spec, k)
         return base + self._staging(spec, nrhs) + (64 << 20)
+
+    def _largest_chunk(self, spec, nrhs, resident):
+        """Most right-hand sides per library solve that keep a request of nrhs
+        within the budget (0: not even one)."""
+        lo, hi = 0, nrhs
+        while lo < hi:
+            mid = (lo + hi + 1) // 2
+            if self._need(spec, nrhs, resident, mid) <= self.budget:
+                lo = mid
+            else:
+                hi = mid - 1
+        return lo
 
     def _torch_idle(self):
         # blocks PyTorch's caching allocator holds without using them: device
@@ -226,12 +240,17 @@ class Server:
                         and self._need(head.spec, nr + r.nrhs, resident) <= self.budget)):
                     batch.append(r)
                     nr += r.nrhs
+            chunk = nr
             need = self._need(head.spec, nr, resident)
             if need > self.budget:
-                for r in batch:
-                    self._queue.remove(r)
-                    r.future.set_exception(helm.HelmError(helm.HELM_ENOMEM, "request larger than the device budget"))
-                return True
+                # a single request too large to solve at once: solve it in chunks
+                # of right-hand sides, one after another on its handle
+                chunk = self._largest_chunk(head.spec, nr, resident)
+                if chunk == 0:
+                    self._queue.remove(head)
+                    head.future.set_exception(helm.HelmError(helm.HELM_ENOMEM, "request larger than the device budget"))
+                    return True
+                need = self._need(head.spec, nr, resident, chunk)
             acc = self._evict_for(need, head.spec)
             if acc is None:
                 continue
@@ -244,11 +263,11 @@ class Server:
             for r in batch:
                 self._queue.remove(r)
             self.stats.peak_accounted = max(self.stats.peak_accounted, acc)
-            self._pool.submit(self._work, e, batch, nr, need)
+            self._pool.submit(self._work, e, batch, nr, need, chunk)
             return True
         return False
 
-    def _work(self, e, batch, nr, reserved):
+    def _work(self, e, batch, nr, reserved, chunk):
         torch = self.torch
         try:
             spec = e.spec
@@ -267,18 +286,30 @@ class Server:
                 return torch.cat(parts, 0).contiguous() if len(parts) > 1 else parts[0].contiguous()
 
             Bd = helm.torch_alloc(stage)
-            X, info = e.solver.solve(Bd, tol=batch[0].tol, maxit=batch[0].maxit)
-            e.solver.release_workspace()
-            del Bd
             # a request gets X where its B was: host arrays come back as host
             # arrays, so delivered results hold no device memory outside the
             # admission accounting
-            outs, i0 = [], 0
-            for r in batch:
-                Xr = X[i0:i0 + r.nrhs]
-                i0 += r.nrhs
-                outs.append(Xr.clone() if helm._is_torch(r.B) else Xr.cpu().numpy())
-            del X
+            if chunk >= nr:
+                X, info = e.solver.solve(Bd, tol=batch[0].tol, maxit=batch[0].maxit)
+                outs, i0 = [], 0
+                for r in batch:
+                    Xr = X[i0:i0 + r.nrhs]
+                    i0 += r.nrhs
+                    outs.append(Xr.clone() if helm._is_torch(r.B) else Xr.cpu().numpy())
+                del X
+            else:  # one request, solved chunk right-hand sides at a time
+                parts, infos = [], []
+                for i0 in range(0, nr, chunk):
+                    Xi, inf = e.solver.solve(Bd[i0:i0 + chunk], tol=batch[0].tol, maxit=batch[0].maxit)
+                    parts.append(Xi if helm._is_torch(batch[0].B) else Xi.cpu().numpy())
+                    infos.append(inf)
+                    del Xi
+                outs = [torch.cat(parts, 0) if helm._is_torch(batch[0].B) else np.concatenate(parts, 0)]
+                info = {"iters": np.concatenate([i["iters"] for i in infos]),
+                        "relres_true": np.concatenate([i["relres_true"] for i in infos]),
+                        "status": max((i["status"] for i in infos), key=abs)}
+            e.solver.release_workspace()
+            del Bd
             done = time.perf_counter()
             i0 = 0
             with self._cv:

@@ -129,3 +129,16 @@ def test_serving_admission_reserves_whole_workspace_and_staging():
         assert srv._need(spec, nr, resident=True) >= ws + staging
         assert srv._need(spec, nr, resident=False) >= fp + staging
         assert srv._need(spec, nr, resident=True) < srv._need(spec, nr, resident=False)
+
+
+def test_serving_splits_a_request_that_does_not_fit_into_chunks():
+    from paper_2103_14921_amd.serving import ProblemSpec, Server
+    srv = Server.__new__(Server)
+    spec = ProblemSpec("p", (48, 40, 32), 25.0, 4.0, parts=(3, 2, 2))
+    for resident in (True, False):
+        srv.budget = srv._need(spec, 9, resident, chunk=3)
+        assert srv._largest_chunk(spec, 9, resident) == 3
+        srv.budget -= 1
+        assert srv._largest_chunk(spec, 9, resident) == 2
+    srv.budget = srv._staging(spec, 9)  # not even one right-hand side fits
+    assert srv._largest_chunk(spec, 9, True) == 0

@@ -87,6 +87,35 @@ def test_admission_respects_the_budget():
     assert evictions >= 1
 
 
+def test_request_larger_than_the_budget_is_solved_in_chunks():
+    # a 7-RHS request whose whole workspace does not fit the budget is solved a
+    # few right-hand sides at a time on its handle; every right-hand side
+    # matches the unconstrained solve
+    from paper_2103_14921_amd.serving import Server
+    specs, vel = _catalogue()
+    spec = specs[0]
+    nx, ny, nz = spec.shape
+    rng = np.random.default_rng(21)
+    src = np.stack([rng.integers(6, nx - 6, 7), rng.integers(6, ny - 6, 7), np.full(7, 4)], axis=1)
+    B = inputs.point_source_rhs(nx, ny, nz, src).reshape(7, -1)
+    free = Server(vel, workers=1)
+    ref = free.submit(spec, B, TOL).result()
+    free.close()
+    probe = Server.__new__(Server)
+    budget = probe._need(spec, 7, resident=False, chunk=2) + 1
+    assert probe._need(spec, 7, resident=False) > budget
+    print("[case] serving chunked, budget", budget, flush=True)
+    srv = Server(vel, budget_bytes=budget, workers=1)
+    got = srv.submit(spec, B, TOL).result()
+    peak = srv.stats.peak_accounted
+    srv.close()
+    assert got["X"].shape == B.shape and got["batch_rhs"] == 7
+    assert np.all(got["relres_true"] <= TOL)
+    assert peak <= budget
+    rel = np.linalg.norm(got["X"] - ref["X"], axis=1) / np.linalg.norm(ref["X"], axis=1)
+    assert np.all(rel <= 10 * TOL), rel
+
+
 def test_async_solves_overlap_and_match_sync():
     # helm_solve_async on two handles at once: each result is bitwise the
     # synchronous result of its handle; a handle with a request in flight
