@@ -148,10 +148,10 @@ WORKLOADS = {
         shape=(128, 128, 128), h=25.0, freq=10.0, model="thrust", npml=(10, 10, 10, 0),
         parts=(4, 4, 4), delta=2, levels=2, restart=30, tol=1e-8, sources=(4, 2),
         precision="fp64"),
-    "c3_thrust192": dict(
+    "c3_thrust192_mixed": dict(
         shape=(192, 192, 192), h=25.0, freq=10.0, model="thrust", npml=(10, 10, 10, 0),
         parts=(12, 12, 12), delta=2, levels=2, restart=20, tol=1e-6, sources=(8, 8),
-        precision="single_local"),
+        precision="mixed"),
     "c5_thrust256_q100": dict(
         shape=(256, 256, 128), h=25.0, freq=10.0, model="thrust_q100", npml=(10, 10, 10, 0),
         parts=(16, 16, 8), delta=2, levels=2, restart=20, tol=1e-6, sources=(16, 8),

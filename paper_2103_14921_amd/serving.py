@@ -45,7 +45,7 @@ class ProblemSpec:
     overlap: int = 2
     levels: int = 2
     coarse_iters: int = 10
-    precision: str = "single_local"
+    precision: str = "mixed"
     restart: int = 20
 
     @property
