@@ -246,9 +246,10 @@ class Server:
                 # a single request too large to solve at once: solve it in chunks
                 # of right-hand sides, one after another on its handle
                 chunk = self._largest_chunk(head.spec, nr, resident)
-                if chunk == 0:
-                    self._queue.remove(head)
-                    head.future.set_exception(helm.HelmError(helm.HELM_ENOMEM, "request larger than the device budget"))
+                if chunk == 0:  # the batch is one request (merges were checked against the budget)
+                    big = batch[0]
+                    self._queue.remove(big)
+                    big.future.set_exception(helm.HelmError(helm.HELM_ENOMEM, "request larger than the device budget"))
                     return True
                 need = self._need(head.spec, nr, resident, chunk)
             acc = self._evict_for(need, head.spec)
