@@ -347,19 +347,28 @@ def run_poisson(server, requests, rate_hz, seed=4, progress=None):
     t0 = time.perf_counter()
     futs = []
     t_next = t0
+    done = [0]
+    lock = threading.Lock()
+
+    def report(_):  # progress as requests complete, also while later ones are still arriving
+        with lock:
+            done[0] += 1
+            if progress:
+                progress(done[0], len(requests))
+
     for (spec, B, tol), gap in zip(requests, gaps):
         t_next += gap
         dt = t_next - time.perf_counter()
         if dt > 0:
             time.sleep(dt)
-        futs.append(server.submit(spec, B, tol))
+        f = server.submit(spec, B, tol)
+        f.add_done_callback(report)
+        futs.append(f)
     results = []
-    for i, f in enumerate(futs):
+    for f in futs:
         r = dict(f.result())
         r["nrhs"] = int(r.pop("X").shape[0])  # the stream's figures need no solutions
         results.append(r)
-        if progress:
-            progress(i + 1, len(futs))
     elapsed = time.perf_counter() - t0
     rhs = sum(r["nrhs"] for r in results)
     out = {"elapsed_s": elapsed, "rhs": rhs, "rhs_per_s": rhs / elapsed, "requests": len(results),

@@ -142,3 +142,35 @@ def test_serving_splits_a_request_that_does_not_fit_into_chunks():
         assert srv._largest_chunk(spec, 9, resident) == 2
     srv.budget = srv._staging(spec, 9)  # not even one right-hand side fits
     assert srv._largest_chunk(spec, 9, True) == 0
+
+
+def test_poisson_stream_reports_each_completion_once():
+    # progress comes from completions as they happen (also while later requests
+    # are still arriving), once per request, and the results keep submission order
+    import threading
+    from concurrent.futures import Future
+
+    import numpy as np
+    from paper_2103_14921_amd.serving import run_poisson
+
+    class Fake:
+        def __init__(self):
+            self.stats = type("S", (), {"latencies": [0.1, 0.2, 0.3]})()
+
+        def submit(self, spec, B, tol):
+            f = Future()
+            threading.Timer(0.01 * (3 - spec), lambda: f.set_result({"X": B, "iters": np.array([spec])})).start()
+            return f
+
+        def latency_percentiles(self):
+            return {"p50_s": 0.2, "p99_s": 0.3, "mean_s": 0.2, "max_s": 0.3}
+
+    seen = []
+    out = run_poisson(Fake(), [(k, np.zeros((k + 1, 4)), 1e-6) for k in range(3)], rate_hz=1000.0,
+                      progress=lambda i, n: seen.append((i, n)))
+    import time
+    t0 = time.time()
+    while len(seen) < 3 and time.time() - t0 < 5:  # a callback may still be running as result() returns
+        time.sleep(0.01)
+    assert sorted(seen) == [(1, 3), (2, 3), (3, 3)]
+    assert [r["nrhs"] for r in out["results"]] == [1, 2, 3]

@@ -51,9 +51,11 @@ def _same(a, b, tag):
     assert torch.equal(Xa, Xb), (tag, float((Xa - Xb).abs().max()))
 
 
-def test_two_level_mixed_graphs_bitwise_equal_direct():
+@pytest.mark.parametrize("prec", ["mixed", "single_local"])
+def test_two_level_mixed_graphs_bitwise_equal_direct(prec):
     shape = (48, 48, 48)
-    g, d, dev = _pair(shape, (3, 3, 3), 2, "mixed", 6)
+    say("graphs", prec)
+    g, d, dev = _pair(shape, (3, 3, 3), 2, prec, 6)
     # 12 RHS: the sweep tuner runs in the first iteration, the rest is captured;
     # restart 6 makes every captured iteration replay in later cycles
     for tag, grid, shift in (("solve 12 rhs", (4, 3), 0), ("again, new rhs", (3, 4), 2), ("5 rhs", (5, 1), 1)):

@@ -57,7 +57,8 @@ def test_fine_sweep_variants_match_oracle(policy, prec, tol, nrhs):
 
 
 @pytest.mark.parametrize("policy", ["item", "pipelined"])
-def test_coarse_sweep_variants_match_oracle(policy):
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("single_local", 5e-4)])
+def test_coarse_sweep_variants_match_oracle(policy, prec, tol):
     from paper_2103_14921_amd import helm
     helm.set_sweep_policy(policy)
     shape, h, f, pml = (28, 26, 24), 25.0, 10.0, (5, 5, 5, 0)
@@ -65,12 +66,12 @@ def test_coarse_sweep_variants_match_oracle(policy):
     prob = Problem(shape, h, c, f, Pml(*pml), WO)
     A = assemble(prob)
     tl = TwoLevel(A, shape, decompose(shape, (2, 2, 2), 2), prob.k().ravel(), h, 2)
-    say("coarse sweep", policy)
-    S = helm.Solver(shape, h, c, f, pml, weights=W, parts=(2, 2, 2), overlap=2, levels=2)
+    say("coarse sweep", policy, prec)
+    S = helm.Solver(shape, h, c, f, pml, weights=W, parts=(2, 2, 2), overlap=2, levels=2, precision=prec)
     Cc = inputs.random_field((20, S.nc), seed=77)
     Zc = S.apply_oras(Cc, level=1)
     for r in range(20):
-        assert rel(Zc[r], tl.coarse.apply(Cc[r])) <= 1e-10, r
+        assert rel(Zc[r], tl.coarse.apply(Cc[r])) <= tol, r
     S.close()
 
 
