@@ -188,7 +188,7 @@ def serving_phase(n_requests, max_rhs=64, seed=4):
     return {"requests": out["requests"], "calibration_requests": ncal, "rate_hz": 0.8 * capacity,
             "p50_s": out["p50_s"], "p99_s": out["p99_s"], "mean_s": out["mean_s"], "rhs_per_s": out["rhs_per_s"],
             "rhs": out["rhs"], "elapsed_s": out["elapsed_s"], "setups": st.setups, "evictions": st.evictions,
-            "batches": st.batches, "max_true_relres": worst}
+            "batches": st.batches, "retries": st.retries, "max_true_relres": worst}
 
 
 def main():

@@ -157,7 +157,9 @@ size_t helm_footprint(const helm_grid_t* grid, const helm_decomp_t* dec, int32_t
  * with the reason in helm_last_error. */
 size_t helm_workspace_bytes(const helm_grid_t* grid, const helm_decomp_t* dec, int32_t nrhs_chunk);
 
-/* Device bytes the handle holds now (factors, operators, cached workspace). */
+/* Device bytes the handle holds now (factors, operators, cached workspace):
+ * the sizes of the blocks it was given, which the library's device cache may
+ * round up by as much as an eighth of a request. */
 size_t helm_resident_bytes(const helm_handle_t* h);
 
 /* Timings of the last setup / solve in seconds, measured with HIP events on the

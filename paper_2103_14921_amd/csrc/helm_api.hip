@@ -1441,7 +1441,24 @@ size_t helm_workspace_bytes(const helm_grid_t* grid, const helm_decomp_t* dec, i
 
 size_t helm_resident_bytes(const helm_handle_t* H) {
   if (!H) return 0;
-  return resident_bytes_planned(H) + (H->ws.nr > 0 ? ws_bytes(H, H->ws.nr) : 0);
+  // the blocks actually held: the device cache may hand out a block up to an
+  // eighth larger than asked for, so this can exceed the planned bytes
+  size_t b = 0;
+  for (const DevBuf* d : {&H->c, &H->sigma, &H->xi_int, &H->xi_half, &H->i2_int, &H->i2_half, &H->flat, &H->vmax,
+                          &H->err})
+    b += d->bytes;
+  for (const Level* L : {&H->fine, &H->coarse})
+    for (const DevBuf* d : {&L->d_subs, &L->aloc, &L->sinv, &L->E, &L->cpl}) b += d->bytes;
+  const Workspace& W = H->ws;
+  for (const DevBuf* d : {&W.b, &W.x, &W.w, &W.V, &W.Zv, &W.q, &W.t, &W.cc, &W.Vc, &W.Zc, &W.wc, &W.ec, &W.yl_f,
+                          &W.tb_f, &W.yl_c, &W.tb_c, &W.zpart, &W.dpart, &W.bn2, &W.beta2, &W.cols})
+    b += d->bytes;
+  for (const KrylovArrays* k : {&W.ko, &W.kc})
+    for (const DevBuf* d : {&k->Rm, &k->g, &k->cs, &k->sn, &k->y, &k->h, &k->h2, &k->nrm2, &k->w0, &k->w1, &k->bnorm,
+                            &k->beta, &k->est, &k->fac, &k->it, &k->kc, &k->active, &k->done, &k->conv, &k->counter,
+                            &k->skip, &k->extra})
+      b += d->bytes;
+  return b;
 }
 
 helm_status helm_last_timings(const helm_handle_t* H, double out[5]) {

@@ -81,6 +81,7 @@ class ServerStats:
     setups: int = 0
     evictions: int = 0
     peak_accounted: int = 0
+    retries: int = 0  # batches put back in the queue after the device ran short
 
 
 class Server:
@@ -106,6 +107,7 @@ class Server:
         self._queue = collections.deque()
         self._entries = collections.OrderedDict()
         self._inflight = 0
+        self._hold = False  # after a batch was put back: launch nothing until another one ends
         self._closed = False
         self.stats = ServerStats()
         self._sched = threading.Thread(target=self._loop, daemon=True)
@@ -173,7 +175,9 @@ class Server:
         the staging of B and X."""
         k = min(chunk or nrhs, nrhs)
         base = self._workspace(spec, k) if resident else self._footprint(spec, k)
-        return base + self._staging(spec, nrhs) + (64 << 20)
+        # the library's device cache may hand out blocks up to an eighth larger
+        # than asked for: reserve for that
+        return base + base // 8 + self._staging(spec, nrhs) + (64 << 20)
 
     def _largest_chunk(self, spec, nrhs, resident):
         """Most right-hand sides per library solve that keep a request of nrhs
@@ -225,6 +229,8 @@ class Server:
                     self._cv.wait(0.05)
 
     def _try_launch(self):
+        if self._hold:
+            return False
         for head in list(self._queue):
             key = (head.spec, head.tol, head.maxit)
             e = self._entries.get(head.spec)
@@ -270,6 +276,7 @@ class Server:
 
     def _work(self, e, batch, nr, reserved, chunk):
         torch = self.torch
+        retried = False
         try:
             spec = e.spec
             if e.solver is None:
@@ -323,13 +330,31 @@ class Server:
                     self.stats.latencies.append(lat)
                     r.future.set_result({"X": Xr, "iters": info["iters"][sl], "relres_true": info["relres_true"][sl],
                                          "status": info["status"], "latency_s": lat, "batch_rhs": nr})
-        except Exception as exc:  # report the failure on every request of the batch
+        except Exception as exc:
+            short = (isinstance(exc, helm.HelmError) and exc.code == helm.HELM_ENOMEM) or \
+                isinstance(exc, torch.OutOfMemoryError)
+            if e.solver is not None:
+                try:  # whatever workspace the failed solve had taken
+                    e.solver.release_workspace()
+                except helm.HelmError:
+                    pass
             with self._cv:
-                for r in batch:
-                    if not r.future.done():
-                        r.future.set_exception(exc)
+                others = any(x.busy for x in self._entries.values() if x is not e)
+                if short and others:
+                    # the device ran short while other batches are in flight (the
+                    # footprints are estimates): put the batch back at the head of
+                    # the queue and try again once one of the others has ended
+                    for r in reversed(batch):
+                        self._queue.appendleft(r)
+                    self.stats.retries += 1
+                    retried = True
+                else:  # report the failure on every request of the batch
+                    for r in batch:
+                        if not r.future.done():
+                            r.future.set_exception(exc)
         finally:
             with self._cv:
+                self._hold = retried
                 e.resident = e.solver.resident_bytes() if e.solver is not None else 0
                 e.busy = False
                 e.last_used = time.perf_counter()
