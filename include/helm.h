@@ -187,6 +187,16 @@ helm_status helm_solve_bound(const helm_handle_t* h, double out[3]);
 helm_status helm_set_sweep_timing(helm_handle_t* h, int32_t enable);
 helm_status helm_sweep_stats(const helm_handle_t* h, int32_t level, double out[4]);
 
+/* With the same timing on, the fine-grid 27-point products of eq. eq1 inside
+ * solves are bracketed too: helm_stencil_stats gives, for kind 0 (y = A x,
+ * the Arnoldi product) or 1 (y = b - A x: the (I - A Q) term of eq. 2lvl and
+ * the true residuals), out[0] launches, out[1] total milliseconds, out[2]
+ * algorithmic real flops (27 complex multiply-adds per node and right-hand
+ * side) and out[3] algorithmic bytes (16 B per node and right-hand side for
+ * x read and y written, and for b in a residual, plus 16 B per node for
+ * s k^2), summed since timing was enabled. */
+helm_status helm_stencil_stats(const helm_handle_t* h, int32_t kind, double out[4]);
+
 /* Captured iterations (batching form).  With graphs enabled (the default),
  * each outer FGMRES iteration -- the two-level preconditioner of eq. 2lvl with
  * its ten inner coarse GMRES iterations, the operator product and the Arnoldi

@@ -338,6 +338,10 @@ struct Workspace {
   KrylovArrays ko, kc;
 };
 
+// Launches timed live when sweep timing is on: 0 fine sweep, 1 coarse sweep,
+// 2 fine product y = A x, 3 fine residual y = b - A x.
+constexpr int NTIMED = 4;
+
 // One outer FGMRES iteration (preconditioner, operator, Arnoldi step) captured
 // as an executable HIP graph.  Kernel arguments are baked in, so an entry is
 // valid for one iteration index, batch width, tolerance, iteration limit and
@@ -349,14 +353,14 @@ struct Captured {
   unsigned gen = 0;
   bool timed = false;
   hipGraphExec_t exec = nullptr;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[2];
-  std::vector<double> fl[2], by[2];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[NTIMED];
+  std::vector<double> fl[NTIMED], by[NTIMED];
   bool pending = false;  // replayed with timing, events not yet read
   WorkBound work;        // algorithmic work of one replay
 
   ~Captured() {
     if (exec) (void)hipGraphExecDestroy(exec);
-    for (int lv = 0; lv < 2; ++lv)
+    for (int lv = 0; lv < NTIMED; ++lv)
       for (auto& e : ev[lv]) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
@@ -380,9 +384,10 @@ struct helm_handle {
   double t_setup = 0, t_solve = 0, t_fact = 0, t_coarse = 0, its = 0;
   // live timing of the local-solve sweeps (HIP events around each launch, per level)
   bool timing = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> sweep_ev[2];
-  std::vector<double> sweep_flops[2], sweep_bytes[2];
-  double sweep_stat[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // launches, ms, flops, bytes
+  // (slots: 0 fine sweep, 1 coarse sweep, 2 fine product A x, 3 fine residual b - A x)
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> sweep_ev[NTIMED];
+  std::vector<double> sweep_flops[NTIMED], sweep_bytes[NTIMED];
+  double sweep_stat[NTIMED][4] = {};  // launches, ms, flops, bytes
   // captured outer iterations
   bool graphs = true;
   bool graph_timing = true;  // event-record nodes accepted inside captured graphs
@@ -553,7 +558,7 @@ size_t resident_bytes_planned(const helm_handle* H) {
 void harvest_graphs(helm_handle* H) {
   for (auto& c : H->captured) {
     if (!c->pending) continue;
-    for (int lv = 0; lv < 2; ++lv)
+    for (int lv = 0; lv < NTIMED; ++lv)
       for (size_t i = 0; i < c->ev[lv].size(); ++i) {
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, c->ev[lv][i].first, c->ev[lv][i].second);
@@ -695,9 +700,37 @@ void oras_apply(helm_handle* H, Level& L, int nr, const z64* u, z64* z, const z6
   }
 }
 
+// The fine 27-point product y = A x, or y = b - A x when b is given; with
+// timing on, bracketed by events like the sweeps (slot 2 or 3) with its
+// algorithmic work: x read and y written once, b read once for a residual,
+// s k^2 once per node; 27 complex multiply-adds per node and right-hand side.
+void fine_product(helm_handle* H, int nr, const z64* b, const z64* x, z64* y) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (H->timing) {
+    HELM_CHECK_HIP(hipEventCreate(&e0));
+    HELM_CHECK_HIP(hipEventCreate(&e1));
+    record_timing_event(H, e0);
+  }
+  if (b)
+    launch_residual(H->op, nr, b, x, y, H->stream);
+  else
+    launch_stencil(H->op, nr, x, y, H->stream);
+  if (H->timing) {
+    record_timing_event(H, e1);
+    const int slot = b ? 3 : 2;
+    const double n = (double)H->n;
+    auto& ev = H->capturing ? H->capturing->ev[slot] : H->sweep_ev[slot];
+    auto& fl = H->capturing ? H->capturing->fl[slot] : H->sweep_flops[slot];
+    auto& bb = H->capturing ? H->capturing->by[slot] : H->sweep_bytes[slot];
+    ev.push_back({e0, e1});
+    fl.push_back(216.0 * n * nr);
+    bb.push_back(16.0 * n * nr * (b ? 3 : 2) + 16.0 * n);
+  }
+}
+
 // Fold the recorded sweep events into the statistics (the stream has been synchronised).
 void collect_sweep_timing(helm_handle* H) {
-  for (int lv = 0; lv < 2; ++lv) {
+  for (int lv = 0; lv < NTIMED; ++lv) {
     for (size_t i = 0; i < H->sweep_ev[lv].size(); ++i) {
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, H->sweep_ev[lv][i].first, H->sweep_ev[lv][i].second);
@@ -790,7 +823,7 @@ void precond(helm_handle* H, int nr, const z64* v, z64* z) {
     return;
   }
   coarse_correction(H, nr, v, W.q.as<z64>());
-  launch_residual(H->op, nr, v, W.q.as<z64>(), W.t.as<z64>(), H->stream);  // t = v - A q
+  fine_product(H, nr, v, W.q.as<z64>(), W.t.as<z64>());  // t = v - A q
   oras_apply(H, H->fine, nr, W.t.as<z64>(), z, W.q.as<z64>(), W.yl_f.p, W.tb_f.p);
 }
 
@@ -815,7 +848,7 @@ void outer_step(helm_handle* H, int nr, int j, double tol, int maxit) {
   z64* vj = W.V.as<z64>() + j * vs;
   z64* zj = W.Zv.as<z64>() + j * vs;
   precond(H, nr, vj, zj);
-  launch_stencil(H->op, nr, zj, W.w.as<z64>(), H->stream);
+  fine_product(H, nr, nullptr, zj, W.w.as<z64>());
   zero_counter(H, W.ko);
   arnoldi_step(H, W.ko, j, W.V.as<z64>(), W.w.as<z64>(), H->n, nr, tol, maxit, 0);
 }
@@ -1045,7 +1078,7 @@ void fgmres_chunk(helm_handle* H, int nr, double tol, int maxit, bool x0, void* 
   launch_norm2(W.b.as<z64>(), n, nr, W.dpart.as<double>(), W.bn2.as<double>(), H->stream);
   launch_krylov_init(K.st, W.bn2.as<double>(), H->stream);
   if (x0) {
-    launch_residual(H->op, nr, W.b.as<z64>(), W.x.as<z64>(), W.w.as<z64>(), H->stream);
+    fine_product(H, nr, W.b.as<z64>(), W.x.as<z64>(), W.w.as<z64>());
   } else {
     launch_fill(W.x.as<z64>(), n * nr, H->stream);
     launch_copy(W.b.as<z64>(), W.w.as<z64>(), n * nr, H->stream);
@@ -1065,7 +1098,7 @@ void fgmres_chunk(helm_handle* H, int nr, double tol, int maxit, bool x0, void* 
     }
     launch_backsolve(K.st, H->stream);
     launch_update(W.Zv.as<z64>(), vs, m, K.y.as<z64>(), W.x.as<z64>(), n, nr, H->stream);
-    launch_residual(H->op, nr, W.b.as<z64>(), W.x.as<z64>(), W.w.as<z64>(), H->stream);
+    fine_product(H, nr, W.b.as<z64>(), W.x.as<z64>(), W.w.as<z64>());
     launch_norm2(W.w.as<z64>(), n, nr, W.dpart.as<double>(), W.beta2.as<double>(), H->stream);
     zero_counter(H, K);
     launch_cycle_start(K.st, W.beta2.as<double>(), tol, maxit, 0, H->stream);
@@ -1558,7 +1591,7 @@ helm_status helm_release_workspace(helm_handle_t* H) {
 helm_status helm_set_sweep_timing(helm_handle_t* H, int32_t enable) {
   if (!H) return fail(HELM_EINVAL, "null handle");
   H->timing = enable != 0;
-  for (int lv = 0; lv < 2; ++lv)
+  for (int lv = 0; lv < NTIMED; ++lv)
     for (int i = 0; i < 4; ++i) H->sweep_stat[lv][i] = 0;
   return HELM_OK;
 }
@@ -1606,6 +1639,12 @@ helm_status helm_graph_stats(const helm_handle_t* H, double out[2]) {
 helm_status helm_sweep_stats(const helm_handle_t* H, int32_t level, double out[4]) {
   if (!H || !out || level < 0 || level > 1) return fail(HELM_EINVAL, "bad arguments");
   for (int i = 0; i < 4; ++i) out[i] = H->sweep_stat[level][i];
+  return HELM_OK;
+}
+
+helm_status helm_stencil_stats(const helm_handle_t* H, int32_t kind, double out[4]) {
+  if (!H || !out || kind < 0 || kind > 1) return fail(HELM_EINVAL, "bad arguments");
+  for (int i = 0; i < 4; ++i) out[i] = H->sweep_stat[2 + kind][i];
   return HELM_OK;
 }
 

@@ -35,7 +35,7 @@ EXPORTS = [
     "helm_fit_weights", "helm_setup", "helm_solve", "helm_footprint", "helm_workspace_bytes", "helm_resident_bytes",
     "helm_last_timings", "helm_destroy", "helm_last_error", "helm_set_stream", "helm_apply_A",
     "helm_apply_M", "helm_apply_oras", "helm_restrict", "helm_prolong", "helm_apply_E", "helm_apply_Q",
-    "helm_num_subdomains", "helm_subdomain_box", "helm_set_sweep_timing", "helm_sweep_stats",
+    "helm_num_subdomains", "helm_subdomain_box", "helm_set_sweep_timing", "helm_sweep_stats", "helm_stencil_stats",
     "helm_local_solve", "helm_release_workspace", "helm_trim_cache", "helm_set_graphs", "helm_graph_stats",
     "helm_set_sweep_policy",
     "helm_set_row_tiling",
@@ -109,6 +109,7 @@ def _load():
         "helm_subdomain_box": ([P, i32, i32, C.POINTER(i32)], C.c_int),
         "helm_set_sweep_timing": ([P, i32], C.c_int),
         "helm_sweep_stats": ([P, i32, C.POINTER(C.c_double)], C.c_int),
+        "helm_stencil_stats": ([P, i32, C.POINTER(C.c_double)], C.c_int),
         "helm_local_solve": ([P, i32, i32, i32, P, P], C.c_int),
         "helm_release_workspace": ([P], C.c_int),
         "helm_trim_cache": ([], C.c_size_t),
@@ -340,6 +341,12 @@ class Solver:
     def sweep_stats(self, level=0):
         out = (C.c_double * 4)()
         _check(lib.helm_sweep_stats(self._h, int(level), out))
+        return dict(launches=int(out[0]), ms=out[1], flops=out[2], bytes=out[3])
+
+    def stencil_stats(self, kind=0):
+        """Timed fine 27-point products of the solves: kind 0 y = A x, 1 y = b - A x."""
+        out = (C.c_double * 4)()
+        _check(lib.helm_stencil_stats(self._h, int(kind), out))
         return dict(launches=int(out[0]), ms=out[1], flops=out[2], bytes=out[3])
 
     def set_graphs(self, enable=True):

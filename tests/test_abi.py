@@ -174,3 +174,20 @@ def test_poisson_stream_reports_each_completion_once():
         time.sleep(0.01)
     assert sorted(seen) == [(1, 3), (2, 3), (3, 3)]
     assert [r["nrhs"] for r in out["results"]] == [1, 2, 3]
+
+
+def test_bench_module_imports_and_summarises_timings():
+    # bench.py imports without a GPU (its work is under main()) and turns live
+    # timings into roofline entries
+    import importlib
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    bench = importlib.import_module("bench")
+    assert "thrust192_mixed" in bench.WORKLOADS and "thrust192_single_local" in bench.WORKLOADS
+    e = bench.stencil_entry([{"launches": 2, "ms": 4.0, "flops": 1.0, "bytes": 16e9},
+                             {"launches": 1, "ms": 2.0, "flops": 1.0, "bytes": 12e9}])
+    assert e["bound"] == "hbm" and abs(e["A_x"]["achieved"] - 4000.0) < 1e-9
+    assert abs(e["achieved"] - 28e9 / 6.0 * 1e-6) < 1e-6 and abs(e["frac"] - e["achieved"] / 8000.0) < 1e-12
+    r = bench.roofline_entry({"launches": 2, "ms": 2.0, "flops": 2e12, "bytes": 1e9}, "c128")
+    assert abs(r["achieved"] - 1000.0) < 1e-9 and abs(r["frac"] - 1000.0 / 78.6) < 1e-12

@@ -111,6 +111,12 @@ def test_sweep_timing_inside_graphs():
         assert sg["launches"] == sd["launches"] > 0
         assert sg["flops"] == sd["flops"]
         assert 0.25 * sd["ms"] < sg["ms"] < 4.0 * sd["ms"]
+    for kind in (0, 1):  # the fine 27-point products, timed the same way
+        sg, sd = g.stencil_stats(kind), d.stencil_stats(kind)
+        say("stencil", kind, "graph", sg, "direct", sd)
+        assert sg["launches"] == sd["launches"] > 0
+        assert sg["bytes"] == sd["bytes"] and sg["flops"] == sd["flops"]
+        assert 0.25 * sd["ms"] < sg["ms"] < 4.0 * sd["ms"]
     # the timed iterations themselves ran from graphs (event-record nodes)
     assert g.graph_stats()["replays"] > before
     g.close()
