@@ -191,3 +191,8 @@ def test_bench_module_imports_and_summarises_timings():
     assert abs(e["achieved"] - 28e9 / 6.0 * 1e-6) < 1e-6 and abs(e["frac"] - e["achieved"] / 8000.0) < 1e-12
     r = bench.roofline_entry({"launches": 2, "ms": 2.0, "flops": 2e12, "bytes": 1e9}, "c128")
     assert abs(r["achieved"] - 1000.0) < 1e-9 and abs(r["frac"] - 1000.0 / 78.6) < 1e-12
+    import torch
+    from paper_2103_14921_amd import helm
+    X = torch.randn(20, 7, dtype=torch.complex128)
+    e = bench.rel_err(helm, torch, X, X * (1 + 1e-3))  # in chunks of 8 rows, the last one ragged
+    assert e.shape == (20,) and torch.allclose(e, torch.full((20,), 1e-3 / (1 + 1e-3), dtype=torch.float64))
