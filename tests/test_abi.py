@@ -191,6 +191,13 @@ def test_bench_module_imports_and_summarises_timings():
     assert abs(e["achieved"] - 28e9 / 6.0 * 1e-6) < 1e-6 and abs(e["frac"] - e["achieved"] / 8000.0) < 1e-12
     r = bench.roofline_entry({"launches": 2, "ms": 2.0, "flops": 2e12, "bytes": 1e9}, "c128")
     assert abs(r["achieved"] - 1000.0) < 1e-9 and abs(r["frac"] - 1000.0 / 78.6) < 1e-12
+    class Boxes:  # two boxes: 4 x 3 planes x 5 and 2 x 2 planes x 3
+        def num_subdomains(self, level):
+            return 2
+
+        def subdomain_box(self, s, level):
+            return [{"elo": (0, 0, 0), "ehi": (4, 3, 5)}, {"elo": (1, 1, 1), "ehi": (3, 3, 4)}][s]
+    assert bench.factor_flops(Boxes()) == 5 * 8.0 * 12 ** 3 + 3 * 8.0 * 4 ** 3
     import torch
     from paper_2103_14921_amd import helm
     X = torch.randn(20, 7, dtype=torch.complex128)
