@@ -89,6 +89,8 @@ class Server:
 
     velocity_of(spec) must return the complex128 velocity [nz][ny][nx] of a
     problem (host array or device tensor); it is called once per set-up.
+    budget_bytes defaults to 85 % of the device less what PyTorch holds
+    allocated when the server starts.
     """
 
     def __init__(self, velocity_of, budget_bytes=None, workers=4, max_batch_rhs=64, device="cuda:0"):
@@ -96,8 +98,9 @@ class Server:
         self.torch = torch
         self.device = torch.device(device)
         if budget_bytes is None:
+            # 85 % of the device, less what the caller's tensors hold already
             free, total = torch.cuda.mem_get_info(self.device)
-            budget_bytes = int(0.85 * total)
+            budget_bytes = int(0.85 * total) - torch.cuda.memory_allocated(self.device)
         self.budget = int(budget_bytes)
         self.velocity_of = velocity_of
         self.max_batch_rhs = max_batch_rhs
