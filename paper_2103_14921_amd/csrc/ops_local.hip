@@ -96,32 +96,50 @@ __global__ void k_local_coarse(int ncx, int ncy, int ncz, const z64* __restrict_
 }
 
 // W = Sinv_{k-1} U_{k-1}:  W[p][q] = sum_{a in N(q)} Sinv[p][a] U[a][q],  U[a][q] = A_i[(k-1,a),(k,q)]
+// A workgroup owns 64 columns q and 32 rows p of one box: the nine coupling
+// values U[a][q] of its columns (and their plane indices a) are staged in LDS
+// once, instead of being gathered from the 27-wide local rows by every
+// output; out-of-plane neighbours get a zero coupling and keep the term order.
+constexpr int SW_TQ = 64, SW_TP = 32;
 template <typename T>
-__global__ void k_schur_W(const Sub* __restrict__ subs, int k, int bpmax, const z64* __restrict__ aloc,
-                          const cpx<T>* __restrict__ sinv, cpx<T>* __restrict__ W) {
-  const int s = blockIdx.y;
-  const Sub sb = subs[s];
-  if (k < 1 || k >= sb.ez) return;
+__global__ void __launch_bounds__(256) k_schur_W(const Sub* __restrict__ subs, int k, int bpmax,
+                                                 const z64* __restrict__ aloc, const cpx<T>* __restrict__ sinv,
+                                                 cpx<T>* __restrict__ W) {
+  const Sub sb = subs[blockIdx.z];
   const int b = sb.b;
-  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= (long long)b * b) return;
-  const int p = (int)(t / b), q = (int)(t % b);
-  const int qx = q % sb.ex, qy = q / sb.ex;
-  const cpx<T>* Sp = sinv + sb.mat_off + (long long)(k - 1) * sb.bp * sb.bp + (long long)p * sb.bp;
-  cpx<T> acc = mk<T>(0, 0);
-  for (int dy = -1; dy <= 1; ++dy) {
-    const int ay = qy + dy;
-    if (ay < 0 || ay >= sb.ey) continue;
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int ax = qx + dx;
-      if (ax < 0 || ax >= sb.ex) continue;
-      const int a = ax + sb.ex * ay;
-      // offset from a (plane k-1) to q (plane k): (-dx, -dy, +1)
-      const z64 u = aloc[(sb.node_off + (long long)(k - 1) * b + a) * 27 + 18 + (1 - dy) * 3 + (1 - dx)];
-      cfma(acc, Sp[a], ccast<T>(u));
+  const int q0 = blockIdx.x * SW_TQ, p0 = blockIdx.y * SW_TP;
+  if (k < 1 || k >= sb.ez || q0 >= b || p0 >= b) return;  // uniform over the workgroup
+  __shared__ cpx<T> uc[SW_TQ][9];
+  __shared__ int ua[SW_TQ][9];
+  for (int e = threadIdx.x; e < SW_TQ * 9; e += blockDim.x) {
+    const int ql = e / 9, d = e % 9, dy = d / 3 - 1, dx = d % 3 - 1;
+    const int q = q0 + ql;
+    cpx<T> u = mk<T>(0, 0);
+    int a = 0;
+    if (q < b) {
+      const int ax = q % sb.ex + dx, ay = q / sb.ex + dy;
+      if (ax >= 0 && ax < sb.ex && ay >= 0 && ay < sb.ey) {
+        a = ax + sb.ex * ay;
+        // offset from a (plane k-1) to q (plane k): (-dx, -dy, +1)
+        u = ccast<T>(aloc[(sb.node_off + (long long)(k - 1) * b + a) * 27 + 18 + (1 - dy) * 3 + (1 - dx)]);
+      }
     }
+    uc[ql][d] = u;
+    ua[ql][d] = a;
   }
-  W[(long long)s * bpmax * bpmax + (long long)p * sb.bp + q] = acc;
+  __syncthreads();
+  const int ql = threadIdx.x % SW_TQ, q = q0 + ql;
+  if (q >= b) return;
+  const cpx<T>* Sb = sinv + sb.mat_off + (long long)(k - 1) * sb.bp * sb.bp;
+  cpx<T>* Wb = W + (long long)blockIdx.z * bpmax * bpmax;
+  const int pend = min(p0 + SW_TP, b);
+  for (int p = p0 + threadIdx.x / SW_TQ; p < pend; p += 256 / SW_TQ) {
+    const cpx<T>* Sp = Sb + (long long)p * sb.bp;
+    cpx<T> acc = mk<T>(0, 0);
+#pragma unroll
+    for (int d = 0; d < 9; ++d) cfma(acc, Sp[ua[ql][d]], uc[ql][d]);
+    Wb[(long long)p * sb.bp + q] = acc;
+  }
 }
 
 // S[p][q] = D_k[p][q] - sum_{c in N(p)} L_k[p][c] W[c][q]  (no L term at k = 0); padding zero
@@ -789,7 +807,9 @@ void Factor<T>::plane(const Sub* subs, int nsub, int bpmax, int k, const z64* al
   const long long cells = (long long)bpmax * bpmax;
   dim3 grid((unsigned)ceil_div(cells, 256), nsub);
   auto factor_with = [&](int nb) {
-    if (k >= 1) hipLaunchKernelGGL(k_schur_W<T>, grid, dim3(256), 0, s, subs, k, bpmax, aloc, sinv, W);
+    if (k >= 1)
+      hipLaunchKernelGGL(k_schur_W<T>, dim3((unsigned)ceil_div(bpmax, SW_TQ), (unsigned)ceil_div(bpmax, SW_TP), nsub),
+                         dim3(256), 0, s, subs, k, bpmax, aloc, sinv, W);
     hipLaunchKernelGGL(k_schur_S<T>, grid, dim3(256), 0, s, subs, k, bpmax, aloc, W, S);
     gj_dispatch<T>(nb, subs, nsub, bpmax, k, S, Rbuf, R64, piv, err, s);
     hipLaunchKernelGGL(k_gj_perm, dim3((unsigned)ceil_div(nsub, 64)), dim3(64), 0, s, subs, nsub, k, bpmax, piv,
