@@ -79,6 +79,22 @@ def test_process_wide_settings_reject_bad_values():
     helm.set_row_tiling(0)
 
 
+def test_statistics_entry_points_reject_null_handles_and_bad_kinds():
+    import ctypes as C
+
+    from paper_2103_14921_amd import helm
+    out = (C.c_double * 4)()
+    for kind in (0, 1):
+        assert helm.lib.helm_stencil_stats(None, kind, out) == helm.HELM_EINVAL
+        assert helm.lib.helm_sweep_stats(None, kind, out) == helm.HELM_EINVAL
+    assert helm.lib.helm_resident_bytes(None) == 0
+    # an unknown precision code is refused before any device work
+    d = helm.DecompT(2, 2, 2, 2, 2, 10, 7, 20, 1, 0)
+    assert helm.lib.helm_footprint(C.byref(helm.Grid(32, 32, 32, 25.0)), C.byref(d), 1) == 0
+    with pytest.raises(ValueError):
+        helm.footprint((32, 32, 32), (2, 2, 2), precision="half")
+
+
 def test_no_kernel_uses_scratch(tmp_path):
     # every kernel of the built library keeps its state in registers and LDS:
     # per-wave scratch would be allocated by the runtime at dispatch, where a
