@@ -209,3 +209,76 @@ def test_local_matrix_from_rows_matches_restriction():
         Ai, _ = local_matrix(A, prob.shape, b, prob.k().ravel(), prob.h)
         Bi = local_matrix_from_rows(prob, b)
         assert abs(Ai - Bi).max() <= 1e-13 * abs(Ai).max()
+
+
+def _co_located_rows(Z):
+    # fine node co-located with each coarse node: the one fine row where the
+    # trilinear weight of that coarse node is exactly 1 (Z is pinned above by
+    # reproducing linear functions)
+    Zc = Z.tocsc()
+    rows = []
+    for c in range(Z.shape[1]):
+        col = Zc[:, c].tocoo()
+        one = col.row[col.data == 1.0]
+        assert len(one) == 1
+        rows.append(int(one[0]))
+    return np.array(rows)
+
+
+def test_coarse_k_takes_k_of_the_co_located_fine_node():
+    from oracle.coarse import coarse_k
+    shape = (9, 8, 7)  # odd and even sizes, not a cube
+    rng = np.random.default_rng(3)
+    n = int(np.prod(shape))
+    k = rng.standard_normal(n) + 1j * rng.standard_normal(n)  # distinct per node
+    rows = _co_located_rows(prolongation(shape))
+    assert np.array_equal(coarse_k(k, shape), k[rows])
+
+
+def test_coarse_fold_uses_co_located_k_and_the_coarse_spacing():
+    # the coarse local problems of eq. 2lvl carry the absorbing fold with the k
+    # of each coarse node's co-located fine node and the coarse grid's own node
+    # spacing (the distance between co-located fine nodes of neighbouring
+    # coarse nodes), both read here off Z, not off the oracle's coarse code
+    import scipy.sparse.linalg as spla
+    prob = _prob(shape=(14, 12, 11), pml=(3, 3, 3, 0), q=30.0)
+    A = assemble(prob)
+    k = prob.k().ravel()
+    boxes = decompose(prob.shape, (2, 2, 1), 2)
+    tl = TwoLevel(A, prob.shape, boxes, k, prob.h, 2)
+    rows = _co_located_rows(tl.Z)
+    nx, ny, _ = prob.shape
+    pos = np.stack([rows % nx, (rows // nx) % ny, rows // (nx * ny)], 1) * prob.h
+    spacing = np.linalg.norm(pos[1] - pos[0])  # coarse nodes 0 and 1 are neighbours along x
+    assert spacing > prob.h
+    kc = k[rows]
+    rng = np.random.default_rng(8)
+    for i, cb in enumerate(tl.cboxes):
+        Ai, idx = local_matrix(tl.E, tl.cshape, cb, kc, spacing)
+        r = rng.standard_normal(len(idx)) + 1j * rng.standard_normal(len(idx))
+        want = spla.spsolve(Ai.tocsc(), r)
+        got = tl.coarse.lu[i].solve(r)
+        assert np.linalg.norm(got - want) <= 1e-10 * np.linalg.norm(want)
+
+
+def test_coarse_outgoing_fold_beats_the_wrong_sign():
+    # on the coarse grid too, the fold (1 + i k h_c) for e^{-i omega t} is the
+    # outgoing condition: the opposite sign makes the coarse one-level ORAS a
+    # far worse preconditioner of E
+    from oracle.coarse import coarse_k
+    prob = _prob(shape=(24, 22, 20), pml=(4, 4, 4, 0))
+    A = assemble(prob)
+    k = prob.k().ravel()
+    boxes = decompose(prob.shape, (2, 2, 2), 2)
+    Z = prolongation(prob.shape)
+    E = (Z.T @ A @ Z).tocsr()
+    cs, cb = coarse_shape(prob.shape), coarse_boxes(boxes, prob.shape, 2)
+    kc = coarse_k(k, prob.shape)
+    b = np.zeros(prob.n, complex)
+    b[12 + 24 * (11 + 22 * 4)] = 1.0
+    c = Z.T @ b
+    its = {}
+    for name, kk in (("outgoing", kc), ("wrong", -kc)):
+        M = Oras(E, cs, cb, kk, 2 * prob.h)
+        its[name] = fgmres(lambda v: E @ v, M.apply, c, 1e-8, 30, 400)[1]
+    assert 2 * its["outgoing"] < its["wrong"]
