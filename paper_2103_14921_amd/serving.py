@@ -170,6 +170,23 @@ class Server:
         # B and X of the batch on the device (complex128 each)
         return 2 * 16 * nrhs * int(np.prod(spec.shape))
 
+    def _staging_room(self, nbytes):
+        """Make sure PyTorch's staging of a batch leaves the library's device headroom
+        (helm_device_headroom) free: the runtime allocates for itself at dispatch,
+        and a failure there aborts the queue.  Trims the library's and PyTorch's
+        idle caches if needed; raises HELM_ENOMEM (the batch goes back to the
+        queue while others run) if the room is still not there."""
+        torch = self.torch
+        if self.device.type != "cuda":
+            return
+        need = nbytes + helm.device_headroom()
+        if torch.cuda.mem_get_info(self.device)[0] >= need:
+            return
+        helm.trim_cache()
+        torch.cuda.empty_cache()
+        if torch.cuda.mem_get_info(self.device)[0] < need:
+            raise helm.HelmError(helm.HELM_ENOMEM, "no room to stage the batch above the device headroom")
+
     def _need(self, spec, nrhs, resident, chunk=None):
         """Device bytes a batch of nrhs right-hand sides takes while in flight when
         the library solves chunk of them at a time (all by default): the whole
@@ -231,9 +248,15 @@ class Server:
                 if not launched:
                     self._cv.wait(0.05)
 
+    def _held(self):
+        # after a batch went back to the queue, nothing new starts until another
+        # batch in flight has ended; with none in flight there is nothing to wait for
+        return self._hold and self._inflight_count() > 0
+
     def _try_launch(self):
-        if self._hold:
+        if self._held():
             return False
+        self._hold = False
         for head in list(self._queue):
             key = (head.spec, head.tol, head.maxit)
             e = self._entries.get(head.spec)
@@ -296,6 +319,7 @@ class Server:
                     parts.append(b.reshape(r.nrhs, -1).to(self.device))
                 return torch.cat(parts, 0).contiguous() if len(parts) > 1 else parts[0].contiguous()
 
+            self._staging_room(self._staging(spec, nr))
             Bd = helm.torch_alloc(stage)
             # a request gets X where its B was: host arrays come back as host
             # arrays, so delivered results hold no device memory outside the
@@ -346,10 +370,13 @@ class Server:
                 if short and others:
                     # the device ran short while other batches are in flight (the
                     # footprints are estimates): put the batch back at the head of
-                    # the queue and try again once one of the others has ended
+                    # the queue and hold new launches until one of the others has
+                    # ended -- set here, in the same critical section that saw them
+                    # busy, so that their ends (which lift the hold) come after it
                     for r in reversed(batch):
                         self._queue.appendleft(r)
                     self.stats.retries += 1
+                    self._hold = True
                     retried = True
                 else:  # report the failure on every request of the batch
                     for r in batch:
@@ -357,7 +384,8 @@ class Server:
                             r.future.set_exception(exc)
         finally:
             with self._cv:
-                self._hold = retried
+                if not retried:  # a batch that ended lifts a hold
+                    self._hold = False
                 e.resident = e.solver.resident_bytes() if e.solver is not None else 0
                 e.busy = False
                 e.last_used = time.perf_counter()

@@ -219,3 +219,74 @@ def test_bench_module_imports_and_summarises_timings():
     X = torch.randn(20, 7, dtype=torch.complex128)
     e = bench.rel_err(helm, torch, X, X * (1 + 1e-3))  # in chunks of 8 rows, the last one ragged
     assert e.shape == (20,) and torch.allclose(e, torch.full((20,), 1e-3 / (1 + 1e-3), dtype=torch.float64))
+
+
+def test_serving_requeue_hold_is_lifted_when_the_other_batch_ends_first():
+    # A batch that finds the device short while another is in flight goes back
+    # to the queue and holds new launches until that other batch ends.  Force
+    # the interleaving where the other batch ends between the failing batch's
+    # re-queue and the end of its worker: the hold must not outlive it (the
+    # scheduler would wait for an end that already happened).
+    import collections
+    import threading
+    from concurrent.futures import Future
+
+    import numpy as np
+    import torch
+    from paper_2103_14921_amd import helm
+    from paper_2103_14921_amd.serving import ProblemSpec, Server, ServerStats, _Entry, _Request
+
+    class Stub:
+        def __init__(self, fail):
+            self.fail = fail
+
+        def solve(self, B, tol, maxit):
+            if self.fail:
+                raise helm.HelmError(helm.HELM_ENOMEM, "short")
+            n = B.shape[0]
+            return B.clone(), {"iters": np.ones(n, np.int32), "relres_true": np.zeros(n), "status": 0}
+
+        def release_workspace(self):
+            pass
+
+        def resident_bytes(self):
+            return 0
+
+    srv = Server.__new__(Server)  # host-side state only: no device, no scheduler thread
+    srv.torch, srv.device = torch, torch.device("cpu")
+    srv._queue, srv._entries = collections.deque(), collections.OrderedDict()
+    srv._inflight, srv._hold, srv._closed, srv.stats = 0, False, False, ServerStats()
+    cv = threading.Condition()
+    calls = {"n": 0}
+    specs = [ProblemSpec(nm, (4, 4, 4), 25.0, 4.0) for nm in ("x", "y")]
+    ex, ey = _Entry(specs[0], Stub(True), busy=True), _Entry(specs[1], Stub(False), busy=True)
+    srv._entries[specs[0]], srv._entries[specs[1]] = ex, ey
+
+    def req(spec):
+        return _Request(spec, np.zeros((1, 64), np.complex128), 1e-6, 10, 0.0, Future(), 1)
+
+    rx, ry = req(specs[0]), req(specs[1])
+
+    class Hooked:  # runs the other batch to its end right before the failing worker's last critical section
+        def __enter__(self):
+            if threading.current_thread().name == "x":
+                calls["n"] += 1
+                if calls["n"] == 2:
+                    srv._work(ey, [ry], 1, 0, 1)
+            return cv.__enter__()
+
+        def __exit__(self, *a):
+            return cv.__exit__(*a)
+
+        def notify_all(self):
+            cv.notify_all()
+
+    srv._cv = Hooked()
+    t = threading.Thread(target=srv._work, args=(ex, [rx], 1, 0, 1), name="x")
+    t.start()
+    t.join(10)
+    assert not t.is_alive()
+    assert ry.future.done() and not rx.future.done()
+    assert list(srv._queue) == [rx] and srv.stats.retries == 1
+    assert not ex.busy and not ey.busy
+    assert not srv._hold and not srv._held()
