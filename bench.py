@@ -84,8 +84,10 @@ PEAK = {"c64": 157.3, "c128": 78.6}  # dense MFMA TFLOP/s of one MI355X (fp32, f
 
 
 def measured_traffic(kernel_file, profile_md, algorithmic_bytes):
-    """HBM bytes per launch from the committed PMC summary, if the kernel source is unchanged since and
-    the tuner chose the same launch shape (same algorithmic bytes per launch)."""
+    """HBM bytes per launch from a committed PMC summary (FETCH_SIZE + WRITE_SIZE of a separate rocprofv3
+    run, calibrated on a plain copy), if the kernel source is unchanged since and the tuner chose the same
+    launch shape (same algorithmic bytes per launch); else None.  Returns (bytes, source description):
+    the figure is not measured in this run, and the line says where it comes from."""
     import hashlib
     import re as _re
     root = os.path.dirname(os.path.abspath(__file__))
@@ -94,12 +96,40 @@ def measured_traffic(kernel_file, profile_md, algorithmic_bytes):
         data = json.loads(_re.search(r"```json\n(.*?)\n```", text, _re.S).group(1))
         src = open(os.path.join(root, "paper_2103_14921_amd", "csrc", kernel_file), "rb").read()
         if hashlib.sha256(src).hexdigest()[:16] != data["source_sha256_16"]:
-            return None
+            return None, None
         if abs(algorithmic_bytes - data["algorithmic_bytes_per_launch"]) > 1e-6 * algorithmic_bytes:
-            return None
-        return data["traffic_bytes_per_launch"]
+            return None, None
+        return data["traffic_bytes_per_launch"], (f"profiles/{profile_md}: PMC counters of an earlier run of the "
+                                                  f"same kernel source ({data['source_sha256_16']}) and launch "
+                                                  f"shape, not measured in this run")
     except Exception:
-        return None
+        return None, None
+
+
+def set_traffic(entry, kernel_file, profile_md):
+    """Attach the measured HBM traffic (or null) and its source to a roofline entry, and label the bound
+    from the arithmetic intensity on that traffic (on the algorithmic bytes when there is none): below
+    the ridge of the kernel's arithmetic the kernel is bandwidth-bound, and achieved/peak/frac are then
+    the algorithmic bytes per second against HBM peak."""
+    traffic, source = measured_traffic(kernel_file, profile_md, entry["bytes_per_launch"])
+    entry["traffic"], entry["traffic_source"] = traffic, source
+    label_bound(entry)
+    return entry
+
+
+def label_bound(entry):
+    peak_flops = entry["mfma_peak"] * 1e12
+    ridge = peak_flops / 8.0e12
+    ai = entry["flops_per_launch"] / (entry["traffic"] or entry["bytes_per_launch"])
+    entry["arithmetic_intensity"] = ai
+    entry["ridge"] = ridge
+    if ai >= ridge:
+        entry.update(bound="mfma", achieved=entry["tflops"], peak=entry["mfma_peak"], unit="TFLOP/s",
+                     frac=entry["tflops"] / entry["mfma_peak"])
+    else:
+        gbs = entry["bytes_per_launch"] / (entry["avg_ms"] * 1e-3) * 1e-9
+        entry.update(bound="hbm", achieved=gbs, peak=8000.0, unit="GB/s", frac=gbs / 8000.0)
+    return entry
 
 
 def factor_flops(S):
@@ -145,9 +175,11 @@ def roofline_entry(st, dtype):
     ms = st["ms"] / max(st["launches"], 1)
     flops = st["flops"] / max(st["launches"], 1)
     achieved = flops / (ms * 1e-3) / 1e12
-    return {"bound": "mfma", "achieved": achieved, "peak": PEAK[dtype], "unit": "TFLOP/s",
-            "frac": achieved / PEAK[dtype], "traffic": None, "launches": st["launches"], "avg_ms": ms,
-            "flops_per_launch": flops, "bytes_per_launch": st["bytes"] / max(st["launches"], 1)}
+    e = {"bound": "mfma", "achieved": achieved, "peak": PEAK[dtype], "unit": "TFLOP/s",
+         "frac": achieved / PEAK[dtype], "traffic": None, "traffic_source": None, "launches": st["launches"],
+         "avg_ms": ms, "flops_per_launch": flops, "bytes_per_launch": st["bytes"] / max(st["launches"], 1),
+         "tflops": achieved, "mfma_peak": PEAK[dtype]}
+    return label_bound(e)
 
 
 def cpu_baseline(w, its_per_rhs, nrhs, budget_s=25.0):
@@ -170,25 +202,52 @@ def cpu_baseline(w, its_per_rhs, nrhs, budget_s=25.0):
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:
         threads = 1
+    ncpu = os.cpu_count() or 1
+    # the local factorisations run in a process pool, one worker per box up to one per host core
+    workers = max(1, min(27, ncpu, 16))
     c = inputs.velocity_thrust_belt(ns, ns, ns, H, q=w["q"])
     src = inputs.source_grid(ns, ns, NPML, NPML, 1, 1, iz=4)
     b = inputs.point_source_rhs(ns, ns, ns, src)
     prob = Problem((ns, ns, ns), H, c, FREQ, Pml(NPML, NPML, NPML, 0), fit_weights())
+    from threadpoolctl import threadpool_limits
     t0 = time.perf_counter()
-    st = setup(prob, (3, 3, 3), 2, 2)
+    with threadpool_limits(1):  # one LAPACK thread per worker process
+        st = setup(prob, (3, 3, 3), 2, 2, workers=workers)
     t_setup = time.perf_counter() - t0
     res = solve(st, b, w["tol"], w["restart"], 60)
     it_s = max(1, int(res["iters"][0]))
     t_iter = res["t_solve"] / it_s
     scale = nboxes_full / 27.0
     t_full = t_setup * scale + t_iter * scale * float(np.sum(its_per_rhs))
-    return {"value": nrhs / t_full, "unit": "RHS/s", "cores": threads, "kind": "oracle",
+    return {"value": nrhs / t_full, "unit": "RHS/s", "cores": max(workers, threads), "kind": "oracle",
+            "cpu_model": cpu_model(), "os_cpu_count": ncpu,
             "sample": (f"oracle set-up + one FGMRES solve of one source on a {ns}^3 grid with 3x3x3 boxes of the "
-                       f"same size ({t_setup:.1f} s set-up, {res['t_solve']:.1f} s for {it_s} iterations; one "
-                       f"process, LAPACK on {threads} threads), scaled by {scale:.0f}x boxes and the GPU's "
-                       f"iteration counts summed over all right-hand sides"),
+                       f"same size ({t_setup:.1f} s set-up with the banded factorisations in a pool of {workers} "
+                       f"processes of one LAPACK thread each, {res['t_solve']:.1f} s for {it_s} iterations in one "
+                       f"process with LAPACK on "
+                       f"{threads} threads), scaled by {scale:.0f}x boxes and the GPU's iteration counts summed "
+                       f"over all right-hand sides"),
             "extrapolated": True, "t_setup_full_s": t_setup * scale,
             "t_solve_full_s": t_iter * scale * float(np.sum(its_per_rhs))}
+
+
+def cpu_model():
+    """Host CPU model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return "unknown"
 
 
 def serving_phase(n_requests, max_rhs=64, seed=4):
@@ -242,9 +301,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-single-local", action="store_true",
                     help="skip the run with the coarse level's local solves in complex FP32 too")
-    ap.add_argument("--serving-requests", type=int, default=12,
-                    help="requests in the serving stream reported beside the main line (0: skip)")
-    ap.add_argument("--serving-max-rhs", type=int, default=16, help="largest request of the serving stream")
+    ap.add_argument("--serving-requests", type=int, default=24,
+                    help="requests in the serving stream reported beside the main line (0: skip); a quarter "
+                         "of them calibrate the capacity, the rest arrive as a Poisson stream")
+    ap.add_argument("--serving-max-rhs", type=int, default=64, help="largest request of the serving stream")
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly (no captured iterations)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
@@ -319,8 +379,7 @@ def main():
         out["roofline"] = roofline_entry(info["sweeps"][1], coarse_dtype)
         out["roofline"]["kernel"] = ("k_oras_fused (coarse level, FP64 complex, MFMA 16x16x4 f64)" if coarse_dtype == "c128"
                                      else "k_oras_fused (coarse level, FP32 complex, MFMA f32)")
-        out["roofline"]["traffic"] = measured_traffic("ops_sweep.hip", f"oras_sweep_coarse_{args.workload}_pmc.md",
-                                                      out["roofline"]["bytes_per_launch"])
+        set_traffic(out["roofline"], "ops_sweep.hip", f"oras_sweep_coarse_{args.workload}_pmc.md")
         out["roofline_fine_sweep"] = roofline_entry(info["sweeps"][0], fine_dtype)
     else:
         out["roofline"] = roofline_entry(info["sweeps"][0], fine_dtype)
@@ -351,9 +410,9 @@ def main():
             "iters_mean": float(isl["iters"].mean()), "max_true_relres": float(isl["relres_true"].max()),
             "coarse_sweep": roofline_entry(isl["sweeps"][1], "c64"), "fine_sweep": roofline_entry(isl["sweeps"][0], "c64"),
             "solve_roofline_frac": isl["bound"]["seconds"] / isl["timings"]["solve"]}
-        cs = out["single_local_form"]["coarse_sweep"]
-        cs["traffic"] = measured_traffic("ops_sweep.hip", "oras_sweep_coarse_thrust192_single_local_pmc.md",
-                                         cs["bytes_per_launch"]) if args.workload == "thrust192_mixed" else None
+        if args.workload == "thrust192_mixed":
+            set_traffic(out["single_local_form"]["coarse_sweep"], "ops_sweep.hip",
+                        "oras_sweep_coarse_thrust192_single_local_pmc.md")
         if "fp64_form" in out:
             err = rel_err(helm, torch, Xs, X64)
             out["single_local_form"]["vs_fp64_rel_l2_max"] = float(err.max().item())

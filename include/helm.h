@@ -23,8 +23,9 @@
  *     owns every buffer it passes in.  The handle owns all device memory it
  *     allocates; only helm_destroy releases it.
  *   - Return codes: HELM_OK = 0; positive = warning with outputs valid;
- *     negative = error with outputs untouched.  helm_last_error() gives the
- *     message of the last failure on the calling thread.
+ *     negative = error with outputs untouched.  helm_last_error(h) gives the
+ *     message of the last failure of a call on handle h, helm_last_error(NULL)
+ *     that of the last failure on the calling thread.
  *   - One solve in flight per handle; handles are independent.
  */
 #ifndef HELM_H_
@@ -102,23 +103,52 @@ typedef struct {
  * the first octant, subject to the two sum constraints.  Host only; needs no GPU. */
 helm_status helm_fit_weights(double gmin, double gmax, int32_t ng, int32_t nang, helm_weights_t* out);
 
+/* Kinds of velocity array accepted by helm_setup. */
+enum {
+  HELM_VEL_COMPLEX128 = 0, /* complex c (interleaved re, im doubles): attenuation c (1 - i/(2Q)) */
+  HELM_VEL_REAL64 = 1      /* real c (doubles): a medium without attenuation */
+};
+
 /* Set up the operator, the decomposition and the factorisations on the current
- * HIP device.  velocity: complex128 [nz][ny][nx], copied (caller may free it on
- * return).  weights == NULL uses helm_fit_weights(4, 10, 7, 15).  On success
- * *out receives a handle. */
-helm_status helm_setup(const helm_grid_t* grid, const void* velocity, double freq_hz,
+ * HIP device: the Helmholtz operator of eq. eqh discretised by the 27-point
+ * mixed-grid stencil of eq. eq1 (FD-vs-FE section) with k = 2 pi freq_hz / c,
+ * the overlapping subdomains with absorbing interfaces and their direct local
+ * factorisations of eq. oras, and for dec->levels = 2 the coarse operator
+ * E = Z^T A Z with its own local factorisations (eq. 2lvl; domain-decomposition
+ * section).
+ *   grid:      node counts (each >= 3) and spacing h > 0 (metres).
+ *   velocity:  [nz][ny][nx] (x fastest), host or device memory, of the kind
+ *              vel_kind names; every value finite with Re c > 0.  Copied: the
+ *              caller may free it on return.  A real array sets up exactly the
+ *              operator of the complex array with zero imaginary parts.
+ *   freq_hz:   frequency > 0.
+ *   pml, dec:  see the structs above; weights == NULL uses
+ *              helm_fit_weights(4, 10, 7, 15).
+ * On success *out receives a handle that owns every device allocation of the
+ * problem (released by helm_destroy).  Errors: HELM_EINVAL (sizes, values,
+ * vel_kind, boxes narrower than 2 overlap + 1), HELM_ENOMEM (the footprint does
+ * not fit the device), HELM_EDEVICE, HELM_EBREAKDOWN (a numerically singular
+ * local factor); *out is then NULL and helm_last_error(NULL) holds the reason. */
+helm_status helm_setup(const helm_grid_t* grid, const void* velocity, int32_t vel_kind, double freq_hz,
                        const helm_pml_t* pml, const helm_weights_t* weights,
                        const helm_decomp_t* dec, helm_handle_t** out);
 
 enum { HELM_X0 = 1u /* X holds the initial guess on entry */ };
 
-/* Solve A X[r] = B[r], r < nrhs, with one Krylov space per right-hand side.
- * Stop when |g_{j+1}|/||b|| <= tol (FGMRES estimate), then confirm with the
- * FP64 true residual ||b - A x||/||b|| and restart from x while it is above
- * tol.  maxit bounds the outer iterations of each right-hand side.
- * B, X: complex128 [nrhs][nz][ny][nx]; iters[nrhs], relres_est[nrhs],
- * relres_true[nrhs] are host arrays (may be NULL).  Returns HELM_NOT_CONVERGED
- * when some right-hand side reached maxit. */
+/* Solve A X[r] = B[r], r < nrhs, by right-preconditioned flexible GMRES (the
+ * Krylov solver of the domain-decomposition section) with the handle's one- or
+ * two-level ORAS preconditioner (eq. oras / eq. 2lvl), one Krylov space per
+ * right-hand side.  Stop when |g_{j+1}|/||b|| <= tol (FGMRES estimate), then
+ * confirm with the FP64 true residual ||b - A x||/||b|| and restart from x
+ * while it is above tol.  maxit bounds the outer iterations of each
+ * right-hand side; x0 = 0 unless flags has HELM_X0 (X holds the guess).
+ *   B, X: complex128 [nrhs][nz][ny][nx], host or device memory, owned by the
+ *         caller; X is written only on HELM_OK / HELM_NOT_CONVERGED.
+ *   iters[nrhs], relres_est[nrhs], relres_true[nrhs]: host arrays (may be NULL).
+ * Returns HELM_NOT_CONVERGED when some right-hand side reached maxit (its
+ * residuals are reported), HELM_EINVAL for bad arguments or a handle with a
+ * request in flight, HELM_ENOMEM when not even one right-hand side's Krylov
+ * workspace fits, HELM_EDEVICE on a runtime error. */
 helm_status helm_solve(helm_handle_t* h, int32_t nrhs, const void* B, void* X, double tol,
                        int32_t maxit, uint32_t flags, int32_t* iters, double* relres_est,
                        double* relres_true);
@@ -126,10 +156,15 @@ helm_status helm_solve(helm_handle_t* h, int32_t nrhs, const void* B, void* X, d
 /* Asynchronous form of helm_solve for callers that overlap solves of several
  * handles (continuous batching of a serving loop): the arguments are checked
  * at once, then the solve runs on a library thread with the handle's device
- * current, in the same order of device work as helm_solve on the handle's
- * stream, so its results are bitwise those of helm_solve.  B, X and the result
- * arrays belong to the caller and must stay valid until helm_request_wait
- * returns.  One solve at a time per handle: helm_solve, helm_solve_async and
+ * current, in the same order of device work as helm_solve, so its results are
+ * bitwise those of helm_solve.  stream (a hipStream_t of the handle's device;
+ * NULL = the handle's own stream) receives every device operation of the
+ * solve, so work the caller enqueued on it before this call (producing B, say)
+ * is ordered before the solve; the caller enqueues nothing more on that stream
+ * until helm_request_wait returns.  The FGMRES loop is driven from the host
+ * (each outer iteration reads the convergence counters), hence the library
+ * thread.  B, X and the result arrays belong to the caller and must stay
+ * valid until helm_request_wait returns.  One solve at a time per handle: helm_solve, helm_solve_async and
  * helm_release_workspace on a handle with a request in flight return
  * HELM_EINVAL; helm_destroy waits for it (the request stays valid for
  * helm_request_wait, which must not run concurrently with helm_destroy of the
@@ -138,7 +173,7 @@ helm_status helm_solve(helm_handle_t* h, int32_t nrhs, const void* B, void* X, d
 typedef struct helm_request helm_request_t;
 helm_status helm_solve_async(helm_handle_t* h, int32_t nrhs, const void* B, void* X, double tol,
                              int32_t maxit, uint32_t flags, int32_t* iters, double* relres_est,
-                             double* relres_true, helm_request_t** req);
+                             double* relres_true, void* stream, helm_request_t** req);
 /* HELM_PENDING while the solve runs, then its helm_solve status (the request
  * stays valid). */
 helm_status helm_request_query(const helm_request_t* req);
@@ -247,8 +282,20 @@ helm_status helm_release_workspace(helm_handle_t* h);
  * runtime (for other allocators in the process) and reports the bytes freed. */
 size_t helm_trim_cache(void);
 
+/* Device bytes the library never allocates into on the current device: 1 % of
+ * its memory, at least 1 GiB (the runtime allocates for itself at dispatch --
+ * kernel arguments, signals, graph instantiation -- and a failure there aborts
+ * the queue instead of returning an error).  Callers that allocate device
+ * memory beside the library, such as staging buffers, keep the same margin. */
+size_t helm_device_headroom(void);
+
 void helm_destroy(helm_handle_t* h);
-const char* helm_last_error(void);
+
+/* Message of the last failed call on handle h (the solve's own failure for an
+ * asynchronous request), or with h == NULL of the last failure on the calling
+ * thread (e.g. a helm_setup that returned no handle).  The string stays valid
+ * in the calling thread until its next helm_last_error call; "" if none. */
+const char* helm_last_error(const helm_handle_t* h);
 
 /* Bind later kernels of this handle to a HIP stream (hipStream_t; NULL = the
  * handle's own stream). */

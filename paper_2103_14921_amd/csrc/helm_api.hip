@@ -36,16 +36,23 @@ helm_status fail(helm_status c, const std::string& m) {
   return c;
 }
 
+// the message of a failed call on a handle is also kept with the handle
+void note_handle_error(helm_handle* H, const std::string& m);
+helm_status fail_h(helm_handle* H, helm_status c, const std::string& m) {
+  if (H) note_handle_error(H, m);
+  return fail(c, m);
+}
+
 template <typename F>
-helm_status guarded(F&& f) {
+helm_status guarded(F&& f, helm_handle* H = nullptr) {
   try {
     return f();
   } catch (const HelmError& e) {
-    return fail(e.code, e.what());
+    return fail_h(H, e.code, e.what());
   } catch (const std::bad_alloc&) {
-    return fail(HELM_ENOMEM, "host allocation failed");
+    return fail_h(H, HELM_ENOMEM, "host allocation failed");
   } catch (const std::exception& e) {
-    return fail(HELM_EDEVICE, e.what());
+    return fail_h(H, HELM_EDEVICE, e.what());
   }
 }
 
@@ -55,14 +62,55 @@ helm_status guarded(F&& f) {
 // repeated solves); the cache is returned to the runtime when an allocation
 // fails.
 // ---------------------------------------------------------------------------
+}  // namespace
+
 // Stream capture (one outer iteration recorded into a graph) may run on one
-// handle's thread while other handles allocate, free or set up on theirs.
-// Device-wide operations (hipMalloc, hipFree) and captures are serialised by
-// this lock; everything else the library enqueues goes to the handles' own
-// non-blocking streams, never to the legacy stream.
+// handle's thread while other handles allocate, free, set up or are destroyed
+// on theirs.  Device-wide operations (hipMalloc, hipFree), the creation and
+// destruction of runtime objects (events, executable graphs) and captures are
+// serialised by this lock; everything the library enqueues goes to the
+// handles' own non-blocking streams, never to the legacy stream.
 std::recursive_mutex& capture_lock() {
   static std::recursive_mutex* m = new std::recursive_mutex();
   return *m;
+}
+hipError_t locked_event_create(hipEvent_t* e) {
+  std::lock_guard<std::recursive_mutex> cl(capture_lock());
+  return hipEventCreate(e);
+}
+void locked_event_destroy(hipEvent_t e) {
+  std::lock_guard<std::recursive_mutex> cl(capture_lock());
+  (void)hipEventDestroy(e);
+}
+
+namespace {
+
+// Streams of handles.  A handle takes a non-blocking stream from this pool at
+// set-up and gives it back (idle: the handle synchronised it) when destroyed;
+// streams are never destroyed, so evicting a problem while other handles
+// capture or trace their iterations touches no stream object.
+struct StreamPool {
+  std::map<int, std::vector<hipStream_t>> idle;  // per device
+  hipStream_t acquire(int dev) {
+    std::lock_guard<std::recursive_mutex> cl(capture_lock());
+    auto& v = idle[dev];
+    if (!v.empty()) {
+      hipStream_t s = v.back();
+      v.pop_back();
+      return s;
+    }
+    hipStream_t s = nullptr;
+    HELM_CHECK_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    return s;
+  }
+  void release(int dev, hipStream_t s) {
+    std::lock_guard<std::recursive_mutex> cl(capture_lock());
+    idle[dev].push_back(s);
+  }
+};
+StreamPool& streams() {
+  static StreamPool* p = new StreamPool();  // never destroyed: streams live until process exit
+  return *p;
 }
 
 struct DevicePool {
@@ -359,11 +407,12 @@ struct Captured {
   WorkBound work;        // algorithmic work of one replay
 
   ~Captured() {
+    std::lock_guard<std::recursive_mutex> cl(capture_lock());
     if (exec) (void)hipGraphExecDestroy(exec);
     for (int lv = 0; lv < NTIMED; ++lv)
       for (auto& e : ev[lv]) {
-        (void)hipEventDestroy(e.first);
-        (void)hipEventDestroy(e.second);
+        locked_event_destroy(e.first);
+        locked_event_destroy(e.second);
       }
   }
 };
@@ -399,15 +448,26 @@ struct helm_handle {
   // the asynchronous solve in flight, if any (helm_solve_async)
   helm_request* pending = nullptr;
   std::mutex pending_mu;
+  // message of the last failed call on this handle (helm_last_error(h))
+  std::string err_msg;
+  mutable std::mutex err_mu;
 
   ~helm_handle() {
     captured.clear();
-    if (own) (void)hipStreamDestroy(own);
+    if (own) {
+      (void)hipStreamSynchronize(own);
+      streams().release(device, own);
+    }
   }
   bool two_level() const { return dec.levels == 2; }
 };
 
 namespace {
+
+void note_handle_error(helm_handle* H, const std::string& m) {
+  std::lock_guard<std::mutex> lk(H->err_mu);
+  H->err_msg = m;
+}
 
 void fit_weights_host(double gmin, double gmax, int ng, int nang, helm_weights_t* out) {
   // unknowns p = (w2, w3, wm2, wm3, wm4); w1 = 1 - w2 - w3, wm1 = 1 - 6wm2 - 12wm3 - 8wm4
@@ -677,8 +737,8 @@ void oras_apply(helm_handle* H, Level& L, int nr, const z64* u, z64* z, const z6
   const int lv = &L == &H->fine ? 0 : 1;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (H->timing) {
-    HELM_CHECK_HIP(hipEventCreate(&e0));
-    HELM_CHECK_HIP(hipEventCreate(&e1));
+    HELM_CHECK_HIP(locked_event_create(&e0));
+    HELM_CHECK_HIP(locked_event_create(&e1));
     record_timing_event(H, e0);
   }
   oras_sweep(H, L, nr, u, z, add, yl, tb);
@@ -707,8 +767,8 @@ void oras_apply(helm_handle* H, Level& L, int nr, const z64* u, z64* z, const z6
 void fine_product(helm_handle* H, int nr, const z64* b, const z64* x, z64* y) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (H->timing) {
-    HELM_CHECK_HIP(hipEventCreate(&e0));
-    HELM_CHECK_HIP(hipEventCreate(&e1));
+    HELM_CHECK_HIP(locked_event_create(&e0));
+    HELM_CHECK_HIP(locked_event_create(&e1));
     record_timing_event(H, e0);
   }
   if (b)
@@ -738,8 +798,8 @@ void collect_sweep_timing(helm_handle* H) {
       H->sweep_stat[lv][1] += ms;
       H->sweep_stat[lv][2] += H->sweep_flops[lv][i];
       H->sweep_stat[lv][3] += H->sweep_bytes[lv][i];
-      (void)hipEventDestroy(H->sweep_ev[lv][i].first);
-      (void)hipEventDestroy(H->sweep_ev[lv][i].second);
+      locked_event_destroy(H->sweep_ev[lv][i].first);
+      locked_event_destroy(H->sweep_ev[lv][i].second);
     }
     H->sweep_ev[lv].clear();
     H->sweep_flops[lv].clear();
@@ -1091,13 +1151,17 @@ void fgmres_chunk(helm_handle* H, int nr, double tol, int maxit, bool x0, void* 
     if (compact && nact < nr) compact_batch(H, nr, orig, X, r0, out);
     const long long vs = n * nr;
     launch_scale(W.w.as<z64>(), K.fac.as<double>(), W.V.as<z64>(), n, nr, H->stream);
+    int steps = 0;  // basis vectors Z_0 .. Z_{steps-1} written in this cycle
     for (int j = 0; j < m; ++j) {
       run_outer_step(H, nr, j, tol, maxit);
+      steps = j + 1;
       if (read_counter(H, K) == 0) break;
       launch_scale(W.w.as<z64>(), K.fac.as<double>(), W.V.as<z64>() + (j + 1) * vs, n, nr, H->stream);
     }
     launch_backsolve(K.st, H->stream);
-    launch_update(W.Zv.as<z64>(), vs, m, K.y.as<z64>(), W.x.as<z64>(), n, nr, H->stream);
+    // only the vectors of this cycle: the rest of Z holds stale (pooled) memory,
+    // and 0 * NaN would spoil x even where y is zero
+    launch_update(W.Zv.as<z64>(), vs, steps, K.y.as<z64>(), W.x.as<z64>(), n, nr, H->stream);
     fine_product(H, nr, W.b.as<z64>(), W.x.as<z64>(), W.w.as<z64>());
     launch_norm2(W.w.as<z64>(), n, nr, W.dpart.as<double>(), W.beta2.as<double>(), H->stream);
     zero_counter(H, K);
@@ -1113,8 +1177,8 @@ struct Timer {
   hipEvent_t a, b;
   hipStream_t s;
   explicit Timer(hipStream_t st) : s(st) {
-    HELM_CHECK_HIP(hipEventCreate(&a));
-    HELM_CHECK_HIP(hipEventCreate(&b));
+    HELM_CHECK_HIP(locked_event_create(&a));
+    HELM_CHECK_HIP(locked_event_create(&b));
     HELM_CHECK_HIP(hipEventRecord(a, s));
   }
   double stop() {
@@ -1125,8 +1189,8 @@ struct Timer {
     return ms * 1e-3;
   }
   ~Timer() {
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
+    locked_event_destroy(a);
+    locked_event_destroy(b);
   }
 };
 
@@ -1174,15 +1238,23 @@ void upload_subs(Level& L, hipStream_t stream) {
   HELM_CHECK_HIP(hipStreamSynchronize(stream));
 }
 
-void setup_impl(helm_handle* H, const void* velocity) {
+void setup_impl(helm_handle* H, const void* velocity, int vel_kind) {
   HELM_CHECK_HIP(hipGetDevice(&H->device));
-  HELM_CHECK_HIP(hipStreamCreateWithFlags(&H->own, hipStreamNonBlocking));
+  H->own = streams().acquire(H->device);
   H->stream = H->own;
   const long long n = H->n;
-  // velocity: validate on the host
+  // velocity: copied to the host (a real array widened to complex with zero
+  // imaginary parts) and validated there
   std::vector<z64> ch((size_t)n);
-  HELM_CHECK_HIP(hipMemcpyAsync(ch.data(), velocity, sizeof(z64) * n, hipMemcpyDefault, H->stream));
-  HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+  if (vel_kind == HELM_VEL_REAL64) {
+    std::vector<double> cr((size_t)n);
+    HELM_CHECK_HIP(hipMemcpyAsync(cr.data(), velocity, sizeof(double) * n, hipMemcpyDefault, H->stream));
+    HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+    for (long long i = 0; i < n; ++i) ch[i] = mk(cr[i], 0.0);
+  } else {
+    HELM_CHECK_HIP(hipMemcpyAsync(ch.data(), velocity, sizeof(z64) * n, hipMemcpyDefault, H->stream));
+    HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+  }
   for (long long i = 0; i < n; ++i) {
     if (!std::isfinite(ch[i].re) || !std::isfinite(ch[i].im) || !(ch[i].re > 0))
       throw HelmError(HELM_EINVAL, "velocity must be finite with a positive real part");
@@ -1297,11 +1369,14 @@ helm_status helm_fit_weights(double gmin, double gmax, int32_t ng, int32_t nang,
   });
 }
 
-helm_status helm_setup(const helm_grid_t* grid, const void* velocity, double freq_hz, const helm_pml_t* pml,
-                       const helm_weights_t* weights, const helm_decomp_t* dec, helm_handle_t** out) {
+helm_status helm_setup(const helm_grid_t* grid, const void* velocity, int32_t vel_kind, double freq_hz,
+                       const helm_pml_t* pml, const helm_weights_t* weights, const helm_decomp_t* dec,
+                       helm_handle_t** out) {
   return guarded([&]() {
     if (!out || !velocity) throw HelmError(HELM_EINVAL, "null argument");
     *out = nullptr;
+    if (vel_kind != HELM_VEL_COMPLEX128 && vel_kind != HELM_VEL_REAL64)
+      throw HelmError(HELM_EINVAL, "vel_kind must be HELM_VEL_COMPLEX128 or HELM_VEL_REAL64");
     validate(grid, pml, dec);
     if (!(freq_hz > 0) || !std::isfinite(freq_hz)) throw HelmError(HELM_EINVAL, "frequency must be positive");
     int ndev = 0;
@@ -1321,7 +1396,7 @@ helm_status helm_setup(const helm_grid_t* grid, const void* velocity, double fre
     H->dec = *dec;
     if (weights) H->w = *weights;
     else fit_weights_host(4.0, 10.0, 7, 15, &H->w);
-    setup_impl(H.get(), velocity);
+    setup_impl(H.get(), velocity, vel_kind);
     *out = H.release();
     return HELM_OK;
   });
@@ -1424,13 +1499,13 @@ helm_status solve_impl(helm_handle* H, int32_t nrhs, const void* B, void* X, dou
     H->its = its;
     HELM_CHECK_HIP(hipGetLastError());
     return all_conv ? HELM_OK : HELM_NOT_CONVERGED;
-  });
+  }, H);
 }
 }  // namespace
 
 helm_status helm_solve(helm_handle_t* H, int32_t nrhs, const void* B, void* X, double tol, int32_t maxit,
                        uint32_t flags, int32_t* iters, double* relres_est, double* relres_true) {
-  if (H && busy(H)) return fail(HELM_EINVAL, "a solve is already in flight on this handle");
+  if (H && busy(H)) return fail_h(H, HELM_EINVAL, "a solve is already in flight on this handle");
   return solve_impl(H, nrhs, B, X, tol, maxit, flags, iters, relres_est, relres_true);
 }
 
@@ -1506,7 +1581,7 @@ helm_status helm_last_timings(const helm_handle_t* H, double out[5]) {
 
 helm_status helm_solve_async(helm_handle_t* H, int32_t nrhs, const void* B, void* X, double tol, int32_t maxit,
                              uint32_t flags, int32_t* iters, double* relres_est, double* relres_true,
-                             helm_request_t** req) {
+                             void* stream, helm_request_t** req) {
   return guarded([&]() {
     if (!H || !B || !X || !req || nrhs < 0 || !(tol >= 0) || maxit < 0)
       throw HelmError(HELM_EINVAL, "bad solve arguments");
@@ -1516,14 +1591,20 @@ helm_status helm_solve_async(helm_handle_t* H, int32_t nrhs, const void* B, void
     q->H = H;
     helm_request* qp = q.get();
     H->pending = qp;
+    const hipStream_t on = stream ? (hipStream_t)stream : nullptr;
     try {
       qp->worker = std::thread([=]() {
         helm_status st;
         if (hipSetDevice(H->device) != hipSuccess) {
           (void)hipGetLastError();
-          st = fail(HELM_EDEVICE, "hipSetDevice failed on the solve thread");
+          st = fail_h(H, HELM_EDEVICE, "hipSetDevice failed on the solve thread");
         } else {
+          // the solve's device work goes to the caller's stream, if given (the
+          // handle is busy meanwhile: no other call uses its stream)
+          const hipStream_t keep = H->stream;
+          if (on) H->stream = on;
           st = solve_impl(H, nrhs, B, X, tol, maxit, flags, iters, relres_est, relres_true);
+          H->stream = keep;
         }
         if (st != HELM_OK && st != HELM_NOT_CONVERGED) qp->message = g_last_error;
         qp->status.store(st);
@@ -1535,7 +1616,7 @@ helm_status helm_solve_async(helm_handle_t* H, int32_t nrhs, const void* B, void
     }
     *req = q.release();
     return HELM_OK;
-  });
+  }, H);
 }
 
 helm_status helm_request_query(const helm_request_t* q) {
@@ -1575,6 +1656,8 @@ size_t helm_trim_cache(void) {
   return b;
 }
 
+size_t helm_device_headroom(void) { return DevicePool::headroom_bytes(); }
+
 helm_status helm_release_workspace(helm_handle_t* H) {
   return guarded([&]() {
     if (!H) throw HelmError(HELM_EINVAL, "null handle");
@@ -1585,7 +1668,7 @@ helm_status helm_release_workspace(helm_handle_t* H) {
     H->ws.~Workspace();  // buffers go back to the device cache
     new (&H->ws) Workspace();
     return HELM_OK;
-  });
+  }, H);
 }
 
 helm_status helm_set_sweep_timing(helm_handle_t* H, int32_t enable) {
@@ -1602,7 +1685,7 @@ helm_status helm_set_graphs(helm_handle_t* H, int32_t enable) {
     drop_graphs(H);
     H->graphs = enable != 0;
     return HELM_OK;
-  });
+  }, H);
 }
 
 helm_status helm_set_sweep_policy(int32_t policy) {
@@ -1648,7 +1731,13 @@ helm_status helm_stencil_stats(const helm_handle_t* H, int32_t kind, double out[
   return HELM_OK;
 }
 
-const char* helm_last_error(void) { return g_last_error.c_str(); }
+const char* helm_last_error(const helm_handle_t* H) {
+  if (!H) return g_last_error.c_str();
+  thread_local std::string copy;  // stable for the caller while the handle may fail again elsewhere
+  std::lock_guard<std::mutex> lk(H->err_mu);
+  copy = H->err_msg;
+  return copy.c_str();
+}
 
 helm_status helm_set_stream(helm_handle_t* H, void* stream) {
   if (!H) return fail(HELM_EINVAL, "null handle");
@@ -1680,7 +1769,7 @@ helm_status map_fields(helm_handle_t* H, int nrhs, long long len_in, long long l
     collect_sweep_timing(H);
     HELM_CHECK_HIP(hipGetLastError());
     return HELM_OK;
-  });
+  }, H);
 }
 }  // namespace
 
@@ -1701,7 +1790,7 @@ helm_status helm_apply_M(helm_handle_t* H, int32_t nrhs, const void* R, void* Z)
 
 helm_status helm_apply_oras(helm_handle_t* H, int32_t level, int32_t nrhs, const void* R, void* Z) {
   if (!H) return fail(HELM_EINVAL, "null handle");
-  if (level != 0 && !(level == 1 && H->two_level())) return fail(HELM_EINVAL, "no such level");
+  if (level != 0 && !(level == 1 && H->two_level())) return fail_h(H, HELM_EINVAL, "no such level");
   Level& L = level == 0 ? H->fine : H->coarse;
   return map_fields(H, nrhs, L.n, L.n, R, Z, [&](const z64* r, z64* z) {
     ensure_ws(H, nrhs);
@@ -1747,7 +1836,7 @@ helm_status helm_local_solve(helm_handle_t* H, int32_t level, int32_t s, int32_t
     HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
     HELM_CHECK_HIP(hipGetLastError());
     return HELM_OK;
-  });
+  }, H);
 }
 
 helm_status helm_restrict(helm_handle_t* H, int32_t nrhs, const void* R, void* C) {

@@ -2,7 +2,17 @@
 // laid out node-major, right-hand side fastest: element (node, r) at
 // node*nrhs + r, complex interleaved.
 #pragma once
+#include <mutex>
+
 #include "common.h"
+
+// Runtime objects -- streams, events, executable graphs -- are created and
+// destroyed under one process-wide lock, which stream capture also holds
+// (helm_api.hip): no thread creates or destroys one while another records a
+// graph.  Handles take their streams from a pool that never destroys them.
+std::recursive_mutex& capture_lock();
+hipError_t locked_event_create(hipEvent_t* e);
+void locked_event_destroy(hipEvent_t e);
 
 // ---- medium and operator (ops_operator.hip) --------------------------------
 struct AxisPml {
@@ -79,9 +89,11 @@ struct Factor {
                     hipStream_t s);
   // one application of the batched local solves on all subdomains:
   // z = sum_i R_i^T D_i A_i^{-1} R_i u  (+ add if add != nullptr)
+  // may_tune = false: an untuned shape takes the default launch shape instead of
+  // timing the candidates (the tuner creates events and synchronises)
   static void sweep(const Sub* subs, int nsub, int bpmax, int maxez, const cpx<T>* cpl,
                     const cpx<T>* sinv, int nrhs, const z64* u, z64* z, const z64* add,
-                    int gnx, int gny, cpx<T>* yloc, cpx<T>* tbuf, hipStream_t s);
+                    int gnx, int gny, cpx<T>* yloc, cpx<T>* tbuf, hipStream_t s, bool may_tune = true);
 };
 
 // Panel width (columns) of the blocked Gauss-Jordan plane inversion: 0 =
@@ -92,7 +104,7 @@ bool set_lu_panel(int nb);
 // Returns false when the plane does not fit the kernel's LDS budget.
 template <typename T>
 bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const cpx<T>* sinv, int nrhs, const z64* u,
-                z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc, hipStream_t s);
+                z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc, hipStream_t s, bool may_tune = true);
 template <typename T>
 int fused_group(int bpmax, int nrhs);
 // right-hand-side group the autotuner chose for this shape (0 = not tuned yet)

@@ -829,8 +829,8 @@ void Factor<T>::plane(const Sub* subs, int nsub, int bpmax, int k, const z64* al
     int nb[2];
     const int nc = gj_candidates((int)ceil_div(bpmax, 256), nb);
     hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+    (void)locked_event_create(&e0);
+    (void)locked_event_create(&e1);
     int best_nb = nb[0];
     float best = 1e30f;
     for (int i = 0; i < nc; ++i) {
@@ -849,8 +849,8 @@ void Factor<T>::plane(const Sub* subs, int nsub, int bpmax, int k, const z64* al
         best_nb = nb[i];
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    locked_event_destroy(e0);
+    locked_event_destroy(e1);
     static const bool verbose = std::getenv("HELM_TUNE_VERBOSE") != nullptr;
     if (verbose)
       std::fprintf(stderr, "helm: LU panel tuned (fp%d, bp %d, %d boxes): %d columns, %.3f ms per plane\n",
@@ -864,9 +864,9 @@ void Factor<T>::plane(const Sub* subs, int nsub, int bpmax, int k, const z64* al
 template <typename T>
 void Factor<T>::sweep(const Sub* subs, int nsub, int bpmax, int maxez, const cpx<T>* cpl, const cpx<T>* sinv,
                       int nrhs, const z64* u, z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc,
-                      cpx<T>* tbuf, hipStream_t s) {
+                      cpx<T>* tbuf, hipStream_t s, bool may_tune) {
   static const bool no_fused = std::getenv("HELM_NO_FUSED") != nullptr;
-  if (!no_fused && oras_fused<T>(subs, nsub, bpmax, cpl, sinv, nrhs, u, z, add, gnx, gny, yloc, s)) return;
+  if (!no_fused && oras_fused<T>(subs, nsub, bpmax, cpl, sinv, nrhs, u, z, add, gnx, gny, yloc, s, may_tune)) return;
   dim3 gv((unsigned)ceil_div((long long)bpmax * nrhs, 256), nsub);
   const int nr = nrhs % 8 == 0 ? 8 : nrhs % 4 == 0 ? 4 : nrhs % 2 == 0 ? 2 : 1;
   dim3 gg((unsigned)ceil_div((long long)bpmax * (nrhs / nr), 256), nsub);

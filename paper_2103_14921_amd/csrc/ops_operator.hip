@@ -520,8 +520,8 @@ int tuned_nxt(const RowKey& key, hipStream_t s, Launch&& launch) {
   (void)hipStreamIsCapturing(s, &cap);
   if (row_no_tune() || cap != hipStreamCaptureStatusNone) return 4;
   hipEvent_t e0, e1;
-  (void)hipEventCreate(&e0);
-  (void)hipEventCreate(&e1);
+  (void)locked_event_create(&e0);
+  (void)locked_event_create(&e1);
   int bestn = 4;
   float best = 1e30f;
   for (int nxt : {2, 4, 8}) {
@@ -540,8 +540,8 @@ int tuned_nxt(const RowKey& key, hipStream_t s, Launch&& launch) {
       bestn = nxt;
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  locked_event_destroy(e0);
+  locked_event_destroy(e1);
   static const bool verbose = std::getenv("HELM_TUNE_VERBOSE") != nullptr;
   if (verbose)
     std::fprintf(stderr, "helm: %s tuned (%dx%dx%d, %d rhs): %d nodes per thread, %.3f ms\n",

@@ -550,7 +550,7 @@ int tuned_group(int es, int bpmax, int nsub, int nrhs, int gnx, int gny) {
 
 template <typename T>
 bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const cpx<T>* sinv, int nrhs, const z64* u,
-                z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc, hipStream_t s) {
+                z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc, hipStream_t s, bool may_tune) {
   const int rgmax = fused_group<T>(bpmax, nrhs);
   if (rgmax == 0) return false;
   const int policy = g_sweep_policy.load();
@@ -569,13 +569,13 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   (void)hipStreamIsCapturing(s, &cap);
   const int r0 = min_rounds<T>(bpmax), nmt = bpmax / 16;
-  if (tv.rg == 0 && !no_tune && cap == hipStreamCaptureStatusNone) {
+  if (tv.rg == 0 && !no_tune && may_tune && cap == hipStreamCaptureStatusNone) {
     // time every admissible (group, rounds) pair twice on this very input (the
     // sweep is idempotent: z and the scratch planes are overwritten) and keep
     // the fastest
     hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+    (void)locked_event_create(&e0);
+    (void)locked_event_create(&e1);
     float best = 1e30f;
     static const bool verbose = std::getenv("HELM_TUNE_VERBOSE") != nullptr;
     for (int cand = 8; cand <= rgmax; cand *= 2) {
@@ -607,8 +607,8 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
         }
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    locked_event_destroy(e0);
+    locked_event_destroy(e1);
     if (verbose)
       std::fprintf(stderr, "helm: sweep tuned (fp%d, bp %d, %d boxes, %d rhs): group %d, %s %d waves, %.3f ms\n",
                    (int)sizeof(T) * 8, bpmax, nsub, nrhs, tv.rg, tv.rounds == 0 ? "pipelined," : "",
@@ -631,8 +631,8 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
 }
 
 template bool oras_fused<float>(const Sub*, int, int, const c32*, const c32*, int, const z64*, z64*, const z64*, int,
-                                int, c32*, hipStream_t);
+                                int, c32*, hipStream_t, bool);
 template bool oras_fused<double>(const Sub*, int, int, const z64*, const z64*, int, const z64*, z64*, const z64*, int,
-                                 int, z64*, hipStream_t);
+                                 int, z64*, hipStream_t, bool);
 template int fused_group<float>(int, int);
 template int fused_group<double>(int, int);

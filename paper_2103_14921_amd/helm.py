@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhelm.so")
 HELM_OK, HELM_NOT_CONVERGED, HELM_PENDING = 0, 1, 2
 HELM_EINVAL, HELM_ENOMEM, HELM_EDEVICE, HELM_EBREAKDOWN = -1, -2, -3, -4
 HELM_FP64, HELM_MIXED, HELM_SINGLE_LOCAL = 0, 1, 2
+HELM_VEL_COMPLEX128, HELM_VEL_REAL64 = 0, 1
 PRECISIONS = {"fp64": HELM_FP64, "mixed": HELM_MIXED, "single_local": HELM_SINGLE_LOCAL}
 
 
@@ -41,6 +42,7 @@ EXPORTS = [
     "helm_set_row_tiling",
     "helm_set_lu_panel",
     "helm_solve_async", "helm_request_query", "helm_request_wait", "helm_solve_bound",
+    "helm_device_headroom",
 ]
 
 
@@ -88,7 +90,7 @@ def _load():
     i32 = C.c_int32
     sig = {
         "helm_fit_weights": ([C.c_double, C.c_double, i32, i32, C.POINTER(WeightsT)], C.c_int),
-        "helm_setup": ([C.POINTER(Grid), P, C.c_double, C.POINTER(PmlT), C.POINTER(WeightsT),
+        "helm_setup": ([C.POINTER(Grid), P, i32, C.c_double, C.POINTER(PmlT), C.POINTER(WeightsT),
                         C.POINTER(DecompT), C.POINTER(P)], C.c_int),
         "helm_solve": ([P, i32, P, P, C.c_double, i32, C.c_uint32, P, P, P], C.c_int),
         "helm_footprint": ([C.POINTER(Grid), C.POINTER(DecompT), i32], C.c_size_t),
@@ -96,7 +98,7 @@ def _load():
         "helm_resident_bytes": ([P], C.c_size_t),
         "helm_last_timings": ([P, C.POINTER(C.c_double)], C.c_int),
         "helm_destroy": ([P], None),
-        "helm_last_error": ([], C.c_char_p),
+        "helm_last_error": ([P], C.c_char_p),
         "helm_set_stream": ([P, P], C.c_int),
         "helm_apply_A": ([P, i32, P, P], C.c_int),
         "helm_apply_M": ([P, i32, P, P], C.c_int),
@@ -118,10 +120,12 @@ def _load():
         "helm_set_sweep_policy": ([i32], C.c_int),
         "helm_set_row_tiling": ([i32], C.c_int),
         "helm_set_lu_panel": ([i32], C.c_int),
-        "helm_solve_async": ([P, i32, P, P, C.c_double, i32, C.c_uint32, P, P, P, C.POINTER(C.c_void_p)], C.c_int),
+        "helm_solve_async": ([P, i32, P, P, C.c_double, i32, C.c_uint32, P, P, P, P, C.POINTER(C.c_void_p)],
+                             C.c_int),
         "helm_request_query": ([P], C.c_int),
         "helm_request_wait": ([P], C.c_int),
         "helm_solve_bound": ([P, C.POINTER(C.c_double)], C.c_int),
+        "helm_device_headroom": ([], C.c_size_t),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -133,13 +137,14 @@ def _load():
 lib = _load()
 
 
-def last_error():
-    return lib.helm_last_error().decode()
+def last_error(handle=None):
+    """Message of the last failure on the calling thread, or of the last failed call on a handle."""
+    return lib.helm_last_error(handle).decode()
 
 
-def _check(code, ok=(HELM_OK,)):
+def _check(code, ok=(HELM_OK,), handle=None):
     if code not in ok:
-        raise HelmError(code, last_error())
+        raise HelmError(code, last_error(handle))
     return code
 
 
@@ -153,21 +158,29 @@ def _is_torch(a):
     return type(a).__module__.startswith("torch")
 
 
-def _ptr(a, n_expect):
-    """Pointer of a contiguous complex128 buffer holding n_expect elements."""
+def _ptr(a, n_expect, real=False):
+    """Pointer of a contiguous complex128 (or, with real=True, float64) buffer of n_expect elements."""
     if _is_torch(a):
         import torch
-        if a.dtype != torch.complex128 or not a.is_contiguous() or a.numel() != n_expect:
-            raise ValueError("expected a contiguous complex128 tensor of %d elements" % n_expect)
+        want = torch.float64 if real else torch.complex128
+        if a.dtype != want or not a.is_contiguous() or a.numel() != n_expect:
+            raise ValueError("expected a contiguous %s tensor of %d elements" % (want, n_expect))
         return C.c_void_p(a.data_ptr())
-    if not isinstance(a, np.ndarray) or a.dtype != np.complex128 or not a.flags.c_contiguous or a.size != n_expect:
-        raise ValueError("expected a C-contiguous complex128 array of %d elements" % n_expect)
+    want = np.float64 if real else np.complex128
+    if not isinstance(a, np.ndarray) or a.dtype != want or not a.flags.c_contiguous or a.size != n_expect:
+        raise ValueError("expected a C-contiguous %s array of %d elements" % (np.dtype(want), n_expect))
     return C.c_void_p(a.ctypes.data)
 
 
 def trim_cache():
     """Return the library's cached device blocks to the runtime; bytes freed."""
     return lib.helm_trim_cache()
+
+
+def device_headroom():
+    """Device bytes the library leaves to the runtime (helm_device_headroom); other
+    allocations beside the library keep the same margin."""
+    return lib.helm_device_headroom()
 
 
 def torch_alloc(fn):
@@ -280,9 +293,17 @@ class Solver:
             if not isinstance(weights, dict):
                 weights = {k: float(getattr(weights, k)) for k, _ in WeightsT._fields_}
             w = WeightsT(**{k: float(weights[k]) for k, _ in WeightsT._fields_})
-        vel = velocity if _is_torch(velocity) else np.ascontiguousarray(velocity, dtype=np.complex128)
+        # a real velocity array (float64) is passed as HELM_VEL_REAL64, anything else as complex128
+        if _is_torch(velocity):
+            import torch
+            real = velocity.dtype == torch.float64
+            vel = velocity
+        else:
+            real = np.asarray(velocity).dtype == np.float64
+            vel = np.ascontiguousarray(velocity, dtype=np.float64 if real else np.complex128)
         handle = C.c_void_p()
-        _check(lib.helm_setup(C.byref(g), _ptr(vel, self.n), float(freq), C.byref(p),
+        _check(lib.helm_setup(C.byref(g), _ptr(vel, self.n, real=real),
+                              HELM_VEL_REAL64 if real else HELM_VEL_COMPLEX128, float(freq), C.byref(p),
                               C.byref(w) if w is not None else None, C.byref(d), C.byref(handle)))
         self._h = handle
 
@@ -308,19 +329,23 @@ class Solver:
         code = lib.helm_solve(self._h, nrhs, _ptr(B, nrhs * self.n), _ptr(X, nrhs * self.n), float(tol), int(maxit),
                               flags, its.ctypes.data_as(C.c_void_p), est.ctypes.data_as(C.c_void_p),
                               tru.ctypes.data_as(C.c_void_p))
-        _check(code, ok=(HELM_OK, HELM_NOT_CONVERGED))
+        _check(code, ok=(HELM_OK, HELM_NOT_CONVERGED), handle=self._h)
         return X, dict(status=code, iters=its, relres_est=est, relres_true=tru, timings=self.timings())
 
-    def solve_async(self, B, tol=1e-8, maxit=500, X0=None):
-        """Start the solve of A X = B on a library thread; returns a Request (wait() -> (X, info))."""
+    def solve_async(self, B, tol=1e-8, maxit=500, X0=None, stream=None):
+        """Start the solve of A X = B on a library thread; returns a Request (wait() -> (X, info)).
+
+        stream: a torch.cuda.Stream (or raw hipStream_t) that receives the solve's device work, ordered
+        after what was already enqueued on it; None = the handle's own stream."""
         nrhs = B.shape[0]
         X = _empty_like_kind(B, tuple(B.shape)) if X0 is None else X0
         req = Request(self, B, X, nrhs)
         h = C.c_void_p()
+        sp = None if stream is None else C.c_void_p(getattr(stream, "cuda_stream", stream))
         _check(lib.helm_solve_async(self._h, nrhs, _ptr(B, nrhs * self.n), _ptr(X, nrhs * self.n), float(tol),
                                     int(maxit), HELM_X0 if X0 is not None else 0,
                                     req.its.ctypes.data_as(C.c_void_p), req.est.ctypes.data_as(C.c_void_p),
-                                    req.tru.ctypes.data_as(C.c_void_p), C.byref(h)))
+                                    req.tru.ctypes.data_as(C.c_void_p), sp, C.byref(h)), handle=self._h)
         req._h = h
         return req
 
@@ -367,8 +392,12 @@ class Solver:
     def _map(self, fn, X, n_in, n_out, *lead):
         nrhs = X.shape[0]
         Y = _empty_like_kind(X, (nrhs, n_out))
-        _check(fn(self._h, *lead, nrhs, _ptr(X, nrhs * n_in), _ptr(Y, nrhs * n_out)))
+        _check(fn(self._h, *lead, nrhs, _ptr(X, nrhs * n_in), _ptr(Y, nrhs * n_out)), handle=self._h)
         return Y
+
+    def last_error(self):
+        """Message of the last failed call on this handle (helm_last_error(h))."""
+        return last_error(self._h)
 
     def apply_A(self, X):
         return self._map(lib.helm_apply_A, X, self.n, self.n)

@@ -1,0 +1,105 @@
+"""The C ABI's boundary behaviour on the GPU: real velocities, the caller's
+stream for asynchronous solves, and per-handle error messages (include/helm.h)."""
+import numpy as np
+import pytest
+
+import inputs
+from oracle.operator import fit_weights
+
+pytestmark = pytest.mark.gpu
+
+WO = fit_weights()
+W = {k: getattr(WO, k) for k in ("w1", "w2", "w3", "wm1", "wm2", "wm3", "wm4")}
+
+
+def helm():
+    from paper_2103_14921_amd import helm as h
+    return h
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _case(shape=(28, 26, 24)):
+    h, f = 25.0, 10.0
+    c = inputs.velocity_thrust_belt(*shape, h=h)  # real-valued model, stored as complex
+    src = inputs.source_grid(shape[0], shape[1], 5, 5, 2, 1, iz=4)
+    b = inputs.point_source_rhs(*shape, src).reshape(len(src), -1)
+    return shape, h, c, f, b
+
+
+def test_real_velocity_setup_equals_complex_bitwise():
+    # HELM_VEL_REAL64 sets up exactly the operator of the complex array with zero
+    # imaginary parts: solutions and iteration counts are bitwise equal
+    shape, h, c, f, b = _case()
+    assert not np.any(c.imag)
+    say("real vs complex velocity", shape)
+    out = []
+    for vel in (np.ascontiguousarray(c.real), c):
+        S = helm().Solver(shape, h, vel, f, (5, 5, 5, 0), weights=W, parts=(2, 2, 2), overlap=2, levels=2,
+                          restart=20)
+        X, info = S.solve(b, tol=1e-8, maxit=300)
+        out.append((X, info["iters"].copy()))
+        S.close()
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][0], out[1][0])
+
+
+def test_real_velocity_from_device_memory():
+    import torch
+    shape, h, c, f, b = _case()
+    say("real device velocity", shape)
+    dev = torch.device("cuda:0")
+    S1 = helm().Solver(shape, h, torch.from_numpy(np.ascontiguousarray(c.real)).to(dev), f, (5, 5, 5, 0),
+                       weights=W, parts=(2, 2, 2), levels=2, restart=20)
+    S2 = helm().Solver(shape, h, c, f, (5, 5, 5, 0), weights=W, parts=(2, 2, 2), levels=2, restart=20)
+    X1 = S1.apply_M(b)
+    X2 = S2.apply_M(b)
+    assert np.array_equal(X1, X2)
+    S1.close()
+    S2.close()
+
+
+def test_async_solve_on_the_callers_stream():
+    # the right-hand sides are produced on a stream of the caller's; the solve is
+    # given that stream, so it runs after them without a host synchronisation,
+    # and its results are bitwise those of the synchronous solve
+    import torch
+    shape, h, c, f, b = _case()
+    say("async on caller stream", shape)
+    dev = torch.device("cuda:0")
+    S = helm().Solver(shape, h, c, f, (5, 5, 5, 0), weights=W, parts=(2, 2, 2), levels=2, restart=20)
+    Xs, inf = S.solve(b, tol=1e-8, maxit=300)
+    st = torch.cuda.Stream(device=dev)
+    src = torch.from_numpy(b).to(dev)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(st):
+        torch.cuda._sleep(20_000_000)  # keep the stream busy, so the solve must wait behind B
+        B = src * 2.0
+        B.mul_(0.5)  # exactly b again, produced on the caller's stream
+    req = S.solve_async(B, tol=1e-8, maxit=300, stream=st)
+    X, info = req.wait()
+    torch.cuda.synchronize()
+    assert np.array_equal(info["iters"], inf["iters"])
+    assert np.array_equal(X.cpu().numpy(), Xs)
+    S.close()
+
+
+def test_last_error_is_kept_per_handle():
+    shape, h, c, f, b = _case()
+    say("per-handle errors")
+    S1 = helm().Solver(shape, h, c, f, (5, 5, 5, 0), weights=W, parts=(2, 2, 2), levels=1)
+    S2 = helm().Solver(shape, h, c, f, (5, 5, 5, 0), weights=W, parts=(2, 2, 2), levels=1)
+    with pytest.raises(helm().HelmError):
+        S1.apply_oras(b, level=1)  # one-level handle: no coarse level
+    m1 = S1.last_error()
+    assert "level" in m1
+    # a later failure elsewhere on this thread does not overwrite the handle's message
+    with pytest.raises(helm().HelmError):
+        helm().fit_weights(ng=0)
+    assert S1.last_error() == m1
+    assert S2.last_error() == ""
+    assert "fit" in helm().last_error()
+    S1.close()
+    S2.close()
