@@ -92,7 +92,7 @@ def test_last_error_is_kept_per_handle():
     S1 = helm().Solver(shape, h, c, f, (5, 5, 5, 0), weights=W, parts=(2, 2, 2), levels=1)
     S2 = helm().Solver(shape, h, c, f, (5, 5, 5, 0), weights=W, parts=(2, 2, 2), levels=1)
     with pytest.raises(helm().HelmError):
-        S1.apply_oras(b, level=1)  # one-level handle: no coarse level
+        S1.apply_oras(np.zeros((2, S1.nc), complex), level=1)  # one-level handle: no coarse level
     m1 = S1.last_error()
     assert "level" in m1
     # a later failure elsewhere on this thread does not overwrite the handle's message
