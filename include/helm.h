@@ -315,6 +315,21 @@ helm_status helm_apply_M(helm_handle_t* h, int32_t nrhs, const void* R, void* Z)
  * ceil(n/2) per axis). */
 helm_status helm_apply_oras(helm_handle_t* h, int32_t level, int32_t nrhs, const void* R, void* Z);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): Z = M1^{-1} R
+ * as helm_apply_oras computes it, with no allocation of any kind.  R and Z are
+ * device arrays owned by the caller, complex128 [nrhs][n of the level] (x
+ * fastest); R is not modified.  The node-major staging of R and Z and the
+ * sweep's plane vectors live in a fixed scratch array of 64 MiB per GPU, which
+ * the library holds from its first use on that GPU until the process ends; a
+ * level and batch needing more return HELM_EINVAL (helm_apply_oras has no such
+ * limit).  A shape the sweep autotuner has not timed yet takes its default
+ * launch shape.  The work is enqueued on the handle's stream and the call
+ * returns without waiting for it.  Every call on one GPU shares that GPU's
+ * scratch, which keeps the last call's contents: calls that overlap on one
+ * GPU (other handles, streams or threads) race, so callers order them. */
+helm_status helm_apply_oras_noalloc(helm_handle_t* h, int32_t level, int32_t nrhs, const void* R, void* Z);
+
 /* X = A_i^{-1} R for one subdomain s of a level (the local problem of eq.
  * oras, with its absorbing interface fold), through the same factors and
  * sweep kernels as the preconditioner.  R, X: complex128 [nrhs][ez][ey][ex]

@@ -1799,6 +1799,86 @@ helm_status helm_apply_oras(helm_handle_t* H, int32_t level, int32_t nrhs, const
   });
 }
 
+}  // extern "C"
+
+// ---- the allocation-free one-level ORAS application ------------------------
+
+namespace {
+// Device scratch of helm_apply_oras_noalloc: node-major staging of R and Z and
+// the sweep's plane vectors.  A file-scope device array, so each GPU the
+// library runs on holds its own copy until the process ends.  In host code its
+// name is not a device address: the address comes from hipGetSymbolAddress,
+// once per device, and only that address reaches kernels and copies.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+void* scratch_on_current_device() {
+  constexpr int MAXDEV = 64;
+  static void* ptr[MAXDEV] = {};
+  static std::mutex mu;
+  int dev = 0;
+  HELM_CHECK_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAXDEV) throw HelmError(HELM_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw HelmError(HELM_EDEVICE, std::string("hipGetSymbolAddress of the scratch array failed: ") +
+                                        hipGetErrorString(e));
+    ptr[dev] = p;
+  }
+  return ptr[dev];
+}
+
+bool on_device(const void* p) {
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+}  // namespace
+
+extern "C" {
+
+helm_status helm_apply_oras_noalloc(helm_handle_t* H, int32_t level, int32_t nrhs, const void* R, void* Z) {
+  return guarded([&]() {
+    if (!H || !R || !Z || nrhs < 1 || nrhs > 256) throw HelmError(HELM_EINVAL, "bad arguments");
+    if (level != 0 && !(level == 1 && H->two_level())) throw HelmError(HELM_EINVAL, "no such level");
+    if (busy(H)) throw HelmError(HELM_EINVAL, "a solve is in flight on this handle");
+    if (!on_device(R) || !on_device(Z)) throw HelmError(HELM_EINVAL, "R and Z must be device memory");
+    Level& L = level == 0 ? H->fine : H->coarse;
+    const size_t es = elem_size(L.prec);
+    const size_t fld = align256(sizeof(z64) * (size_t)L.n * nrhs);
+    const size_t yl = align256((size_t)L.vec_total * nrhs * es);
+    const size_t tb = align256((size_t)L.nsub * L.bpmax * nrhs * es);
+    const size_t need = 2 * fld + yl + tb;
+    if (need > NOALLOC_SCRATCH_BYTES)
+      throw HelmError(HELM_EINVAL, "helm_apply_oras_noalloc needs " + std::to_string(need) +
+                                       " bytes of scratch for this level and batch; the limit is " +
+                                       std::to_string(NOALLOC_SCRATCH_BYTES) + " (use helm_apply_oras)");
+    char* base = static_cast<char*>(scratch_on_current_device());
+    z64* ni = reinterpret_cast<z64*>(base);
+    z64* no = reinterpret_cast<z64*>(base + fld);
+    void* ylp = base + 2 * fld;
+    void* tbp = base + 2 * fld + yl;
+    launch_to_node_major(static_cast<const z64*>(R), ni, L.n, nrhs, H->stream);
+    if (L.prec == 1)
+      Factor<float>::sweep(L.d_subs.as<Sub>(), L.nsub, L.bpmax, L.maxez, L.cpl.as<c32>(), L.sinv.as<c32>(), nrhs, ni,
+                           no, nullptr, L.nx, L.ny, (c32*)ylp, (c32*)tbp, H->stream, false);
+    else
+      Factor<double>::sweep(L.d_subs.as<Sub>(), L.nsub, L.bpmax, L.maxez, L.cpl.as<z64>(), L.sinv.as<z64>(), nrhs, ni,
+                            no, nullptr, L.nx, L.ny, (z64*)ylp, (z64*)tbp, H->stream, false);
+    launch_to_field_major(no, static_cast<z64*>(Z), L.n, nrhs, H->stream);
+    HELM_CHECK_HIP(hipGetLastError());
+    return HELM_OK;
+  }, H);
+}
+
 helm_status helm_local_solve(helm_handle_t* H, int32_t level, int32_t s, int32_t nrhs, const void* R, void* X) {
   return guarded([&]() {
     if (!H || !R || !X || nrhs < 1 || nrhs > 256) throw HelmError(HELM_EINVAL, "bad arguments");

@@ -42,7 +42,7 @@ EXPORTS = [
     "helm_set_row_tiling",
     "helm_set_lu_panel",
     "helm_solve_async", "helm_request_query", "helm_request_wait", "helm_solve_bound",
-    "helm_device_headroom",
+    "helm_device_headroom", "helm_apply_oras_noalloc",
 ]
 
 
@@ -126,6 +126,7 @@ def _load():
         "helm_request_wait": ([P], C.c_int),
         "helm_solve_bound": ([P, C.POINTER(C.c_double)], C.c_int),
         "helm_device_headroom": ([], C.c_size_t),
+        "helm_apply_oras_noalloc": ([P, i32, i32, P, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -408,6 +409,15 @@ class Solver:
     def apply_oras(self, R, level=0):
         n = self.n if level == 0 else self.nc
         return self._map(lib.helm_apply_oras, R, n, n, int(level))
+
+    def apply_oras_noalloc(self, R, Z, level=0):
+        """Z = M1^{-1} R without allocating (helm_apply_oras_noalloc): R and Z are device tensors
+        [nrhs][n]; the work is enqueued on the handle's stream (the call does not wait for it)."""
+        n = self.n if level == 0 else self.nc
+        nrhs = R.shape[0]
+        _check(lib.helm_apply_oras_noalloc(self._h, int(level), nrhs, _ptr(R, nrhs * n), _ptr(Z, nrhs * n)),
+               handle=self._h)
+        return Z
 
     def restrict(self, R):
         return self._map(lib.helm_restrict, R, self.n, self.nc)
