@@ -250,8 +250,13 @@ helm_status helm_graph_stats(const helm_handle_t* h, double out[2]);
  * variants once per problem shape and keeps the fastest; 1 restricts to the
  * one-workgroup-per-box sweep; 2 uses the pipelined persistent sweep (two
  * boxes per compute unit, operand build overlapped with the matrix-core
- * product) wherever its two operand slots fit in LDS.  Results agree to
- * rounding.  Graphs captured under one policy are not replayed under another. */
+ * product) wherever its two operand slots fit in LDS; 3 uses the
+ * one-workgroup-per-box sweep built for two workgroups per compute unit
+ * (complex FP64, groups of 32 right-hand sides, planes of up to 144 nodes)
+ * wherever it exists, else as 1.  Planes whose operand does not fit in LDS
+ * (complex FP64 above 600 nodes, complex FP32 above 1200) keep it in global
+ * memory under every policy.  Results agree to rounding.  Graphs captured
+ * under one policy are not replayed under another. */
 helm_status helm_set_sweep_policy(int32_t policy);
 
 /* Process-wide tiling of the 27-point products (the fine operator of eq. eq1

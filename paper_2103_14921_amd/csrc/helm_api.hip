@@ -327,7 +327,7 @@ size_t level_setup_bytes(const Level& L) {
          (size_t)L.nsub * (16 + 64) * L.bpmax * elem_size(L.prec) + (size_t)L.nsub * L.bpmax * sizeof(int) * 2 + 64;
 }
 size_t level_ws_bytes(const Level& L, int nr) {
-  return ((size_t)L.vec_total * nr + (size_t)L.nsub * L.bpmax * nr) * elem_size(L.prec);
+  return ((size_t)L.vec_total * nr + (size_t)sweep_tbuf_elems(L.nsub, L.bpmax, nr)) * elem_size(L.prec);
 }
 
 }  // namespace
@@ -663,7 +663,7 @@ void ensure_ws(helm_handle* H, int nr) {
   W.V.alloc(vec * (m + 1));
   W.Zv.alloc(vec * m);
   W.yl_f.alloc((size_t)H->fine.vec_total * nr * elem_size(H->fine.prec));
-  W.tb_f.alloc((size_t)H->fine.nsub * H->fine.bpmax * nr * elem_size(H->fine.prec));
+  W.tb_f.alloc((size_t)sweep_tbuf_elems(H->fine.nsub, H->fine.bpmax, nr) * elem_size(H->fine.prec));
   W.zpart.alloc(sizeof(z64) * RED_BLOCKS * 32 * (size_t)nr);
   W.dpart.alloc(sizeof(double) * RED_BLOCKS * (size_t)nr);
   W.bn2.alloc(sizeof(double) * nr);
@@ -681,7 +681,7 @@ void ensure_ws(helm_handle* H, int nr) {
     W.Vc.alloc(cvec * (ci + 1));
     W.Zc.alloc(cvec * ci);
     W.yl_c.alloc((size_t)H->coarse.vec_total * nr * elem_size(H->coarse.prec));
-    W.tb_c.alloc((size_t)H->coarse.nsub * H->coarse.bpmax * nr * elem_size(H->coarse.prec));
+    W.tb_c.alloc((size_t)sweep_tbuf_elems(H->coarse.nsub, H->coarse.bpmax, nr) * elem_size(H->coarse.prec));
     W.kc.alloc(ci, nr);
   }
   W.nr = nr;
@@ -918,8 +918,6 @@ void outer_step(helm_handle* H, int nr, int j, double tol, int maxit) {
 bool sweep_untuned(const Level& L, int nr) {
   static const bool no_tune = std::getenv("HELM_NO_TUNE") != nullptr || std::getenv("HELM_NO_FUSED") != nullptr;
   if (no_tune) return false;
-  const int rgmax = L.prec ? fused_group<float>(L.bpmax, nr) : fused_group<double>(L.bpmax, nr);
-  if (rgmax == 0) return false;  // the per-plane path has nothing to tune
   return tuned_group((int)elem_size(L.prec) / 2, L.bpmax, L.nsub, nr, L.nx, L.ny) == 0;
 }
 
@@ -1689,7 +1687,7 @@ helm_status helm_set_graphs(helm_handle_t* H, int32_t enable) {
 }
 
 helm_status helm_set_sweep_policy(int32_t policy) {
-  if (policy < 0 || policy > 2) return fail(HELM_EINVAL, "sweep policy must be 0, 1 or 2");
+  if (policy < 0 || policy > 3) return fail(HELM_EINVAL, "sweep policy must be 0, 1, 2 or 3");
   set_sweep_policy(policy);
   return HELM_OK;
 }
@@ -1855,7 +1853,7 @@ helm_status helm_apply_oras_noalloc(helm_handle_t* H, int32_t level, int32_t nrh
     const size_t es = elem_size(L.prec);
     const size_t fld = align256(sizeof(z64) * (size_t)L.n * nrhs);
     const size_t yl = align256((size_t)L.vec_total * nrhs * es);
-    const size_t tb = align256((size_t)L.nsub * L.bpmax * nrhs * es);
+    const size_t tb = align256((size_t)sweep_tbuf_elems(L.nsub, L.bpmax, nrhs) * es);
     const size_t need = 2 * fld + yl + tb;
     if (need > NOALLOC_SCRATCH_BYTES)
       throw HelmError(HELM_EINVAL, "helm_apply_oras_noalloc needs " + std::to_string(need) +

@@ -101,12 +101,20 @@ struct Factor {
 bool set_lu_panel(int nb);
 
 // Fused single-launch ORAS local solves on matrix cores (ops_sweep.hip).
-// Returns false when the plane does not fit the kernel's LDS budget.
+// Planes whose operand does not fit in LDS keep it in tbuf (at least
+// sweep_tbuf_elems elements); returns false for them when tbuf is null.
 template <typename T>
 bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const cpx<T>* sinv, int nrhs, const z64* u,
-                z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc, hipStream_t s, bool may_tune = true);
+                z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc, cpx<T>* tbuf, hipStream_t s,
+                bool may_tune = true);
 template <typename T>
 int fused_group(int bpmax, int nrhs);
+// Elements of the sweeps' operand buffer for nsub boxes of planes up to bpmax
+// and nrhs right-hand sides: the per-plane path's [nsub][bpmax][nrhs] and the
+// global-operand sweep's [nsub * ceil(nrhs / 8)][bpmax][16].
+inline long long sweep_tbuf_elems(int nsub, int bpmax, int nrhs) {
+  return (long long)nsub * bpmax * 2 * ((nrhs + 7) / 8 * 8);
+}
 // right-hand-side group the autotuner chose for this shape (0 = not tuned yet)
 int tuned_group(int es, int bpmax, int nsub, int nrhs, int gnx, int gny);
 // process-wide sweep policy: 0 autotune over all variants, 1 one-item sweeps,

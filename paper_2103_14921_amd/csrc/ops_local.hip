@@ -866,7 +866,8 @@ void Factor<T>::sweep(const Sub* subs, int nsub, int bpmax, int maxez, const cpx
                       int nrhs, const z64* u, z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc,
                       cpx<T>* tbuf, hipStream_t s, bool may_tune) {
   static const bool no_fused = std::getenv("HELM_NO_FUSED") != nullptr;
-  if (!no_fused && oras_fused<T>(subs, nsub, bpmax, cpl, sinv, nrhs, u, z, add, gnx, gny, yloc, s, may_tune)) return;
+  if (!no_fused && oras_fused<T>(subs, nsub, bpmax, cpl, sinv, nrhs, u, z, add, gnx, gny, yloc, tbuf, s, may_tune))
+    return;
   dim3 gv((unsigned)ceil_div((long long)bpmax * nrhs, 256), nsub);
   const int nr = nrhs % 8 == 0 ? 8 : nrhs % 4 == 0 ? 4 : nrhs % 2 == 0 ? 2 : 1;
   dim3 gg((unsigned)ceil_div((long long)bpmax * (nrhs / nr), 256), nsub);

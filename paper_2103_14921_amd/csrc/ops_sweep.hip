@@ -193,6 +193,64 @@ __device__ __forceinline__ void put_operand(cpx<T>* Bs, int p, int r, cpx<T> v) 
   }
 }
 
+// Planes too large for their operand in LDS: the operand of an item (the
+// RG = 8 split layout, [bp][16]) lives in a slice of global memory and is read
+// back through L2.  Each chunk's operand values are loaded together with its
+// factor values: lane l reads rows 16 c + 4 (l/16) + t, t < 4, column l % 16 of
+// the operand for chunk c, the rows its A values multiply.
+template <typename T>
+__device__ __forceinline__ void next_chunk_gl(ChunkStream<T>& cs, const cpx<T>* __restrict__ bcol, cpx<T> (&a)[4],
+                                              cpx<T> (&b)[4]) {
+  const int c = cs.tile >= cs.ntw ? cs.nct - 1 : cs.chunk;  // the chunk this load covers (clamped past the end)
+  cs.next(a);
+  const cpx<T>* q = bcol + (long long)c * 16 * 16;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) b[t] = q[t * 16];
+}
+
+// plane_product for RG = 8 with the operand in global memory (bcol = operand +
+// 4 (lane/16) 16 + lane % 16); a and b hold the PF chunks in flight.
+template <typename T, int PF, typename Init, typename Out>
+__device__ __forceinline__ void plane_product_gl(ChunkStream<T>& cs, const cpx<T>* __restrict__ bcol, int wave,
+                                                 int nwaves, int lane, cpx<T> (&a)[PF][4], cpx<T> (&b)[PF][4],
+                                                 Init&& init, Out&& out) {
+  using V4 = typename Mfma<T>::v4;
+  const int lrow = lane & 15, lg = lane >> 4;
+  const int nct = cs.nct, total = cs.ntw * cs.nct;
+  V4 acc;
+  int mt = wave, kc = 0;
+  for (int c0 = 0; c0 < total; c0 += PF) {
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      if (c0 + j < total) {
+        if (kc == 0) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const cpx<T> y0 = init(mt * 16 + Mfma<T>::row(lg, v), lrow & 7);
+            acc[v] = lrow < 8 ? y0.re : y0.im;
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          acc = Mfma<T>::op(a[j][t].re, b[j][t].re, acc);
+          acc = Mfma<T>::op(a[j][t].im, b[j][t].im, acc);
+        }
+        kc += 16;
+        if (kc == 16 * nct) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const T im = __shfl_xor(acc[v], 8);  // column lrow + 8 holds Im of column lrow
+            if (lrow < 8) out(mt * 16 + Mfma<T>::row(lg, v), lrow, mk<T>(acc[v], im));
+          }
+          kc = 0;
+          mt += nwaves;
+        }
+      }
+      next_chunk_gl(cs, bcol, a[j], b[j]);  // chunk c0 + j + PF (unconditional)
+    }
+  }
+}
+
 // LDS holds only the right operand T of the plane product; the plane solutions
 // y_k / x_k live in yloc and reach the other waves of the workgroup through L2
 // (workgroup-scope release/acquire around the barrier).
@@ -242,8 +300,34 @@ struct BoxCtx {
   // bases are 32-bit (plane vectors of a box stay far below 2^31 elements).
   static constexpr int NE = sizeof(T) == 8 ? 1 : 2, LP = RG / NE;
   // v[j] = (u_k - L_k y_{k-1}) (dz = -1, with_u) or -U_k x_{k+1} (dz = +1) at (p, r + j LP)
+  // Taps [I0, I0 + N) of the nine couplings: all loads of the batch are issued
+  // before any is used.
+  template <int I0, int N>
+  __device__ __forceinline__ void taps(int p, int px, int py, int ro, int yo, const int (&col)[NE],
+                                       cpx<T> (&v)[NE]) const {
+    const int ex = sb.ex, ey = sb.ey;
+    cpx<T> cv[N];
+    cpx<T> yv[N][NE];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+      const int i = I0 + n;
+      const int cx = px + i % 3 - 1, cy = py + i / 3 - 1;
+      const bool in = cx >= 0 && cx < ex && cy >= 0 && cy < ey;  // taps leaving the box have zero coefficients
+      const int q = yo + (in ? cx + ex * cy : p) * nrhs;
+      cv[n] = cbox[ro + i];
+#pragma unroll
+      for (int j = 0; j < NE; ++j) yv[n][j] = yb[q + col[j]];
+    }
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+#pragma unroll
+      for (int j = 0; j < NE; ++j) cfms(v[j], cv[n], yv[n][j]);
+  }
+  // SPLIT: the nine taps in two batches (five, then four), which halves the
+  // registers the build holds at once, for kernels sized for more waves per SIMD.
+  template <bool SPLIT = false>
   __device__ __forceinline__ void build(int k, int p, int r, int dz, bool with_u, cpx<T> (&v)[NE]) const {
-    const int b = sb.b, ex = sb.ex, ey = sb.ey, bp = sb.bp;
+    const int b = sb.b, ex = sb.ex, bp = sb.bp;
 #pragma unroll
     for (int j = 0; j < NE; ++j) v[j] = mk<T>(0, 0);
     if (p >= b) return;
@@ -259,29 +343,21 @@ struct BoxCtx {
     const int px = p % ex, py = p / ex;
     const int ro = (k * b + p) * 18 + (dz + 1) / 2 * 9;
     const int yo = (k + dz) * bp * nrhs;
-    cpx<T> cv[9];
-    cpx<T> yv[9][NE];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const int cx = px + i % 3 - 1, cy = py + i / 3 - 1;
-      const bool in = cx >= 0 && cx < ex && cy >= 0 && cy < ey;  // taps leaving the box have zero coefficients
-      const int q = yo + (in ? cx + ex * cy : p) * nrhs;
-      cv[i] = cbox[ro + i];
-#pragma unroll
-      for (int j = 0; j < NE; ++j) yv[i][j] = yb[q + col[j]];
+    if constexpr (SPLIT) {
+      taps<0, 5>(p, px, py, ro, yo, col, v);
+      taps<5, 4>(p, px, py, ro, yo, col, v);
+    } else {
+      taps<0, 9>(p, px, py, ro, yo, col, v);
     }
-#pragma unroll
-    for (int i = 0; i < 9; ++i)
-#pragma unroll
-      for (int j = 0; j < NE; ++j) cfms(v[j], cv[i], yv[i][j]);
   }
   // operand of plane k into Bs, threads t0, t0 + nt, ... of the workgroup
+  template <bool SPLIT = false>
   __device__ __forceinline__ void build_plane(int k, int dz, bool with_u, cpx<T>* Bs, int t0, int nt) const {
 #pragma unroll 1
     for (int e = t0; e < sb.bp * LP; e += nt) {
       const int p = e / LP, r = e % LP;
       cpx<T> v[NE];
-      build(k, p, r, dz, with_u, v);
+      build<SPLIT>(k, p, r, dz, with_u, v);
 #pragma unroll
       for (int j = 0; j < NE; ++j) put_operand<T, RG>(Bs, p, r + j * LP, r + j * LP < nrg ? v[j] : mk<T>(0, 0));
     }
@@ -302,9 +378,10 @@ struct BoxCtx {
   // then backward planes k = ez - 2, ..., 0.
   __device__ __forceinline__ int nsteps() const { return 2 * sb.ez - 1; }
   __device__ __forceinline__ int plane_of(int s) const { return s < sb.ez ? s : 2 * sb.ez - 2 - s; }
+  template <bool SPLIT = false>
   __device__ __forceinline__ void build_step(int s, cpx<T>* Bs, int t0, int nt) const {
-    if (s < sb.ez) build_plane(s, -1, true, Bs, t0, nt);
-    else build_plane(plane_of(s), +1, false, Bs, t0, nt);
+    if (s < sb.ez) build_plane<SPLIT>(s, -1, true, Bs, t0, nt);
+    else build_plane<SPLIT>(plane_of(s), +1, false, Bs, t0, nt);
   }
   __device__ __forceinline__ const cpx<T>* factor(const cpx<T>* sinv, int s) const {
     return sinv + sb.mat_off + (long long)plane_of(s) * sb.bp * sb.bp;
@@ -328,8 +405,10 @@ struct BoxCtx {
 // y_k / x_k live in yloc and reach the other waves of the workgroup through L2
 // (workgroup-scope release/acquire around the barrier).  One workgroup per
 // item, all its waves building and then multiplying each plane in turn.
-template <typename T, int RG, int PF>
-__global__ void __launch_bounds__(64 * fused_max_waves<T>()) k_oras_fused(const Sub* __restrict__ subs, int ngroups, int nrhs,
+// MINW > 1: compiled for at least MINW waves per SIMD (two 9-wave workgroups
+// on a compute unit at MINW = 5), with the operand build's taps split in two.
+template <typename T, int RG, int PF, int MINW>
+__global__ void __launch_bounds__(64 * fused_max_waves<T>(), MINW) k_oras_fused(const Sub* __restrict__ subs, int ngroups, int nrhs,
                                                    const cpx<T>* __restrict__ cpl, const cpx<T>* __restrict__ sinv,
                                                    const z64* __restrict__ u, z64* __restrict__ z,
                                                    const z64* __restrict__ add, int gnx, int gny,
@@ -344,12 +423,43 @@ __global__ void __launch_bounds__(64 * fused_max_waves<T>()) k_oras_fused(const 
   const int FT = blockDim.x, nwaves = FT >> 6;
   const int bp = bx.sb.bp, ns = bx.nsteps();
   for (int st = 0; st < ns; ++st) {
-    bx.build_step(st, Bs, tid, FT);
+    bx.template build_step<(MINW > 1)>(st, Bs, tid, FT);
     cpx<T> a[PF][4];  // per plane, so nothing stays live across the operand build
     ChunkStream<T> cs = prefetch_tile<T, PF>(bx.factor(sinv, st), bp, wave, nwaves, lane, a);  // across the barrier
     __syncthreads();
     plane_product<T, RG, PF>(
         cs, Bs, wave, nwaves, lane, a, [&](int p, int r) { return bx.init(st, p, r); },
+        [&](int p, int r, cpx<T> val) { bx.output(st, p, r, val); });
+    wg_sync_global();
+  }
+}
+
+// The same sweep for planes whose operand does not fit in LDS: the operand of
+// item i is tglob[i][bpmax][16] (RG = 8 split layout) in global memory, built
+// by all waves, published by the workgroup-scope release/acquire barrier, and
+// streamed back through L2 with the factor chunks.
+template <typename T, int PF>
+__global__ void __launch_bounds__(64 * fused_max_waves<T>()) k_oras_gl(const Sub* __restrict__ subs, int ngroups, int nrhs,
+                                                   const cpx<T>* __restrict__ cpl, const cpx<T>* __restrict__ sinv,
+                                                   const z64* __restrict__ u, z64* __restrict__ z,
+                                                   const z64* __restrict__ add, int gnx, int gny,
+                                                   cpx<T>* __restrict__ yloc, cpx<T>* __restrict__ tglob, int bpmax) {
+  const int item = (int)xcd_contiguous(blockIdx.x, gridDim.x);
+  const BoxCtx<T, 8> bx(subs, item, ngroups, nrhs, cpl, u, z, add, gnx, gny, yloc);
+  cpx<T>* Bs = tglob + (long long)item * bpmax * 16;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int FT = blockDim.x, nwaves = FT >> 6;
+  const int bp = bx.sb.bp, ns = bx.nsteps();
+  const cpx<T>* bcol = Bs + 4 * (lane >> 4) * 16 + (lane & 15);
+  for (int st = 0; st < ns; ++st) {
+    bx.build_step(st, Bs, tid, FT);
+    wg_sync_global();  // the operand, written by every wave, is read by every wave
+    cpx<T> a[PF][4], b[PF][4];
+    ChunkStream<T> cs(bx.factor(sinv, st), bp, wave, nwaves, lane);
+#pragma unroll
+    for (int j = 0; j < PF; ++j) next_chunk_gl(cs, bcol, a[j], b[j]);
+    plane_product_gl<T, PF>(
+        cs, bcol, wave, nwaves, lane, a, b, [&](int p, int r) { return bx.init(st, p, r); },
         [&](int p, int r, cpx<T> val) { bx.output(st, p, r, val); });
     wg_sync_global();
   }
@@ -426,15 +536,26 @@ int min_rounds(int bpmax) {
   return (bpmax / 16 + MW - 1) / MW;
 }
 
-template <typename T, int RG>
-void launch_fused_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, int rounds, const cpx<T>* cpl,
+template <typename T>
+void launch_gl_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, int rounds, const cpx<T>* cpl,
+                 const cpx<T>* sinv, const z64* u, z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc,
+                 cpx<T>* tglob, hipStream_t s) {
+  constexpr int PF = 2;
+  const int nmt = bpmax / 16;
+  rounds = std::max(rounds, min_rounds<T>(bpmax));
+  const int nwaves = (nmt + rounds - 1) / rounds;
+  hipLaunchKernelGGL((k_oras_gl<T, PF>), dim3(nsub * ngroups), dim3(64 * nwaves), 0, s, subs, ngroups, nrhs, cpl, sinv,
+                     u, z, add, gnx, gny, yloc, tglob, bpmax);
+}
+
+template <typename T, int RG, int PF, int MINW>
+void launch_fused_k(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, int rounds, const cpx<T>* cpl,
                     const cpx<T>* sinv, const z64* u, z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc,
                     hipStream_t s) {
-  constexpr int PF = sizeof(T) == 4 ? 4 : 2;
   const size_t lds = (size_t)bpmax * lds_width<T>(RG) * sizeof(cpx<T>);
-  static bool attr = false;
+  static bool attr = false;  // one per kernel instance
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_oras_fused<T, RG, PF>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)k_oras_fused<T, RG, PF, MINW>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               160 * 1024);
     attr = true;
   }
@@ -442,8 +563,29 @@ void launch_fused_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax,
   const int nmt = bpmax / 16;
   rounds = std::max(rounds, min_rounds<T>(bpmax));
   const int nwaves = (nmt + rounds - 1) / rounds;
-  hipLaunchKernelGGL((k_oras_fused<T, RG, PF>), dim3(nsub * ngroups), dim3(64 * nwaves), lds, s, subs, ngroups, nrhs, cpl,
-                     sinv, u, z, add, gnx, gny, yloc);
+  hipLaunchKernelGGL((k_oras_fused<T, RG, PF, MINW>), dim3(nsub * ngroups), dim3(64 * nwaves), lds, s, subs, ngroups,
+                     nrhs, cpl, sinv, u, z, add, gnx, gny, yloc);
+}
+
+// Whether the two-workgroups-per-CU build of the sweep exists for this shape:
+// FP64 groups of 32 right-hand sides, two operands in one CU's LDS.
+template <typename T>
+bool lowreg_fits(int rg, int bpmax) {
+  return sizeof(T) == 8 && rg == 32 && 2 * (size_t)bpmax * lds_width<T>(rg) * sizeof(cpx<T>) <= 160 * 1024;
+}
+
+template <typename T, int RG>
+void launch_fused_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, int rounds, bool lowreg,
+                    const cpx<T>* cpl, const cpx<T>* sinv, const z64* u, z64* z, const z64* add, int gnx, int gny,
+                    cpx<T>* yloc, hipStream_t s) {
+  constexpr int PF = sizeof(T) == 4 ? 4 : 2;
+  if constexpr (sizeof(T) == 8 && RG == 32) {
+    if (lowreg) {  // one factor chunk in flight per wave: five waves per SIMD hide the latency instead
+      launch_fused_k<T, RG, 1, 5>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx, gny, yloc, s);
+      return;
+    }
+  }
+  launch_fused_k<T, RG, PF, 1>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx, gny, yloc, s);
 }
 
 // Two operand slots of the pipelined sweep must fit one compute unit's LDS.
@@ -488,19 +630,30 @@ void launch_pipe_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, 
 constexpr size_t FUSED_LDS = 150 * 1024;
 
 template <typename T>
+bool lds_fits(int rg, int bpmax) {
+  return (size_t)bpmax * lds_width<T>(rg) * sizeof(cpx<T>) <= FUSED_LDS;
+}
+
+// Widest right-hand-side group for this plane size and batch; 8 also where
+// not even its operand fits in LDS (then the global-operand sweep k_oras_gl).
+template <typename T>
 int fused_group(int bpmax, int nrhs) {
   int rg = nrhs <= 8 ? 8 : (nrhs <= 16 ? 16 : 32);
-  while (rg >= 8 && (size_t)bpmax * lds_width<T>(rg) * sizeof(cpx<T>) > FUSED_LDS) rg /= 2;
-  return rg >= 8 ? rg : 0;
+  while (rg > 8 && !lds_fits<T>(rg, bpmax)) rg /= 2;
+  return rg;
 }
 
 namespace {
 
 template <typename T>
-void launch_rg(int rg, int rounds, const Sub* subs, int nsub, int nrhs, int bpmax, const cpx<T>* cpl,
+void launch_rg(int rg, int rounds, bool lowreg, const Sub* subs, int nsub, int nrhs, int bpmax, const cpx<T>* cpl,
                const cpx<T>* sinv, const z64* u, z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc,
-               hipStream_t s) {
+               cpx<T>* tglob, hipStream_t s) {
   const int ngroups = (nrhs + rg - 1) / rg;
+  if (!lds_fits<T>(rg, bpmax)) {  // operand in global memory: the RG = 8 sweep k_oras_gl
+    launch_gl_t<T>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx, gny, yloc, tglob, s);
+    return;
+  }
   if (rounds == 0) {  // pipelined persistent sweep
     if (rg == 16)
       launch_pipe_t<T, 16>(subs, nsub, ngroups, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, s);
@@ -510,13 +663,16 @@ void launch_rg(int rg, int rounds, const Sub* subs, int nsub, int nrhs, int bpma
   }
   switch (rg) {
     case 8:
-      launch_fused_t<T, 8>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx, gny, yloc, s);
+      launch_fused_t<T, 8>(subs, nsub, ngroups, nrhs, bpmax, rounds, lowreg, cpl, sinv, u, z, add, gnx, gny, yloc,
+                            s);
       break;
     case 16:
-      launch_fused_t<T, 16>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx, gny, yloc, s);
+      launch_fused_t<T, 16>(subs, nsub, ngroups, nrhs, bpmax, rounds, lowreg, cpl, sinv, u, z, add, gnx, gny, yloc,
+                            s);
       break;
     default:
-      launch_fused_t<T, 32>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx, gny, yloc, s);
+      launch_fused_t<T, 32>(subs, nsub, ngroups, nrhs, bpmax, rounds, lowreg, cpl, sinv, u, z, add, gnx, gny, yloc,
+                            s);
       break;
   }
 }
@@ -533,6 +689,7 @@ struct TuneKey {
 std::atomic<int> g_sweep_policy{0};
 struct TuneVal {
   int rg, rounds;
+  bool lowreg;  // the build for two workgroups per compute unit (lowreg_fits)
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
@@ -550,16 +707,21 @@ int tuned_group(int es, int bpmax, int nsub, int nrhs, int gnx, int gny) {
 
 template <typename T>
 bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const cpx<T>* sinv, int nrhs, const z64* u,
-                z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc, hipStream_t s, bool may_tune) {
+                z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc, cpx<T>* tbuf, hipStream_t s, bool may_tune) {
   const int rgmax = fused_group<T>(bpmax, nrhs);
-  if (rgmax == 0) return false;
+  if (!lds_fits<T>(rgmax, bpmax) && !tbuf) return false;  // the global-operand sweep needs its operand slices
   const int policy = g_sweep_policy.load();
+  if (policy == 3 && lowreg_fits<T>(rgmax, bpmax)) {  // forced: the two-workgroups-per-CU build
+    launch_rg<T>(rgmax, min_rounds<T>(bpmax), true, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc,
+                 tbuf, s);
+    return true;
+  }
   const TuneKey key{(int)sizeof(T), bpmax, nsub, nrhs, gnx, gny, policy};
   // policy 1: one-item sweeps only; 2: the pipelined sweep wherever it fits
   bool any_pipe = false;
   for (int cand = 8; cand <= rgmax; cand *= 2) any_pipe = any_pipe || pipe_fits<T>(cand, bpmax);
-  const bool allow_pipe = policy != 1, allow_item = policy != 2 || !any_pipe;
-  TuneVal tv{0, 0};
+  const bool allow_pipe = policy != 1 && policy != 3, allow_item = policy != 2 || !any_pipe;
+  TuneVal tv{0, 0, false};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(key);
@@ -581,58 +743,63 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
     for (int cand = 8; cand <= rgmax; cand *= 2) {
       int last_waves = 0;
       // rounds 0 = the pipelined persistent sweep, then the one-item sweep with
-      // r0, r0 + 1, r0 + 2 tile rounds per wave
+      // r0, r0 + 1, r0 + 2 tile rounds per wave (and, where it exists, its
+      // two-workgroups-per-CU build at r0)
       for (int rounds = 0; rounds <= r0 + 2; rounds = rounds == 0 ? r0 : rounds + 1) {
         if (rounds == 0 && (!allow_pipe || !pipe_fits<T>(cand, bpmax))) continue;
         if (rounds != 0 && !allow_item) continue;
         const int waves = rounds == 0 ? -1 : (nmt + rounds - 1) / rounds;
         if (waves == last_waves) continue;
         last_waves = waves;
-        float tot = 0.f;
-        for (int rep = 0; rep < 2; ++rep) {
-          (void)hipEventRecord(e0, s);
-          launch_rg<T>(cand, rounds, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, s);
-          (void)hipEventRecord(e1, s);
-          (void)hipEventSynchronize(e1);
-          float ms = 0.f;
-          (void)hipEventElapsedTime(&ms, e0, e1);
-          if (rep > 0) tot += ms;
-        }
-        if (verbose)
-          std::fprintf(stderr, "helm:   candidate group %d %s %d waves: %.3f ms\n", cand,
-                       rounds == 0 ? "pipelined," : "", rounds == 0 ? 12 : waves, tot);
-        if (tot < best) {
-          best = tot;
-          tv = {cand, rounds};
+        for (int lr = 0; lr < 2; ++lr) {
+          if (lr && !(rounds == r0 && lowreg_fits<T>(cand, bpmax))) continue;
+          float tot = 0.f;
+          for (int rep = 0; rep < 2; ++rep) {
+            (void)hipEventRecord(e0, s);
+            launch_rg<T>(cand, rounds, lr != 0, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, tbuf,
+                         s);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) tot += ms;
+          }
+          if (verbose)
+            std::fprintf(stderr, "helm:   candidate group %d %s %d waves%s: %.3f ms\n", cand,
+                         rounds == 0 ? "pipelined," : "", rounds == 0 ? 12 : waves, lr ? " (two per CU)" : "", tot);
+          if (tot < best) {
+            best = tot;
+            tv = {cand, rounds, lr != 0};
+          }
         }
       }
     }
     locked_event_destroy(e0);
     locked_event_destroy(e1);
     if (verbose)
-      std::fprintf(stderr, "helm: sweep tuned (fp%d, bp %d, %d boxes, %d rhs): group %d, %s %d waves, %.3f ms\n",
+      std::fprintf(stderr, "helm: sweep tuned (fp%d, bp %d, %d boxes, %d rhs): group %d, %s %d waves%s, %.3f ms\n",
                    (int)sizeof(T) * 8, bpmax, nsub, nrhs, tv.rg, tv.rounds == 0 ? "pipelined," : "",
-                   tv.rounds == 0 ? 12 : (nmt + tv.rounds - 1) / tv.rounds, best);
+                   tv.rounds == 0 ? 12 : (nmt + tv.rounds - 1) / tv.rounds, tv.lowreg ? " (two per CU)" : "", best);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = tv;
   }
   if (tv.rg == 0) {  // untuned (tuning off, or inside a capture): the widest group
-    tv = {rgmax, r0};
+    tv = {rgmax, r0, false};
     if (!allow_item) {
       for (int cand = rgmax; cand >= 16; cand /= 2)
         if (pipe_fits<T>(cand, bpmax)) {
-          tv = {cand, 0};
+          tv = {cand, 0, false};
           break;
         }
     }
   }
-  launch_rg<T>(tv.rg, tv.rounds, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, s);
+  launch_rg<T>(tv.rg, tv.rounds, tv.lowreg, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, tbuf, s);
   return true;
 }
 
 template bool oras_fused<float>(const Sub*, int, int, const c32*, const c32*, int, const z64*, z64*, const z64*, int,
-                                int, c32*, hipStream_t, bool);
+                                int, c32*, c32*, hipStream_t, bool);
 template bool oras_fused<double>(const Sub*, int, int, const z64*, const z64*, int, const z64*, z64*, const z64*, int,
-                                 int, z64*, hipStream_t, bool);
+                                 int, z64*, z64*, hipStream_t, bool);
 template int fused_group<float>(int, int);
 template int fused_group<double>(int, int);

@@ -240,11 +240,11 @@ class Request:
             pass
 
 
-SWEEP_POLICIES = {"auto": 0, "item": 1, "pipelined": 2}
+SWEEP_POLICIES = {"auto": 0, "item": 1, "pipelined": 2, "two_per_cu": 3}
 
 
 def set_sweep_policy(policy):
-    """Process-wide choice of local-solve sweep: "auto" (tuned), "item" or "pipelined"."""
+    """Process-wide choice of local-solve sweep: "auto" (tuned), "item", "pipelined" or "two_per_cu"."""
     _check(lib.helm_set_sweep_policy(SWEEP_POLICIES[policy]))
 
 

@@ -51,3 +51,27 @@ def test_fp64_two_level_parity_with_1296_node_planes():
         res = b[r].ravel() - st.A @ X[r].ravel()
         assert np.linalg.norm(res) / np.linalg.norm(b[r]) <= tol
     S.close()
+
+
+@pytest.mark.timeout(600)
+def test_sweep_with_operand_in_global_memory_matches_oracle():
+    # 36 x 36 = 1296-node planes: the operand of a plane product no longer fits
+    # in LDS (complex FP64 or FP32), so the sweep keeps it in global memory; 12
+    # right-hand sides make one full and one partial group of 8
+    from oracle.dd import Oras, decompose
+    from oracle.operator import assemble
+    from paper_2103_14921_amd import helm
+    shape, h, f, pml = (68, 68, 8), 25.0, 10.0, (8, 8, 3, 0)
+    c = inputs.velocity_thrust_belt(*shape, h=h, q=100.0)
+    prob = Problem(shape, h, c, f, Pml(*pml), WO)
+    say("oracle one-level ORAS", shape)
+    M = Oras(assemble(prob), shape, decompose(shape, (2, 2, 1), 2), prob.k().ravel(), h)
+    R = inputs.random_field((12, prob.n), seed=61)
+    ref = np.stack([M.apply(R[r]) for r in range(12)])
+    for prec, tol in (("fp64", 1e-10), ("mixed", 5e-4)):
+        say("gpu sweep", prec)
+        S = helm.Solver(shape, h, c, f, pml, weights=W, parts=(2, 2, 1), overlap=2, levels=1, precision=prec)
+        Z = S.apply_oras(R)
+        for r in range(12):
+            assert rel(Z[r], ref[r]) <= tol, (prec, r)
+        S.close()
