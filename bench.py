@@ -80,7 +80,7 @@ def gpu_solve(helm, w, c_dev, b_dev, precision, weights, timing=False, graphs=Tr
     return X, info
 
 
-PEAK = {"c64": 157.3, "c128": 78.6}  # dense MFMA TFLOP/s of one MI355X (fp32, fp64)
+PEAK = {"c64": 157.3, "c128": 78.6, "c32": 2500.0}  # dense MFMA TFLOP/s of one MI355X (fp32, fp64, fp16)
 
 
 def measured_traffic(kernel_file, profile_md, algorithmic_bytes):
@@ -301,6 +301,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-single-local", action="store_true",
                     help="skip the run with the coarse level's local solves in complex FP32 too")
+    ap.add_argument("--no-approx", action="store_true",
+                    help="skip the run with approximate fine local solves (complex-FP16 plane inverses)")
     ap.add_argument("--serving-requests", type=int, default=24,
                     help="requests in the serving stream reported beside the main line (0: skip); a quarter "
                          "of them calibrate the capacity, the rest arrive as a Poisson stream")
@@ -417,6 +419,20 @@ def main():
             err = rel_err(helm, torch, Xs, X64)
             out["single_local_form"]["vs_fp64_rel_l2_max"] = float(err.max().item())
         del Xs
+    if not args.no_approx and w["precision"] == "mixed":
+        # approximate fine local solves (complex-FP16 plane inverses on FP16 matrix cores; one step)
+        Xa, iap = gpu_solve(helm, w, c_dev, b_dev, "approx_local", weights, timing=True, graphs=not args.no_graphs)
+        tap = iap["timings"]["setup"] + iap["timings"]["solve"]
+        out["approx_local_form"] = {
+            "rhs_per_s": nrhs / tap, "solve_only_rhs_per_s": nrhs / iap["timings"]["solve"],
+            "setup_s": iap["timings"]["setup"], "solve_s": iap["timings"]["solve"],
+            "iters_mean": float(iap["iters"].mean()), "iters_max": int(iap["iters"].max()),
+            "max_true_relres": float(iap["relres_true"].max()),
+            "fine_sweep": roofline_entry(iap["sweeps"][0], "c32"),
+            "solve_roofline_frac": iap["bound"]["seconds"] / iap["timings"]["solve"]}
+        if "fp64_form" in out:
+            out["approx_local_form"]["vs_fp64_rel_l2_max"] = float(rel_err(helm, torch, Xa, X64).max().item())
+        del Xa
     if "fp64_form" in out:
         del X64
     if args.serving_requests > 0:

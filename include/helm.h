@@ -72,7 +72,7 @@ typedef struct {
   double w1, w2, w3, wm1, wm2, wm3, wm4;
 } helm_weights_t;
 
-enum { HELM_FP64 = 0, HELM_MIXED = 1, HELM_SINGLE_LOCAL = 2 };
+enum { HELM_FP64 = 0, HELM_MIXED = 1, HELM_SINGLE_LOCAL = 2, HELM_APPROX_LOCAL = 3 };
 
 /* Decomposition and solver options (domain-decomposition section).  Boxes
  * split each axis into p ranges (floor(n/p), the first n mod p one longer),
@@ -85,13 +85,20 @@ enum { HELM_FP64 = 0, HELM_MIXED = 1, HELM_SINGLE_LOCAL = 2 };
  * (the one-level preconditioner of the coarse GMRES) in complex FP32; the
  * coarse GMRES itself, E and the transfers stay FP64 (the numerical-results
  * section runs every part in single precision with unchanged iteration
- * counts, Table 2). */
+ * counts, Table 2).  HELM_APPROX_LOCAL makes the fine level's local solves
+ * approximate, as the paper's incomplete Cholesky factors do (numerical-results
+ * section, Table 2: cheaper and smaller local solves, FGMRES unchanged): the
+ * plane inverses, factored in complex FP32, are kept as complex FP16 with a
+ * power-of-two scale per plane (half the memory), and the sweeps multiply them
+ * on FP16 matrix cores (FP32 accumulation) by the operand rounded to FP16 with
+ * a power-of-two scale per column; everything else is as in HELM_MIXED.  Its
+ * fine planes are limited to 960 nodes. */
 typedef struct {
   int32_t px, py, pz;     /* subdomains per axis, >= 1 */
   int32_t overlap;        /* added layers per interior side, >= 1 */
   int32_t levels;         /* 1 or 2 */
   int32_t coarse_iters;   /* GMRES iterations of the coarse solve (paper: 10) */
-  int32_t precision;      /* HELM_FP64, HELM_MIXED or HELM_SINGLE_LOCAL */
+  int32_t precision;      /* HELM_FP64, HELM_MIXED, HELM_SINGLE_LOCAL or HELM_APPROX_LOCAL */
   int32_t restart;        /* FGMRES restart length m, >= 1 */
   int32_t robin;          /* 1: absorbing interfaces (ORAS); 0: Dirichlet (RAS) */
   int32_t nrhs_chunk;     /* right-hand sides per batch; 0 = planner's choice */

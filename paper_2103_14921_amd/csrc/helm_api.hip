@@ -222,7 +222,9 @@ struct Level {
   int nsub = 0, bpmax = 0, maxez = 0;
   long long nodes_total = 0, mat_total = 0, vec_total = 0, maxnodes = 0, maxcore = 0;
   int prec = 0;  // 0 = complex FP64 factors, 1 = complex FP32 factors
+  bool half = false;  // approximate local solves: factors kept as complex FP16 (sinv16, sexp) after set-up
   DevBuf d_subs, aloc, sinv, E;
+  DevBuf sinv16, sexp;  // [mat_total / 4] 16-byte blocks; [nsub][maxez] scale exponents
   DevBuf cpl;  // plane couplings [node][18] in the factor precision (aloc is set-up only)
 };
 
@@ -318,13 +320,14 @@ size_t elem_size(int prec) { return prec ? sizeof(c32) : sizeof(z64); }
 
 // Bytes of the handle's resident data for a level (operators and factors).
 size_t level_resident_bytes(const Level& L) {
-  return (size_t)L.nodes_total * 18 * elem_size(L.prec) + (size_t)L.mat_total * elem_size(L.prec) +
-         (size_t)L.nsub * sizeof(Sub);
+  return (size_t)L.nodes_total * 18 * elem_size(L.prec) + (size_t)L.mat_total * (L.half ? 4 : elem_size(L.prec)) +
+         (size_t)L.nsub * sizeof(Sub) + (L.half ? (size_t)L.nsub * L.maxez * sizeof(int) : 0);
 }
 // Temporary set-up bytes of a level (local operator rows, Schur blocks, pivots).
 size_t level_setup_bytes(const Level& L) {
   return (size_t)L.nodes_total * 27 * sizeof(z64) + (size_t)L.nsub * L.bpmax * L.bpmax * elem_size(L.prec) * 2 +
-         (size_t)L.nsub * (16 + 64) * L.bpmax * elem_size(L.prec) + (size_t)L.nsub * L.bpmax * sizeof(int) * 2 + 64;
+         (size_t)L.nsub * (16 + 64) * L.bpmax * elem_size(L.prec) + (size_t)L.nsub * L.bpmax * sizeof(int) * 2 + 64 +
+         (L.half ? (size_t)L.mat_total * elem_size(L.prec) : 0);  // complex FP32 factors before conversion
 }
 size_t level_ws_bytes(const Level& L, int nr) {
   return ((size_t)L.vec_total * nr + (size_t)sweep_tbuf_elems(L.nsub, L.bpmax, nr)) * elem_size(L.prec);
@@ -566,7 +569,8 @@ void validate(const helm_grid_t* g, const helm_pml_t* pml, const helm_decomp_t* 
   if (d->levels != 1 && d->levels != 2) throw HelmError(HELM_EINVAL, "levels must be 1 or 2");
   if (d->levels == 2 && d->coarse_iters < 1) throw HelmError(HELM_EINVAL, "coarse_iters must be >= 1");
   if (d->restart < 1 || d->restart > 64) throw HelmError(HELM_EINVAL, "restart must be in [1, 64]");
-  if (d->precision != HELM_FP64 && d->precision != HELM_MIXED && d->precision != HELM_SINGLE_LOCAL)
+  if (d->precision != HELM_FP64 && d->precision != HELM_MIXED && d->precision != HELM_SINGLE_LOCAL &&
+      d->precision != HELM_APPROX_LOCAL)
     throw HelmError(HELM_EINVAL, "bad precision");
   const int n[3] = {g->nx, g->ny, g->nz}, p[3] = {d->px, d->py, d->pz};
   for (int a = 0; a < 3; ++a) {
@@ -583,6 +587,9 @@ void plan(helm_handle* H) {
   auto cores = fine_cores(H->nx, H->ny, H->nz, d.px, d.py, d.pz);
   plan_level(H->fine, H->nx, H->ny, H->nz, cores, d.overlap, d.precision != HELM_FP64 ? 1 : 0);
   if (H->fine.bpmax > MAX_PLANE) throw HelmError(HELM_EINVAL, "subdomain plane larger than 2048 nodes");
+  H->fine.half = d.precision == HELM_APPROX_LOCAL;
+  if (H->fine.half && half_group(H->fine.bpmax, 1) == 0)
+    throw HelmError(HELM_EINVAL, "approximate local solves need subdomain planes of at most 960 nodes");
   if (H->two_level()) {
     plan_level(H->coarse, (H->nx + 1) / 2, (H->ny + 1) / 2, (H->nz + 1) / 2, coarse_cores(H->fine.subs), d.overlap,
                d.precision == HELM_SINGLE_LOCAL ? 1 : 0);
@@ -698,16 +705,18 @@ void oras_sweep(helm_handle* H, Level& L, int nr, const z64* u, z64* z, const z6
 // right-hand side; the bytes count the factors once per right-hand-side group
 // plus the plane vectors (gather, scatter, stored planes).
 void sweep_work(const helm_handle* H, const Level& L, int nr, double* flops, double* bytes) {
-  const int es = (int)elem_size(L.prec);
-  int rg = tuned_group(es / 2, L.bpmax, L.nsub, nr, L.nx, L.ny);  // keyed by the real type's size
-  if (rg == 0) rg = L.prec ? fused_group<float>(L.bpmax, nr) : fused_group<double>(L.bpmax, nr);
+  const int es = (int)elem_size(L.prec);          // plane vectors
+  const int fs = L.half ? 4 : es;                 // factor entries
+  int rg = tuned_group(fs / 2, L.bpmax, L.nsub, nr, L.nx, L.ny);  // keyed by the real type's size
+  if (rg == 0)
+    rg = L.half ? half_group(L.bpmax, nr) : (L.prec ? fused_group<float>(L.bpmax, nr) : fused_group<double>(L.bpmax, nr));
   const int ngroups = rg > 0 ? (nr + rg - 1) / rg : 1;
   double f = 0, by = 0;
   for (const Sub& sb : L.subs) {
     const double planes = 2.0 * sb.ez - 1.0;
     const double b = sb.b;
     f += planes * 8.0 * b * b * nr;
-    by += planes * b * b * es * ngroups;                      // factors
+    by += planes * b * b * fs * ngroups;                      // factors
     by += (double)sb.b * sb.ez * nr * (16.0 + 3.0 * es);      // gather + stored planes (w, r, w)
     by += (double)(sb.hi[0] - sb.lo[0]) * (sb.hi[1] - sb.lo[1]) * (sb.hi[2] - sb.lo[2]) * nr * 16.0;  // scatter
   }
@@ -745,7 +754,7 @@ void oras_apply(helm_handle* H, Level& L, int nr, const z64* u, z64* z, const z6
   if (g_work) {  // after the launch: a first sweep of a shape has run the tuner, whose group sets the bytes
     double f, by;
     sweep_work(H, L, nr, &f, &by);
-    account(by, f, L.prec ? FP32_PEAK : FP64_PEAK);
+    account(by, f, L.half ? FP16_PEAK : (L.prec ? FP32_PEAK : FP64_PEAK));
   }
   if (H->timing) {
     record_timing_event(H, e1);
@@ -808,6 +817,12 @@ void collect_sweep_timing(helm_handle* H) {
 }
 
 void oras_sweep(helm_handle* H, Level& L, int nr, const z64* u, z64* z, const z64* add, void* yl, void* tb) {
+  if (L.half) {
+    if (!oras_half(L.d_subs.as<Sub>(), L.nsub, L.bpmax, L.cpl.as<c32>(), L.sinv16.as<uint4>(), L.sexp.as<int>(),
+                   L.maxez, nr, u, z, add, L.nx, L.ny, (c32*)yl, H->stream))
+      throw HelmError(HELM_EINVAL, "approximate local solves do not fit this plane size");
+    return;
+  }
   if (L.prec == 1)
     Factor<float>::sweep(L.d_subs.as<Sub>(), L.nsub, L.bpmax, L.maxez, L.cpl.as<c32>(), L.sinv.as<c32>(), nr, u, z,
                          add, L.nx, L.ny, (c32*)yl, (c32*)tb, H->stream);
@@ -918,7 +933,7 @@ void outer_step(helm_handle* H, int nr, int j, double tol, int maxit) {
 bool sweep_untuned(const Level& L, int nr) {
   static const bool no_tune = std::getenv("HELM_NO_TUNE") != nullptr || std::getenv("HELM_NO_FUSED") != nullptr;
   if (no_tune) return false;
-  return tuned_group((int)elem_size(L.prec) / 2, L.bpmax, L.nsub, nr, L.nx, L.ny) == 0;
+  return tuned_group(L.half ? 2 : (int)elem_size(L.prec) / 2, L.bpmax, L.nsub, nr, L.nx, L.ny) == 0;
 }
 
 // Run outer iteration j from its captured graph, capturing it first if needed.
@@ -1321,6 +1336,14 @@ void setup_impl(helm_handle* H, const void* velocity, int vel_kind) {
     H->t_fact = tf.stop();
   }
   extract_couplings(H, F);
+  if (F.half) {  // approximate local solves: the complex FP32 inverses to FP16 with a scale per plane
+    F.sinv16.alloc(sizeof(uint4) * (size_t)(F.mat_total / 4));
+    F.sexp.alloc(sizeof(int) * (size_t)F.nsub * F.maxez);
+    launch_to_half(F.d_subs.as<Sub>(), F.nsub, F.maxez, F.sinv.as<c32>(), F.sinv16.as<uint4>(), F.sexp.as<int>(),
+                   H->stream);
+    HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+    F.sinv.release();
+  }
   if (H->two_level()) {
     Timer tc(H->stream);
     Level& C = H->coarse;
@@ -1554,7 +1577,7 @@ size_t helm_resident_bytes(const helm_handle_t* H) {
                           &H->err})
     b += d->bytes;
   for (const Level* L : {&H->fine, &H->coarse})
-    for (const DevBuf* d : {&L->d_subs, &L->aloc, &L->sinv, &L->E, &L->cpl}) b += d->bytes;
+    for (const DevBuf* d : {&L->d_subs, &L->aloc, &L->sinv, &L->E, &L->cpl, &L->sinv16, &L->sexp}) b += d->bytes;
   const Workspace& W = H->ws;
   for (const DevBuf* d : {&W.b, &W.x, &W.w, &W.V, &W.Zv, &W.q, &W.t, &W.cc, &W.Vc, &W.Zc, &W.wc, &W.ec, &W.yl_f,
                           &W.tb_f, &W.yl_c, &W.tb_c, &W.zpart, &W.dpart, &W.bn2, &W.beta2, &W.cols})
@@ -1865,7 +1888,11 @@ helm_status helm_apply_oras_noalloc(helm_handle_t* H, int32_t level, int32_t nrh
     void* ylp = base + 2 * fld;
     void* tbp = base + 2 * fld + yl;
     launch_to_node_major(static_cast<const z64*>(R), ni, L.n, nrhs, H->stream);
-    if (L.prec == 1)
+    if (L.half) {
+      if (!oras_half(L.d_subs.as<Sub>(), L.nsub, L.bpmax, L.cpl.as<c32>(), L.sinv16.as<uint4>(), L.sexp.as<int>(),
+                     L.maxez, nrhs, ni, no, nullptr, L.nx, L.ny, (c32*)ylp, H->stream, false))
+        throw HelmError(HELM_EINVAL, "approximate local solves do not fit this plane size");
+    } else if (L.prec == 1)
       Factor<float>::sweep(L.d_subs.as<Sub>(), L.nsub, L.bpmax, L.maxez, L.cpl.as<c32>(), L.sinv.as<c32>(), nrhs, ni,
                            no, nullptr, L.nx, L.ny, (c32*)ylp, (c32*)tbp, H->stream, false);
     else
@@ -1900,7 +1927,12 @@ helm_status helm_local_solve(helm_handle_t* H, int32_t level, int32_t s, int32_t
     void* yl = level == 0 ? H->ws.yl_f.p : H->ws.yl_c.p;
     void* tb = level == 0 ? H->ws.tb_f.p : H->ws.tb_c.p;
     const Sub* one = L.d_subs.as<Sub>() + s;
-    if (L.prec == 1) {
+    if (L.half) {
+      if (!oras_half(one, 1, L.bpmax, L.cpl.as<c32>(), L.sinv16.as<uint4>(), L.sexp.as<int>() + (long long)s * L.maxez,
+                     L.maxez, nrhs, u.as<z64>(), zg.as<z64>(), nullptr, L.nx, L.ny, (c32*)yl, H->stream))
+        throw HelmError(HELM_EINVAL, "approximate local solves do not fit this plane size");
+      launch_box_gather<float>(sb, nrhs, (const c32*)yl, xo.as<z64>(), H->stream);
+    } else if (L.prec == 1) {
       Factor<float>::sweep(one, 1, L.bpmax, sb.ez, L.cpl.as<c32>(), L.sinv.as<c32>(), nrhs, u.as<z64>(), zg.as<z64>(),
                            nullptr, L.nx, L.ny, (c32*)yl, (c32*)tb, H->stream);
       launch_box_gather<float>(sb, nrhs, (const c32*)yl, xo.as<z64>(), H->stream);

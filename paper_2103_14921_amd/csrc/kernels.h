@@ -20,7 +20,7 @@ struct AxisPml {
 };
 // Lower bound of the solve: every launch of the solve phase adds its
 // algorithmic bytes and flops and the time they take at the device's peaks
-// (HBM 8 TB/s; FP64 78.6, FP32 157.3 TFLOP/s), into the accumulator the
+// (HBM 8 TB/s; FP64 78.6, FP32 157.3, dense FP16 matrix 2500 TFLOP/s), into the accumulator the
 // calling thread has installed (none outside solves).
 struct WorkBound {
   double bytes = 0, flops = 0, seconds = 0;
@@ -30,7 +30,7 @@ struct WorkBound {
     seconds += o.seconds;
   }
 };
-constexpr double HBM_PEAK = 8.0e12, FP64_PEAK = 78.6e12, FP32_PEAK = 157.3e12;
+constexpr double HBM_PEAK = 8.0e12, FP64_PEAK = 78.6e12, FP32_PEAK = 157.3e12, FP16_PEAK = 2.5e15;
 extern thread_local WorkBound* g_work;
 inline void account(double bytes, double flops, double peak = FP64_PEAK) {
   if (WorkBound* w = g_work) {
@@ -115,6 +115,16 @@ int fused_group(int bpmax, int nrhs);
 inline long long sweep_tbuf_elems(int nsub, int bpmax, int nrhs) {
   return (long long)nsub * bpmax * 2 * ((nrhs + 7) / 8 * 8);
 }
+// Approximate local solves (the FP16 sweep k_oras_half): plane inverses
+// converted from complex FP32 by launch_to_half into 16-byte blocks (four real
+// parts, four imaginary parts of one row) scaled by 2^-sexp[s * maxez + k].
+// oras_half returns false where the complex-FP32 operand of a plane does not
+// fit in LDS (half_group 0: planes above 960 nodes).
+int half_group(int bpmax, int nrhs);
+bool oras_half(const Sub* subs, int nsub, int bpmax, const c32* cpl, const uint4* sinv16, const int* sexp, int maxez,
+               int nrhs, const z64* u, z64* z, const z64* add, int gnx, int gny, c32* yloc, hipStream_t s,
+               bool may_tune = true);
+void launch_to_half(const Sub* subs, int nsub, int maxez, const c32* sinv, uint4* sinv16, int* sexp, hipStream_t s);
 // right-hand-side group the autotuner chose for this shape (0 = not tuned yet)
 int tuned_group(int es, int bpmax, int nsub, int nrhs, int gnx, int gny);
 // process-wide sweep policy: 0 autotune over all variants, 1 one-item sweeps,

@@ -350,16 +350,36 @@ struct BoxCtx {
       taps<0, 9>(p, px, py, ro, yo, col, v);
     }
   }
-  // operand of plane k into Bs, threads t0, t0 + nt, ... of the workgroup
-  template <bool SPLIT = false>
-  __device__ __forceinline__ void build_plane(int k, int dz, bool with_u, cpx<T>* Bs, int t0, int nt) const {
+  // operand of plane k into Bs, threads t0, t0 + nt, ... of the workgroup.
+  // With cmax (nt a multiple of LP, so each thread keeps its columns), the
+  // largest |Re| or |Im| of every operand column is also reduced into
+  // cmax[column] (float bits, atomic max; cmax zeroed by the caller).
+  template <bool SPLIT = false, bool CMAX = false>
+  __device__ __forceinline__ void build_plane(int k, int dz, bool with_u, cpx<T>* Bs, int t0, int nt,
+                                              unsigned* cmax = nullptr) const {
+    T m[NE];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) m[j] = 0;
 #pragma unroll 1
     for (int e = t0; e < sb.bp * LP; e += nt) {
       const int p = e / LP, r = e % LP;
       cpx<T> v[NE];
       build<SPLIT>(k, p, r, dz, with_u, v);
 #pragma unroll
-      for (int j = 0; j < NE; ++j) put_operand<T, RG>(Bs, p, r + j * LP, r + j * LP < nrg ? v[j] : mk<T>(0, 0));
+      for (int j = 0; j < NE; ++j) {
+        const cpx<T> w = r + j * LP < nrg ? v[j] : mk<T>(0, 0);
+        put_operand<T, RG>(Bs, p, r + j * LP, w);
+        if constexpr (CMAX) m[j] = fmax(m[j], fmax(fabs(w.re), fabs(w.im)));
+      }
+    }
+    if constexpr (CMAX) {
+      static_assert(sizeof(T) == 4, "column maxima of complex FP32 operands");
+      const int lane = t0 & 63, r = t0 % LP;
+#pragma unroll
+      for (int j = 0; j < NE; ++j) {
+        for (int off = LP; off < 64; off <<= 1) m[j] = fmax(m[j], __shfl_xor(m[j], off));
+        if (lane < LP) atomicMax(&cmax[r + j * LP], __float_as_uint(m[j]));
+      }
     }
   }
   // core node (k, p) of the box: z = x (+ add)
@@ -378,10 +398,10 @@ struct BoxCtx {
   // then backward planes k = ez - 2, ..., 0.
   __device__ __forceinline__ int nsteps() const { return 2 * sb.ez - 1; }
   __device__ __forceinline__ int plane_of(int s) const { return s < sb.ez ? s : 2 * sb.ez - 2 - s; }
-  template <bool SPLIT = false>
-  __device__ __forceinline__ void build_step(int s, cpx<T>* Bs, int t0, int nt) const {
-    if (s < sb.ez) build_plane<SPLIT>(s, -1, true, Bs, t0, nt);
-    else build_plane<SPLIT>(plane_of(s), +1, false, Bs, t0, nt);
+  template <bool SPLIT = false, bool CMAX = false>
+  __device__ __forceinline__ void build_step(int s, cpx<T>* Bs, int t0, int nt, unsigned* cmax = nullptr) const {
+    if (s < sb.ez) build_plane<SPLIT, CMAX>(s, -1, true, Bs, t0, nt, cmax);
+    else build_plane<SPLIT, CMAX>(plane_of(s), +1, false, Bs, t0, nt, cmax);
   }
   __device__ __forceinline__ const cpx<T>* factor(const cpx<T>* sinv, int s) const {
     return sinv + sb.mat_off + (long long)plane_of(s) * sb.bp * sb.bp;
@@ -462,6 +482,204 @@ __global__ void __launch_bounds__(64 * fused_max_waves<T>()) k_oras_gl(const Sub
         cs, bcol, wave, nwaves, lane, a, b, [&](int p, int r) { return bx.init(st, p, r); },
         [&](int p, int r, cpx<T> val) { bx.output(st, p, r, val); });
     wg_sync_global();
+  }
+}
+
+// ---- approximate local solves: plane inverses in complex FP16 ----------------
+//
+// Factor storage of the approximate form: plane k of box s holds
+// Sinv_k 2^-e (e = sexp[s maxez + k], chosen so that the largest |Re| or |Im|
+// lies in [2^13, 2^14)), in blocks of 16 bytes: for row p and column group g
+// (columns 4g .. 4g + 3) the four real parts, then the four imaginary parts, as
+// FP16.  The operand T stays complex FP32 in LDS; each column is scaled by a
+// power of two (its largest |Re| or |Im| to [2^13, 2^14)) and rounded to FP16
+// as the product reads it.  Products on v_mfma_f32_16x16x16_f16, FP32
+// accumulation; the accumulators start from y_k and end as the output scaled
+// by the inverse powers of two (exact).
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+union H4U {
+  uint2 u;
+  h4 h;
+};
+
+// A wave's 16-row tiles of a FP16 plane inverse, 16 columns (one 16-byte block
+// per lane: row wave 16 + lane % 16, column group 4 c + lane / 16) per chunk,
+// unconditional loads clamped past the end as in ChunkStream.
+struct HalfStream {
+  const uint4* base;
+  long long tile_step;
+  int nct, ntw, tile, chunk;
+  __device__ __forceinline__ HalfStream(const uint4* Sk, int bp, int wave, int nwaves, int lane) {
+    const int nmt = bp >> 4, bq = bp >> 2;
+    nct = nmt;
+    ntw = wave < nmt ? (nmt - wave + nwaves - 1) / nwaves : 0;
+    base = Sk + (long long)(min(wave, nmt - 1) * 16 + (lane & 15)) * bq + (lane >> 4);
+    tile_step = (long long)nwaves * 16 * bq;
+    tile = 0;
+    chunk = 0;
+  }
+  __device__ __forceinline__ uint4 next() {
+    const bool past = tile >= ntw;
+    const uint4* p = base + (past ? (long long)(ntw > 0 ? ntw - 1 : 0) * tile_step + 4 * (nct - 1)
+                                  : (long long)tile * tile_step + 4 * chunk);
+    const uint4 v = *p;
+    if (++chunk == nct) {
+      chunk = 0;
+      ++tile;
+    }
+    return v;
+  }
+};
+
+// Power-of-two exponent that maps m (>= 0) into [2^13, 2^14): m = f 2^x, f in [0.5, 1).
+__device__ __forceinline__ int half_shift(float m) {
+  int x = 0;
+  (void)frexpf(m, &x);
+  return m > 0.f ? x - 14 : 0;
+}
+
+// Sinv_k T for the wave's tiles with the FP16 factors; cmax holds the operand's
+// column maxima (float bits), sS the plane's scale exponent.
+template <int RG, int PF, typename Init, typename Out>
+__device__ __forceinline__ void plane_product_half(HalfStream& cs, const c32* __restrict__ Bs,
+                                                   const unsigned* cmax, int sS, int wave, int nwaves, int lane,
+                                                   uint4 (&a)[PF], Init&& init, Out&& out) {
+  constexpr int W = lds_width<float>(RG), NT = RG / 16;
+  const int lrow = lane & 15, lg = lane >> 4;
+  int sT[NT];
+  float tin[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    sT[nt] = half_shift(__uint_as_float(cmax[nt * 16 + lrow]));
+    tin[nt] = ldexpf(1.f, -sT[nt]);
+  }
+  const c32* Bcol = Bs + 4 * lg * W + lrow;
+  const int nct = cs.nct, total = cs.ntw * cs.nct;
+  f4v acc[NT][2];
+  int mt = wave, kc = 0;
+  for (int c0 = 0; c0 < total; c0 += PF) {
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      if (c0 + j < total) {
+        if (kc == 0) {  // start from y_k (backward) or zero, in the product's scale
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            const float f = ldexpf(1.f, -(sS + sT[nt]));
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const c32 y0 = init(mt * 16 + Mfma<float>::row(lg, v), nt * 16 + lrow);
+              acc[nt][0][v] = y0.re * f;
+              acc[nt][1][v] = y0.im * f;
+            }
+          }
+        }
+        H4U sr, si;
+        sr.u = make_uint2(a[j].x, a[j].y);
+        si.u = make_uint2(a[j].z, a[j].w);
+        const h4 nsi = -si.h;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          h4 tre, tim;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const c32 tv = Bcol[(kc + t) * W + nt * 16];
+            tre[t] = (_Float16)(tv.re * tin[nt]);
+            tim[t] = (_Float16)(tv.im * tin[nt]);
+          }
+          acc[nt][0] = __builtin_amdgcn_mfma_f32_16x16x16f16(sr.h, tre, acc[nt][0], 0, 0, 0);
+          acc[nt][0] = __builtin_amdgcn_mfma_f32_16x16x16f16(nsi, tim, acc[nt][0], 0, 0, 0);
+          acc[nt][1] = __builtin_amdgcn_mfma_f32_16x16x16f16(sr.h, tim, acc[nt][1], 0, 0, 0);
+          acc[nt][1] = __builtin_amdgcn_mfma_f32_16x16x16f16(si.h, tre, acc[nt][1], 0, 0, 0);
+        }
+        kc += 16;
+        if (kc == 16 * nct) {
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            const float f = ldexpf(1.f, sS + sT[nt]);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              out(mt * 16 + Mfma<float>::row(lg, v), nt * 16 + lrow, mk<float>(acc[nt][0][v] * f, acc[nt][1][v] * f));
+          }
+          kc = 0;
+          mt += nwaves;
+        }
+      }
+      a[j] = cs.next();  // chunk c0 + j + PF (unconditional)
+    }
+  }
+}
+
+// The one-workgroup-per-item sweep with FP16 factors: build (complex FP32
+// operand in LDS, column maxima into cmax), barrier, product, barrier.  The
+// column maxima alternate between two buffers; the one not in use is cleared
+// during the build.
+template <int RG, int PF>
+__global__ void __launch_bounds__(64 * 16) k_oras_half(const Sub* __restrict__ subs, int ngroups, int nrhs,
+                                                       const c32* __restrict__ cpl, const uint4* __restrict__ sinv16,
+                                                       const int* __restrict__ sexp, int maxez,
+                                                       const z64* __restrict__ u, z64* __restrict__ z,
+                                                       const z64* __restrict__ add, int gnx, int gny,
+                                                       c32* __restrict__ yloc) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  c32* Bs = reinterpret_cast<c32*>(smem_raw);
+  __shared__ unsigned cmax[2][RG];
+  const int item = (int)xcd_contiguous(blockIdx.x, gridDim.x);
+  const int box = item / ngroups;
+  const BoxCtx<float, RG> bx(subs, item, ngroups, nrhs, cpl, u, z, add, gnx, gny, yloc);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int FT = blockDim.x, nwaves = FT >> 6;
+  const int bp = bx.sb.bp, ns = bx.nsteps();
+  for (int i = tid; i < 2 * RG; i += FT) (&cmax[0][0])[i] = 0u;
+  __syncthreads();
+  for (int st = 0; st < ns; ++st) {
+    const int cb = st & 1, k = bx.plane_of(st);
+    for (int i = tid; i < RG; i += FT) cmax[cb ^ 1][i] = 0u;
+    bx.template build_step<false, true>(st, Bs, tid, FT, cmax[cb]);
+    uint4 a[PF];
+    HalfStream cs(sinv16 + (bx.sb.mat_off + (long long)k * bp * bp) / 4, bp, wave, nwaves, lane);
+#pragma unroll
+    for (int j = 0; j < PF; ++j) a[j] = cs.next();
+    __syncthreads();
+    plane_product_half<RG, PF>(
+        cs, Bs, cmax[cb], sexp[box * maxez + k], wave, nwaves, lane, a,
+        [&](int p, int r) { return bx.init(st, p, r); }, [&](int p, int r, c32 val) { bx.output(st, p, r, val); });
+    wg_sync_global();
+  }
+}
+
+// Plane inverses of one level to the FP16 storage above: one workgroup per
+// (plane, box); the plane's largest |Re| or |Im| sets its exponent.
+__global__ void __launch_bounds__(256) k_to_half(const Sub* __restrict__ subs, int maxez, const c32* __restrict__ sinv,
+                                                 uint4* __restrict__ sinv16, int* __restrict__ sexp) {
+  const int k = blockIdx.x, s = blockIdx.y;
+  const Sub sb = subs[s];
+  if (k >= sb.ez) return;
+  const int bp = sb.bp, bq = bp / 4;
+  const long long off = sb.mat_off + (long long)k * bp * bp;
+  const c32* S = sinv + off;
+  float m = 0.f;
+  for (long long i = threadIdx.x; i < (long long)bp * bp; i += blockDim.x)
+    m = fmaxf(m, fmaxf(fabsf(S[i].re), fabsf(S[i].im)));
+  __shared__ float red[4];
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  const int e = half_shift(m);
+  const float f = ldexpf(1.f, -e);
+  if (threadIdx.x == 0) sexp[s * maxez + k] = e;
+  uint4* D = sinv16 + off / 4;
+  for (long long i = threadIdx.x; i < (long long)bp * bq; i += blockDim.x) {
+    const long long p = i / bq, g = i % bq;
+    const c32* q = S + p * bp + 4 * g;
+    H4U re, im;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      re.h[t] = (_Float16)(q[t].re * f);
+      im.h[t] = (_Float16)(q[t].im * f);
+    }
+    D[i] = make_uint4(re.u.x, re.u.y, im.u.x, im.u.y);
   }
 }
 
@@ -803,3 +1021,104 @@ template bool oras_fused<double>(const Sub*, int, int, const z64*, const z64*, i
                                  int, z64*, z64*, hipStream_t, bool);
 template int fused_group<float>(int, int);
 template int fused_group<double>(int, int);
+
+// ---- approximate local solves: launch and tuning ------------------------------
+
+namespace {
+template <int RG>
+void launch_half_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, int rounds, const c32* cpl,
+                   const uint4* sinv16, const int* sexp, int maxez, const z64* u, z64* z, const z64* add, int gnx,
+                   int gny, c32* yloc, hipStream_t s) {
+  constexpr int PF = 4;
+  const size_t lds = (size_t)bpmax * lds_width<float>(RG) * sizeof(c32);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_oras_half<RG, PF>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024 - 2 * RG * (int)sizeof(unsigned));
+    attr = true;
+  }
+  const int nmt = bpmax / 16;
+  rounds = std::max(rounds, (nmt + 15) / 16);  // at most 16 waves
+  const int nwaves = (nmt + rounds - 1) / rounds;
+  hipLaunchKernelGGL((k_oras_half<RG, PF>), dim3(nsub * ngroups), dim3(64 * nwaves), lds, s, subs, ngroups, nrhs, cpl,
+                     sinv16, sexp, maxez, u, z, add, gnx, gny, yloc);
+}
+
+void launch_half_rg(int rg, int rounds, const Sub* subs, int nsub, int nrhs, int bpmax, const c32* cpl,
+                    const uint4* sinv16, const int* sexp, int maxez, const z64* u, z64* z, const z64* add, int gnx,
+                    int gny, c32* yloc, hipStream_t s) {
+  const int ngroups = (nrhs + rg - 1) / rg;
+  if (rg == 16)
+    launch_half_t<16>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv16, sexp, maxez, u, z, add, gnx, gny, yloc, s);
+  else
+    launch_half_t<32>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv16, sexp, maxez, u, z, add, gnx, gny, yloc, s);
+}
+}  // namespace
+
+int half_group(int bpmax, int nrhs) {
+  int rg = nrhs <= 16 ? 16 : 32;
+  while (rg >= 16 && !lds_fits<float>(rg, bpmax)) rg /= 2;
+  return rg >= 16 ? rg : 0;
+}
+
+bool oras_half(const Sub* subs, int nsub, int bpmax, const c32* cpl, const uint4* sinv16, const int* sexp, int maxez,
+               int nrhs, const z64* u, z64* z, const z64* add, int gnx, int gny, c32* yloc, hipStream_t s,
+               bool may_tune) {
+  const int rgmax = half_group(bpmax, nrhs);
+  if (rgmax == 0) return false;
+  const TuneKey key{2, bpmax, nsub, nrhs, gnx, gny, g_sweep_policy.load()};
+  TuneVal tv{0, 0, false};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) tv = it->second;
+  }
+  static const bool no_tune = std::getenv("HELM_NO_TUNE") != nullptr;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  (void)hipStreamIsCapturing(s, &cap);
+  const int nmt = bpmax / 16, r0 = (nmt + 15) / 16;
+  if (tv.rg == 0 && !no_tune && may_tune && cap == hipStreamCaptureStatusNone) {
+    hipEvent_t e0, e1;
+    (void)locked_event_create(&e0);
+    (void)locked_event_create(&e1);
+    float best = 1e30f;
+    static const bool verbose = std::getenv("HELM_TUNE_VERBOSE") != nullptr;
+    for (int cand = 16; cand <= rgmax; cand *= 2) {
+      int last_waves = 0;
+      for (int rounds = r0; rounds <= r0 + 2; ++rounds) {
+        const int waves = (nmt + rounds - 1) / rounds;
+        if (waves == last_waves) continue;
+        last_waves = waves;
+        float tot = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {
+          (void)hipEventRecord(e0, s);
+          launch_half_rg(cand, rounds, subs, nsub, nrhs, bpmax, cpl, sinv16, sexp, maxez, u, z, add, gnx, gny, yloc, s);
+          (void)hipEventRecord(e1, s);
+          (void)hipEventSynchronize(e1);
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          if (rep > 0) tot += ms;
+        }
+        if (verbose) std::fprintf(stderr, "helm:   fp16 candidate group %d, %d waves: %.3f ms\n", cand, waves, tot);
+        if (tot < best) {
+          best = tot;
+          tv = {cand, rounds, false};
+        }
+      }
+    }
+    locked_event_destroy(e0);
+    locked_event_destroy(e1);
+    if (verbose)
+      std::fprintf(stderr, "helm: fp16 sweep tuned (bp %d, %d boxes, %d rhs): group %d, %d waves, %.3f ms\n", bpmax,
+                   nsub, nrhs, tv.rg, (nmt + tv.rounds - 1) / tv.rounds, best);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = tv;
+  }
+  if (tv.rg == 0) tv = {rgmax, r0, false};
+  launch_half_rg(tv.rg, tv.rounds, subs, nsub, nrhs, bpmax, cpl, sinv16, sexp, maxez, u, z, add, gnx, gny, yloc, s);
+  return true;
+}
+
+void launch_to_half(const Sub* subs, int nsub, int maxez, const c32* sinv, uint4* sinv16, int* sexp, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_half, dim3(maxez, nsub), dim3(256), 0, s, subs, maxez, sinv, sinv16, sexp);
+}

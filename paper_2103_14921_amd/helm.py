@@ -17,15 +17,18 @@ LIB_PATH = os.path.join(_HERE, "libhelm.so")
 
 HELM_OK, HELM_NOT_CONVERGED, HELM_PENDING = 0, 1, 2
 HELM_EINVAL, HELM_ENOMEM, HELM_EDEVICE, HELM_EBREAKDOWN = -1, -2, -3, -4
-HELM_FP64, HELM_MIXED, HELM_SINGLE_LOCAL = 0, 1, 2
+HELM_FP64, HELM_MIXED, HELM_SINGLE_LOCAL, HELM_APPROX_LOCAL = 0, 1, 2, 3
 HELM_VEL_COMPLEX128, HELM_VEL_REAL64 = 0, 1
-PRECISIONS = {"fp64": HELM_FP64, "mixed": HELM_MIXED, "single_local": HELM_SINGLE_LOCAL}
+PRECISIONS = {"fp64": HELM_FP64, "mixed": HELM_MIXED, "single_local": HELM_SINGLE_LOCAL,
+              "approx_local": HELM_APPROX_LOCAL}
 
 
 def _precision(name):
     """Library code of a precision name: "fp64" (everything complex FP64), "mixed"
-    (fine local solves complex FP32) or "single_local" (local solves of both
-    levels complex FP32); Krylov, residuals and the coarse GMRES stay FP64."""
+    (fine local solves complex FP32), "single_local" (local solves of both
+    levels complex FP32) or "approx_local" (fine local solves approximate: plane
+    inverses in complex FP16 on FP16 matrix cores); Krylov, residuals and the
+    coarse GMRES stay FP64."""
     try:
         return PRECISIONS[name]
     except KeyError:

@@ -90,6 +90,9 @@ def test_statistics_entry_points_reject_null_handles_and_bad_kinds():
     assert helm.lib.helm_resident_bytes(None) == 0
     # an unknown precision code is refused before any device work
     d = helm.DecompT(2, 2, 2, 2, 2, 10, 7, 20, 1, 0)
+    assert helm.footprint((32, 32, 32), (2, 2, 2), precision="approx_local") > 0
+    # approximate local solves need fine planes of at most 960 nodes
+    assert helm.footprint((68, 68, 16), (2, 2, 1), precision="approx_local") == 0
     assert helm.lib.helm_footprint(C.byref(helm.Grid(32, 32, 32, 25.0)), C.byref(d), 1) == 0
     with pytest.raises(ValueError):
         helm.footprint((32, 32, 32), (2, 2, 2), precision="half")
