@@ -107,10 +107,8 @@ def measured_traffic(kernel_file, profile_md, algorithmic_bytes):
 
 
 def set_traffic(entry, kernel_file, profile_md):
-    """Attach the measured HBM traffic (or null) and its source to a roofline entry, and label the bound
-    from the arithmetic intensity on that traffic (on the algorithmic bytes when there is none): below
-    the ridge of the kernel's arithmetic the kernel is bandwidth-bound, and achieved/peak/frac are then
-    the algorithmic bytes per second against HBM peak."""
+    """Attach the measured HBM traffic (or null) and its source to a roofline entry, with the arithmetic
+    intensity on that traffic beside the algorithmic one."""
     traffic, source = measured_traffic(kernel_file, profile_md, entry["bytes_per_launch"])
     entry["traffic"], entry["traffic_source"] = traffic, source
     label_bound(entry)
@@ -118,11 +116,19 @@ def set_traffic(entry, kernel_file, profile_md):
 
 
 def label_bound(entry):
+    """The kernel's roofline from its algorithmic intensity (flops over the algorithmic bytes: every
+    factor once per application, the plane vectors): above the ridge of its arithmetic it is bound by
+    the matrix cores (achieved TFLOP/s against that peak), below by HBM (algorithmic GB/s against 8 TB/s).
+    With measured traffic, its intensity is reported beside: below the ridge, the implementation's own
+    re-reads make it bandwidth-limited in practice although its algorithm is not."""
     peak_flops = entry["mfma_peak"] * 1e12
     ridge = peak_flops / 8.0e12
-    ai = entry["flops_per_launch"] / (entry["traffic"] or entry["bytes_per_launch"])
+    ai = entry["flops_per_launch"] / entry["bytes_per_launch"]
     entry["arithmetic_intensity"] = ai
     entry["ridge"] = ridge
+    if entry.get("traffic"):
+        entry["measured_arithmetic_intensity"] = entry["flops_per_launch"] / entry["traffic"]
+        entry["bandwidth_limited_in_practice"] = entry["measured_arithmetic_intensity"] < ridge
     if ai >= ridge:
         entry.update(bound="mfma", achieved=entry["tflops"], peak=entry["mfma_peak"], unit="TFLOP/s",
                      frac=entry["tflops"] / entry["mfma_peak"])

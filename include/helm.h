@@ -224,7 +224,7 @@ helm_status helm_solve_bound(const helm_handle_t* h, double out[3]);
  * level 0 (fine) or 1 (coarse), out[0] launches, out[1] total milliseconds,
  * out[2] algorithmic real flops (8 b^2 per plane product and right-hand side,
  * b the unpadded plane size, 2 ez - 1 plane products per box) and out[3]
- * algorithmic bytes (factors once per right-hand-side group plus plane
+ * algorithmic bytes (every factor once per application plus the plane
  * vectors), summed over the launches since enabling.  Enabling resets them. */
 helm_status helm_set_sweep_timing(helm_handle_t* h, int32_t enable);
 helm_status helm_sweep_stats(const helm_handle_t* h, int32_t level, double out[4]);

@@ -702,21 +702,19 @@ void oras_sweep(helm_handle* H, Level& L, int nr, const z64* u, z64* z, const z6
 
 // Algorithmic work of one batched local-solve launch: every plane product
 // Sinv_k T (ez forward + ez-1 backward per box) costs 8 b^2 real flops per
-// right-hand side; the bytes count the factors once per right-hand-side group
-// plus the plane vectors (gather, scatter, stored planes).
+// right-hand side; the bytes count each factor once per application (the
+// implementation reads it once per plane product and right-hand-side group:
+// that excess is what measured traffic shows) plus the plane vectors (gather,
+// scatter, stored planes).
 void sweep_work(const helm_handle* H, const Level& L, int nr, double* flops, double* bytes) {
   const int es = (int)elem_size(L.prec);          // plane vectors
   const int fs = L.half ? 4 : es;                 // factor entries
-  int rg = tuned_group(fs / 2, L.bpmax, L.nsub, nr, L.nx, L.ny);  // keyed by the real type's size
-  if (rg == 0)
-    rg = L.half ? half_group(L.bpmax, nr) : (L.prec ? fused_group<float>(L.bpmax, nr) : fused_group<double>(L.bpmax, nr));
-  const int ngroups = rg > 0 ? (nr + rg - 1) / rg : 1;
   double f = 0, by = 0;
   for (const Sub& sb : L.subs) {
     const double planes = 2.0 * sb.ez - 1.0;
     const double b = sb.b;
     f += planes * 8.0 * b * b * nr;
-    by += planes * b * b * fs * ngroups;                      // factors
+    by += (double)sb.ez * b * b * fs;                         // factors, once per application
     by += (double)sb.b * sb.ez * nr * (16.0 + 3.0 * es);      // gather + stored planes (w, r, w)
     by += (double)(sb.hi[0] - sb.lo[0]) * (sb.hi[1] - sb.lo[1]) * (sb.hi[2] - sb.lo[2]) * nr * 16.0;  // scatter
   }
@@ -751,7 +749,7 @@ void oras_apply(helm_handle* H, Level& L, int nr, const z64* u, z64* z, const z6
     record_timing_event(H, e0);
   }
   oras_sweep(H, L, nr, u, z, add, yl, tb);
-  if (g_work) {  // after the launch: a first sweep of a shape has run the tuner, whose group sets the bytes
+  if (g_work) {
     double f, by;
     sweep_work(H, L, nr, &f, &by);
     account(by, f, L.half ? FP16_PEAK : (L.prec ? FP32_PEAK : FP64_PEAK));
