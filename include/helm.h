@@ -102,6 +102,7 @@ typedef struct {
   int32_t restart;        /* FGMRES restart length m, >= 1 */
   int32_t robin;          /* 1: absorbing interfaces (ORAS); 0: Dirichlet (RAS) */
   int32_t nrhs_chunk;     /* right-hand sides per batch; 0 = planner's choice */
+  int32_t adaptive;       /* 1: adaptive stencil coefficients (helm_fit_weight_table); 0: one weight set */
 } helm_decomp_t;
 
 /* Least-squares fit of the mixed-grid weights on the dispersion relation
@@ -109,6 +110,19 @@ typedef struct {
  * G = gmin..gmax points per wavelength (ng values) and nang x nang directions in
  * the first octant, subject to the two sum constraints.  Host only; needs no GPU. */
 helm_status helm_fit_weights(double gmin, double gmax, int32_t ng, int32_t nang, helm_weights_t* out);
+
+/* Adaptive stencil coefficients (FD-vs-FE section: coefficients matched to the
+ * local wavespeed).  out[j], j < n, is the weight set fitted as in
+ * helm_fit_weights on the band of three G values from G_j / 1.05 to
+ * G_j * 1.05, G_j = g0 + j dg, with nang x nang directions.  With
+ * dec->adaptive = 1, helm_setup fits the table g0 = 3, dg = 0.25, n = 29,
+ * nang = 15 (G from 3 to 10: above, every consistent stencil is accurate and
+ * the fit loses its conditioning) and gives each node the weights interpolated
+ * linearly in its G = Re(c)/(f h) (clamped at the table's ends); every edge
+ * takes the mean of its two end nodes' stiffness weights and the mean of
+ * wm sigma at its ends as its mass coupling, so the operator stays complex
+ * symmetric; helm_setup's weights argument is then ignored.  Host only. */
+helm_status helm_fit_weight_table(double g0, double dg, int32_t n, int32_t nang, helm_weights_t* out);
 
 /* Kinds of velocity array accepted by helm_setup. */
 enum {

@@ -101,6 +101,36 @@ def fit_weights(g_values=tuple(range(4, 11)), n_angles=15):
     return Weights(1.0 - w2 - w3, w2, w3, 1.0 - 6.0 * wm2 - 12.0 * wm3 - 8.0 * wm4, wm2, wm3, wm4)
 
 
+# Adaptive coefficients (FD-vs-FE section: the stencil's coefficients are
+# matched to the local wavespeed).  Reading: a table of weight sets, entry j
+# fitted on the band [G_j / 1.05, G_j * 1.05] (three G values) around
+# G_j = ADAPT_G0 + j * ADAPT_DG points per wavelength, j < ADAPT_N (G from 3 to
+# 10; above 10 every consistent stencil is accurate and the fit loses its
+# conditioning, so larger G take the last entry); a node with G = Re(c)/(f h)
+# takes the weights interpolated linearly in G between the two entries around
+# it (clamped at the ends).
+ADAPT_G0, ADAPT_DG, ADAPT_N = 3.0, 0.25, 29
+
+
+def adaptive_table(g0=ADAPT_G0, dg=ADAPT_DG, n=ADAPT_N, n_angles=15):
+    """Weight sets fitted per points-per-wavelength band (list of Weights, entry j at G = g0 + j dg)."""
+    out = []
+    for j in range(n):
+        G = g0 + j * dg
+        out.append(fit_weights(g_values=np.linspace(G / 1.05, G * 1.05, 3), n_angles=n_angles))
+    return out
+
+
+def interpolate_weights(table, G, g0=ADAPT_G0, dg=ADAPT_DG):
+    """Weights at points per wavelength G (scalar): linear in G between table entries, clamped."""
+    n = len(table)
+    x = min(max((G - g0) / dg, 0.0), n - 1.0)
+    j = min(int(np.floor(x)), n - 2)
+    t = x - j
+    a, b = table[j].as_array(), table[j + 1].as_array()
+    return Weights(*((1.0 - t) * a + t * b))
+
+
 def phase_velocity_ratio(w: Weights, G, theta, phi):
     """v_phase / c of the discrete stencil for a plane wave of G points per wavelength."""
     kh = 2.0 * np.pi / G
@@ -159,13 +189,21 @@ def pml_xi(n, npml_lo, npml_hi, h, omega, vmax, R=PML_R):
 
 @dataclass
 class Problem:
-    """Discrete Helmholtz problem: grid (nx, ny, nz), spacing h, complex velocity c[nz][ny][nx]."""
+    """Discrete Helmholtz problem: grid (nx, ny, nz), spacing h, complex velocity c[nz][ny][nx].
+
+    adaptive=True replaces the one weight set by per-node weights from
+    ``adaptive_table`` (``node_weights``): each edge (i, j) takes the mean of its
+    two end nodes' stiffness weights, the mass coupling the mean of
+    wm_class sigma at its two ends, the diagonal the node's own wm1 sigma_i (and
+    its own stiffness weights toward ghost neighbours), so that A = A^T.
+    """
     shape: tuple
     h: float
     c: np.ndarray
     freq: float
     pml: Pml
     weights: Weights = field(default_factory=lambda: SEVEN_POINT)
+    adaptive: bool = False
 
     @property
     def n(self):
@@ -194,6 +232,28 @@ class Problem:
         (xx, _), (xy, _), (xz, _) = self.profiles()
         s = xz[:, None, None] * xy[None, :, None] * xx[None, None, :]
         return s * self.k() ** 2
+
+    def node_weights(self):
+        """Per-node (alphas [3][nz][ny][nx], wm [4][nz][ny][nx]): the fixed weights everywhere, or with
+        adaptive=True the table's weights at each node's G = Re(c)/(f h)."""
+        nz_ny_nx = self.c.shape
+        if not self.adaptive:
+            al = np.array(self.weights.alphas())[:, None, None, None] * np.ones((1,) + nz_ny_nx)
+            wm = np.array([self.weights.wm1, *self.weights.masses()])[:, None, None, None] * np.ones((1,) + nz_ny_nx)
+            return al, wm
+        if "_table" not in self.__dict__:
+            self.__dict__["_table"] = np.array([w.as_array() for w in adaptive_table()])  # [n][7]
+        T = self.__dict__["_table"]
+        n = T.shape[0]
+        G = self.c.real / (self.freq * self.h)
+        x = np.clip((G - ADAPT_G0) / ADAPT_DG, 0.0, n - 1.0)
+        j = np.minimum(np.floor(x).astype(np.int64), n - 2)
+        t = x - j
+        W = (1.0 - t)[..., None] * T[j] + t[..., None] * T[j + 1]  # [nz][ny][nx][7]: w1 w2 w3 wm1 wm2 wm3 wm4
+        w1, w2, w3 = W[..., 0], W[..., 1], W[..., 2]
+        al = np.stack([w1 + w2 / 3.0, w2 / 6.0, w3 / 4.0])
+        wm = np.moveaxis(W[..., 3:7], -1, 0)
+        return al, wm
 
 
 def _midpoint_factor(profiles, e, sign):
@@ -224,6 +284,8 @@ def assemble(prob: Problem):
       A[i, i]    = -sum_{e,+-} (alpha_e/h^2) a_e(i +- e/2) + wm1 sigma_i
     (the diagonal sum runs over ghost neighbours too).
     """
+    if prob.adaptive:
+        return _assemble_adaptive(prob)
     nx, ny, nz = prob.shape
     h2 = prob.h ** 2
     prof = prob.profiles()
@@ -262,6 +324,64 @@ def assemble(prob: Problem):
     return A
 
 
+def _shifted(a, e, sign):
+    """b[i] = a[i + sign e] where that node is in the grid, else a[i] (a: [..., nz, ny, nx])."""
+    b = a.copy()
+    nz, ny, nx = a.shape[-3:]
+    ex, ey, ez = (sign * v for v in e)
+    dst = (Ellipsis, slice(max(0, -ez), nz - max(0, ez)), slice(max(0, -ey), ny - max(0, ey)),
+           slice(max(0, -ex), nx - max(0, ex)))
+    src = (Ellipsis, slice(max(0, ez), nz - max(0, -ez)), slice(max(0, ey), ny - max(0, -ey)),
+           slice(max(0, ex), nx - max(0, -ex)))
+    b[dst] = a[src]
+    return b
+
+
+def _assemble_adaptive(prob: Problem):
+    """``assemble`` with per-node weights (Problem.adaptive):
+      A[i, j] = (alpha_e(i, j)/h^2) a_e(m) + (wm_class,i sigma_i + wm_class,j sigma_j)/2,
+      alpha_e(i, j) = (alpha_e,i + alpha_e,j)/2,
+      A[i, i] = -sum_{e,+-} (alpha_e(i, i+-e)/h^2) a_e(i +- e/2) + wm1,i sigma_i,
+    a ghost neighbour j taking alpha_e(i, j) = alpha_e,i."""
+    nx, ny, nz = prob.shape
+    h2 = prob.h ** 2
+    prof = prob.profiles()
+    sig = prob.sigma()
+    al, wm = prob.node_weights()
+    idx = np.arange(prob.n, dtype=np.int64).reshape(nz, ny, nx)
+    diag = wm[0] * sig
+    rows, cols, vals = [], [], []
+    for cls, ci in _classes():
+        for e in cls:
+            ap = _midpoint_factor(prof, e, +1)
+            am = _midpoint_factor(prof, e, -1)
+            a_p = 0.5 * (al[ci] + _shifted(al[ci], e, +1))
+            a_m = 0.5 * (al[ci] + _shifted(al[ci], e, -1))
+            diag = diag - (a_p / h2) * ap - (a_m / h2) * am
+            ex, ey, ez = e
+            sx = slice(max(0, -ex), nx - max(0, ex))
+            sy = slice(max(0, -ey), ny - max(0, ey))
+            sz = slice(max(0, -ez), nz - max(0, ez))
+            tx = slice(max(0, ex), nx - max(0, -ex))
+            ty = slice(max(0, ey), ny - max(0, -ey))
+            tz = slice(max(0, ez), nz - max(0, -ez))
+            i_idx = idx[sz, sy, sx].ravel()
+            j_idx = idx[tz, ty, tx].ravel()
+            ws = wm[ci + 1] * sig
+            v = (a_p[sz, sy, sx].ravel() / h2) * ap[sz, sy, sx].ravel() \
+                + 0.5 * (ws[sz, sy, sx].ravel() + ws[tz, ty, tx].ravel())
+            rows += [i_idx, j_idx]
+            cols += [j_idx, i_idx]
+            vals += [v, v]
+    rows.append(idx.ravel())
+    cols.append(idx.ravel())
+    vals.append(diag.ravel())
+    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(prob.n, prob.n)).tocsr()
+    A.sum_duplicates()
+    return A
+
+
 def row(prob: Problem, ix, iy, iz):
     """Row (ix, iy, iz) of A computed on its own: (global column indices, values).
 
@@ -269,6 +389,8 @@ def row(prob: Problem, ix, iy, iz):
     docstring), evaluated one neighbour at a time so that single rows of very
     large grids can be checked without assembling the matrix.
     """
+    if prob.adaptive:
+        return _row_adaptive(prob, ix, iy, iz)
     if "_row_cache" not in prob.__dict__:
         prob.__dict__["_row_cache"] = (prob.profiles(), prob.sigma())
     prof, sig = prob.__dict__["_row_cache"]
@@ -298,6 +420,43 @@ def row(prob: Problem, ix, iy, iz):
                 if 0 <= jx < nx and 0 <= jy < ny and 0 <= jz < nz:
                     cols.append(jx + nx * (jy + ny * jz))
                     vals.append(st + ms[ci] * 0.5 * (si + sig[jz, jy, jx]))
+    cols.append(ix + nx * (iy + ny * iz))
+    vals.append(diag)
+    return np.array(cols, dtype=np.int64), np.array(vals, dtype=np.complex128)
+
+
+def _row_adaptive(prob: Problem, ix, iy, iz):
+    """``row`` with per-node weights (the entries of ``_assemble_adaptive``), one neighbour at a time."""
+    if "_row_cache_adaptive" not in prob.__dict__:
+        prob.__dict__["_row_cache_adaptive"] = (prob.profiles(), prob.sigma(), prob.node_weights())
+    prof, sig, (al, wm) = prob.__dict__["_row_cache_adaptive"]
+    nx, ny, nz = prob.shape
+    h2 = prob.h ** 2
+    pos = (ix, iy, iz)
+    si = sig[iz, iy, ix]
+    diag = wm[0][iz, iy, ix] * si
+    cols, vals = [], []
+    for cls, ci in _classes():
+        for e in cls:
+            for sign in (+1, -1):
+                s = 1.0 + 0j
+                inv = 0j
+                e2 = float(e[0] ** 2 + e[1] ** 2 + e[2] ** 2)
+                for d in range(3):
+                    xi_int, xi_half = prof[d]
+                    ed = sign * e[d]
+                    xv = xi_int[pos[d]] if ed == 0 else (xi_half[pos[d] + 1] if ed > 0 else xi_half[pos[d]])
+                    s = s * xv
+                    inv = inv + (e[d] ** 2 / e2) / xv ** 2
+                jx, jy, jz = ix + sign * e[0], iy + sign * e[1], iz + sign * e[2]
+                inside = 0 <= jx < nx and 0 <= jy < ny and 0 <= jz < nz
+                a_i = al[ci][iz, iy, ix]
+                a_e = 0.5 * (a_i + al[ci][jz, jy, jx]) if inside else a_i
+                st = (a_e / h2) * (s * inv)
+                diag = diag - st
+                if inside:
+                    cols.append(jx + nx * (jy + ny * jz))
+                    vals.append(st + 0.5 * (wm[ci + 1][iz, iy, ix] * si + wm[ci + 1][jz, jy, jx] * sig[jz, jy, jx]))
     cols.append(ix + nx * (iy + ny * iz))
     vals.append(diag)
     return np.array(cols, dtype=np.int64), np.array(vals, dtype=np.complex128)

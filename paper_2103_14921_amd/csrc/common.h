@@ -121,6 +121,9 @@ struct OpDev {
   const uint8_t* flat; // per-axis flag: 1 where the 3-point neighbourhood has xi == 1
   int off_int[3];      // offsets of each axis in the int tables
   int off_half[3];     // offsets of each axis in the half tables
+  // adaptive coefficients: per node {alpha_face, alpha_edge, alpha_corner, wm1,
+  // wm2, wm3, wm4, 0}; nullptr = the single set alpha, wm above
+  const double* wnode;
 };
 
 // Per-subdomain description (device and host).

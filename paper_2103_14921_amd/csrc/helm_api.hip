@@ -430,6 +430,7 @@ struct helm_handle {
   helm_weights_t w{};
   helm_decomp_t dec{};
   DevBuf c, sigma, xi_int, xi_half, i2_int, i2_half, flat, vmax, err;
+  DevBuf wtab, wnode;  // adaptive coefficients: weight table [n][7], per-node weights [n][8]
   OpDev op{};
   Level fine, coarse;
   Workspace ws;
@@ -541,6 +542,17 @@ void fit_weights_host(double gmin, double gmax, int ng, int nang, helm_weights_t
   out->wm1 = 1.0 - 6.0 * p[2] - 12.0 * p[3] - 8.0 * p[4];
 }
 
+// The adaptive coefficients' table (helm_fit_weight_table).
+constexpr double ADAPT_G0 = 3.0, ADAPT_DG = 0.25;
+constexpr int ADAPT_N = 29, ADAPT_NANG = 15;
+
+void fit_weight_table_host(double g0, double dg, int n, int nang, helm_weights_t* out) {
+  for (int j = 0; j < n; ++j) {
+    const double G = g0 + j * dg;
+    fit_weights_host(G / 1.05, G * 1.05, 3, nang, out + j);
+  }
+}
+
 size_t budget_bytes() {
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
@@ -568,6 +580,7 @@ void validate(const helm_grid_t* g, const helm_pml_t* pml, const helm_decomp_t* 
   if (d->overlap < 1) throw HelmError(HELM_EINVAL, "overlap must be >= 1");
   if (d->levels != 1 && d->levels != 2) throw HelmError(HELM_EINVAL, "levels must be 1 or 2");
   if (d->levels == 2 && d->coarse_iters < 1) throw HelmError(HELM_EINVAL, "coarse_iters must be >= 1");
+  if (d->adaptive != 0 && d->adaptive != 1) throw HelmError(HELM_EINVAL, "adaptive must be 0 or 1");
   if (d->restart < 1 || d->restart > 64) throw HelmError(HELM_EINVAL, "restart must be in [1, 64]");
   if (d->precision != HELM_FP64 && d->precision != HELM_MIXED && d->precision != HELM_SINGLE_LOCAL &&
       d->precision != HELM_APPROX_LOCAL)
@@ -616,6 +629,7 @@ size_t ws_bytes(const helm_handle* H, int nr) {
 
 size_t resident_bytes_planned(const helm_handle* H) {
   size_t b = sizeof(z64) * (size_t)H->n * 2 + level_resident_bytes(H->fine);
+  if (H->dec.adaptive) b += sizeof(double) * 8 * (size_t)H->n + sizeof(double) * 7 * ADAPT_N;
   if (H->two_level()) b += level_resident_bytes(H->coarse) + sizeof(z64) * (size_t)H->coarse.n * 27;
   return b;
 }
@@ -1319,6 +1333,24 @@ void setup_impl(helm_handle* H, const void* velocity, int vel_kind) {
   op.off_half[0] = 0;
   op.off_half[1] = H->nx + 1;
   op.off_half[2] = H->nx + H->ny + 2;
+  op.wnode = nullptr;
+  if (H->dec.adaptive) {  // per-node weights from the table at each node's points per wavelength
+    std::vector<helm_weights_t> tw(ADAPT_N);
+    fit_weight_table_host(ADAPT_G0, ADAPT_DG, ADAPT_N, ADAPT_NANG, tw.data());
+    std::vector<double> tab((size_t)ADAPT_N * 7);
+    for (int j = 0; j < ADAPT_N; ++j) {
+      const helm_weights_t& w = tw[j];
+      const double v[7] = {w.w1, w.w2, w.w3, w.wm1, w.wm2, w.wm3, w.wm4};
+      for (int q = 0; q < 7; ++q) tab[(size_t)j * 7 + q] = v[q];
+    }
+    H->wtab.alloc(sizeof(double) * tab.size());
+    H->wnode.alloc(sizeof(double) * 8 * (size_t)n);
+    HELM_CHECK_HIP(hipMemcpyAsync(H->wtab.p, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, H->stream));
+    launch_node_weights(H->c.as<z64>(), n, H->freq, H->h, H->wtab.as<double>(), ADAPT_N, ADAPT_G0, ADAPT_DG,
+                        H->wnode.as<double>(), H->stream);
+    HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+    op.wnode = H->wnode.as<double>();
+  }
   launch_sigma(op, H->c.as<z64>(), H->omega, H->stream);
 
   // fine level: local operators with absorbing interfaces, then factorisation
@@ -1384,6 +1416,15 @@ helm_status helm_fit_weights(double gmin, double gmax, int32_t ng, int32_t nang,
     if (!out || ng < 1 || nang < 1 || !(gmin > 0) || !(gmax >= gmin))
       throw HelmError(HELM_EINVAL, "bad fit parameters");
     fit_weights_host(gmin, gmax, ng, nang, out);
+    return HELM_OK;
+  });
+}
+
+helm_status helm_fit_weight_table(double g0, double dg, int32_t n, int32_t nang, helm_weights_t* out) {
+  return guarded([&]() {
+    if (!out || n < 1 || nang < 1 || !(g0 > 0) || !(dg > 0) || !std::isfinite(g0) || !std::isfinite(dg))
+      throw HelmError(HELM_EINVAL, "bad table parameters");
+    fit_weight_table_host(g0, dg, n, nang, out);
     return HELM_OK;
   });
 }
@@ -1572,7 +1613,7 @@ size_t helm_resident_bytes(const helm_handle_t* H) {
   // eighth larger than asked for, so this can exceed the planned bytes
   size_t b = 0;
   for (const DevBuf* d : {&H->c, &H->sigma, &H->xi_int, &H->xi_half, &H->i2_int, &H->i2_half, &H->flat, &H->vmax,
-                          &H->err})
+                          &H->err, &H->wtab, &H->wnode})
     b += d->bytes;
   for (const Level* L : {&H->fine, &H->coarse})
     for (const DevBuf* d : {&L->d_subs, &L->aloc, &L->sinv, &L->E, &L->cpl, &L->sinv16, &L->sexp}) b += d->bytes;

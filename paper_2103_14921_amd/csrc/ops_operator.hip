@@ -91,7 +91,39 @@ __global__ void k_sigma(OpDev op, const z64* __restrict__ c, double omega, z64* 
   }
 }
 
+// Adaptive coefficients: per node G = Re(c)/(f h) points per wavelength, the
+// weight set interpolated linearly in G between the table entries around it
+// (entry j at g0 + j dg, [n][7] = w1 w2 w3 wm1 wm2 wm3 wm4; clamped at the
+// ends), stored as alpha_face, alpha_edge, alpha_corner, wm1..wm4.
+__global__ void k_node_weights(const z64* __restrict__ c, long long n, double freq, double h, const double* __restrict__ tab,
+                               int ntab, double g0, double dg, double* __restrict__ wnode) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double G = c[i].re / (freq * h);
+    const double x = fmin(fmax((G - g0) / dg, 0.0), ntab - 1.0);
+    const int j = min((int)floor(x), ntab - 2);
+    const double t = x - j;
+    double w[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) w[q] = (1.0 - t) * tab[j * 7 + q] + t * tab[(j + 1) * 7 + q];
+    double* o = wnode + i * 8;
+    o[0] = w[0] + w[1] / 3.0;
+    o[1] = w[1] / 6.0;
+    o[2] = w[2] / 4.0;
+    o[3] = w[3];
+    o[4] = w[4];
+    o[5] = w[5];
+    o[6] = w[6];
+    o[7] = 0.0;
+  }
+}
+
 }  // namespace
+
+void launch_node_weights(const z64* c, long long n, double freq, double h, const double* tab, int ntab, double g0,
+                         double dg, double* wnode, hipStream_t s) {
+  hipLaunchKernelGGL(k_node_weights, dim3((unsigned)std::min<long long>(ceil_div(n, 256), 16384)), dim3(256), 0, s, c, n,
+                     freq, h, tab, ntab, g0, dg, wnode);
+}
 
 namespace {
 
@@ -121,21 +153,19 @@ __global__ void __launch_bounds__(256) k_stencil2(OpDev op, int nrhs, const z64*
     const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
     const int cls = abs(ox) + abs(oy) + abs(oz);
     const bool flat = op.flat[op.off_int[0] + ix] && op.flat[op.off_int[1] + iy] && op.flat[op.off_int[2] + iz];
-    const z64 st = flat ? mk(op.alpha[cls - 1] * op.h2inv, 0.0) : stiff_coef(op, ix, iy, iz, ox, oy, oz);
-    stf[a][o] = st;
     const int jx = ix + ox, jy = iy + oy, jz = iz + oz;
-    if (jx >= 0 && jx < op.nx && jy >= 0 && jy < op.ny && jz >= 0 && jz < op.nz) {
-      const long long j = jx + (long long)op.nx * (jy + (long long)op.ny * jz);
-      coef[a][o] = st + (0.5 * op.wm[cls]) * (op.sigma[i] + op.sigma[j]);
-    } else {
-      coef[a][o] = mk(0.0, 0.0);
-    }
+    const bool inside = jx >= 0 && jx < op.nx && jy >= 0 && jy < op.ny && jz >= 0 && jz < op.nz;
+    const long long j = inside ? jx + (long long)op.nx * (jy + (long long)op.ny * jz) : -1;
+    const double al = edge_alpha(op, i, j, cls);
+    const z64 st = flat ? mk(al * op.h2inv, 0.0) : stiff_coef(op, al, ix, iy, iz, ox, oy, oz);
+    stf[a][o] = st;
+    coef[a][o] = inside ? st + edge_mass(op, i, j, cls, op.sigma[i], op.sigma[j]) : mk(0.0, 0.0);
   }
   __syncthreads();
   for (int a = tid; a < nb; a += 256) {
     const long long i = i0 + a;
     if (i >= n) continue;
-    z64 d = op.wm[0] * op.sigma[i];
+    z64 d = diag_mass(op, i) * op.sigma[i];
     for (int o = 0; o < 27; ++o)
       if (o != 13) d -= stf[a][o];
     coef[a][13] = d;
@@ -260,13 +290,13 @@ __global__ void __launch_bounds__(256) k_stencil_rows(OpDev op, int nrhs, const 
       if (o == 13) continue;
       const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
       const int cls = abs(ox) + abs(oy) + abs(oz);
-      const z64 st = flat ? mk(op.alpha[cls - 1] * op.h2inv, 0.0) : stiff_coef(op, ix, t.iy, t.iz, ox, oy, oz);
-      ssum += st;
       const int jx = ix + ox, jy = t.iy + oy, jz = t.iz + oz;
-      z64 c = mk(0.0, 0.0);
-      if (jx >= 0 && jx < op.nx && jy >= 0 && jy < op.ny && jz >= 0 && jz < op.nz)
-        c = st + (0.5 * op.wm[cls]) * (si + op.sigma[jx + (long long)op.nx * (jy + (long long)op.ny * jz)]);
-      cf[a][o] = c;
+      const bool inside = jx >= 0 && jx < op.nx && jy >= 0 && jy < op.ny && jz >= 0 && jz < op.nz;
+      const long long j = inside ? jx + (long long)op.nx * (jy + (long long)op.ny * jz) : -1;
+      const double al = edge_alpha(op, i, j, cls);
+      const z64 st = flat ? mk(al * op.h2inv, 0.0) : stiff_coef(op, al, ix, t.iy, t.iz, ox, oy, oz);
+      ssum += st;
+      cf[a][o] = inside ? st + edge_mass(op, i, j, cls, si, op.sigma[j]) : mk(0.0, 0.0);
     }
   } else if (a < TW) {
     for (int o = q; o < 27; o += 4) cf[a][o] = mk(0.0, 0.0);
@@ -275,7 +305,9 @@ __global__ void __launch_bounds__(256) k_stencil_rows(OpDev op, int nrhs, const 
   ssum.im += __shfl_xor(ssum.im, 1);
   ssum.re += __shfl_xor(ssum.re, 2);
   ssum.im += __shfl_xor(ssum.im, 2);
-  if (q == 0 && a < TW) cf[a][13] = a < t.w ? op.wm[0] * si - ssum : mk(0.0, 0.0);
+  if (q == 0 && a < TW)
+    cf[a][13] = a < t.w ? diag_mass(op, t.x0 + a + (long long)op.nx * (t.iy + (long long)op.ny * t.iz)) * si - ssum
+                        : mk(0.0, 0.0);
   __syncthreads();
   tile_product<NXT>(t, op.nx, op.ny, op.nz, nrhs, cf, x, y, b);
 }

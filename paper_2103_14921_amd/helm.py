@@ -45,7 +45,7 @@ EXPORTS = [
     "helm_set_row_tiling",
     "helm_set_lu_panel",
     "helm_solve_async", "helm_request_query", "helm_request_wait", "helm_solve_bound",
-    "helm_device_headroom", "helm_apply_oras_noalloc",
+    "helm_device_headroom", "helm_apply_oras_noalloc", "helm_fit_weight_table",
 ]
 
 
@@ -70,7 +70,7 @@ class WeightsT(C.Structure):
 
 class DecompT(C.Structure):
     _fields_ = [(k, C.c_int32) for k in ("px", "py", "pz", "overlap", "levels", "coarse_iters",
-                                         "precision", "restart", "robin", "nrhs_chunk")]
+                                         "precision", "restart", "robin", "nrhs_chunk", "adaptive")]
 
 
 def _init_torch_runtime_first():
@@ -130,6 +130,7 @@ def _load():
         "helm_solve_bound": ([P, C.POINTER(C.c_double)], C.c_int),
         "helm_device_headroom": ([], C.c_size_t),
         "helm_apply_oras_noalloc": ([P, i32, i32, P, P], C.c_int),
+        "helm_fit_weight_table": ([C.c_double, C.c_double, i32, i32, C.POINTER(WeightsT)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -156,6 +157,13 @@ def fit_weights(gmin=4.0, gmax=10.0, ng=7, nang=15):
     w = WeightsT()
     _check(lib.helm_fit_weights(gmin, gmax, ng, nang, C.byref(w)))
     return {k: getattr(w, k) for k, _ in WeightsT._fields_}
+
+
+def fit_weight_table(g0=3.0, dg=0.25, n=29, nang=15):
+    """The adaptive coefficients' weight table (helm_fit_weight_table): a list of n weight dicts."""
+    out = (WeightsT * n)()
+    _check(lib.helm_fit_weight_table(g0, dg, n, nang, out))
+    return [{k: getattr(w, k) for k, _ in WeightsT._fields_} for w in out]
 
 
 def _is_torch(a):
@@ -280,7 +288,8 @@ class Solver:
     """A set-up problem (helm_setup); owns the library handle."""
 
     def __init__(self, shape, h, velocity, freq, pml=(0, 0, 0, 0), weights=None, parts=(1, 1, 1), overlap=2,
-                 levels=1, coarse_iters=10, precision="fp64", restart=30, robin=True, nrhs_chunk=0, R=1e-3):
+                 levels=1, coarse_iters=10, precision="fp64", restart=30, robin=True, nrhs_chunk=0, R=1e-3,
+                 adaptive=False):
         self.shape = tuple(int(v) for v in shape)
         nx, ny, nz = self.shape
         self.n = nx * ny * nz
@@ -291,7 +300,7 @@ class Solver:
         p = PmlT(*[int(v) for v in pml], float(R))
         d = DecompT(*[int(v) for v in parts], int(overlap), int(levels), int(coarse_iters),
                     _precision(precision), int(restart), 1 if robin else 0,
-                    int(nrhs_chunk))
+                    int(nrhs_chunk), 1 if adaptive else 0)
         w = None
         if weights is not None:
             if not isinstance(weights, dict):

@@ -293,3 +293,18 @@ def test_serving_requeue_hold_is_lifted_when_the_other_batch_ends_first():
     assert list(srv._queue) == [rx] and srv.stats.retries == 1
     assert not ex.busy and not ey.busy
     assert not srv._hold and not srv._held()
+
+
+def test_native_weight_table_matches_oracle():
+    # the adaptive coefficients' table: the library's fit (Householder QR) and
+    # the oracle's (numpy least squares) agree entry by entry
+    from paper_2103_14921_amd import helm
+    from oracle.operator import ADAPT_DG, ADAPT_G0, ADAPT_N, adaptive_table
+    a = helm.fit_weight_table(ADAPT_G0, ADAPT_DG, ADAPT_N, 15)
+    b = adaptive_table()
+    assert len(a) == len(b) == ADAPT_N
+    for wa, wb in zip(a, b):
+        for k in wa:
+            assert abs(wa[k] - getattr(wb, k)) <= 1e-10 * max(1.0, abs(getattr(wb, k))), k
+    with pytest.raises(helm.HelmError):
+        helm.fit_weight_table(n=0)

@@ -17,7 +17,9 @@ at that sampling.
 
 The paper prints relative l2 errors of 0.0079 (alpha = 0.8) and 0.044
 (alpha = 2) for its FD scheme with adaptive stencil coefficients; those are
-context (parity unpinned), and the test bounds the error loosely.
+context (parity unpinned), and the test bounds the error loosely.  It runs
+with the one fixed weight set and with the adaptive coefficients (weights
+matched to each node's points per wavelength).
 """
 import numpy as np
 import pytest
@@ -31,8 +33,9 @@ def say(*a):
     print("[case]", *a, flush=True)
 
 
+@pytest.mark.parametrize("adaptive", [False, True], ids=["fixed", "adaptive"])
 @pytest.mark.parametrize("alpha,paper", [(0.8, 0.0079), (2.0, 0.044)])
-def test_table1_linear_gradient_against_analytic(alpha, paper):
+def test_table1_linear_gradient_against_analytic(alpha, paper, adaptive):
     from paper_2103_14921_amd import helm
     h, f, c0, npml = 31.25, 8.0, 1000.0, 40
     ni = (65, 129, 385)  # 2 x 4 x 12 km, nodes on both ends
@@ -41,16 +44,21 @@ def test_table1_linear_gradient_against_analytic(alpha, paper):
     cz = c0 + alpha * np.maximum(z, 0.0)
     c = np.ascontiguousarray(np.broadcast_to(cz[:, None, None], (nz, ny, nx)).astype(np.complex128))
     sx, sy, sz = npml + 32, npml + 64, npml + 32  # centre of x and y, 1 km deep
-    say("table1", alpha, (nx, ny, nz))
+    say("table1", alpha, "adaptive" if adaptive else "fixed", (nx, ny, nz))
     w = helm.fit_weights()
-    wm = (w["wm1"], w["wm2"], w["wm3"], w["wm4"])
+    if adaptive:  # the source spread with its own node's weights
+        from oracle.operator import adaptive_table, interpolate_weights
+        ws = interpolate_weights(adaptive_table(), c[sz, sy, sx].real / (f * h))
+        wm = (ws.wm1, ws.wm2, ws.wm3, ws.wm4)
+    else:
+        wm = (w["wm1"], w["wm2"], w["wm3"], w["wm4"])
     b = np.zeros((1, nz, ny, nx), np.complex128)
     for dz in (-1, 0, 1):
         for dy in (-1, 0, 1):
             for dx in (-1, 0, 1):
                 b[0, sz + dz, sy + dy, sx + dx] = wm[abs(dx) + abs(dy) + abs(dz)] / h ** 3
     S = helm.Solver((nx, ny, nz), h, c, f, (npml, npml, npml, npml), weights=w, parts=(8, 12, 27), overlap=2,
-                    levels=2, precision="mixed", restart=30)
+                    levels=2, precision="mixed", restart=30, adaptive=adaptive)
     X, info = S.solve(b, tol=1e-7, maxit=1000)
     S.close()
     assert info["relres_true"][0] <= 1e-7
@@ -64,6 +72,6 @@ def test_table1_linear_gradient_against_analytic(alpha, paper):
     err = float(np.linalg.norm(um - G) / np.linalg.norm(G))
     near = r[m] < 500.0
     err_near = float(np.linalg.norm(um[near] - G[near]) / np.linalg.norm(G[near]))
-    say("alpha", alpha, "dof", nx * ny * nz, "iterations", int(info["iters"][0]), "l2 error", round(err, 4),
-        "within 500 m", round(err_near, 4), "paper FD", paper)
+    say("alpha", alpha, "adaptive" if adaptive else "fixed", "dof", nx * ny * nz, "iterations",
+        int(info["iters"][0]), "l2 error", round(err, 4), "within 500 m", round(err_near, 4), "paper FD", paper)
     assert err <= 0.06 and err_near <= 0.02

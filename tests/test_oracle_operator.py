@@ -155,3 +155,75 @@ def test_single_row_matches_assembled_rows():
         got = np.zeros_like(ref)
         np.add.at(got, cols, vals)
         assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+# ---- adaptive coefficients (weights matched to the local wavespeed) ----------
+
+def test_adaptive_operator_symmetric_and_rows_match():
+    shape = (11, 9, 8)
+    c = inputs.velocity_thrust_belt(*shape, h=25.0, q=60.0)
+    prob = Problem(shape, 25.0, c, 10.0, Pml(3, 2, 3, 0), W, adaptive=True)
+    A = assemble(prob)
+    assert abs(A - A.T).max() == 0.0
+    from oracle.operator import row
+    rng = np.random.default_rng(5)
+    for _ in range(40):
+        ix, iy, iz = rng.integers(0, 11), rng.integers(0, 9), rng.integers(0, 8)
+        cols, vals = row(prob, ix, iy, iz)
+        ref = A[ix + 11 * (iy + 9 * iz)].toarray().ravel()
+        got = np.zeros_like(ref)
+        np.add.at(got, cols, vals)
+        assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("G", [3.0, 4.6, 7.25, 10.0, 14.0])
+def test_adaptive_operator_in_a_homogeneous_medium_is_the_fixed_stencil_of_its_G(G):
+    # one wavespeed: every node has the same weights, those of the table at G,
+    # and the operator is the fixed-weight stencil with them (pinned above by
+    # its DST eigenpairs)
+    from oracle.operator import adaptive_table, interpolate_weights
+    shape, h, f = (9, 8, 7), 20.0, 7.0
+    c = np.full(shape[::-1], G * f * h, dtype=np.complex128) * (1 - 0.01j)
+    wg = interpolate_weights(adaptive_table(), G)
+    A = assemble(Problem(shape, h, c, f, Pml(2, 2, 2, 0), wg))
+    B = assemble(Problem(shape, h, c, f, Pml(2, 2, 2, 0), W, adaptive=True))
+    assert abs(A - B).max() <= 1e-13 * abs(A).max()
+    assert abs(wg.w1 + wg.w2 + wg.w3 - 1) < 1e-13 and abs(wg.wm1 + 6 * wg.wm2 + 12 * wg.wm3 + 8 * wg.wm4 - 1) < 1e-13
+
+
+def test_adaptive_weights_dispersion_per_G():
+    # each G takes weights fitted around it: the phase velocity is within 1e-3
+    # of the true one at every G from 3 (2.4e-2 with the one fixed set) and
+    # every propagation direction, and never worse than the fixed set
+    from oracle.operator import adaptive_table, interpolate_weights
+    table = adaptive_table()
+    angles = [(th, ph) for th in np.linspace(0, np.pi / 2, 9) for ph in np.linspace(0, np.pi / 2, 9)]
+    for G in list(np.arange(3.0, 10.01, 0.125)) + [12.0, 16.0, 24.0]:
+        wg = interpolate_weights(table, G)
+        err = max(abs(phase_velocity_ratio(wg, G, th, ph) - 1.0) for th, ph in angles)
+        fixed = max(abs(phase_velocity_ratio(W, G, th, ph) - 1.0) for th, ph in angles)
+        assert err <= 1e-3, (G, err)
+        assert err <= fixed, (G, err, fixed)
+
+
+@pytest.mark.parametrize("G,theta,phi", [(3.5, 0.3, 0.2), (4.6, 0.9, 0.7), (8.1, 1.3, 0.1)])
+def test_adaptive_plane_wave_in_the_assembled_operator(G, theta, phi):
+    # homogeneous medium of G = Re(c)/(f h) points per wavelength: the plane wave
+    # exp(i kappa n.x) solves the assembled adaptive operator at interior nodes
+    # for the kappa at which the dispersion symbol of the table's weights at G
+    # gives k = omega/c (kappa found by fixed-point iteration on that symbol)
+    from oracle.operator import adaptive_table, interpolate_weights
+    shape, h, f = (9, 9, 9), 10.0, 20.0
+    c = np.full(shape[::-1], G * f * h, dtype=np.complex128)
+    k = 2 * np.pi * f / (G * f * h)
+    wg = interpolate_weights(adaptive_table(), G)
+    kappa = k
+    for _ in range(60):
+        kappa = k / phase_velocity_ratio(wg, 2 * np.pi / (kappa * h), theta, phi)
+    A = assemble(Problem(shape, h, c, f, Pml(), W, adaptive=True))
+    n = np.array([np.sin(theta) * np.cos(phi), np.sin(theta) * np.sin(phi), np.cos(theta)])
+    z, y, x = np.meshgrid(*(np.arange(s) * h for s in shape[::-1]), indexing="ij")
+    u = np.exp(1j * kappa * (n[0] * x + n[1] * y + n[2] * z)).ravel()
+    Au = (A @ u).reshape(shape[::-1])[1:-1, 1:-1, 1:-1]
+    assert np.max(np.abs(Au)) <= 1e-10 * k ** 2
+    assert abs(kappa / k - 1) <= 1e-3  # the wave travels at the medium's speed to the table's accuracy
