@@ -309,7 +309,7 @@ def main():
                     help="skip the run with the coarse level's local solves in complex FP32 too")
     ap.add_argument("--no-approx", action="store_true",
                     help="skip the run with approximate fine local solves (complex-FP16 plane inverses)")
-    ap.add_argument("--serving-requests", type=int, default=24,
+    ap.add_argument("--serving-requests", type=int, default=12,
                     help="requests in the serving stream reported beside the main line (0: skip); a quarter "
                          "of them calibrate the capacity, the rest arrive as a Poisson stream")
     ap.add_argument("--serving-max-rhs", type=int, default=64, help="largest request of the serving stream")
