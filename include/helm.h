@@ -274,7 +274,9 @@ helm_status helm_graph_stats(const helm_handle_t* h, double out[2]);
  * product) wherever its two operand slots fit in LDS; 3 uses the
  * one-workgroup-per-box sweep built for two workgroups per compute unit
  * (complex FP64, groups of 32 right-hand sides, planes of up to 144 nodes)
- * wherever it exists, else as 1.  Planes whose operand does not fit in LDS
+ * wherever it exists, else as 1; 4 uses the pipelined sweep with eight
+ * producer waves beside the eight consumers (16 waves) wherever the pipelined
+ * sweep fits, else as 1.  Planes whose operand does not fit in LDS
  * (complex FP64 above 600 nodes, complex FP32 above 1200) keep it in global
  * memory under every policy.  Results agree to rounding.  Graphs captured
  * under one policy are not replayed under another. */

@@ -1749,7 +1749,7 @@ helm_status helm_set_graphs(helm_handle_t* H, int32_t enable) {
 }
 
 helm_status helm_set_sweep_policy(int32_t policy) {
-  if (policy < 0 || policy > 3) return fail(HELM_EINVAL, "sweep policy must be 0, 1, 2 or 3");
+  if (policy < 0 || policy > 4) return fail(HELM_EINVAL, "sweep policy must be 0, 1, 2, 3 or 4");
   set_sweep_policy(policy);
   return HELM_OK;
 }

@@ -694,8 +694,10 @@ __global__ void __launch_bounds__(256) k_to_half(const Sub* __restrict__ subs, i
 // the SIMDs.
 constexpr int PIPE_CONSUMERS = 8;
 
-template <typename T, int RG, int PF>
-__global__ void __launch_bounds__(64 * 12) k_oras_pipe(const Sub* __restrict__ subs, int nitems, int ngroups,
+// NW = 12 (four producer waves) or 16 (eight producer waves, for planes whose
+// operand build is slower than the product with four).
+template <typename T, int RG, int PF, int NW>
+__global__ void __launch_bounds__(64 * NW) k_oras_pipe(const Sub* __restrict__ subs, int nitems, int ngroups,
                                                        int nrhs, int bpmax, const cpx<T>* __restrict__ cpl,
                                                        const cpx<T>* __restrict__ sinv, const z64* __restrict__ u,
                                                        z64* __restrict__ z, const z64* __restrict__ add, int gnx,
@@ -825,20 +827,20 @@ int compute_units() {
   return per_device[dev];
 }
 
-template <typename T, int RG>
+template <typename T, int RG, int NW>
 void launch_pipe_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, const cpx<T>* cpl, const cpx<T>* sinv,
                    const z64* u, z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc, hipStream_t s) {
-  constexpr int PF = sizeof(T) == 4 ? 4 : 2;
+  constexpr int PF = sizeof(T) == 4 ? 4 : (NW == 16 ? 1 : 2);
   const size_t lds = 2 * (size_t)bpmax * lds_width<T>(RG) * sizeof(cpx<T>);
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_oras_pipe<T, RG, PF>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)k_oras_pipe<T, RG, PF, NW>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               160 * 1024);
     attr = true;
   }
   const int nitems = nsub * ngroups;
   const int grid = std::min(nitems, compute_units());
-  hipLaunchKernelGGL((k_oras_pipe<T, RG, PF>), dim3(grid), dim3(64 * 12), lds, s, subs, nitems, ngroups, nrhs, bpmax,
+  hipLaunchKernelGGL((k_oras_pipe<T, RG, PF, NW>), dim3(grid), dim3(64 * NW), lds, s, subs, nitems, ngroups, nrhs, bpmax,
                      cpl, sinv, u, z, add, gnx, gny, yloc);
 }
 
@@ -872,11 +874,14 @@ void launch_rg(int rg, int rounds, bool lowreg, const Sub* subs, int nsub, int n
     launch_gl_t<T>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx, gny, yloc, tglob, s);
     return;
   }
-  if (rounds == 0) {  // pipelined persistent sweep
-    if (rg == 16)
-      launch_pipe_t<T, 16>(subs, nsub, ngroups, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, s);
-    else
-      launch_pipe_t<T, 32>(subs, nsub, ngroups, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, s);
+  if (rounds == 0) {  // pipelined persistent sweep (lowreg: the 16-wave build)
+    if (rg == 16) {
+      if (lowreg) launch_pipe_t<T, 16, 16>(subs, nsub, ngroups, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, s);
+      else launch_pipe_t<T, 16, 12>(subs, nsub, ngroups, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, s);
+    } else {
+      if (lowreg) launch_pipe_t<T, 32, 16>(subs, nsub, ngroups, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, s);
+      else launch_pipe_t<T, 32, 12>(subs, nsub, ngroups, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, s);
+    }
     return;
   }
   switch (rg) {
@@ -934,11 +939,18 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
                  tbuf, s);
     return true;
   }
+  if (policy == 4) {  // forced: the 16-wave pipelined sweep with the widest group that fits
+    for (int cand = rgmax; cand >= 16; cand /= 2)
+      if (pipe_fits<T>(cand, bpmax)) {
+        launch_rg<T>(cand, 0, true, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, tbuf, s);
+        return true;
+      }
+  }
   const TuneKey key{(int)sizeof(T), bpmax, nsub, nrhs, gnx, gny, policy};
   // policy 1: one-item sweeps only; 2: the pipelined sweep wherever it fits
   bool any_pipe = false;
   for (int cand = 8; cand <= rgmax; cand *= 2) any_pipe = any_pipe || pipe_fits<T>(cand, bpmax);
-  const bool allow_pipe = policy != 1 && policy != 3, allow_item = policy != 2 || !any_pipe;
+  const bool allow_pipe = policy != 1 && policy != 3, allow_item = (policy != 2 && policy != 4) || !any_pipe;
   TuneVal tv{0, 0, false};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -970,7 +982,7 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
         if (waves == last_waves) continue;
         last_waves = waves;
         for (int lr = 0; lr < 2; ++lr) {
-          if (lr && !(rounds == r0 && lowreg_fits<T>(cand, bpmax))) continue;
+          if (lr && !(rounds == 0 || (rounds == r0 && lowreg_fits<T>(cand, bpmax)))) continue;
           float tot = 0.f;
           for (int rep = 0; rep < 2; ++rep) {
             (void)hipEventRecord(e0, s);
@@ -984,7 +996,8 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
           }
           if (verbose)
             std::fprintf(stderr, "helm:   candidate group %d %s %d waves%s: %.3f ms\n", cand,
-                         rounds == 0 ? "pipelined," : "", rounds == 0 ? 12 : waves, lr ? " (two per CU)" : "", tot);
+                         rounds == 0 ? "pipelined," : "", rounds == 0 ? (lr ? 16 : 12) : waves,
+                         lr && rounds != 0 ? " (two per CU)" : "", tot);
           if (tot < best) {
             best = tot;
             tv = {cand, rounds, lr != 0};
@@ -997,7 +1010,8 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
     if (verbose)
       std::fprintf(stderr, "helm: sweep tuned (fp%d, bp %d, %d boxes, %d rhs): group %d, %s %d waves%s, %.3f ms\n",
                    (int)sizeof(T) * 8, bpmax, nsub, nrhs, tv.rg, tv.rounds == 0 ? "pipelined," : "",
-                   tv.rounds == 0 ? 12 : (nmt + tv.rounds - 1) / tv.rounds, tv.lowreg ? " (two per CU)" : "", best);
+                   tv.rounds == 0 ? (tv.lowreg ? 16 : 12) : (nmt + tv.rounds - 1) / tv.rounds,
+                   tv.lowreg && tv.rounds != 0 ? " (two per CU)" : "", best);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = tv;
   }

@@ -251,7 +251,7 @@ class Request:
             pass
 
 
-SWEEP_POLICIES = {"auto": 0, "item": 1, "pipelined": 2, "two_per_cu": 3}
+SWEEP_POLICIES = {"auto": 0, "item": 1, "pipelined": 2, "two_per_cu": 3, "pipelined16": 4}
 
 
 def set_sweep_policy(policy):

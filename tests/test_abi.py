@@ -71,7 +71,7 @@ def test_process_wide_settings_reject_bad_values():
         with pytest.raises(helm.HelmError) as e:
             helm.set_row_tiling(bad)
         assert e.value.code == helm.HELM_EINVAL
-    assert helm.lib.helm_set_sweep_policy(4) == helm.HELM_EINVAL
+    assert helm.lib.helm_set_sweep_policy(5) == helm.HELM_EINVAL
     for bad in (1, 2, 12, 32):
         with pytest.raises(helm.HelmError):
             helm.set_lu_panel(bad)

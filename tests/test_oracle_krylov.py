@@ -70,3 +70,61 @@ def test_fgmres_maxit_reports_not_converged():
     A, b = _system()
     x, it, est, tru = fgmres(lambda v: A @ v, lambda v: v, b, 1e-14, 5, 3)
     assert it == 3 and tru > 1e-14 and abs(est - tru) <= 1e-10
+
+
+# ---- block FGMRES (one Krylov space shared by the right-hand sides) ----------
+
+def _dense_system(n=40, s=5, seed=11):
+    rng = np.random.default_rng(seed)
+    A = np.diag(np.linspace(1, 4, n)) + 0.4 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    B = rng.standard_normal((n, s)) + 1j * rng.standard_normal((n, s))
+    P = np.diag(1.0 / (1.0 + 0.05 * np.arange(n)))
+    return A, B, P
+
+
+def test_block_fgmres_solves_dense_systems_with_restarts():
+    from oracle.krylov import block_fgmres
+    A, B, P = _dense_system()
+    X, it, est, tru = block_fgmres(lambda v: A @ v, lambda v: P @ v, B, 1e-10, 3, 500)
+    ref = np.linalg.solve(A, B)
+    assert np.all(tru <= 1e-10) and np.all(it == it[0])
+    assert np.linalg.norm(X - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_block_fgmres_is_minimal_residual_over_the_block_krylov_space():
+    # after k block steps without restart, X minimises ||B - A X||_F over the
+    # block Krylov space P [R, (AP) R, ..., (AP)^(k-1) R] (explicit basis, QR, lstsq)
+    from oracle.krylov import block_fgmres
+    A, B, P = _dense_system(n=60, s=3, seed=2)
+    AP = A @ P
+    for k in (1, 2, 4):
+        X, it, est, tru = block_fgmres(lambda v: A @ v, lambda v: P @ v, B, 0.0, 10, k)
+        assert it[0] == k
+        K = [B]
+        for _ in range(k - 1):
+            K.append(AP @ K[-1])
+        Q, _ = np.linalg.qr(np.concatenate(K, axis=1))
+        Y = np.linalg.lstsq(AP @ Q, B, rcond=None)[0]
+        Xref = P @ (Q @ Y)
+        assert np.linalg.norm(X - Xref) <= 1e-8 * np.linalg.norm(Xref)
+        assert np.allclose(np.linalg.norm(B - A @ X, axis=0) / np.linalg.norm(B, axis=0), tru, rtol=1e-8)
+
+
+def test_block_fgmres_with_one_column_is_fgmres():
+    from oracle.krylov import block_fgmres
+    A, B, P = _dense_system(s=1, seed=7)
+    hb, hs = [], []
+    X, it, est, tru = block_fgmres(lambda v: A @ v, lambda v: P @ v, B, 1e-9, 5, 200, history=hb)
+    x, its, ests, trus = fgmres(lambda v: A @ v, lambda v: P @ v, B[:, 0], 1e-9, 5, 200, history=hs)
+    assert it[0] == its
+    assert np.linalg.norm(X[:, 0] - x) <= 1e-10 * np.linalg.norm(x)
+    assert np.allclose([h[0] for h in hb], hs, rtol=1e-7)
+
+
+def test_block_fgmres_zero_columns_and_maxit():
+    from oracle.krylov import block_fgmres
+    A, B, P = _dense_system(s=3, seed=3)
+    B[:, 1] = 0.0
+    X, it, est, tru = block_fgmres(lambda v: A @ v, lambda v: P @ v, B, 1e-12, 4, 3)
+    assert it[1] == 0 and not np.any(X[:, 1]) and tru[1] == 0
+    assert it[0] == it[2] == 3 and tru[0] > 1e-12
