@@ -62,14 +62,14 @@ def make_inputs(w):
     return c, b
 
 
-def gpu_solve(helm, w, c_dev, b_dev, precision, weights, timing=False, graphs=True):
+def gpu_solve(helm, w, c_dev, b_dev, precision, weights, timing=False, graphs=True, block=False):
     S = helm.Solver(w["shape"], H, c_dev, FREQ, (NPML, NPML, NPML, 0), weights=weights, parts=w["parts"],
                     overlap=2, levels=w["levels"], coarse_iters=10, precision=precision, restart=w["restart"])
     if timing:
         S.set_sweep_timing(True)
     if not graphs:
         S.set_graphs(False)
-    X, info = S.solve(b_dev, tol=w["tol"], maxit=400)
+    X, info = S.solve(b_dev, tol=w["tol"], maxit=400, block=block)
     if timing:
         info["sweeps"] = [S.sweep_stats(0), S.sweep_stats(w["levels"] - 1)]
         info["stencil"] = [S.stencil_stats(0), S.stencil_stats(1)]
@@ -305,8 +305,10 @@ def main():
     ap.add_argument("--workload", default="thrust192_mixed", choices=sorted(WORKLOADS))
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--no-single-local", action="store_true",
-                    help="skip the run with the coarse level's local solves in complex FP32 too")
+    ap.add_argument("--single-local", action="store_true",
+                    help="also run with the coarse level's local solves in complex FP32")
+    ap.add_argument("--no-block", action="store_true",
+                    help="skip the block FGMRES run (one Krylov space per batch of right-hand sides)")
     ap.add_argument("--no-approx", action="store_true",
                     help="skip the run with approximate fine local solves (complex-FP16 plane inverses)")
     ap.add_argument("--serving-requests", type=int, default=12,
@@ -408,7 +410,7 @@ def main():
                             "max_true_relres": float(i64["relres_true"].max())}
         out["mixed_vs_fp64_rel_l2_max"] = float(err.max().item())
         out["speedup_mixed_vs_fp64"] = value / out["fp64_form"]["rhs_per_s"]
-    if not args.no_single_local and w["precision"] == "mixed":
+    if args.single_local and w["precision"] == "mixed":
         # the coarse level's local solves in complex FP32 too (one step, same inputs)
         Xs, isl = gpu_solve(helm, w, c_dev, b_dev, "single_local", weights, timing=True, graphs=not args.no_graphs)
         tsl = isl["timings"]["setup"] + isl["timings"]["solve"]
@@ -439,6 +441,19 @@ def main():
         if "fp64_form" in out:
             out["approx_local_form"]["vs_fp64_rel_l2_max"] = float(rel_err(helm, torch, Xa, X64).max().item())
         del Xa
+    if not args.no_block:
+        # block FGMRES: the right-hand sides of each batch share one Krylov space (one step, same inputs)
+        Xb, ibl = gpu_solve(helm, w, c_dev, b_dev, w["precision"], weights, graphs=not args.no_graphs, block=True)
+        tbl = ibl["timings"]["setup"] + ibl["timings"]["solve"]
+        out["block_form"] = {
+            "rhs_per_s": nrhs / tbl, "solve_only_rhs_per_s": nrhs / ibl["timings"]["solve"],
+            "setup_s": ibl["timings"]["setup"], "solve_s": ibl["timings"]["solve"],
+            "block_iters_mean": float(ibl["iters"].mean()), "block_iters_max": int(ibl["iters"].max()),
+            "max_true_relres": float(ibl["relres_true"].max()),
+            "solve_roofline_frac": ibl["bound"]["seconds"] / ibl["timings"]["solve"]}
+        if "fp64_form" in out:
+            out["block_form"]["vs_fp64_rel_l2_max"] = float(rel_err(helm, torch, Xb, X64).max().item())
+        del Xb
     if "fp64_form" in out:
         del X64
     if args.serving_requests > 0:

@@ -154,7 +154,10 @@ helm_status helm_setup(const helm_grid_t* grid, const void* velocity, int32_t ve
                        const helm_pml_t* pml, const helm_weights_t* weights,
                        const helm_decomp_t* dec, helm_handle_t** out);
 
-enum { HELM_X0 = 1u /* X holds the initial guess on entry */ };
+enum {
+  HELM_X0 = 1u,   /* X holds the initial guess on entry */
+  HELM_BLOCK = 2u /* block FGMRES: one Krylov space shared by the right-hand sides of each batch */
+};
 
 /* Solve A X[r] = B[r], r < nrhs, by right-preconditioned flexible GMRES (the
  * Krylov solver of the domain-decomposition section) with the handle's one- or
@@ -166,6 +169,16 @@ enum { HELM_X0 = 1u /* X holds the initial guess on entry */ };
  *   B, X: complex128 [nrhs][nz][ny][nx], host or device memory, owned by the
  *         caller; X is written only on HELM_OK / HELM_NOT_CONVERGED.
  *   iters[nrhs], relres_est[nrhs], relres_true[nrhs]: host arrays (may be NULL).
+ * With HELM_BLOCK in flags the right-hand sides of each batch (at most 32;
+ * nrhs_chunk or the planner's choice) share one Krylov space (block FGMRES,
+ * the paper's many sources per frequency taken together): block j applies the
+ * preconditioner to the s basis vectors, orthogonalises A Z_j against the
+ * basis by two block classical Gram-Schmidt passes and factors it by two
+ * Cholesky-QR passes; the block least-squares problem is solved on the host
+ * and every right-hand side stops when all of its batch are at tol (iters
+ * counts block iterations).  Zero right-hand sides get X = 0 and no iteration;
+ * a numerically rank-deficient block at a (re)start makes the batch continue
+ * with one Krylov space per right-hand side.  Results depend on the batch.
  * Returns HELM_NOT_CONVERGED when some right-hand side reached maxit (its
  * residuals are reported), HELM_EINVAL for bad arguments or a handle with a
  * request in flight, HELM_ENOMEM when not even one right-hand side's Krylov

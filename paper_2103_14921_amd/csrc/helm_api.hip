@@ -6,6 +6,7 @@
 #include <array>
 #include <atomic>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -386,6 +387,7 @@ struct KrylovArrays {
 struct Workspace {
   int nr = 0;
   DevBuf b, x, w, V, Zv, q, t, cc, Vc, Zc, wc, ec, yl_f, tb_f, yl_c, tb_c, zpart, dpart, bn2, beta2, cols;
+  DevBuf bpart, bcoef;  // block FGMRES: block-dot partial sums, coefficient blocks [m + 1][32][32]
   KrylovArrays ko, kc;
 };
 
@@ -613,6 +615,7 @@ void plan(helm_handle* H) {
 size_t ws_bytes(const helm_handle* H, int nr) {
   const int m = H->dec.restart;
   size_t b = sizeof(z64) * (size_t)H->n * nr * (3 + (m + 1) + m);
+  b += sizeof(z64) * 1024 * (size_t)(m + 1) * (block_chunks(H->n) + 1);  // block FGMRES
   b += level_ws_bytes(H->fine, nr);
   b += KrylovArrays::bytes(m, nr);
   b += sizeof(z64) * RED_BLOCKS * 32 * (size_t)nr + sizeof(double) * RED_BLOCKS * (size_t)nr + 2 * sizeof(double) * nr;
@@ -690,6 +693,8 @@ void ensure_ws(helm_handle* H, int nr) {
   W.bn2.alloc(sizeof(double) * nr);
   W.beta2.alloc(sizeof(double) * nr);
   W.cols.alloc(sizeof(int) * nr);
+  W.bpart.alloc(sizeof(z64) * 1024 * (size_t)(m + 1) * block_chunks(H->n));
+  W.bcoef.alloc(sizeof(z64) * 1024 * (size_t)(m + 1));
   W.ko.alloc(m, nr);
   if (H->two_level()) {
     const int ci = H->dec.coarse_iters;
@@ -1150,13 +1155,15 @@ void compact_batch(helm_handle* H, int& nr, std::vector<int>& orig, void* X, int
 }
 
 // FGMRES on one batch; finished right-hand sides leave the batch at restarts.
-void fgmres_chunk(helm_handle* H, int nr, double tol, int maxit, bool x0, void* X, int r0, ChunkOut& out) {
+// orig0: the chunk index of each batch column (identity when null).
+void fgmres_chunk(helm_handle* H, int nr, double tol, int maxit, bool x0, void* X, int r0, ChunkOut& out,
+                  const std::vector<int>* orig0 = nullptr) {
   Workspace& W = H->ws;
   KrylovArrays& K = W.ko;
   const long long n = H->n;
   const int m = H->dec.restart;
   std::vector<int> orig(nr);
-  for (int c = 0; c < nr; ++c) orig[c] = c;
+  for (int c = 0; c < nr; ++c) orig[c] = orig0 ? (*orig0)[c] : c;
   // compaction stages three vectors of the batch in the basis storage
   static const bool no_compact = std::getenv("HELM_NO_COMPACT") != nullptr;
   const bool compact = !no_compact && m + 1 >= 3;
@@ -1196,6 +1203,318 @@ void fgmres_chunk(helm_handle* H, int nr, double tol, int maxit, bool x0, void* 
   std::vector<int> all(nr);
   for (int c = 0; c < nr; ++c) all[c] = c;
   emit_columns(H, nr, orig, all, X, r0, out);
+}
+
+// ---- block FGMRES: one Krylov space shared by the right-hand sides of a batch ----
+using cd = std::complex<double>;
+
+// The block least-squares problem min ||E_1 beta - Hbar Y||_F of block FGMRES.
+// Hbar is block upper Hessenberg ((m+1)s x ms, s subdiagonals); it is reduced
+// to triangular form column by column by Householder reflectors acting on the
+// s + 1 rows c .. c + s of column c, applied to G = E_1 beta as they are made.
+// After block column j the residual of right-hand side r is the norm of the
+// s rows of G below the triangle.
+struct BlockLS {
+  int s = 0, m = 0;
+  std::vector<std::vector<cd>> col;  // transformed columns, each (m+1)s rows
+  std::vector<std::vector<cd>> ref;  // reflector vectors, s + 1 entries
+  std::vector<double> tau;
+  std::vector<cd> G;                 // [(m+1)s][s]
+  void reset(int s_, int m_, const std::vector<cd>& beta) {  // beta: s x s, row-major
+    s = s_;
+    m = m_;
+    col.clear();
+    ref.clear();
+    tau.clear();
+    G.assign((size_t)(m + 1) * s * s, cd(0, 0));
+    for (int a = 0; a < s; ++a)
+      for (int b = 0; b < s; ++b) G[(size_t)a * s + b] = beta[(size_t)a * s + b];
+  }
+  void apply(int c, cd* y, int stride) const {  // y[r * stride], r = c .. c + s
+    const std::vector<cd>& v = ref[c];
+    cd d(0, 0);
+    for (int i = 0; i <= s; ++i) d += std::conj(v[i]) * y[(size_t)(c + i) * stride];
+    d *= tau[c];
+    for (int i = 0; i <= s; ++i) y[(size_t)(c + i) * stride] -= v[i] * d;
+  }
+  // Block column j: hcol[row * s + q], rows 0 .. (j+2)s - 1.
+  void add_block(int j, const std::vector<cd>& hcol) {
+    const int rows = (m + 1) * s;
+    for (int q = 0; q < s; ++q) {
+      const int c = j * s + q;
+      std::vector<cd> x(rows, cd(0, 0));
+      for (int r = 0; r < (j + 2) * s; ++r) x[r] = hcol[(size_t)r * s + q];
+      for (int cp = 0; cp < c; ++cp) apply(cp, x.data(), 1);
+      // reflector for rows c .. c + s: x -> alpha e_1
+      double nrm = 0;
+      for (int i = 0; i <= s; ++i) nrm += std::norm(x[c + i]);
+      nrm = std::sqrt(nrm);
+      std::vector<cd> v(s + 1, cd(0, 0));
+      double t = 0;
+      cd alpha(0, 0);
+      if (nrm > 0) {
+        const cd x0 = x[c];
+        const cd ph = std::abs(x0) > 0 ? x0 / std::abs(x0) : cd(1, 0);
+        alpha = -ph * nrm;
+        for (int i = 0; i <= s; ++i) v[i] = x[c + i];
+        v[0] -= alpha;
+        double vv = 0;
+        for (int i = 0; i <= s; ++i) vv += std::norm(v[i]);
+        t = vv > 0 ? 2.0 / vv : 0.0;
+      }
+      ref.push_back(v);
+      tau.push_back(t);
+      x[c] = t > 0 ? alpha : x[c];
+      for (int i = 1; i <= s; ++i) x[c + i] = cd(0, 0);
+      col.push_back(x);
+      for (int b = 0; b < s; ++b) apply(c, G.data() + b, s);
+    }
+  }
+  double residual(int j, int r) const {  // after add_block(j)
+    double acc = 0;
+    for (int row = (j + 1) * s; row < (j + 2) * s; ++row) acc += std::norm(G[(size_t)row * s + r]);
+    return std::sqrt(acc);
+  }
+  // Y (nb s x s, row-major) from the triangle of the first nb block columns.
+  std::vector<cd> solve(int nb) const {
+    const int K = nb * s;
+    std::vector<cd> Y((size_t)K * s, cd(0, 0));
+    for (int b = 0; b < s; ++b)
+      for (int i = K - 1; i >= 0; --i) {
+        cd acc = G[(size_t)i * s + b];
+        for (int k = i + 1; k < K; ++k) acc -= col[k][i] * Y[(size_t)k * s + b];
+        Y[(size_t)i * s + b] = acc / col[i][i];
+      }
+    return Y;
+  }
+};
+
+// Cholesky factor R (upper, G = R^H R) of an s x s Hermitian block G given as
+// [a][32 + b] complex128; false when a pivot is not positive beyond rounding
+// (the block is numerically rank deficient).  Rinv = R^{-1}.
+bool chol_upper(const std::vector<z64>& Gd, int s, std::vector<cd>& R, std::vector<cd>& Rinv) {
+  R.assign((size_t)s * s, cd(0, 0));
+  double gmax = 0;
+  for (int k = 0; k < s; ++k) gmax = std::max(gmax, Gd[(size_t)k * 32 + k].re);
+  for (int k = 0; k < s; ++k) {
+    double d = Gd[(size_t)k * 32 + k].re;
+    for (int i = 0; i < k; ++i) d -= std::norm(R[(size_t)i * s + k]);
+    if (!(d > 1e-28 * gmax) || !std::isfinite(d)) return false;
+    const double rk = std::sqrt(d);
+    R[(size_t)k * s + k] = rk;
+    for (int j = k + 1; j < s; ++j) {
+      cd g(Gd[(size_t)k * 32 + j].re, Gd[(size_t)k * 32 + j].im);
+      for (int i = 0; i < k; ++i) g -= std::conj(R[(size_t)i * s + k]) * R[(size_t)i * s + j];
+      R[(size_t)k * s + j] = g / rk;
+    }
+  }
+  Rinv.assign((size_t)s * s, cd(0, 0));
+  for (int j = 0; j < s; ++j) {  // column j of R^{-1}: back substitution on e_j
+    Rinv[(size_t)j * s + j] = 1.0 / R[(size_t)j * s + j];
+    for (int i = j - 1; i >= 0; --i) {
+      cd acc(0, 0);
+      for (int k = i + 1; k <= j; ++k) acc += R[(size_t)i * s + k] * Rinv[(size_t)k * s + j];
+      Rinv[(size_t)i * s + j] = -acc / R[(size_t)i * s + i];
+    }
+  }
+  return true;
+}
+
+std::vector<z64> to_padded(const std::vector<cd>& M, int s) {  // s x s row-major -> [32][32]
+  std::vector<z64> P(1024, mk(0.0, 0.0));
+  for (int a = 0; a < s; ++a)
+    for (int b = 0; b < s; ++b) P[(size_t)a * 32 + b] = mk(M[(size_t)a * s + b].real(), M[(size_t)a * s + b].imag());
+  return P;
+}
+
+// Q R = Win (n x s) by two Cholesky-QR passes: Qout = Win R1^{-1} R2^{-1},
+// R = R2 R1.  Win is overwritten.  False when the block is rank deficient.
+bool cholqr2(helm_handle* H, int s, z64* Win, z64* Qout, std::vector<cd>& R) {
+  Workspace& W = H->ws;
+  const long long n = H->n;
+  std::vector<cd> R1, R2, T;
+  std::vector<z64> Gd(1024);
+  for (int pass = 0; pass < 2; ++pass) {
+    z64* src = pass == 0 ? Win : Qout;
+    z64* dst = pass == 0 ? Qout : Win;
+    launch_block_dots(src, 0, 1, src, n, s, W.bpart.as<z64>(), W.bcoef.as<z64>(), H->stream);
+    HELM_CHECK_HIP(hipMemcpyAsync(Gd.data(), W.bcoef.p, sizeof(z64) * 1024, hipMemcpyDeviceToHost, H->stream));
+    HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+    std::vector<cd>& Rp = pass == 0 ? R1 : R2;
+    if (!chol_upper(Gd, s, Rp, T)) return false;
+    const std::vector<z64> Tp = to_padded(T, s);
+    HELM_CHECK_HIP(hipMemcpyAsync(W.bcoef.p, Tp.data(), sizeof(z64) * 1024, hipMemcpyHostToDevice, H->stream));
+    launch_block_gemm(src, 0, 1, W.bcoef.as<z64>(), n, s, 1.0, false, dst, H->stream);
+  }
+  launch_copy(Win, Qout, n * s, H->stream);  // the second pass wrote into Win
+  R.assign((size_t)s * s, cd(0, 0));
+  for (int a = 0; a < s; ++a)
+    for (int b = a; b < s; ++b)
+      for (int k = a; k <= b; ++k) R[(size_t)a * s + b] += R2[(size_t)a * s + k] * R1[(size_t)k * s + b];
+  return true;
+}
+
+std::vector<double> column_norms(helm_handle* H, const z64* v, int s) {
+  Workspace& W = H->ws;
+  std::vector<double> out(s);
+  launch_norm2(v, H->n, s, W.dpart.as<double>(), W.bn2.as<double>(), H->stream);
+  HELM_CHECK_HIP(hipMemcpyAsync(out.data(), W.bn2.p, sizeof(double) * s, hipMemcpyDeviceToHost, H->stream));
+  HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+  for (double& x : out) x = std::sqrt(x);
+  return out;
+}
+
+// Block FGMRES on the s columns of W.b (all nonzero), x in W.x (zero, or the
+// initial guess when x0): the oracle's block_fgmres step for step.  Returns
+// false, with W.x holding the iterate so far, when a block to orthonormalise at
+// a (re)start is rank deficient; iters and the residuals go to the per-column
+// vectors.
+bool block_fgmres_batch(helm_handle* H, int s, double tol, int maxit, bool x0, std::vector<int>& its,
+                        std::vector<double>& est, std::vector<double>& tru, int& k) {
+  Workspace& W = H->ws;
+  const long long n = H->n, vs = n * s;
+  const int m = H->dec.restart;
+  const std::vector<double> bn = column_norms(H, W.b.as<z64>(), s);
+  if (x0) fine_product(H, s, W.b.as<z64>(), W.x.as<z64>(), W.w.as<z64>());
+  else {
+    launch_fill(W.x.as<z64>(), vs, H->stream);
+    launch_copy(W.b.as<z64>(), W.w.as<z64>(), vs, H->stream);
+  }
+  std::vector<double> rn = column_norms(H, W.w.as<z64>(), s);
+  for (int r = 0; r < s; ++r) est[r] = rn[r] / bn[r];
+  BlockLS ls;
+  std::vector<z64> Cd((size_t)1024 * (m + 1));
+  while (true) {
+    bool done = true;
+    for (int r = 0; r < s; ++r) done = done && rn[r] <= tol * bn[r];
+    if (done || k >= maxit) break;
+    std::vector<cd> beta;
+    if (!cholqr2(H, s, W.w.as<z64>(), W.V.as<z64>(), beta)) return false;
+    ls.reset(s, m, beta);
+    int nb = 0;
+    for (int j = 0; j < m; ++j) {
+      z64* vj = W.V.as<z64>() + j * vs;
+      z64* zj = W.Zv.as<z64>() + j * vs;
+      precond(H, s, vj, zj);
+      fine_product(H, s, nullptr, zj, W.w.as<z64>());
+      double w0 = 0;
+      for (double x : column_norms(H, W.w.as<z64>(), s)) w0 += x * x;
+      w0 = std::sqrt(w0);
+      // two classical block Gram-Schmidt passes, coefficients accumulated
+      std::vector<cd> hcol((size_t)(j + 2) * s * s, cd(0, 0));
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_block_dots(W.V.as<z64>(), vs, j + 1, W.w.as<z64>(), n, s, W.bpart.as<z64>(), W.bcoef.as<z64>(),
+                          H->stream);
+        launch_block_gemm(W.V.as<z64>(), vs, j + 1, W.bcoef.as<z64>(), n, s, -1.0, true, W.w.as<z64>(), H->stream);
+        HELM_CHECK_HIP(hipMemcpyAsync(Cd.data(), W.bcoef.p, sizeof(z64) * 1024 * (j + 1), hipMemcpyDeviceToHost,
+                                      H->stream));
+        HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+        for (int i = 0; i <= j; ++i)
+          for (int a = 0; a < s; ++a)
+            for (int b = 0; b < s; ++b) {
+              const z64 c = Cd[(size_t)i * 1024 + a * 32 + b];
+              hcol[(size_t)(i * s + a) * s + b] += cd(c.re, c.im);
+            }
+      }
+      // W = V_{j+1} H_{j+1,j}; a rank-deficient W is a breakdown (its block stays zero)
+      std::vector<cd> Rn;
+      const bool full = j + 1 <= m && cholqr2(H, s, W.w.as<z64>(), W.V.as<z64>() + (j + 1) * vs, Rn);
+      double dmin = 0;
+      if (full) {
+        dmin = std::abs(Rn[0]);
+        for (int a = 0; a < s; ++a) {
+          dmin = std::min(dmin, std::abs(Rn[(size_t)a * s + a]));
+          for (int b = 0; b < s; ++b) hcol[(size_t)((j + 1) * s + a) * s + b] = Rn[(size_t)a * s + b];
+        }
+      }
+      ls.add_block(j, hcol);
+      ++k;
+      nb = j + 1;
+      bool conv = true;
+      for (int r = 0; r < s; ++r) {
+        est[r] = ls.residual(j, r) / bn[r];
+        conv = conv && est[r] <= tol;
+      }
+      const bool breakdown = !full || dmin <= 1e-14 * w0;
+      if (conv || breakdown || k >= maxit) break;
+    }
+    // X += sum_i Z_i Y_i, then the true residual
+    const std::vector<cd> Y = ls.solve(nb);
+    std::vector<z64> Yp((size_t)1024 * nb, mk(0.0, 0.0));
+    for (int i = 0; i < nb; ++i)
+      for (int a = 0; a < s; ++a)
+        for (int b = 0; b < s; ++b) {
+          const cd y = Y[(size_t)(i * s + a) * s + b];
+          Yp[(size_t)i * 1024 + a * 32 + b] = mk(y.real(), y.imag());
+        }
+    HELM_CHECK_HIP(hipMemcpyAsync(W.bcoef.p, Yp.data(), sizeof(z64) * Yp.size(), hipMemcpyHostToDevice, H->stream));
+    launch_block_gemm(W.Zv.as<z64>(), vs, nb, W.bcoef.as<z64>(), n, s, 1.0, true, W.x.as<z64>(), H->stream);
+    fine_product(H, s, W.b.as<z64>(), W.x.as<z64>(), W.w.as<z64>());
+    rn = column_norms(H, W.w.as<z64>(), s);
+  }
+  for (int r = 0; r < s; ++r) {
+    its[r] = k;
+    tru[r] = rn[r] / bn[r];
+  }
+  return true;
+}
+
+// Block FGMRES on a staged batch (W.b, and W.x when x0), results into out and X
+// (chunk offset r0).  Right-hand sides that are zero get X = 0 and no
+// iteration and stay out of the block; if a block to orthonormalise is rank
+// deficient, the batch continues from the current iterate with one Krylov
+// space per right-hand side (fgmres_chunk), its iterations added to the
+// block's.
+void block_chunk(helm_handle* H, int nr, double tol, int maxit, bool x0, void* X, int r0, ChunkOut& out) {
+  Workspace& W = H->ws;
+  const long long n = H->n;
+  const std::vector<double> bn = column_norms(H, W.b.as<z64>(), nr);
+  std::vector<int> keep, zero;
+  for (int c = 0; c < nr; ++c) (bn[c] > 0 ? keep : zero).push_back(c);
+  if (!zero.empty()) {
+    launch_fill(W.w.as<z64>(), n, H->stream);
+    for (int c : zero) {
+      HELM_CHECK_HIP(hipMemcpyAsync((char*)X + sizeof(z64) * (size_t)n * (r0 + c), W.w.p, sizeof(z64) * (size_t)n,
+                                    hipMemcpyDefault, H->stream));
+      out.it[c] = 0;
+      out.conv[c] = 1;
+      out.est[c] = 0;
+      out.tru[c] = 0;
+    }
+    HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+  }
+  const int s = (int)keep.size();
+  if (s == 0) return;
+  if (s < nr) {  // the nonzero columns to the front (the basis storage is free here)
+    z64* tmp = W.V.as<z64>();
+    HELM_CHECK_HIP(hipMemcpyAsync(W.cols.p, keep.data(), sizeof(int) * s, hipMemcpyHostToDevice, H->stream));
+    launch_gather_cols(W.b.as<z64>(), nr, W.cols.as<int>(), s, n, tmp, H->stream);
+    launch_gather_cols(W.x.as<z64>(), nr, W.cols.as<int>(), s, n, tmp + n * s, H->stream);
+    launch_copy(tmp, W.b.as<z64>(), n * s, H->stream);
+    launch_copy(tmp + n * s, W.x.as<z64>(), n * s, H->stream);
+  }
+  set_batch(H, s);
+  std::vector<int> its(s, 0);
+  std::vector<double> est(s, 0.0), tru(s, 0.0);
+  int k = 0;
+  if (!block_fgmres_batch(H, s, tol, maxit, x0, its, est, tru, k)) {
+    fgmres_chunk(H, s, tol, std::max(maxit - k, 0), true, X, r0, out, &keep);
+    for (int c : keep) out.it[c] += k;
+    return;
+  }
+  // solutions field-major to X at their chunk index
+  launch_to_field_major(W.x.as<z64>(), W.w.as<z64>(), n, s, H->stream);
+  for (int q = 0; q < s; ++q)
+    HELM_CHECK_HIP(hipMemcpyAsync((char*)X + sizeof(z64) * (size_t)n * (r0 + keep[q]), W.w.as<z64>() + n * q,
+                                  sizeof(z64) * (size_t)n, hipMemcpyDefault, H->stream));
+  HELM_CHECK_HIP(hipStreamSynchronize(H->stream));
+  for (int q = 0; q < s; ++q) {
+    const int c = keep[q];
+    out.it[c] = its[q];
+    out.est[c] = est[q];
+    out.tru[c] = tru[q];
+    out.conv[c] = tru[q] <= tol ? 1 : 0;
+  }
 }
 
 struct Timer {
@@ -1392,10 +1711,10 @@ void setup_impl(helm_handle* H, const void* velocity, int vel_kind) {
   HELM_CHECK_HIP(hipGetLastError());
 }
 
-int choose_chunk(helm_handle* H, int nrhs) {
+int choose_chunk(helm_handle* H, int nrhs, bool block) {
   int nr = H->dec.nrhs_chunk > 0 ? H->dec.nrhs_chunk : nrhs;
   nr = std::min(nr, nrhs);
-  nr = std::min(nr, 256);
+  nr = std::min(nr, block ? 32 : 256);  // a block Krylov space spans at most 32 right-hand sides
   if (H->ws.nr >= nr) return nr;  // already allocated
   const size_t held = H->ws.nr > 0 ? ws_bytes(H, H->ws.nr) : 0;
   const size_t avail = budget_bytes() + held;
@@ -1497,7 +1816,8 @@ helm_status solve_impl(helm_handle* H, int32_t nrhs, const void* B, void* X, dou
     if (!H || !B || !X || nrhs < 0 || !(tol >= 0) || maxit < 0) throw HelmError(HELM_EINVAL, "bad solve arguments");
     if (nrhs == 0) return HELM_OK;
     const long long n = H->n;
-    const int nr_max = choose_chunk(H, nrhs);
+    const bool block = (flags & HELM_BLOCK) != 0;
+    const int nr_max = choose_chunk(H, nrhs, block);
     ensure_ws(H, nr_max);
     Workspace& W = H->ws;
     H->work_solve = WorkBound{};
@@ -1529,7 +1849,8 @@ helm_status solve_impl(helm_handle* H, int32_t nrhs, const void* B, void* X, dou
       co.conv.assign(nr, 0);
       co.est.assign(nr, 0.0);
       co.tru.assign(nr, 0.0);
-      fgmres_chunk(H, nr, tol, maxit, x0, X, r0, co);
+      if (block) block_chunk(H, nr, tol, maxit, x0, X, r0, co);
+      else fgmres_chunk(H, nr, tol, maxit, x0, X, r0, co);
       for (int r = 0; r < nr; ++r) {
         it_all[r0 + r] = co.it[r];
         conv_all[r0 + r] = co.conv[r];
@@ -1619,7 +1940,8 @@ size_t helm_resident_bytes(const helm_handle_t* H) {
     for (const DevBuf* d : {&L->d_subs, &L->aloc, &L->sinv, &L->E, &L->cpl, &L->sinv16, &L->sexp}) b += d->bytes;
   const Workspace& W = H->ws;
   for (const DevBuf* d : {&W.b, &W.x, &W.w, &W.V, &W.Zv, &W.q, &W.t, &W.cc, &W.Vc, &W.Zc, &W.wc, &W.ec, &W.yl_f,
-                          &W.tb_f, &W.yl_c, &W.tb_c, &W.zpart, &W.dpart, &W.bn2, &W.beta2, &W.cols})
+                          &W.tb_f, &W.yl_c, &W.tb_c, &W.zpart, &W.dpart, &W.bn2, &W.beta2, &W.cols, &W.bpart,
+                          &W.bcoef})
     b += d->bytes;
   for (const KrylovArrays* k : {&W.ko, &W.kc})
     for (const DevBuf* d : {&k->Rm, &k->g, &k->cs, &k->sn, &k->y, &k->h, &k->h2, &k->nrm2, &k->w0, &k->w1, &k->bnorm,

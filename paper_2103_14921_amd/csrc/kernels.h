@@ -169,6 +169,18 @@ void launch_update(const z64* Z, long long zstride, int nv, const z64* y, z64* x
 // a = a - b
 void launch_sub(z64* a, const z64* b, long long n, hipStream_t s);
 
+// Block Krylov kernels (block FGMRES): block vectors are batches of s <= 32
+// right-hand sides, node-major; coefficient blocks [block][32][32] (padded).
+// Chunks of the two-stage block reductions for vectors of len nodes.
+int block_chunks(long long len);
+// C[i] = V_i^H W, i < nv (V_i = V + i * vstride); partial holds
+// block_chunks(len) * nv * 1024 elements.  Deterministic.
+void launch_block_dots(const z64* V, long long vstride, int nv, const z64* W, long long len, int s, z64* partial,
+                       z64* C, hipStream_t st);
+// out = (accumulate ? out : 0) + sign sum_{i < nv} In_i C[i]  (In_i = In + i * istride; out aliases no In_i)
+void launch_block_gemm(const z64* In, long long istride, int nv, const z64* C, long long len, int s, double sign,
+                       bool accumulate, z64* out, hipStream_t st);
+
 // Per-right-hand-side GMRES state (device arrays of length nrhs unless noted).
 struct KrylovState {
   int m, nrhs;

@@ -603,3 +603,145 @@ void launch_givens(KrylovState st, int j, double tol, int maxit, int fixed, hipS
 void launch_backsolve(KrylovState st, hipStream_t s) {
   hipLaunchKernelGGL(k_backsolve, dim3((unsigned)ceil_div(st.nrhs, 64)), dim3(64), 0, s, st);
 }
+
+// ---- block Krylov kernels (block FGMRES) ------------------------------------
+//
+// Block vectors are batches of s <= 32 right-hand sides, node-major
+// (element (node, a) at node * s + a).  Small s x s coefficient blocks are
+// stored padded, [block][32][32].
+
+namespace {
+
+constexpr int BK_TILE = 32;  // nodes per LDS tile
+
+// partial[ch][i][a][b] = sum over the nodes of chunk ch of conj(V_i[node][a]) W[node][b].
+// 256 threads: four groups of 64, group g takes the tile's nodes g, g + 4, ...;
+// lane l of a group owns the 4 x 4 block a = 4 (l / 8) + x, b = 4 (l % 8) + y.
+__global__ void __launch_bounds__(256) k_bdot(const z64* __restrict__ V, long long vstride, const z64* __restrict__ W,
+                                              long long len, int s, z64* __restrict__ partial) {
+  __shared__ z64 sv[BK_TILE][33], sw[BK_TILE][33];
+  __shared__ z64 red[32][33];
+  const int i = blockIdx.y, ch = blockIdx.x, nch = gridDim.x;
+  const z64* Vi = V + i * vstride;
+  const long long per = ceil_div(len, nch);
+  const long long n0 = ch * per, n1 = min(len, n0 + per);
+  const int t = threadIdx.x, g = t >> 6, l = t & 63, a0 = 4 * (l >> 3), b0 = 4 * (l & 7);
+  z64 acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = mk(0.0, 0.0);
+  for (long long base = n0; base < n1; base += BK_TILE) {
+    const int nt = (int)min((long long)BK_TILE, n1 - base);
+    for (int e = t; e < BK_TILE * 32; e += 256) {
+      const int q = e >> 5, c = e & 31;
+      const bool in = q < nt && c < s;
+      sv[q][c] = in ? Vi[(base + q) * s + c] : mk(0.0, 0.0);
+      sw[q][c] = in ? W[(base + q) * s + c] : mk(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int q = g; q < BK_TILE; q += 4) {
+      z64 va[4], wb[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) va[x] = sv[q][a0 + x];
+#pragma unroll
+      for (int y = 0; y < 4; ++y) wb[y] = sw[q][b0 + y];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) cdot_acc(acc[x][y], va[x], wb[y]);
+    }
+    __syncthreads();
+  }
+  // sum the four groups in a fixed order: 0 + 1 + 2 + 3
+  for (int gg = 1; gg < 4; ++gg) {
+    if (g == gg)
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) red[a0 + x][b0 + y] = acc[x][y];
+    __syncthreads();
+    if (g == 0)
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] += red[a0 + x][b0 + y];
+    __syncthreads();
+  }
+  if (g == 0) {
+    z64* out = partial + ((long long)ch * gridDim.y + i) * 1024;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) out[(a0 + x) * 32 + b0 + y] = acc[x][y];
+  }
+}
+
+// C[i][a][b] = sum over chunks, in chunk order, of partial[ch][i][a][b].
+__global__ void k_bdot_reduce(const z64* __restrict__ partial, int nch, int nv, z64* __restrict__ C) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nv * 1024) return;
+  z64 acc = mk(0.0, 0.0);
+  for (int ch = 0; ch < nch; ++ch) acc += partial[(long long)ch * nv * 1024 + e];
+  C[e] = acc;
+}
+
+// out[node][b] = (accumulate ? out[node][b] : 0) + sign sum_{i < nv} sum_{a < s} In_i[node][a] C[i][a][b].
+// 256 threads per tile of 32 nodes: thread t owns node t / 8 and the four columns b = 4 (t % 8) + y.
+__global__ void __launch_bounds__(256) k_bgemm(const z64* __restrict__ In, long long istride, int nv,
+                                               const z64* __restrict__ C, long long len, int s, double sign,
+                                               int accumulate, z64* __restrict__ out) {
+  __shared__ z64 si[BK_TILE][33], cs[32][33];
+  const long long base = (long long)blockIdx.x * BK_TILE;
+  const int t = threadIdx.x, nl = t >> 3, b0 = 4 * (t & 7);
+  const long long node = base + nl;
+  const int nt = (int)min((long long)BK_TILE, len - base);
+  z64 acc[4];
+#pragma unroll
+  for (int y = 0; y < 4; ++y) acc[y] = mk(0.0, 0.0);
+  for (int i = 0; i < nv; ++i) {
+    const z64* Ii = In + i * istride;
+    for (int e = t; e < BK_TILE * 32; e += 256) {
+      const int q = e >> 5, c = e & 31;
+      si[q][c] = (q < nt && c < s) ? Ii[(base + q) * s + c] : mk(0.0, 0.0);
+      cs[q][c] = C[(long long)i * 1024 + e];
+    }
+    __syncthreads();
+    for (int a = 0; a < s; ++a) {
+      const z64 v = si[nl][a];
+#pragma unroll
+      for (int y = 0; y < 4; ++y) cfma(acc[y], v, cs[a][b0 + y]);
+    }
+    __syncthreads();
+  }
+  if (nl < nt) {
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int b = b0 + y;
+      if (b >= s) continue;
+      z64* o = out + node * s + b;
+      const z64 d = mk(sign * acc[y].re, sign * acc[y].im);
+      *o = accumulate ? *o + d : d;
+    }
+  }
+}
+
+}  // namespace
+
+int block_chunks(long long len) { return (int)std::min<long long>(std::max<long long>(ceil_div(len, 8192), 1), 240); }
+
+void launch_block_dots(const z64* V, long long vstride, int nv, const z64* W, long long len, int s, z64* partial,
+                       z64* C, hipStream_t st) {
+  const int nch = block_chunks(len);
+  account(16.0 * (nv + 1) * len * s, 8.0 * nv * len * (double)s * s);
+  hipLaunchKernelGGL(k_bdot, dim3(nch, nv), dim3(256), 0, st, V, vstride, W, len, s, partial);
+  hipLaunchKernelGGL(k_bdot_reduce, dim3((unsigned)ceil_div((long long)nv * 1024, 256)), dim3(256), 0, st, partial, nch,
+                     nv, C);
+}
+
+void launch_block_gemm(const z64* In, long long istride, int nv, const z64* C, long long len, int s, double sign,
+                       bool accumulate, z64* out, hipStream_t st) {
+  account(16.0 * (nv + (accumulate ? 2 : 1)) * len * s, 8.0 * nv * len * (double)s * s);
+  hipLaunchKernelGGL(k_bgemm, dim3((unsigned)ceil_div(len, BK_TILE)), dim3(256), 0, st, In, istride, nv, C, len, s, sign,
+                     accumulate ? 1 : 0, out);
+}

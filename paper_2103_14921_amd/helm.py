@@ -34,6 +34,7 @@ def _precision(name):
     except KeyError:
         raise ValueError(f"precision must be one of {sorted(PRECISIONS)}, not {name!r}") from None
 HELM_X0 = 1
+HELM_BLOCK = 2
 
 EXPORTS = [
     "helm_fit_weights", "helm_setup", "helm_solve", "helm_footprint", "helm_workspace_bytes", "helm_resident_bytes",
@@ -331,11 +332,13 @@ class Solver:
         except Exception:
             pass
 
-    def solve(self, B, tol=1e-8, maxit=500, X0=None):
-        """Solve A X = B, B of shape [nrhs][nz][ny][nx] (or [nrhs][n]); returns (X, info)."""
+    def solve(self, B, tol=1e-8, maxit=500, X0=None, block=False):
+        """Solve A X = B, B of shape [nrhs][nz][ny][nx] (or [nrhs][n]); returns (X, info).
+
+        block=True: block FGMRES, one Krylov space per batch of at most 32 right-hand sides."""
         nrhs = B.shape[0]
         X = _empty_like_kind(B, tuple(B.shape)) if X0 is None else X0
-        flags = HELM_X0 if X0 is not None else 0
+        flags = (HELM_X0 if X0 is not None else 0) | (HELM_BLOCK if block else 0)
         its = np.zeros(nrhs, np.int32)
         est = np.zeros(nrhs)
         tru = np.zeros(nrhs)
