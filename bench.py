@@ -12,10 +12,13 @@ top), 12 x 12 x 12 subdomains of 16^3 with overlap 2, two-level ORAS with the
 coarse grid at 2h, 64 point sources on an 8 x 8 grid at depth index 4; the
 fine level's local factors and solves in complex FP32, everything else
 (FGMRES, orthogonalisation, Givens, residuals and the whole coarse level) FP64
-("mixed").  The same workload is also run in plain FP64, and the error of the
-mixed solution against it is reported, and once with the coarse level's local
-factors and solves in complex FP32 as well ("single_local"; the coarse GMRES
-stays FP64), reported beside the headline.
+("mixed").  Beside the headline, one step of each comparison form on the same
+inputs: plain FP64 (and the error of the mixed solution against it), the
+oracle's CPU baseline, approximate fine local solves (complex-FP16 plane
+inverses), block FGMRES (one Krylov space per batch), optionally the coarse
+local solves in complex FP32 too ("single_local"), and a Poisson serving
+stream.  These legs run in that order while their estimated cost fits
+--time-budget (default 540 s of wall clock); a skipped leg is listed.
 
 Prints one JSON line.
 """
@@ -28,6 +31,8 @@ import sys
 import time
 
 import numpy as np
+
+T_START = time.perf_counter()
 
 WORKLOADS = {
     # name: (shape, parts, n_src grid, restart)
@@ -256,10 +261,11 @@ def cpu_model():
     return "unknown"
 
 
-def serving_phase(n_requests, max_rhs=64, seed=4):
+def serving_phase(n_requests, max_rhs=64, seed=4, deadline=None):
     """Poisson stream over the seeded serving catalogue (grids 64^3..160^3, 2-8 Hz, 1-64 sources,
     two-level ORAS with 16^3 boxes, complex-FP32 local solves, tol 1e-6) at 0.8 x the capacity measured on a
-    burst of the first requests; returns p50/p99 latency and RHS/s."""
+    burst of the first requests; returns p50/p99 latency and RHS/s.  No request of the stream is submitted
+    after ``deadline`` (time.perf_counter())."""
     import inputs
     from paper_2103_14921_amd.serving import ProblemSpec, Server, run_poisson
     cat = inputs.serving_catalogue(seed=seed)
@@ -285,13 +291,14 @@ def serving_phase(n_requests, max_rhs=64, seed=4):
         print(f"[bench] serving calibration {i + 1}/{ncal} done", file=sys.stderr, flush=True)
     capacity = ncal / (time.perf_counter() - t0)  # requests/s with set-ups included
     srv.stats.latencies.clear()
-    out = run_poisson(srv, reqs[ncal:], rate_hz=0.8 * capacity, seed=seed,
+    out = run_poisson(srv, reqs[ncal:], rate_hz=0.8 * capacity, seed=seed, deadline=deadline,
                       progress=lambda i, n: print(f"[bench] serving request {i}/{n} done", file=sys.stderr,
                                                   flush=True))
     st = srv.stats
     srv.close()
     worst = max(float(r["relres_true"].max()) for r in out["results"])
-    return {"requests": out["requests"], "calibration_requests": ncal, "rate_hz": 0.8 * capacity,
+    return {"requests": out["requests"], "requests_planned": len(reqs) - ncal, "calibration_requests": ncal,
+            "rate_hz": 0.8 * capacity,
             "p50_s": out["p50_s"], "p99_s": out["p99_s"], "mean_s": out["mean_s"], "rhs_per_s": out["rhs_per_s"],
             "rhs": out["rhs"], "elapsed_s": out["elapsed_s"], "setups": st.setups, "evictions": st.evictions,
             "batches": st.batches, "retries": st.retries, "max_true_relres": worst}
@@ -316,6 +323,10 @@ def main():
                          "of them calibrate the capacity, the rest arrive as a Poisson stream")
     ap.add_argument("--serving-max-rhs", type=int, default=64, help="largest request of the serving stream")
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly (no captured iterations)")
+    ap.add_argument("--time-budget", type=float, default=540.0,
+                    help="wall-clock seconds (from start) the whole run aims to stay within: after the timed "
+                         "steps, each comparison leg runs only if its estimated cost still fits (skipped legs "
+                         "are listed), and the serving stream submits no request past the budget")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -400,7 +411,19 @@ def main():
     ach = info["factor_flops"] / max(t_fact, 1e-9) / 1e12
     out["roofline_factorisation"] = {"bound": "mfma", "achieved": ach, "peak": PEAK[fine_dtype], "unit": "TFLOP/s",
                                      "frac": ach / PEAK[fine_dtype], "flops": info["factor_flops"], "seconds": t_fact}
-    if not args.no_fp64 and w["precision"] != "fp64":
+    # comparison legs, most important first, each only while its estimated cost fits the time budget
+    t_step = T / args.steps
+    skipped = {}
+
+    def fits(name, est_s):
+        left = args.time_budget - (time.perf_counter() - T_START)
+        if est_s <= left:
+            return True
+        skipped[name] = f"time budget: needs about {est_s:.0f} s, {max(left, 0.0):.0f} s left"
+        print(f"[bench] skipping {name} ({skipped[name]})", file=sys.stderr, flush=True)
+        return False
+
+    if not args.no_fp64 and w["precision"] != "fp64" and fits("fp64_form", 1.9 * t_step):
         X64, i64 = gpu_solve(helm, w, c_dev, b_dev, "fp64", weights, graphs=not args.no_graphs)
         t64 = i64["timings"]["setup"] + i64["timings"]["solve"]
         err = rel_err(helm, torch, X, X64)
@@ -410,7 +433,41 @@ def main():
                             "max_true_relres": float(i64["relres_true"].max())}
         out["mixed_vs_fp64_rel_l2_max"] = float(err.max().item())
         out["speedup_mixed_vs_fp64"] = value / out["fp64_form"]["rhs_per_s"]
-    if args.single_local and w["precision"] == "mixed":
+        print("[bench] fp64 form done", file=sys.stderr, flush=True)
+    if not args.no_cpu:
+        # the oracle on the host cores (a bounded sample, about 10-30 s); always run when asked for
+        out["cpu_baseline"] = cpu_baseline(w, info["iters"], nrhs)
+        print("[bench] cpu baseline done", file=sys.stderr, flush=True)
+    if not args.no_approx and w["precision"] == "mixed" and fits("approx_local_form", 1.2 * t_step):
+        # approximate fine local solves (complex-FP16 plane inverses on FP16 matrix cores; one step)
+        Xa, iap = gpu_solve(helm, w, c_dev, b_dev, "approx_local", weights, timing=True, graphs=not args.no_graphs)
+        tap = iap["timings"]["setup"] + iap["timings"]["solve"]
+        out["approx_local_form"] = {
+            "rhs_per_s": nrhs / tap, "solve_only_rhs_per_s": nrhs / iap["timings"]["solve"],
+            "setup_s": iap["timings"]["setup"], "solve_s": iap["timings"]["solve"],
+            "iters_mean": float(iap["iters"].mean()), "iters_max": int(iap["iters"].max()),
+            "max_true_relres": float(iap["relres_true"].max()),
+            "fine_sweep": roofline_entry(iap["sweeps"][0], "c32"),
+            "solve_roofline_frac": iap["bound"]["seconds"] / iap["timings"]["solve"]}
+        if "fp64_form" in out:
+            out["approx_local_form"]["vs_fp64_rel_l2_max"] = float(rel_err(helm, torch, Xa, X64).max().item())
+        del Xa
+        print("[bench] approx_local form done", file=sys.stderr, flush=True)
+    if not args.no_block and fits("block_form", 1.5 * t_step):
+        # block FGMRES: the right-hand sides of each batch share one Krylov space (one step, same inputs)
+        Xb, ibl = gpu_solve(helm, w, c_dev, b_dev, w["precision"], weights, graphs=not args.no_graphs, block=True)
+        tbl = ibl["timings"]["setup"] + ibl["timings"]["solve"]
+        out["block_form"] = {
+            "rhs_per_s": nrhs / tbl, "solve_only_rhs_per_s": nrhs / ibl["timings"]["solve"],
+            "setup_s": ibl["timings"]["setup"], "solve_s": ibl["timings"]["solve"],
+            "block_iters_mean": float(ibl["iters"].mean()), "block_iters_max": int(ibl["iters"].max()),
+            "max_true_relres": float(ibl["relres_true"].max()),
+            "solve_roofline_frac": ibl["bound"]["seconds"] / ibl["timings"]["solve"]}
+        if "fp64_form" in out:
+            out["block_form"]["vs_fp64_rel_l2_max"] = float(rel_err(helm, torch, Xb, X64).max().item())
+        del Xb
+        print("[bench] block form done", file=sys.stderr, flush=True)
+    if args.single_local and w["precision"] == "mixed" and fits("single_local_form", 1.2 * t_step):
         # the coarse level's local solves in complex FP32 too (one step, same inputs)
         Xs, isl = gpu_solve(helm, w, c_dev, b_dev, "single_local", weights, timing=True, graphs=not args.no_graphs)
         tsl = isl["timings"]["setup"] + isl["timings"]["solve"]
@@ -427,42 +484,18 @@ def main():
             err = rel_err(helm, torch, Xs, X64)
             out["single_local_form"]["vs_fp64_rel_l2_max"] = float(err.max().item())
         del Xs
-    if not args.no_approx and w["precision"] == "mixed":
-        # approximate fine local solves (complex-FP16 plane inverses on FP16 matrix cores; one step)
-        Xa, iap = gpu_solve(helm, w, c_dev, b_dev, "approx_local", weights, timing=True, graphs=not args.no_graphs)
-        tap = iap["timings"]["setup"] + iap["timings"]["solve"]
-        out["approx_local_form"] = {
-            "rhs_per_s": nrhs / tap, "solve_only_rhs_per_s": nrhs / iap["timings"]["solve"],
-            "setup_s": iap["timings"]["setup"], "solve_s": iap["timings"]["solve"],
-            "iters_mean": float(iap["iters"].mean()), "iters_max": int(iap["iters"].max()),
-            "max_true_relres": float(iap["relres_true"].max()),
-            "fine_sweep": roofline_entry(iap["sweeps"][0], "c32"),
-            "solve_roofline_frac": iap["bound"]["seconds"] / iap["timings"]["solve"]}
-        if "fp64_form" in out:
-            out["approx_local_form"]["vs_fp64_rel_l2_max"] = float(rel_err(helm, torch, Xa, X64).max().item())
-        del Xa
-    if not args.no_block:
-        # block FGMRES: the right-hand sides of each batch share one Krylov space (one step, same inputs)
-        Xb, ibl = gpu_solve(helm, w, c_dev, b_dev, w["precision"], weights, graphs=not args.no_graphs, block=True)
-        tbl = ibl["timings"]["setup"] + ibl["timings"]["solve"]
-        out["block_form"] = {
-            "rhs_per_s": nrhs / tbl, "solve_only_rhs_per_s": nrhs / ibl["timings"]["solve"],
-            "setup_s": ibl["timings"]["setup"], "solve_s": ibl["timings"]["solve"],
-            "block_iters_mean": float(ibl["iters"].mean()), "block_iters_max": int(ibl["iters"].max()),
-            "max_true_relres": float(ibl["relres_true"].max()),
-            "solve_roofline_frac": ibl["bound"]["seconds"] / ibl["timings"]["solve"]}
-        if "fp64_form" in out:
-            out["block_form"]["vs_fp64_rel_l2_max"] = float(rel_err(helm, torch, Xb, X64).max().item())
-        del Xb
     if "fp64_form" in out:
         del X64
-    if args.serving_requests > 0:
+    # the serving stream needs its calibration burst (about 30 s) and room for a few requests
+    if args.serving_requests > 0 and fits("serving", 60.0):
         del X
         torch.cuda.empty_cache()
         helm.trim_cache()
-        out["serving"] = serving_phase(args.serving_requests, args.serving_max_rhs)
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, info["iters"], nrhs)
+        out["serving"] = serving_phase(args.serving_requests, args.serving_max_rhs,
+                                       deadline=T_START + args.time_budget - 15.0)
+    if skipped:
+        out["skipped_legs"] = skipped
+    out["bench_wall_s"] = time.perf_counter() - T_START
     print(json.dumps(out))
 
 

@@ -393,9 +393,11 @@ class Server:
                 self._cv.notify_all()
 
 
-def run_poisson(server, requests, rate_hz, seed=4, progress=None):
+def run_poisson(server, requests, rate_hz, seed=4, progress=None, deadline=None):
     """Submit (spec, B, tol) requests with Poisson arrivals of the given rate; wait for all.
 
+    ``deadline`` (a time.perf_counter() value): submit no request whose arrival
+    falls after it (those already submitted still complete).
     Returns dict(elapsed_s, rhs, rhs_per_s, latency percentiles, results).
     """
     rng = np.random.default_rng(seed)
@@ -410,10 +412,14 @@ def run_poisson(server, requests, rate_hz, seed=4, progress=None):
         with lock:
             done[0] += 1
             if progress:
-                progress(done[0], len(requests))
+                progress(done[0], n_sub)
 
-    for (spec, B, tol), gap in zip(requests, gaps):
+    n_sub = len(requests)
+    for k, ((spec, B, tol), gap) in enumerate(zip(requests, gaps)):
         t_next += gap
+        if deadline is not None and t_next > deadline:
+            n_sub = k
+            break
         dt = t_next - time.perf_counter()
         if dt > 0:
             time.sleep(dt)
