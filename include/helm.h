@@ -289,19 +289,27 @@ helm_status helm_graph_stats(const helm_handle_t* h, double out[2]);
  * (complex FP64, groups of 32 right-hand sides, planes of up to 144 nodes)
  * wherever it exists, else as 1; 4 uses the pipelined sweep with eight
  * producer waves beside the eight consumers (16 waves) wherever the pipelined
- * sweep fits, else as 1.  Planes whose operand does not fit in LDS
+ * sweep fits, else as 1; 5 uses the paired sweep (two right-hand-side groups of
+ * one box per workgroup, each on half of its waves, so that both stream the
+ * box's factors in step and the second read hits L2) wherever the batch
+ * splits into an even number of groups whose two operands fit in LDS, else
+ * as 0.  Planes whose operand does not fit in LDS
  * (complex FP64 above 600 nodes, complex FP32 above 1200) keep it in global
  * memory under every policy.  Results agree to rounding.  Graphs captured
  * under one policy are not replayed under another. */
 helm_status helm_set_sweep_policy(int32_t policy);
 
-/* Process-wide tiling of the 27-point products (the fine operator of eq. eq1
- * and the coarse operator E of eq. 2lvl) for batches of 4 or
- * more right-hand sides: each thread computes nodes_per_thread consecutive
- * nodes of a grid row (2, 4 or 8); 0 (default) times the three once per grid
- * and batch size and keeps the fastest.  Every tiling sums the 27 terms of an
- * output in the same order, so results are bitwise identical.  Returns
- * HELM_EINVAL for any other value. */
+/* Process-wide schedule of the 27-point products (the fine operator of eq. eq1
+ * and the coarse operator E of eq. 2lvl) for batches of 4 or more right-hand
+ * sides.  2, 4 or 8: row tiles, each thread computing that many consecutive
+ * nodes of a grid row; HELM_TILE_MARCH | n (n = 2 or 3): plane-marching, each
+ * thread keeping n nodes of a row and marching through a chunk of planes, for
+ * batches of 16 k right-hand sides (other batches then take row tiles of 4);
+ * 0 (default) times every admissible schedule once per grid and batch size and
+ * keeps the fastest.  Every schedule sums the 27 terms of an output in the
+ * same order from the same coefficients, so results are bitwise identical.
+ * Returns HELM_EINVAL for any other value. */
+enum { HELM_TILE_MARCH = 0x100 };
 helm_status helm_set_row_tiling(int32_t nodes_per_thread);
 
 /* Process-wide panel width of the blocked Gauss-Jordan inversion of the plane

@@ -124,6 +124,8 @@ struct OpDev {
   // adaptive coefficients: per node {alpha_face, alpha_edge, alpha_corner, wm1,
   // wm2, wm3, wm4, 0}; nullptr = the single set alpha, wm above
   const double* wnode;
+  // row diagonals A[i, i] (set-up, in fine_row's order of terms); the products read them
+  const z64* diag;
 };
 
 // Per-subdomain description (device and host).

@@ -431,7 +431,7 @@ struct helm_handle {
   helm_pml_t pml{};
   helm_weights_t w{};
   helm_decomp_t dec{};
-  DevBuf c, sigma, xi_int, xi_half, i2_int, i2_half, flat, vmax, err;
+  DevBuf c, sigma, diag, xi_int, xi_half, i2_int, i2_half, flat, vmax, err;
   DevBuf wtab, wnode;  // adaptive coefficients: weight table [n][7], per-node weights [n][8]
   OpDev op{};
   Level fine, coarse;
@@ -631,7 +631,7 @@ size_t ws_bytes(const helm_handle* H, int nr) {
 }
 
 size_t resident_bytes_planned(const helm_handle* H) {
-  size_t b = sizeof(z64) * (size_t)H->n * 2 + level_resident_bytes(H->fine);
+  size_t b = sizeof(z64) * (size_t)H->n * 3 + level_resident_bytes(H->fine);  // velocity, sigma, row diagonals
   if (H->dec.adaptive) b += sizeof(double) * 8 * (size_t)H->n + sizeof(double) * 7 * ADAPT_N;
   if (H->two_level()) b += level_resident_bytes(H->coarse) + sizeof(z64) * (size_t)H->coarse.n * 27;
   return b;
@@ -1671,6 +1671,10 @@ void setup_impl(helm_handle* H, const void* velocity, int vel_kind) {
     op.wnode = H->wnode.as<double>();
   }
   launch_sigma(op, H->c.as<z64>(), H->omega, H->stream);
+  H->diag.alloc(sizeof(z64) * n);
+  op.diag = nullptr;
+  launch_row_diag(op, H->diag.as<z64>(), H->stream);
+  op.diag = H->diag.as<z64>();
 
   // fine level: local operators with absorbing interfaces, then factorisation
   Level& F = H->fine;
@@ -2071,13 +2075,14 @@ helm_status helm_set_graphs(helm_handle_t* H, int32_t enable) {
 }
 
 helm_status helm_set_sweep_policy(int32_t policy) {
-  if (policy < 0 || policy > 4) return fail(HELM_EINVAL, "sweep policy must be 0, 1, 2, 3 or 4");
+  if (policy < 0 || policy > 5) return fail(HELM_EINVAL, "sweep policy must be 0, 1, 2, 3, 4 or 5");
   set_sweep_policy(policy);
   return HELM_OK;
 }
 
 helm_status helm_set_row_tiling(int32_t nodes_per_thread) {
-  if (!set_row_tiling(nodes_per_thread)) return fail(HELM_EINVAL, "nodes per thread must be 0, 2, 4 or 8");
+  if (!set_row_tiling(nodes_per_thread))
+    return fail(HELM_EINVAL, "tiling must be 0, 2, 4, 8, HELM_TILE_MARCH | 2 or HELM_TILE_MARCH | 3");
   return HELM_OK;
 }
 

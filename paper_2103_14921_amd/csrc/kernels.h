@@ -45,6 +45,8 @@ void launch_pml_tables(const AxisPml ax[3], double h, double omega, double R, co
                        z64* xi_int, z64* xi_half, z64* i2_int, z64* i2_half, uint8_t* flat,
                        hipStream_t s);
 void launch_sigma(const OpDev& op, const z64* c, double omega, hipStream_t s);
+// Row diagonals A[i, i] into diag[n] (OpDev::diag), after sigma and the node weights.
+void launch_row_diag(const OpDev& op, z64* diag, hipStream_t s);
 // Per-node weights of the adaptive coefficients (OpDev::wnode, 8 doubles per
 // node) from the weight table tab[ntab][7] at G = g0 + j dg.
 void launch_node_weights(const z64* c, long long n, double freq, double h, const double* tab, int ntab, double g0,

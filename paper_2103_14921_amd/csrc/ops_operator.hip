@@ -14,6 +14,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <vector>
 #include "kernels.h"
 #include "stencil_row.h"
 
@@ -138,37 +139,14 @@ __global__ void __launch_bounds__(256) k_stencil2(OpDev op, int nrhs, const z64*
   const long long n = (long long)op.nx * op.ny * op.nz;
   const int nb = nrhs >= 256 ? 1 : (nrhs >= 4 ? 256 / nrhs : 64);
   z64(*coef)[27] = reinterpret_cast<z64(*)[27]>(lds_coef);
-  z64(*stf)[27] = reinterpret_cast<z64(*)[27]>(lds_coef + nb * 27);
   const long long i0 = (long long)blockIdx.x * nb;
   const int tid = threadIdx.x;
   // phase 1: coefficients (node a, offset o)
-  for (int t = tid; t < nb * 27; t += 256) {
-    const int a = t / 27, o = t % 27;
+  for (int t = tid; t < nb * 4; t += 256) {  // four lanes per node
+    const int a = t >> 2;
     const long long i = i0 + a;
-    if (i >= n || o == 13) continue;
-    const int ix = (int)(i % op.nx);
-    const long long q = i / op.nx;
-    const int iy = (int)(q % op.ny);
-    const int iz = (int)(q / op.ny);
-    const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
-    const int cls = abs(ox) + abs(oy) + abs(oz);
-    const bool flat = op.flat[op.off_int[0] + ix] && op.flat[op.off_int[1] + iy] && op.flat[op.off_int[2] + iz];
-    const int jx = ix + ox, jy = iy + oy, jz = iz + oz;
-    const bool inside = jx >= 0 && jx < op.nx && jy >= 0 && jy < op.ny && jz >= 0 && jz < op.nz;
-    const long long j = inside ? jx + (long long)op.nx * (jy + (long long)op.ny * jz) : -1;
-    const double al = edge_alpha(op, i, j, cls);
-    const z64 st = flat ? mk(al * op.h2inv, 0.0) : stiff_coef(op, al, ix, iy, iz, ox, oy, oz);
-    stf[a][o] = st;
-    coef[a][o] = inside ? st + edge_mass(op, i, j, cls, op.sigma[i], op.sigma[j]) : mk(0.0, 0.0);
-  }
-  __syncthreads();
-  for (int a = tid; a < nb; a += 256) {
-    const long long i = i0 + a;
-    if (i >= n) continue;
-    z64 d = diag_mass(op, i) * op.sigma[i];
-    for (int o = 0; o < 27; ++o)
-      if (o != 13) d -= stf[a][o];
-    coef[a][13] = d;
+    const long long ic = i < n ? i : 0;
+    row_coefs<4>(op, i < n, (int)(ic % op.nx), (int)((ic / op.nx) % op.ny), (int)(ic / op.nx / op.ny), t & 3, coef[a]);
   }
   __syncthreads();
   // phase 2: one thread per (node, rhs)
@@ -277,37 +255,9 @@ __global__ void __launch_bounds__(256) k_stencil_rows(OpDev op, int nrhs, const 
                                                       z64* __restrict__ y, const z64* __restrict__ b) {
   __shared__ z64 cf[TW][27];
   const RowTile t = row_tile<NXT>(op.nx, op.ny, op.nz);
-  // phase 1: four lanes per node, offsets o = q, q + 4, ...; the stiffness sum
-  // of the diagonal is reduced over the four lanes
-  const int a = threadIdx.x >> 2, q = threadIdx.x & 3;
-  z64 ssum = mk(0.0, 0.0), si = mk(0.0, 0.0);
-  if (a < t.w) {
-    const int ix = t.x0 + a;
-    const long long i = ix + (long long)op.nx * (t.iy + (long long)op.ny * t.iz);
-    si = op.sigma[i];
-    const bool flat = op.flat[op.off_int[0] + ix] && op.flat[op.off_int[1] + t.iy] && op.flat[op.off_int[2] + t.iz];
-    for (int o = q; o < 27; o += 4) {
-      if (o == 13) continue;
-      const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
-      const int cls = abs(ox) + abs(oy) + abs(oz);
-      const int jx = ix + ox, jy = t.iy + oy, jz = t.iz + oz;
-      const bool inside = jx >= 0 && jx < op.nx && jy >= 0 && jy < op.ny && jz >= 0 && jz < op.nz;
-      const long long j = inside ? jx + (long long)op.nx * (jy + (long long)op.ny * jz) : -1;
-      const double al = edge_alpha(op, i, j, cls);
-      const z64 st = flat ? mk(al * op.h2inv, 0.0) : stiff_coef(op, al, ix, t.iy, t.iz, ox, oy, oz);
-      ssum += st;
-      cf[a][o] = inside ? st + edge_mass(op, i, j, cls, si, op.sigma[j]) : mk(0.0, 0.0);
-    }
-  } else if (a < TW) {
-    for (int o = q; o < 27; o += 4) cf[a][o] = mk(0.0, 0.0);
-  }
-  ssum.re += __shfl_xor(ssum.re, 1);
-  ssum.im += __shfl_xor(ssum.im, 1);
-  ssum.re += __shfl_xor(ssum.re, 2);
-  ssum.im += __shfl_xor(ssum.im, 2);
-  if (q == 0 && a < TW)
-    cf[a][13] = a < t.w ? diag_mass(op, t.x0 + a + (long long)op.nx * (t.iy + (long long)op.ny * t.iz)) * si - ssum
-                        : mk(0.0, 0.0);
+  // phase 1: the tile's row coefficients, four lanes per node
+  const int a = threadIdx.x >> 2;
+  row_coefs<4>(op, a < t.w, t.x0 + a, t.iy, t.iz, threadIdx.x & 3, cf[a]);
   __syncthreads();
   tile_product<NXT>(t, op.nx, op.ny, op.nz, nrhs, cf, x, y, b);
 }
@@ -329,6 +279,130 @@ __global__ void __launch_bounds__(256) k_coarse_spmv_rows(int ncx, int ncy, int 
   }
   __syncthreads();
   tile_product<NXT>(t, ncx, ncy, ncz, nrhs, cf, x, y, nullptr);
+}
+
+// Plane-marching 27-point products for batches of 16 k right-hand sides.  A
+// workgroup owns a segment of MW = (256 / RW) NXT consecutive nodes of one grid
+// row and MZ planes of it, for RW right-hand sides (one block of the batch):
+// thread (g, r) keeps NXT consecutive nodes of right-hand side r and marches
+// through the planes, loading each plane's three neighbour rows once (NXT + 2
+// values each) and adding their terms to the outputs of the planes below, at
+// and above it, whose accumulators rotate; the output of plane p - 1 is
+// complete once plane p is in.  A row-tiled product loads nine neighbour rows
+// per output plane, this form three.  The row coefficients of the three planes
+// in flight sit in an LDS ring: generated (row_coefs, as the row-tiled product
+// does, eight lanes per node) or, for E, copied from its stored rows.  Every
+// output sums its 27 terms in offset order, as the row-tiled product, so the
+// results are bitwise identical (terms with a neighbour plane outside the grid
+// have zero coefficients and are skipped).
+constexpr int MZ = 16;
+template <int NXT, int RW>
+struct March {
+  static constexpr int MW = (256 / RW) * NXT;  // nodes per segment
+};
+struct MarchTile {
+  int x0, w, iy, z0, z1;
+};
+template <int NXT, int RW>
+__device__ __forceinline__ MarchTile march_tile(int nx, int ny, int nz) {
+  constexpr int MW = March<NXT, RW>::MW;
+  const int nt = (nx + MW - 1) / MW;
+  // segments of a row fastest, then rows, then plane chunks; XCDs take contiguous ranges
+  const long long lb = xcd_contiguous(blockIdx.x, gridDim.x);
+  MarchTile t;
+  const int tx = (int)(lb % nt);
+  t.iy = (int)((lb / nt) % ny);
+  t.z0 = (int)(lb / ((long long)nt * ny)) * MZ;
+  t.z1 = min(t.z0 + MZ, nz);
+  t.x0 = tx * MW;
+  t.w = min(MW, nx - t.x0);
+  return t;
+}
+template <int NXT, int RW>
+static unsigned march_tiles(int nx, int ny, int nz) {
+  constexpr int MW = March<NXT, RW>::MW;
+  return (unsigned)((long long)((nx + MW - 1) / MW) * ny * ((nz + MZ - 1) / MZ));
+}
+
+// E == nullptr: the fine operator's rows, generated; else E's stored rows [node][27]
+template <int NXT, int RW>
+__global__ void __launch_bounds__(256) k_march(OpDev op, int nx, int ny, int nz, const z64* __restrict__ E, int nrhs,
+                                               const z64* __restrict__ x, z64* __restrict__ y,
+                                               const z64* __restrict__ b) {
+  constexpr int MW = March<NXT, RW>::MW;
+  __shared__ z64 ring[3][MW][27];
+  const MarchTile t = march_tile<NXT, RW>(nx, ny, nz);
+  const int g = threadIdx.x / RW, r = (int)blockIdx.y * RW + threadIdx.x % RW;
+  const int xa = t.x0 + g * NXT;
+  const long long plane = (long long)nx * ny;
+  z64 acc[3][NXT];  // outputs of planes p - 1, p, p + 1
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int m = 0; m < NXT; ++m) acc[a][m] = mk(0.0, 0.0);
+  for (int p = t.z0 - 1; p <= t.z1; ++p) {
+    __syncthreads();  // the slot refilled below was last read in the previous step
+    const int zn = p + 1;
+    if (zn >= t.z0 && zn < t.z1) {
+      z64(*slot)[27] = ring[zn % 3];
+      if (E == nullptr) {
+        constexpr int L = 256 / MW >= 8 ? 8 : 4;  // lanes per node
+        const int a = threadIdx.x / L;
+        if (a < MW) row_coefs<L>(op, a < t.w, t.x0 + a, t.iy, zn, threadIdx.x % L, slot[a]);
+      } else {
+        const long long rowi = (long long)nx * (t.iy + (long long)ny * zn);
+        for (int e = threadIdx.x; e < MW * 27; e += 256) {
+          const int a = e / 27, o = e % 27;
+          z64 c = mk(0.0, 0.0);
+          if (a < t.w) {
+            const int jx = t.x0 + a + o % 3 - 1, jy = t.iy + (o / 3) % 3 - 1, jz = zn + o / 9 - 1;
+            if (jx >= 0 && jx < nx && jy >= 0 && jy < ny && jz >= 0 && jz < nz) c = E[(rowi + t.x0 + a) * 27 + o];
+          }
+          slot[a][o] = c;
+        }
+      }
+    }
+    __syncthreads();
+    if (p >= 0 && p < nz && g * NXT < t.w) {
+      z64 v[3][NXT + 2];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int jy = min(max(t.iy + k - 1, 0), ny - 1);
+        const z64* xr = x + (p * plane + (long long)jy * nx) * nrhs + r;
+#pragma unroll
+        for (int q = 0; q < NXT + 2; ++q) v[k][q] = xr[(long long)min(max(xa - 1 + q, 0), nx - 1) * nrhs];
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int zt = p - 1 + a;  // output plane; this plane is its neighbour at dz = 1 - a
+        if (zt < t.z0 || zt >= t.z1) continue;
+        const z64(*cf)[27] = ring[zt % 3];
+        const int ob = 9 * (2 - a);
+#pragma unroll
+        for (int m = 0; m < NXT; ++m)
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) cfma(acc[a][m], cf[g * NXT + m][ob + 3 * k + dx], v[k][m + dx]);
+      }
+    }
+    const int zo = p - 1;
+    if (zo >= t.z0 && zo < t.z1) {
+      const long long rowi = zo * plane + (long long)t.iy * nx;
+#pragma unroll
+      for (int m = 0; m < NXT; ++m) {
+        if (xa + m >= t.x0 + t.w) break;
+        const long long e = (rowi + xa + m) * nrhs + r;
+        y[e] = b ? b[e] - acc[0][m] : acc[0][m];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < NXT; ++m) {
+      acc[0][m] = acc[1][m];
+      acc[1][m] = acc[2][m];
+      acc[2][m] = mk(0.0, 0.0);
+    }
+  }
 }
 
 // E[I][o] = sum_i sum_j Z[i,I] A[i,j] Z[j,I+o]; one thread per coarse node I,
@@ -484,7 +558,22 @@ __global__ void k_prolong(int nx, int ny, int nz, int nrhs, const z64* __restric
   q[i * nrhs + r] = acc;
 }
 
+// Row diagonals A[i, i] (set-up), one thread per node.
+__global__ void __launch_bounds__(256) k_row_diag(OpDev op, z64* __restrict__ diag) {
+  const long long n = (long long)op.nx * op.ny * op.nz;
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += 256ll * gridDim.x) {
+    const int ix = (int)(i % op.nx), iy = (int)((i / op.nx) % op.ny), iz = (int)(i / op.nx / op.ny);
+    diag[i] = row_diag(op, ix, iy, iz);
+  }
+}
+
 }  // namespace
+
+void launch_row_diag(const OpDev& op, z64* diag, hipStream_t s) {
+  const long long n = (long long)op.nx * op.ny * op.nz;
+  hipLaunchKernelGGL(k_row_diag, dim3((unsigned)std::min<long long>(ceil_div(n, 256), 65536)), dim3(256), 0, s, op,
+                     diag);
+}
 
 void launch_vmax(const z64* c, long long n, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_vmax, dim3(1), dim3(1024), 0, s, c, n, out);
@@ -540,9 +629,14 @@ bool row_untuned(const RowKey& key) {
   return g_row_tune.find(key) == g_row_tune.end();
 }
 
+// Schedules: 2, 4, 8 = row tiles with that many nodes per thread; MARCH | n =
+// plane-marching with n nodes per thread (batches of 16 k right-hand sides).
+constexpr int MARCH = 0x100;
+bool march_ok(int nrhs) { return nrhs % 16 == 0; }
+
 template <typename Launch>
 int tuned_nxt(const RowKey& key, hipStream_t s, Launch&& launch) {
-  if (const int f = g_row_forced.load()) return f;
+  if (const int f = g_row_forced.load()) return (f & MARCH) && !march_ok(key.nrhs) ? 4 : f;
   {
     std::lock_guard<std::mutex> lk(g_row_mu);
     auto it = g_row_tune.find(key);
@@ -556,7 +650,12 @@ int tuned_nxt(const RowKey& key, hipStream_t s, Launch&& launch) {
   (void)locked_event_create(&e1);
   int bestn = 4;
   float best = 1e30f;
-  for (int nxt : {2, 4, 8}) {
+  std::vector<int> cand{2, 4, 8};
+  if (march_ok(key.nrhs)) {
+    cand.push_back(MARCH | 2);
+    cand.push_back(MARCH | 3);
+  }
+  for (int nxt : cand) {
     float tot = 0.f;
     for (int rep = 0; rep < 2; ++rep) {
       (void)hipEventRecord(e0, s);
@@ -567,6 +666,10 @@ int tuned_nxt(const RowKey& key, hipStream_t s, Launch&& launch) {
       (void)hipEventElapsedTime(&ms, e0, e1);
       if (rep > 0) tot += ms;
     }
+    static const bool verbose_c = std::getenv("HELM_TUNE_VERBOSE") != nullptr;
+    if (verbose_c)
+      std::fprintf(stderr, "helm:   candidate %s, %d nodes per thread: %.3f ms\n",
+                   (nxt & MARCH) ? "plane-marching" : "row tiles", nxt & 0xff, tot);
     if (tot < best) {
       best = tot;
       bestn = nxt;
@@ -576,18 +679,37 @@ int tuned_nxt(const RowKey& key, hipStream_t s, Launch&& launch) {
   locked_event_destroy(e1);
   static const bool verbose = std::getenv("HELM_TUNE_VERBOSE") != nullptr;
   if (verbose)
-    std::fprintf(stderr, "helm: %s tuned (%dx%dx%d, %d rhs): %d nodes per thread, %.3f ms\n",
-                 key.kind ? "coarse product" : "stencil", key.nx, key.ny, key.nz, key.nrhs, bestn, best);
+    std::fprintf(stderr, "helm: %s tuned (%dx%dx%d, %d rhs): %s, %d nodes per thread, %.3f ms\n",
+                 key.kind ? "coarse product" : "stencil", key.nx, key.ny, key.nz, key.nrhs,
+                 (bestn & MARCH) ? "plane-marching" : "row tiles", bestn & 0xff, best);
   std::lock_guard<std::mutex> lk(g_row_mu);
   g_row_tune[key] = bestn;
   return bestn;
+}
+
+template <int NXT, int RW>
+void launch_march_t(const OpDev& op, int nx, int ny, int nz, const z64* E, int nrhs, const z64* x, z64* y,
+                    const z64* b, hipStream_t s) {
+  hipLaunchKernelGGL((k_march<NXT, RW>), dim3(march_tiles<NXT, RW>(nx, ny, nz), (unsigned)(nrhs / RW)), dim3(256), 0,
+                     s, op, nx, ny, nz, E, nrhs, x, y, b);
+}
+// plane-marching product with n nodes per thread (2 or 3); nrhs a multiple of 16
+void launch_march(int n, const OpDev& op, int nx, int ny, int nz, const z64* E, int nrhs, const z64* x, z64* y,
+                  const z64* b, hipStream_t s) {
+  if (nrhs % 32 == 0) {
+    if (n == 2) launch_march_t<2, 32>(op, nx, ny, nz, E, nrhs, x, y, b, s);
+    else launch_march_t<3, 32>(op, nx, ny, nz, E, nrhs, x, y, b, s);
+  } else {
+    if (n == 2) launch_march_t<2, 16>(op, nx, ny, nz, E, nrhs, x, y, b, s);
+    else launch_march_t<3, 16>(op, nx, ny, nz, E, nrhs, x, y, b, s);
+  }
 }
 }  // namespace
 
 bool stencil_untuned(const OpDev& op, int nrhs) { return row_untuned({0, op.nx, op.ny, op.nz, nrhs}); }
 bool coarse_spmv_untuned(int ncx, int ncy, int ncz, int nrhs) { return row_untuned({1, ncx, ncy, ncz, nrhs}); }
 bool set_row_tiling(int nxt) {
-  if (nxt != 0 && nxt != 2 && nxt != 4 && nxt != 8) return false;
+  if (nxt != 0 && nxt != 2 && nxt != 4 && nxt != 8 && nxt != (MARCH | 2) && nxt != (MARCH | 3)) return false;
   g_row_forced.store(nxt);
   return true;
 }
@@ -600,7 +722,8 @@ static void stencil_dispatch(const OpDev& op, int nrhs, const z64* x, z64* y, co
   if (nrhs >= 4) {
     const dim3 grid(row_tiles(op.nx, op.ny, op.nz));
     auto launch = [&](int nxt) {
-      if (nxt == 2) hipLaunchKernelGGL(k_stencil_rows<2>, grid, dim3(256), 0, s, op, nrhs, x, y, b);
+      if (nxt & MARCH) launch_march(nxt & 0xff, op, op.nx, op.ny, op.nz, nullptr, nrhs, x, y, b, s);
+      else if (nxt == 2) hipLaunchKernelGGL(k_stencil_rows<2>, grid, dim3(256), 0, s, op, nrhs, x, y, b);
       else if (nxt == 8) hipLaunchKernelGGL(k_stencil_rows<8>, grid, dim3(256), 0, s, op, nrhs, x, y, b);
       else hipLaunchKernelGGL(k_stencil_rows<4>, grid, dim3(256), 0, s, op, nrhs, x, y, b);
     };
@@ -609,7 +732,7 @@ static void stencil_dispatch(const OpDev& op, int nrhs, const z64* x, z64* y, co
   }
   const long long n = (long long)op.nx * op.ny * op.nz;
   const int nb = nrhs >= 256 ? 1 : (nrhs >= 4 ? 256 / nrhs : 64);
-  hipLaunchKernelGGL(k_stencil2, dim3((unsigned)ceil_div(n, nb)), dim3(256), sizeof(z64) * 27 * 2 * nb, s, op, nrhs, x,
+  hipLaunchKernelGGL(k_stencil2, dim3((unsigned)ceil_div(n, nb)), dim3(256), sizeof(z64) * 27 * nb, s, op, nrhs, x,
                      y, b);
 }
 
@@ -636,7 +759,8 @@ void launch_coarse_spmv(int ncx, int ncy, int ncz, const z64* E, int nrhs, const
   if (nrhs >= 4) {
     const dim3 grid(row_tiles(ncx, ncy, ncz));
     auto launch = [&](int nxt) {
-      if (nxt == 2) hipLaunchKernelGGL(k_coarse_spmv_rows<2>, grid, dim3(256), 0, s, ncx, ncy, ncz, E, nrhs, x, y);
+      if (nxt & MARCH) launch_march(nxt & 0xff, OpDev{}, ncx, ncy, ncz, E, nrhs, x, y, nullptr, s);
+      else if (nxt == 2) hipLaunchKernelGGL(k_coarse_spmv_rows<2>, grid, dim3(256), 0, s, ncx, ncy, ncz, E, nrhs, x, y);
       else if (nxt == 8) hipLaunchKernelGGL(k_coarse_spmv_rows<8>, grid, dim3(256), 0, s, ncx, ncy, ncz, E, nrhs, x, y);
       else hipLaunchKernelGGL(k_coarse_spmv_rows<4>, grid, dim3(256), 0, s, ncx, ncy, ncz, E, nrhs, x, y);
     };

@@ -427,28 +427,42 @@ struct BoxCtx {
 // item, all its waves building and then multiplying each plane in turn.
 // MINW > 1: compiled for at least MINW waves per SIMD (two 9-wave workgroups
 // on a compute unit at MINW = 5), with the operand build's taps split in two.
-template <typename T, int RG, int PF, int MINW>
+// PAIR: the workgroup takes two right-hand-side groups of one box (items
+// 2j, 2j + 1 of the box), each on half of its waves with its own operand slot
+// (half_elems elements apart in LDS).  Both halves stream the same factor
+// chunks within the same plane step, so the second read of each chunk mostly
+// hits L2, and the factors cross HBM about once per application.
+template <typename T, int RG, int PF, int MINW, bool PAIR>
 __global__ void __launch_bounds__(64 * fused_max_waves<T>(), MINW) k_oras_fused(const Sub* __restrict__ subs, int ngroups, int nrhs,
                                                    const cpx<T>* __restrict__ cpl, const cpx<T>* __restrict__ sinv,
                                                    const z64* __restrict__ u, z64* __restrict__ z,
                                                    const z64* __restrict__ add, int gnx, int gny,
-                                                   cpx<T>* __restrict__ yloc) {
+                                                   cpx<T>* __restrict__ yloc, int half_elems) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cpx<T>* Bs = reinterpret_cast<cpx<T>*>(smem_raw);
-  // items of one box (its RHS groups) and neighbouring boxes go to the same XCD
-  // back to back, so the groups' reads of the box's factors meet in its L2
-  const int item = (int)xcd_contiguous(blockIdx.x, gridDim.x);
-  const BoxCtx<T, RG> bx(subs, item, ngroups, nrhs, cpl, u, z, add, gnx, gny, yloc);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int FT = blockDim.x, nwaves = FT >> 6;
+  // the item's waves (wave-uniform values, kept in scalar registers)
+  int hw = nwaves, half = 0, wv = __builtin_amdgcn_readfirstlane(wave), ht = tid;
+  if constexpr (PAIR) {
+    hw = nwaves >> 1;
+    half = __builtin_amdgcn_readfirstlane(wave >= hw ? 1 : 0);
+    wv = __builtin_amdgcn_readfirstlane(wave - half * hw);
+    ht = tid - half * hw * 64;
+  }
+  cpx<T>* Bs = reinterpret_cast<cpx<T>*>(smem_raw) + half * half_elems;
+  // items of one box (its RHS groups) and neighbouring boxes go to the same XCD
+  // back to back, so the groups' reads of the box's factors meet in its L2
+  const int wg = (int)xcd_contiguous(blockIdx.x, gridDim.x);
+  const int item = PAIR ? (wg / (ngroups / 2)) * ngroups + 2 * (wg % (ngroups / 2)) + half : wg;
+  const BoxCtx<T, RG> bx(subs, item, ngroups, nrhs, cpl, u, z, add, gnx, gny, yloc);
   const int bp = bx.sb.bp, ns = bx.nsteps();
   for (int st = 0; st < ns; ++st) {
-    bx.template build_step<(MINW > 1)>(st, Bs, tid, FT);
+    bx.template build_step<(MINW > 1)>(st, Bs, ht, hw * 64);
     cpx<T> a[PF][4];  // per plane, so nothing stays live across the operand build
-    ChunkStream<T> cs = prefetch_tile<T, PF>(bx.factor(sinv, st), bp, wave, nwaves, lane, a);  // across the barrier
+    ChunkStream<T> cs = prefetch_tile<T, PF>(bx.factor(sinv, st), bp, wv, hw, lane, a);  // across the barrier
     __syncthreads();
     plane_product<T, RG, PF>(
-        cs, Bs, wave, nwaves, lane, a, [&](int p, int r) { return bx.init(st, p, r); },
+        cs, Bs, wv, hw, lane, a, [&](int p, int r) { return bx.init(st, p, r); },
         [&](int p, int r, cpx<T> val) { bx.output(st, p, r, val); });
     wg_sync_global();
   }
@@ -755,6 +769,12 @@ int min_rounds(int bpmax) {
   constexpr int MW = fused_max_waves<T>();
   return (bpmax / 16 + MW - 1) / MW;
 }
+// the paired sweep: both halves within the wave limit
+template <typename T>
+int pair_min_rounds(int bpmax) {
+  constexpr int MW = fused_max_waves<T>() / 2;
+  return (bpmax / 16 + MW - 1) / MW;
+}
 
 template <typename T>
 void launch_gl_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, int rounds, const cpx<T>* cpl,
@@ -768,23 +788,33 @@ void launch_gl_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, in
                      u, z, add, gnx, gny, yloc, tglob, bpmax);
 }
 
-template <typename T, int RG, int PF, int MINW>
+template <typename T, int RG, int PF, int MINW, bool PAIR = false>
 void launch_fused_k(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, int rounds, const cpx<T>* cpl,
                     const cpx<T>* sinv, const z64* u, z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc,
                     hipStream_t s) {
-  const size_t lds = (size_t)bpmax * lds_width<T>(RG) * sizeof(cpx<T>);
+  const int half_elems = bpmax * lds_width<T>(RG);
+  const size_t lds = (size_t)(PAIR ? 2 : 1) * half_elems * sizeof(cpx<T>);
   static bool attr = false;  // one per kernel instance
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_oras_fused<T, RG, PF, MINW>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
+    (void)hipFuncSetAttribute((const void*)k_oras_fused<T, RG, PF, MINW, PAIR>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr = true;
   }
-  // waves per workgroup: the tiles spread evenly over the given number of rounds
+  // waves per item: the tiles spread evenly over the given number of rounds
   const int nmt = bpmax / 16;
-  rounds = std::max(rounds, min_rounds<T>(bpmax));
+  rounds = std::max(rounds, PAIR ? pair_min_rounds<T>(bpmax) : min_rounds<T>(bpmax));
   const int nwaves = (nmt + rounds - 1) / rounds;
-  hipLaunchKernelGGL((k_oras_fused<T, RG, PF, MINW>), dim3(nsub * ngroups), dim3(64 * nwaves), lds, s, subs, ngroups,
-                     nrhs, cpl, sinv, u, z, add, gnx, gny, yloc);
+  hipLaunchKernelGGL((k_oras_fused<T, RG, PF, MINW, PAIR>), dim3(nsub * (PAIR ? ngroups / 2 : ngroups)),
+                     dim3(64 * nwaves * (PAIR ? 2 : 1)), lds, s, subs, ngroups, nrhs, cpl, sinv, u, z, add, gnx, gny,
+                     yloc, half_elems);
+}
+
+// Whether the paired sweep (two groups of a box per workgroup) exists for this
+// shape: an even number of groups, two operands in one CU's LDS.
+template <typename T>
+bool pair_fits(int rg, int bpmax, int nrhs) {
+  const int ngroups = (nrhs + rg - 1) / rg;
+  return rg >= 16 && ngroups % 2 == 0 && 2 * (size_t)bpmax * lds_width<T>(rg) * sizeof(cpx<T>) <= 160 * 1024;
 }
 
 // Whether the two-workgroups-per-CU build of the sweep exists for this shape:
@@ -795,10 +825,17 @@ bool lowreg_fits(int rg, int bpmax) {
 }
 
 template <typename T, int RG>
-void launch_fused_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, int rounds, bool lowreg,
+void launch_fused_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, int rounds, bool lowreg, bool pair,
                     const cpx<T>* cpl, const cpx<T>* sinv, const z64* u, z64* z, const z64* add, int gnx, int gny,
                     cpx<T>* yloc, hipStream_t s) {
   constexpr int PF = sizeof(T) == 4 ? 4 : 2;
+  if constexpr (RG >= 16) {
+    if (pair) {
+      launch_fused_k<T, RG, PF, 1, true>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx, gny,
+                                         yloc, s);
+      return;
+    }
+  }
   if constexpr (sizeof(T) == 8 && RG == 32) {
     if (lowreg) {  // one factor chunk in flight per wave: five waves per SIMD hide the latency instead
       launch_fused_k<T, RG, 1, 5>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx, gny, yloc, s);
@@ -866,9 +903,9 @@ int fused_group(int bpmax, int nrhs) {
 namespace {
 
 template <typename T>
-void launch_rg(int rg, int rounds, bool lowreg, const Sub* subs, int nsub, int nrhs, int bpmax, const cpx<T>* cpl,
-               const cpx<T>* sinv, const z64* u, z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc,
-               cpx<T>* tglob, hipStream_t s) {
+void launch_rg(int rg, int rounds, bool lowreg, bool pair, const Sub* subs, int nsub, int nrhs, int bpmax,
+               const cpx<T>* cpl, const cpx<T>* sinv, const z64* u, z64* z, const z64* add, int gnx, int gny,
+               cpx<T>* yloc, cpx<T>* tglob, hipStream_t s) {
   const int ngroups = (nrhs + rg - 1) / rg;
   if (!lds_fits<T>(rg, bpmax)) {  // operand in global memory: the RG = 8 sweep k_oras_gl
     launch_gl_t<T>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx, gny, yloc, tglob, s);
@@ -886,15 +923,15 @@ void launch_rg(int rg, int rounds, bool lowreg, const Sub* subs, int nsub, int n
   }
   switch (rg) {
     case 8:
-      launch_fused_t<T, 8>(subs, nsub, ngroups, nrhs, bpmax, rounds, lowreg, cpl, sinv, u, z, add, gnx, gny, yloc,
+      launch_fused_t<T, 8>(subs, nsub, ngroups, nrhs, bpmax, rounds, lowreg, pair, cpl, sinv, u, z, add, gnx, gny, yloc,
                             s);
       break;
     case 16:
-      launch_fused_t<T, 16>(subs, nsub, ngroups, nrhs, bpmax, rounds, lowreg, cpl, sinv, u, z, add, gnx, gny, yloc,
+      launch_fused_t<T, 16>(subs, nsub, ngroups, nrhs, bpmax, rounds, lowreg, pair, cpl, sinv, u, z, add, gnx, gny, yloc,
                             s);
       break;
     default:
-      launch_fused_t<T, 32>(subs, nsub, ngroups, nrhs, bpmax, rounds, lowreg, cpl, sinv, u, z, add, gnx, gny, yloc,
+      launch_fused_t<T, 32>(subs, nsub, ngroups, nrhs, bpmax, rounds, lowreg, pair, cpl, sinv, u, z, add, gnx, gny, yloc,
                             s);
       break;
   }
@@ -913,6 +950,7 @@ std::atomic<int> g_sweep_policy{0};
 struct TuneVal {
   int rg, rounds;
   bool lowreg;  // the build for two workgroups per compute unit (lowreg_fits)
+  bool pair;    // two groups of a box per workgroup (pair_fits)
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
@@ -935,14 +973,22 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
   if (!lds_fits<T>(rgmax, bpmax) && !tbuf) return false;  // the global-operand sweep needs its operand slices
   const int policy = g_sweep_policy.load();
   if (policy == 3 && lowreg_fits<T>(rgmax, bpmax)) {  // forced: the two-workgroups-per-CU build
-    launch_rg<T>(rgmax, min_rounds<T>(bpmax), true, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc,
+    launch_rg<T>(rgmax, min_rounds<T>(bpmax), true, false, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc,
                  tbuf, s);
     return true;
+  }
+  if (policy == 5) {  // forced: the paired sweep with the widest group that pairs
+    for (int cand = rgmax; cand >= 16; cand /= 2)
+      if (pair_fits<T>(cand, bpmax, nrhs)) {
+        launch_rg<T>(cand, pair_min_rounds<T>(bpmax), false, true, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx,
+                     gny, yloc, tbuf, s);
+        return true;
+      }
   }
   if (policy == 4) {  // forced: the 16-wave pipelined sweep with the widest group that fits
     for (int cand = rgmax; cand >= 16; cand /= 2)
       if (pipe_fits<T>(cand, bpmax)) {
-        launch_rg<T>(cand, 0, true, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, tbuf, s);
+        launch_rg<T>(cand, 0, true, false, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, tbuf, s);
         return true;
       }
   }
@@ -951,7 +997,7 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
   bool any_pipe = false;
   for (int cand = 8; cand <= rgmax; cand *= 2) any_pipe = any_pipe || pipe_fits<T>(cand, bpmax);
   const bool allow_pipe = policy != 1 && policy != 3, allow_item = (policy != 2 && policy != 4) || !any_pipe;
-  TuneVal tv{0, 0, false};
+  TuneVal tv{0, 0, false, false};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(key);
@@ -986,7 +1032,7 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
           float tot = 0.f;
           for (int rep = 0; rep < 2; ++rep) {
             (void)hipEventRecord(e0, s);
-            launch_rg<T>(cand, rounds, lr != 0, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, tbuf,
+            launch_rg<T>(cand, rounds, lr != 0, false, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, tbuf,
                          s);
             (void)hipEventRecord(e1, s);
             (void)hipEventSynchronize(e1);
@@ -1000,7 +1046,34 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
                          lr && rounds != 0 ? " (two per CU)" : "", tot);
           if (tot < best) {
             best = tot;
-            tv = {cand, rounds, lr != 0};
+            tv = {cand, rounds, lr != 0, false};
+          }
+        }
+      }
+      // the paired sweep: two groups of a box per workgroup
+      if ((policy == 0 || policy == 5) && pair_fits<T>(cand, bpmax, nrhs)) {
+        const int pr0 = pair_min_rounds<T>(bpmax);
+        int last = 0;
+        for (int rounds = pr0; rounds <= pr0 + 2; ++rounds) {
+          const int waves = (nmt + rounds - 1) / rounds;
+          if (waves == last) continue;
+          last = waves;
+          float tot = 0.f;
+          for (int rep = 0; rep < 2; ++rep) {
+            (void)hipEventRecord(e0, s);
+            launch_rg<T>(cand, rounds, false, true, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc,
+                         tbuf, s);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) tot += ms;
+          }
+          if (verbose)
+            std::fprintf(stderr, "helm:   candidate group %d paired, 2 x %d waves: %.3f ms\n", cand, waves, tot);
+          if (tot < best) {
+            best = tot;
+            tv = {cand, rounds, false, true};
           }
         }
       }
@@ -1009,23 +1082,24 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
     locked_event_destroy(e1);
     if (verbose)
       std::fprintf(stderr, "helm: sweep tuned (fp%d, bp %d, %d boxes, %d rhs): group %d, %s %d waves%s, %.3f ms\n",
-                   (int)sizeof(T) * 8, bpmax, nsub, nrhs, tv.rg, tv.rounds == 0 ? "pipelined," : "",
+                   (int)sizeof(T) * 8, bpmax, nsub, nrhs, tv.rg,
+                   tv.rounds == 0 ? "pipelined," : (tv.pair ? "paired, 2 x" : ""),
                    tv.rounds == 0 ? (tv.lowreg ? 16 : 12) : (nmt + tv.rounds - 1) / tv.rounds,
                    tv.lowreg && tv.rounds != 0 ? " (two per CU)" : "", best);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = tv;
   }
   if (tv.rg == 0) {  // untuned (tuning off, or inside a capture): the widest group
-    tv = {rgmax, r0, false};
+    tv = {rgmax, r0, false, false};
     if (!allow_item) {
       for (int cand = rgmax; cand >= 16; cand /= 2)
         if (pipe_fits<T>(cand, bpmax)) {
-          tv = {cand, 0, false};
+          tv = {cand, 0, false, false};
           break;
         }
     }
   }
-  launch_rg<T>(tv.rg, tv.rounds, tv.lowreg, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, tbuf, s);
+  launch_rg<T>(tv.rg, tv.rounds, tv.lowreg, tv.pair, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, tbuf, s);
   return true;
 }
 
@@ -1081,7 +1155,7 @@ bool oras_half(const Sub* subs, int nsub, int bpmax, const c32* cpl, const uint4
   const int rgmax = half_group(bpmax, nrhs);
   if (rgmax == 0) return false;
   const TuneKey key{2, bpmax, nsub, nrhs, gnx, gny, g_sweep_policy.load()};
-  TuneVal tv{0, 0, false};
+  TuneVal tv{0, 0, false, false};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(key);

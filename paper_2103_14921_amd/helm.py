@@ -35,6 +35,7 @@ def _precision(name):
         raise ValueError(f"precision must be one of {sorted(PRECISIONS)}, not {name!r}") from None
 HELM_X0 = 1
 HELM_BLOCK = 2
+HELM_TILE_MARCH = 0x100
 
 EXPORTS = [
     "helm_fit_weights", "helm_setup", "helm_solve", "helm_footprint", "helm_workspace_bytes", "helm_resident_bytes",
@@ -252,7 +253,7 @@ class Request:
             pass
 
 
-SWEEP_POLICIES = {"auto": 0, "item": 1, "pipelined": 2, "two_per_cu": 3, "pipelined16": 4}
+SWEEP_POLICIES = {"auto": 0, "item": 1, "pipelined": 2, "two_per_cu": 3, "pipelined16": 4, "paired": 5}
 
 
 def set_sweep_policy(policy):
@@ -261,7 +262,8 @@ def set_sweep_policy(policy):
 
 
 def set_row_tiling(nodes_per_thread):
-    """Process-wide nodes per thread of the 27-point products: 0 (autotuned), 2, 4 or 8."""
+    """Process-wide schedule of the 27-point products: 0 (autotuned), 2, 4 or 8 (row tiles with that many
+    nodes per thread), HELM_TILE_MARCH | 2 or | 3 (plane-marching, batches of 16 k right-hand sides)."""
     _check(lib.helm_set_row_tiling(int(nodes_per_thread)))
 
 

@@ -67,11 +67,12 @@ def test_workspace_bytes_is_the_rhs_dependent_part_of_the_footprint():
 
 def test_process_wide_settings_reject_bad_values():
     from paper_2103_14921_amd import helm
-    for bad in (1, 3, 16, -2):
+    for bad in (1, 3, 16, -2, helm.HELM_TILE_MARCH | 4, helm.HELM_TILE_MARCH):
         with pytest.raises(helm.HelmError) as e:
             helm.set_row_tiling(bad)
         assert e.value.code == helm.HELM_EINVAL
-    assert helm.lib.helm_set_sweep_policy(5) == helm.HELM_EINVAL
+    helm.set_row_tiling(helm.HELM_TILE_MARCH | 3)
+    assert helm.lib.helm_set_sweep_policy(6) == helm.HELM_EINVAL
     for bad in (1, 2, 12, 32):
         with pytest.raises(helm.HelmError):
             helm.set_lu_panel(bad)

@@ -163,31 +163,43 @@ def test_coarse_operator_batches_match_oracle(nrhs):
 
 
 def test_row_tilings_agree_bitwise():
-    # the fine and coarse 27-point products under each forced tiling (2, 4, 8
-    # nodes per thread) and the autotuned one: every tiling matches the oracle
-    # and all are bitwise equal; 70 nodes per row leave a ragged second tile
-    shape, h, c, f, pml = _thrust_case(shape=(70, 13, 11), pml=(3, 3, 3, 0))
+    # the fine and coarse 27-point products under each forced schedule (row
+    # tiles of 2, 4, 8 nodes per thread; plane-marching with 2 or 3) and the
+    # autotuned one: every schedule matches the oracle and all are bitwise
+    # equal; 70 nodes per row leave ragged segments, 37 planes a ragged plane
+    # chunk; 12 and 9 right-hand sides take row tiles under every schedule,
+    # 16 and 32 the plane-marching blocks of 16 and 32
+    shape, h, c, f, pml = _thrust_case(shape=(70, 13, 37), pml=(3, 3, 3, 0))
     say("row tilings", shape)
     prob = Problem(shape, h, c, f, Pml(*pml), WO)
     A = assemble(prob)
-    tl = TwoLevel(A, shape, decompose(shape, (2, 1, 1), 2), prob.k().ravel(), h, 2)
+    tl = TwoLevel(A, shape, decompose(shape, (2, 1, 2), 2), prob.k().ravel(), h, 2)
     hm = helm()
-    S = hm.Solver(shape, h, c, f, pml, weights=W, parts=(2, 1, 1), overlap=2, levels=2)
-    X = inputs.random_field((12, prob.n), seed=55)
-    Cc = inputs.random_field((9, S.nc), seed=56)
-    ref, refE = (A @ X.T).T, (tl.E @ Cc.T).T
-    outs = []
-    try:
-        for nxt in (2, 4, 8, 0):
-            hm.set_row_tiling(nxt)
-            Y, E = S.apply_A(X), S.apply_E(Cc)
-            assert np.max(np.abs(Y - ref)) <= 1e-12 * np.max(np.abs(ref)), nxt
-            assert rel(E, refE) <= 1e-12, nxt
-            outs.append((Y, E))
-    finally:
-        hm.set_row_tiling(0)
-    for Y, E in outs[1:]:
-        assert np.array_equal(Y, outs[0][0]) and np.array_equal(E, outs[0][1])
+    S = hm.Solver(shape, h, c, f, pml, weights=W, parts=(2, 1, 2), overlap=2, levels=2)
+    for nf, nc in ((12, 9), (32, 16), (16, 32)):
+        X = inputs.random_field((nf, prob.n), seed=55 + nf)
+        Cc = inputs.random_field((nc, S.nc), seed=56 + nc)
+        ref, refE = (A @ X.T).T, (tl.E @ Cc.T).T
+        B = inputs.random_field((nf, prob.n), seed=57 + nf)
+        res = np.linalg.norm(B - ref, axis=1) / np.linalg.norm(B, axis=1)
+        outs = []
+        try:
+            for sched in (2, 4, 8, hm.HELM_TILE_MARCH | 2, hm.HELM_TILE_MARCH | 3, 0):
+                say("  batch", nf, nc, "schedule", sched)
+                hm.set_row_tiling(sched)
+                Y, E = S.apply_A(X), S.apply_E(Cc)
+                assert np.max(np.abs(Y - ref)) <= 1e-12 * np.max(np.abs(ref)), sched
+                assert rel(E, refE) <= 1e-12, sched
+                # the residual form b - A x: a solve with the initial guess X and no iteration
+                # reports ||b - A x|| / ||b|| from it
+                _, info = S.solve(B, tol=1e-30, maxit=0, X0=X.copy())
+                assert np.all(np.abs(info["relres_true"] - res) <= 1e-10 * res), sched
+                outs.append((Y, E, info["relres_true"]))
+        finally:
+            hm.set_row_tiling(0)
+        for Y, E, rr in outs[1:]:
+            assert np.array_equal(Y, outs[0][0]) and np.array_equal(E, outs[0][1])
+            assert np.array_equal(rr, outs[0][2])
     S.close()
 
 
