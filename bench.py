@@ -134,6 +134,10 @@ def label_bound(entry):
     if entry.get("traffic"):
         entry["measured_arithmetic_intensity"] = entry["flops_per_launch"] / entry["traffic"]
         entry["bandwidth_limited_in_practice"] = entry["measured_arithmetic_intensity"] < ridge
+        # the measured HBM traffic against the HBM roof (how busy the memory system is)
+        gbs = entry["traffic"] / (entry["avg_ms"] * 1e-3) * 1e-9
+        entry["measured_traffic_gbs"] = gbs
+        entry["measured_traffic_frac_of_hbm_peak"] = gbs / 8000.0
     if ai >= ridge:
         entry.update(bound="mfma", achieved=entry["tflops"], peak=entry["mfma_peak"], unit="TFLOP/s",
                      frac=entry["tflops"] / entry["mfma_peak"])
