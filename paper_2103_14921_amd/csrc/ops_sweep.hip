@@ -382,6 +382,61 @@ struct BoxCtx {
       }
     }
   }
+  // The same operand with NEB columns of one node per thread (LPB = RG / NEB
+  // lanes per node; NEB = 2 in FP64, where build() takes one): the nine
+  // coupling coefficients are loaded once for NEB columns and all loads of a
+  // thread's entry are issued before any is used, so the build waits on L2
+  // half as often.  Every entry sums its terms in the order build() does, so
+  // the operand is the same bit for bit.
+  template <int NEB>
+  __device__ __forceinline__ void build_plane_ne(int k, int dz, bool with_u, cpx<T>* Bs, int t0, int nt) const {
+    constexpr int LPB = RG / NEB;
+    const int b = sb.b, ex = sb.ex, ey = sb.ey, bp = sb.bp;
+    const bool taps_on = k + dz >= 0 && k + dz < sb.ez;
+    const int yo = (k + dz) * bp * nrhs;
+#pragma unroll 1
+    for (int e = t0; e < bp * LPB; e += nt) {
+      const int p = e / LPB, r = e % LPB;
+      cpx<T> v[NEB];
+#pragma unroll
+      for (int j = 0; j < NEB; ++j) v[j] = mk<T>(0, 0);
+      if (p < b) {
+        int col[NEB];
+#pragma unroll
+        for (int j = 0; j < NEB; ++j) col[j] = min(r + j * LPB, nrg - 1);
+        if (with_u) {
+          const long long gu = gnode(k, p) * nrhs + r0;
+#pragma unroll
+          for (int j = 0; j < NEB; ++j) v[j] = ccast<T>(u[gu + col[j]]);
+        }
+        if (taps_on) {
+          const int px = p % ex, py = p / ex;
+          const int ro = (k * b + p) * 18 + (dz + 1) / 2 * 9;
+          cpx<T> cv[9], yv[9][NEB];
+#pragma unroll
+          for (int i = 0; i < 9; ++i) {
+            const int cx = px + i % 3 - 1, cy = py + i / 3 - 1;
+            const bool in = cx >= 0 && cx < ex && cy >= 0 && cy < ey;  // taps leaving the box have zero coefficients
+            const int qi = yo + (in ? cx + ex * cy : p) * nrhs;
+            cv[i] = cbox[ro + i];
+#pragma unroll
+            for (int j = 0; j < NEB; ++j) yv[i][j] = yb[qi + col[j]];
+          }
+#pragma unroll
+          for (int i = 0; i < 9; ++i)
+#pragma unroll
+            for (int j = 0; j < NEB; ++j) cfms(v[j], cv[i], yv[i][j]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NEB; ++j) put_operand<T, RG>(Bs, p, r + j * LPB, r + j * LPB < nrg ? v[j] : mk<T>(0, 0));
+    }
+  }
+  template <int NEB>
+  __device__ __forceinline__ void build_step_ne(int s, cpx<T>* Bs, int t0, int nt) const {
+    if (s < sb.ez) build_plane_ne<NEB>(s, -1, true, Bs, t0, nt);
+    else build_plane_ne<NEB>(plane_of(s), +1, false, Bs, t0, nt);
+  }
   // core node (k, p) of the box: z = x (+ add)
   __device__ __forceinline__ void scatter(int k, int p, int r, cpx<T> val) const {
     if (k < sb.lo[2] - sb.elo[2] || k >= sb.hi[2] - sb.elo[2] || p >= sb.b || r >= nrg) return;
@@ -457,9 +512,19 @@ __global__ void __launch_bounds__(64 * fused_max_waves<T>(), MINW) k_oras_fused(
   const BoxCtx<T, RG> bx(subs, item, ngroups, nrhs, cpl, u, z, add, gnx, gny, yloc);
   const int bp = bx.sb.bp, ns = bx.nsteps();
   for (int st = 0; st < ns; ++st) {
-    bx.template build_step<(MINW > 1)>(st, Bs, ht, hw * 64);
-    cpx<T> a[PF][4];  // per plane, so nothing stays live across the operand build
-    ChunkStream<T> cs = prefetch_tile<T, PF>(bx.factor(sinv, st), bp, wv, hw, lane, a);  // across the barrier
+    cpx<T> a[PF][4];
+    ChunkStream<T> cs;
+    if constexpr (sizeof(T) == 8 && MINW == 1 && RG >= 16) {
+      // the first factor chunk is in flight during the operand build
+      cs = ChunkStream<T>(bx.factor(sinv, st), bp, wv, hw, lane);
+      cs.next(a[0]);
+      bx.template build_step_ne<2>(st, Bs, ht, hw * 64);
+#pragma unroll
+      for (int j = 1; j < PF; ++j) cs.next(a[j]);
+    } else {
+      bx.template build_step<(MINW > 1)>(st, Bs, ht, hw * 64);
+      cs = prefetch_tile<T, PF>(bx.factor(sinv, st), bp, wv, hw, lane, a);  // across the barrier
+    }
     __syncthreads();
     plane_product<T, RG, PF>(
         cs, Bs, wv, hw, lane, a, [&](int p, int r) { return bx.init(st, p, r); },
