@@ -285,8 +285,9 @@ helm_status helm_graph_stats(const helm_handle_t* h, double out[2]);
  * one-workgroup-per-box sweep; 2 uses the pipelined persistent sweep (two
  * boxes per compute unit, operand build overlapped with the matrix-core
  * product) wherever its two operand slots fit in LDS; 3 uses the
- * one-workgroup-per-box sweep built for two workgroups per compute unit
- * (complex FP64, groups of 32 right-hand sides, planes of up to 144 nodes)
+ * one-workgroup-per-box sweep built for fewer registers -- two workgroups per
+ * compute unit for complex FP64 groups of 32 right-hand sides (planes of up
+ * to 144 nodes), four waves per SIMD for complex FP64 groups of 16 --
  * wherever it exists, else as 1; 4 uses the pipelined sweep with eight
  * producer waves beside the eight consumers (16 waves) wherever the pipelined
  * sweep fits, else as 1; 5 uses the paired sweep (two right-hand-side groups of

@@ -388,7 +388,7 @@ struct BoxCtx {
   // thread's entry are issued before any is used, so the build waits on L2
   // half as often.  Every entry sums its terms in the order build() does, so
   // the operand is the same bit for bit.
-  template <int NEB>
+  template <int NEB, int TB = 9>
   __device__ __forceinline__ void build_plane_ne(int k, int dz, bool with_u, cpx<T>* Bs, int t0, int nt) const {
     constexpr int LPB = RG / NEB;
     const int b = sb.b, ex = sb.ex, ey = sb.ey, bp = sb.bp;
@@ -412,30 +412,36 @@ struct BoxCtx {
         if (taps_on) {
           const int px = p % ex, py = p / ex;
           const int ro = (k * b + p) * 18 + (dz + 1) / 2 * 9;
-          cpx<T> cv[9], yv[9][NEB];
+          // the nine taps in batches of TB: all loads of a batch are issued before any is used
 #pragma unroll
-          for (int i = 0; i < 9; ++i) {
-            const int cx = px + i % 3 - 1, cy = py + i / 3 - 1;
-            const bool in = cx >= 0 && cx < ex && cy >= 0 && cy < ey;  // taps leaving the box have zero coefficients
-            const int qi = yo + (in ? cx + ex * cy : p) * nrhs;
-            cv[i] = cbox[ro + i];
+          for (int i0 = 0; i0 < 9; i0 += TB) {
+            cpx<T> cv[TB], yv[TB][NEB];
 #pragma unroll
-            for (int j = 0; j < NEB; ++j) yv[i][j] = yb[qi + col[j]];
+            for (int n = 0; n < TB; ++n) {
+              const int i = min(i0 + n, 8);
+              const int cx = px + i % 3 - 1, cy = py + i / 3 - 1;
+              const bool in = cx >= 0 && cx < ex && cy >= 0 && cy < ey;  // taps leaving the box have zero coefficients
+              const int qi = yo + (in ? cx + ex * cy : p) * nrhs;
+              cv[n] = cbox[ro + i];
+#pragma unroll
+              for (int j = 0; j < NEB; ++j) yv[n][j] = yb[qi + col[j]];
+            }
+#pragma unroll
+            for (int n = 0; n < TB; ++n)
+              if (i0 + n < 9)
+#pragma unroll
+                for (int j = 0; j < NEB; ++j) cfms(v[j], cv[n], yv[n][j]);
           }
-#pragma unroll
-          for (int i = 0; i < 9; ++i)
-#pragma unroll
-            for (int j = 0; j < NEB; ++j) cfms(v[j], cv[i], yv[i][j]);
         }
       }
 #pragma unroll
       for (int j = 0; j < NEB; ++j) put_operand<T, RG>(Bs, p, r + j * LPB, r + j * LPB < nrg ? v[j] : mk<T>(0, 0));
     }
   }
-  template <int NEB>
+  template <int NEB, int TB = 9>
   __device__ __forceinline__ void build_step_ne(int s, cpx<T>* Bs, int t0, int nt) const {
-    if (s < sb.ez) build_plane_ne<NEB>(s, -1, true, Bs, t0, nt);
-    else build_plane_ne<NEB>(plane_of(s), +1, false, Bs, t0, nt);
+    if (s < sb.ez) build_plane_ne<NEB, TB>(s, -1, true, Bs, t0, nt);
+    else build_plane_ne<NEB, TB>(plane_of(s), +1, false, Bs, t0, nt);
   }
   // core node (k, p) of the box: z = x (+ add)
   __device__ __forceinline__ void scatter(int k, int p, int r, cpx<T> val) const {
@@ -514,11 +520,11 @@ __global__ void __launch_bounds__(64 * fused_max_waves<T>(), MINW) k_oras_fused(
   for (int st = 0; st < ns; ++st) {
     cpx<T> a[PF][4];
     ChunkStream<T> cs;
-    if constexpr (sizeof(T) == 8 && MINW == 1 && RG >= 16) {
+    if constexpr (sizeof(T) == 8 && (MINW == 1 || MINW == 4) && RG >= 16) {
       // the first factor chunk is in flight during the operand build
       cs = ChunkStream<T>(bx.factor(sinv, st), bp, wv, hw, lane);
       cs.next(a[0]);
-      bx.template build_step_ne<2>(st, Bs, ht, hw * 64);
+      bx.template build_step_ne<2, MINW == 4 ? 5 : 9>(st, Bs, ht, hw * 64);
 #pragma unroll
       for (int j = 1; j < PF; ++j) cs.next(a[j]);
     } else {
@@ -907,6 +913,12 @@ void launch_fused_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax,
       return;
     }
   }
+  if constexpr (sizeof(T) == 8 && RG == 16) {
+    if (lowreg && !pair) {  // registers for four waves per SIMD: the build's taps in two batches
+      launch_fused_k<T, RG, PF, 4>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx, gny, yloc, s);
+      return;
+    }
+  }
   launch_fused_k<T, RG, PF, 1>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx, gny, yloc, s);
 }
 
@@ -1037,7 +1049,8 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
   const int rgmax = fused_group<T>(bpmax, nrhs);
   if (!lds_fits<T>(rgmax, bpmax) && !tbuf) return false;  // the global-operand sweep needs its operand slices
   const int policy = g_sweep_policy.load();
-  if (policy == 3 && lowreg_fits<T>(rgmax, bpmax)) {  // forced: the two-workgroups-per-CU build
+  if (policy == 3 && (lowreg_fits<T>(rgmax, bpmax) || (sizeof(T) == 8 && rgmax == 16 && lds_fits<T>(16, bpmax)))) {
+    // forced: the low-register builds (two workgroups per CU for groups of 32, four waves per SIMD for 16)
     launch_rg<T>(rgmax, min_rounds<T>(bpmax), true, false, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc,
                  tbuf, s);
     return true;
@@ -1093,7 +1106,11 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
         if (waves == last_waves) continue;
         last_waves = waves;
         for (int lr = 0; lr < 2; ++lr) {
-          if (lr && !(rounds == 0 || (rounds == r0 && lowreg_fits<T>(cand, bpmax)))) continue;
+          // lowreg: the 16-wave pipelined build, the FP64 32-group build for two workgroups per CU,
+          // or the FP64 16-group build for four waves per SIMD
+          if (lr && !(rounds == 0 || (rounds == r0 && lowreg_fits<T>(cand, bpmax)) ||
+                      (sizeof(T) == 8 && cand == 16)))
+            continue;
           float tot = 0.f;
           for (int rep = 0; rep < 2; ++rep) {
             (void)hipEventRecord(e0, s);
@@ -1108,7 +1125,7 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
           if (verbose)
             std::fprintf(stderr, "helm:   candidate group %d %s %d waves%s: %.3f ms\n", cand,
                          rounds == 0 ? "pipelined," : "", rounds == 0 ? (lr ? 16 : 12) : waves,
-                         lr && rounds != 0 ? " (two per CU)" : "", tot);
+                         lr && rounds != 0 ? (cand == 16 ? " (four per SIMD)" : " (two per CU)") : "", tot);
           if (tot < best) {
             best = tot;
             tv = {cand, rounds, lr != 0, false};
@@ -1150,7 +1167,7 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
                    (int)sizeof(T) * 8, bpmax, nsub, nrhs, tv.rg,
                    tv.rounds == 0 ? "pipelined," : (tv.pair ? "paired, 2 x" : ""),
                    tv.rounds == 0 ? (tv.lowreg ? 16 : 12) : (nmt + tv.rounds - 1) / tv.rounds,
-                   tv.lowreg && tv.rounds != 0 ? " (two per CU)" : "", best);
+                   tv.lowreg && tv.rounds != 0 ? (tv.rg == 16 ? " (four per SIMD)" : " (two per CU)") : "", best);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = tv;
   }

@@ -1,8 +1,10 @@
 """The implementations of the batched local solves against the oracle.
 
 The one-workgroup-per-box sweep, the pipelined persistent sweep (two boxes
-per compute unit), the one-workgroup-per-box sweep built for two
-workgroups per compute unit (FP64, groups of 32) and the paired sweep (two
+per compute unit), the one-workgroup-per-box sweep built for fewer
+registers (FP64: two workgroups per compute unit for groups of 32, four
+waves per SIMD for groups of 16, e.g. 12 right-hand sides) and the paired
+sweep (two
 right-hand-side groups of a box per workgroup; 20 and 40 right-hand sides
 pair) are forced in turn through the process-wide sweep policy,
 on right-hand-side batches that use full and partial groups of 16 and 32
@@ -39,7 +41,7 @@ def _restore_policy():
     helm.set_sweep_policy("auto")
 
 
-@pytest.mark.parametrize("policy", ["item", "pipelined", "pipelined16", "paired"])
+@pytest.mark.parametrize("policy", ["item", "pipelined", "two_per_cu", "pipelined16", "paired"])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 5e-4)])
 @pytest.mark.parametrize("nrhs", [12, 20, 40])
 def test_fine_sweep_variants_match_oracle(policy, prec, tol, nrhs):
