@@ -383,11 +383,12 @@ struct BoxCtx {
     }
   }
   // The same operand with NEB columns of one node per thread (LPB = RG / NEB
-  // lanes per node; NEB = 2 in FP64, where build() takes one): the nine
-  // coupling coefficients are loaded once for NEB columns and all loads of a
-  // thread's entry are issued before any is used, so the build waits on L2
-  // half as often.  Every entry sums its terms in the order build() does, so
-  // the operand is the same bit for bit.
+  // lanes per node; NEB = 2 in FP64 and 4 in FP32, where build() takes one
+  // and two): each coupling coefficient is loaded once for NEB columns, and
+  // the taps go in batches of TB whose loads are all issued before any is
+  // used, so the build waits on L2 fewer times per entry.  Every entry sums
+  // its terms in the order build() does, so the operand is the same bit for
+  // bit.
   template <int NEB, int TB = 9>
   __device__ __forceinline__ void build_plane_ne(int k, int dz, bool with_u, cpx<T>* Bs, int t0, int nt) const {
     constexpr int LPB = RG / NEB;
@@ -527,6 +528,9 @@ __global__ void __launch_bounds__(64 * fused_max_waves<T>(), MINW) k_oras_fused(
       bx.template build_step_ne<2, MINW == 4 ? 5 : 9>(st, Bs, ht, hw * 64);
 #pragma unroll
       for (int j = 1; j < PF; ++j) cs.next(a[j]);
+    } else if constexpr (sizeof(T) == 4 && RG >= 16) {
+      bx.template build_step_ne<4, 5>(st, Bs, ht, hw * 64);
+      cs = prefetch_tile<T, PF>(bx.factor(sinv, st), bp, wv, hw, lane, a);  // across the barrier
     } else {
       bx.template build_step<(MINW > 1)>(st, Bs, ht, hw * 64);
       cs = prefetch_tile<T, PF>(bx.factor(sinv, st), bp, wv, hw, lane, a);  // across the barrier
