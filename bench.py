@@ -77,6 +77,10 @@ def gpu_solve(helm, w, c_dev, b_dev, precision, weights, timing=False, graphs=Tr
     X, info = S.solve(b_dev, tol=w["tol"], maxit=400, block=block)
     if timing:
         info["sweeps"] = [S.sweep_stats(0), S.sweep_stats(w["levels"] - 1)]
+        # the launches the tuner chose for the dominant sweep, at the batch widths of this solve
+        lv = w["levels"] - 1
+        info["sweep_config"] = {str(nr): S.sweep_config(lv, nr) for nr in (32, 16)
+                                if S.sweep_config(lv, nr)["group"] > 0}
         info["stencil"] = [S.stencil_stats(0), S.stencil_stats(1)]
         info["factor_flops"] = factor_flops(S)
     info["graphs"] = S.graph_stats()
@@ -88,11 +92,12 @@ def gpu_solve(helm, w, c_dev, b_dev, precision, weights, timing=False, graphs=Tr
 PEAK = {"c64": 157.3, "c128": 78.6, "c32": 2500.0}  # dense MFMA TFLOP/s of one MI355X (fp32, fp64, fp16)
 
 
-def measured_traffic(kernel_file, profile_md, algorithmic_bytes):
+def measured_traffic(kernel_file, profile_md, algorithmic_bytes, sweep_config=None):
     """HBM bytes per launch from a committed PMC summary (FETCH_SIZE + WRITE_SIZE of a separate rocprofv3
-    run, calibrated on a plain copy), if the kernel source is unchanged since and the tuner chose the same
-    launch shape (same algorithmic bytes per launch); else None.  Returns (bytes, source description):
-    the figure is not measured in this run, and the line says where it comes from."""
+    run, calibrated on a plain copy), if the kernel source is unchanged since, the step's launches have
+    the same algorithmic bytes and the tuner chose the same launches (sweep_config, per batch width) as
+    in the counter runs; else None.  Returns (bytes, source description): the figure is not measured in
+    this run, and the line says where it comes from."""
     import hashlib
     import re as _re
     root = os.path.dirname(os.path.abspath(__file__))
@@ -104,6 +109,8 @@ def measured_traffic(kernel_file, profile_md, algorithmic_bytes):
             return None, None
         if abs(algorithmic_bytes - data["algorithmic_bytes_per_launch"]) > 1e-6 * algorithmic_bytes:
             return None, None
+        if data.get("sweep_config") is None or sweep_config != data["sweep_config"]:
+            return None, None
         return data["traffic_bytes_per_launch"], (f"profiles/{profile_md}: PMC counters of an earlier run of the "
                                                   f"same kernel source ({data['source_sha256_16']}) and launch "
                                                   f"shape, not measured in this run")
@@ -111,10 +118,11 @@ def measured_traffic(kernel_file, profile_md, algorithmic_bytes):
         return None, None
 
 
-def set_traffic(entry, kernel_file, profile_md):
+def set_traffic(entry, kernel_file, profile_md, sweep_config=None):
     """Attach the measured HBM traffic (or null) and its source to a roofline entry, with the arithmetic
     intensity on that traffic beside the algorithmic one."""
-    traffic, source = measured_traffic(kernel_file, profile_md, entry["bytes_per_launch"])
+    traffic, source = measured_traffic(kernel_file, profile_md, entry["bytes_per_launch"], sweep_config)
+    entry["sweep_config"] = sweep_config
     entry["traffic"], entry["traffic_source"] = traffic, source
     label_bound(entry)
     return entry
@@ -327,6 +335,9 @@ def main():
                          "of them calibrate the capacity, the rest arrive as a Poisson stream")
     ap.add_argument("--serving-max-rhs", type=int, default=64, help="largest request of the serving stream")
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly (no captured iterations)")
+    ap.add_argument("--sweep-policy", default="auto",
+                    help="force a local-solve sweep implementation (helm.SWEEP_POLICIES; e.g. for counter runs "
+                         "that must see the same launches)")
     ap.add_argument("--time-budget", type=float, default=540.0,
                     help="wall-clock seconds (from start) the whole run aims to stay within: after the timed "
                          "steps, each comparison leg runs only if its estimated cost still fits (skipped legs "
@@ -344,6 +355,7 @@ def main():
     from paper_2103_14921_amd import helm
 
     w = WORKLOADS[args.workload]
+    helm.set_sweep_policy(args.sweep_policy)
     c, b = make_inputs(w)
     nrhs = b.shape[0]
     dev = torch.device("cuda:0")
@@ -404,7 +416,8 @@ def main():
         out["roofline"] = roofline_entry(info["sweeps"][1], coarse_dtype)
         out["roofline"]["kernel"] = ("k_oras_fused (coarse level, FP64 complex, MFMA 16x16x4 f64)" if coarse_dtype == "c128"
                                      else "k_oras_fused (coarse level, FP32 complex, MFMA f32)")
-        set_traffic(out["roofline"], "ops_sweep.hip", f"oras_sweep_coarse_{args.workload}_pmc.md")
+        set_traffic(out["roofline"], "ops_sweep.hip", f"oras_sweep_coarse_{args.workload}_pmc.md",
+                    info.get("sweep_config"))
         out["roofline_fine_sweep"] = roofline_entry(info["sweeps"][0], fine_dtype)
     else:
         out["roofline"] = roofline_entry(info["sweeps"][0], fine_dtype)
@@ -483,7 +496,7 @@ def main():
             "solve_roofline_frac": isl["bound"]["seconds"] / isl["timings"]["solve"]}
         if args.workload == "thrust192_mixed":
             set_traffic(out["single_local_form"]["coarse_sweep"], "ops_sweep.hip",
-                        "oras_sweep_coarse_thrust192_single_local_pmc.md")
+                        "oras_sweep_coarse_thrust192_single_local_pmc.md", isl.get("sweep_config"))
         if "fp64_form" in out:
             err = rel_err(helm, torch, Xs, X64)
             out["single_local_form"]["vs_fp64_rel_l2_max"] = float(err.max().item())

@@ -256,6 +256,20 @@ helm_status helm_solve_bound(const helm_handle_t* h, double out[3]);
 helm_status helm_set_sweep_timing(helm_handle_t* h, int32_t enable);
 helm_status helm_sweep_stats(const helm_handle_t* h, int32_t level, double out[4]);
 
+/* The autotuned launch of the batched local solves (eq. oras) of level 0 (fine)
+ * or 1 (coarse) on batches of nrhs right-hand sides under the current sweep
+ * policy: out[0] right-hand-side group, out[1] waves per item (0 for the
+ * pipelined sweep), out[2] the variant, numbered as the sweep policy that
+ * forces it (1 one item per workgroup, 2 pipelined, 3 low-register build,
+ * 4 pipelined with 16 waves, 5 paired), out[3] waves per workgroup; all zero
+ * if that batch width has not been tuned yet.  HELM_EINVAL for a bad level
+ * or nrhs <= 0. */
+helm_status helm_sweep_config(const helm_handle_t* h, int32_t level, int32_t nrhs, int32_t out[4]);
+/* Environment: HELM_TUNE_FILE=path persists the sweep tuner's decisions --
+ * decisions recorded in the file are used as tuned, new ones are appended --
+ * so that separate processes launch the same sweeps; HELM_TUNE_VERBOSE=1
+ * prints every candidate the tuners time; HELM_NO_TUNE=1 skips tuning. */
+
 /* With the same timing on, the fine-grid 27-point products of eq. eq1 inside
  * solves are bracketed too: helm_stencil_stats gives, for kind 0 (y = A x,
  * the Arnoldi product) or 1 (y = b - A x: the (I - A Q) term of eq. 2lvl and

@@ -2112,6 +2112,16 @@ helm_status helm_sweep_stats(const helm_handle_t* H, int32_t level, double out[4
   return HELM_OK;
 }
 
+helm_status helm_sweep_config(const helm_handle_t* H, int32_t level, int32_t nrhs, int32_t out[4]) {
+  if (!H || !out || level < 0 || level > (H->two_level() ? 1 : 0) || nrhs <= 0) return fail(HELM_EINVAL, "bad arguments");
+  const Level& L = level == 0 ? H->fine : H->coarse;
+  int v[4] = {0, 0, 0, 0};
+  if (!tuned_config(L.half ? 2 : (int)elem_size(L.prec) / 2, L.bpmax, L.nsub, nrhs, L.nx, L.ny, v))
+    for (int& x : v) x = 0;
+  for (int i = 0; i < 4; ++i) out[i] = v[i];
+  return HELM_OK;
+}
+
 helm_status helm_stencil_stats(const helm_handle_t* H, int32_t kind, double out[4]) {
   if (!H || !out || kind < 0 || kind > 1) return fail(HELM_EINVAL, "bad arguments");
   for (int i = 0; i < 4; ++i) out[i] = H->sweep_stat[2 + kind][i];

@@ -133,6 +133,9 @@ bool oras_half(const Sub* subs, int nsub, int bpmax, const c32* cpl, const uint4
 void launch_to_half(const Sub* subs, int nsub, int maxez, const c32* sinv, uint4* sinv16, int* sexp, hipStream_t s);
 // right-hand-side group the autotuner chose for this shape (0 = not tuned yet)
 int tuned_group(int es, int bpmax, int nsub, int nrhs, int gnx, int gny);
+// The tuned launch of that key: out = {group, waves per item, variant (numbered as the sweep
+// policy that forces it), waves per workgroup}; false if not tuned yet.
+bool tuned_config(int es, int bpmax, int nsub, int nrhs, int gnx, int gny, int out[4]);
 // process-wide sweep policy: 0 autotune over all variants, 1 one-item sweeps,
 // 2 the pipelined persistent sweep wherever it fits
 void set_sweep_policy(int policy);

@@ -337,50 +337,6 @@ __global__ void k_gj_swap(const Sub* __restrict__ subs, int k, int j0, int bpmax
     Rbuf[((long long)s * NB + jj) * bpmax + c] = A[(long long)(j0 + jj) * bp + c];
 }
 
-// Deferred Gauss-Jordan update of the columns c in [c_lo, c_hi) outside the
-// panel: A[i][c] = (i in panel rows ? 0 : A[i][c]) + sum_jj A[i][j0+jj] R[jj][c].
-// One thread per row and CPT consecutive columns; the panel row is read once.
-template <typename T, int NB, int CPT>
-__global__ void __launch_bounds__(256) k_gj_update(const Sub* __restrict__ subs, int k, int j0, int bpmax, int c_lo,
-                                                   int c_hi, cpx<T>* __restrict__ S, const cpx<T>* __restrict__ Rbuf) {
-  const int s = blockIdx.y;
-  const Sub sb = subs[s];
-  if (k >= sb.ez) return;
-  const int b = sb.b, bp = sb.bp;
-  if (j0 >= b) return;
-  c_hi = min(c_hi, b);
-  if (c_lo >= c_hi) return;
-  const int nbw = min(NB, b - j0);
-  const int ncg = (c_hi - c_lo + CPT - 1) / CPT;
-  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= (long long)b * ncg) return;
-  const int i = (int)(t / ncg), c0 = c_lo + (int)(t % ncg) * CPT;
-  cpx<T>* A = S + (long long)s * bpmax * bpmax;
-  const bool prow = i >= j0 && i < j0 + nbw;
-  cpx<T> acc[CPT];
-#pragma unroll
-  for (int q = 0; q < CPT; ++q) {
-    const int c = c0 + q;
-    acc[q] = (c < c_hi && !prow) ? A[(long long)i * bp + c] : mk<T>(0, 0);
-  }
-  const cpx<T>* Ri = A + (long long)i * bp + j0;
-  const cpx<T>* Rb = Rbuf + (long long)s * NB * bpmax + c0;
-#pragma unroll
-  for (int jj = 0; jj < NB; ++jj) {
-    if (jj < nbw) {
-      const cpx<T> pv = Ri[jj];
-#pragma unroll
-      for (int q = 0; q < CPT; ++q)
-        if (c0 + q < c_hi) cfma(acc[q], pv, Rb[(long long)jj * bpmax + q]);
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < CPT; ++q) {
-    const int c = c0 + q;
-    if (c < c_hi && (c < j0 || c >= j0 + nbw)) A[(long long)i * bp + c] = acc[q];
-  }
-}
-
 // Pivot rows of a block of OB Gauss-Jordan columns [J0, J0 + OB), as they stand
 // after the block's row interchanges (the columns outside the block are only
 // interchanged while the block is processed), for the block's deferred update.
@@ -465,6 +421,72 @@ __global__ void __launch_bounds__(256) k_gj_outer(const Sub* __restrict__ subs, 
       if (i >= b || c >= b || (c >= J0 && c < J0 + nbw)) continue;
       cpx<T>* a = A + (long long)i * bp + c;
       const cpx<T> old = (i >= J0 && i < J0 + nbw) ? mk<T>(0, 0) : *a;
+      *a = mk<T>(old.re + acc[nt][0][v], old.im + acc[nt][1][v]);
+    }
+}
+
+// The panel's deferred update inside its block on matrix cores:
+// A[i][c] = (i in panel rows ? 0 : A[i][c]) + sum_jj A[i][j0 + jj] R[jj][c]
+// for the block's columns c in [J0, J0 + OB) outside the panel, a rank-NB
+// complex product (R = the interchanged pivot rows in Rbuf[s][jj][c]).  A
+// workgroup owns 64 rows of one box's block; the R rows are staged in LDS and
+// each of the four waves forms 16 rows with the planar complex scheme.
+template <typename T, int NB>
+__global__ void __launch_bounds__(256) k_gj_inner(const Sub* __restrict__ subs, int k, int j0, int J0, int bpmax,
+                                                  cpx<T>* __restrict__ S, const cpx<T>* __restrict__ Rbuf) {
+  using V4 = typename Mfma<T>::v4;
+  constexpr int RW = 64 + (sizeof(T) == 4 ? 4 : 2);  // padded LDS row
+  __shared__ cpx<T> Rs[NB][RW];
+  const int s = blockIdx.y;
+  const Sub sb = subs[s];
+  if (k >= sb.ez) return;
+  const int b = sb.b, bp = sb.bp;
+  if (j0 >= b) return;
+  const int nbw = min(NB, b - j0);
+  const int i0 = blockIdx.x * 64;
+  if (i0 >= b) return;
+  cpx<T>* A = S + (long long)s * bpmax * bpmax;
+  for (int e = threadIdx.x; e < NB * 64; e += 256) {
+    const int kk = e / 64, cc = e % 64;
+    Rs[kk][cc] = (kk < nbw && J0 + cc < b) ? Rbuf[((long long)s * NB + kk) * bpmax + J0 + cc] : mk<T>(0, 0);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lrow = lane & 15, lg = lane >> 4;
+  const int row = i0 + 16 * wave + lrow;
+  const cpx<T>* Arow = A + (long long)min(row, b - 1) * bp + j0;  // clamped: rows past b contribute nothing stored
+  V4 acc[4][2];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) acc[nt][0] = acc[nt][1] = V4{0, 0, 0, 0};
+#pragma unroll
+  for (int kc = 0; kc < NB; kc += 16) {
+    cpx<T> av[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int kk = kc + 4 * lg + t;
+      av[t] = kk < nbw ? Arow[kk] : mk<T>(0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const T are = av[t].re, aim = av[t].im, naim = -aim;
+      const int kk = min(kc + 4 * lg + t, NB - 1);  // past the panel: av is zero
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        const cpx<T> tv = Rs[kk][nt * 16 + lrow];
+        acc[nt][0] = Mfma<T>::op(are, tv.re, acc[nt][0]);
+        acc[nt][1] = Mfma<T>::op(are, tv.im, acc[nt][1]);
+        acc[nt][0] = Mfma<T>::op(naim, tv.im, acc[nt][0]);
+        acc[nt][1] = Mfma<T>::op(aim, tv.re, acc[nt][1]);
+      }
+    }
+  }
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + 16 * wave + Mfma<T>::row(lg, v), c = J0 + nt * 16 + lrow;
+      if (i >= b || c >= b || (c >= j0 && c < j0 + nbw)) continue;
+      cpx<T>* a = A + (long long)i * bp + c;
+      const cpx<T> old = (i >= j0 && i < j0 + nbw) ? mk<T>(0, 0) : *a;
       *a = mk<T>(old.re + acc[nt][0][v], old.im + acc[nt][1][v]);
     }
 }
@@ -712,10 +734,8 @@ void gj_panels(const Sub* subs, int nsub, int bpmax, int k, cpx<T>* S, cpx<T>* R
       hipLaunchKernelGGL((k_gj_panel<T, NB, R>), dim3(nsub), dim3(256), 0, s, subs, k, j0, bpmax, S, piv, err);
       hipLaunchKernelGGL((k_gj_swap<T, NB>), dim3((unsigned)ceil_div(bpmax, 256), nsub), dim3(256), 0, s, subs, k, j0,
                          bpmax, S, piv, Rbuf);
-      const int c_hi = std::min(J0 + GJ_OB, bpmax);
-      const long long cells = (long long)bpmax * ((c_hi - J0 + 3) / 4);
-      hipLaunchKernelGGL((k_gj_update<T, NB, 4>), dim3((unsigned)ceil_div(cells, 256), nsub), dim3(256), 0, s, subs,
-                         k, j0, bpmax, J0, c_hi, S, Rbuf);
+      hipLaunchKernelGGL((k_gj_inner<T, NB>), dim3((unsigned)ceil_div(bpmax, 64), nsub), dim3(256), 0, s, subs, k, j0,
+                         J0, bpmax, S, Rbuf);
     }
     if (J0 + GJ_OB >= bpmax && J0 == 0) continue;  // one block covers the matrix: nothing outside it
     hipLaunchKernelGGL(k_gj_rows<T>, dim3((unsigned)ceil_div((long long)GJ_OB * bpmax, 256), nsub), dim3(256), 0, s,

@@ -19,6 +19,7 @@
 #include <cstdlib>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 
 #include "kernels.h"
@@ -1036,6 +1037,40 @@ struct TuneVal {
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
 
+// Tuning decisions persisted across processes: with HELM_TUNE_FILE set, the
+// tuned launches recorded there are taken as tuned (read once, on the first
+// lookup) and every new decision is appended, one line per key:
+//   sweep es bpmax nsub nrhs gnx gny policy  rg rounds lowreg pair
+// so that separate runs (e.g. one per hardware counter) launch the same kernels.
+const char* tune_file() {
+  static const char* f = std::getenv("HELM_TUNE_FILE");
+  return f && *f ? f : nullptr;
+}
+void load_tune_file_locked() {  // with g_tune_mu held
+  static bool loaded = false;
+  if (loaded || !tune_file()) return;
+  loaded = true;
+  FILE* fp = std::fopen(tune_file(), "r");
+  if (!fp) return;
+  char tag[16];
+  TuneKey k{};
+  int rg, rounds, lowreg, pair;
+  while (std::fscanf(fp, "%15s %d %d %d %d %d %d %d %d %d %d %d", tag, &k.es, &k.bpmax, &k.nsub, &k.nrhs, &k.gnx,
+                     &k.gny, &k.policy, &rg, &rounds, &lowreg, &pair) == 12) {
+    if (std::string(tag) == "sweep" && rg > 0) g_tune[k] = TuneVal{rg, rounds, lowreg != 0, pair != 0};
+  }
+  std::fclose(fp);
+}
+void store_tune_locked(const TuneKey& k, const TuneVal& v) {  // with g_tune_mu held
+  g_tune[k] = v;
+  if (!tune_file()) return;
+  if (FILE* fp = std::fopen(tune_file(), "a")) {
+    std::fprintf(fp, "sweep %d %d %d %d %d %d %d %d %d %d %d\n", k.es, k.bpmax, k.nsub, k.nrhs, k.gnx, k.gny, k.policy,
+                 v.rg, v.rounds, v.lowreg ? 1 : 0, v.pair ? 1 : 0);
+    std::fclose(fp);
+  }
+}
+
 }  // namespace
 
 void set_sweep_policy(int policy) { g_sweep_policy.store(policy); }
@@ -1043,8 +1078,28 @@ int sweep_policy() { return g_sweep_policy.load(); }
 
 int tuned_group(int es, int bpmax, int nsub, int nrhs, int gnx, int gny) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_tune_file_locked();
   auto it = g_tune.find({es, bpmax, nsub, nrhs, gnx, gny, g_sweep_policy.load()});
   return it == g_tune.end() ? 0 : it->second.rg;
+}
+
+bool tuned_config(int es, int bpmax, int nsub, int nrhs, int gnx, int gny, int out[4]) {
+  TuneVal tv{0, 0, false, false};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_file_locked();
+    auto it = g_tune.find({es, bpmax, nsub, nrhs, gnx, gny, g_sweep_policy.load()});
+    if (it == g_tune.end()) return false;
+    tv = it->second;
+  }
+  const int nmt = bpmax / 16;
+  const int per_item = tv.rounds == 0 ? 0 : (nmt + tv.rounds - 1) / tv.rounds;
+  out[0] = tv.rg;
+  out[1] = per_item;
+  // the variant, numbered as the sweep policies that force it
+  out[2] = tv.rounds == 0 ? (tv.lowreg ? 4 : 2) : (tv.pair ? 5 : (tv.lowreg ? 3 : 1));
+  out[3] = tv.rounds == 0 ? (tv.lowreg ? 16 : 12) : (tv.pair ? 2 * per_item : per_item);
+  return true;
 }
 
 template <typename T>
@@ -1082,6 +1137,7 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
   TuneVal tv{0, 0, false, false};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_file_locked();
     auto it = g_tune.find(key);
     if (it != g_tune.end()) tv = it->second;
   }
@@ -1173,7 +1229,7 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
                    tv.rounds == 0 ? (tv.lowreg ? 16 : 12) : (nmt + tv.rounds - 1) / tv.rounds,
                    tv.lowreg && tv.rounds != 0 ? (tv.rg == 16 ? " (four per SIMD)" : " (two per CU)") : "", best);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[key] = tv;
+    store_tune_locked(key, tv);
   }
   if (tv.rg == 0) {  // untuned (tuning off, or inside a capture): the widest group
     tv = {rgmax, r0, false, false};
@@ -1244,6 +1300,7 @@ bool oras_half(const Sub* subs, int nsub, int bpmax, const c32* cpl, const uint4
   TuneVal tv{0, 0, false, false};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_file_locked();
     auto it = g_tune.find(key);
     if (it != g_tune.end()) tv = it->second;
   }
@@ -1286,7 +1343,7 @@ bool oras_half(const Sub* subs, int nsub, int bpmax, const c32* cpl, const uint4
       std::fprintf(stderr, "helm: fp16 sweep tuned (bp %d, %d boxes, %d rhs): group %d, %d waves, %.3f ms\n", bpmax,
                    nsub, nrhs, tv.rg, (nmt + tv.rounds - 1) / tv.rounds, best);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[key] = tv;
+    store_tune_locked(key, tv);
   }
   if (tv.rg == 0) tv = {rgmax, r0, false};
   launch_half_rg(tv.rg, tv.rounds, subs, nsub, nrhs, bpmax, cpl, sinv16, sexp, maxez, u, z, add, gnx, gny, yloc, s);

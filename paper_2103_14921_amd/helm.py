@@ -42,6 +42,7 @@ EXPORTS = [
     "helm_last_timings", "helm_destroy", "helm_last_error", "helm_set_stream", "helm_apply_A",
     "helm_apply_M", "helm_apply_oras", "helm_restrict", "helm_prolong", "helm_apply_E", "helm_apply_Q",
     "helm_num_subdomains", "helm_subdomain_box", "helm_set_sweep_timing", "helm_sweep_stats", "helm_stencil_stats",
+    "helm_sweep_config",
     "helm_local_solve", "helm_release_workspace", "helm_trim_cache", "helm_set_graphs", "helm_graph_stats",
     "helm_set_sweep_policy",
     "helm_set_row_tiling",
@@ -116,6 +117,7 @@ def _load():
         "helm_subdomain_box": ([P, i32, i32, C.POINTER(i32)], C.c_int),
         "helm_set_sweep_timing": ([P, i32], C.c_int),
         "helm_sweep_stats": ([P, i32, C.POINTER(C.c_double)], C.c_int),
+        "helm_sweep_config": ([P, i32, i32, C.POINTER(C.c_int32)], C.c_int),
         "helm_stencil_stats": ([P, i32, C.POINTER(C.c_double)], C.c_int),
         "helm_local_solve": ([P, i32, i32, i32, P, P], C.c_int),
         "helm_release_workspace": ([P], C.c_int),
@@ -385,6 +387,13 @@ class Solver:
         out = (C.c_double * 4)()
         _check(lib.helm_sweep_stats(self._h, int(level), out))
         return dict(launches=int(out[0]), ms=out[1], flops=out[2], bytes=out[3])
+
+    def sweep_config(self, level=0, nrhs=32):
+        """The autotuned local-solve launch of a level at a batch width: group, waves per item, variant
+        (numbered as the sweep policy that forces it) and waves per workgroup; zeros if not tuned yet."""
+        out = (C.c_int32 * 4)()
+        _check(lib.helm_sweep_config(self._h, int(level), int(nrhs), out), handle=self._h)
+        return dict(group=out[0], waves_per_item=out[1], variant=out[2], waves=out[3])
 
     def stencil_stats(self, kind=0):
         """Timed fine 27-point products of the solves: kind 0 y = A x, 1 y = b - A x."""
