@@ -105,7 +105,7 @@ __device__ __forceinline__ ChunkStream<T> prefetch_tile(const cpx<T>* __restrict
 // each complex output entry (row p, column r).
 // WS is the row stride of the operand in LDS (a wider operand's column block
 // can be multiplied on its own).
-template <typename T, int RG, int PF, int WS = lds_width<T>(RG), typename Init, typename Out>
+template <typename T, int RG, int PF, int WS = lds_width<T>(RG), bool LATE_INIT = false, typename Init, typename Out>
 __device__ __forceinline__ void plane_product(ChunkStream<T>& cs, const cpx<T>* Bs, int wave, int nwaves, int lane,
                                               cpx<T> (&a)[PF][4], Init&& init, Out&& out) {
   using V4 = typename Mfma<T>::v4;
@@ -116,13 +116,23 @@ __device__ __forceinline__ void plane_product(ChunkStream<T>& cs, const cpx<T>* 
   const int nct = cs.nct, total = cs.ntw * cs.nct;
   const cpx<T>* Bcol = Bs + 4 * lg * W + lrow;
   V4 acc[NT][NACC];
+  [[maybe_unused]] cpx<T> y0s[LATE_INIT ? NT : 1][4];
   int mt = wave, kc = 0;
   for (int c0 = 0; c0 < total; c0 += PF) {
 #pragma unroll
     for (int j = 0; j < PF; ++j) {
       if (c0 + j < total) {
         if (kc == 0) {  // accumulators start from init(p, r) (zero, or y_k in the backward sweep)
-          if constexpr (RG >= 16) {
+          if constexpr (RG >= 16 && LATE_INIT) {
+            // FP64: the tile starts from zero and y_k is added at its output, so
+            // the load of y_k is in flight during the tile's products
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+              acc[nt][0] = acc[nt][1] = V4{0, 0, 0, 0};
+#pragma unroll
+              for (int v = 0; v < 4; ++v) y0s[nt][v] = init(mt * 16 + Mfma<T>::row(lg, v), nt * 16 + lrow);
+            }
+          } else if constexpr (RG >= 16) {
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
@@ -160,7 +170,14 @@ __device__ __forceinline__ void plane_product(ChunkStream<T>& cs, const cpx<T>* 
         }
         kc += 16;
         if (kc == 16 * nct) {
-          if constexpr (RG >= 16) {
+          if constexpr (RG >= 16 && LATE_INIT) {
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                out(mt * 16 + Mfma<T>::row(lg, v), nt * 16 + lrow,
+                    mk<T>(y0s[nt][v].re + acc[nt][0][v], y0s[nt][v].im + acc[nt][1][v]));
+          } else if constexpr (RG >= 16) {
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
@@ -537,7 +554,8 @@ __global__ void __launch_bounds__(64 * fused_max_waves<T>(), MINW) k_oras_fused(
       cs = prefetch_tile<T, PF>(bx.factor(sinv, st), bp, wv, hw, lane, a);  // across the barrier
     }
     __syncthreads();
-    plane_product<T, RG, PF>(
+    constexpr bool late = sizeof(T) == 8 && MINW == 1 && RG >= 16;
+    plane_product<T, RG, PF, lds_width<T>(RG), late>(
         cs, Bs, wv, hw, lane, a, [&](int p, int r) { return bx.init(st, p, r); },
         [&](int p, int r, cpx<T> val) { bx.output(st, p, r, val); });
     wg_sync_global();
