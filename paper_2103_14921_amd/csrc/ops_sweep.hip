@@ -554,7 +554,7 @@ __global__ void __launch_bounds__(64 * fused_max_waves<T>(), MINW) k_oras_fused(
       cs = prefetch_tile<T, PF>(bx.factor(sinv, st), bp, wv, hw, lane, a);  // across the barrier
     }
     __syncthreads();
-    constexpr bool late = sizeof(T) == 8 && MINW == 1 && RG >= 16;
+    constexpr bool late = (sizeof(T) == 8 && MINW == 1 && RG >= 16) || (sizeof(T) == 4 && RG >= 16 && !PAIR);
     plane_product<T, RG, PF, lds_width<T>(RG), late>(
         cs, Bs, wv, hw, lane, a, [&](int p, int r) { return bx.init(st, p, r); },
         [&](int p, int r, cpx<T> val) { bx.output(st, p, r, val); });
