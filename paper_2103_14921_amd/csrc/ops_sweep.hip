@@ -407,9 +407,13 @@ struct BoxCtx {
   // used, so the build waits on L2 fewer times per entry.  Every entry sums
   // its terms in the order build() does, so the operand is the same bit for
   // bit.
-  template <int NEB, int TB = 9>
-  __device__ __forceinline__ void build_plane_ne(int k, int dz, bool with_u, cpx<T>* Bs, int t0, int nt) const {
+  template <int NEB, int TB = 9, bool CMAX = false>
+  __device__ __forceinline__ void build_plane_ne(int k, int dz, bool with_u, cpx<T>* Bs, int t0, int nt,
+                                                 unsigned* cmax = nullptr) const {
     constexpr int LPB = RG / NEB;
+    T m[NEB];
+#pragma unroll
+    for (int j = 0; j < NEB; ++j) m[j] = 0;
     const int b = sb.b, ex = sb.ex, ey = sb.ey, bp = sb.bp;
     const bool taps_on = k + dz >= 0 && k + dz < sb.ez;
     const int yo = (k + dz) * bp * nrhs;
@@ -454,13 +458,26 @@ struct BoxCtx {
         }
       }
 #pragma unroll
-      for (int j = 0; j < NEB; ++j) put_operand<T, RG>(Bs, p, r + j * LPB, r + j * LPB < nrg ? v[j] : mk<T>(0, 0));
+      for (int j = 0; j < NEB; ++j) {
+        const cpx<T> w = r + j * LPB < nrg ? v[j] : mk<T>(0, 0);
+        put_operand<T, RG>(Bs, p, r + j * LPB, w);
+        if constexpr (CMAX) m[j] = fmax(m[j], fmax(fabs(w.re), fabs(w.im)));
+      }
+    }
+    if constexpr (CMAX) {  // column maxima, as build_plane's (nt a multiple of 64, so lanes keep their columns)
+      static_assert(sizeof(T) == 4, "column maxima of complex FP32 operands");
+      const int lane = t0 & 63, r = t0 % LPB;
+#pragma unroll
+      for (int j = 0; j < NEB; ++j) {
+        for (int off = LPB; off < 64; off <<= 1) m[j] = fmax(m[j], __shfl_xor(m[j], off));
+        if (lane < LPB) atomicMax(&cmax[r + j * LPB], __float_as_uint(m[j]));
+      }
     }
   }
-  template <int NEB, int TB = 9>
-  __device__ __forceinline__ void build_step_ne(int s, cpx<T>* Bs, int t0, int nt) const {
-    if (s < sb.ez) build_plane_ne<NEB, TB>(s, -1, true, Bs, t0, nt);
-    else build_plane_ne<NEB, TB>(plane_of(s), +1, false, Bs, t0, nt);
+  template <int NEB, int TB = 9, bool CMAX = false>
+  __device__ __forceinline__ void build_step_ne(int s, cpx<T>* Bs, int t0, int nt, unsigned* cmax = nullptr) const {
+    if (s < sb.ez) build_plane_ne<NEB, TB, CMAX>(s, -1, true, Bs, t0, nt, cmax);
+    else build_plane_ne<NEB, TB, CMAX>(plane_of(s), +1, false, Bs, t0, nt, cmax);
   }
   // core node (k, p) of the box: z = x (+ add)
   __device__ __forceinline__ void scatter(int k, int p, int r, cpx<T> val) const {
@@ -743,7 +760,7 @@ __global__ void __launch_bounds__(64 * 16) k_oras_half(const Sub* __restrict__ s
   for (int st = 0; st < ns; ++st) {
     const int cb = st & 1, k = bx.plane_of(st);
     for (int i = tid; i < RG; i += FT) cmax[cb ^ 1][i] = 0u;
-    bx.template build_step<false, true>(st, Bs, tid, FT, cmax[cb]);
+    bx.template build_step_ne<4, 5, true>(st, Bs, tid, FT, cmax[cb]);
     uint4 a[PF];
     HalfStream cs(sinv16 + (bx.sb.mat_off + (long long)k * bp * bp) / 4, bp, wave, nwaves, lane);
 #pragma unroll
