@@ -335,6 +335,11 @@ def main():
                          "of them calibrate the capacity, the rest arrive as a Poisson stream")
     ap.add_argument("--serving-max-rhs", type=int, default=64, help="largest request of the serving stream")
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly (no captured iterations)")
+    ap.add_argument("--retune", action="store_true",
+                    help="tune the local-solve sweeps live instead of starting from the sweep decisions shipped in "
+                         "paper_2103_14921_amd/tuned/mi355x_sweeps.txt (decisions within the timing noise of each "
+                         "other can differ between processes; the shipped ones are those the committed counter "
+                         "profiles were taken with)")
     ap.add_argument("--sweep-policy", default="auto",
                     help="force a local-solve sweep implementation (helm.SWEEP_POLICIES; e.g. for counter runs "
                          "that must see the same launches)")
@@ -349,6 +354,19 @@ def main():
         print("bench.py measures one GPU: the solver is a single-device library (no collectives); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if not args.retune and "HELM_TUNE_FILE" not in os.environ:
+        # a private copy: decisions for shapes the file does not hold are appended to it, not to the shipped file
+        import shutil
+        import tempfile
+        shipped = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2103_14921_amd", "tuned",
+                               "mi355x_sweeps.txt")
+        fd, tune_copy = tempfile.mkstemp(prefix="helm_tune_", suffix=".txt")
+        os.close(fd)
+        shutil.copyfile(shipped, tune_copy)
+        os.environ["HELM_TUNE_FILE"] = tune_copy
+        import atexit
+        atexit.register(lambda: os.path.exists(tune_copy) and os.remove(tune_copy))
 
     import torch
 
