@@ -261,7 +261,8 @@ helm_status helm_sweep_stats(const helm_handle_t* h, int32_t level, double out[4
  * policy: out[0] right-hand-side group, out[1] waves per item (0 for the
  * pipelined sweep), out[2] the variant, numbered as the sweep policy that
  * forces it (1 one item per workgroup, 2 pipelined, 3 low-register build,
- * 4 pipelined with 16 waves, 5 paired), out[3] waves per workgroup; all zero
+ * 4 pipelined with 16 waves, 5 paired, 6 paired with the plane solutions in
+ * LDS), out[3] waves per workgroup; all zero
  * if that batch width has not been tuned yet.  HELM_EINVAL for a bad level
  * or nrhs <= 0. */
 helm_status helm_sweep_config(const helm_handle_t* h, int32_t level, int32_t nrhs, int32_t out[4]);
@@ -299,16 +300,18 @@ helm_status helm_graph_stats(const helm_handle_t* h, double out[2]);
  * one-workgroup-per-box sweep; 2 uses the pipelined persistent sweep (two
  * boxes per compute unit, operand build overlapped with the matrix-core
  * product) wherever its two operand slots fit in LDS; 3 uses the
- * one-workgroup-per-box sweep built for fewer registers -- two workgroups per
- * compute unit for complex FP64 groups of 32 right-hand sides (planes of up
- * to 144 nodes), four waves per SIMD for complex FP64 groups of 16 --
+ * one-workgroup-per-box sweep built for two workgroups per compute unit
+ * (complex FP64, groups of 32 right-hand sides, planes of up to 144 nodes)
  * wherever it exists, else as 1; 4 uses the pipelined sweep with eight
  * producer waves beside the eight consumers (16 waves) wherever the pipelined
  * sweep fits, else as 1; 5 uses the paired sweep (two right-hand-side groups of
  * one box per workgroup, each on half of its waves, so that both stream the
  * box's factors in step and the second read hits L2) wherever the batch
  * splits into an even number of groups whose two operands fit in LDS, else
- * as 0.  Planes whose operand does not fit in LDS
+ * as 0; 6 uses the paired sweep that also keeps each item's last plane
+ * solution in LDS (complex FP64 groups of 16 whose operands and solutions
+ * fit), so that a plane step needs only a workgroup barrier, else as 0.
+ * Planes whose operand does not fit in LDS
  * (complex FP64 above 600 nodes, complex FP32 above 1200) keep it in global
  * memory under every policy.  Results agree to rounding.  Graphs captured
  * under one policy are not replayed under another. */

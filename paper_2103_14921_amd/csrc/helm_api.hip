@@ -2075,7 +2075,7 @@ helm_status helm_set_graphs(helm_handle_t* H, int32_t enable) {
 }
 
 helm_status helm_set_sweep_policy(int32_t policy) {
-  if (policy < 0 || policy > 5) return fail(HELM_EINVAL, "sweep policy must be 0, 1, 2, 3, 4 or 5");
+  if (policy < 0 || policy > 6) return fail(HELM_EINVAL, "sweep policy must be 0, 1, 2, 3, 4, 5 or 6");
   set_sweep_policy(policy);
   return HELM_OK;
 }

@@ -407,9 +407,10 @@ struct BoxCtx {
   // used, so the build waits on L2 fewer times per entry.  Every entry sums
   // its terms in the order build() does, so the operand is the same bit for
   // bit.
-  template <int NEB, int TB = 9, bool CMAX = false>
+  // ys: the neighbouring plane's solution in LDS ([bp][RG], this item's columns), else read from yloc
+  template <int NEB, int TB = 9, bool CMAX = false, bool YS = false>
   __device__ __forceinline__ void build_plane_ne(int k, int dz, bool with_u, cpx<T>* Bs, int t0, int nt,
-                                                 unsigned* cmax = nullptr) const {
+                                                 unsigned* cmax = nullptr, const cpx<T>* ys = nullptr) const {
     constexpr int LPB = RG / NEB;
     T m[NEB];
 #pragma unroll
@@ -444,10 +445,16 @@ struct BoxCtx {
               const int i = min(i0 + n, 8);
               const int cx = px + i % 3 - 1, cy = py + i / 3 - 1;
               const bool in = cx >= 0 && cx < ex && cy >= 0 && cy < ey;  // taps leaving the box have zero coefficients
-              const int qi = yo + (in ? cx + ex * cy : p) * nrhs;
+              const int q = in ? cx + ex * cy : p;
               cv[n] = cbox[ro + i];
+              if constexpr (YS) {
 #pragma unroll
-              for (int j = 0; j < NEB; ++j) yv[n][j] = yb[qi + col[j]];
+                for (int j = 0; j < NEB; ++j) yv[n][j] = ys[q * RG + col[j]];
+              } else {
+                const int qi = yo + q * nrhs;
+#pragma unroll
+                for (int j = 0; j < NEB; ++j) yv[n][j] = yb[qi + col[j]];
+              }
             }
 #pragma unroll
             for (int n = 0; n < TB; ++n)
@@ -474,10 +481,11 @@ struct BoxCtx {
       }
     }
   }
-  template <int NEB, int TB = 9, bool CMAX = false>
-  __device__ __forceinline__ void build_step_ne(int s, cpx<T>* Bs, int t0, int nt, unsigned* cmax = nullptr) const {
-    if (s < sb.ez) build_plane_ne<NEB, TB, CMAX>(s, -1, true, Bs, t0, nt, cmax);
-    else build_plane_ne<NEB, TB, CMAX>(plane_of(s), +1, false, Bs, t0, nt, cmax);
+  template <int NEB, int TB = 9, bool CMAX = false, bool YS = false>
+  __device__ __forceinline__ void build_step_ne(int s, cpx<T>* Bs, int t0, int nt, unsigned* cmax = nullptr,
+                                                const cpx<T>* ys = nullptr) const {
+    if (s < sb.ez) build_plane_ne<NEB, TB, CMAX, YS>(s, -1, true, Bs, t0, nt, cmax, ys);
+    else build_plane_ne<NEB, TB, CMAX, YS>(plane_of(s), +1, false, Bs, t0, nt, cmax, ys);
   }
   // core node (k, p) of the box: z = x (+ add)
   __device__ __forceinline__ void scatter(int k, int p, int r, cpx<T> val) const {
@@ -529,12 +537,18 @@ struct BoxCtx {
 // (half_elems elements apart in LDS).  Both halves stream the same factor
 // chunks within the same plane step, so the second read of each chunk mostly
 // hits L2, and the factors cross HBM about once per application.
-template <typename T, int RG, int PF, int MINW, bool PAIR>
+// YLDS (FP64 paired sweep): each item also keeps its last plane solution in LDS
+// ([bp][RG] at ys_off elements after its operand), written by the products
+// beside yloc; the next plane's operand build reads its neighbours there, so a
+// plane step needs only a workgroup barrier, and the release/acquire through
+// L2 happens once, when the forward sweep turns (the backward products start
+// from y_k in yloc).
+template <typename T, int RG, int PF, int MINW, bool PAIR, bool YLDS = false>
 __global__ void __launch_bounds__(64 * fused_max_waves<T>(), MINW) k_oras_fused(const Sub* __restrict__ subs, int ngroups, int nrhs,
                                                    const cpx<T>* __restrict__ cpl, const cpx<T>* __restrict__ sinv,
                                                    const z64* __restrict__ u, z64* __restrict__ z,
                                                    const z64* __restrict__ add, int gnx, int gny,
-                                                   cpx<T>* __restrict__ yloc, int half_elems) {
+                                                   cpx<T>* __restrict__ yloc, int half_elems, int ys_off) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int FT = blockDim.x, nwaves = FT >> 6;
@@ -556,11 +570,11 @@ __global__ void __launch_bounds__(64 * fused_max_waves<T>(), MINW) k_oras_fused(
   for (int st = 0; st < ns; ++st) {
     cpx<T> a[PF][4];
     ChunkStream<T> cs;
-    if constexpr (sizeof(T) == 8 && (MINW == 1 || MINW == 4) && RG >= 16) {
+    if constexpr (sizeof(T) == 8 && MINW == 1 && RG >= 16) {
       // the first factor chunk is in flight during the operand build
       cs = ChunkStream<T>(bx.factor(sinv, st), bp, wv, hw, lane);
       cs.next(a[0]);
-      bx.template build_step_ne<2, MINW == 4 ? 5 : 9>(st, Bs, ht, hw * 64);
+      bx.template build_step_ne<2, 9, false, YLDS>(st, Bs, ht, hw * 64, nullptr, Bs + ys_off);
 #pragma unroll
       for (int j = 1; j < PF; ++j) cs.next(a[j]);
     } else if constexpr (sizeof(T) == 4 && RG >= 16) {
@@ -574,8 +588,16 @@ __global__ void __launch_bounds__(64 * fused_max_waves<T>(), MINW) k_oras_fused(
     constexpr bool late = (sizeof(T) == 8 && MINW == 1 && RG >= 16) || (sizeof(T) == 4 && RG >= 16 && !PAIR);
     plane_product<T, RG, PF, lds_width<T>(RG), late>(
         cs, Bs, wv, hw, lane, a, [&](int p, int r) { return bx.init(st, p, r); },
-        [&](int p, int r, cpx<T> val) { bx.output(st, p, r, val); });
-    wg_sync_global();
+        [&](int p, int r, cpx<T> val) {
+          bx.output(st, p, r, val);
+          if constexpr (YLDS) Bs[ys_off + p * RG + r] = val;
+        });
+    if constexpr (YLDS) {
+      if (st == bx.sb.ez - 1) wg_sync_global();  // the forward solutions in yloc, for the backward products
+      else __syncthreads();
+    } else {
+      wg_sync_global();
+    }
   }
 }
 
@@ -899,15 +921,16 @@ void launch_gl_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, in
                      u, z, add, gnx, gny, yloc, tglob, bpmax);
 }
 
-template <typename T, int RG, int PF, int MINW, bool PAIR = false>
+template <typename T, int RG, int PF, int MINW, bool PAIR = false, bool YLDS = false>
 void launch_fused_k(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, int rounds, const cpx<T>* cpl,
                     const cpx<T>* sinv, const z64* u, z64* z, const z64* add, int gnx, int gny, cpx<T>* yloc,
                     hipStream_t s) {
-  const int half_elems = bpmax * lds_width<T>(RG);
+  const int ys_off = YLDS ? bpmax * lds_width<T>(RG) : 0;
+  const int half_elems = bpmax * lds_width<T>(RG) + (YLDS ? bpmax * RG : 0);
   const size_t lds = (size_t)(PAIR ? 2 : 1) * half_elems * sizeof(cpx<T>);
   static bool attr = false;  // one per kernel instance
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_oras_fused<T, RG, PF, MINW, PAIR>,
+    (void)hipFuncSetAttribute((const void*)k_oras_fused<T, RG, PF, MINW, PAIR, YLDS>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr = true;
   }
@@ -915,9 +938,9 @@ void launch_fused_k(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax,
   const int nmt = bpmax / 16;
   rounds = std::max(rounds, PAIR ? pair_min_rounds<T>(bpmax) : min_rounds<T>(bpmax));
   const int nwaves = (nmt + rounds - 1) / rounds;
-  hipLaunchKernelGGL((k_oras_fused<T, RG, PF, MINW, PAIR>), dim3(nsub * (PAIR ? ngroups / 2 : ngroups)),
+  hipLaunchKernelGGL((k_oras_fused<T, RG, PF, MINW, PAIR, YLDS>), dim3(nsub * (PAIR ? ngroups / 2 : ngroups)),
                      dim3(64 * nwaves * (PAIR ? 2 : 1)), lds, s, subs, ngroups, nrhs, cpl, sinv, u, z, add, gnx, gny,
-                     yloc, half_elems);
+                     yloc, half_elems, ys_off);
 }
 
 // Whether the paired sweep (two groups of a box per workgroup) exists for this
@@ -926,6 +949,12 @@ template <typename T>
 bool pair_fits(int rg, int bpmax, int nrhs) {
   const int ngroups = (nrhs + rg - 1) / rg;
   return rg >= 16 && ngroups % 2 == 0 && 2 * (size_t)bpmax * lds_width<T>(rg) * sizeof(cpx<T>) <= 160 * 1024;
+}
+// ... and its form with the plane solutions in LDS (FP64 groups of 16)
+template <typename T>
+bool pair_ylds_fits(int rg, int bpmax, int nrhs) {
+  return sizeof(T) == 8 && rg == 16 && pair_fits<T>(rg, bpmax, nrhs) &&
+         2 * (size_t)bpmax * (lds_width<T>(rg) + rg) * sizeof(cpx<T>) <= 160 * 1024;
 }
 
 // Whether the two-workgroups-per-CU build of the sweep exists for this shape:
@@ -936,10 +965,17 @@ bool lowreg_fits(int rg, int bpmax) {
 }
 
 template <typename T, int RG>
-void launch_fused_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, int rounds, bool lowreg, bool pair,
+void launch_fused_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, int rounds, bool lowreg, int pair,
                     const cpx<T>* cpl, const cpx<T>* sinv, const z64* u, z64* z, const z64* add, int gnx, int gny,
                     cpx<T>* yloc, hipStream_t s) {
   constexpr int PF = sizeof(T) == 4 ? 4 : 2;
+  if constexpr (sizeof(T) == 8 && RG == 16) {
+    if (pair == 2) {  // paired, plane solutions in LDS
+      launch_fused_k<T, RG, PF, 1, true, true>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx,
+                                               gny, yloc, s);
+      return;
+    }
+  }
   if constexpr (RG >= 16) {
     if (pair) {
       launch_fused_k<T, RG, PF, 1, true>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx, gny,
@@ -950,12 +986,6 @@ void launch_fused_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax,
   if constexpr (sizeof(T) == 8 && RG == 32) {
     if (lowreg) {  // one factor chunk in flight per wave: five waves per SIMD hide the latency instead
       launch_fused_k<T, RG, 1, 5>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx, gny, yloc, s);
-      return;
-    }
-  }
-  if constexpr (sizeof(T) == 8 && RG == 16) {
-    if (lowreg && !pair) {  // registers for four waves per SIMD: the build's taps in two batches
-      launch_fused_k<T, RG, PF, 4>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx, gny, yloc, s);
       return;
     }
   }
@@ -1020,7 +1050,7 @@ int fused_group(int bpmax, int nrhs) {
 namespace {
 
 template <typename T>
-void launch_rg(int rg, int rounds, bool lowreg, bool pair, const Sub* subs, int nsub, int nrhs, int bpmax,
+void launch_rg(int rg, int rounds, bool lowreg, int pair, const Sub* subs, int nsub, int nrhs, int bpmax,
                const cpx<T>* cpl, const cpx<T>* sinv, const z64* u, z64* z, const z64* add, int gnx, int gny,
                cpx<T>* yloc, cpx<T>* tglob, hipStream_t s) {
   const int ngroups = (nrhs + rg - 1) / rg;
@@ -1067,7 +1097,7 @@ std::atomic<int> g_sweep_policy{0};
 struct TuneVal {
   int rg, rounds;
   bool lowreg;  // the build for two workgroups per compute unit (lowreg_fits)
-  bool pair;    // two groups of a box per workgroup (pair_fits)
+  int pair;     // two groups of a box per workgroup (pair_fits); 2: with the plane solutions in LDS
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
@@ -1092,7 +1122,7 @@ void load_tune_file_locked() {  // with g_tune_mu held
   int rg, rounds, lowreg, pair;
   while (std::fscanf(fp, "%15s %d %d %d %d %d %d %d %d %d %d %d", tag, &k.es, &k.bpmax, &k.nsub, &k.nrhs, &k.gnx,
                      &k.gny, &k.policy, &rg, &rounds, &lowreg, &pair) == 12) {
-    if (std::string(tag) == "sweep" && rg > 0) g_tune[k] = TuneVal{rg, rounds, lowreg != 0, pair != 0};
+    if (std::string(tag) == "sweep" && rg > 0) g_tune[k] = TuneVal{rg, rounds, lowreg != 0, pair};
   }
   std::fclose(fp);
 }
@@ -1101,7 +1131,7 @@ void store_tune_locked(const TuneKey& k, const TuneVal& v) {  // with g_tune_mu 
   if (!tune_file()) return;
   if (FILE* fp = std::fopen(tune_file(), "a")) {
     std::fprintf(fp, "sweep %d %d %d %d %d %d %d %d %d %d %d\n", k.es, k.bpmax, k.nsub, k.nrhs, k.gnx, k.gny, k.policy,
-                 v.rg, v.rounds, v.lowreg ? 1 : 0, v.pair ? 1 : 0);
+                 v.rg, v.rounds, v.lowreg ? 1 : 0, v.pair);
     std::fclose(fp);
   }
 }
@@ -1119,7 +1149,7 @@ int tuned_group(int es, int bpmax, int nsub, int nrhs, int gnx, int gny) {
 }
 
 bool tuned_config(int es, int bpmax, int nsub, int nrhs, int gnx, int gny, int out[4]) {
-  TuneVal tv{0, 0, false, false};
+  TuneVal tv{0, 0, false, 0};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_file_locked();
@@ -1132,7 +1162,7 @@ bool tuned_config(int es, int bpmax, int nsub, int nrhs, int gnx, int gny, int o
   out[0] = tv.rg;
   out[1] = per_item;
   // the variant, numbered as the sweep policies that force it
-  out[2] = tv.rounds == 0 ? (tv.lowreg ? 4 : 2) : (tv.pair ? 5 : (tv.lowreg ? 3 : 1));
+  out[2] = tv.rounds == 0 ? (tv.lowreg ? 4 : 2) : (tv.pair == 2 ? 6 : (tv.pair ? 5 : (tv.lowreg ? 3 : 1)));
   out[3] = tv.rounds == 0 ? (tv.lowreg ? 16 : 12) : (tv.pair ? 2 * per_item : per_item);
   return true;
 }
@@ -1143,16 +1173,20 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
   const int rgmax = fused_group<T>(bpmax, nrhs);
   if (!lds_fits<T>(rgmax, bpmax) && !tbuf) return false;  // the global-operand sweep needs its operand slices
   const int policy = g_sweep_policy.load();
-  if (policy == 3 && (lowreg_fits<T>(rgmax, bpmax) || (sizeof(T) == 8 && rgmax == 16 && lds_fits<T>(16, bpmax)))) {
-    // forced: the low-register builds (two workgroups per CU for groups of 32, four waves per SIMD for 16)
+  if (policy == 3 && lowreg_fits<T>(rgmax, bpmax)) {  // forced: the two-workgroups-per-CU build
     launch_rg<T>(rgmax, min_rounds<T>(bpmax), true, false, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc,
+                 tbuf, s);
+    return true;
+  }
+  if (policy == 6 && pair_ylds_fits<T>(16, bpmax, nrhs)) {  // forced: paired, plane solutions in LDS
+    launch_rg<T>(16, pair_min_rounds<T>(bpmax), false, 2, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc,
                  tbuf, s);
     return true;
   }
   if (policy == 5) {  // forced: the paired sweep with the widest group that pairs
     for (int cand = rgmax; cand >= 16; cand /= 2)
       if (pair_fits<T>(cand, bpmax, nrhs)) {
-        launch_rg<T>(cand, pair_min_rounds<T>(bpmax), false, true, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx,
+        launch_rg<T>(cand, pair_min_rounds<T>(bpmax), false, 1, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx,
                      gny, yloc, tbuf, s);
         return true;
       }
@@ -1169,7 +1203,7 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
   bool any_pipe = false;
   for (int cand = 8; cand <= rgmax; cand *= 2) any_pipe = any_pipe || pipe_fits<T>(cand, bpmax);
   const bool allow_pipe = policy != 1 && policy != 3, allow_item = (policy != 2 && policy != 4) || !any_pipe;
-  TuneVal tv{0, 0, false, false};
+  TuneVal tv{0, 0, false, 0};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_file_locked();
@@ -1201,11 +1235,8 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
         if (waves == last_waves) continue;
         last_waves = waves;
         for (int lr = 0; lr < 2; ++lr) {
-          // lowreg: the 16-wave pipelined build, the FP64 32-group build for two workgroups per CU,
-          // or the FP64 16-group build for four waves per SIMD
-          if (lr && !(rounds == 0 || (rounds == r0 && lowreg_fits<T>(cand, bpmax)) ||
-                      (sizeof(T) == 8 && cand == 16)))
-            continue;
+          // lowreg: the 16-wave pipelined build, or the FP64 32-group build for two workgroups per CU
+          if (lr && !(rounds == 0 || (rounds == r0 && lowreg_fits<T>(cand, bpmax)))) continue;
           float tot = 0.f;
           for (int rep = 0; rep < 2; ++rep) {
             (void)hipEventRecord(e0, s);
@@ -1220,15 +1251,17 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
           if (verbose)
             std::fprintf(stderr, "helm:   candidate group %d %s %d waves%s: %.3f ms\n", cand,
                          rounds == 0 ? "pipelined," : "", rounds == 0 ? (lr ? 16 : 12) : waves,
-                         lr && rounds != 0 ? (cand == 16 ? " (four per SIMD)" : " (two per CU)") : "", tot);
+                         lr && rounds != 0 ? " (two per CU)" : "", tot);
           if (tot < best) {
             best = tot;
-            tv = {cand, rounds, lr != 0, false};
+            tv = {cand, rounds, lr != 0, 0};
           }
         }
       }
       // the paired sweep: two groups of a box per workgroup
-      if ((policy == 0 || policy == 5) && pair_fits<T>(cand, bpmax, nrhs)) {
+      for (int pm = 1; pm <= 2; ++pm) {
+        if (!(policy == 0 || policy == 5 || policy == 6) || !pair_fits<T>(cand, bpmax, nrhs)) break;
+        if (pm == 2 && !pair_ylds_fits<T>(cand, bpmax, nrhs)) break;
         const int pr0 = pair_min_rounds<T>(bpmax);
         int last = 0;
         for (int rounds = pr0; rounds <= pr0 + 2; ++rounds) {
@@ -1238,8 +1271,8 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
           float tot = 0.f;
           for (int rep = 0; rep < 2; ++rep) {
             (void)hipEventRecord(e0, s);
-            launch_rg<T>(cand, rounds, false, true, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc,
-                         tbuf, s);
+            launch_rg<T>(cand, rounds, false, pm, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, tbuf,
+                         s);
             (void)hipEventRecord(e1, s);
             (void)hipEventSynchronize(e1);
             float ms = 0.f;
@@ -1247,10 +1280,11 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
             if (rep > 0) tot += ms;
           }
           if (verbose)
-            std::fprintf(stderr, "helm:   candidate group %d paired, 2 x %d waves: %.3f ms\n", cand, waves, tot);
+            std::fprintf(stderr, "helm:   candidate group %d paired%s, 2 x %d waves: %.3f ms\n", cand,
+                         pm == 2 ? " (solutions in LDS)" : "", waves, tot);
           if (tot < best) {
             best = tot;
-            tv = {cand, rounds, false, true};
+            tv = {cand, rounds, false, pm};
           }
         }
       }
@@ -1260,18 +1294,18 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
     if (verbose)
       std::fprintf(stderr, "helm: sweep tuned (fp%d, bp %d, %d boxes, %d rhs): group %d, %s %d waves%s, %.3f ms\n",
                    (int)sizeof(T) * 8, bpmax, nsub, nrhs, tv.rg,
-                   tv.rounds == 0 ? "pipelined," : (tv.pair ? "paired, 2 x" : ""),
+                   tv.rounds == 0 ? "pipelined," : (tv.pair == 2 ? "paired (LDS solutions), 2 x" : (tv.pair ? "paired, 2 x" : "")),
                    tv.rounds == 0 ? (tv.lowreg ? 16 : 12) : (nmt + tv.rounds - 1) / tv.rounds,
-                   tv.lowreg && tv.rounds != 0 ? (tv.rg == 16 ? " (four per SIMD)" : " (two per CU)") : "", best);
+                   tv.lowreg && tv.rounds != 0 ? " (two per CU)" : "", best);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     store_tune_locked(key, tv);
   }
   if (tv.rg == 0) {  // untuned (tuning off, or inside a capture): the widest group
-    tv = {rgmax, r0, false, false};
+    tv = {rgmax, r0, false, 0};
     if (!allow_item) {
       for (int cand = rgmax; cand >= 16; cand /= 2)
         if (pipe_fits<T>(cand, bpmax)) {
-          tv = {cand, 0, false, false};
+          tv = {cand, 0, false, 0};
           break;
         }
     }
@@ -1332,7 +1366,7 @@ bool oras_half(const Sub* subs, int nsub, int bpmax, const c32* cpl, const uint4
   const int rgmax = half_group(bpmax, nrhs);
   if (rgmax == 0) return false;
   const TuneKey key{2, bpmax, nsub, nrhs, gnx, gny, g_sweep_policy.load()};
-  TuneVal tv{0, 0, false, false};
+  TuneVal tv{0, 0, false, 0};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_file_locked();

@@ -255,7 +255,8 @@ class Request:
             pass
 
 
-SWEEP_POLICIES = {"auto": 0, "item": 1, "pipelined": 2, "two_per_cu": 3, "pipelined16": 4, "paired": 5}
+SWEEP_POLICIES = {"auto": 0, "item": 1, "pipelined": 2, "two_per_cu": 3, "pipelined16": 4, "paired": 5,
+                  "paired_lds": 6}
 
 
 def set_sweep_policy(policy):

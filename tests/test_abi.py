@@ -72,7 +72,7 @@ def test_process_wide_settings_reject_bad_values():
             helm.set_row_tiling(bad)
         assert e.value.code == helm.HELM_EINVAL
     helm.set_row_tiling(helm.HELM_TILE_MARCH | 3)
-    assert helm.lib.helm_set_sweep_policy(6) == helm.HELM_EINVAL
+    assert helm.lib.helm_set_sweep_policy(7) == helm.HELM_EINVAL
     for bad in (1, 2, 12, 32):
         with pytest.raises(helm.HelmError):
             helm.set_lu_panel(bad)

@@ -1,12 +1,11 @@
 """The implementations of the batched local solves against the oracle.
 
 The one-workgroup-per-box sweep, the pipelined persistent sweep (two boxes
-per compute unit), the one-workgroup-per-box sweep built for fewer
-registers (FP64: two workgroups per compute unit for groups of 32, four
-waves per SIMD for groups of 16, e.g. 12 right-hand sides) and the paired
-sweep (two
+per compute unit), the one-workgroup-per-box sweep built for two
+workgroups per compute unit (FP64, groups of 32) and the paired sweep (two
 right-hand-side groups of a box per workgroup; 20 and 40 right-hand sides
-pair) are forced in turn through the process-wide sweep policy,
+pair), also with the plane solutions kept in LDS (FP64 coarse level), are
+forced in turn through the process-wide sweep policy,
 on right-hand-side batches that use full and partial groups of 16 and 32
 columns, on the fine level (FP64 and complex FP32 factors) and on the coarse
 level; each result is compared with the oracle's one-level ORAS applied per
@@ -61,7 +60,7 @@ def test_fine_sweep_variants_match_oracle(policy, prec, tol, nrhs):
     S.close()
 
 
-@pytest.mark.parametrize("policy", ["item", "pipelined", "two_per_cu", "pipelined16", "paired"])
+@pytest.mark.parametrize("policy", ["item", "pipelined", "two_per_cu", "pipelined16", "paired", "paired_lds"])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("single_local", 5e-4)])
 def test_coarse_sweep_variants_match_oracle(policy, prec, tol):
     from paper_2103_14921_amd import helm
@@ -87,14 +86,14 @@ def test_policies_agree_in_a_two_level_solve():
     src = inputs.source_grid(shape[0], shape[1], 5, 5, 4, 5, iz=4)
     b = inputs.point_source_rhs(*shape, src)
     out = {}
-    for policy in ("item", "pipelined", "two_per_cu", "pipelined16", "paired"):
+    for policy in ("item", "pipelined", "two_per_cu", "pipelined16", "paired", "paired_lds"):
         helm.set_sweep_policy(policy)
         say("two-level solve", policy, len(src))
         S = helm.Solver(shape, h, c, f, (5, 5, 5, 0), weights=W, parts=(2, 2, 2), overlap=2, levels=2, restart=20)
         out[policy] = S.solve(b, tol=tol, maxit=300)
         S.close()
     Xa, ia = out["item"]
-    for other in ("pipelined", "two_per_cu", "pipelined16", "paired"):
+    for other in ("pipelined", "two_per_cu", "pipelined16", "paired", "paired_lds"):
         Xb, ib = out[other]
         assert np.all(ia["relres_true"] <= tol) and np.all(ib["relres_true"] <= tol)
         assert np.max(np.abs(ia["iters"] - ib["iters"])) <= 1
