@@ -261,14 +261,15 @@ helm_status helm_sweep_stats(const helm_handle_t* h, int32_t level, double out[4
  * policy: out[0] right-hand-side group, out[1] waves per item (0 for the
  * pipelined sweep), out[2] the variant, numbered as the sweep policy that
  * forces it (1 one item per workgroup, 2 pipelined, 3 low-register build,
- * 4 pipelined with 16 waves, 5 paired, 6 paired with the plane solutions in
- * LDS), out[3] waves per workgroup; all zero
+ * 4 pipelined with 16 waves, 5 paired, 6 plane solutions in LDS, paired or
+ * one group), out[3] waves per workgroup; all zero
  * if that batch width has not been tuned yet.  HELM_EINVAL for a bad level
  * or nrhs <= 0. */
 helm_status helm_sweep_config(const helm_handle_t* h, int32_t level, int32_t nrhs, int32_t out[4]);
 /* Environment: HELM_TUNE_FILE=path persists the sweep tuner's decisions --
  * decisions recorded in the file are used as tuned, new ones are appended --
- * so that separate processes launch the same sweeps; HELM_TUNE_VERBOSE=1
+ * so that separate processes launch the same sweeps (an entry naming a launch
+ * that cannot run on the problem is ignored and tuned again); HELM_TUNE_VERBOSE=1
  * prints every candidate the tuners time; HELM_NO_TUNE=1 skips tuning. */
 
 /* With the same timing on, the fine-grid 27-point products of eq. eq1 inside
@@ -308,9 +309,10 @@ helm_status helm_graph_stats(const helm_handle_t* h, double out[2]);
  * one box per workgroup, each on half of its waves, so that both stream the
  * box's factors in step and the second read hits L2) wherever the batch
  * splits into an even number of groups whose two operands fit in LDS, else
- * as 0; 6 uses the paired sweep that also keeps each item's last plane
- * solution in LDS (complex FP64 groups of 16 whose operands and solutions
- * fit), so that a plane step needs only a workgroup barrier, else as 0.
+ * as 0; 6 uses the sweep that also keeps each item's last plane solution in
+ * LDS (complex FP64 groups of 16 whose operands and solutions fit), so that a
+ * plane step needs only a workgroup barrier: paired where the groups pair,
+ * else one group per workgroup, else as 0.
  * Planes whose operand does not fit in LDS
  * (complex FP64 above 600 nodes, complex FP32 above 1200) keep it in global
  * memory under every policy.  Results agree to rounding.  Graphs captured

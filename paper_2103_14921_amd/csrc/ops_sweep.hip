@@ -537,7 +537,7 @@ struct BoxCtx {
 // (half_elems elements apart in LDS).  Both halves stream the same factor
 // chunks within the same plane step, so the second read of each chunk mostly
 // hits L2, and the factors cross HBM about once per application.
-// YLDS (FP64 paired sweep): each item also keeps its last plane solution in LDS
+// YLDS (FP64, groups of 16): each item also keeps its last plane solution in LDS
 // ([bp][RG] at ys_off elements after its operand), written by the products
 // beside yloc; the next plane's operand build reads its neighbours there, so a
 // plane step needs only a workgroup barrier, and the release/acquire through
@@ -956,6 +956,11 @@ bool pair_ylds_fits(int rg, int bpmax, int nrhs) {
   return sizeof(T) == 8 && rg == 16 && pair_fits<T>(rg, bpmax, nrhs) &&
          2 * (size_t)bpmax * (lds_width<T>(rg) + rg) * sizeof(cpx<T>) <= 160 * 1024;
 }
+// the one-group sweep with the plane solutions in LDS (FP64 groups of 16)
+template <typename T>
+bool item_ylds_fits(int rg, int bpmax) {
+  return sizeof(T) == 8 && rg == 16 && (size_t)bpmax * (lds_width<T>(rg) + rg) * sizeof(cpx<T>) <= 160 * 1024;
+}
 
 // Whether the two-workgroups-per-CU build of the sweep exists for this shape:
 // FP64 groups of 32 right-hand sides, two operands in one CU's LDS.
@@ -970,14 +975,18 @@ void launch_fused_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax,
                     cpx<T>* yloc, hipStream_t s) {
   constexpr int PF = sizeof(T) == 4 ? 4 : 2;
   if constexpr (sizeof(T) == 8 && RG == 16) {
-    if (pair == 2) {  // paired, plane solutions in LDS
-      launch_fused_k<T, RG, PF, 1, true, true>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx,
-                                               gny, yloc, s);
+    if (pair & 2) {  // plane solutions in LDS (pair & 1: paired)
+      if (pair & 1)
+        launch_fused_k<T, RG, PF, 1, true, true>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx,
+                                                 gny, yloc, s);
+      else
+        launch_fused_k<T, RG, PF, 1, false, true>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx,
+                                                  gny, yloc, s);
       return;
     }
   }
   if constexpr (RG >= 16) {
-    if (pair) {
+    if (pair & 1) {
       launch_fused_k<T, RG, PF, 1, true>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx, gny,
                                          yloc, s);
       return;
@@ -1097,7 +1106,7 @@ std::atomic<int> g_sweep_policy{0};
 struct TuneVal {
   int rg, rounds;
   bool lowreg;  // the build for two workgroups per compute unit (lowreg_fits)
-  int pair;     // two groups of a box per workgroup (pair_fits); 2: with the plane solutions in LDS
+  int pair;     // bit 0: two groups of a box per workgroup (pair_fits); bit 1: plane solutions in LDS
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
@@ -1111,6 +1120,19 @@ const char* tune_file() {
   static const char* f = std::getenv("HELM_TUNE_FILE");
   return f && *f ? f : nullptr;
 }
+// Whether a sweep shape (from the tuner or a tuning file) can run on this
+// problem: a group the operand width allows, and the LDS its variant needs.
+template <typename T>
+bool admissible(const TuneVal& v, int rgmax, int bpmax, int nrhs) {
+  if ((v.rg != 8 && v.rg != 16 && v.rg != 32) || v.rg > rgmax || v.rounds < 0 || v.pair < 0 || v.pair > 3) return false;
+  if (!lds_fits<T>(v.rg, bpmax)) return v.pair == 0;  // the global-operand sweep
+  if (v.rounds == 0) return v.pair == 0 && pipe_fits<T>(v.rg, bpmax);
+  if ((v.pair & 1) && !pair_fits<T>(v.rg, bpmax, nrhs)) return false;
+  if (v.pair == 3 && !pair_ylds_fits<T>(v.rg, bpmax, nrhs)) return false;
+  if (v.pair == 2 && !item_ylds_fits<T>(v.rg, bpmax)) return false;
+  return !v.lowreg || v.pair != 0 || lowreg_fits<T>(v.rg, bpmax);
+}
+
 void load_tune_file_locked() {  // with g_tune_mu held
   static bool loaded = false;
   if (loaded || !tune_file()) return;
@@ -1162,8 +1184,8 @@ bool tuned_config(int es, int bpmax, int nsub, int nrhs, int gnx, int gny, int o
   out[0] = tv.rg;
   out[1] = per_item;
   // the variant, numbered as the sweep policies that force it
-  out[2] = tv.rounds == 0 ? (tv.lowreg ? 4 : 2) : (tv.pair == 2 ? 6 : (tv.pair ? 5 : (tv.lowreg ? 3 : 1)));
-  out[3] = tv.rounds == 0 ? (tv.lowreg ? 16 : 12) : (tv.pair ? 2 * per_item : per_item);
+  out[2] = tv.rounds == 0 ? (tv.lowreg ? 4 : 2) : ((tv.pair & 2) ? 6 : (tv.pair ? 5 : (tv.lowreg ? 3 : 1)));
+  out[3] = tv.rounds == 0 ? (tv.lowreg ? 16 : 12) : ((tv.pair & 1) ? 2 * per_item : per_item);
   return true;
 }
 
@@ -1178,10 +1200,17 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
                  tbuf, s);
     return true;
   }
-  if (policy == 6 && pair_ylds_fits<T>(16, bpmax, nrhs)) {  // forced: paired, plane solutions in LDS
-    launch_rg<T>(16, pair_min_rounds<T>(bpmax), false, 2, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc,
-                 tbuf, s);
-    return true;
+  if (policy == 6) {  // forced: plane solutions in LDS, paired where the groups pair
+    if (pair_ylds_fits<T>(16, bpmax, nrhs)) {
+      launch_rg<T>(16, pair_min_rounds<T>(bpmax), false, 3, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny,
+                   yloc, tbuf, s);
+      return true;
+    }
+    if (rgmax >= 16 && item_ylds_fits<T>(16, bpmax)) {
+      launch_rg<T>(16, min_rounds<T>(bpmax), false, 2, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc,
+                   tbuf, s);
+      return true;
+    }
   }
   if (policy == 5) {  // forced: the paired sweep with the widest group that pairs
     for (int cand = rgmax; cand >= 16; cand /= 2)
@@ -1210,6 +1239,7 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
     auto it = g_tune.find(key);
     if (it != g_tune.end()) tv = it->second;
   }
+  if (tv.rg != 0 && !admissible<T>(tv, rgmax, bpmax, nrhs)) tv = TuneVal{0, 0, false, 0};  // a stale or foreign entry
   static const bool no_tune = std::getenv("HELM_NO_TUNE") != nullptr;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   (void)hipStreamIsCapturing(s, &cap);
@@ -1234,14 +1264,16 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
         const int waves = rounds == 0 ? -1 : (nmt + rounds - 1) / rounds;
         if (waves == last_waves) continue;
         last_waves = waves;
-        for (int lr = 0; lr < 2; ++lr) {
-          // lowreg: the 16-wave pipelined build, or the FP64 32-group build for two workgroups per CU
-          if (lr && !(rounds == 0 || (rounds == r0 && lowreg_fits<T>(cand, bpmax)))) continue;
+        for (int lr = 0; lr < 3; ++lr) {
+          // lr 1: the 16-wave pipelined build, or the FP64 32-group build for two workgroups per CU;
+          // lr 2: the one-group sweep with its plane solutions in LDS
+          if (lr == 1 && !(rounds == 0 || (rounds == r0 && lowreg_fits<T>(cand, bpmax)))) continue;
+          if (lr == 2 && !(rounds != 0 && (policy == 0 || policy == 6) && item_ylds_fits<T>(cand, bpmax))) continue;
           float tot = 0.f;
           for (int rep = 0; rep < 2; ++rep) {
             (void)hipEventRecord(e0, s);
-            launch_rg<T>(cand, rounds, lr != 0, false, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, tbuf,
-                         s);
+            launch_rg<T>(cand, rounds, lr == 1, lr == 2 ? 2 : 0, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny,
+                         yloc, tbuf, s);
             (void)hipEventRecord(e1, s);
             (void)hipEventSynchronize(e1);
             float ms = 0.f;
@@ -1251,10 +1283,10 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
           if (verbose)
             std::fprintf(stderr, "helm:   candidate group %d %s %d waves%s: %.3f ms\n", cand,
                          rounds == 0 ? "pipelined," : "", rounds == 0 ? (lr ? 16 : 12) : waves,
-                         lr && rounds != 0 ? " (two per CU)" : "", tot);
+                         lr == 1 && rounds != 0 ? " (two per CU)" : (lr == 2 ? " (solutions in LDS)" : ""), tot);
           if (tot < best) {
             best = tot;
-            tv = {cand, rounds, lr != 0, 0};
+            tv = {cand, rounds, lr == 1, lr == 2 ? 2 : 0};
           }
         }
       }
@@ -1271,8 +1303,8 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
           float tot = 0.f;
           for (int rep = 0; rep < 2; ++rep) {
             (void)hipEventRecord(e0, s);
-            launch_rg<T>(cand, rounds, false, pm, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny, yloc, tbuf,
-                         s);
+            launch_rg<T>(cand, rounds, false, pm == 2 ? 3 : 1, subs, nsub, nrhs, bpmax, cpl, sinv, u, z, add, gnx, gny,
+                         yloc, tbuf, s);
             (void)hipEventRecord(e1, s);
             (void)hipEventSynchronize(e1);
             float ms = 0.f;
@@ -1284,7 +1316,7 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
                          pm == 2 ? " (solutions in LDS)" : "", waves, tot);
           if (tot < best) {
             best = tot;
-            tv = {cand, rounds, false, pm};
+            tv = {cand, rounds, false, pm == 2 ? 3 : 1};
           }
         }
       }
@@ -1294,7 +1326,9 @@ bool oras_fused(const Sub* subs, int nsub, int bpmax, const cpx<T>* cpl, const c
     if (verbose)
       std::fprintf(stderr, "helm: sweep tuned (fp%d, bp %d, %d boxes, %d rhs): group %d, %s %d waves%s, %.3f ms\n",
                    (int)sizeof(T) * 8, bpmax, nsub, nrhs, tv.rg,
-                   tv.rounds == 0 ? "pipelined," : (tv.pair == 2 ? "paired (LDS solutions), 2 x" : (tv.pair ? "paired, 2 x" : "")),
+                   tv.rounds == 0 ? "pipelined,"
+                                  : (tv.pair == 3 ? "paired (LDS solutions), 2 x"
+                                                  : (tv.pair == 1 ? "paired, 2 x" : (tv.pair == 2 ? "LDS solutions," : ""))),
                    tv.rounds == 0 ? (tv.lowreg ? 16 : 12) : (nmt + tv.rounds - 1) / tv.rounds,
                    tv.lowreg && tv.rounds != 0 ? " (two per CU)" : "", best);
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1373,10 +1407,12 @@ bool oras_half(const Sub* subs, int nsub, int bpmax, const c32* cpl, const uint4
     auto it = g_tune.find(key);
     if (it != g_tune.end()) tv = it->second;
   }
+  const int nmt = bpmax / 16, r0 = (nmt + 15) / 16;
+  if (tv.rg != 0 && ((tv.rg != 16 && tv.rg != 32) || tv.rg > rgmax || tv.rounds < r0 || tv.pair != 0 || tv.lowreg))
+    tv = TuneVal{0, 0, false, 0};  // a stale or foreign entry
   static const bool no_tune = std::getenv("HELM_NO_TUNE") != nullptr;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   (void)hipStreamIsCapturing(s, &cap);
-  const int nmt = bpmax / 16, r0 = (nmt + 15) / 16;
   if (tv.rg == 0 && !no_tune && may_tune && cap == hipStreamCaptureStatusNone) {
     hipEvent_t e0, e1;
     (void)locked_event_create(&e0);

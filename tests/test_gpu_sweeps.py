@@ -4,8 +4,8 @@ The one-workgroup-per-box sweep, the pipelined persistent sweep (two boxes
 per compute unit), the one-workgroup-per-box sweep built for two
 workgroups per compute unit (FP64, groups of 32) and the paired sweep (two
 right-hand-side groups of a box per workgroup; 20 and 40 right-hand sides
-pair), also with the plane solutions kept in LDS (FP64 coarse level), are
-forced in turn through the process-wide sweep policy,
+pair), and the FP64 sweeps with the plane solutions kept in LDS (paired at
+20 right-hand sides, one group at 12) are forced in turn through the process-wide sweep policy,
 on right-hand-side batches that use full and partial groups of 16 and 32
 columns, on the fine level (FP64 and complex FP32 factors) and on the coarse
 level; each result is compared with the oracle's one-level ORAS applied per
@@ -62,7 +62,8 @@ def test_fine_sweep_variants_match_oracle(policy, prec, tol, nrhs):
 
 @pytest.mark.parametrize("policy", ["item", "pipelined", "two_per_cu", "pipelined16", "paired", "paired_lds"])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("single_local", 5e-4)])
-def test_coarse_sweep_variants_match_oracle(policy, prec, tol):
+@pytest.mark.parametrize("nrhs", [20, 12])
+def test_coarse_sweep_variants_match_oracle(policy, prec, tol, nrhs):
     from paper_2103_14921_amd import helm
     helm.set_sweep_policy(policy)
     shape, h, f, pml = (28, 26, 24), 25.0, 10.0, (5, 5, 5, 0)
@@ -70,11 +71,11 @@ def test_coarse_sweep_variants_match_oracle(policy, prec, tol):
     prob = Problem(shape, h, c, f, Pml(*pml), WO)
     A = assemble(prob)
     tl = TwoLevel(A, shape, decompose(shape, (2, 2, 2), 2), prob.k().ravel(), h, 2)
-    say("coarse sweep", policy, prec)
+    say("coarse sweep", policy, prec, nrhs)
     S = helm.Solver(shape, h, c, f, pml, weights=W, parts=(2, 2, 2), overlap=2, levels=2, precision=prec)
-    Cc = inputs.random_field((20, S.nc), seed=77)
+    Cc = inputs.random_field((nrhs, S.nc), seed=77)
     Zc = S.apply_oras(Cc, level=1)
-    for r in range(20):
+    for r in range(nrhs):
         assert rel(Zc[r], tl.coarse.apply(Cc[r])) <= tol, r
     S.close()
 

@@ -3,7 +3,9 @@
 The first process tunes the coarse one-level ORAS sweep of a small two-level
 problem and records the decision; the second reads it, reports the same
 launch (helm_sweep_config) and appends nothing, since it did not tune; both
-applications agree with each other bitwise.
+applications agree with each other bitwise.  A file whose entries name
+launches that cannot run on the problem (a group the library does not have,
+an unknown variant) is not trusted: the process tunes again.
 """
 import json
 import os
@@ -54,3 +56,22 @@ def test_second_process_launches_the_recorded_sweep(tmp_path):
     assert cfg2 == cfg1
     assert (tmp_path / "tune.txt").read_text().splitlines() == lines  # nothing re-tuned
     assert np.array_equal(np.load(tmp_path / "z1.npy"), np.load(tmp_path / "z2.npy"))
+
+
+def test_inadmissible_entries_are_retuned(tmp_path):
+    import numpy as np
+    _run(tmp_path, 1)
+    good = (tmp_path / "tune.txt").read_text().splitlines()
+    bad = []
+    for l in good:
+        f = l.split()
+        if f[0] == "sweep":
+            f[8], f[11] = "64", "7"  # group 64, variant 7: neither exists
+        bad.append(" ".join(f))
+    (tmp_path / "tune.txt").write_text("\n".join(bad) + "\n")
+    cfg = _run(tmp_path, 3)
+    after = (tmp_path / "tune.txt").read_text().splitlines()
+    assert len(after) > len(bad)  # tuned again and recorded
+    assert cfg["group"] in (8, 16, 32)
+    z1, z3 = np.load(tmp_path / "z1.npy"), np.load(tmp_path / "z3.npy")
+    assert np.linalg.norm(z3 - z1) <= 1e-10 * np.linalg.norm(z1)
