@@ -537,7 +537,7 @@ struct BoxCtx {
 // (half_elems elements apart in LDS).  Both halves stream the same factor
 // chunks within the same plane step, so the second read of each chunk mostly
 // hits L2, and the factors cross HBM about once per application.
-// YLDS (FP64, groups of 16): each item also keeps its last plane solution in LDS
+// YLDS (groups of 16): each item also keeps its last plane solution in LDS
 // ([bp][RG] at ys_off elements after its operand), written by the products
 // beside yloc; the next plane's operand build reads its neighbours there, so a
 // plane step needs only a workgroup barrier, and the release/acquire through
@@ -578,7 +578,7 @@ __global__ void __launch_bounds__(64 * fused_max_waves<T>(), MINW) k_oras_fused(
 #pragma unroll
       for (int j = 1; j < PF; ++j) cs.next(a[j]);
     } else if constexpr (sizeof(T) == 4 && RG >= 16) {
-      bx.template build_step_ne<4, 5>(st, Bs, ht, hw * 64);
+      bx.template build_step_ne<4, 5, false, YLDS>(st, Bs, ht, hw * 64, nullptr, Bs + ys_off);
       cs = prefetch_tile<T, PF>(bx.factor(sinv, st), bp, wv, hw, lane, a);  // across the barrier
     } else {
       bx.template build_step<(MINW > 1)>(st, Bs, ht, hw * 64);
@@ -956,10 +956,10 @@ bool pair_ylds_fits(int rg, int bpmax, int nrhs) {
   return sizeof(T) == 8 && rg == 16 && pair_fits<T>(rg, bpmax, nrhs) &&
          2 * (size_t)bpmax * (lds_width<T>(rg) + rg) * sizeof(cpx<T>) <= 160 * 1024;
 }
-// the one-group sweep with the plane solutions in LDS (FP64 groups of 16)
+// the one-group sweep with the plane solutions in LDS (groups of 16)
 template <typename T>
 bool item_ylds_fits(int rg, int bpmax) {
-  return sizeof(T) == 8 && rg == 16 && (size_t)bpmax * (lds_width<T>(rg) + rg) * sizeof(cpx<T>) <= 160 * 1024;
+  return rg == 16 && (size_t)bpmax * (lds_width<T>(rg) + rg) * sizeof(cpx<T>) <= 160 * 1024;
 }
 
 // Whether the two-workgroups-per-CU build of the sweep exists for this shape:
@@ -974,14 +974,17 @@ void launch_fused_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax,
                     const cpx<T>* cpl, const cpx<T>* sinv, const z64* u, z64* z, const z64* add, int gnx, int gny,
                     cpx<T>* yloc, hipStream_t s) {
   constexpr int PF = sizeof(T) == 4 ? 4 : 2;
-  if constexpr (sizeof(T) == 8 && RG == 16) {
-    if (pair & 2) {  // plane solutions in LDS (pair & 1: paired)
-      if (pair & 1)
-        launch_fused_k<T, RG, PF, 1, true, true>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx,
-                                                 gny, yloc, s);
-      else
-        launch_fused_k<T, RG, PF, 1, false, true>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx,
-                                                  gny, yloc, s);
+  if constexpr (RG == 16) {
+    if (pair & 2) {  // plane solutions in LDS (pair & 1: paired, complex FP64 only)
+      if constexpr (sizeof(T) == 8) {
+        if (pair & 1) {
+          launch_fused_k<T, RG, PF, 1, true, true>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx,
+                                                   gny, yloc, s);
+          return;
+        }
+      }
+      launch_fused_k<T, RG, PF, 1, false, true>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv, u, z, add, gnx,
+                                                gny, yloc, s);
       return;
     }
   }

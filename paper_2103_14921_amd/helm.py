@@ -256,7 +256,7 @@ class Request:
 
 
 SWEEP_POLICIES = {"auto": 0, "item": 1, "pipelined": 2, "two_per_cu": 3, "pipelined16": 4, "paired": 5,
-                  "paired_lds": 6}
+                  "paired_lds": 6, "lds_solutions": 6}
 
 
 def set_sweep_policy(policy):
