@@ -194,7 +194,9 @@ __global__ void __launch_bounds__(256) k_axpy_multi(const z64* __restrict__ V, l
 // Fused CGS pass: w -= sum_v h[v][r] V_v, then partial[v][r][blk] = sum conj(V_v) w
 // over the block's nodes -- the update of the first Gram-Schmidt pass and the
 // projections of the second in one read of the basis.
-__global__ void __launch_bounds__(256) k_axpy_dots(const z64* __restrict__ V, long long vstride, int nv,
+// nv vectors update w; the first ndot <= NVMAX of them also take the projections
+// (the rest, if any, by a separate dot-product launch on the updated w).
+__global__ void __launch_bounds__(256) k_axpy_dots(const z64* __restrict__ V, long long vstride, int nv, int ndot,
                                                    const z64* __restrict__ h, z64* __restrict__ w, long long len,
                                                    int nrhs, z64* __restrict__ partial, double* __restrict__ npart) {
   extern __shared__ z64 hs[];  // [nv][nrhs]
@@ -216,15 +218,16 @@ __global__ void __launch_bounds__(256) k_axpy_dots(const z64* __restrict__ V, lo
       z64 vv[NVMAX];
 #pragma unroll
       for (int v = 0; v < NVMAX; ++v)
-        if (v < nv) {
+        if (v < ndot) {
           vv[v] = V[(long long)v * vstride + e];
           cfms(x, hs[v * nrhs + r], vv[v]);
         }
+      for (int v = ndot; v < nv; ++v) cfms(x, hs[v * nrhs + r], V[(long long)v * vstride + e]);
       w[e] = x;
       accn += abs2(x);
 #pragma unroll
       for (int v = 0; v < NVMAX; ++v)
-        if (v < nv) cdot_acc(acc[v], vv[v], x);
+        if (v < ndot) cdot_acc(acc[v], vv[v], x);
     }
   }
   if (npart) {  // ||w'||^2 partial, [r][blk] as k_norm2 (red reused as doubles after a barrier)
@@ -240,7 +243,7 @@ __global__ void __launch_bounds__(256) k_axpy_dots(const z64* __restrict__ V, lo
   }
 #pragma unroll
   for (int v = 0; v < NVMAX; ++v) {
-    if (v < nv) {  // uniform over the block
+    if (v < ndot) {  // uniform over the block
       red[tid] = (lane < nl) ? acc[v] : mk(0.0, 0.0);
       __syncthreads();
       if (lane == 0) {
@@ -553,16 +556,20 @@ void launch_reorth_check(KrylovState st, int nv, double tau2, double vec_bytes, 
 
 bool launch_axpy_dots(const z64* V, long long vstride, int nv, const z64* h, z64* w, long long len, int nrhs,
                       z64* partial, z64* h2, hipStream_t s, double* npart, double* nrm2) {
-  if (nv > NVMAX || (size_t)nv * nrhs * sizeof(z64) > 64 * 1024) return false;
-  account(16.0 * (nv + 2) * len * nrhs, 16.0 * nv * len * nrhs);
+  if ((size_t)nv * nrhs * sizeof(z64) > 64 * 1024) return false;
+  // the update and the first NVMAX projections in one pass; projections on
+  // further vectors (restart lengths above NVMAX) read the updated w once more
+  const int nd = std::min(nv, NVMAX);
+  account(16.0 * (nv + 2) * len * nrhs, 8.0 * (nv + nd) * len * nrhs);  // launch_dots accounts its own pass
   const int nblk = red_blocks(len);
-  hipLaunchKernelGGL(k_axpy_dots, dim3(nblk), dim3(256), (size_t)nv * nrhs * sizeof(z64), s, V, vstride, nv, h, w, len,
-                     nrhs, partial, nrm2 ? npart : nullptr);
+  hipLaunchKernelGGL(k_axpy_dots, dim3(nblk), dim3(256), (size_t)nv * nrhs * sizeof(z64), s, V, vstride, nv, nd, h, w,
+                     len, nrhs, partial, nrm2 ? npart : nullptr);
   if (nrm2)
     hipLaunchKernelGGL(k_sum_final, dim3((unsigned)ceil_div(nrhs, 4)), dim3(256), 0, s, npart, nblk, nrhs, nrm2,
                        (const int*)nullptr);
-  hipLaunchKernelGGL(k_dots_final, dim3((unsigned)ceil_div(nv * nrhs, 4)), dim3(256), 0, s, partial, nblk, nv, nrhs,
+  hipLaunchKernelGGL(k_dots_final, dim3((unsigned)ceil_div(nd * nrhs, 4)), dim3(256), 0, s, partial, nblk, nd, nrhs,
                      h2);
+  if (nv > nd) launch_dots(V + (long long)nd * vstride, vstride, nv - nd, w, len, nrhs, partial, h2 + (long long)nd * nrhs, s);
   return true;
 }
 
