@@ -322,7 +322,7 @@ size_t elem_size(int prec) { return prec ? sizeof(c32) : sizeof(z64); }
 // Bytes of the handle's resident data for a level (operators and factors).
 size_t level_resident_bytes(const Level& L) {
   return (size_t)L.nodes_total * 18 * elem_size(L.prec) + (size_t)L.mat_total * (L.half ? 4 : elem_size(L.prec)) +
-         (size_t)L.nsub * sizeof(Sub) + (L.half ? (size_t)L.nsub * L.maxez * sizeof(int) : 0);
+         (size_t)L.nsub * sizeof(Sub) * 2 + (L.half ? (size_t)L.nsub * L.maxez * sizeof(int) : 0);
 }
 // Temporary set-up bytes of a level (local operator rows, Schur blocks, pivots).
 size_t level_setup_bytes(const Level& L) {
@@ -840,12 +840,13 @@ void oras_sweep(helm_handle* H, Level& L, int nr, const z64* u, z64* z, const z6
       throw HelmError(HELM_EINVAL, "approximate local solves do not fit this plane size");
     return;
   }
+  const Sub* order = L.d_subs.as<Sub>() + L.nsub;  // the boxes in sweep launch order
   if (L.prec == 1)
-    Factor<float>::sweep(L.d_subs.as<Sub>(), L.nsub, L.bpmax, L.maxez, L.cpl.as<c32>(), L.sinv.as<c32>(), nr, u, z,
-                         add, L.nx, L.ny, (c32*)yl, (c32*)tb, H->stream);
+    Factor<float>::sweep(order, L.nsub, L.bpmax, L.maxez, L.cpl.as<c32>(), L.sinv.as<c32>(), nr, u, z, add, L.nx, L.ny,
+                         (c32*)yl, (c32*)tb, H->stream);
   else
-    Factor<double>::sweep(L.d_subs.as<Sub>(), L.nsub, L.bpmax, L.maxez, L.cpl.as<z64>(), L.sinv.as<z64>(), nr, u, z,
-                          add, L.nx, L.ny, (z64*)yl, (z64*)tb, H->stream);
+    Factor<double>::sweep(order, L.nsub, L.bpmax, L.maxez, L.cpl.as<z64>(), L.sinv.as<z64>(), nr, u, z, add, L.nx,
+                          L.ny, (z64*)yl, (z64*)tb, H->stream);
 }
 
 void coarse_spmv(helm_handle* H, int nr, const z64* x, z64* y) {
@@ -1576,9 +1577,36 @@ void factor_level(helm_handle* H, Level& L) {
   if (e) throw HelmError(HELM_EBREAKDOWN, "numerically singular pivot in a local factorisation");
 }
 
+// The boxes in launch order for the batched local solves: by decreasing work
+// ((2 ez - 1) b^2 per right-hand side, the plane products), dealt round-robin
+// over the eight XCDs' contiguous ranges of logical workgroups
+// (xcd_contiguous), so that every XCD starts on its largest boxes and the last
+// wave of workgroups holds the smallest.  A sweep's results do not depend on
+// the order: every box writes only its own plane vectors and its core nodes.
+std::vector<Sub> sweep_order(const std::vector<Sub>& subs) {
+  const int n = (int)subs.size();
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  auto work = [&](int i) { return (2.0 * subs[i].ez - 1.0) * (double)subs[i].b * subs[i].b; };
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return work(a) > work(b); });
+  constexpr int NXCD = 8;
+  const int per = n / NXCD, rem = n % NXCD;
+  std::vector<Sub> out(n);
+  for (int i = 0; i < n; ++i) {
+    const int c = i % NXCD, li = i / NXCD;
+    out[c * per + std::min(c, rem) + li] = subs[idx[i]];
+  }
+  return out;
+}
+
+// Device copies of the boxes: [0, nsub) in box order (set-up kernels, arrays
+// indexed by box), [nsub, 2 nsub) in sweep launch order.
 void upload_subs(Level& L, hipStream_t stream) {
-  L.d_subs.alloc(sizeof(Sub) * L.subs.size());
-  HELM_CHECK_HIP(hipMemcpyAsync(L.d_subs.p, L.subs.data(), sizeof(Sub) * L.subs.size(), hipMemcpyHostToDevice, stream));
+  const size_t n = L.subs.size();
+  const std::vector<Sub> order = sweep_order(L.subs);
+  L.d_subs.alloc(sizeof(Sub) * n * 2);
+  HELM_CHECK_HIP(hipMemcpyAsync(L.d_subs.p, L.subs.data(), sizeof(Sub) * n, hipMemcpyHostToDevice, stream));
+  HELM_CHECK_HIP(hipMemcpyAsync(L.d_subs.as<Sub>() + n, order.data(), sizeof(Sub) * n, hipMemcpyHostToDevice, stream));
   HELM_CHECK_HIP(hipStreamSynchronize(stream));
 }
 
