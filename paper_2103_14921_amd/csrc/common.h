@@ -134,6 +134,7 @@ struct Sub {
   int lo[3], hi[3];    // core box
   int ex, ey, ez;      // extended sizes
   int b, bp;           // plane size ex*ey and padded plane size
+  int id;              // the box's index in box order (for arrays indexed per box)
   long long node_off;  // offset of the box's nodes in the concatenated local arrays
   long long mat_off;   // offset (elements) of the box's plane matrices [ez][bp][bp]
   long long vec_off;   // offset (elements / nrhs) of the box's local vector [ez][bp]

@@ -280,6 +280,7 @@ void plan_level(Level& L, int nx, int ny, int nz, const std::vector<Sub>& cores,
     L.maxez = std::max(L.maxez, s.ez);
     L.maxnodes = std::max(L.maxnodes, nodes);
     L.maxcore = std::max(L.maxcore, (long long)(s.hi[0] - s.lo[0]) * (s.hi[1] - s.lo[1]) * (s.hi[2] - s.lo[2]));
+    s.id = (int)L.subs.size();
     L.subs.push_back(s);
   }
   L.nsub = (int)L.subs.size();
@@ -834,13 +835,13 @@ void collect_sweep_timing(helm_handle* H) {
 }
 
 void oras_sweep(helm_handle* H, Level& L, int nr, const z64* u, z64* z, const z64* add, void* yl, void* tb) {
+  const Sub* order = L.d_subs.as<Sub>() + L.nsub;  // the boxes in sweep launch order
   if (L.half) {
-    if (!oras_half(L.d_subs.as<Sub>(), L.nsub, L.bpmax, L.cpl.as<c32>(), L.sinv16.as<uint4>(), L.sexp.as<int>(),
+    if (!oras_half(order, L.nsub, L.bpmax, L.cpl.as<c32>(), L.sinv16.as<uint4>(), L.sexp.as<int>(),
                    L.maxez, nr, u, z, add, L.nx, L.ny, (c32*)yl, H->stream))
       throw HelmError(HELM_EINVAL, "approximate local solves do not fit this plane size");
     return;
   }
-  const Sub* order = L.d_subs.as<Sub>() + L.nsub;  // the boxes in sweep launch order
   if (L.prec == 1)
     Factor<float>::sweep(order, L.nsub, L.bpmax, L.maxez, L.cpl.as<c32>(), L.sinv.as<c32>(), nr, u, z, add, L.nx, L.ny,
                          (c32*)yl, (c32*)tb, H->stream);
@@ -2332,7 +2333,7 @@ helm_status helm_local_solve(helm_handle_t* H, int32_t level, int32_t s, int32_t
     void* tb = level == 0 ? H->ws.tb_f.p : H->ws.tb_c.p;
     const Sub* one = L.d_subs.as<Sub>() + s;
     if (L.half) {
-      if (!oras_half(one, 1, L.bpmax, L.cpl.as<c32>(), L.sinv16.as<uint4>(), L.sexp.as<int>() + (long long)s * L.maxez,
+      if (!oras_half(one, 1, L.bpmax, L.cpl.as<c32>(), L.sinv16.as<uint4>(), L.sexp.as<int>(),  // indexed by Sub::id
                      L.maxez, nrhs, u.as<z64>(), zg.as<z64>(), nullptr, L.nx, L.ny, (c32*)yl, H->stream))
         throw HelmError(HELM_EINVAL, "approximate local solves do not fit this plane size");
       launch_box_gather<float>(sb, nrhs, (const c32*)yl, xo.as<z64>(), H->stream);

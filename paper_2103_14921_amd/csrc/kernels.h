@@ -123,7 +123,8 @@ inline long long sweep_tbuf_elems(int nsub, int bpmax, int nrhs) {
 }
 // Approximate local solves (the FP16 sweep k_oras_half): plane inverses
 // converted from complex FP32 by launch_to_half into 16-byte blocks (four real
-// parts, four imaginary parts of one row) scaled by 2^-sexp[s * maxez + k].
+// parts, four imaginary parts of one row) scaled by 2^-sexp[id * maxez + k]
+// (id = the box's Sub::id, so the boxes may be passed in any order).
 // oras_half returns false where the complex-FP32 operand of a plane does not
 // fit in LDS (half_group 0: planes above 960 nodes).
 int half_group(int bpmax, int nrhs);

@@ -634,9 +634,9 @@ __global__ void __launch_bounds__(64 * fused_max_waves<T>()) k_oras_gl(const Sub
 
 // ---- approximate local solves: plane inverses in complex FP16 ----------------
 //
-// Factor storage of the approximate form: plane k of box s holds
-// Sinv_k 2^-e (e = sexp[s maxez + k], chosen so that the largest |Re| or |Im|
-// lies in [2^13, 2^14)), in blocks of 16 bytes: for row p and column group g
+// Factor storage of the approximate form: plane k of a box holds Sinv_k 2^-e
+// (e = sexp[id maxez + k], id = the box's Sub::id, chosen so that the largest
+// |Re| or |Im| lies in [2^13, 2^14)), in blocks of 16 bytes: for row p and column group g
 // (columns 4g .. 4g + 3) the four real parts, then the four imaginary parts, as
 // FP16.  The operand T stays complex FP32 in LDS; each column is scaled by a
 // power of two (its largest |Re| or |Im| to [2^13, 2^14)) and rounded to FP16
@@ -772,8 +772,8 @@ __global__ void __launch_bounds__(64 * 16) k_oras_half(const Sub* __restrict__ s
   c32* Bs = reinterpret_cast<c32*>(smem_raw);
   __shared__ unsigned cmax[2][RG];
   const int item = (int)xcd_contiguous(blockIdx.x, gridDim.x);
-  const int box = item / ngroups;
   const BoxCtx<float, RG> bx(subs, item, ngroups, nrhs, cpl, u, z, add, gnx, gny, yloc);
+  const int box = bx.sb.id;  // the exponents are stored in box order
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int FT = blockDim.x, nwaves = FT >> 6;
   const int bp = bx.sb.bp, ns = bx.nsteps();
@@ -815,7 +815,7 @@ __global__ void __launch_bounds__(256) k_to_half(const Sub* __restrict__ subs, i
   m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
   const int e = half_shift(m);
   const float f = ldexpf(1.f, -e);
-  if (threadIdx.x == 0) sexp[s * maxez + k] = e;
+  if (threadIdx.x == 0) sexp[sb.id * maxez + k] = e;
   uint4* D = sinv16 + off / 4;
   for (long long i = threadIdx.x; i < (long long)bp * bq; i += blockDim.x) {
     const long long p = i / bq, g = i % bq;
