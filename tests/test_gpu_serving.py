@@ -1,13 +1,15 @@
 """Serving form on the GPU: continuous batching across problems.
 
 Each result must be the same alone and in the mix (within 10 x tol, and every
-right-hand side at its FP64 true residual); admission by device footprint
-must never account for more than the budget, evicting idle factorisations.
+right-hand side at its FP64 true residual, recomputed on the CPU with the
+oracle's assembled operator); admission by device footprint must never
+account for more than the budget, evicting idle factorisations.
 """
 import numpy as np
 import pytest
 
 import inputs
+from oracle.operator import Pml, Problem, assemble, fit_weights
 
 pytestmark = pytest.mark.gpu
 
@@ -47,11 +49,15 @@ def test_results_alone_equal_results_in_the_mix():
     specs, vel = _catalogue()
     reqs = _requests(specs)
     print("[case] serving alone", flush=True)
+    WO = fit_weights()
+    W = {k: getattr(WO, k) for k in ("w1", "w2", "w3", "wm1", "wm2", "wm3", "wm4")}
     alone = Server(vel, workers=1)
+    alone.weights = W  # the oracle's stencil weights, so that its operator is the library's
     ref = [alone.submit(spec, B, TOL).result() for spec, B in reqs]
     alone.close()
     print("[case] serving mix", flush=True)
     mix = Server(vel, workers=3)
+    mix.weights = W
     futs = [mix.submit(spec, B, TOL) for spec, B in reqs]
     got = [f.result() for f in futs]
     stats = mix.latency_percentiles()
@@ -63,6 +69,15 @@ def test_results_alone_equal_results_in_the_mix():
         assert np.all(a["relres_true"] <= TOL) and np.all(g["relres_true"] <= TOL)
         rel = np.linalg.norm(Xa - Xg, axis=1) / np.linalg.norm(Xa, axis=1)
         assert np.all(rel <= 10 * TOL), rel
+    # every right-hand side of the mix at its true residual under the oracle's operator (FP64, CPU)
+    ops = {}
+    for (spec, B), g in zip(reqs, got):
+        if spec.name not in ops:
+            ops[spec.name] = assemble(Problem(spec.shape, spec.h, vel(spec), spec.freq, Pml(*spec.pml), WO))
+        A = ops[spec.name]
+        for r in range(B.shape[0]):
+            res = np.linalg.norm(B[r] - A @ g["X"][r]) / np.linalg.norm(B[r])
+            assert res <= 1.0001 * TOL, (spec.name, r, res)
     # requests of one problem were merged into larger batches
     assert batched > max(B.shape[0] for _, B in reqs)
     assert stats["p99_s"] >= stats["p50_s"] > 0
