@@ -279,7 +279,8 @@ helm_status helm_sweep_config(const helm_handle_t* h, int32_t level, int32_t nrh
  * algorithmic real flops (27 complex multiply-adds per node and right-hand
  * side) and out[3] algorithmic bytes (16 B per node and right-hand side for
  * x read and y written, and for b in a residual, plus 16 B per node for
- * s k^2), summed since timing was enabled. */
+ * s k^2 and 16 B per node for the stored row diagonal), summed since timing
+ * was enabled. */
 helm_status helm_stencil_stats(const helm_handle_t* h, int32_t kind, double out[4]);
 
 /* Captured iterations (batching form).  With graphs enabled (the default),

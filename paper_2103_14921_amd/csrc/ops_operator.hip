@@ -715,9 +715,10 @@ bool set_row_tiling(int nxt) {
 }
 
 static void stencil_dispatch(const OpDev& op, int nrhs, const z64* x, z64* y, const z64* b, hipStream_t s) {
-  {  // x read and y written once, b read once for a residual, the node values s k^2 once; 27 complex products
+  {  // x read and y written once, b read once for a residual, the node values s k^2 and the stored row
+     // diagonals once; 27 complex products
     const double n = (double)op.nx * op.ny * op.nz;
-    account(16.0 * n * nrhs * (b ? 3 : 2) + 16.0 * n, 216.0 * n * nrhs);
+    account(16.0 * n * nrhs * (b ? 3 : 2) + 32.0 * n, 216.0 * n * nrhs);
   }
   if (nrhs >= 4) {
     const dim3 grid(row_tiles(op.nx, op.ny, op.nz));
