@@ -490,16 +490,13 @@ __global__ void __launch_bounds__(256) k_coarse_spmv2(int ncx, int ncy, int ncz,
 }
 
 // c[I] = sum_i Z[i, I] r[i]   (Z^T, full weighting with weights 1, 1/2 per axis)
+// Grid (ceil(ncx nrhs / 256), ncy, ncz): a thread per (coarse node, column) of one coarse grid row.
 __global__ void k_restrict(int nx, int ny, int nz, int nrhs, const z64* __restrict__ rf, z64* __restrict__ c) {
-  const int ncx = (nx + 1) / 2, ncy = (ny + 1) / 2, ncz = (nz + 1) / 2;
-  const long long nc = (long long)ncx * ncy * ncz;
-  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= nc * nrhs) return;
-  const long long I = t / nrhs;
-  const int r = (int)(t % nrhs);
-  const int cx = (int)(I % ncx);
-  const int cy = (int)((I / ncx) % ncy);
-  const int cz = (int)(I / ((long long)ncx * ncy));
+  const int ncx = (nx + 1) / 2, ncy = (ny + 1) / 2;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ncx * nrhs) return;
+  const int cx = t / nrhs, r = t % nrhs, cy = blockIdx.y, cz = blockIdx.z;
+  const long long I = cx + (long long)ncx * (cy + (long long)ncy * cz);
   z64 acc = mk(0.0, 0.0);
   // branch-free: fine indices clamped into the grid, weights of taps leaving it zero
 #pragma unroll
@@ -521,16 +518,13 @@ __global__ void k_restrict(int nx, int ny, int nz, int nrhs, const z64* __restri
 }
 
 // q[i] = sum_I Z[i, I] c[I]   (trilinear prolongation)
+// Grid (ceil(nx nrhs / 256), ny, nz): a thread per (fine node, column) of one fine grid row.
 __global__ void k_prolong(int nx, int ny, int nz, int nrhs, const z64* __restrict__ c, z64* __restrict__ q) {
   const int ncx = (nx + 1) / 2, ncy = (ny + 1) / 2, ncz = (nz + 1) / 2;
-  const long long n = (long long)nx * ny * nz;
-  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= n * nrhs) return;
-  const long long i = t / nrhs;
-  const int r = (int)(t % nrhs);
-  const int ix = (int)(i % nx);
-  const int iy = (int)((i / nx) % ny);
-  const int iz = (int)(i / ((long long)nx * ny));
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nx * nrhs) return;
+  const int ix = t / nrhs, r = t % nrhs, iy = blockIdx.y, iz = blockIdx.z;
+  const long long i = ix + (long long)nx * (iy + (long long)ny * iz);
   // two coarse taps per axis: (i - 1)/2 and (i + 1)/2 with weight 1/2 each for
   // odd i; i/2 with weight 1 (and a zero-weight second tap) for even i; taps
   // beyond the coarse grid get weight zero and a clamped index
@@ -776,11 +770,13 @@ void launch_coarse_spmv(int ncx, int ncy, int ncz, const z64* E, int nrhs, const
 void launch_restrict(int nx, int ny, int nz, int nrhs, const z64* r, z64* c, hipStream_t s) {
   const long long nc = (long long)((nx + 1) / 2) * ((ny + 1) / 2) * ((nz + 1) / 2);
   account(16.0 * ((double)nx * ny * nz + nc) * nrhs, 2.0 * 27 * nc * nrhs);
-  hipLaunchKernelGGL(k_restrict, dim3((unsigned)ceil_div(nc * nrhs, 256)), dim3(256), 0, s, nx, ny, nz, nrhs, r, c);
+  const dim3 grid((unsigned)ceil_div((long long)((nx + 1) / 2) * nrhs, 256), (ny + 1) / 2, (nz + 1) / 2);
+  hipLaunchKernelGGL(k_restrict, grid, dim3(256), 0, s, nx, ny, nz, nrhs, r, c);
 }
 
 void launch_prolong(int nx, int ny, int nz, int nrhs, const z64* c, z64* q, hipStream_t s) {
   const long long n = (long long)nx * ny * nz;
   account(16.0 * (n + (double)((nx + 1) / 2) * ((ny + 1) / 2) * ((nz + 1) / 2)) * nrhs, 2.0 * 8 * n * nrhs);
-  hipLaunchKernelGGL(k_prolong, dim3((unsigned)ceil_div(n * nrhs, 256)), dim3(256), 0, s, nx, ny, nz, nrhs, c, q);
+  hipLaunchKernelGGL(k_prolong, dim3((unsigned)ceil_div((long long)nx * nrhs, 256), ny, nz), dim3(256), 0, s, nx, ny, nz,
+                     nrhs, c, q);
 }
