@@ -313,7 +313,8 @@ helm_status helm_graph_stats(const helm_handle_t* h, double out[2]);
  * as 0; 6 uses the sweep that also keeps each item's last plane solution in
  * LDS (groups of 16 whose operands and solutions fit), so that a plane step
  * needs only a workgroup barrier: paired where the complex FP64 groups pair,
- * else one group per workgroup, else as 0.
+ * else one group per workgroup (the approximate form's FP16 sweep too), else
+ * as 0.
  * Planes whose operand does not fit in LDS
  * (complex FP64 above 600 nodes, complex FP32 above 1200) keep it in global
  * memory under every policy.  Results agree to rounding.  Graphs captured

@@ -760,14 +760,15 @@ __device__ __forceinline__ void plane_product_half(HalfStream& cs, const c32* __
 // The one-workgroup-per-item sweep with FP16 factors: build (complex FP32
 // operand in LDS, column maxima into cmax), barrier, product, barrier.  The
 // column maxima alternate between two buffers; the one not in use is cleared
-// during the build.
-template <int RG, int PF>
+// during the build.  YLDS: the plane solutions are also kept in LDS
+// ([bp][RG] at ys_off elements), as in k_oras_fused.
+template <int RG, int PF, bool YLDS = false>
 __global__ void __launch_bounds__(64 * 16) k_oras_half(const Sub* __restrict__ subs, int ngroups, int nrhs,
                                                        const c32* __restrict__ cpl, const uint4* __restrict__ sinv16,
                                                        const int* __restrict__ sexp, int maxez,
                                                        const z64* __restrict__ u, z64* __restrict__ z,
                                                        const z64* __restrict__ add, int gnx, int gny,
-                                                       c32* __restrict__ yloc) {
+                                                       c32* __restrict__ yloc, int ys_off) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   c32* Bs = reinterpret_cast<c32*>(smem_raw);
   __shared__ unsigned cmax[2][RG];
@@ -782,7 +783,7 @@ __global__ void __launch_bounds__(64 * 16) k_oras_half(const Sub* __restrict__ s
   for (int st = 0; st < ns; ++st) {
     const int cb = st & 1, k = bx.plane_of(st);
     for (int i = tid; i < RG; i += FT) cmax[cb ^ 1][i] = 0u;
-    bx.template build_step_ne<4, 5, true>(st, Bs, tid, FT, cmax[cb]);
+    bx.template build_step_ne<4, 5, true, YLDS>(st, Bs, tid, FT, cmax[cb], Bs + ys_off);
     uint4 a[PF];
     HalfStream cs(sinv16 + (bx.sb.mat_off + (long long)k * bp * bp) / 4, bp, wave, nwaves, lane);
 #pragma unroll
@@ -790,8 +791,17 @@ __global__ void __launch_bounds__(64 * 16) k_oras_half(const Sub* __restrict__ s
     __syncthreads();
     plane_product_half<RG, PF>(
         cs, Bs, cmax[cb], sexp[box * maxez + k], wave, nwaves, lane, a,
-        [&](int p, int r) { return bx.init(st, p, r); }, [&](int p, int r, c32 val) { bx.output(st, p, r, val); });
-    wg_sync_global();
+        [&](int p, int r) { return bx.init(st, p, r); },
+        [&](int p, int r, c32 val) {
+          bx.output(st, p, r, val);
+          if constexpr (YLDS) Bs[ys_off + p * RG + r] = val;
+        });
+    if constexpr (YLDS) {
+      if (st == bx.sb.ez - 1) wg_sync_global();  // the forward solutions in yloc, for the backward products
+      else __syncthreads();
+    } else {
+      wg_sync_global();
+    }
   }
 }
 
@@ -1361,30 +1371,39 @@ template int fused_group<double>(int, int);
 // ---- approximate local solves: launch and tuning ------------------------------
 
 namespace {
-template <int RG>
+template <int RG, bool YLDS = false>
 void launch_half_t(const Sub* subs, int nsub, int ngroups, int nrhs, int bpmax, int rounds, const c32* cpl,
                    const uint4* sinv16, const int* sexp, int maxez, const z64* u, z64* z, const z64* add, int gnx,
                    int gny, c32* yloc, hipStream_t s) {
   constexpr int PF = 4;
-  const size_t lds = (size_t)bpmax * lds_width<float>(RG) * sizeof(c32);
+  const int ys_off = bpmax * lds_width<float>(RG);
+  const size_t lds = ((size_t)ys_off + (YLDS ? (size_t)bpmax * RG : 0)) * sizeof(c32);
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_oras_half<RG, PF>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)k_oras_half<RG, PF, YLDS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               160 * 1024 - 2 * RG * (int)sizeof(unsigned));
     attr = true;
   }
   const int nmt = bpmax / 16;
   rounds = std::max(rounds, (nmt + 15) / 16);  // at most 16 waves
   const int nwaves = (nmt + rounds - 1) / rounds;
-  hipLaunchKernelGGL((k_oras_half<RG, PF>), dim3(nsub * ngroups), dim3(64 * nwaves), lds, s, subs, ngroups, nrhs, cpl,
-                     sinv16, sexp, maxez, u, z, add, gnx, gny, yloc);
+  hipLaunchKernelGGL((k_oras_half<RG, PF, YLDS>), dim3(nsub * ngroups), dim3(64 * nwaves), lds, s, subs, ngroups, nrhs,
+                     cpl, sinv16, sexp, maxez, u, z, add, gnx, gny, yloc, ys_off);
 }
 
-void launch_half_rg(int rg, int rounds, const Sub* subs, int nsub, int nrhs, int bpmax, const c32* cpl,
+// The FP16 sweep with its plane solutions in LDS (groups of 16): operand, solutions and column maxima in one CU's LDS.
+bool half_ylds_fits(int rg, int bpmax) {
+  return rg == 16 && (size_t)bpmax * (lds_width<float>(rg) + rg) * sizeof(c32) <= 160 * 1024 - 2 * rg * sizeof(unsigned);
+}
+
+void launch_half_rg(int rg, int rounds, bool ylds, const Sub* subs, int nsub, int nrhs, int bpmax, const c32* cpl,
                     const uint4* sinv16, const int* sexp, int maxez, const z64* u, z64* z, const z64* add, int gnx,
                     int gny, c32* yloc, hipStream_t s) {
   const int ngroups = (nrhs + rg - 1) / rg;
-  if (rg == 16)
+  if (rg == 16 && ylds)
+    launch_half_t<16, true>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv16, sexp, maxez, u, z, add, gnx, gny,
+                            yloc, s);
+  else if (rg == 16)
     launch_half_t<16>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv16, sexp, maxez, u, z, add, gnx, gny, yloc, s);
   else
     launch_half_t<32>(subs, nsub, ngroups, nrhs, bpmax, rounds, cpl, sinv16, sexp, maxez, u, z, add, gnx, gny, yloc, s);
@@ -1411,8 +1430,14 @@ bool oras_half(const Sub* subs, int nsub, int bpmax, const c32* cpl, const uint4
     if (it != g_tune.end()) tv = it->second;
   }
   const int nmt = bpmax / 16, r0 = (nmt + 15) / 16;
-  if (tv.rg != 0 && ((tv.rg != 16 && tv.rg != 32) || tv.rg > rgmax || tv.rounds < r0 || tv.pair != 0 || tv.lowreg))
+  if (tv.rg != 0 && ((tv.rg != 16 && tv.rg != 32) || tv.rg > rgmax || tv.rounds < r0 || tv.lowreg ||
+                     (tv.pair != 0 && !(tv.pair == 2 && half_ylds_fits(tv.rg, bpmax)))))
     tv = TuneVal{0, 0, false, 0};  // a stale or foreign entry
+  const int policy = g_sweep_policy.load();
+  if (policy == 6 && rgmax >= 16 && half_ylds_fits(16, bpmax)) {  // forced: plane solutions in LDS
+    launch_half_rg(16, r0, true, subs, nsub, nrhs, bpmax, cpl, sinv16, sexp, maxez, u, z, add, gnx, gny, yloc, s);
+    return true;
+  }
   static const bool no_tune = std::getenv("HELM_NO_TUNE") != nullptr;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   (void)hipStreamIsCapturing(s, &cap);
@@ -1428,33 +1453,41 @@ bool oras_half(const Sub* subs, int nsub, int bpmax, const c32* cpl, const uint4
         const int waves = (nmt + rounds - 1) / rounds;
         if (waves == last_waves) continue;
         last_waves = waves;
-        float tot = 0.f;
-        for (int rep = 0; rep < 2; ++rep) {
-          (void)hipEventRecord(e0, s);
-          launch_half_rg(cand, rounds, subs, nsub, nrhs, bpmax, cpl, sinv16, sexp, maxez, u, z, add, gnx, gny, yloc, s);
-          (void)hipEventRecord(e1, s);
-          (void)hipEventSynchronize(e1);
-          float ms = 0.f;
-          (void)hipEventElapsedTime(&ms, e0, e1);
-          if (rep > 0) tot += ms;
-        }
-        if (verbose) std::fprintf(stderr, "helm:   fp16 candidate group %d, %d waves: %.3f ms\n", cand, waves, tot);
-        if (tot < best) {
-          best = tot;
-          tv = {cand, rounds, false};
+        for (int yl = 0; yl < 2; ++yl) {  // yl 1: the plane solutions in LDS
+          if (yl && !((policy == 0 || policy == 6) && half_ylds_fits(cand, bpmax))) continue;
+          float tot = 0.f;
+          for (int rep = 0; rep < 2; ++rep) {
+            (void)hipEventRecord(e0, s);
+            launch_half_rg(cand, rounds, yl != 0, subs, nsub, nrhs, bpmax, cpl, sinv16, sexp, maxez, u, z, add, gnx, gny,
+                           yloc, s);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) tot += ms;
+          }
+          if (verbose)
+            std::fprintf(stderr, "helm:   fp16 candidate group %d, %d waves%s: %.3f ms\n", cand, waves,
+                         yl ? " (solutions in LDS)" : "", tot);
+          if (tot < best) {
+            best = tot;
+            tv = {cand, rounds, false, yl ? 2 : 0};
+          }
         }
       }
     }
     locked_event_destroy(e0);
     locked_event_destroy(e1);
     if (verbose)
-      std::fprintf(stderr, "helm: fp16 sweep tuned (bp %d, %d boxes, %d rhs): group %d, %d waves, %.3f ms\n", bpmax,
-                   nsub, nrhs, tv.rg, (nmt + tv.rounds - 1) / tv.rounds, best);
+      std::fprintf(stderr, "helm: fp16 sweep tuned (bp %d, %d boxes, %d rhs): group %d, %d waves%s, %.3f ms\n", bpmax,
+                   nsub, nrhs, tv.rg, (nmt + tv.rounds - 1) / tv.rounds, tv.pair == 2 ? " (solutions in LDS)" : "",
+                   best);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     store_tune_locked(key, tv);
   }
-  if (tv.rg == 0) tv = {rgmax, r0, false};
-  launch_half_rg(tv.rg, tv.rounds, subs, nsub, nrhs, bpmax, cpl, sinv16, sexp, maxez, u, z, add, gnx, gny, yloc, s);
+  if (tv.rg == 0) tv = {rgmax, r0, false, 0};
+  launch_half_rg(tv.rg, tv.rounds, tv.pair == 2, subs, nsub, nrhs, bpmax, cpl, sinv16, sexp, maxez, u, z, add, gnx, gny,
+                 yloc, s);
   return true;
 }
 

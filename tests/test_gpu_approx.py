@@ -53,6 +53,33 @@ def test_approximate_local_solves_stay_close_to_the_exact_ones(nrhs):
     S.close()
 
 
+@pytest.mark.parametrize("nrhs", [12, 20])
+def test_fp16_sweep_with_plane_solutions_in_lds(nrhs):
+    # the FP16 sweep forced to keep its plane solutions in LDS (groups of 16,
+    # sweep policy 6) against the same sweep tuned without that form (policy 1)
+    # and against the oracle's exact local solves
+    from paper_2103_14921_amd import helm
+    shape, h, f, pml = (21, 18, 16), 25.0, 10.0, (3, 3, 3, 0)
+    c = inputs.velocity_thrust_belt(*shape, h=h, q=100.0)
+    prob = Problem(shape, h, c, f, Pml(*pml), WO)
+    M = Oras(assemble(prob), shape, decompose(shape, (2, 2, 2), 2), prob.k().ravel(), h)
+    R = inputs.random_field((nrhs, prob.n), seed=70 + nrhs)
+    out = {}
+    try:
+        for policy in ("item", "lds_solutions"):
+            helm.set_sweep_policy(policy)
+            say("approx one-level ORAS", policy, nrhs)
+            S = helm.Solver(shape, h, c, f, pml, weights=W, parts=(2, 2, 2), overlap=2, levels=1,
+                            precision="approx_local")
+            out[policy] = S.apply_oras(R)
+            S.close()
+    finally:
+        helm.set_sweep_policy("auto")
+    for r in range(nrhs):
+        assert rel(out["lds_solutions"][r], out["item"][r]) <= 1e-6, r
+        assert rel(out["lds_solutions"][r], M.apply(R[r])) <= 2e-2, r
+
+
 @pytest.mark.parametrize("tol", [1e-6, 1e-8])
 def test_approximate_two_level_solve_reaches_the_fp64_residual(tol):
     from paper_2103_14921_amd import helm
