@@ -225,6 +225,37 @@ def test_bench_module_imports_and_summarises_timings():
     assert e.shape == (20,) and torch.allclose(e, torch.full((20,), 1e-3 / (1 + 1e-3), dtype=torch.float64))
 
 
+def test_bench_attaches_profile_traffic_only_to_matching_launches():
+    # bench.py copies a committed counter profile's HBM traffic into its line
+    # only for the same sweep source (hash), the same average algorithmic
+    # bytes per launch and the same tuned launches; anything else gives null
+    import hashlib
+    import importlib
+    import json
+    import os
+    import re
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    bench = importlib.import_module("bench")
+    for md in ("oras_sweep_coarse_thrust192_mixed_pmc.md", "oras_sweep_coarse_thrust192_single_local_pmc.md"):
+        text = open(os.path.join(root, "profiles", md)).read()
+        data = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+        src = open(os.path.join(root, "paper_2103_14921_amd", "csrc", "ops_sweep.hip"), "rb").read()
+        same_source = hashlib.sha256(src).hexdigest()[:16] == data["source_sha256_16"]
+        alg, cfg = data["algorithmic_bytes_per_launch"], data["sweep_config"]
+        got, where = bench.measured_traffic("ops_sweep.hip", md, alg, cfg)
+        if same_source:
+            assert got == data["traffic_bytes_per_launch"] and md in where
+        else:
+            assert got is None
+        other = json.loads(json.dumps(cfg))
+        other["32"]["waves"] += 1
+        assert bench.measured_traffic("ops_sweep.hip", md, alg, other) == (None, None)
+        assert bench.measured_traffic("ops_sweep.hip", md, alg * 1.01, cfg) == (None, None)
+        assert bench.measured_traffic("ops_sweep.hip", md, alg, None) == (None, None)
+
+
 def test_serving_requeue_hold_is_lifted_when_the_other_batch_ends_first():
     # A batch that finds the device short while another is in flight goes back
     # to the queue and holds new launches until that other batch ends.  Force
