@@ -4,10 +4,10 @@ The one-workgroup-per-box sweep, the pipelined persistent sweep (two boxes
 per compute unit), the one-workgroup-per-box sweep built for two
 workgroups per compute unit (FP64, groups of 32) and the paired sweep (two
 right-hand-side groups of a box per workgroup; 20 and 40 right-hand sides
-pair), and the sweeps with the plane solutions kept in LDS (complex FP64
-paired at 20 right-hand sides, one group otherwise and in complex FP32) are
-forced in turn through the process-wide sweep policy,
-on right-hand-side batches that use full and partial groups of 16 and 32
+pair; at 64 two pairs per box), and the sweeps with the plane solutions
+kept in LDS (complex FP64 paired at 20 and 64 right-hand sides, one group
+otherwise and in complex FP32) are forced in turn through the process-wide
+sweep policy, on right-hand-side batches that use full and partial groups of 16 and 32
 columns, on the fine level (FP64 and complex FP32 factors) and on the coarse
 level; each result is compared with the oracle's one-level ORAS applied per
 right-hand side.
@@ -63,7 +63,7 @@ def test_fine_sweep_variants_match_oracle(policy, prec, tol, nrhs):
 
 @pytest.mark.parametrize("policy", ["item", "pipelined", "two_per_cu", "pipelined16", "paired", "paired_lds"])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("single_local", 5e-4)])
-@pytest.mark.parametrize("nrhs", [20, 12])
+@pytest.mark.parametrize("nrhs", [20, 12, 64])
 def test_coarse_sweep_variants_match_oracle(policy, prec, tol, nrhs):
     from paper_2103_14921_amd import helm
     helm.set_sweep_policy(policy)
