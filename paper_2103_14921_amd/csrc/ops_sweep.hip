@@ -111,7 +111,11 @@ __device__ __forceinline__ void plane_product(ChunkStream<T>& cs, const cpx<T>* 
   using V4 = typename Mfma<T>::v4;
   constexpr int W = WS;
   constexpr int NT = RG >= 16 ? RG / 16 : 1;  // 16-column MFMA tiles
-  constexpr int NACC = RG >= 16 ? 2 : 1;
+  // GAUSS (FP64, one 16-column tile, accumulators from zero): the complex
+  // product from three real ones, P1 = Re S Re T, P2 = Im S Im T,
+  // P3 = (Re S + Im S)(Re T + Im T): Re C = P1 - P2, Im C = P3 - P1 - P2
+  constexpr bool GAUSS = sizeof(T) == 8 && LATE_INIT && RG == 16;
+  constexpr int NACC = GAUSS ? 3 : (RG >= 16 ? 2 : 1);
   const int lrow = lane & 15, lg = lane >> 4;
   const int nct = cs.nct, total = cs.ntw * cs.nct;
   const cpx<T>* Bcol = Bs + 4 * lg * W + lrow;
@@ -128,7 +132,8 @@ __device__ __forceinline__ void plane_product(ChunkStream<T>& cs, const cpx<T>* 
             // the load of y_k is in flight during the tile's products
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
-              acc[nt][0] = acc[nt][1] = V4{0, 0, 0, 0};
+#pragma unroll
+              for (int q = 0; q < NACC; ++q) acc[nt][q] = V4{0, 0, 0, 0};
 #pragma unroll
               for (int v = 0; v < 4; ++v) y0s[nt][v] = init(mt * 16 + Mfma<T>::row(lg, v), nt * 16 + lrow);
             }
@@ -152,7 +157,13 @@ __device__ __forceinline__ void plane_product(ChunkStream<T>& cs, const cpx<T>* 
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const T are = a[j][t].re, aim = a[j][t].im;
-          if constexpr (RG >= 16) {
+          if constexpr (GAUSS) {
+            const T asum = are + aim;
+            const cpx<T> tv = Bcol[(kc + t) * W];
+            acc[0][0] = Mfma<T>::op(are, tv.re, acc[0][0]);
+            acc[0][1] = Mfma<T>::op(aim, tv.im, acc[0][1]);
+            acc[0][2] = Mfma<T>::op(asum, tv.re + tv.im, acc[0][2]);
+          } else if constexpr (RG >= 16) {
             const T naim = -aim;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
@@ -170,7 +181,13 @@ __device__ __forceinline__ void plane_product(ChunkStream<T>& cs, const cpx<T>* 
         }
         kc += 16;
         if (kc == 16 * nct) {
-          if constexpr (RG >= 16 && LATE_INIT) {
+          if constexpr (GAUSS) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const T re = acc[0][0][v] - acc[0][1][v], im = (acc[0][2][v] - acc[0][0][v]) - acc[0][1][v];
+              out(mt * 16 + Mfma<T>::row(lg, v), lrow, mk<T>(y0s[0][v].re + re, y0s[0][v].im + im));
+            }
+          } else if constexpr (RG >= 16 && LATE_INIT) {
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
