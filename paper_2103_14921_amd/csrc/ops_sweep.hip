@@ -111,10 +111,10 @@ __device__ __forceinline__ void plane_product(ChunkStream<T>& cs, const cpx<T>* 
   using V4 = typename Mfma<T>::v4;
   constexpr int W = WS;
   constexpr int NT = RG >= 16 ? RG / 16 : 1;  // 16-column MFMA tiles
-  // GAUSS (FP64, one 16-column tile, accumulators from zero): the complex
-  // product from three real ones, P1 = Re S Re T, P2 = Im S Im T,
+  // GAUSS (one 16-column tile, accumulators from zero): the complex product
+  // from three real ones, P1 = Re S Re T, P2 = Im S Im T,
   // P3 = (Re S + Im S)(Re T + Im T): Re C = P1 - P2, Im C = P3 - P1 - P2
-  constexpr bool GAUSS = sizeof(T) == 8 && LATE_INIT && RG == 16;
+  constexpr bool GAUSS = LATE_INIT && RG == 16;
   constexpr int NACC = GAUSS ? 3 : (RG >= 16 ? 2 : 1);
   const int lrow = lane & 15, lg = lane >> 4;
   const int nct = cs.nct, total = cs.ntw * cs.nct;
